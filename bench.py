@@ -1,0 +1,205 @@
+"""Benchmark: exact triangle counting of a synthetic R-MAT graph on one MI355X.
+
+A step is one pass of the whole path over the device-resident edge array: degrees, order,
+orientation, key sort, node array, in-edge lists (tc_preprocess) and the counting kernel
+(tc_count_prepared) -- i.e. exactly what tc_count enqueues.  The headline workload is R-MAT
+scale 23, edgefactor 24, (a, b, c) = (0.57, 0.19, 0.19), seed 0: about 1.9e8 undirected
+edges.  `value` is oriented edges (one sorted-list intersection each) per second of step
+time.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # 256 CUs x 64 int32 lanes/clk x 2.4 GHz = 39.3
+
+WORKLOADS = {
+    "rmat23": dict(kind="rmat", scale=23, ef=24, seed=0,
+                   label="R-MAT scale 23, edgefactor 24, a=0.57 b=0.19 c=0.19, seed 0"),
+    "rmat20": dict(kind="rmat", scale=20, ef=16, seed=0,
+                   label="R-MAT scale 20, edgefactor 16, a=0.57 b=0.19 c=0.19, seed 0"),
+    "er1000": dict(kind="er", label="Erdos-Renyi G(1000, 0.02), seed 0"),
+}
+GOLDEN_KEYS = {"rmat23": "rmat_s23_ef24_s0", "rmat20": "rmat_s20_ef16_s0",
+               "er1000": "er_1000_p0.02_s0"}
+COUNT_SRC = os.path.join(ROOT, "paper_1503_00576_amd", "csrc", "count.hip")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_sha() -> str:
+    with open(COUNT_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic(workload: str):
+    """HBM bytes per launch of the counting kernel from the committed rocprofv3 counter
+    summary, or None when absent or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_k_count_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_sha") != kernel_sha():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def make_graph(name: str, dev):
+    from paper_1503_00576_amd import synth
+    w = WORKLOADS[name]
+    if w["kind"] == "rmat":
+        return synth.rmat_graph(w["scale"], w["ef"], seed=w["seed"], device=dev)
+    return synth.er_1000(device=dev)
+
+
+def cpu_baseline(dev, seconds_hint: float):
+    """The oracle (single-threaded C, test infrastructure) on a bounded sample of the same
+    workload family: R-MAT scale 19, edgefactor 24, same (a, b, c), seed 0."""
+    import oracle
+    from paper_1503_00576_amd import synth
+    e, n = synth.rmat_graph(19, 24, seed=0, device=dev)
+    eh = e.cpu().numpy()
+    m = eh.shape[0]
+    t0 = time.perf_counter()
+    tot = oracle.count(eh, n)
+    dt = time.perf_counter() - t0
+    return {"value": m / dt, "unit": "oriented-edge intersections/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"R-MAT scale 19, edgefactor 24, seed 0 ({m} edges, {tot} triangles): "
+                      f"oracle end to end (degrees, orientation, sorted lists, merges) "
+                      f"in {dt:.2f} s on one host core"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rmat23", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (the counting path is single-GPU); "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1503_00576_amd import api
+
+    dev = torch.device("cuda:0")
+    torch.cuda.init()
+    torch.cuda.set_device(dev)
+    log(f"generating {WORKLOADS[args.workload]['label']}")
+    t0 = time.perf_counter()
+    edges, n = make_graph(args.workload, dev)
+    torch.cuda.synchronize()
+    m = int(edges.shape[0])
+    log(f"n={n} m={m} generated in {time.perf_counter() - t0:.1f} s")
+
+    ws = api.alloc_workspace(n, m, False, dev)
+    out = api.Result(torch.empty(1, dtype=torch.int64, device=dev),
+                     torch.empty(1, dtype=torch.int32, device=dev))
+    L = api._native.lib()
+    stream = torch.cuda.current_stream(dev)
+    sp = api._stream(dev)
+    wsz = ws.numel()
+
+    def step():
+        api._raise(L.tc_preprocess(api._ptr(edges), n, m, 0, api._ptr(ws), wsz, sp, None),
+                   "tc_preprocess")
+        api._raise(L.tc_count_prepared(n, m, 0, api._ptr(ws), wsz, sp, api._ptr(out.total),
+                                       None, api._ptr(out.status)), "tc_count_prepared")
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{args.warmup} done")
+    out.check()
+    total = int(out.total.item())
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        api._raise(L.tc_preprocess(api._ptr(edges), n, m, 0, api._ptr(ws), wsz, sp, None),
+                   "tc_preprocess")
+        ev[i][0].record(stream)
+        api._raise(L.tc_count_prepared(n, m, 0, api._ptr(ws), wsz, sp, api._ptr(out.total),
+                                       None, api._ptr(out.status)), "tc_count_prepared")
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    out.check()
+    assert int(out.total.item()) == total, "count changed between runs"
+    ms_per_step = elapsed * 1e3 / args.steps
+    count_ms = sum(a.elapsed_time(b) for a, b in ev) / args.steps
+    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, counting kernel {count_ms:.3f} ms")
+
+    # graph statistics for the roofline: streamed elements W = sum_u C(d+(u), 2)
+    arrs = api.Prepared(edges, n).arrays()
+    dplus = (arrs["row_ptr"][1:] - arrs["row_ptr"][:-1]).to(torch.int64)
+    wedges = int((dplus * (dplus - 1) // 2).sum().item())
+    del arrs
+    golden_ok = None
+    gpath = os.path.join(ROOT, "tests", "golden", "workloads.json")
+    if os.path.exists(gpath):
+        g = json.load(open(gpath)).get(GOLDEN_KEYS[args.workload])
+        if g is not None:
+            golden_ok = (g["total"] == total)
+
+    # counting kernel: algorithmic bytes = 4 B per streamed element + 8 B per oriented edge
+    # (its in-edge range) + the node array and out-lists once
+    alg_bytes = 4.0 * wedges + 8.0 * m + 4.0 * (n + 1) + 4.0 * m
+    achieved = alg_bytes / (count_ms * 1e-3) / 1e9
+    traffic = load_traffic(args.workload)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "kernel": "k_count",
+                "kernel_ms": round(count_ms, 4), "algorithmic_bytes": alg_bytes}
+
+    res = {
+        "metric": "oriented-edge intersections/s",
+        "value": m / (ms_per_step * 1e-3),
+        "unit": "intersections/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32/uint64", "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.workload]["label"], "n": n, "m": m,
+                   "triangles": total, "golden_match": golden_ok, "wedges": wedges,
+                   "parallelism": "single GPU"},
+        "count_kernel_intersections_per_s": m / (count_ms * 1e-3),
+        "triangles_per_s": total / (ms_per_step * 1e-3),
+        "roofline": roofline,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on a bounded sample) ...")
+        res["cpu_baseline"] = cpu_baseline(dev, 20.0)
+        log("cpu baseline done")
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

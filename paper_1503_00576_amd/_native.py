@@ -1,0 +1,55 @@
+"""ctypes loader for libtc.so (the HIP library).  There is no fallback: if the library is
+missing or fails to load, every entry point raises."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("TC_LIB", os.path.join(HERE, "libtc.so"))
+
+EXPORTS = [
+    "tc_strerror", "tc_workspace_size", "tc_count", "tc_count_per_vertex",
+    "tc_workspace_layout", "tc_preprocess", "tc_count_prepared", "tc_sort_workspace_size", "tc_sort_u64",
+]
+
+
+class TcLayout(ctypes.Structure):
+    _fields_ = [("deg", ctypes.c_size_t), ("perm", ctypes.c_size_t), ("rank", ctypes.c_size_t),
+                ("row_ptr", ctypes.c_size_t), ("col", ctypes.c_size_t),
+                ("m_fwd", ctypes.c_int64), ("id_bits", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises RuntimeError when it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libtc.so not found at {LIB_PATH}: build it first "
+                           "(python -c 'import __graft_entry__ as g; g.build()')")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, u32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32, ctypes.c_size_t
+    L.tc_strerror.argtypes = [ctypes.c_int]
+    L.tc_strerror.restype = ctypes.c_char_p
+    L.tc_workspace_size.argtypes = [i64, i64, u32]
+    L.tc_workspace_size.restype = sz
+    L.tc_count.argtypes = [vp, i64, i64, u32, vp, sz, vp, vp, vp]
+    L.tc_count.restype = ctypes.c_int
+    L.tc_count_per_vertex.argtypes = [vp, i64, i64, u32, vp, sz, vp, vp, vp, vp]
+    L.tc_count_per_vertex.restype = ctypes.c_int
+    L.tc_workspace_layout.argtypes = [i64, i64, u32, ctypes.POINTER(TcLayout)]
+    L.tc_workspace_layout.restype = ctypes.c_int
+    L.tc_preprocess.argtypes = [vp, i64, i64, u32, vp, sz, vp, vp]
+    L.tc_preprocess.restype = ctypes.c_int
+    L.tc_count_prepared.argtypes = [i64, i64, u32, vp, sz, vp, vp, vp, vp]
+    L.tc_count_prepared.restype = ctypes.c_int
+    L.tc_sort_workspace_size.argtypes = [i64]
+    L.tc_sort_workspace_size.restype = sz
+    L.tc_sort_u64.argtypes = [vp, vp, i64, ctypes.c_int32, vp, sz, vp]
+    L.tc_sort_u64.restype = ctypes.c_int
+    _lib = L
+    return L

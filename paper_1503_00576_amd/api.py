@@ -1,0 +1,214 @@
+"""Python binding of libtc.so: argument marshalling only (every step of the path runs in the
+library's HIP kernels).  Device memory comes from torch; the work is enqueued on torch's
+current stream of the edge tensor's device."""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _native
+
+OK, E_ARG, E_RANGE, E_SELF_LOOP, E_DUP_EDGE, E_ASYMMETRIC, E_UNSORTED, E_WORKSPACE, \
+    E_TOO_LARGE, E_HIP = range(10)
+STATUS_NAMES = {OK: "ok", E_ARG: "arg", E_RANGE: "range", E_SELF_LOOP: "self_loop",
+                E_DUP_EDGE: "dup_edge", E_ASYMMETRIC: "asymmetric", E_UNSORTED: "unsorted",
+                E_WORKSPACE: "workspace", E_TOO_LARGE: "too_large", E_HIP: "hip"}
+
+EDGES_ONCE = 0
+EDGES_BOTH = 1
+
+
+class TCError(RuntimeError):
+    def __init__(self, code: int, where: str = ""):
+        msg = _native.lib().tc_strerror(code).decode()
+        super().__init__(f"{where}: {msg} (status {code})" if where else msg)
+        self.code = code
+        self.name = STATUS_NAMES.get(code, "?")
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(dev: torch.device):
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _check_edges(edges: torch.Tensor) -> torch.Tensor:
+    if not isinstance(edges, torch.Tensor) or not edges.is_cuda:
+        raise TypeError("edges must be a CUDA (HIP) tensor")
+    if edges.dtype != torch.int32:
+        raise TypeError("edges must be int32")
+    if edges.dim() != 2 or edges.shape[1] != 2:
+        raise ValueError("edges must have shape [m, 2]")
+    return edges.contiguous()
+
+
+def _flags(both: bool) -> int:
+    return EDGES_BOTH if both else EDGES_ONCE
+
+
+def workspace_size(n: int, m: int, both: bool = False) -> int:
+    s = _native.lib().tc_workspace_size(int(n), int(m), _flags(both))
+    if s == 0:
+        raise TCError(E_ARG, "tc_workspace_size")
+    return s
+
+
+def alloc_workspace(n: int, m: int, both: bool = False, device=None) -> torch.Tensor:
+    return torch.empty(workspace_size(n, m, both), dtype=torch.uint8, device=device)
+
+
+def _raise(code: int, where: str):
+    if code != OK:
+        raise TCError(code, where)
+
+
+@dataclass
+class Result:
+    total: torch.Tensor        # uint64 as int64 [1] on the device
+    status: torch.Tensor       # int32 [1] on the device
+    per_vertex: torch.Tensor | None = None  # uint64 as int64 [n]
+
+    def check(self) -> "Result":
+        st = int(self.status.item())
+        if st != OK:
+            raise TCError(st, "device")
+        return self
+
+
+def count_async(edges: torch.Tensor, n: int, both: bool = False, per_vertex: bool = False,
+                workspace: torch.Tensor | None = None, out: Result | None = None) -> Result:
+    """Enqueue tc_count (or tc_count_per_vertex) on the current stream; no synchronisation."""
+    edges = _check_edges(edges)
+    dev = edges.device
+    m = edges.shape[0]
+    ws = workspace if workspace is not None else alloc_workspace(n, m, both, dev)
+    if out is None:
+        out = Result(torch.empty(1, dtype=torch.int64, device=dev),
+                     torch.empty(1, dtype=torch.int32, device=dev),
+                     torch.empty(n, dtype=torch.int64, device=dev) if per_vertex else None)
+    L = _native.lib()
+    if per_vertex:
+        code = L.tc_count_per_vertex(_ptr(edges), n, m, _flags(both), _ptr(ws), ws.numel(),
+                                     _stream(dev), _ptr(out.total), _ptr(out.per_vertex),
+                                     _ptr(out.status))
+    else:
+        code = L.tc_count(_ptr(edges), n, m, _flags(both), _ptr(ws), ws.numel(), _stream(dev),
+                          _ptr(out.total), _ptr(out.status))
+    _raise(code, "tc_count")
+    return out
+
+
+def count(edges: torch.Tensor, n: int, both: bool = False) -> int:
+    """Exact number of triangles of the graph given as an int32 [m, 2] edge array."""
+    r = count_async(edges, n, both).check()
+    return int(r.total.item()) & 0xFFFFFFFFFFFFFFFF
+
+
+def count_per_vertex(edges: torch.Tensor, n: int, both: bool = False):
+    """(total, per-vertex counts as int64 [n] on the device)."""
+    r = count_async(edges, n, both, per_vertex=True).check()
+    return int(r.total.item()) & 0xFFFFFFFFFFFFFFFF, r.per_vertex
+
+
+def layout(n: int, m: int, both: bool = False) -> _native.TcLayout:
+    lay = _native.TcLayout()
+    _raise(_native.lib().tc_workspace_layout(n, m, _flags(both), ctypes.byref(lay)),
+           "tc_workspace_layout")
+    return lay
+
+
+class Prepared:
+    """A graph preprocessed on the device (tc_preprocess): its workspace stays resident and
+    can be counted again with count_prepared()."""
+
+    def __init__(self, edges: torch.Tensor, n: int, both: bool = False,
+                 workspace: torch.Tensor | None = None):
+        edges = _check_edges(edges)
+        self.device = edges.device
+        self.n, self.m, self.both = int(n), int(edges.shape[0]), bool(both)
+        self.workspace = (workspace if workspace is not None
+                          else alloc_workspace(self.n, self.m, self.both, self.device))
+        self.status = torch.zeros(1, dtype=torch.int32, device=self.device)
+        _raise(_native.lib().tc_preprocess(_ptr(edges), self.n, self.m, _flags(self.both),
+                                           _ptr(self.workspace), self.workspace.numel(),
+                                           _stream(self.device), _ptr(self.status)),
+               "tc_preprocess")
+
+    def count_async(self, per_vertex: bool = False, out: Result | None = None) -> Result:
+        dev = self.device
+        if out is None:
+            out = Result(torch.empty(1, dtype=torch.int64, device=dev),
+                         torch.empty(1, dtype=torch.int32, device=dev),
+                         torch.empty(self.n, dtype=torch.int64, device=dev) if per_vertex else None)
+        _raise(_native.lib().tc_count_prepared(
+            self.n, self.m, _flags(self.both), _ptr(self.workspace), self.workspace.numel(),
+            _stream(dev), _ptr(out.total), _ptr(out.per_vertex) if per_vertex else None,
+            _ptr(out.status)), "tc_count_prepared")
+        return out
+
+    def count(self) -> int:
+        return int(self.count_async().check().total.item()) & 0xFFFFFFFFFFFFFFFF
+
+    def arrays(self) -> dict:
+        """Views of the preprocessing arrays: deg, perm, rank (int32 [n]), row_ptr
+        (int32 [n+1]), col (int32 [m_fwd]); raises on a data error."""
+        st = int(self.status.item())
+        if st:
+            raise TCError(st, "device")
+        lay = layout(self.n, self.m, self.both)
+        ws = self.workspace
+
+        def view(off, count):
+            return ws[off: off + 4 * count].view(torch.int32)
+
+        return {"deg": view(lay.deg, self.n), "perm": view(lay.perm, self.n),
+                "rank": view(lay.rank, self.n), "row_ptr": view(lay.row_ptr, self.n + 1),
+                "col": view(lay.col, lay.m_fwd), "id_bits": lay.id_bits}
+
+
+def preprocess(edges: torch.Tensor, n: int, both: bool = False) -> dict:
+    """Run the preprocessing phase only and return views of its arrays (see Prepared)."""
+    p = Prepared(edges, n, both)
+    out = p.arrays()
+    out["prepared"] = p
+    return out
+
+
+def sort_u64(keys: torch.Tensor, bits: int) -> torch.Tensor:
+    """Sort int64 storage of uint64 keys in place on their low `bits` bits (stable)."""
+    if not keys.is_cuda or keys.dtype != torch.int64 or not keys.is_contiguous():
+        raise TypeError("keys must be a contiguous int64 CUDA tensor")
+    dev = keys.device
+    n = keys.numel()
+    tmp = torch.empty_like(keys)
+    L = _native.lib()
+    ws = torch.empty(max(L.tc_sort_workspace_size(n), 256), dtype=torch.uint8, device=dev)
+    _raise(L.tc_sort_u64(_ptr(keys), _ptr(tmp), n, bits, _ptr(ws), ws.numel(), _stream(dev)),
+           "tc_sort_u64")
+    return keys
+
+
+# ------------------------------------------------------------------ derived quantities
+
+def clustering(per_vertex, degree):
+    """Local clustering coefficient C(v) = 2 T(v) / (deg(v) (deg(v) - 1)), 0 when deg < 2,
+    computed in float64 on the host from exact integer counts."""
+    import numpy as np
+    t = np.asarray(per_vertex.cpu() if hasattr(per_vertex, "cpu") else per_vertex, dtype=np.float64)
+    d = np.asarray(degree.cpu() if hasattr(degree, "cpu") else degree, dtype=np.float64)
+    den = d * (d - 1.0)
+    out = np.zeros_like(t)
+    np.divide(2.0 * t, den, out=out, where=d >= 2)
+    return out
+
+
+def transitivity(total: int, degree) -> float:
+    """3 * T / (number of paths of length two) = 3T / sum_v C(deg v, 2); 0 if no such path."""
+    import numpy as np
+    d = np.asarray(degree.cpu() if hasattr(degree, "cpu") else degree, dtype=np.int64)
+    wedges = int((d * (d - 1) // 2).sum())
+    return 0.0 if wedges == 0 else 3.0 * total / wedges

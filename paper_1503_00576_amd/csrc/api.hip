@@ -1,0 +1,400 @@
+// C ABI of libtc.so: argument checks, workspace layout and the launch sequence of the
+// preprocessing and counting phases.  Everything is enqueued on the caller's stream; the
+// library never allocates device memory and never synchronises.
+#include <string.h>
+
+#include "internal.h"
+
+namespace tc {
+
+// kernels of prep.hip
+__global__ void k_degree(const int2 *, uint64_t, uint32_t, uint32_t, uint32_t *, int32_t *);
+__global__ void k_vkeys(const uint32_t *, uint32_t, int, uint64_t *);
+__global__ void k_rank(const uint64_t *, uint32_t, int, uint32_t *, uint32_t *);
+__global__ void k_orient(const int2 *, uint64_t, uint32_t, const uint32_t *, int, uint64_t *,
+                         uint32_t *, const int32_t *);
+__global__ void k_both_check(const uint32_t *, uint32_t, int32_t *);
+__global__ void k_csr(const uint64_t *, uint32_t, uint32_t, int, uint32_t *, uint32_t *,
+                      int32_t *);
+__global__ void k_csc_count(const uint64_t *, uint32_t, int, const uint32_t *, const uint32_t *,
+                            uint32_t *, const int32_t *);
+__global__ void k_csc_fill(const uint64_t *, uint32_t, int, const uint32_t *, const uint32_t *,
+                           const uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t *,
+                           const int32_t *);
+__global__ void k_items(const uint32_t *, const uint32_t *, const uint32_t *, uint32_t, uint32_t,
+                        uint32_t, uint32_t, uint32_t, uint32_t *, uint32_t *, uint32_t *,
+                        uint32_t *, const int32_t *);
+__global__ void k_item_fill(const uint32_t *, const uint32_t *, uint32_t, uint32_t *,
+                            const int32_t *);
+__global__ void k_pv_out(const unsigned long long *, const uint32_t *, uint32_t,
+                         unsigned long long *);
+__global__ void k_zero_u64(unsigned long long *, uint64_t);
+
+
+__global__ void k_copy_status(const int32_t *__restrict__ src, int32_t *__restrict__ dst) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src;
+}
+
+int device_cu_count() {
+    static int cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+    if (cache[dev] == 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            v <= 0)
+            v = 256;
+        cache[dev] = v;
+    }
+    return cache[dev];
+}
+
+// ------------------------------------------------------------------ workspace layout
+
+struct Layout {
+    size_t ctl, deg, perm, rank, keys_a, keys_b, sort_scratch, row_ptr, col, cdeg, cptr, cfill,
+        cbeg, cend, cu, items[4], off[4], item_v[4], scan_scratch, tpv, total_bytes;
+    uint32_t n, m, mf, kcap, id_bits;
+};
+
+// item spaces: [0] wave / [1] workgroup items for total counts, [2] / [3] for per-vertex counts
+enum { kCtlStatus = 0, kCtlBoth = 1, kCtlQueueA = 2, kCtlQueueB = 3, kCtlWords = 64 };
+
+static int id_bits_for(uint32_t n) {
+    int b = 1;
+    while (b < 31 && (1ull << b) < n) ++b;
+    return b;
+}
+
+static bool make_layout(int64_t n, int64_t m, uint32_t flags, Layout &L) {
+    if (n < 0 || m < 0 || n >= (1ll << 31) || m >= (1ll << 32)) return false;
+    if (flags & ~TC_EDGES_BOTH) return false;
+    L.n = (uint32_t)n;
+    L.m = (uint32_t)m;
+    L.mf = (flags & TC_EDGES_BOTH) ? (uint32_t)(m / 2) : (uint32_t)m;
+    L.kcap = L.m > L.n ? L.m : L.n;
+    L.id_bits = (uint32_t)id_bits_for(L.n);
+    const uint64_t n1 = (uint64_t)n + 1;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align_up(off + (bytes ? bytes : 1), 256);
+        return at;
+    };
+    L.ctl = take(kCtlWords * 4);
+    L.deg = take((size_t)n * 4);
+    L.perm = take((size_t)n * 4);
+    L.rank = take((size_t)n * 4);
+    L.keys_a = take((size_t)L.kcap * 8);
+    L.keys_b = take((size_t)L.kcap * 8);
+    L.sort_scratch = take(sort_scratch_bytes(L.kcap));
+    L.row_ptr = take(n1 * 4);
+    L.col = take((size_t)L.mf * 4 + 64);
+    L.cdeg = take(n1 * 4);
+    L.cptr = take(n1 * 4);
+    L.cfill = take(n1 * 4);
+    L.cbeg = take((size_t)L.mf * 4);
+    L.cend = take((size_t)L.mf * 4);
+    L.cu = take((size_t)L.mf * 4);
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t per = (k & 1) ? count_item_edges_block() : count_item_edges_wave();
+        L.items[k] = take(n1 * 4);
+        L.off[k] = take(n1 * 4);
+        L.item_v[k] = take(((size_t)L.mf / per + n1 + 1) * 4);
+    }
+    L.scan_scratch = take(scan_scratch_words(n1) * 4);
+    L.tpv = take((size_t)n * 8);
+    L.total_bytes = off;
+    return true;
+}
+
+template <class T>
+static T *at(void *ws, size_t off) {
+    return (T *)((char *)ws + off);
+}
+
+static inline uint32_t grid_for(uint64_t items, uint32_t threads, uint32_t cap = 1u << 20) {
+    uint64_t g = (items + threads - 1) / threads;
+    if (g == 0) g = 1;
+    if (g > cap) g = cap;
+    return (uint32_t)g;
+}
+
+#define TC_LAUNCH_CHECK()                    \
+    do {                                     \
+        if (hipGetLastError() != hipSuccess) \
+            return TC_E_HIP;                 \
+    } while (0)
+
+#define TC_HIP(x)                \
+    do {                         \
+        if ((x) != hipSuccess)   \
+            return TC_E_HIP;     \
+    } while (0)
+
+static int check_args(const int32_t *d_edges, int64_t n, int64_t m, uint32_t flags, void *d_ws,
+                      size_t ws_bytes, Layout &L) {
+    if (n < 0 || m < 0 || (flags & ~TC_EDGES_BOTH)) return TC_E_ARG;
+    if (n >= (1ll << 31) || m >= (1ll << 32)) return TC_E_TOO_LARGE;
+    if (n == 0 && m > 0) return TC_E_ARG;
+    if (m > 0 && (!d_edges || ((uintptr_t)d_edges & 7))) return TC_E_ARG;
+    if ((flags & TC_EDGES_BOTH) && (m & 1)) return TC_E_ASYMMETRIC;
+    if (!make_layout(n, m, flags, L)) return TC_E_ARG;
+    if (!d_ws || ((uintptr_t)d_ws & 255) || ws_bytes < L.total_bytes) return TC_E_WORKSPACE;
+    return TC_OK;
+}
+
+// Preprocessing (Section 3.2) plus the counting kernel's work lists: degrees, order,
+// orientation, key sort, node array, in-edge lists, work items.
+static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, const Layout &L,
+                          hipStream_t s) {
+    const uint32_t n = L.n, m = L.m, mf = L.mf, n1 = L.n + 1;
+    const int b = (int)L.id_bits;
+    uint32_t *ctl = at<uint32_t>(ws, L.ctl);
+    int32_t *status = (int32_t *)ctl + kCtlStatus;
+    uint32_t *deg = at<uint32_t>(ws, L.deg);
+    uint32_t *perm = at<uint32_t>(ws, L.perm);
+    uint32_t *rank = at<uint32_t>(ws, L.rank);
+    uint64_t *ka = at<uint64_t>(ws, L.keys_a), *kb = at<uint64_t>(ws, L.keys_b);
+    void *sort_scr = at<void>(ws, L.sort_scratch);
+    uint32_t *row_ptr = at<uint32_t>(ws, L.row_ptr);
+    uint32_t *col = at<uint32_t>(ws, L.col);
+    const int2 *edges = (const int2 *)d_edges;
+    const bool both = flags & TC_EDGES_BOTH;
+
+    TC_HIP(fill_u32(ctl, 0u, kCtlWords, s));
+    TC_HIP(fill_u32(deg, 0u, n, s));
+    if (m > 0) {
+        hipLaunchKernelGGL(k_degree, dim3(grid_for(m, 256, 8192)), dim3(256), 0, s, edges,
+                           (uint64_t)m, n, (uint32_t)both, deg, status);
+        TC_LAUNCH_CHECK();
+    }
+    // the order of Section 2.2 as ranks: stable sort of (degree << b | id) on the degree bits
+    if (n > 0) {
+        hipLaunchKernelGGL(k_vkeys, dim3(grid_for(n, 256)), dim3(256), 0, s, deg, n, b, ka);
+        TC_LAUNCH_CHECK();
+        uint64_t *vs = nullptr;
+        TC_HIP(sort_u64(ka, kb, n, b, 2 * b, sort_scr, nullptr, s, &vs));
+        hipLaunchKernelGGL(k_rank, dim3(grid_for(n, 256)), dim3(256), 0, s, vs, n, b, perm, rank);
+        TC_LAUNCH_CHECK();
+    }
+    uint64_t *sorted = ka;
+    if (m > 0) {
+        hipLaunchKernelGGL(k_orient, dim3(grid_for(m, 256, 8192)), dim3(256), 0, s, edges,
+                           (uint64_t)m, (uint32_t)both, rank, b, ka, ctl + kCtlBoth, status);
+        TC_LAUNCH_CHECK();
+        if (both) {
+            hipLaunchKernelGGL(k_both_check, dim3(1), dim3(64), 0, s, ctl + kCtlBoth, mf, status);
+            TC_LAUNCH_CHECK();
+        }
+        TC_HIP(sort_u64(ka, kb, mf, 0, 2 * b, sort_scr, status, s, &sorted));
+    }
+    if (mf == 0) {
+        TC_HIP(fill_u32(row_ptr, 0u, n1, s));
+        return TC_OK;
+    }
+    hipLaunchKernelGGL(k_csr, dim3(grid_for(mf, 256)), dim3(256), 0, s, sorted, mf, n, b, row_ptr,
+                       col, status);
+    TC_LAUNCH_CHECK();
+    // in-edge lists and work items of the counting kernel
+    uint32_t *cdeg = at<uint32_t>(ws, L.cdeg), *cptr = at<uint32_t>(ws, L.cptr);
+    uint32_t *cfill = at<uint32_t>(ws, L.cfill);
+    uint32_t *items[4], *offs[4], *iv[4];
+    for (int k = 0; k < 4; ++k) {
+        items[k] = at<uint32_t>(ws, L.items[k]);
+        offs[k] = at<uint32_t>(ws, L.off[k]);
+        iv[k] = at<uint32_t>(ws, L.item_v[k]);
+    }
+    uint32_t *scan_scr = at<uint32_t>(ws, L.scan_scratch);
+    TC_HIP(fill_u32(cdeg, 0u, n1, s));
+    TC_HIP(fill_u32(cfill, 0u, n1, s));
+    hipLaunchKernelGGL(k_csc_count, dim3(grid_for(mf, 256)), dim3(256), 0, s, sorted, mf, b,
+                       row_ptr, col, cdeg, status);
+    TC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_items, dim3(grid_for(n1, 256)), dim3(256), 0, s, row_ptr, col, cdeg, n,
+                       count_wave_span(false), count_wave_list(true), count_item_edges_wave(),
+                       count_item_edges_block(), items[0], items[1], items[2], items[3], status);
+    TC_LAUNCH_CHECK();
+    TC_HIP(scan_exclusive_u32(cdeg, cptr, n1, scan_scr, s));
+    for (int k = 0; k < 4; ++k) TC_HIP(scan_exclusive_u32(items[k], offs[k], n1, scan_scr, s));
+    hipLaunchKernelGGL(k_csc_fill, dim3(grid_for(mf, 256)), dim3(256), 0, s, sorted, mf, b,
+                       row_ptr, col, cptr, cfill, at<uint32_t>(ws, L.cbeg),
+                       at<uint32_t>(ws, L.cend), at<uint32_t>(ws, L.cu), status);
+    TC_LAUNCH_CHECK();
+    for (int k = 0; k < 4; ++k) {
+        hipLaunchKernelGGL(k_item_fill, dim3(grid_for(n, 256)), dim3(256), 0, s, items[k], offs[k],
+                           n, iv[k], status);
+        TC_LAUNCH_CHECK();
+    }
+    return TC_OK;
+}
+
+// Counting phase on a prepared workspace.
+static int run_count_prepared(void *ws, const Layout &L, hipStream_t s, uint64_t *d_total,
+                              uint64_t *d_pv) {
+    const bool pv = d_pv != nullptr;
+    const uint32_t n = L.n;
+    uint32_t *ctl = at<uint32_t>(ws, L.ctl);
+    int32_t *status = (int32_t *)ctl + kCtlStatus;
+    unsigned long long *total = (unsigned long long *)d_total;
+    unsigned long long *tpv = at<unsigned long long>(ws, L.tpv);
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, total, (uint64_t)1);
+    TC_LAUNCH_CHECK();
+    if (pv && n > 0) {
+        hipLaunchKernelGGL(k_zero_u64, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, tpv,
+                           (uint64_t)n);
+        TC_LAUNCH_CHECK();
+    }
+    if (L.mf > 0) {
+        TC_HIP(fill_u32(ctl + kCtlQueueA, 0u, 2, s));
+        const int a0 = pv ? 2 : 0, b0 = pv ? 3 : 1;
+        CountArgs a;
+        a.row_ptr = at<uint32_t>(ws, L.row_ptr);
+        a.col = at<uint32_t>(ws, L.col);
+        a.cptr = at<uint32_t>(ws, L.cptr);
+        a.cbeg = at<uint32_t>(ws, L.cbeg);
+        a.cend = at<uint32_t>(ws, L.cend);
+        a.cu = at<uint32_t>(ws, L.cu);
+        a.item_v_a = at<uint32_t>(ws, L.item_v[a0]);
+        a.item_off_a = at<uint32_t>(ws, L.off[a0]);
+        a.n_items_a = a.item_off_a + n;
+        a.item_v_b = at<uint32_t>(ws, L.item_v[b0]);
+        a.item_off_b = at<uint32_t>(ws, L.off[b0]);
+        a.n_items_b = a.item_off_b + n;
+        a.queue_a = ctl + kCtlQueueA;
+        a.queue_b = ctl + kCtlQueueB;
+        a.total = total;
+        a.tpv = tpv;
+        a.status = status;
+        TC_HIP(launch_count(a, pv, s));
+    }
+    if (pv && n > 0) {
+        hipLaunchKernelGGL(k_pv_out, dim3(grid_for(n, 256)), dim3(256), 0, s, tpv,
+                           at<uint32_t>(ws, L.perm), n, (unsigned long long *)d_pv);
+        TC_LAUNCH_CHECK();
+    }
+    return TC_OK;
+}
+
+static int copy_status(void *ws, const Layout &L, int32_t *d_status, hipStream_t s) {
+    if (!d_status) return TC_OK;
+    hipLaunchKernelGGL(k_copy_status, dim3(1), dim3(64), 0, s, at<int32_t>(ws, L.ctl), d_status);
+    TC_LAUNCH_CHECK();
+    return TC_OK;
+}
+
+static int run_count(const int32_t *d_edges, int64_t n, int64_t m, uint32_t flags, void *ws,
+                     size_t ws_bytes, hipStream_t s, uint64_t *d_total, uint64_t *d_pv,
+                     int32_t *d_status) {
+    Layout L;
+    int st = check_args(d_edges, n, m, flags, ws, ws_bytes, L);
+    if (st) return st;
+    if (!d_total) return TC_E_ARG;
+    st = run_preprocess(d_edges, flags, ws, L, s);
+    if (st) return st;
+    st = run_count_prepared(ws, L, s, d_total, L.n > 0 ? d_pv : nullptr);
+    if (st) return st;
+    return copy_status(ws, L, d_status, s);
+}
+
+}  // namespace tc
+
+using namespace tc;
+
+extern "C" {
+
+const char *tc_strerror(int status) {
+    switch (status) {
+        case TC_OK: return "ok";
+        case TC_E_ARG: return "invalid argument";
+        case TC_E_RANGE: return "vertex id out of range";
+        case TC_E_SELF_LOOP: return "self-loop";
+        case TC_E_DUP_EDGE: return "duplicate edge";
+        case TC_E_ASYMMETRIC: return "two-direction edge array without matching mirror entries";
+        case TC_E_UNSORTED: return "adjacency row not strictly ascending";
+        case TC_E_WORKSPACE: return "workspace too small or misaligned";
+        case TC_E_TOO_LARGE: return "graph too large for 32-bit indices";
+        case TC_E_HIP: return "HIP runtime error";
+        default: return "unknown status";
+    }
+}
+
+size_t tc_workspace_size(int64_t n, int64_t m, uint32_t flags) {
+    Layout L;
+    if (!make_layout(n, m, flags, L)) return 0;
+    return L.total_bytes;
+}
+
+int tc_workspace_layout(int64_t n, int64_t m, uint32_t flags, tc_layout *out) {
+    Layout L;
+    if (!out) return TC_E_ARG;
+    if (!make_layout(n, m, flags, L)) return TC_E_ARG;
+    out->deg = L.deg;
+    out->perm = L.perm;
+    out->rank = L.rank;
+    out->row_ptr = L.row_ptr;
+    out->col = L.col;
+    out->m_fwd = L.mf;
+    out->id_bits = (int32_t)L.id_bits;
+    return TC_OK;
+}
+
+int tc_count(const int32_t *d_edges, int64_t n, int64_t m, uint32_t flags, void *d_ws,
+             size_t ws_bytes, void *stream, uint64_t *d_total, int32_t *d_status) {
+    return run_count(d_edges, n, m, flags, d_ws, ws_bytes, (hipStream_t)stream, d_total,
+                     nullptr, d_status);
+}
+
+int tc_count_per_vertex(const int32_t *d_edges, int64_t n, int64_t m, uint32_t flags,
+                        void *d_ws, size_t ws_bytes, void *stream, uint64_t *d_total,
+                        uint64_t *d_per_vertex, int32_t *d_status) {
+    if (!d_per_vertex && n > 0) return TC_E_ARG;
+    return run_count(d_edges, n, m, flags, d_ws, ws_bytes, (hipStream_t)stream, d_total,
+                     d_per_vertex, d_status);
+}
+
+int tc_preprocess(const int32_t *d_edges, int64_t n, int64_t m, uint32_t flags, void *d_ws,
+                  size_t ws_bytes, void *stream, int32_t *d_status) {
+    Layout L;
+    int st = check_args(d_edges, n, m, flags, d_ws, ws_bytes, L);
+    if (st) return st;
+    st = run_preprocess(d_edges, flags, d_ws, L, (hipStream_t)stream);
+    if (st) return st;
+    return copy_status(d_ws, L, d_status, (hipStream_t)stream);
+}
+
+int tc_count_prepared(int64_t n, int64_t m, uint32_t flags, void *d_ws, size_t ws_bytes,
+                      void *stream, uint64_t *d_total, uint64_t *d_per_vertex,
+                      int32_t *d_status) {
+    Layout L;
+    if (n < 0 || m < 0 || (flags & ~TC_EDGES_BOTH)) return TC_E_ARG;
+    if (n >= (1ll << 31) || m >= (1ll << 32)) return TC_E_TOO_LARGE;
+    if (!make_layout(n, m, flags, L) || !d_total) return TC_E_ARG;
+    if (!d_ws || ((uintptr_t)d_ws & 255) || ws_bytes < L.total_bytes) return TC_E_WORKSPACE;
+    int st = run_count_prepared(d_ws, L, (hipStream_t)stream, d_total,
+                                L.n > 0 ? d_per_vertex : nullptr);
+    if (st) return st;
+    return copy_status(d_ws, L, d_status, (hipStream_t)stream);
+}
+
+size_t tc_sort_workspace_size(int64_t count) {
+    if (count < 0 || count >= (1ll << 32)) return 0;
+    return sort_scratch_bytes((uint64_t)count);
+}
+
+int tc_sort_u64(uint64_t *d_keys, uint64_t *d_tmp, int64_t count, int32_t bits, void *d_ws,
+                size_t ws_bytes, void *stream) {
+    if (count < 0 || bits < 1 || bits > 64) return TC_E_ARG;
+    if (count >= (1ll << 32)) return TC_E_TOO_LARGE;
+    if (count > 0 && (!d_keys || !d_tmp)) return TC_E_ARG;
+    if (!d_ws || ((uintptr_t)d_ws & 255) || ws_bytes < sort_scratch_bytes((uint64_t)count))
+        return TC_E_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    uint64_t *res = nullptr;
+    TC_HIP(sort_u64(d_keys, d_tmp, (uint32_t)count, 0, bits, d_ws, nullptr, s, &res));
+    if (res != d_keys)
+        TC_HIP(hipMemcpyAsync(d_keys, res, (size_t)count * 8, hipMemcpyDeviceToDevice, s));
+    return TC_OK;
+}
+
+}  // extern "C"

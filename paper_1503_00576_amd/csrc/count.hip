@@ -1,0 +1,323 @@
+// Counting phase (Section 2.2 and Section 3.3): the sum over oriented edges u -> v of
+// |N+(u) n N+(v)|.
+//
+// Vertices are ranks in the order of Section 2.2, so every list N+(x) holds only ranks > x
+// and is sorted ascending.  For an edge u -> v, every common element w of the two lists is
+// > v, so |N+(u) n N+(v)| = |suffix of N+(u) after v  n  N+(v)|.  The kernel therefore groups
+// the work by the middle vertex v: N+(v) is staged once in LDS and the suffixes of the lists
+// of all in-neighbours u of v are streamed through it.  The number of membership tests is
+// sum_u C(d+(u), 2) instead of the sum of the lengths of both lists per edge; each test is
+// one LDS bit lookup when N+(v) fits a bitmap over its rank range.
+//
+// Work items are (v, a chunk of v's in-edges).  One persistent kernel pulls items from two
+// device counters: first the "workgroup" items (out-lists whose rank span needs the
+// workgroup's whole LDS bitmap, or a sorted list), cooperatively, then the "wave" items, each
+// wave with its own slice of LDS.  Items run heaviest (highest-rank) vertices first.  Inside a
+// wave every in-edge suffix is cut into pieces of kPiece consecutive elements and each lane
+// runs whole pieces, so one load and one lookup per element are the per-element costs,
+// whatever the spread of suffix lengths.
+//
+// Per-vertex counts (T(x) = triangles through x) use sorted lists in LDS instead of bitmaps
+// so that a hit's position indexes an LDS counter: T(w) for the third vertex is flushed once
+// per item, T(u) once per in-edge, T(v) once per item and wave.
+#include "internal.h"
+
+namespace tc {
+
+constexpr uint32_t kPiece = 16;
+constexpr int kThreads = 512;
+constexpr int kWaves = kThreads / kWave;
+constexpr uint32_t kLdsWords = 16384;                 // 64 KiB per workgroup
+constexpr uint32_t kSliceWords = kLdsWords / kWaves;  // 8 KiB per wave
+constexpr uint32_t kWaveBits = kSliceWords * 32;      // wave bitmap: rank span < 65536
+constexpr uint32_t kWaveListPV = kSliceWords / 2;     // per-vertex: list + counters per wave
+constexpr uint32_t kBlockBits = kLdsWords * 32;       // workgroup bitmap: span < 524288
+constexpr uint32_t kBlockList = kLdsWords;            // workgroup sorted list
+constexpr uint32_t kBlockListPV = kLdsWords / 2;      // per-vertex: list + counters
+constexpr uint32_t kItemEdgesWave = 256;
+constexpr uint32_t kItemEdgesBlock = 2048;
+
+// ------------------------------------------------------------------ membership probes
+
+struct BitmapProbe {
+    const uint32_t *bm;
+    uint32_t lo, span;  // bitmap covers ranks [lo, lo + span]
+    __device__ __forceinline__ bool operator()(uint32_t w, uint32_t &) const {
+        uint32_t o = w - lo;
+        return o <= span && ((bm[o >> 5] >> (o & 31u)) & 1u);
+    }
+};
+
+// lower_bound with a lane-independent trip count (d is uniform)
+__device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t *list, uint32_t d,
+                                                    uint32_t w) {
+    uint32_t base = 0, len = d;
+    while (len > 1) {
+        uint32_t half = len >> 1;
+        base = (list[base + half - 1] < w) ? base + half : base;
+        len -= half;
+    }
+    return base + ((len == 1 && list[base] < w) ? 1u : 0u);
+}
+
+struct ListProbe {  // sorted list in LDS or in global memory
+    const uint32_t *list;
+    uint32_t d;
+    __device__ __forceinline__ bool operator()(uint32_t w, uint32_t &pos) const {
+        pos = lower_bound_u32(list, d, w);
+        return pos < d && list[pos] == w;
+    }
+};
+
+// ------------------------------------------------------------------ per-batch streaming
+
+struct WaveScratch {
+    uint32_t off[kWave], beg[kWave], end[kWave], cnt[kWave], u[kWave];
+};
+
+// The calling wave processes in-edges [eb, min(eb + 64, e1)) of the current item and returns
+// this lane's hits.  PV: per-vertex accumulation -- LDS counters `tcnt` indexed by the probe's
+// position when `tcnt` is non-null, global atomics on `tpv` otherwise.
+template <bool PV, class Probe>
+__device__ __forceinline__ uint32_t run_batch(uint32_t eb, uint32_t e1,
+                                              const uint32_t *__restrict__ cbeg,
+                                              const uint32_t *__restrict__ cend,
+                                              const uint32_t *__restrict__ cu,
+                                              const uint32_t *__restrict__ col, const Probe &probe,
+                                              WaveScratch &ws, uint32_t *tcnt,
+                                              unsigned long long *__restrict__ tpv) {
+    const uint32_t lane = lane_id();
+    const uint32_t e = eb + lane;
+    const bool valid = e < e1;
+    uint32_t b = 0, en = 0;
+    if (valid) {
+        b = cbeg[e];
+        en = cend[e];
+    }
+    const uint32_t p = (en - b + kPiece - 1) / kPiece;
+    const uint32_t incl = wave_incl_scan(p);
+    const uint32_t Q = wave_bcast(incl, kWave - 1);
+    ws.off[lane] = incl - p;
+    ws.beg[lane] = b;
+    ws.end[lane] = en;
+    if (PV) {
+        ws.cnt[lane] = 0;
+        ws.u[lane] = valid ? cu[e] : 0u;
+    }
+    wave_lds_sync();
+    uint32_t hits_total = 0;
+    for (uint32_t q0 = 0; q0 < Q; q0 += kWave) {
+        const uint32_t q = q0 + lane;
+        if (q < Q) {
+            // owner: the last in-edge whose first piece is <= q (zero-piece lanes share the
+            // offset of the next lane and lose to it)
+            uint32_t k = 0;
+#pragma unroll
+            for (uint32_t step = 32; step; step >>= 1)
+                if (ws.off[k + step] <= q) k += step;
+            const uint32_t start = ws.beg[k] + (q - ws.off[k]) * kPiece;
+            const uint32_t stop = min(start + kPiece, ws.end[k]);
+            uint32_t hits = 0;
+#pragma unroll
+            for (uint32_t i = 0; i < kPiece; ++i) {
+                const uint32_t idx = start + i;
+                if (idx < stop) {
+                    const uint32_t w = col[idx];
+                    uint32_t pos;
+                    if (probe(w, pos)) {
+                        ++hits;
+                        if (PV) {
+                            if (tcnt) atomicAdd(&tcnt[pos], 1u);
+                            else atomicAdd(&tpv[w], 1ull);
+                        }
+                    }
+                }
+            }
+            hits_total += hits;
+            if (PV && hits) atomicAdd(&ws.cnt[k], hits);
+        }
+    }
+    wave_lds_sync();
+    if (PV) {
+        if (ws.cnt[lane]) atomicAdd(&tpv[ws.u[lane]], (unsigned long long)ws.cnt[lane]);
+        wave_lds_sync();
+    }
+    return hits_total;
+}
+
+struct ItemRange {
+    uint32_t v, e0, e1, r0, d;
+};
+
+__device__ __forceinline__ ItemRange item_range(uint32_t q, uint32_t kitem,
+                                                const uint32_t *__restrict__ item_v,
+                                                const uint32_t *__restrict__ item_off,
+                                                const uint32_t *__restrict__ cptr,
+                                                const uint32_t *__restrict__ row_ptr) {
+    ItemRange it;
+    it.v = item_v[q];
+    const uint32_t chunk = q - item_off[it.v];
+    const uint32_t c1 = cptr[it.v + 1];
+    it.e0 = cptr[it.v] + chunk * kitem;
+    it.e1 = min(it.e0 + kitem, c1);
+    it.r0 = row_ptr[it.v];
+    it.d = row_ptr[it.v + 1] - it.r0;
+    return it;
+}
+
+// ------------------------------------------------------------------ the kernel
+
+template <bool PV>
+__global__ __launch_bounds__(kThreads) void k_count(
+    const uint32_t *__restrict__ row_ptr, const uint32_t *__restrict__ col,
+    const uint32_t *__restrict__ cptr, const uint32_t *__restrict__ cbeg,
+    const uint32_t *__restrict__ cend, const uint32_t *__restrict__ cu,
+    const uint32_t *__restrict__ item_v_a, const uint32_t *__restrict__ item_off_a,
+    const uint32_t *__restrict__ n_items_a_ptr, const uint32_t *__restrict__ item_v_b,
+    const uint32_t *__restrict__ item_off_b, const uint32_t *__restrict__ n_items_b_ptr,
+    uint32_t *__restrict__ queue_a, uint32_t *__restrict__ queue_b,
+    unsigned long long *__restrict__ total, unsigned long long *__restrict__ tpv,
+    const int32_t *__restrict__ status) {
+    __shared__ uint32_t s_mem[kLdsWords];
+    __shared__ WaveScratch s_ws[kWaves];
+    __shared__ uint32_t s_item;
+    if (*status) return;
+    const uint32_t t = threadIdx.x, w = t / kWave, lane = lane_id();
+    WaveScratch &ws = s_ws[w];
+    for (uint32_t i = t; i < kLdsWords; i += kThreads) s_mem[i] = 0;
+    uint64_t acc = 0;
+
+    // phase 1: workgroup items
+    const uint32_t n_items_b = *n_items_b_ptr;
+    for (;;) {
+        __syncthreads();
+        if (t == 0) s_item = atomicAdd(queue_b, 1u);
+        __syncthreads();
+        uint32_t q = s_item;
+        if (q >= n_items_b) break;
+        q = n_items_b - 1 - q;
+        const ItemRange it = item_range(q, kItemEdgesBlock, item_v_b, item_off_b, cptr, row_ptr);
+        const uint32_t lo = col[it.r0];
+        const uint32_t span = col[it.r0 + it.d - 1] - lo;
+        // 0 = bitmap, 1 = LDS list, 2 = global list
+        const int mode = (!PV && span < kBlockBits) ? 0
+                         : (it.d <= (PV ? kBlockListPV : kBlockList)) ? 1 : 2;
+        if (mode == 0) {
+            for (uint32_t i = t; i < it.d; i += kThreads) {
+                const uint32_t o = col[it.r0 + i] - lo;
+                atomicOr(&s_mem[o >> 5], 1u << (o & 31u));
+            }
+        } else if (mode == 1) {
+            for (uint32_t i = t; i < it.d; i += kThreads) s_mem[i] = col[it.r0 + i];
+        }
+        __syncthreads();
+        uint32_t cnt = 0;
+        const uint32_t first = it.e0 + w * kWave, step = kWaves * kWave;
+        if (mode == 0) {
+            const BitmapProbe probe{s_mem, lo, span};
+            for (uint32_t eb = first; eb < it.e1; eb += step)
+                cnt += run_batch<PV>(eb, it.e1, cbeg, cend, cu, col, probe, ws, nullptr, tpv);
+        } else if (mode == 1) {
+            const ListProbe probe{s_mem, it.d};
+            uint32_t *tc = PV ? s_mem + kBlockListPV : nullptr;
+            for (uint32_t eb = first; eb < it.e1; eb += step)
+                cnt += run_batch<PV>(eb, it.e1, cbeg, cend, cu, col, probe, ws, tc, tpv);
+        } else {
+            const ListProbe probe{col + it.r0, it.d};
+            for (uint32_t eb = first; eb < it.e1; eb += step)
+                cnt += run_batch<PV>(eb, it.e1, cbeg, cend, cu, col, probe, ws, nullptr, tpv);
+        }
+        if (PV) {
+            uint64_t wave_hits = wave_sum_u64(cnt);
+            if (lane == 0 && wave_hits) atomicAdd(&tpv[it.v], (unsigned long long)wave_hits);
+        }
+        acc += cnt;
+        __syncthreads();
+        if (mode == 0) {
+            for (uint32_t i = t; i < it.d; i += kThreads) s_mem[(col[it.r0 + i] - lo) >> 5] = 0;
+        } else if (mode == 1) {
+            for (uint32_t i = t; i < it.d; i += kThreads) {
+                s_mem[i] = 0;
+                if (PV) {
+                    uint32_t c = s_mem[kBlockListPV + i];
+                    if (c) {
+                        atomicAdd(&tpv[col[it.r0 + i]], (unsigned long long)c);
+                        s_mem[kBlockListPV + i] = 0;
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // phase 2: wave items, each wave in its own LDS slice
+    uint32_t *mem = s_mem + w * kSliceWords;
+    const uint32_t n_items_a = *n_items_a_ptr;
+    for (;;) {
+        uint32_t q = 0;
+        if (lane == 0) q = atomicAdd(queue_a, 1u);
+        q = wave_bcast(q, 0);
+        if (q >= n_items_a) break;
+        q = n_items_a - 1 - q;
+        const ItemRange it = item_range(q, kItemEdgesWave, item_v_a, item_off_a, cptr, row_ptr);
+        uint32_t cnt = 0;
+        if (!PV) {
+            const uint32_t lo = col[it.r0];
+            const uint32_t span = col[it.r0 + it.d - 1] - lo;
+            for (uint32_t i = lane; i < it.d; i += kWave) {
+                const uint32_t o = col[it.r0 + i] - lo;
+                atomicOr(&mem[o >> 5], 1u << (o & 31u));
+            }
+            wave_lds_sync();
+            const BitmapProbe probe{mem, lo, span};
+            for (uint32_t eb = it.e0; eb < it.e1; eb += kWave)
+                cnt += run_batch<false>(eb, it.e1, cbeg, cend, cu, col, probe, ws, nullptr, tpv);
+            for (uint32_t i = lane; i < it.d; i += kWave) mem[(col[it.r0 + i] - lo) >> 5] = 0;
+            wave_lds_sync();
+        } else {
+            uint32_t *list = mem, *tc = mem + kWaveListPV;
+            for (uint32_t i = lane; i < it.d; i += kWave) list[i] = col[it.r0 + i];
+            wave_lds_sync();
+            const ListProbe probe{list, it.d};
+            for (uint32_t eb = it.e0; eb < it.e1; eb += kWave)
+                cnt += run_batch<true>(eb, it.e1, cbeg, cend, cu, col, probe, ws, tc, tpv);
+            for (uint32_t i = lane; i < it.d; i += kWave) {
+                uint32_t c = tc[i];
+                if (c) {
+                    atomicAdd(&tpv[list[i]], (unsigned long long)c);
+                    tc[i] = 0;
+                }
+            }
+            uint64_t item_hits = wave_sum_u64(cnt);
+            if (lane == 0 && item_hits) atomicAdd(&tpv[it.v], (unsigned long long)item_hits);
+            wave_lds_sync();
+        }
+        acc += cnt;
+    }
+    acc = wave_sum_u64(acc);
+    if (lane == 0 && acc) atomicAdd(total, (unsigned long long)acc);
+}
+
+// ------------------------------------------------------------------ host side
+
+uint32_t count_wave_span(bool per_vertex) { return per_vertex ? 0u : kWaveBits; }
+uint32_t count_wave_list(bool per_vertex) { return per_vertex ? kWaveListPV : 0u; }
+uint32_t count_item_edges_wave() { return kItemEdgesWave; }
+uint32_t count_item_edges_block() { return kItemEdgesBlock; }
+
+hipError_t launch_count(const CountArgs &x, bool per_vertex, hipStream_t s) {
+    const dim3 grid(device_cu_count() * 2), block(kThreads);
+    if (per_vertex)
+        hipLaunchKernelGGL(k_count<true>, grid, block, 0, s, x.row_ptr, x.col, x.cptr, x.cbeg,
+                           x.cend, x.cu, x.item_v_a, x.item_off_a, x.n_items_a, x.item_v_b,
+                           x.item_off_b, x.n_items_b, x.queue_a, x.queue_b, x.total, x.tpv,
+                           x.status);
+    else
+        hipLaunchKernelGGL(k_count<false>, grid, block, 0, s, x.row_ptr, x.col, x.cptr, x.cbeg,
+                           x.cend, x.cu, x.item_v_a, x.item_off_a, x.n_items_a, x.item_v_b,
+                           x.item_off_b, x.n_items_b, x.queue_a, x.queue_b, x.total, x.tpv,
+                           x.status);
+    return hipGetLastError();
+}
+
+}  // namespace tc

@@ -1,0 +1,96 @@
+// Internal declarations shared by the HIP translation units of libtc.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/tc.h"
+
+namespace tc {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------- device helpers
+
+__device__ __forceinline__ uint32_t lane_id() {
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+// number of set bits of `mask` at lanes below the calling lane
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Orders this wave's LDS accesses before the ones that follow (all lanes of a wave).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint32_t wave_bcast(uint32_t x, int src) {
+    return (uint32_t)__shfl((int)x, src, kWave);
+}
+
+// inclusive prefix sum over the 64 lanes (inactive lanes must hold 0 and be active)
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    const uint32_t l = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        uint32_t y = (uint32_t)__shfl_up((int)x, d, kWave);
+        if (l >= (uint32_t)d) x += y;
+    }
+    return x;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) {
+        uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, d, kWave);
+        uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), d, kWave);
+        x += ((uint64_t)hi << 32) | lo;
+    }
+    return x;
+}
+
+__device__ __forceinline__ void set_status(int32_t *st, int32_t code) {
+    atomicCAS(st, 0, code);
+}
+
+// ---------------------------------------------------------------- host helpers
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+inline uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+
+// exclusive scan of uint32 (in may equal out); scratch: scan_scratch_words(N) words
+size_t scan_scratch_words(uint64_t N);
+hipError_t scan_exclusive_u32(const uint32_t *in, uint32_t *out, uint32_t N, uint32_t *scratch,
+                              hipStream_t s);
+
+// radix sort: result lands in *result (== keys or tmp); scratch: sort_scratch_bytes(count)
+size_t sort_scratch_bytes(uint64_t count);
+hipError_t sort_u64(uint64_t *keys, uint64_t *tmp, uint32_t count, int lo_bit, int hi_bit,
+                    void *scratch, const int32_t *status, hipStream_t s, uint64_t **result);
+
+hipError_t fill_u32(uint32_t *p, uint32_t value, uint64_t count, hipStream_t s);
+
+int device_cu_count();
+
+// counting kernels (count.hip)
+struct CountArgs {
+    const uint32_t *row_ptr, *col, *cptr, *cbeg, *cend, *cu;
+    const uint32_t *item_v_a, *item_off_a, *n_items_a;
+    const uint32_t *item_v_b, *item_off_b, *n_items_b;
+    uint32_t *queue_a, *queue_b;
+    unsigned long long *total, *tpv;
+    const int32_t *status;
+};
+hipError_t launch_count(const CountArgs &a, bool per_vertex, hipStream_t s);
+uint32_t count_wave_span(bool per_vertex);
+uint32_t count_wave_list(bool per_vertex);
+uint32_t count_item_edges_wave();
+uint32_t count_item_edges_block();
+
+}  // namespace tc

@@ -1,0 +1,235 @@
+// Device-wide exclusive scan and stable LSD radix sort of uint64 keys.
+//
+// The sort replaces the library sort of packed 64-bit edge keys in the preprocessing phase
+// (Section 3.2, step 3, and the note on sorting edges as 64-bit integers): keys are ordered
+// on a bit range [lo_bit, hi_bit) with 8-bit digits, least significant digit first; every
+// pass is an upsweep (per-tile digit histograms), an exclusive scan of the digit-major
+// histogram table, and a stable scatter in which a wave ranks equal digits with ballots.
+#include "internal.h"
+
+namespace tc {
+
+// ======================================================================= fill
+
+__global__ void k_fill_u32(uint32_t *__restrict__ p, uint32_t value, uint64_t count) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (; i < count; i += stride) p[i] = value;
+}
+
+hipError_t fill_u32(uint32_t *p, uint32_t value, uint64_t count, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    uint64_t blocks = (count + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)blocks), dim3(256), 0, s, p, value, count);
+    return hipGetLastError();
+}
+
+// ======================================================================= scan
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;  // 4096
+
+__device__ __forceinline__ uint32_t pad_idx(uint32_t i) { return i + (i >> 5); }
+
+// Block-level exclusive scan of one 4096-element tile.
+//   mode 0: write only the tile total to sums[blockIdx.x]
+//   mode 1: write the exclusive scan, offset by carry[blockIdx.x] (if carry != nullptr)
+__global__ __launch_bounds__(kScanThreads) void k_scan_tile(const uint32_t *__restrict__ in,
+                                                            uint32_t *__restrict__ out,
+                                                            uint32_t N, int mode,
+                                                            uint32_t *__restrict__ sums,
+                                                            const uint32_t *__restrict__ carry) {
+    __shared__ uint32_t s[kScanTile + kScanTile / 32];
+    __shared__ uint32_t s_wave[kScanThreads / kWave];
+    const uint32_t t = threadIdx.x;
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        uint32_t i = j * kScanThreads + t;
+        s[pad_idx(i)] = (base + i < N) ? in[base + i] : 0u;
+    }
+    __syncthreads();
+    uint32_t v[kScanItems];
+    uint32_t run = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        v[j] = run;
+        run += s[pad_idx(t * kScanItems + j)];
+    }
+    uint32_t incl = wave_incl_scan(run);
+    const uint32_t w = t / kWave;
+    if (lane_id() == kWave - 1) s_wave[w] = incl;
+    __syncthreads();
+    uint32_t wave_off = 0, total = 0;
+#pragma unroll
+    for (int k = 0; k < kScanThreads / kWave; ++k) {
+        if ((uint32_t)k < w) wave_off += s_wave[k];
+        total += s_wave[k];
+    }
+    if (mode == 0) {
+        if (t == 0) sums[blockIdx.x] = total;
+        return;
+    }
+    uint32_t off = (incl - run) + wave_off + (carry ? carry[blockIdx.x] : 0u);
+    // all reads of s above happened before the barrier below
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) s[pad_idx(t * kScanItems + j)] = v[j] + off;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        uint32_t i = j * kScanThreads + t;
+        if (base + i < N) out[base + i] = s[pad_idx(i)];
+    }
+}
+
+size_t scan_scratch_words(uint64_t N) {
+    uint64_t nb = (N + kScanTile - 1) / kScanTile;
+    uint64_t words = nb + 1;
+    if (nb > 1) words += scan_scratch_words(nb);
+    return (size_t)align_up(words, 64);
+}
+
+hipError_t scan_exclusive_u32(const uint32_t *in, uint32_t *out, uint32_t N, uint32_t *scratch,
+                              hipStream_t s) {
+    if (N == 0) return hipSuccess;
+    uint32_t nb = ceil_div(N, kScanTile);
+    if (nb == 1) {
+        hipLaunchKernelGGL(k_scan_tile, dim3(1), dim3(kScanThreads), 0, s, in, out, N, 1,
+                           (uint32_t *)nullptr, (const uint32_t *)nullptr);
+        return hipGetLastError();
+    }
+    uint32_t *sums = scratch;
+    uint32_t *rest = scratch + align_up((size_t)nb + 1, 64);
+    hipLaunchKernelGGL(k_scan_tile, dim3(nb), dim3(kScanThreads), 0, s, in, out, N, 0, sums,
+                       (const uint32_t *)nullptr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = scan_exclusive_u32(sums, sums, nb, rest, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan_tile, dim3(nb), dim3(kScanThreads), 0, s, in, out, N, 1,
+                       (uint32_t *)nullptr, (const uint32_t *)sums);
+    return hipGetLastError();
+}
+
+// ======================================================================= radix sort
+
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;  // 4096 keys per tile
+constexpr int kSortWaves = kSortThreads / kWave;
+
+// Lanes holding the same digit: returns the mask of such (valid) lanes.
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, uint32_t nbits, bool valid) {
+    uint64_t peers = __ballot(valid);
+    for (uint32_t b = 0; b < nbits; ++b) {
+        uint64_t bb = __ballot((d >> b) & 1u);
+        peers &= ((d >> b) & 1u) ? bb : ~bb;
+    }
+    return peers;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t *__restrict__ in,
+                                                             uint32_t count, int shift,
+                                                             uint32_t nbits,
+                                                             uint32_t *__restrict__ hist,
+                                                             uint32_t tiles,
+                                                             const int32_t *__restrict__ status) {
+    if (status && *status) return;
+    __shared__ uint32_t h[kSortWaves][256];
+    const uint32_t t = threadIdx.x, w = t / kWave;
+    for (int k = 0; k < kSortWaves; ++k) h[k][t] = 0;
+    __syncthreads();
+    const uint32_t mask = (1u << nbits) - 1u;
+    const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+#pragma unroll 4
+    for (int r = 0; r < kSortItems; ++r) {
+        uint64_t idx = base + (uint64_t)r * kSortThreads + t;
+        bool valid = idx < count;
+        uint32_t d = valid ? (uint32_t)(in[idx] >> shift) & mask : 0u;
+        uint64_t peers = match_digit(d, nbits, valid);
+        if (valid && lanes_below(peers) == 0) h[w][d] += (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    uint32_t sum = 0;
+    for (int k = 0; k < kSortWaves; ++k) sum += h[k][t];
+    hist[(uint64_t)t * tiles + blockIdx.x] = sum;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
+    const uint64_t *__restrict__ in, uint64_t *__restrict__ out, uint32_t count, int shift,
+    uint32_t nbits, const uint32_t *__restrict__ offs, uint32_t tiles,
+    const int32_t *__restrict__ status) {
+    if (status && *status) return;
+    __shared__ uint32_t s_base[256];
+    __shared__ uint32_t s_wcnt[kSortWaves][256];
+    const uint32_t t = threadIdx.x, w = t / kWave;
+    s_base[t] = offs[(uint64_t)t * tiles + blockIdx.x];
+    for (int k = 0; k < kSortWaves; ++k) s_wcnt[k][t] = 0;
+    __syncthreads();
+    const uint32_t mask = (1u << nbits) - 1u;
+    const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+    for (int r = 0; r < kSortItems; ++r) {
+        uint64_t idx = base + (uint64_t)r * kSortThreads + t;
+        bool valid = idx < count;
+        uint64_t key = valid ? in[idx] : 0ull;
+        uint32_t d = (uint32_t)(key >> shift) & mask;
+        uint64_t peers = match_digit(d, nbits, valid);
+        uint32_t rank = lanes_below(peers);
+        if (valid && rank == 0) s_wcnt[w][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = s_base[d] + rank;
+            for (uint32_t k = 0; k < w; ++k) pos += s_wcnt[k][d];
+            out[pos] = key;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+        for (int k = 0; k < kSortWaves; ++k) {
+            add += s_wcnt[k][t];
+            s_wcnt[k][t] = 0;
+        }
+        s_base[t] += add;
+        __syncthreads();
+    }
+}
+
+size_t sort_scratch_bytes(uint64_t count) {
+    uint64_t tiles = (count + kSortTile - 1) / kSortTile;
+    if (tiles == 0) tiles = 1;
+    uint64_t hist = 256 * tiles;
+    return align_up(hist * 4, 256) + align_up(scan_scratch_words(hist) * 4, 256);
+}
+
+hipError_t sort_u64(uint64_t *keys, uint64_t *tmp, uint32_t count, int lo_bit, int hi_bit,
+                    void *scratch, const int32_t *status, hipStream_t s, uint64_t **result) {
+    *result = keys;
+    if (count <= 1 || hi_bit <= lo_bit) return hipSuccess;
+    uint32_t tiles = ceil_div(count, kSortTile);
+    uint64_t hist_n = 256ull * tiles;
+    uint32_t *hist = (uint32_t *)scratch;
+    uint32_t *scan_scratch = (uint32_t *)((char *)scratch + align_up(hist_n * 4, 256));
+    uint64_t *src = keys, *dst = tmp;
+    for (int shift = lo_bit; shift < hi_bit; shift += 8) {
+        uint32_t nbits = (uint32_t)((hi_bit - shift) < 8 ? (hi_bit - shift) : 8);
+        hipLaunchKernelGGL(k_radix_hist, dim3(tiles), dim3(kSortThreads), 0, s, src, count,
+                           shift, nbits, hist, tiles, status);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        e = scan_exclusive_u32(hist, hist, (uint32_t)hist_n, scan_scratch, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_radix_scatter, dim3(tiles), dim3(kSortThreads), 0, s, src, dst,
+                           count, shift, nbits, hist, tiles, status);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        uint64_t *x = src;
+        src = dst;
+        dst = x;
+    }
+    *result = src;
+    return hipSuccess;
+}
+
+}  // namespace tc

@@ -1,0 +1,253 @@
+"""GPU parity: the HIP path (through libtc.so's C ABI) against the CPU oracle, bit-exact.
+
+Integer results, so the bar is equality: totals, per-vertex counts, the degree array, the
+order, the oriented sorted lists, the sort.  Sizes span several tiles and ragged tails; the
+full-size R-MAT case is checked against the oracle's stored total and sampled per-vertex
+values computed one vertex at a time from the definition."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1503_00576_amd import api, synth
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEV = "cuda:0"
+
+
+def golden():
+    with open(os.path.join(HERE, "golden", "workloads.json")) as f:
+        return json.load(f)
+
+
+def gpu_counts(edges_np, n, both=False, per_vertex=True):
+    e = torch.as_tensor(np.ascontiguousarray(np.asarray(edges_np, dtype=np.int32).reshape(-1, 2)),
+                        device=DEV)
+    if per_vertex:
+        tot, pv = api.count_per_vertex(e, n, both)
+        return tot, pv.cpu().numpy().astype(np.uint64)
+    return api.count(e, n, both), None
+
+
+def check_vs_oracle(edges_np, n, both=False):
+    e = np.asarray(edges_np, dtype=np.int32).reshape(-1, 2)
+    ot, opv = oracle.count(e, n, both=both, per_vertex=True)
+    gt, gpv = gpu_counts(e, n, both)
+    assert gt == ot
+    assert np.array_equal(gpv, opv)
+    assert api.count(torch.as_tensor(e, device=DEV), n, both) == ot
+    return ot
+
+
+def complete(k):
+    return [(i, j) for i in range(k) for j in range(i + 1, k)]
+
+
+# ------------------------------------------------------------------ small / closed forms
+
+def test_closed_forms_and_named():
+    for k in [0, 1, 2, 3, 4, 5, 17, 64, 65, 130]:
+        assert check_vs_oracle(complete(k) or np.zeros((0, 2)), k) == math.comb(k, 3)
+    for n in [5, 6, 100, 1000]:
+        rim = list(range(1, n))
+        e = [(0, r) for r in rim] + [(rim[i], rim[(i + 1) % len(rim)]) for i in range(len(rim))]
+        assert check_vs_oracle(e, n) == n - 1
+    e = [(a, b) for a in range(40) for b in range(40, 90)]
+    assert check_vs_oracle(e, 90) == 0
+    with open(os.path.join(HERE, "golden", "named_graphs.json")) as f:
+        for name, g in json.load(f).items():
+            assert check_vs_oracle(g["edges"], g["n"]) == g["total"], name
+
+
+def test_empty_and_isolated():
+    assert check_vs_oracle(np.zeros((0, 2)), 10) == 0
+    assert check_vs_oracle([(3, 7)], 1000) == 0
+    # n = 0, m = 0
+    tot, _ = gpu_counts(np.zeros((0, 2)), 0, per_vertex=False)
+    assert tot == 0
+
+
+def test_random_small_graphs():
+    rng = np.random.default_rng(5)
+    for trial in range(40):
+        n = int(rng.integers(2, 300))
+        p = float(rng.choice([0.01, 0.05, 0.2, 0.6]))
+        iu = np.triu_indices(n, 1)
+        keep = rng.random(iu[0].size) < p
+        e = np.stack([iu[0][keep], iu[1][keep]], 1)
+        e = e[rng.permutation(len(e))]
+        flip = rng.random(len(e)) < 0.5
+        e[flip] = e[flip][:, ::-1]
+        check_vs_oracle(e, n)
+
+
+def test_er_1000_golden():
+    g = golden()["er_1000_p0.02_s0"]
+    e, n = synth.er_1000(device=DEV)
+    assert synth.edges_sha256(e) == g["sha256"]
+    tot, pv = api.count_per_vertex(e, n)
+    assert tot == g["total"]
+    pv = pv.cpu().numpy()
+    for v, want in g["per_vertex_sample"].items():
+        assert pv[int(v)] == want
+    check_vs_oracle(e.cpu().numpy(), n)
+
+
+@pytest.mark.parametrize("scale,ef,seed", [(8, 8, 1), (10, 16, 2), (12, 16, 3), (14, 16, 4), (16, 16, 0)])
+def test_rmat_vs_oracle(scale, ef, seed):
+    e, n = synth.rmat_graph(scale, ef, seed=seed, device=DEV)
+    check_vs_oracle(e.cpu().numpy(), n)
+
+
+@pytest.mark.parametrize("kind,n,k", [(0, 5000, 8), (1, 5000, 8), (0, 20000, 16), (1, 20000, 2)])
+def test_ba_ws_vs_oracle(kind, n, k):
+    e = synth.batch_graph(kind, n, k, seed=11, device=DEV)
+    check_vs_oracle(e.cpu().numpy(), n)
+
+
+def test_two_direction_format():
+    e, n = synth.rmat_graph(12, 16, seed=7)
+    en = e.numpy()
+    both = np.concatenate([en, en[:, ::-1]])[np.random.default_rng(1).permutation(2 * len(en))]
+    t = check_vs_oracle(both, n, both=True)
+    assert t == oracle.count(en, n)
+
+
+def test_repeat_runs_identical():
+    e, n = synth.rmat_graph(14, 16, seed=9, device=DEV)
+    outs = [gpu_counts(e.cpu().numpy(), n) for _ in range(3)]
+    for t, pv in outs[1:]:
+        assert t == outs[0][0] and np.array_equal(pv, outs[0][1])
+
+
+def test_prepared_recount():
+    """A resident preprocessed graph counted repeatedly, with and without per-vertex counts."""
+    e, n = synth.rmat_graph(13, 16, seed=12, device=DEV)
+    ot, opv = oracle.count(e.cpu().numpy(), n, per_vertex=True)
+    p = api.Prepared(e, n)
+    for _ in range(3):
+        assert p.count() == ot
+        r = p.count_async(per_vertex=True).check()
+        assert int(r.total.item()) == ot
+        assert np.array_equal(r.per_vertex.cpu().numpy().astype(np.uint64), opv)
+
+
+# ------------------------------------------------------------------ intermediate stages
+
+def test_preprocess_stages():
+    for e, n in [synth.er_1000(), synth.rmat_graph(13, 16, seed=5), (synth.watts_strogatz(5000, 6, 0.1, 2), 5000)]:
+        en = e.numpy()
+        out = api.preprocess(e.to(DEV), n)
+        deg = out["deg"].cpu().numpy().astype(np.int64)
+        assert np.array_equal(deg, oracle.degrees(en, n))
+        perm = out["perm"].cpu().numpy().astype(np.int64)
+        rank = out["rank"].cpu().numpy().astype(np.int64)
+        # the order of Section 2.2: ascending (degree, id)
+        keyed = deg[perm] * n + perm
+        assert np.all(np.diff(keyed) > 0)
+        assert np.array_equal(rank[perm], np.arange(n))
+        rp = out["row_ptr"].cpu().numpy().astype(np.int64)
+        col = out["col"].cpu().numpy().astype(np.int64)
+        orp, ocol = oracle.oriented_csr(en, n)
+        assert rp[-1] == len(en) == col.size
+        for r in range(n):
+            row = col[rp[r]:rp[r + 1]]
+            assert np.all(np.diff(row) > 0)
+            assert np.all(row > r)
+            v = perm[r]
+            assert sorted(perm[row].tolist()) == ocol[orp[v]:orp[v + 1]].tolist()
+
+
+@pytest.mark.parametrize("count,bits", [(1, 8), (100, 7), (4096, 64), (4097, 40), (100003, 46),
+                                        (1 << 20, 20), (3_000_001, 33)])
+def test_radix_sort(count, bits):
+    g = torch.Generator().manual_seed(count + bits)
+    keys = torch.randint(-(1 << 62), 1 << 62, (count,), generator=g, dtype=torch.int64)
+    if bits < 20:
+        keys = keys & 0xFF  # many equal low bits: stability matters
+    ref = keys.numpy().view(np.uint64)
+    mask = np.uint64((1 << bits) - 1) if bits < 64 else np.uint64(0xFFFFFFFFFFFFFFFF)
+    order = np.argsort(ref & mask, kind="stable")
+    want = ref[order]
+    got = api.sort_u64(keys.to(DEV), bits).cpu().numpy().view(np.uint64)
+    assert np.array_equal(got, want)
+
+
+# ------------------------------------------------------------------ errors
+
+@pytest.mark.parametrize("edges,n,both,name", [
+    ([(0, 1), (1, 5)], 5, False, "range"),
+    ([(0, 1), (-1, 2)], 5, False, "range"),
+    ([(0, 1), (2, 2)], 5, False, "self_loop"),
+    ([(0, 1), (1, 2), (1, 0)], 5, False, "dup_edge"),
+    ([(0, 1), (1, 2), (0, 1)], 5, False, "dup_edge"),
+    ([(0, 1), (1, 0), (1, 2), (3, 2)], 5, True, "asymmetric"),
+])
+def test_device_errors(edges, n, both, name):
+    e = torch.tensor(edges, dtype=torch.int32, device=DEV)
+    with pytest.raises(api.TCError) as ei:
+        api.count(e, n, both)
+    assert ei.value.name == name
+    with pytest.raises(api.TCError) as ei:
+        api.count_per_vertex(e, n, both)
+    assert ei.value.name == name
+
+
+def test_host_errors():
+    e = torch.tensor([(0, 1), (1, 2), (0, 2)], dtype=torch.int32, device=DEV)
+    ws = api.alloc_workspace(3, 3, device=DEV)
+    short = ws[: ws.numel() - 256]
+    with pytest.raises(api.TCError) as ei:
+        api.count_async(e, 3, workspace=short)
+    assert ei.value.name == "workspace"
+    with pytest.raises(api.TCError) as ei:
+        api.count_async(torch.tensor([(0, 1), (1, 0), (1, 2)], dtype=torch.int32, device=DEV), 3,
+                        both=True)
+    assert ei.value.name == "asymmetric"
+    # a valid call after the errors still works
+    assert api.count(e, 3) == 1
+
+
+# ------------------------------------------------------------------ full-size workloads
+
+def test_rmat20_golden():
+    g = golden()["rmat_s20_ef16_s0"]
+    e, n = synth.rmat_graph(20, 16, seed=0, device=DEV)
+    assert synth.edges_sha256(e) == g["sha256"]
+    tot, pv = api.count_per_vertex(e, n)
+    assert tot == g["total"]
+    pv = pv.cpu().numpy()
+    assert int(pv.sum()) == g["per_vertex_sum"] == 3 * tot
+    for v, want in g["per_vertex_sample"].items():
+        assert pv[int(v)] == want
+    assert api.count(e, n) == tot
+
+
+def test_rmat23_full_size():
+    """The headline workload at full size, as the benchmark launches it."""
+    gd = golden().get("rmat_s23_ef24_s0")
+    e, n = synth.rmat_graph(23, 24, seed=0, device=DEV)
+    if gd is not None:
+        assert synth.edges_sha256(e) == gd["sha256"]
+    tot = api.count(e, n)
+    tot2, pv = api.count_per_vertex(e, n)
+    assert tot2 == tot
+    assert int(pv.sum().item()) == 3 * tot
+    if gd is not None:
+        assert tot == gd["total"]
+        pvh = pv.cpu().numpy()
+        for v, want in gd["per_vertex_sample"].items():
+            assert pvh[int(v)] == want
+    # sampled per-vertex counts from the definition, one vertex at a time
+    pvh = pv.cpu().numpy()
+    deg = api.preprocess(e, n)["deg"].cpu().numpy()
+    rng = np.random.default_rng(0)
+    cand = np.flatnonzero((deg >= 2) & (deg <= 2000))
+    q = rng.choice(cand, size=min(64, cand.size), replace=False)
+    want = oracle.vertex_triangles(e.cpu().numpy(), n, q)
+    assert np.array_equal(pvh[q].astype(np.uint64), want)
