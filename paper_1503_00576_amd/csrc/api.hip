@@ -8,19 +8,23 @@
 namespace tc {
 
 // kernels of prep.hip
+constexpr uint32_t kStripes = 8;
 __global__ void k_degree(const int2 *, uint64_t, uint32_t, uint32_t, uint32_t *, int32_t *);
-__global__ void k_vkeys(const uint32_t *, uint32_t, int, uint64_t *);
+__global__ void k_degree_sum(const uint32_t *, uint32_t, int, uint32_t *, uint64_t *);
 __global__ void k_rank(const uint64_t *, uint32_t, int, uint32_t *, uint32_t *);
 __global__ void k_orient(const int2 *, uint64_t, uint32_t, const uint32_t *, int, uint64_t *,
                          uint32_t *, const int32_t *);
 __global__ void k_both_check(const uint32_t *, uint32_t, int32_t *);
 __global__ void k_csr(const uint64_t *, uint32_t, uint32_t, int, uint32_t *, uint32_t *,
-                      int32_t *);
-__global__ void k_csc_count(const uint64_t *, uint32_t, int, const uint32_t *, const uint32_t *,
-                            uint32_t *, const int32_t *);
-__global__ void k_csc_fill(const uint64_t *, uint32_t, int, const uint32_t *, const uint32_t *,
-                           const uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t *,
-                           const int32_t *);
+                      uint32_t *, int32_t *);
+__global__ void k_rowlen(const uint32_t *, const uint32_t *, uint32_t, uint32_t *);
+__global__ void k_csc_count(const uint64_t *, uint32_t, int, uint32_t, const uint32_t *,
+                            const uint32_t *, uint32_t *, const int32_t *);
+__global__ void k_csc_merge(const uint32_t *, uint32_t, uint32_t *, uint32_t *);
+__global__ void k_csc_ptr(const uint32_t *, uint32_t, uint32_t *);
+__global__ void k_csc_fill(const uint64_t *, uint32_t, int, uint32_t, const uint32_t *,
+                           const uint32_t *, const uint32_t *, uint32_t *, uint32_t *,
+                           uint32_t *, uint32_t *, const int32_t *);
 __global__ void k_items(const uint32_t *, const uint32_t *, const uint32_t *, uint32_t, uint32_t,
                         uint32_t, uint32_t, uint32_t, uint32_t *, uint32_t *, uint32_t *,
                         uint32_t *, const int32_t *);
@@ -29,7 +33,6 @@ __global__ void k_item_fill(const uint32_t *, const uint32_t *, uint32_t, uint32
 __global__ void k_pv_out(const unsigned long long *, const uint32_t *, uint32_t,
                          unsigned long long *);
 __global__ void k_zero_u64(unsigned long long *, uint64_t);
-
 
 __global__ void k_copy_status(const int32_t *__restrict__ src, int32_t *__restrict__ dst) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src;
@@ -52,8 +55,9 @@ int device_cu_count() {
 // ------------------------------------------------------------------ workspace layout
 
 struct Layout {
-    size_t ctl, deg, perm, rank, keys_a, keys_b, sort_scratch, row_ptr, col, cdeg, cptr, cfill,
-        cbeg, cend, cu, items[4], off[4], item_v[4], scan_scratch, tpv, total_bytes;
+    size_t ctl, deg_s, deg, perm, rank, keys_a, keys_b, sort_scratch, rs, re, rowlen, row_ptr,
+        col, cdeg_s, cfill_s, cnt8, ofs8, cdeg, cptr, cbeg, cend, cu, items[4], off[4],
+        item_v[4], scan_scratch, tpv, total_bytes;
     uint32_t n, m, mf, kcap, id_bits;
 };
 
@@ -82,17 +86,24 @@ static bool make_layout(int64_t n, int64_t m, uint32_t flags, Layout &L) {
         return at;
     };
     L.ctl = take(kCtlWords * 4);
+    L.deg_s = take((size_t)kStripes * n * 4);
     L.deg = take((size_t)n * 4);
     L.perm = take((size_t)n * 4);
     L.rank = take((size_t)n * 4);
     L.keys_a = take((size_t)L.kcap * 8);
     L.keys_b = take((size_t)L.kcap * 8);
     L.sort_scratch = take(sort_scratch_bytes(L.kcap));
+    L.rs = take(n1 * 4);
+    L.re = take(n1 * 4);
+    L.rowlen = take(n1 * 4);
     L.row_ptr = take(n1 * 4);
-    L.col = take((size_t)L.mf * 4 + 64);
+    L.col = take((size_t)L.mf * 4 + 64);  // padded: aligned 16-element reads may pass the end
+    L.cdeg_s = take(kStripes * n1 * 4);
+    L.cfill_s = take(kStripes * n1 * 4);
+    L.cnt8 = take(kStripes * n1 * 4);
+    L.ofs8 = take(kStripes * n1 * 4);
     L.cdeg = take(n1 * 4);
     L.cptr = take(n1 * 4);
-    L.cfill = take(n1 * 4);
     L.cbeg = take((size_t)L.mf * 4);
     L.cend = take((size_t)L.mf * 4);
     L.cu = take((size_t)L.mf * 4);
@@ -102,7 +113,7 @@ static bool make_layout(int64_t n, int64_t m, uint32_t flags, Layout &L) {
         L.off[k] = take(n1 * 4);
         L.item_v[k] = take(((size_t)L.mf / per + n1 + 1) * 4);
     }
-    L.scan_scratch = take(scan_scratch_words(n1) * 4);
+    L.scan_scratch = take(scan_scratch_words(kStripes * n1) * 4);
     L.tpv = take((size_t)n * 8);
     L.total_bytes = off;
     return true;
@@ -113,7 +124,7 @@ static T *at(void *ws, size_t off) {
     return (T *)((char *)ws + off);
 }
 
-static inline uint32_t grid_for(uint64_t items, uint32_t threads, uint32_t cap = 1u << 20) {
+static inline uint32_t grid_for(uint64_t items, uint32_t threads, uint32_t cap = 0x7FFFFFFFu) {
     uint64_t g = (items + threads - 1) / threads;
     if (g == 0) g = 1;
     if (g > cap) g = cap;
@@ -162,16 +173,19 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
     const int2 *edges = (const int2 *)d_edges;
     const bool both = flags & TC_EDGES_BOTH;
 
+    uint32_t *deg_s = at<uint32_t>(ws, L.deg_s);
+    uint32_t *scan_scr = at<uint32_t>(ws, L.scan_scratch);
     TC_HIP(fill_u32(ctl, 0u, kCtlWords, s));
-    TC_HIP(fill_u32(deg, 0u, n, s));
+    TC_HIP(fill_u32(deg_s, 0u, (uint64_t)kStripes * n, s));
     if (m > 0) {
         hipLaunchKernelGGL(k_degree, dim3(grid_for(m, 256, 8192)), dim3(256), 0, s, edges,
-                           (uint64_t)m, n, (uint32_t)both, deg, status);
+                           (uint64_t)m, n, (uint32_t)both, deg_s, status);
         TC_LAUNCH_CHECK();
     }
     // the order of Section 2.2 as ranks: stable sort of (degree << b | id) on the degree bits
     if (n > 0) {
-        hipLaunchKernelGGL(k_vkeys, dim3(grid_for(n, 256)), dim3(256), 0, s, deg, n, b, ka);
+        hipLaunchKernelGGL(k_degree_sum, dim3(grid_for(n, 256)), dim3(256), 0, s, deg_s, n, b,
+                           deg, ka);
         TC_LAUNCH_CHECK();
         uint64_t *vs = nullptr;
         TC_HIP(sort_u64(ka, kb, n, b, 2 * b, sort_scr, nullptr, s, &vs));
@@ -193,32 +207,45 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
         TC_HIP(fill_u32(row_ptr, 0u, n1, s));
         return TC_OK;
     }
-    hipLaunchKernelGGL(k_csr, dim3(grid_for(mf, 256)), dim3(256), 0, s, sorted, mf, n, b, row_ptr,
-                       col, status);
+    // node array: row boundaries -> row lengths -> exclusive scan
+    uint32_t *rs = at<uint32_t>(ws, L.rs), *re = at<uint32_t>(ws, L.re);
+    uint32_t *rowlen = at<uint32_t>(ws, L.rowlen);
+    TC_HIP(fill_u32(rs, 0u, n1, s));
+    TC_HIP(fill_u32(re, 0u, n1, s));
+    hipLaunchKernelGGL(k_csr, dim3(grid_for(mf, 256)), dim3(256), 0, s, sorted, mf, n, b, col, rs,
+                       re, status);
     TC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_rowlen, dim3(grid_for(n1, 256)), dim3(256), 0, s, rs, re, n, rowlen);
+    TC_LAUNCH_CHECK();
+    TC_HIP(scan_exclusive_u32(rowlen, row_ptr, n1, scan_scr, s));
     // in-edge lists and work items of the counting kernel
+    uint32_t *cdeg_s = at<uint32_t>(ws, L.cdeg_s), *cfill_s = at<uint32_t>(ws, L.cfill_s);
+    uint32_t *cnt8 = at<uint32_t>(ws, L.cnt8), *ofs8 = at<uint32_t>(ws, L.ofs8);
     uint32_t *cdeg = at<uint32_t>(ws, L.cdeg), *cptr = at<uint32_t>(ws, L.cptr);
-    uint32_t *cfill = at<uint32_t>(ws, L.cfill);
     uint32_t *items[4], *offs[4], *iv[4];
     for (int k = 0; k < 4; ++k) {
         items[k] = at<uint32_t>(ws, L.items[k]);
         offs[k] = at<uint32_t>(ws, L.off[k]);
         iv[k] = at<uint32_t>(ws, L.item_v[k]);
     }
-    uint32_t *scan_scr = at<uint32_t>(ws, L.scan_scratch);
-    TC_HIP(fill_u32(cdeg, 0u, n1, s));
-    TC_HIP(fill_u32(cfill, 0u, n1, s));
-    hipLaunchKernelGGL(k_csc_count, dim3(grid_for(mf, 256)), dim3(256), 0, s, sorted, mf, b,
-                       row_ptr, col, cdeg, status);
+    TC_HIP(fill_u32(cdeg_s, 0u, (uint64_t)kStripes * n1, s));
+    TC_HIP(fill_u32(cfill_s, 0u, (uint64_t)kStripes * n1, s));
+    hipLaunchKernelGGL(k_csc_count, dim3(grid_for(mf, 256)), dim3(256), 0, s, sorted, mf, b, n,
+                       row_ptr, col, cdeg_s, status);
+    TC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_csc_merge, dim3(grid_for(n1, 256)), dim3(256), 0, s, cdeg_s, n, cdeg,
+                       cnt8);
+    TC_LAUNCH_CHECK();
+    TC_HIP(scan_exclusive_u32(cnt8, ofs8, kStripes * n1, scan_scr, s));
+    hipLaunchKernelGGL(k_csc_ptr, dim3(grid_for(n1, 256)), dim3(256), 0, s, ofs8, n, cptr);
     TC_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_items, dim3(grid_for(n1, 256)), dim3(256), 0, s, row_ptr, col, cdeg, n,
                        count_wave_span(false), count_wave_list(true), count_item_edges_wave(),
                        count_item_edges_block(), items[0], items[1], items[2], items[3], status);
     TC_LAUNCH_CHECK();
-    TC_HIP(scan_exclusive_u32(cdeg, cptr, n1, scan_scr, s));
     for (int k = 0; k < 4; ++k) TC_HIP(scan_exclusive_u32(items[k], offs[k], n1, scan_scr, s));
-    hipLaunchKernelGGL(k_csc_fill, dim3(grid_for(mf, 256)), dim3(256), 0, s, sorted, mf, b,
-                       row_ptr, col, cptr, cfill, at<uint32_t>(ws, L.cbeg),
+    hipLaunchKernelGGL(k_csc_fill, dim3(grid_for(mf, 256)), dim3(256), 0, s, sorted, mf, b, n,
+                       row_ptr, col, ofs8, cfill_s, at<uint32_t>(ws, L.cbeg),
                        at<uint32_t>(ws, L.cend), at<uint32_t>(ws, L.cu), status);
     TC_LAUNCH_CHECK();
     for (int k = 0; k < 4; ++k) {

@@ -72,7 +72,7 @@ struct ListProbe {  // sorted list in LDS or in global memory
 // ------------------------------------------------------------------ per-batch streaming
 
 struct WaveScratch {
-    uint32_t off[kWave], beg[kWave], end[kWave], cnt[kWave], u[kWave];
+    uint32_t off[kWave], beg[kWave], first[kWave], end[kWave], cnt[kWave], u[kWave];
 };
 
 // The calling wave processes in-edges [eb, min(eb + 64, e1)) of the current item and returns
@@ -94,11 +94,15 @@ __device__ __forceinline__ uint32_t run_batch(uint32_t eb, uint32_t e1,
         b = cbeg[e];
         en = cend[e];
     }
-    const uint32_t p = (en - b + kPiece - 1) / kPiece;
+    // pieces are 16-element windows starting at 4-element (16-byte) boundaries, so each lane
+    // reads its piece with four aligned 16-byte loads; elements outside [b, en) are masked
+    const uint32_t a0 = b & ~3u;
+    const uint32_t p = valid ? (en - a0 + kPiece - 1) / kPiece : 0u;
     const uint32_t incl = wave_incl_scan(p);
     const uint32_t Q = wave_bcast(incl, kWave - 1);
     ws.off[lane] = incl - p;
-    ws.beg[lane] = b;
+    ws.beg[lane] = a0;
+    ws.first[lane] = b;
     ws.end[lane] = en;
     if (PV) {
         ws.cnt[lane] = 0;
@@ -116,13 +120,23 @@ __device__ __forceinline__ uint32_t run_batch(uint32_t eb, uint32_t e1,
             for (uint32_t step = 32; step; step >>= 1)
                 if (ws.off[k + step] <= q) k += step;
             const uint32_t start = ws.beg[k] + (q - ws.off[k]) * kPiece;
-            const uint32_t stop = min(start + kPiece, ws.end[k]);
+            const uint32_t first = ws.first[k], stop = ws.end[k];
+            const uint4 *p4 = reinterpret_cast<const uint4 *>(col + start);
+            uint32_t wv[kPiece];
+#pragma unroll
+            for (uint32_t j = 0; j < kPiece / 4; ++j) {
+                const uint4 x = p4[j];
+                wv[4 * j] = x.x;
+                wv[4 * j + 1] = x.y;
+                wv[4 * j + 2] = x.z;
+                wv[4 * j + 3] = x.w;
+            }
             uint32_t hits = 0;
 #pragma unroll
             for (uint32_t i = 0; i < kPiece; ++i) {
                 const uint32_t idx = start + i;
-                if (idx < stop) {
-                    const uint32_t w = col[idx];
+                if (idx >= first && idx < stop) {
+                    const uint32_t w = wv[i];
                     uint32_t pos;
                     if (probe(w, pos)) {
                         ++hits;

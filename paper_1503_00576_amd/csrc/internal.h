@@ -66,7 +66,7 @@ inline uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1)
 
 // exclusive scan of uint32 (in may equal out); scratch: scan_scratch_words(N) words
 size_t scan_scratch_words(uint64_t N);
-hipError_t scan_exclusive_u32(const uint32_t *in, uint32_t *out, uint32_t N, uint32_t *scratch,
+hipError_t scan_exclusive_u32(const uint32_t *in, uint32_t *out, uint64_t N, uint32_t *scratch,
                               hipStream_t s);
 
 // radix sort: result lands in *result (== keys or tmp); scratch: sort_scratch_bytes(count)

@@ -1,14 +1,14 @@
 // Preprocessing phase (Section 3.2) on the device, in "rank space".
 //
 //   k_degree     degrees of the vertices and the input checks of Section 3.1
-//   k_vkeys      packs (degree, id) so that a stable sort yields the total order of Section 2.2
+//   k_degree_sum packs (degree, id) so that a stable sort yields the total order of Section 2.2
 //                (degree first, ties by id); the position of a vertex in that order is its rank
 //   k_rank       perm[r] = vertex of rank r, rank[v] = r
 //   k_orient     every edge becomes a packed key (rank s << b) | rank t with s < t, i.e. the
 //                edge kept only in its forward direction (Section 3.2, steps 5-6); in the
 //                paper's two-direction format backward entries are dropped
-//   k_csr        node array (Section 3.2, step 4/8: row_ptr[x] = first key whose source is
-//                >= x) and the unzipped neighbour array (step 7), duplicate check
+//   k_csr        the unzipped neighbour array (step 7), row boundaries for the node array
+//                (steps 4/8: row_ptr[x] = first key whose source is >= x), duplicate check
 //   k_csc_*      for every vertex v the list of in-edges u -> v that can close a triangle
 //                through v: the suffix of N+(u) after v, stored as a [begin, end) range
 //   k_items_*    work items of the counting kernels (see count.hip)
@@ -20,8 +20,14 @@
 
 namespace tc {
 
+// Workgroups are dispatched to the chip's 8 XCDs round-robin, so counters striped by
+// (blockIdx & 7) keep each copy's cache lines inside one XCD's L2: the many increments of a
+// hub vertex then no longer bounce one line between XCDs.  kStripes copies are summed after.
+constexpr uint32_t kStripes = 8;
+
 __global__ void k_degree(const int2 *__restrict__ edges, uint64_t m, uint32_t n, uint32_t both,
-                         uint32_t *__restrict__ deg, int32_t *__restrict__ status) {
+                         uint32_t *__restrict__ deg_s, int32_t *__restrict__ status) {
+    uint32_t *deg = deg_s + (size_t)(blockIdx.x & (kStripes - 1)) * n;
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (; i < m; i += stride) {
@@ -39,14 +45,19 @@ __global__ void k_degree(const int2 *__restrict__ edges, uint64_t m, uint32_t n,
     }
 }
 
-__global__ void k_vkeys(const uint32_t *__restrict__ deg, uint32_t n, int b,
-                        uint64_t *__restrict__ vkeys) {
+// deg[x] = sum of the striped counts; vkeys[x] = (degree << b) | x, whose stable sort on the
+// degree bits yields the total order of Section 2.2 (degree first, ties by id)
+__global__ void k_degree_sum(const uint32_t *__restrict__ deg_s, uint32_t n, int b,
+                             uint32_t *__restrict__ deg, uint64_t *__restrict__ vkeys) {
     uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
+    uint32_t d = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kStripes; ++k) d += deg_s[(size_t)k * n + x];
+    deg[x] = d;
     const uint64_t lim = (1ull << b) - 1;
-    uint64_t d = deg[x];
-    if (d > lim) d = lim;  // only possible for invalid input, which is reported elsewhere
-    vkeys[x] = (d << b) | x;
+    uint64_t dk = d > lim ? lim : d;  // only possible for invalid input, reported elsewhere
+    vkeys[x] = (dk << b) | x;
 }
 
 __global__ void k_rank(const uint64_t *__restrict__ sorted, uint32_t n, int b,
@@ -99,25 +110,30 @@ __global__ void k_both_check(const uint32_t *__restrict__ counter, uint32_t expe
         set_status(status, TC_E_ASYMMETRIC);
 }
 
+// Unzip the sorted keys into the neighbour array (Section 3.2, step 7) and mark where every
+// non-empty row starts and ends; row lengths and their prefix sum give the node array.
 __global__ void k_csr(const uint64_t *__restrict__ keys, uint32_t mf, uint32_t n, int b,
-                      uint32_t *__restrict__ row_ptr, uint32_t *__restrict__ col,
-                      int32_t *__restrict__ status) {
+                      uint32_t *__restrict__ col, uint32_t *__restrict__ rs,
+                      uint32_t *__restrict__ re, int32_t *__restrict__ status) {
     if (*status) return;
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= mf) return;
     const uint64_t k = keys[i];
     const uint32_t s = (uint32_t)(k >> b);
     col[i] = (uint32_t)(k & ((1ull << b) - 1));
-    int64_t prev = -1;
-    if (i > 0) {
-        uint64_t kp = keys[i - 1];
-        prev = (int64_t)(kp >> b);
-        if (kp == k) set_status(status, TC_E_DUP_EDGE);
-    }
-    const int64_t hi = s < n ? (int64_t)s : (int64_t)n - 1;
-    for (int64_t r = prev + 1; r <= hi; ++r) row_ptr[r] = i;
-    if (i == mf - 1)
-        for (int64_t r = hi + 1; r <= (int64_t)n; ++r) row_ptr[r] = mf;
+    if (s >= n) return;  // only for invalid input, reported elsewhere
+    if (i == 0 || (uint32_t)(keys[i - 1] >> b) != s) rs[s] = i;
+    if (i > 0 && keys[i - 1] == k) set_status(status, TC_E_DUP_EDGE);
+    if (i == mf - 1 || (uint32_t)(keys[i + 1] >> b) != s) re[s] = i + 1;
+}
+
+// row length = end - start (both zero for empty rows); entry n is 0 so that the exclusive
+// scan over n + 1 entries ends with row_ptr[n] = m_fwd
+__global__ void k_rowlen(const uint32_t *__restrict__ rs, const uint32_t *__restrict__ re,
+                         uint32_t n, uint32_t *__restrict__ len) {
+    uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r > n) return;
+    len[r] = r < n ? re[r] - rs[r] : 0u;
 }
 
 // In-edge u -> v (at CSR position e) can close a triangle u < v < w only through an element
@@ -133,21 +149,45 @@ __device__ __forceinline__ bool useful_inedge(uint32_t e, uint32_t u, uint32_t v
     return col[e + 1] <= col[rv1 - 1] && col[end_u - 1] >= col[rv0];
 }
 
-__global__ void k_csc_count(const uint64_t *__restrict__ keys, uint32_t mf, int b,
+__global__ void k_csc_count(const uint64_t *__restrict__ keys, uint32_t mf, int b, uint32_t n,
                             const uint32_t *__restrict__ row_ptr,
-                            const uint32_t *__restrict__ col, uint32_t *__restrict__ cdeg,
+                            const uint32_t *__restrict__ col, uint32_t *__restrict__ cdeg_s,
                             const int32_t *__restrict__ status) {
     if (*status) return;
     uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= mf) return;
     uint32_t u = (uint32_t)(keys[e] >> b), v = col[e], end_u;
-    if (useful_inedge(e, u, v, row_ptr, col, end_u)) atomicAdd(&cdeg[v], 1u);
+    if (useful_inedge(e, u, v, row_ptr, col, end_u))
+        atomicAdd(&cdeg_s[(size_t)(blockIdx.x & (kStripes - 1)) * (n + 1) + v], 1u);
 }
 
-__global__ void k_csc_fill(const uint64_t *__restrict__ keys, uint32_t mf, int b,
+// cdeg[v] = in-edges of v in total; cnt8[v * 8 + k] = those counted in stripe k (v-major, so
+// that one exclusive scan gives every (v, stripe) its own block of slots)
+__global__ void k_csc_merge(const uint32_t *__restrict__ cdeg_s, uint32_t n,
+                            uint32_t *__restrict__ cdeg, uint32_t *__restrict__ cnt8) {
+    uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v > n) return;
+    uint32_t t = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kStripes; ++k) {
+        uint32_t c = cdeg_s[(size_t)k * (n + 1) + v];
+        cnt8[(size_t)v * kStripes + k] = c;
+        t += c;
+    }
+    cdeg[v] = t;
+}
+
+__global__ void k_csc_ptr(const uint32_t *__restrict__ ofs8, uint32_t n,
+                          uint32_t *__restrict__ cptr) {
+    uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v <= n) cptr[v] = ofs8[(size_t)v * kStripes];
+}
+
+// same launch shape as k_csc_count, so every edge lands in the stripe that counted it
+__global__ void k_csc_fill(const uint64_t *__restrict__ keys, uint32_t mf, int b, uint32_t n,
                            const uint32_t *__restrict__ row_ptr,
-                           const uint32_t *__restrict__ col, const uint32_t *__restrict__ cptr,
-                           uint32_t *__restrict__ cfill, uint32_t *__restrict__ cbeg,
+                           const uint32_t *__restrict__ col, const uint32_t *__restrict__ ofs8,
+                           uint32_t *__restrict__ cfill_s, uint32_t *__restrict__ cbeg,
                            uint32_t *__restrict__ cend, uint32_t *__restrict__ cu,
                            const int32_t *__restrict__ status) {
     if (*status) return;
@@ -155,7 +195,9 @@ __global__ void k_csc_fill(const uint64_t *__restrict__ keys, uint32_t mf, int b
     if (e >= mf) return;
     uint32_t u = (uint32_t)(keys[e] >> b), v = col[e], end_u;
     if (!useful_inedge(e, u, v, row_ptr, col, end_u)) return;
-    uint32_t slot = cptr[v] + atomicAdd(&cfill[v], 1u);
+    const uint32_t k = blockIdx.x & (kStripes - 1);
+    uint32_t slot =
+        ofs8[(size_t)v * kStripes + k] + atomicAdd(&cfill_s[(size_t)k * (n + 1) + v], 1u);
     cbeg[slot] = e + 1;
     cend[slot] = end_u;
     cu[slot] = u;

@@ -38,7 +38,7 @@ __device__ __forceinline__ uint32_t pad_idx(uint32_t i) { return i + (i >> 5); }
 //   mode 1: write the exclusive scan, offset by carry[blockIdx.x] (if carry != nullptr)
 __global__ __launch_bounds__(kScanThreads) void k_scan_tile(const uint32_t *__restrict__ in,
                                                             uint32_t *__restrict__ out,
-                                                            uint32_t N, int mode,
+                                                            uint64_t N, int mode,
                                                             uint32_t *__restrict__ sums,
                                                             const uint32_t *__restrict__ carry) {
     __shared__ uint32_t s[kScanTile + kScanTile / 32];
@@ -92,7 +92,7 @@ size_t scan_scratch_words(uint64_t N) {
     return (size_t)align_up(words, 64);
 }
 
-hipError_t scan_exclusive_u32(const uint32_t *in, uint32_t *out, uint32_t N, uint32_t *scratch,
+hipError_t scan_exclusive_u32(const uint32_t *in, uint32_t *out, uint64_t N, uint32_t *scratch,
                               hipStream_t s) {
     if (N == 0) return hipSuccess;
     uint32_t nb = ceil_div(N, kScanTile);
