@@ -97,6 +97,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat23", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run three plain 1 GiB device-to-device copies (counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (the counting path is single-GPU); "
@@ -109,6 +111,14 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.init()
     torch.cuda.set_device(dev)
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copied 3 x 1 GiB")
+        return
     log(f"generating {WORKLOADS[args.workload]['label']}")
     t0 = time.perf_counter()
     edges, n = make_graph(args.workload, dev)
@@ -134,8 +144,10 @@ def main():
         step()
         torch.cuda.synchronize()
         log(f"warmup {i + 1}/{args.warmup} done")
-    out.check()
-    total = int(out.total.item())
+    total = None
+    if args.warmup > 0:
+        out.check()
+        total = int(out.total.item())
 
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(args.steps)]
@@ -151,6 +163,8 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     out.check()
+    if total is None:
+        total = int(out.total.item())
     assert int(out.total.item()) == total, "count changed between runs"
     ms_per_step = elapsed * 1e3 / args.steps
     count_ms = sum(a.elapsed_time(b) for a, b in ev) / args.steps
