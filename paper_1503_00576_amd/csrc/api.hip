@@ -1,6 +1,7 @@
 // C ABI of libtc.so: argument checks, workspace layout and the launch sequence of the
 // preprocessing and counting phases.  Everything is enqueued on the caller's stream; the
 // library never allocates device memory and never synchronises.
+#include <stdlib.h>
 #include <string.h>
 
 #include "internal.h"
@@ -18,17 +19,15 @@ __global__ void k_both_check(const uint32_t *, uint32_t, int32_t *);
 __global__ void k_csr(const uint64_t *, uint32_t, uint32_t, int, uint32_t *, uint32_t *,
                       uint32_t *, int32_t *);
 __global__ void k_rowlen(const uint32_t *, const uint32_t *, uint32_t, uint32_t *);
-__global__ void k_csc_count(const uint64_t *, uint32_t, int, uint32_t, const uint32_t *,
+__global__ void k_csc_count(const uint64_t *, uint32_t, int, uint32_t, uint32_t, const uint32_t *,
                             const uint32_t *, uint32_t *, const int32_t *);
-__global__ void k_csc_merge(const uint32_t *, uint32_t, uint32_t *, uint32_t *);
-__global__ void k_csc_ptr(const uint32_t *, uint32_t, uint32_t *);
-__global__ void k_csc_fill(const uint64_t *, uint32_t, int, uint32_t, const uint32_t *,
+__global__ void k_csc_fill(const uint64_t *, uint32_t, int, uint32_t, uint32_t, const uint32_t *,
                            const uint32_t *, const uint32_t *, uint32_t *, uint32_t *,
                            uint32_t *, uint32_t *, const int32_t *);
 __global__ void k_items(const uint32_t *, const uint32_t *, const uint32_t *, uint32_t, uint32_t,
-                        uint32_t, uint32_t, uint32_t, uint32_t *, uint32_t *, uint32_t *,
-                        uint32_t *, const int32_t *);
-__global__ void k_item_fill(const uint32_t *, const uint32_t *, uint32_t, uint32_t *,
+                        uint32_t, uint32_t, uint32_t, uint32_t, uint32_t *, uint32_t *,
+                        uint32_t *, uint32_t *, const int32_t *);
+__global__ void k_item_fill(const uint32_t *, const uint32_t *, uint64_t, uint32_t *,
                             const int32_t *);
 __global__ void k_pv_out(const unsigned long long *, const uint32_t *, uint32_t,
                          unsigned long long *);
@@ -56,13 +55,30 @@ int device_cu_count() {
 
 struct Layout {
     size_t ctl, deg_s, deg, perm, rank, keys_a, keys_b, sort_scratch, rs, re, rowlen, row_ptr,
-        col, cdeg_s, cfill_s, cnt8, ofs8, cdeg, cptr, cbeg, cend, cu, items[4], off[4],
-        item_v[4], scan_scratch, tpv, total_bytes;
-    uint32_t n, m, mf, kcap, id_bits;
+        col, cnt, cfill, cptr, cbeg, cend, cu, items[4], off[4], item_v[4], scan_scratch, tpv,
+        total_bytes;
+    uint32_t n, m, mf, kcap, id_bits, nblk;
+    uint64_t lists;  // in-edge lists: nblk * (n + 1)
 };
 
 // item spaces: [0] wave / [1] workgroup items for total counts, [2] / [3] for per-vertex counts
 enum { kCtlStatus = 0, kCtlBoth = 1, kCtlQueueA = 2, kCtlQueueB = 3, kCtlWords = 64 };
+
+// Row blocks of the in-edge lists: contiguous CSR ranges of at most ~96 MiB of neighbour ids,
+// so that the rows the counting kernel streams while it works on one block stay resident in
+// the 256 MiB memory-side cache; at most 8 blocks.
+static uint32_t row_blocks_for(uint32_t n, uint32_t mf) {
+    uint64_t block_bytes = 96ull << 20;
+    if (const char *env = getenv("TC_ROW_BLOCK_BYTES")) {  // tuning / testing override
+        unsigned long long v = strtoull(env, nullptr, 10);
+        if (v >= 64) block_bytes = v;
+    }
+    uint64_t k = ((uint64_t)mf * 4 + block_bytes - 1) / block_bytes;
+    if (k < 1) k = 1;
+    if (k > 8) k = 8;
+    while (k > 1 && k * ((uint64_t)n + 1) >= (1ull << 32)) --k;
+    return (uint32_t)k;
+}
 
 static int id_bits_for(uint32_t n) {
     int b = 1;
@@ -78,7 +94,10 @@ static bool make_layout(int64_t n, int64_t m, uint32_t flags, Layout &L) {
     L.mf = (flags & TC_EDGES_BOTH) ? (uint32_t)(m / 2) : (uint32_t)m;
     L.kcap = L.m > L.n ? L.m : L.n;
     L.id_bits = (uint32_t)id_bits_for(L.n);
+    L.nblk = row_blocks_for(L.n, L.mf);
     const uint64_t n1 = (uint64_t)n + 1;
+    L.lists = (uint64_t)L.nblk * n1;
+    const uint64_t l1 = L.lists + 1;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t at = off;
@@ -98,22 +117,19 @@ static bool make_layout(int64_t n, int64_t m, uint32_t flags, Layout &L) {
     L.rowlen = take(n1 * 4);
     L.row_ptr = take(n1 * 4);
     L.col = take((size_t)L.mf * 4 + 64);  // padded: aligned 16-element reads may pass the end
-    L.cdeg_s = take(kStripes * n1 * 4);
-    L.cfill_s = take(kStripes * n1 * 4);
-    L.cnt8 = take(kStripes * n1 * 4);
-    L.ofs8 = take(kStripes * n1 * 4);
-    L.cdeg = take(n1 * 4);
-    L.cptr = take(n1 * 4);
+    L.cnt = take(l1 * 4);
+    L.cfill = take(l1 * 4);
+    L.cptr = take(l1 * 4);
     L.cbeg = take((size_t)L.mf * 4);
     L.cend = take((size_t)L.mf * 4);
     L.cu = take((size_t)L.mf * 4);
     for (int k = 0; k < 4; ++k) {
         const uint32_t per = (k & 1) ? count_item_edges_block() : count_item_edges_wave();
-        L.items[k] = take(n1 * 4);
-        L.off[k] = take(n1 * 4);
-        L.item_v[k] = take(((size_t)L.mf / per + n1 + 1) * 4);
+        L.items[k] = take(l1 * 4);
+        L.off[k] = take(l1 * 4);
+        L.item_v[k] = take(((size_t)L.mf / per + l1 + 1) * 4);
     }
-    L.scan_scratch = take(scan_scratch_words(kStripes * n1) * 4);
+    L.scan_scratch = take(scan_scratch_words(l1 > n1 ? l1 : n1) * 4);
     L.tpv = take((size_t)n * 8);
     L.total_bytes = off;
     return true;
@@ -218,39 +234,35 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
     hipLaunchKernelGGL(k_rowlen, dim3(grid_for(n1, 256)), dim3(256), 0, s, rs, re, n, rowlen);
     TC_LAUNCH_CHECK();
     TC_HIP(scan_exclusive_u32(rowlen, row_ptr, n1, scan_scr, s));
-    // in-edge lists and work items of the counting kernel
-    uint32_t *cdeg_s = at<uint32_t>(ws, L.cdeg_s), *cfill_s = at<uint32_t>(ws, L.cfill_s);
-    uint32_t *cnt8 = at<uint32_t>(ws, L.cnt8), *ofs8 = at<uint32_t>(ws, L.ofs8);
-    uint32_t *cdeg = at<uint32_t>(ws, L.cdeg), *cptr = at<uint32_t>(ws, L.cptr);
+    // in-edge lists (blocked by row block of u) and work items of the counting kernel
+    const uint64_t l1 = L.lists + 1;
+    uint32_t *cnt = at<uint32_t>(ws, L.cnt), *cfill = at<uint32_t>(ws, L.cfill);
+    uint32_t *cptr = at<uint32_t>(ws, L.cptr);
     uint32_t *items[4], *offs[4], *iv[4];
     for (int k = 0; k < 4; ++k) {
         items[k] = at<uint32_t>(ws, L.items[k]);
         offs[k] = at<uint32_t>(ws, L.off[k]);
         iv[k] = at<uint32_t>(ws, L.item_v[k]);
     }
-    TC_HIP(fill_u32(cdeg_s, 0u, (uint64_t)kStripes * n1, s));
-    TC_HIP(fill_u32(cfill_s, 0u, (uint64_t)kStripes * n1, s));
+    TC_HIP(fill_u32(cnt, 0u, l1, s));
+    TC_HIP(fill_u32(cfill, 0u, l1, s));
     hipLaunchKernelGGL(k_csc_count, dim3(grid_for(mf, 256)), dim3(256), 0, s, sorted, mf, b, n,
-                       row_ptr, col, cdeg_s, status);
+                       L.nblk, row_ptr, col, cnt, status);
     TC_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_csc_merge, dim3(grid_for(n1, 256)), dim3(256), 0, s, cdeg_s, n, cdeg,
-                       cnt8);
+    TC_HIP(scan_exclusive_u32(cnt, cptr, l1, scan_scr, s));
+    hipLaunchKernelGGL(k_items, dim3(grid_for(l1, 256)), dim3(256), 0, s, row_ptr, col, cnt, n,
+                       L.nblk, count_wave_span(false), count_wave_list(true),
+                       count_item_edges_wave(), count_item_edges_block(), items[0], items[1],
+                       items[2], items[3], status);
     TC_LAUNCH_CHECK();
-    TC_HIP(scan_exclusive_u32(cnt8, ofs8, kStripes * n1, scan_scr, s));
-    hipLaunchKernelGGL(k_csc_ptr, dim3(grid_for(n1, 256)), dim3(256), 0, s, ofs8, n, cptr);
-    TC_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_items, dim3(grid_for(n1, 256)), dim3(256), 0, s, row_ptr, col, cdeg, n,
-                       count_wave_span(false), count_wave_list(true), count_item_edges_wave(),
-                       count_item_edges_block(), items[0], items[1], items[2], items[3], status);
-    TC_LAUNCH_CHECK();
-    for (int k = 0; k < 4; ++k) TC_HIP(scan_exclusive_u32(items[k], offs[k], n1, scan_scr, s));
+    for (int k = 0; k < 4; ++k) TC_HIP(scan_exclusive_u32(items[k], offs[k], l1, scan_scr, s));
     hipLaunchKernelGGL(k_csc_fill, dim3(grid_for(mf, 256)), dim3(256), 0, s, sorted, mf, b, n,
-                       row_ptr, col, ofs8, cfill_s, at<uint32_t>(ws, L.cbeg),
+                       L.nblk, row_ptr, col, cptr, cfill, at<uint32_t>(ws, L.cbeg),
                        at<uint32_t>(ws, L.cend), at<uint32_t>(ws, L.cu), status);
     TC_LAUNCH_CHECK();
     for (int k = 0; k < 4; ++k) {
-        hipLaunchKernelGGL(k_item_fill, dim3(grid_for(n, 256)), dim3(256), 0, s, items[k], offs[k],
-                           n, iv[k], status);
+        hipLaunchKernelGGL(k_item_fill, dim3(grid_for(L.lists, 256)), dim3(256), 0, s, items[k],
+                           offs[k], L.lists, iv[k], status);
         TC_LAUNCH_CHECK();
     }
     return TC_OK;
@@ -284,14 +296,15 @@ static int run_count_prepared(void *ws, const Layout &L, hipStream_t s, uint64_t
         a.cu = at<uint32_t>(ws, L.cu);
         a.item_v_a = at<uint32_t>(ws, L.item_v[a0]);
         a.item_off_a = at<uint32_t>(ws, L.off[a0]);
-        a.n_items_a = a.item_off_a + n;
+        a.n_items_a = a.item_off_a + L.lists;
         a.item_v_b = at<uint32_t>(ws, L.item_v[b0]);
         a.item_off_b = at<uint32_t>(ws, L.off[b0]);
-        a.n_items_b = a.item_off_b + n;
+        a.n_items_b = a.item_off_b + L.lists;
         a.queue_a = ctl + kCtlQueueA;
         a.queue_b = ctl + kCtlQueueB;
         a.total = total;
         a.tpv = tpv;
+        a.n1 = n + 1;
         a.status = status;
         TC_HIP(launch_count(a, pv, s));
     }

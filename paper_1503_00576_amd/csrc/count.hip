@@ -163,17 +163,18 @@ struct ItemRange {
     uint32_t v, e0, e1, r0, d;
 };
 
-__device__ __forceinline__ ItemRange item_range(uint32_t q, uint32_t kitem,
-                                                const uint32_t *__restrict__ item_v,
+// Item q of a queue covers in-edges [e0, e1) of list c = row block * (n + 1) + v.
+__device__ __forceinline__ ItemRange item_range(uint32_t q, uint32_t kitem, uint32_t n1,
+                                                const uint32_t *__restrict__ item_c,
                                                 const uint32_t *__restrict__ item_off,
                                                 const uint32_t *__restrict__ cptr,
                                                 const uint32_t *__restrict__ row_ptr) {
     ItemRange it;
-    it.v = item_v[q];
-    const uint32_t chunk = q - item_off[it.v];
-    const uint32_t c1 = cptr[it.v + 1];
-    it.e0 = cptr[it.v] + chunk * kitem;
-    it.e1 = min(it.e0 + kitem, c1);
+    const uint32_t c = item_c[q];
+    it.v = c % n1;
+    const uint32_t chunk = q - item_off[c];
+    it.e0 = cptr[c] + chunk * kitem;
+    it.e1 = min(it.e0 + kitem, cptr[c + 1]);
     it.r0 = row_ptr[it.v];
     it.d = row_ptr[it.v + 1] - it.r0;
     return it;
@@ -190,7 +191,7 @@ __global__ __launch_bounds__(kThreads) void k_count(
     const uint32_t *__restrict__ n_items_a_ptr, const uint32_t *__restrict__ item_v_b,
     const uint32_t *__restrict__ item_off_b, const uint32_t *__restrict__ n_items_b_ptr,
     uint32_t *__restrict__ queue_a, uint32_t *__restrict__ queue_b,
-    unsigned long long *__restrict__ total, unsigned long long *__restrict__ tpv,
+    unsigned long long *__restrict__ total, unsigned long long *__restrict__ tpv, uint32_t n1,
     const int32_t *__restrict__ status) {
     __shared__ uint32_t s_mem[kLdsWords];
     __shared__ WaveScratch s_ws[kWaves];
@@ -210,7 +211,8 @@ __global__ __launch_bounds__(kThreads) void k_count(
         uint32_t q = s_item;
         if (q >= n_items_b) break;
         q = n_items_b - 1 - q;
-        const ItemRange it = item_range(q, kItemEdgesBlock, item_v_b, item_off_b, cptr, row_ptr);
+        const ItemRange it =
+            item_range(q, kItemEdgesBlock, n1, item_v_b, item_off_b, cptr, row_ptr);
         const uint32_t lo = col[it.r0];
         const uint32_t span = col[it.r0 + it.d - 1] - lo;
         // 0 = bitmap, 1 = LDS list, 2 = global list
@@ -273,7 +275,8 @@ __global__ __launch_bounds__(kThreads) void k_count(
         q = wave_bcast(q, 0);
         if (q >= n_items_a) break;
         q = n_items_a - 1 - q;
-        const ItemRange it = item_range(q, kItemEdgesWave, item_v_a, item_off_a, cptr, row_ptr);
+        const ItemRange it =
+            item_range(q, kItemEdgesWave, n1, item_v_a, item_off_a, cptr, row_ptr);
         uint32_t cnt = 0;
         if (!PV) {
             const uint32_t lo = col[it.r0];
@@ -325,12 +328,12 @@ hipError_t launch_count(const CountArgs &x, bool per_vertex, hipStream_t s) {
         hipLaunchKernelGGL(k_count<true>, grid, block, 0, s, x.row_ptr, x.col, x.cptr, x.cbeg,
                            x.cend, x.cu, x.item_v_a, x.item_off_a, x.n_items_a, x.item_v_b,
                            x.item_off_b, x.n_items_b, x.queue_a, x.queue_b, x.total, x.tpv,
-                           x.status);
+                           x.n1, x.status);
     else
         hipLaunchKernelGGL(k_count<false>, grid, block, 0, s, x.row_ptr, x.col, x.cptr, x.cbeg,
                            x.cend, x.cu, x.item_v_a, x.item_off_a, x.n_items_a, x.item_v_b,
                            x.item_off_b, x.n_items_b, x.queue_a, x.queue_b, x.total, x.tpv,
-                           x.status);
+                           x.n1, x.status);
     return hipGetLastError();
 }
 

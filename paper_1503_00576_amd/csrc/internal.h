@@ -85,6 +85,7 @@ struct CountArgs {
     const uint32_t *item_v_b, *item_off_b, *n_items_b;
     uint32_t *queue_a, *queue_b;
     unsigned long long *total, *tpv;
+    uint32_t n1;
     const int32_t *status;
 };
 hipError_t launch_count(const CountArgs &a, bool per_vertex, hipStream_t s);

@@ -149,45 +149,32 @@ __device__ __forceinline__ bool useful_inedge(uint32_t e, uint32_t u, uint32_t v
     return col[e + 1] <= col[rv1 - 1] && col[end_u - 1] >= col[rv0];
 }
 
+// In-edge lists are blocked by the row block of u: block k holds the in-edges whose CSR
+// position e lies in [k * mf / nblk, (k + 1) * mf / nblk), i.e. a contiguous range of rows.
+// The counting kernel runs the blocks one after another, so the rows whose suffixes it
+// streams stay within one block (sized to stay resident in the memory-side cache).
+__device__ __forceinline__ uint32_t row_block(uint32_t e, uint32_t mf, uint32_t nblk) {
+    return (uint32_t)(((uint64_t)e * nblk) / mf);
+}
+
 __global__ void k_csc_count(const uint64_t *__restrict__ keys, uint32_t mf, int b, uint32_t n,
-                            const uint32_t *__restrict__ row_ptr,
-                            const uint32_t *__restrict__ col, uint32_t *__restrict__ cdeg_s,
+                            uint32_t nblk, const uint32_t *__restrict__ row_ptr,
+                            const uint32_t *__restrict__ col, uint32_t *__restrict__ cnt,
                             const int32_t *__restrict__ status) {
     if (*status) return;
     uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= mf) return;
     uint32_t u = (uint32_t)(keys[e] >> b), v = col[e], end_u;
     if (useful_inedge(e, u, v, row_ptr, col, end_u))
-        atomicAdd(&cdeg_s[(size_t)(blockIdx.x & (kStripes - 1)) * (n + 1) + v], 1u);
+        atomicAdd(&cnt[(size_t)row_block(e, mf, nblk) * (n + 1) + v], 1u);
 }
 
-// cdeg[v] = in-edges of v in total; cnt8[v * 8 + k] = those counted in stripe k (v-major, so
-// that one exclusive scan gives every (v, stripe) its own block of slots)
-__global__ void k_csc_merge(const uint32_t *__restrict__ cdeg_s, uint32_t n,
-                            uint32_t *__restrict__ cdeg, uint32_t *__restrict__ cnt8) {
-    uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v > n) return;
-    uint32_t t = 0;
-#pragma unroll
-    for (uint32_t k = 0; k < kStripes; ++k) {
-        uint32_t c = cdeg_s[(size_t)k * (n + 1) + v];
-        cnt8[(size_t)v * kStripes + k] = c;
-        t += c;
-    }
-    cdeg[v] = t;
-}
-
-__global__ void k_csc_ptr(const uint32_t *__restrict__ ofs8, uint32_t n,
-                          uint32_t *__restrict__ cptr) {
-    uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v <= n) cptr[v] = ofs8[(size_t)v * kStripes];
-}
-
-// same launch shape as k_csc_count, so every edge lands in the stripe that counted it
+// cnt / ofs are indexed by c = block * (n + 1) + v; the exclusive scan of cnt gives every
+// (block, v) list its slots, block-major
 __global__ void k_csc_fill(const uint64_t *__restrict__ keys, uint32_t mf, int b, uint32_t n,
-                           const uint32_t *__restrict__ row_ptr,
-                           const uint32_t *__restrict__ col, const uint32_t *__restrict__ ofs8,
-                           uint32_t *__restrict__ cfill_s, uint32_t *__restrict__ cbeg,
+                           uint32_t nblk, const uint32_t *__restrict__ row_ptr,
+                           const uint32_t *__restrict__ col, const uint32_t *__restrict__ ofs,
+                           uint32_t *__restrict__ fill, uint32_t *__restrict__ cbeg,
                            uint32_t *__restrict__ cend, uint32_t *__restrict__ cu,
                            const int32_t *__restrict__ status) {
     if (*status) return;
@@ -195,9 +182,8 @@ __global__ void k_csc_fill(const uint64_t *__restrict__ keys, uint32_t mf, int b
     if (e >= mf) return;
     uint32_t u = (uint32_t)(keys[e] >> b), v = col[e], end_u;
     if (!useful_inedge(e, u, v, row_ptr, col, end_u)) return;
-    const uint32_t k = blockIdx.x & (kStripes - 1);
-    uint32_t slot =
-        ofs8[(size_t)v * kStripes + k] + atomicAdd(&cfill_s[(size_t)k * (n + 1) + v], 1u);
+    const size_t c = (size_t)row_block(e, mf, nblk) * (n + 1) + v;
+    uint32_t slot = ofs[c] + atomicAdd(&fill[c], 1u);
     cbeg[slot] = e + 1;
     cend[slot] = end_u;
     cu[slot] = u;
@@ -209,36 +195,38 @@ __global__ void k_csc_fill(const uint64_t *__restrict__ keys, uint32_t mf, int b
 // per-workgroup queue.  Both classifications are prepared, so a prepared graph can be
 // counted either way.
 __global__ void k_items(const uint32_t *__restrict__ row_ptr, const uint32_t *__restrict__ col,
-                        const uint32_t *__restrict__ cdeg, uint32_t n, uint32_t wave_span,
-                        uint32_t wave_list_pv, uint32_t ka, uint32_t kb,
+                        const uint32_t *__restrict__ cnt, uint32_t n, uint32_t nblk,
+                        uint32_t wave_span, uint32_t wave_list_pv, uint32_t ka, uint32_t kb,
                         uint32_t *__restrict__ ia, uint32_t *__restrict__ ib,
                         uint32_t *__restrict__ ia_pv, uint32_t *__restrict__ ib_pv,
                         const int32_t *__restrict__ status) {
     if (*status) return;
-    uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v > n) return;
+    const uint64_t total = (uint64_t)nblk * (n + 1);
+    uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c > total) return;
     uint32_t a = 0, b = 0, apv = 0, bpv = 0;
-    if (v < n && cdeg[v] > 0) {
+    const uint32_t v = c < total ? (uint32_t)(c % (n + 1)) : n;
+    if (v < n && cnt[c] > 0) {
         const uint32_t r0 = row_ptr[v], d = row_ptr[v + 1] - r0;
         const uint32_t span = col[r0 + d - 1] - col[r0];
-        const uint32_t na = (cdeg[v] + ka - 1) / ka, nb = (cdeg[v] + kb - 1) / kb;
+        const uint32_t na = (cnt[c] + ka - 1) / ka, nb = (cnt[c] + kb - 1) / kb;
         if (span < wave_span) a = na; else b = nb;
         if (d <= wave_list_pv) apv = na; else bpv = nb;
     }
-    ia[v] = a;
-    ib[v] = b;
-    ia_pv[v] = apv;
-    ib_pv[v] = bpv;
+    ia[c] = a;
+    ib[c] = b;
+    ia_pv[c] = apv;
+    ib_pv[c] = bpv;
 }
 
 __global__ void k_item_fill(const uint32_t *__restrict__ items, const uint32_t *__restrict__ off,
-                            uint32_t n, uint32_t *__restrict__ item_v,
+                            uint64_t total, uint32_t *__restrict__ item_c,
                             const int32_t *__restrict__ status) {
     if (*status) return;
-    uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= n) return;
-    uint32_t k = items[v], o = off[v];
-    for (uint32_t j = 0; j < k; ++j) item_v[o + j] = v;
+    uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= total) return;
+    uint32_t k = items[c], o = off[c];
+    for (uint32_t j = 0; j < k; ++j) item_c[o + j] = (uint32_t)c;
 }
 
 // per-vertex counts back from rank space to vertex ids

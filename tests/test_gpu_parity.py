@@ -125,6 +125,16 @@ def test_repeat_runs_identical():
         assert t == outs[0][0] and np.array_equal(pv, outs[0][1])
 
 
+def test_row_blocks_forced(monkeypatch):
+    """In-edge lists split into 8 row blocks (the layout used for the largest graphs)."""
+    monkeypatch.setenv("TC_ROW_BLOCK_BYTES", "65536")
+    for e, n in [synth.rmat_graph(16, 16, seed=2, device=DEV), synth.er_1000(device=DEV)]:
+        check_vs_oracle(e.cpu().numpy(), n)
+    monkeypatch.setenv("TC_ROW_BLOCK_BYTES", "4096")
+    e, n = synth.rmat_graph(12, 16, seed=3, device=DEV)
+    check_vs_oracle(e.cpu().numpy(), n)
+
+
 def test_prepared_recount():
     """A resident preprocessed graph counted repeatedly, with and without per-vertex counts."""
     e, n = synth.rmat_graph(13, 16, seed=12, device=DEV)
