@@ -24,10 +24,10 @@
  *     kernel reads or writes outside the caller's buffers.
  *   - Vertex ids are int32 in [0, n); n < 2^31 and the number of edge entries m < 2^32.
  *     Counts are exact uint64.
- *   - Tuning: the environment variable TC_ROW_BLOCK_BYTES (default 100663296 = 96 MiB) sets
- *     the size of the row blocks the counting phase works through one at a time; it changes
- *     tc_workspace_size and must not change between a tc_preprocess and the calls that use
- *     its workspace.
+ *   - Tuning: the environment variable TC_ROW_BLOCK_BYTES (unset = one block) splits the
+ *     counting phase's in-edge lists into up to 8 row blocks of at most that many bytes of
+ *     neighbour ids, worked through one after another; it changes tc_workspace_size and must
+ *     not change between a tc_preprocess and the calls that use its workspace.
  */
 #ifndef TC_H
 #define TC_H

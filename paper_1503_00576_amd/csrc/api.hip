@@ -17,13 +17,15 @@ __global__ void k_orient(const int2 *, uint64_t, uint32_t, const uint32_t *, int
                          uint32_t *, const int32_t *);
 __global__ void k_both_check(const uint32_t *, uint32_t, int32_t *);
 __global__ void k_csr(const uint64_t *, uint32_t, uint32_t, int, uint32_t *, uint32_t *,
-                      uint32_t *, int32_t *);
+                      uint32_t *, uint32_t *, int32_t *);
 __global__ void k_rowlen(const uint32_t *, const uint32_t *, uint32_t, uint32_t *);
-__global__ void k_csc_count(const uint64_t *, uint32_t, int, uint32_t, uint32_t, const uint32_t *,
-                            const uint32_t *, uint32_t *, const int32_t *);
-__global__ void k_csc_fill(const uint64_t *, uint32_t, int, uint32_t, uint32_t, const uint32_t *,
-                           const uint32_t *, const uint32_t *, uint32_t *, uint32_t *,
-                           uint32_t *, uint32_t *, const int32_t *);
+__global__ void k_vrange(const uint32_t *, const uint32_t *, uint32_t, uint64_t *);
+__global__ void k_csc_keys(const uint32_t *, const uint32_t *, const uint32_t *, const uint64_t *,
+                           uint32_t, uint32_t, uint32_t, uint64_t *, const int32_t *);
+__global__ void k_csc_bounds(const uint64_t *, uint32_t, uint64_t, uint32_t *, uint32_t *,
+                             const int32_t *);
+__global__ void k_csc_final(const uint64_t *, uint32_t, uint64_t, const uint32_t *,
+                            const uint32_t *, uint32_t *, uint32_t *, uint32_t *, const int32_t *);
 __global__ void k_items(const uint32_t *, const uint32_t *, const uint32_t *, uint32_t, uint32_t,
                         uint32_t, uint32_t, uint32_t, uint32_t, uint32_t *, uint32_t *,
                         uint32_t *, uint32_t *, const int32_t *);
@@ -55,8 +57,8 @@ int device_cu_count() {
 
 struct Layout {
     size_t ctl, deg_s, deg, perm, rank, keys_a, keys_b, sort_scratch, rs, re, rowlen, row_ptr,
-        col, cnt, cfill, cptr, cbeg, cend, cu, items[4], off[4], item_v[4], scan_scratch, tpv,
-        total_bytes;
+        col, src, vrange, lrs, lre, cnt, cptr, cbeg, cend, cu, items[4], off[4], item_v[4],
+        scan_scratch, tpv, total_bytes;
     uint32_t n, m, mf, kcap, id_bits, nblk;
     uint64_t lists;  // in-edge lists: nblk * (n + 1)
 };
@@ -64,15 +66,16 @@ struct Layout {
 // item spaces: [0] wave / [1] workgroup items for total counts, [2] / [3] for per-vertex counts
 enum { kCtlStatus = 0, kCtlBoth = 1, kCtlQueueA = 2, kCtlQueueB = 3, kCtlWords = 64 };
 
-// Row blocks of the in-edge lists: contiguous CSR ranges of at most ~96 MiB of neighbour ids,
-// so that the rows the counting kernel streams while it works on one block stay resident in
-// the 256 MiB memory-side cache; at most 8 blocks.
+// Row blocks of the in-edge lists: contiguous CSR ranges of at most TC_ROW_BLOCK_BYTES of
+// neighbour ids (at most 8 blocks), worked through one after another by the counting kernel.
+// Default: one block (blocking at the memory-side cache size measured slower on R-MAT 23).
 static uint32_t row_blocks_for(uint32_t n, uint32_t mf) {
-    uint64_t block_bytes = 96ull << 20;
+    uint64_t block_bytes = 0;  // one block unless overridden
     if (const char *env = getenv("TC_ROW_BLOCK_BYTES")) {  // tuning / testing override
         unsigned long long v = strtoull(env, nullptr, 10);
         if (v >= 64) block_bytes = v;
     }
+    if (block_bytes == 0) return 1;
     uint64_t k = ((uint64_t)mf * 4 + block_bytes - 1) / block_bytes;
     if (k < 1) k = 1;
     if (k > 8) k = 8;
@@ -83,6 +86,13 @@ static uint32_t row_blocks_for(uint32_t n, uint32_t mf) {
 static int id_bits_for(uint32_t n) {
     int b = 1;
     while (b < 31 && (1ull << b) < n) ++b;
+    return b;
+}
+
+// bits needed to hold values in [0, x)
+static int id_bits_for64(uint64_t x) {
+    int b = 1;
+    while (b < 63 && (1ull << b) < x) ++b;
     return b;
 }
 
@@ -111,14 +121,17 @@ static bool make_layout(int64_t n, int64_t m, uint32_t flags, Layout &L) {
     L.rank = take((size_t)n * 4);
     L.keys_a = take((size_t)L.kcap * 8);
     L.keys_b = take((size_t)L.kcap * 8);
-    L.sort_scratch = take(sort_scratch_bytes(L.kcap));
+    L.sort_scratch = take(sort_scratch_bytes(L.kcap));  // edge, vertex and in-edge sorts
     L.rs = take(n1 * 4);
     L.re = take(n1 * 4);
     L.rowlen = take(n1 * 4);
     L.row_ptr = take(n1 * 4);
     L.col = take((size_t)L.mf * 4 + 64);  // padded: aligned 16-element reads may pass the end
+    L.src = take((size_t)L.mf * 4);
+    L.vrange = take((size_t)n * 8);
+    L.lrs = take(l1 * 4);
+    L.lre = take(l1 * 4);
     L.cnt = take(l1 * 4);
-    L.cfill = take(l1 * 4);
     L.cptr = take(l1 * 4);
     L.cbeg = take((size_t)L.mf * 4);
     L.cend = take((size_t)L.mf * 4);
@@ -228,38 +241,53 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
     uint32_t *rowlen = at<uint32_t>(ws, L.rowlen);
     TC_HIP(fill_u32(rs, 0u, n1, s));
     TC_HIP(fill_u32(re, 0u, n1, s));
-    hipLaunchKernelGGL(k_csr, dim3(grid_for(mf, 256)), dim3(256), 0, s, sorted, mf, n, b, col, rs,
-                       re, status);
+    uint32_t *src = at<uint32_t>(ws, L.src);
+    hipLaunchKernelGGL(k_csr, dim3(grid_for(mf, 256)), dim3(256), 0, s, sorted, mf, n, b, col, src,
+                       rs, re, status);
     TC_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_rowlen, dim3(grid_for(n1, 256)), dim3(256), 0, s, rs, re, n, rowlen);
     TC_LAUNCH_CHECK();
     TC_HIP(scan_exclusive_u32(rowlen, row_ptr, n1, scan_scr, s));
-    // in-edge lists (blocked by row block of u) and work items of the counting kernel
+    // in-edge lists (grouped by list c = row block * (n + 1) + v) and the counting kernel's
+    // work items
     const uint64_t l1 = L.lists + 1;
-    uint32_t *cnt = at<uint32_t>(ws, L.cnt), *cfill = at<uint32_t>(ws, L.cfill);
-    uint32_t *cptr = at<uint32_t>(ws, L.cptr);
+    uint32_t *lrs = at<uint32_t>(ws, L.lrs), *lre = at<uint32_t>(ws, L.lre);
+    uint32_t *cnt = at<uint32_t>(ws, L.cnt), *cptr = at<uint32_t>(ws, L.cptr);
+    uint64_t *vr = at<uint64_t>(ws, L.vrange);
     uint32_t *items[4], *offs[4], *iv[4];
     for (int k = 0; k < 4; ++k) {
         items[k] = at<uint32_t>(ws, L.items[k]);
         offs[k] = at<uint32_t>(ws, L.off[k]);
         iv[k] = at<uint32_t>(ws, L.item_v[k]);
     }
-    TC_HIP(fill_u32(cnt, 0u, l1, s));
-    TC_HIP(fill_u32(cfill, 0u, l1, s));
-    hipLaunchKernelGGL(k_csc_count, dim3(grid_for(mf, 256)), dim3(256), 0, s, sorted, mf, b, n,
-                       L.nblk, row_ptr, col, cnt, status);
+    hipLaunchKernelGGL(k_vrange, dim3(grid_for(n, 256)), dim3(256), 0, s, row_ptr, col, n, vr);
+    TC_LAUNCH_CHECK();
+    uint64_t *ck = (sorted == ka) ? kb : ka;  // the sorted edge keys are no longer needed
+    uint64_t *ck2 = (sorted == ka) ? ka : kb;
+    hipLaunchKernelGGL(k_csc_keys, dim3(grid_for(mf, 256)), dim3(256), 0, s, col, src, row_ptr, vr,
+                       mf, n, L.nblk, ck, status);
+    TC_LAUNCH_CHECK();
+    uint64_t *cks = ck;
+    TC_HIP(sort_u64(ck, ck2, mf, 32, 32 + id_bits_for64(l1), sort_scr, status, s, &cks));
+    TC_HIP(fill_u32(lrs, 0u, l1, s));
+    TC_HIP(fill_u32(lre, 0u, l1, s));
+    hipLaunchKernelGGL(k_csc_bounds, dim3(grid_for(mf, 256)), dim3(256), 0, s, cks, mf, L.lists,
+                       lrs, lre, status);
+    TC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_rowlen, dim3(grid_for(l1, 256)), dim3(256), 0, s, lrs, lre,
+                       (uint32_t)L.lists, cnt);
     TC_LAUNCH_CHECK();
     TC_HIP(scan_exclusive_u32(cnt, cptr, l1, scan_scr, s));
+    hipLaunchKernelGGL(k_csc_final, dim3(grid_for(mf, 256)), dim3(256), 0, s, cks, mf, L.lists,
+                       src, row_ptr, at<uint32_t>(ws, L.cbeg), at<uint32_t>(ws, L.cend),
+                       at<uint32_t>(ws, L.cu), status);
+    TC_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_items, dim3(grid_for(l1, 256)), dim3(256), 0, s, row_ptr, col, cnt, n,
                        L.nblk, count_wave_span(false), count_wave_list(true),
                        count_item_edges_wave(), count_item_edges_block(), items[0], items[1],
                        items[2], items[3], status);
     TC_LAUNCH_CHECK();
     for (int k = 0; k < 4; ++k) TC_HIP(scan_exclusive_u32(items[k], offs[k], l1, scan_scr, s));
-    hipLaunchKernelGGL(k_csc_fill, dim3(grid_for(mf, 256)), dim3(256), 0, s, sorted, mf, b, n,
-                       L.nblk, row_ptr, col, cptr, cfill, at<uint32_t>(ws, L.cbeg),
-                       at<uint32_t>(ws, L.cend), at<uint32_t>(ws, L.cu), status);
-    TC_LAUNCH_CHECK();
     for (int k = 0; k < 4; ++k) {
         hipLaunchKernelGGL(k_item_fill, dim3(grid_for(L.lists, 256)), dim3(256), 0, s, items[k],
                            offs[k], L.lists, iv[k], status);

@@ -10,7 +10,8 @@
 //   k_csr        the unzipped neighbour array (step 7), row boundaries for the node array
 //                (steps 4/8: row_ptr[x] = first key whose source is >= x), duplicate check
 //   k_csc_*      for every vertex v the list of in-edges u -> v that can close a triangle
-//                through v: the suffix of N+(u) after v, stored as a [begin, end) range
+//                through v: the suffix of N+(u) after v, stored as a [begin, end) range;
+//                built by a radix sort of (list << 32 | e) keys, so no atomics are needed
 //   k_items_*    work items of the counting kernels (see count.hip)
 //
 // Working with ranks instead of ids makes the order test a plain comparison, groups the
@@ -113,14 +114,16 @@ __global__ void k_both_check(const uint32_t *__restrict__ counter, uint32_t expe
 // Unzip the sorted keys into the neighbour array (Section 3.2, step 7) and mark where every
 // non-empty row starts and ends; row lengths and their prefix sum give the node array.
 __global__ void k_csr(const uint64_t *__restrict__ keys, uint32_t mf, uint32_t n, int b,
-                      uint32_t *__restrict__ col, uint32_t *__restrict__ rs,
-                      uint32_t *__restrict__ re, int32_t *__restrict__ status) {
+                      uint32_t *__restrict__ col, uint32_t *__restrict__ src,
+                      uint32_t *__restrict__ rs, uint32_t *__restrict__ re,
+                      int32_t *__restrict__ status) {
     if (*status) return;
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= mf) return;
     const uint64_t k = keys[i];
     const uint32_t s = (uint32_t)(k >> b);
     col[i] = (uint32_t)(k & ((1ull << b) - 1));
+    src[i] = s;
     if (s >= n) return;  // only for invalid input, reported elsewhere
     if (i == 0 || (uint32_t)(keys[i - 1] >> b) != s) rs[s] = i;
     if (i > 0 && keys[i - 1] == k) set_status(status, TC_E_DUP_EDGE);
@@ -136,57 +139,68 @@ __global__ void k_rowlen(const uint32_t *__restrict__ rs, const uint32_t *__rest
     len[r] = r < n ? re[r] - rs[r] : 0u;
 }
 
-// In-edge u -> v (at CSR position e) can close a triangle u < v < w only through an element
-// w of N+(u) after v that also lies in N+(v); the ranges of the two lists must overlap.
-__device__ __forceinline__ bool useful_inedge(uint32_t e, uint32_t u, uint32_t v,
-                                              const uint32_t *__restrict__ row_ptr,
-                                              const uint32_t *__restrict__ col,
-                                              uint32_t &end_u) {
-    end_u = row_ptr[u + 1];
-    if (e + 1 >= end_u) return false;
-    uint32_t rv0 = row_ptr[v], rv1 = row_ptr[v + 1];
-    if (rv1 == rv0) return false;
-    return col[e + 1] <= col[rv1 - 1] && col[end_u - 1] >= col[rv0];
+// Rank span of every out-list: (min << 32) | max, or 0xFFFFFFFF00000000 (min > max) if empty.
+__global__ void k_vrange(const uint32_t *__restrict__ row_ptr, const uint32_t *__restrict__ col,
+                         uint32_t n, uint64_t *__restrict__ vr) {
+    uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const uint32_t r0 = row_ptr[v], r1 = row_ptr[v + 1];
+    vr[v] = r1 > r0 ? ((uint64_t)col[r0] << 32) | col[r1 - 1] : 0xFFFFFFFF00000000ull;
 }
 
-// In-edge lists are blocked by the row block of u: block k holds the in-edges whose CSR
-// position e lies in [k * mf / nblk, (k + 1) * mf / nblk), i.e. a contiguous range of rows.
-// The counting kernel runs the blocks one after another, so the rows whose suffixes it
-// streams stay within one block (sized to stay resident in the memory-side cache).
-__device__ __forceinline__ uint32_t row_block(uint32_t e, uint32_t mf, uint32_t nblk) {
-    return (uint32_t)(((uint64_t)e * nblk) / mf);
-}
-
-__global__ void k_csc_count(const uint64_t *__restrict__ keys, uint32_t mf, int b, uint32_t n,
-                            uint32_t nblk, const uint32_t *__restrict__ row_ptr,
-                            const uint32_t *__restrict__ col, uint32_t *__restrict__ cnt,
-                            const int32_t *__restrict__ status) {
-    if (*status) return;
-    uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= mf) return;
-    uint32_t u = (uint32_t)(keys[e] >> b), v = col[e], end_u;
-    if (useful_inedge(e, u, v, row_ptr, col, end_u))
-        atomicAdd(&cnt[(size_t)row_block(e, mf, nblk) * (n + 1) + v], 1u);
-}
-
-// cnt / ofs are indexed by c = block * (n + 1) + v; the exclusive scan of cnt gives every
-// (block, v) list its slots, block-major
-__global__ void k_csc_fill(const uint64_t *__restrict__ keys, uint32_t mf, int b, uint32_t n,
-                           uint32_t nblk, const uint32_t *__restrict__ row_ptr,
-                           const uint32_t *__restrict__ col, const uint32_t *__restrict__ ofs,
-                           uint32_t *__restrict__ fill, uint32_t *__restrict__ cbeg,
-                           uint32_t *__restrict__ cend, uint32_t *__restrict__ cu,
+// In-edge u -> v (CSR position e) can close a triangle u < v < w only through an element w of
+// N+(u) after v that also lies in N+(v): the suffix must be non-empty and its rank range must
+// overlap that of N+(v).  Such in-edges are keyed by their list c = row block * (n + 1) + v
+// (row blocks: contiguous CSR ranges, see the host code), the others by `lists` (sorted last);
+// the low 32 bits hold e, so a stable sort on the list bits groups every list in CSR order.
+__global__ void k_csc_keys(const uint32_t *__restrict__ col, const uint32_t *__restrict__ src,
+                           const uint32_t *__restrict__ row_ptr,
+                           const uint64_t *__restrict__ vr, uint32_t mf, uint32_t n,
+                           uint32_t nblk, uint64_t *__restrict__ keys,
                            const int32_t *__restrict__ status) {
     if (*status) return;
     uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= mf) return;
-    uint32_t u = (uint32_t)(keys[e] >> b), v = col[e], end_u;
-    if (!useful_inedge(e, u, v, row_ptr, col, end_u)) return;
-    const size_t c = (size_t)row_block(e, mf, nblk) * (n + 1) + v;
-    uint32_t slot = ofs[c] + atomicAdd(&fill[c], 1u);
-    cbeg[slot] = e + 1;
-    cend[slot] = end_u;
-    cu[slot] = u;
+    const uint32_t u = src[e], v = col[e];
+    const uint32_t end_u = row_ptr[u + 1];
+    uint64_t c = (uint64_t)nblk * (n + 1);
+    if (e + 1 < end_u) {
+        const uint64_t r = vr[v];
+        const uint32_t lo = (uint32_t)(r >> 32), hi = (uint32_t)r;
+        if (lo <= hi && col[e + 1] <= hi && col[end_u - 1] >= lo)
+            c = (uint64_t)(((uint64_t)e * nblk) / mf) * (n + 1) + v;
+    }
+    keys[e] = (c << 32) | e;
+}
+
+// list boundaries of the sorted keys (useful in-edges only)
+__global__ void k_csc_bounds(const uint64_t *__restrict__ keys, uint32_t mf, uint64_t lists,
+                             uint32_t *__restrict__ rs, uint32_t *__restrict__ re,
+                             const int32_t *__restrict__ status) {
+    if (*status) return;
+    uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= mf) return;
+    const uint64_t c = keys[j] >> 32;
+    if (c >= lists) return;
+    if (j == 0 || (keys[j - 1] >> 32) != c) rs[c] = j;
+    if (j == mf - 1 || (keys[j + 1] >> 32) != c) re[c] = j + 1;
+}
+
+// the lists themselves: in-edge u -> v at CSR position e contributes the suffix [e + 1, end_u)
+__global__ void k_csc_final(const uint64_t *__restrict__ keys, uint32_t mf, uint64_t lists,
+                            const uint32_t *__restrict__ src, const uint32_t *__restrict__ row_ptr,
+                            uint32_t *__restrict__ cbeg, uint32_t *__restrict__ cend,
+                            uint32_t *__restrict__ cu, const int32_t *__restrict__ status) {
+    if (*status) return;
+    uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= mf) return;
+    const uint64_t k = keys[j];
+    if ((k >> 32) >= lists) return;
+    const uint32_t e = (uint32_t)k;
+    const uint32_t u = src[e];
+    cbeg[j] = e + 1;
+    cend[j] = row_ptr[u + 1];
+    cu[j] = u;
 }
 
 // Work items of the counting kernel.  A vertex's in-edges are cut into chunks; the chunks go

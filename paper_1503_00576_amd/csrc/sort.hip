@@ -4,7 +4,8 @@
 // (Section 3.2, step 3, and the note on sorting edges as 64-bit integers): keys are ordered
 // on a bit range [lo_bit, hi_bit) with 8-bit digits, least significant digit first; every
 // pass is an upsweep (per-tile digit histograms), an exclusive scan of the digit-major
-// histogram table, and a stable scatter in which a wave ranks equal digits with ballots.
+// histogram table, and a stable scatter in which a wave ranks equal digits with ballots,
+// the tile is ordered by digit in LDS, and every digit's run is written out contiguously.
 #include "internal.h"
 
 namespace tc {
@@ -158,16 +159,32 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t *__r
     hist[(uint64_t)t * tiles + blockIdx.x] = sum;
 }
 
+// Stable scatter of one 4096-key tile: the keys are first ranked and placed in LDS in digit
+// order (tile-local counting sort), then written out so that consecutive threads write
+// consecutive positions of one digit's run.
+//   hist: raw per-tile digit counts (digit-major), offs: their exclusive scan
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint64_t *__restrict__ in, uint64_t *__restrict__ out, uint32_t count, int shift,
-    uint32_t nbits, const uint32_t *__restrict__ offs, uint32_t tiles,
-    const int32_t *__restrict__ status) {
+    uint32_t nbits, const uint32_t *__restrict__ hist, const uint32_t *__restrict__ offs,
+    uint32_t tiles, const int32_t *__restrict__ status) {
     if (status && *status) return;
-    __shared__ uint32_t s_base[256];
+    __shared__ uint64_t s_stage[kSortTile];
+    __shared__ uint32_t s_loc[256];   // next local position per digit
+    __shared__ uint32_t s_glob[256];  // global start minus local start per digit
     __shared__ uint32_t s_wcnt[kSortWaves][256];
+    __shared__ uint32_t s_wsum[kSortWaves];
     const uint32_t t = threadIdx.x, w = t / kWave;
-    s_base[t] = offs[(uint64_t)t * tiles + blockIdx.x];
+    // tile-local exclusive offsets of the digits
+    const uint32_t c = hist[(uint64_t)t * tiles + blockIdx.x];
+    const uint32_t incl = wave_incl_scan(c);
+    if (lane_id() == kWave - 1) s_wsum[w] = incl;
     for (int k = 0; k < kSortWaves; ++k) s_wcnt[k][t] = 0;
+    __syncthreads();
+    uint32_t before = 0;
+    for (uint32_t k = 0; k < w; ++k) before += s_wsum[k];
+    const uint32_t loc = before + incl - c;
+    s_loc[t] = loc;
+    s_glob[t] = offs[(uint64_t)t * tiles + blockIdx.x] - loc;
     __syncthreads();
     const uint32_t mask = (1u << nbits) - 1u;
     const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
@@ -181,9 +198,9 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
         if (valid && rank == 0) s_wcnt[w][d] = (uint32_t)__popcll(peers);
         __syncthreads();
         if (valid) {
-            uint32_t pos = s_base[d] + rank;
+            uint32_t pos = s_loc[d] + rank;
             for (uint32_t k = 0; k < w; ++k) pos += s_wcnt[k][d];
-            out[pos] = key;
+            s_stage[pos] = key;
         }
         __syncthreads();
         uint32_t add = 0;
@@ -191,8 +208,15 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
             add += s_wcnt[k][t];
             s_wcnt[k][t] = 0;
         }
-        s_base[t] += add;
+        s_loc[t] += add;
         __syncthreads();
+    }
+    const uint64_t rest = count - base;
+    const uint32_t ntile = rest < (uint64_t)kSortTile ? (uint32_t)rest : (uint32_t)kSortTile;
+    for (uint32_t j = t; j < ntile; j += kSortThreads) {
+        const uint64_t key = s_stage[j];
+        const uint32_t d = (uint32_t)(key >> shift) & mask;
+        out[s_glob[d] + j] = key;
     }
 }
 
@@ -200,7 +224,7 @@ size_t sort_scratch_bytes(uint64_t count) {
     uint64_t tiles = (count + kSortTile - 1) / kSortTile;
     if (tiles == 0) tiles = 1;
     uint64_t hist = 256 * tiles;
-    return align_up(hist * 4, 256) + align_up(scan_scratch_words(hist) * 4, 256);
+    return 2 * align_up(hist * 4, 256) + align_up(scan_scratch_words(hist) * 4, 256);
 }
 
 hipError_t sort_u64(uint64_t *keys, uint64_t *tmp, uint32_t count, int lo_bit, int hi_bit,
@@ -210,7 +234,8 @@ hipError_t sort_u64(uint64_t *keys, uint64_t *tmp, uint32_t count, int lo_bit, i
     uint32_t tiles = ceil_div(count, kSortTile);
     uint64_t hist_n = 256ull * tiles;
     uint32_t *hist = (uint32_t *)scratch;
-    uint32_t *scan_scratch = (uint32_t *)((char *)scratch + align_up(hist_n * 4, 256));
+    uint32_t *offs = (uint32_t *)((char *)scratch + align_up(hist_n * 4, 256));
+    uint32_t *scan_scratch = (uint32_t *)((char *)scratch + 2 * align_up(hist_n * 4, 256));
     uint64_t *src = keys, *dst = tmp;
     for (int shift = lo_bit; shift < hi_bit; shift += 8) {
         uint32_t nbits = (uint32_t)((hi_bit - shift) < 8 ? (hi_bit - shift) : 8);
@@ -218,10 +243,10 @@ hipError_t sort_u64(uint64_t *keys, uint64_t *tmp, uint32_t count, int lo_bit, i
                            shift, nbits, hist, tiles, status);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        e = scan_exclusive_u32(hist, hist, (uint32_t)hist_n, scan_scratch, s);
+        e = scan_exclusive_u32(hist, offs, hist_n, scan_scratch, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_radix_scatter, dim3(tiles), dim3(kSortThreads), 0, s, src, dst,
-                           count, shift, nbits, hist, tiles, status);
+                           count, shift, nbits, hist, offs, tiles, status);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         uint64_t *x = src;
