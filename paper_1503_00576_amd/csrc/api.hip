@@ -9,9 +9,15 @@
 namespace tc {
 
 // kernels of prep.hip
-constexpr uint32_t kStripes = 8;
-__global__ void k_degree(const int2 *, uint64_t, uint32_t, uint32_t, uint32_t *, int32_t *);
-__global__ void k_degree_sum(const uint32_t *, uint32_t, int, uint32_t *, uint64_t *);
+__global__ void k_part_hist(const int2 *, uint64_t, uint32_t, uint32_t, int, uint32_t *, uint32_t,
+                            int32_t *);
+__global__ void k_part_scatter(const int2 *, uint64_t, uint32_t, uint32_t, int, const uint32_t *,
+                               const uint32_t *, uint32_t, uint32_t *);
+__global__ void k_part_count(const uint32_t *, const uint32_t *, uint32_t, int, uint32_t,
+                             uint32_t, uint32_t *, const int32_t *);
+__global__ void k_degree_atomic(const int2 *, uint64_t, uint32_t, uint32_t, uint32_t *,
+                                int32_t *);
+__global__ void k_vkeys(const uint32_t *, uint32_t, int, uint64_t *);
 __global__ void k_rank(const uint64_t *, uint32_t, int, uint32_t *, uint32_t *);
 __global__ void k_orient(const int2 *, uint64_t, uint32_t, const uint32_t *, int, uint64_t *,
                          uint32_t *, const int32_t *);
@@ -21,11 +27,11 @@ __global__ void k_csr(const uint64_t *, uint32_t, uint32_t, int, uint32_t *, uin
 __global__ void k_rowlen(const uint32_t *, const uint32_t *, uint32_t, uint32_t *);
 __global__ void k_vrange(const uint32_t *, const uint32_t *, uint32_t, uint64_t *);
 __global__ void k_csc_keys(const uint32_t *, const uint32_t *, const uint32_t *, const uint64_t *,
-                           uint32_t, uint32_t, uint32_t, uint64_t *, const int32_t *);
+                           uint32_t, uint32_t, uint32_t, uint64_t *, uint2 *, const int32_t *);
 __global__ void k_csc_bounds(const uint64_t *, uint32_t, uint64_t, uint32_t *, uint32_t *,
                              const int32_t *);
-__global__ void k_csc_final(const uint64_t *, uint32_t, uint64_t, const uint32_t *,
-                            const uint32_t *, uint32_t *, uint32_t *, uint32_t *, const int32_t *);
+__global__ void k_csc_final(const uint64_t *, uint32_t, uint64_t, const uint2 *, uint32_t *,
+                            uint32_t *, uint32_t *, const int32_t *);
 __global__ void k_items(const uint32_t *, const uint32_t *, const uint32_t *, uint32_t, uint32_t,
                         uint32_t, uint32_t, uint32_t, uint32_t, uint32_t *, uint32_t *,
                         uint32_t *, uint32_t *, const int32_t *);
@@ -56,15 +62,18 @@ int device_cu_count() {
 // ------------------------------------------------------------------ workspace layout
 
 struct Layout {
-    size_t ctl, deg_s, deg, perm, rank, keys_a, keys_b, sort_scratch, rs, re, rowlen, row_ptr,
-        col, src, vrange, lrs, lre, cnt, cptr, cbeg, cend, cu, items[4], off[4], item_v[4],
-        scan_scratch, tpv, total_bytes;
+    size_t ctl, part_hist, part_offs, part_scan, deg, perm, rank, keys_a, keys_b, sort_scratch,
+        rs, re, rowlen, row_ptr, col, src, vrange, eu, lrs, lre, cnt, cptr, cbeg, cend, cu,
+        items[4], off[4], item_v[4], scan_scratch, tpv, total_bytes;
+    uint32_t part_tiles;  // 0: degrees by atomics (inputs too large for the partition)
+    int part_shift;
     uint32_t n, m, mf, kcap, id_bits, nblk;
     uint64_t lists;  // in-edge lists: nblk * (n + 1)
 };
 
 // item spaces: [0] wave / [1] workgroup items for total counts, [2] / [3] for per-vertex counts
 enum { kCtlStatus = 0, kCtlBoth = 1, kCtlQueueA = 2, kCtlQueueB = 3, kCtlWords = 64 };
+constexpr uint32_t kPartTileEdges = 4096;  // edges per tile of the degree partition
 
 // Row blocks of the in-edge lists: contiguous CSR ranges of at most TC_ROW_BLOCK_BYTES of
 // neighbour ids (at most 8 blocks), worked through one after another by the counting kernel.
@@ -115,7 +124,19 @@ static bool make_layout(int64_t n, int64_t m, uint32_t flags, Layout &L) {
         return at;
     };
     L.ctl = take(kCtlWords * 4);
-    L.deg_s = take((size_t)kStripes * n * 4);
+    // degree partition: buckets of 2^part_shift ids, at most 256 of them
+    {
+        const uint64_t endpoints = (flags & TC_EDGES_BOTH) ? (uint64_t)m : 2ull * (uint64_t)m;
+        const int db = L.id_bits < 8 ? (int)L.id_bits : 8;
+        L.part_shift = (int)L.id_bits - db;
+        L.part_tiles = (endpoints < (1ull << 32) && L.part_shift <= 19)
+                           ? ceil_div((uint64_t)m > 0 ? (uint64_t)m : 1, kPartTileEdges)
+                           : 0u;
+        const uint64_t hp = 256ull * (L.part_tiles ? L.part_tiles : 1) + 1;
+        L.part_hist = take(hp * 4);
+        L.part_offs = take(hp * 4);
+        L.part_scan = take(scan_scratch_words(hp) * 4);
+    }
     L.deg = take((size_t)n * 4);
     L.perm = take((size_t)n * 4);
     L.rank = take((size_t)n * 4);
@@ -129,6 +150,7 @@ static bool make_layout(int64_t n, int64_t m, uint32_t flags, Layout &L) {
     L.col = take((size_t)L.mf * 4 + 64);  // padded: aligned 16-element reads may pass the end
     L.src = take((size_t)L.mf * 4);
     L.vrange = take((size_t)n * 8);
+    L.eu = take((size_t)L.mf * 8);
     L.lrs = take(l1 * 4);
     L.lre = take(l1 * 4);
     L.cnt = take(l1 * 4);
@@ -202,19 +224,35 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
     const int2 *edges = (const int2 *)d_edges;
     const bool both = flags & TC_EDGES_BOTH;
 
-    uint32_t *deg_s = at<uint32_t>(ws, L.deg_s);
     uint32_t *scan_scr = at<uint32_t>(ws, L.scan_scratch);
     TC_HIP(fill_u32(ctl, 0u, kCtlWords, s));
-    TC_HIP(fill_u32(deg_s, 0u, (uint64_t)kStripes * n, s));
-    if (m > 0) {
-        hipLaunchKernelGGL(k_degree, dim3(grid_for(m, 256, 8192)), dim3(256), 0, s, edges,
-                           (uint64_t)m, n, (uint32_t)both, deg_s, status);
+    TC_HIP(fill_u32(deg, 0u, n, s));
+    if (m > 0 && L.part_tiles) {
+        const uint32_t tiles = L.part_tiles;
+        const uint64_t hp = 256ull * tiles;
+        uint32_t *ph = at<uint32_t>(ws, L.part_hist), *po = at<uint32_t>(ws, L.part_offs);
+        uint32_t *parts = (uint32_t *)kb;  // 4-byte endpoints fit the 8-byte key buffer
+        TC_HIP(fill_u32(ph + hp, 0u, 1, s));
+        hipLaunchKernelGGL(k_part_hist, dim3(tiles), dim3(256), 0, s, edges, (uint64_t)m, n,
+                           (uint32_t)both, L.part_shift, ph, tiles, status);
+        TC_LAUNCH_CHECK();
+        TC_HIP(scan_exclusive_u32(ph, po, hp + 1, at<uint32_t>(ws, L.part_scan), s));
+        hipLaunchKernelGGL(k_part_scatter, dim3(tiles), dim3(256), 0, s, edges, (uint64_t)m, n,
+                           (uint32_t)both, L.part_shift, ph, po, tiles, parts);
+        TC_LAUNCH_CHECK();
+        const uint32_t buckets = 1u << (L.id_bits - L.part_shift);
+        const uint32_t slices = buckets >= 512 ? 1u : 512u / buckets;
+        hipLaunchKernelGGL(k_part_count, dim3(buckets * slices), dim3(1024), 0, s, parts, po,
+                           tiles, L.part_shift, n, slices, deg, status);
+        TC_LAUNCH_CHECK();
+    } else if (m > 0) {
+        hipLaunchKernelGGL(k_degree_atomic, dim3(grid_for(m, 256, 8192)), dim3(256), 0, s, edges,
+                           (uint64_t)m, n, (uint32_t)both, deg, status);
         TC_LAUNCH_CHECK();
     }
     // the order of Section 2.2 as ranks: stable sort of (degree << b | id) on the degree bits
     if (n > 0) {
-        hipLaunchKernelGGL(k_degree_sum, dim3(grid_for(n, 256)), dim3(256), 0, s, deg_s, n, b,
-                           deg, ka);
+        hipLaunchKernelGGL(k_vkeys, dim3(grid_for(n, 256)), dim3(256), 0, s, deg, n, b, ka);
         TC_LAUNCH_CHECK();
         uint64_t *vs = nullptr;
         TC_HIP(sort_u64(ka, kb, n, b, 2 * b, sort_scr, nullptr, s, &vs));
@@ -264,8 +302,9 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
     TC_LAUNCH_CHECK();
     uint64_t *ck = (sorted == ka) ? kb : ka;  // the sorted edge keys are no longer needed
     uint64_t *ck2 = (sorted == ka) ? ka : kb;
+    uint2 *eu = at<uint2>(ws, L.eu);
     hipLaunchKernelGGL(k_csc_keys, dim3(grid_for(mf, 256)), dim3(256), 0, s, col, src, row_ptr, vr,
-                       mf, n, L.nblk, ck, status);
+                       mf, n, L.nblk, ck, eu, status);
     TC_LAUNCH_CHECK();
     uint64_t *cks = ck;
     TC_HIP(sort_u64(ck, ck2, mf, 32, 32 + id_bits_for64(l1), sort_scr, status, s, &cks));
@@ -279,7 +318,7 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
     TC_LAUNCH_CHECK();
     TC_HIP(scan_exclusive_u32(cnt, cptr, l1, scan_scr, s));
     hipLaunchKernelGGL(k_csc_final, dim3(grid_for(mf, 256)), dim3(256), 0, s, cks, mf, L.lists,
-                       src, row_ptr, at<uint32_t>(ws, L.cbeg), at<uint32_t>(ws, L.cend),
+                       eu, at<uint32_t>(ws, L.cbeg), at<uint32_t>(ws, L.cend),
                        at<uint32_t>(ws, L.cu), status);
     TC_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_items, dim3(grid_for(l1, 256)), dim3(256), 0, s, row_ptr, col, cnt, n,

@@ -1,7 +1,8 @@
 // Preprocessing phase (Section 3.2) on the device, in "rank space".
 //
-//   k_degree     degrees of the vertices and the input checks of Section 3.1
-//   k_degree_sum packs (degree, id) so that a stable sort yields the total order of Section 2.2
+//   k_part_*     degrees of the vertices (bucket partition + LDS counting) and the input
+//                checks of Section 3.1
+//   k_vkeys      packs (degree, id) so that a stable sort yields the total order of Section 2.2
 //                (degree first, ties by id); the position of a vertex in that order is its rank
 //   k_rank       perm[r] = vertex of rank r, rank[v] = r
 //   k_orient     every edge becomes a packed key (rank s << b) | rank t with s < t, i.e. the
@@ -21,24 +22,140 @@
 
 namespace tc {
 
-// Workgroups are dispatched to the chip's 8 XCDs round-robin, so counters striped by
-// (blockIdx & 7) keep each copy's cache lines inside one XCD's L2: the many increments of a
-// hub vertex then no longer bounce one line between XCDs.  kStripes copies are summed after.
-constexpr uint32_t kStripes = 8;
+// ---------------------------------------------------------------- degrees
+// Degrees are a histogram of the 2m endpoints over n vertices.  Scattered atomics into an
+// n-entry array miss the caches on every increment, so the endpoints are first partitioned by
+// their high id bits into at most 256 buckets (bucket = x >> sh, a range of 2^sh ids), then
+// every bucket is counted in LDS.  The first pass also checks the input (Section 3.1).
+constexpr int kPartThreads = 256;
+constexpr int kPartEdges = 16;                               // edges per thread
+constexpr uint32_t kPartTile = kPartThreads * kPartEdges;    // 4096 edges per tile
+constexpr uint32_t kPartWindow = 32768;                      // LDS counters per workgroup
 
-__global__ void k_degree(const int2 *__restrict__ edges, uint64_t m, uint32_t n, uint32_t both,
-                         uint32_t *__restrict__ deg_s, int32_t *__restrict__ status) {
-    uint32_t *deg = deg_s + (size_t)(blockIdx.x & (kStripes - 1)) * n;
+__device__ __forceinline__ bool endpoint_ok(int2 e, uint32_t n) {
+    return (uint32_t)e.x < n && (uint32_t)e.y < n && e.x != e.y;
+}
+
+__global__ __launch_bounds__(kPartThreads) void k_part_hist(
+    const int2 *__restrict__ edges, uint64_t m, uint32_t n, uint32_t both, int sh,
+    uint32_t *__restrict__ hist, uint32_t tiles, int32_t *__restrict__ status) {
+    __shared__ uint32_t h[256];
+    const uint32_t t = threadIdx.x;
+    h[t] = 0;
+    __syncthreads();
+    const uint64_t base = (uint64_t)blockIdx.x * kPartTile;
+    int2 ed[kPartEdges];
+#pragma unroll
+    for (int r = 0; r < kPartEdges; ++r) {
+        uint64_t i = base + (uint64_t)r * kPartThreads + t;
+        ed[r] = i < m ? edges[i] : make_int2(-1, -1);
+    }
+#pragma unroll
+    for (int r = 0; r < kPartEdges; ++r) {
+        uint64_t i = base + (uint64_t)r * kPartThreads + t;
+        if (i >= m) continue;
+        const int2 e = ed[r];
+        if (!endpoint_ok(e, n)) {
+            set_status(status, ((uint32_t)e.x >= n || (uint32_t)e.y >= n) ? TC_E_RANGE
+                                                                          : TC_E_SELF_LOOP);
+            continue;
+        }
+        atomicAdd(&h[(uint32_t)e.x >> sh], 1u);
+        if (!both) atomicAdd(&h[(uint32_t)e.y >> sh], 1u);
+    }
+    __syncthreads();
+    hist[(uint64_t)t * tiles + blockIdx.x] = h[t];
+}
+
+// endpoints of one tile placed bucket by bucket in LDS, then written as contiguous runs
+__global__ __launch_bounds__(kPartThreads) void k_part_scatter(
+    const int2 *__restrict__ edges, uint64_t m, uint32_t n, uint32_t both, int sh,
+    const uint32_t *__restrict__ hist, const uint32_t *__restrict__ offs, uint32_t tiles,
+    uint32_t *__restrict__ parts) {
+    __shared__ uint32_t s_stage[2 * kPartTile];
+    __shared__ uint32_t s_fill[256], s_glob[256], s_wsum[kPartThreads / kWave];
+    const uint32_t t = threadIdx.x, w = t / kWave;
+    const uint32_t c = hist[(uint64_t)t * tiles + blockIdx.x];
+    const uint32_t incl = wave_incl_scan(c);
+    if (lane_id() == kWave - 1) s_wsum[w] = incl;
+    __syncthreads();
+    uint32_t before = 0;
+    for (uint32_t k = 0; k < w; ++k) before += s_wsum[k];
+    const uint32_t loc = before + incl - c;
+    s_fill[t] = loc;
+    s_glob[t] = offs[(uint64_t)t * tiles + blockIdx.x] - loc;
+    __syncthreads();
+    const uint64_t base = (uint64_t)blockIdx.x * kPartTile;
+    int2 ed[kPartEdges];
+#pragma unroll
+    for (int r = 0; r < kPartEdges; ++r) {
+        uint64_t i = base + (uint64_t)r * kPartThreads + t;
+        ed[r] = i < m ? edges[i] : make_int2(-1, -1);
+    }
+#pragma unroll
+    for (int r = 0; r < kPartEdges; ++r) {
+        const int2 e = ed[r];
+        if (!endpoint_ok(e, n)) continue;  // also the padding beyond m
+        s_stage[atomicAdd(&s_fill[(uint32_t)e.x >> sh], 1u)] = (uint32_t)e.x;
+        if (!both) s_stage[atomicAdd(&s_fill[(uint32_t)e.y >> sh], 1u)] = (uint32_t)e.y;
+    }
+    __syncthreads();
+    const uint32_t total = s_fill[255];  // end of the last bucket = endpoints in this tile
+    for (uint32_t j = t; j < total; j += kPartThreads) {
+        const uint32_t x = s_stage[j];
+        parts[s_glob[x >> sh] + j] = x;
+    }
+}
+
+// Workgroup (bucket, slice): counts its slice of the bucket's endpoints in LDS, window by
+// window of kPartWindow ids, and adds the counts to deg (zeroed beforehand).
+__global__ __launch_bounds__(1024) void k_part_count(const uint32_t *__restrict__ parts,
+                                                     const uint32_t *__restrict__ offs,
+                                                     uint32_t tiles, int sh, uint32_t n,
+                                                     uint32_t slices,
+                                                     uint32_t *__restrict__ deg,
+                                                     const int32_t *__restrict__ status) {
+    if (*status) return;
+    __shared__ uint32_t cntr[kPartWindow];
+    const uint32_t t = threadIdx.x, bucket = blockIdx.x / slices, g = blockIdx.x % slices;
+    const uint32_t beg = offs[(uint64_t)bucket * tiles];
+    const uint32_t end = offs[(uint64_t)(bucket + 1) * tiles];  // entry 256 * tiles = total
+    const uint64_t len = end - beg;
+    const uint32_t s0 = beg + (uint32_t)(len * g / slices);
+    const uint32_t s1 = beg + (uint32_t)(len * (g + 1) / slices);
+    const uint64_t id0 = (uint64_t)bucket << sh;
+    if (id0 >= n) return;
+    const uint64_t ids = ((1ull << sh) < n - id0) ? (1ull << sh) : (n - id0);
+    for (uint64_t w0 = 0; w0 < ids; w0 += kPartWindow) {
+        const uint32_t wn = (uint32_t)((ids - w0) < kPartWindow ? (ids - w0) : kPartWindow);
+        for (uint32_t i = t; i < wn; i += blockDim.x) cntr[i] = 0;
+        __syncthreads();
+        const uint32_t lo = (uint32_t)(id0 + w0);
+        for (uint32_t j = s0 + t; j < s1; j += blockDim.x) {
+            const uint32_t o = parts[j] - lo;
+            if (o < wn) atomicAdd(&cntr[o], 1u);
+        }
+        __syncthreads();
+        for (uint32_t i = t; i < wn; i += blockDim.x) {
+            const uint32_t c = cntr[i];
+            if (c) atomicAdd(&deg[lo + i], c);
+        }
+        __syncthreads();
+    }
+}
+
+// Fallback for inputs whose endpoint count does not fit the partition's 32-bit offsets, or
+// whose buckets would need too many LDS windows: one atomic increment per endpoint.
+__global__ void k_degree_atomic(const int2 *__restrict__ edges, uint64_t m, uint32_t n,
+                                uint32_t both, uint32_t *__restrict__ deg,
+                                int32_t *__restrict__ status) {
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (; i < m; i += stride) {
-        int2 e = edges[i];
-        if ((uint32_t)e.x >= n || (uint32_t)e.y >= n) {
-            set_status(status, TC_E_RANGE);
-            continue;
-        }
-        if (e.x == e.y) {
-            set_status(status, TC_E_SELF_LOOP);
+        const int2 e = edges[i];
+        if (!endpoint_ok(e, n)) {
+            set_status(status, ((uint32_t)e.x >= n || (uint32_t)e.y >= n) ? TC_E_RANGE
+                                                                          : TC_E_SELF_LOOP);
             continue;
         }
         atomicAdd(&deg[e.x], 1u);
@@ -46,19 +163,16 @@ __global__ void k_degree(const int2 *__restrict__ edges, uint64_t m, uint32_t n,
     }
 }
 
-// deg[x] = sum of the striped counts; vkeys[x] = (degree << b) | x, whose stable sort on the
-// degree bits yields the total order of Section 2.2 (degree first, ties by id)
-__global__ void k_degree_sum(const uint32_t *__restrict__ deg_s, uint32_t n, int b,
-                             uint32_t *__restrict__ deg, uint64_t *__restrict__ vkeys) {
+// vkeys[x] = (degree << b) | x, whose stable sort on the degree bits yields the total order
+// of Section 2.2 (degree first, ties by id)
+__global__ void k_vkeys(const uint32_t *__restrict__ deg, uint32_t n, int b,
+                        uint64_t *__restrict__ vkeys) {
     uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
-    uint32_t d = 0;
-#pragma unroll
-    for (uint32_t k = 0; k < kStripes; ++k) d += deg_s[(size_t)k * n + x];
-    deg[x] = d;
     const uint64_t lim = (1ull << b) - 1;
-    uint64_t dk = d > lim ? lim : d;  // only possible for invalid input, reported elsewhere
-    vkeys[x] = (dk << b) | x;
+    uint64_t d = deg[x];
+    if (d > lim) d = lim;  // only possible for invalid input, which is reported elsewhere
+    vkeys[x] = (d << b) | x;
 }
 
 __global__ void k_rank(const uint64_t *__restrict__ sorted, uint32_t n, int b,
@@ -156,7 +270,7 @@ __global__ void k_vrange(const uint32_t *__restrict__ row_ptr, const uint32_t *_
 __global__ void k_csc_keys(const uint32_t *__restrict__ col, const uint32_t *__restrict__ src,
                            const uint32_t *__restrict__ row_ptr,
                            const uint64_t *__restrict__ vr, uint32_t mf, uint32_t n,
-                           uint32_t nblk, uint64_t *__restrict__ keys,
+                           uint32_t nblk, uint64_t *__restrict__ keys, uint2 *__restrict__ eu,
                            const int32_t *__restrict__ status) {
     if (*status) return;
     uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -171,6 +285,7 @@ __global__ void k_csc_keys(const uint32_t *__restrict__ col, const uint32_t *__r
             c = (uint64_t)(((uint64_t)e * nblk) / mf) * (n + 1) + v;
     }
     keys[e] = (c << 32) | e;
+    eu[e] = make_uint2(end_u, u);
 }
 
 // list boundaries of the sorted keys (useful in-edges only)
@@ -188,19 +303,19 @@ __global__ void k_csc_bounds(const uint64_t *__restrict__ keys, uint32_t mf, uin
 
 // the lists themselves: in-edge u -> v at CSR position e contributes the suffix [e + 1, end_u)
 __global__ void k_csc_final(const uint64_t *__restrict__ keys, uint32_t mf, uint64_t lists,
-                            const uint32_t *__restrict__ src, const uint32_t *__restrict__ row_ptr,
-                            uint32_t *__restrict__ cbeg, uint32_t *__restrict__ cend,
-                            uint32_t *__restrict__ cu, const int32_t *__restrict__ status) {
+                            const uint2 *__restrict__ eu, uint32_t *__restrict__ cbeg,
+                            uint32_t *__restrict__ cend, uint32_t *__restrict__ cu,
+                            const int32_t *__restrict__ status) {
     if (*status) return;
     uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= mf) return;
     const uint64_t k = keys[j];
     if ((k >> 32) >= lists) return;
     const uint32_t e = (uint32_t)k;
-    const uint32_t u = src[e];
+    const uint2 x = eu[e];
     cbeg[j] = e + 1;
-    cend[j] = row_ptr[u + 1];
-    cu[j] = u;
+    cend[j] = x.x;
+    cu[j] = x.y;
 }
 
 // Work items of the counting kernel.  A vertex's in-edges are cut into chunks; the chunks go

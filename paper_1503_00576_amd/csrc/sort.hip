@@ -145,11 +145,16 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t *__r
     __syncthreads();
     const uint32_t mask = (1u << nbits) - 1u;
     const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
-#pragma unroll 4
+    uint32_t dg[kSortItems];  // all loads in flight before any ranking
+#pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         uint64_t idx = base + (uint64_t)r * kSortThreads + t;
-        bool valid = idx < count;
-        uint32_t d = valid ? (uint32_t)(in[idx] >> shift) & mask : 0u;
+        dg[r] = idx < count ? (uint32_t)(in[idx] >> shift) & mask : 0xFFFFFFFFu;
+    }
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        bool valid = dg[r] != 0xFFFFFFFFu;
+        uint32_t d = valid ? dg[r] : 0u;
         uint64_t peers = match_digit(d, nbits, valid);
         if (valid && lanes_below(peers) == 0) h[w][d] += (uint32_t)__popcll(peers);
     }
@@ -188,10 +193,17 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     __syncthreads();
     const uint32_t mask = (1u << nbits) - 1u;
     const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+    uint64_t keys[kSortItems];  // all loads in flight before any ranking
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        uint64_t idx = base + (uint64_t)r * kSortThreads + t;
+        keys[r] = idx < count ? in[idx] : 0ull;
+    }
+#pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         uint64_t idx = base + (uint64_t)r * kSortThreads + t;
         bool valid = idx < count;
-        uint64_t key = valid ? in[idx] : 0ull;
+        uint64_t key = keys[r];
         uint32_t d = (uint32_t)(key >> shift) & mask;
         uint64_t peers = match_digit(d, nbits, valid);
         uint32_t rank = lanes_below(peers);
