@@ -29,9 +29,9 @@ constexpr int kThreads = 512;
 constexpr int kWaves = kThreads / kWave;
 constexpr uint32_t kLdsWords = 16384;                 // 64 KiB per workgroup
 constexpr uint32_t kSliceWords = kLdsWords / kWaves;  // 8 KiB per wave
-constexpr uint32_t kWaveBits = kSliceWords * 32;      // wave bitmap: rank span < 65536
+constexpr uint32_t kWaveBits = kSliceWords * 32 - 32; // wave bitmap: span < 65504
 constexpr uint32_t kWaveListPV = kSliceWords / 2;     // per-vertex: list + counters per wave
-constexpr uint32_t kBlockBits = kLdsWords * 32;       // workgroup bitmap: span < 524288
+constexpr uint32_t kBlockBits = kLdsWords * 32 - 32;  // workgroup bitmap: span < 524256
 constexpr uint32_t kBlockList = kLdsWords;            // workgroup sorted list
 constexpr uint32_t kBlockListPV = kLdsWords / 2;      // per-vertex: list + counters
 constexpr uint32_t kItemEdgesWave = 256;
@@ -39,13 +39,18 @@ constexpr uint32_t kItemEdgesBlock = 2048;
 
 // ------------------------------------------------------------------ membership probes
 
+// N+(v) as a bitmap over ranks [lo, lo + span].  Bit span + 1 is always zero and lies inside
+// the LDS region (spans are kept below the region's bits minus 32), so an id outside the span
+// is clamped onto it instead of branching: every lookup is one unconditional LDS read.
 struct BitmapProbe {
     const uint32_t *bm;
-    uint32_t lo, span;  // bitmap covers ranks [lo, lo + span]
-    __device__ __forceinline__ bool operator()(uint32_t w, uint32_t &) const {
-        uint32_t o = w - lo;
-        return o <= span && ((bm[o >> 5] >> (o & 31u)) & 1u);
+    uint32_t lo, span;
+    static constexpr bool kBranchFree = true;
+    __device__ __forceinline__ uint32_t bit(uint32_t w) const {
+        const uint32_t o = min(w - lo, span + 1u);
+        return __builtin_amdgcn_ubfe(bm[__builtin_amdgcn_ubfe(o, 5u, 27u)], o, 1u);
     }
+    __device__ __forceinline__ bool operator()(uint32_t w, uint32_t &) const { return bit(w); }
 };
 
 // lower_bound with a lane-independent trip count (d is uniform)
@@ -63,6 +68,7 @@ __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t *list, uint32
 struct ListProbe {  // sorted list in LDS or in global memory
     const uint32_t *list;
     uint32_t d;
+    static constexpr bool kBranchFree = false;
     __device__ __forceinline__ bool operator()(uint32_t w, uint32_t &pos) const {
         pos = lower_bound_u32(list, d, w);
         return pos < d && list[pos] == w;
@@ -132,17 +138,29 @@ __device__ __forceinline__ uint32_t run_batch(uint32_t eb, uint32_t e1,
                 wv[4 * j + 3] = x.w;
             }
             uint32_t hits = 0;
+            // element i of the piece belongs to the suffix iff start + i - first < stop - first
+            const uint32_t rel0 = start - first, len = stop - first;
+            if constexpr (!PV && Probe::kBranchFree) {
+                // the piece's valid elements are the contiguous range [lo_i, hi_i) of positions
+                uint32_t packed = 0;
 #pragma unroll
-            for (uint32_t i = 0; i < kPiece; ++i) {
-                const uint32_t idx = start + i;
-                if (idx >= first && idx < stop) {
-                    const uint32_t w = wv[i];
-                    uint32_t pos;
-                    if (probe(w, pos)) {
-                        ++hits;
-                        if (PV) {
-                            if (tcnt) atomicAdd(&tcnt[pos], 1u);
-                            else atomicAdd(&tpv[w], 1ull);
+                for (uint32_t i = 0; i < kPiece; ++i) packed |= probe.bit(wv[i]) << i;
+                const uint32_t lo_i = first > start ? first - start : 0u;
+                const uint32_t hi_i = min(stop - start, kPiece);
+                const uint32_t mask = ((1u << hi_i) - 1u) & ~((1u << lo_i) - 1u);
+                hits = __popc(packed & mask);
+            } else {
+#pragma unroll
+                for (uint32_t i = 0; i < kPiece; ++i) {
+                    if (rel0 + i < len) {
+                        const uint32_t w = wv[i];
+                        uint32_t pos;
+                        if (probe(w, pos)) {
+                            ++hits;
+                            if (PV) {
+                                if (tcnt) atomicAdd(&tcnt[pos], 1u);
+                                else atomicAdd(&tpv[w], 1ull);
+                            }
                         }
                     }
                 }
