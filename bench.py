@@ -90,6 +90,61 @@ def cpu_baseline(dev, seconds_hint: float):
                       f"in {dt:.2f} s on one host core"}
 
 
+def batched_section(dev, steps: int):
+    """4096 Barabasi-Albert / Watts-Strogatz graphs (50/50, n log-uniform in [50, 20000],
+    average degree in [4, 32]) in one captured plan, tuned, against a loop of one tc_count
+    call per graph on the same GPU."""
+    import torch
+    from paper_1503_00576_amd import api, autotune, synth
+    spec = synth.BatchSpec(graphs=4096, seed=0)
+    t0 = time.perf_counter()
+    graphs = synth.batch_graphs(spec, device=dev)
+    packed = synth.pack_symmetric(graphs, device=dev)
+    b = api.Batch(packed["vtx_off"], packed["adj_off"], packed["row_ptr"], packed["col"],
+                  packed["G"], packed["n_total"], packed["adj_total"])
+    edges = packed["adj_total"] // 2
+    torch.cuda.synchronize()
+    log(f"batch: {b.G} graphs, {b.n_total} vertices, {edges} edges in "
+        f"{time.perf_counter() - t0:.1f} s")
+    best, timings = autotune.tune_batched(b)
+    log(f"tuned: {best} ({min(t for _, t in timings):.3f} ms)")
+    plan = api.BatchPlan(b.G, b.n_total, b.adj_total, best, device=dev)
+    res = plan.run_async(b)
+    torch.cuda.synchronize()
+    res.check()
+    totals = res.totals.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.run_async(b, out=res)
+    torch.cuda.synchronize()
+    batch_ms = (time.perf_counter() - t0) * 1e3 / steps
+    assert torch.equal(res.totals, totals)
+    # the plain per-graph loop: one tc_count per graph, workspace sized for the largest
+    nmax = max(n for _, n in graphs)
+    mmax = max(int(e.shape[0]) for e, _ in graphs)
+    ws = api.alloc_workspace(nmax, mmax, False, dev)
+    outs = [api.Result(torch.empty(1, dtype=torch.int64, device=dev),
+                       torch.empty(1, dtype=torch.int32, device=dev)) for _ in graphs]
+    for (e, n), o in zip(graphs, outs):
+        api.count_async(e, n, workspace=ws, out=o)
+    torch.cuda.synchronize()
+    loop_totals = torch.cat([o.total for o in outs])
+    assert torch.equal(loop_totals, totals), "batched and per-graph totals differ"
+    t0 = time.perf_counter()
+    for (e, n), o in zip(graphs, outs):
+        api.count_async(e, n, workspace=ws, out=o)
+    torch.cuda.synchronize()
+    loop_ms = (time.perf_counter() - t0) * 1e3
+    plan.close()
+    return {"graphs": b.G, "vertices": b.n_total, "edges": edges,
+            "triangles": int(totals.sum().item()), "ms_per_batch": round(batch_ms, 3),
+            "graphs_per_s": b.G / (batch_ms * 1e-3), "edges_per_s": edges / (batch_ms * 1e-3),
+            "loop_ms": round(loop_ms, 3), "loop_graphs_per_s": b.G / (loop_ms * 1e-3),
+            "speedup_vs_loop": round(loop_ms / batch_ms, 2), "tuning": best,
+            "tuning_ms": [[t, round(ms, 3)] for t, ms in timings]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +152,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat23", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched measurement (4096 small graphs)")
+    ap.add_argument("--batched-only", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run three plain 1 GiB device-to-device copies (counter scale)")
     args = ap.parse_args()
@@ -118,6 +176,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         log("copied 3 x 1 GiB")
+        return
+    if args.batched_only:
+        print(json.dumps({"batched": batched_section(dev, args.steps)}), flush=True)
         return
     log(f"generating {WORKLOADS[args.workload]['label']}")
     t0 = time.perf_counter()
@@ -207,7 +268,12 @@ def main():
         "triangles_per_s": total / (ms_per_step * 1e-3),
         "roofline": roofline,
         "cpu_baseline": None,
+        "batched": None,
     }
+    if not args.no_batched:
+        log("batched: 4096 graphs ...")
+        res["batched"] = batched_section(dev, args.steps)
+        log("batched done")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample) ...")
         res["cpu_baseline"] = cpu_baseline(dev, 20.0)

@@ -123,6 +123,51 @@ size_t tc_sort_workspace_size(int64_t count);
 int tc_sort_u64(uint64_t *d_keys, uint64_t *d_tmp, int64_t count, int32_t bits, void *d_ws,
                 size_t ws_bytes, void *stream);
 
+/* ---------------------------------------------------------------- batched counting
+ *
+ * Many independent graphs counted by one launch sequence.  Input: the graphs' symmetric
+ * adjacency lists (every undirected edge in both rows, rows strictly ascending; the
+ * adjacency-list format of Section 3.1), concatenated:
+ *   d_vtx_off: int64[G+1], d_vtx_off[0] = 0; graph g has n_g = d_vtx_off[g+1] - d_vtx_off[g]
+ *              vertices, numbered d_vtx_off[g] .. d_vtx_off[g+1]-1 in the union
+ *   d_adj_off: int64[G+1], d_adj_off[0] = 0; graph g's adjacency entries are
+ *              d_col[d_adj_off[g] .. d_adj_off[g+1])
+ *   d_row_ptr: int32[n_total + G]; graph g's n_g + 1 row offsets (0 .. its entry count) are at
+ *              d_row_ptr[d_vtx_off[g] + g ..]
+ *   d_col    : int32[adj_total], local vertex ids 0 .. n_g - 1
+ * Output: d_totals uint64[G] (triangles per graph), d_per_vertex uint64[n_total] (per vertex of
+ * the union, nullable), d_status int32[G] (per-graph data error, nullable: range, self-loop,
+ * duplicate or unsorted row, missing mirror entry, inconsistent offsets).
+ * Method: degree = row length; a stable per-row filter keeps the neighbours later in the
+ * order of Section 2.2, so the oriented rows stay sorted without any sort; the counting kernel
+ * stages N+(u) in LDS and streams the lists N+(v) of u's out-neighbours (Section 2.2's
+ * intersections, grouped by u).
+ *
+ * A plan binds a workspace of tc_batched_workspace_size(g_cap, n_cap, adj_cap) bytes and
+ * captures the whole launch sequence once per mode (with / without per-vertex counts) into a
+ * hipGraph on its first run; later runs only write a small argument block and replay the
+ * graph, for any batch within the capacities.  tuning_json (nullable) may set "items_k"
+ * (out-neighbours per work item, >= 16, default 256) and "wgs_per_cu" (1 or 2, default 2).
+ * Runs of one plan must not overlap (they share the workspace); the plan must outlive its
+ * last run on the GPU.  flags must be 0. */
+typedef struct tc_plan tc_plan;
+
+size_t tc_batched_workspace_size(int32_t g_cap, int64_t n_cap, int64_t adj_cap);
+int tc_batched_plan_create(int32_t g_cap, int64_t n_cap, int64_t adj_cap, uint32_t flags,
+                           const char *tuning_json, void *d_ws, size_t ws_bytes,
+                           tc_plan **out);
+int tc_batched_plan_run(tc_plan *plan, int32_t G, const int64_t *d_vtx_off,
+                        const int64_t *d_adj_off, const int32_t *d_row_ptr, const int32_t *d_col,
+                        int64_t n_total, int64_t adj_total, void *stream, uint64_t *d_totals,
+                        uint64_t *d_per_vertex, int32_t *d_status);
+void tc_batched_plan_destroy(tc_plan *plan);
+
+/* One-shot form: the same launch sequence enqueued directly (no graph capture). */
+int tc_count_batched(int32_t G, const int64_t *d_vtx_off, const int64_t *d_adj_off,
+                     const int32_t *d_row_ptr, const int32_t *d_col, int64_t n_total,
+                     int64_t adj_total, void *d_ws, size_t ws_bytes, void *stream,
+                     uint64_t *d_totals, uint64_t *d_per_vertex, int32_t *d_status);
+
 #ifdef __cplusplus
 }
 #endif

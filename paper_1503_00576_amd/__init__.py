@@ -4,6 +4,6 @@ kernels behind a C ABI (libtc.so, include/tc.h).
 
 The library is loaded on first use; importing the package (e.g. for ``synth``) does not need
 it.  ``api`` holds the binding; ``synth`` the seeded synthetic inputs."""
-from .api import (EDGES_BOTH, EDGES_ONCE, Result, TCError, alloc_workspace, clustering, count,  # noqa: F401
+from .api import (Batch, BatchPlan, BatchResult, EDGES_BOTH, batched_workspace_size, count_batched, EDGES_ONCE, Result, TCError, alloc_workspace, clustering, count,  # noqa: F401
                   count_async, count_per_vertex, layout, Prepared, preprocess, sort_u64, transitivity,
                   workspace_size)

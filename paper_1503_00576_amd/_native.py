@@ -10,7 +10,9 @@ LIB_PATH = os.environ.get("TC_LIB", os.path.join(HERE, "libtc.so"))
 
 EXPORTS = [
     "tc_strerror", "tc_workspace_size", "tc_count", "tc_count_per_vertex",
-    "tc_workspace_layout", "tc_preprocess", "tc_count_prepared", "tc_sort_workspace_size", "tc_sort_u64",
+    "tc_workspace_layout", "tc_preprocess", "tc_count_prepared", "tc_sort_workspace_size",
+    "tc_sort_u64", "tc_batched_workspace_size", "tc_batched_plan_create", "tc_batched_plan_run",
+    "tc_batched_plan_destroy", "tc_count_batched",
 ]
 
 
@@ -51,5 +53,17 @@ def lib():
     L.tc_sort_workspace_size.restype = sz
     L.tc_sort_u64.argtypes = [vp, vp, i64, ctypes.c_int32, vp, sz, vp]
     L.tc_sort_u64.restype = ctypes.c_int
+    i32 = ctypes.c_int32
+    L.tc_batched_workspace_size.argtypes = [i32, i64, i64]
+    L.tc_batched_workspace_size.restype = sz
+    L.tc_batched_plan_create.argtypes = [i32, i64, i64, u32, ctypes.c_char_p, vp, sz,
+                                         ctypes.POINTER(vp)]
+    L.tc_batched_plan_create.restype = ctypes.c_int
+    L.tc_batched_plan_run.argtypes = [vp, i32, vp, vp, vp, vp, i64, i64, vp, vp, vp, vp]
+    L.tc_batched_plan_run.restype = ctypes.c_int
+    L.tc_batched_plan_destroy.argtypes = [vp]
+    L.tc_batched_plan_destroy.restype = None
+    L.tc_count_batched.argtypes = [i32, vp, vp, vp, vp, i64, i64, vp, sz, vp, vp, vp, vp]
+    L.tc_count_batched.restype = ctypes.c_int
     _lib = L
     return L

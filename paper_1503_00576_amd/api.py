@@ -212,3 +212,100 @@ def transitivity(total: int, degree) -> float:
     d = np.asarray(degree.cpu() if hasattr(degree, "cpu") else degree, dtype=np.int64)
     wedges = int((d * (d - 1) // 2).sum())
     return 0.0 if wedges == 0 else 3.0 * total / wedges
+
+
+# ------------------------------------------------------------------ batched counting
+
+@dataclass
+class Batch:
+    """Concatenated symmetric CSRs of G graphs on the device (see tc.h, batched counting)."""
+    vtx_off: torch.Tensor   # int64 [G+1]
+    adj_off: torch.Tensor   # int64 [G+1]
+    row_ptr: torch.Tensor   # int32 [n_total + G]
+    col: torch.Tensor       # int32 [adj_total]
+    G: int
+    n_total: int
+    adj_total: int
+
+
+@dataclass
+class BatchResult:
+    totals: torch.Tensor            # uint64 as int64 [G]
+    status: torch.Tensor            # int32 [G]
+    per_vertex: torch.Tensor | None = None   # uint64 as int64 [n_total]
+
+    def check(self) -> "BatchResult":
+        bad = torch.nonzero(self.status).flatten()
+        if bad.numel():
+            g = int(bad[0])
+            raise TCError(int(self.status[g]), f"graph {g}")
+        return self
+
+
+def batched_workspace_size(g_cap: int, n_cap: int, adj_cap: int) -> int:
+    s = _native.lib().tc_batched_workspace_size(int(g_cap), int(n_cap), int(adj_cap))
+    if s == 0:
+        raise TCError(E_ARG, "tc_batched_workspace_size")
+    return s
+
+
+class BatchPlan:
+    """A captured launch sequence for batches within (g_cap, n_cap, adj_cap), bound to its own
+    workspace; run() replays it on the current stream."""
+
+    def __init__(self, g_cap: int, n_cap: int, adj_cap: int, tuning: dict | None = None,
+                 device=None):
+        import json
+        self.device = torch.device(device if device is not None else "cuda")
+        self.caps = (int(g_cap), int(n_cap), int(adj_cap))
+        self.workspace = torch.empty(batched_workspace_size(*self.caps), dtype=torch.uint8,
+                                     device=self.device)
+        self.tuning = dict(tuning or {})
+        js = json.dumps(self.tuning).encode() if self.tuning else None
+        h = ctypes.c_void_p()
+        _raise(_native.lib().tc_batched_plan_create(*self.caps, 0, js, _ptr(self.workspace),
+                                                    self.workspace.numel(), ctypes.byref(h)),
+               "tc_batched_plan_create")
+        self._h = h
+
+    def run_async(self, b: Batch, per_vertex: bool = False,
+                  out: BatchResult | None = None) -> BatchResult:
+        dev = self.device
+        if out is None:
+            out = BatchResult(torch.empty(b.G, dtype=torch.int64, device=dev),
+                              torch.empty(b.G, dtype=torch.int32, device=dev),
+                              torch.empty(b.n_total, dtype=torch.int64, device=dev)
+                              if per_vertex else None)
+        _raise(_native.lib().tc_batched_plan_run(
+            self._h, b.G, _ptr(b.vtx_off), _ptr(b.adj_off), _ptr(b.row_ptr), _ptr(b.col),
+            b.n_total, b.adj_total, _stream(dev), _ptr(out.totals),
+            _ptr(out.per_vertex) if per_vertex else None, _ptr(out.status)),
+            "tc_batched_plan_run")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            torch.cuda.synchronize(self.device)
+            _native.lib().tc_batched_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def count_batched(b: Batch, per_vertex: bool = False) -> BatchResult:
+    """One-shot batched count (no graph capture); returns checked results."""
+    dev = b.vtx_off.device
+    ws = torch.empty(batched_workspace_size(b.G, b.n_total, b.adj_total), dtype=torch.uint8,
+                     device=dev)
+    out = BatchResult(torch.empty(b.G, dtype=torch.int64, device=dev),
+                      torch.empty(b.G, dtype=torch.int32, device=dev),
+                      torch.empty(b.n_total, dtype=torch.int64, device=dev) if per_vertex else None)
+    _raise(_native.lib().tc_count_batched(
+        b.G, _ptr(b.vtx_off), _ptr(b.adj_off), _ptr(b.row_ptr), _ptr(b.col), b.n_total,
+        b.adj_total, _ptr(ws), ws.numel(), _stream(dev), _ptr(out.totals),
+        _ptr(out.per_vertex) if per_vertex else None, _ptr(out.status)), "tc_count_batched")
+    return out.check()

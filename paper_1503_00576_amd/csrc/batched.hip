@@ -1,0 +1,430 @@
+// Batched counting: many small graphs in one launch sequence, captured once in a hipGraph.
+//
+// Input: the graphs' symmetric adjacency lists (the format Section 3.1 contrasts with the
+// edge array), concatenated.  Graph g has n_g = vtx_off[g+1] - vtx_off[g] vertices and its
+// own CSR: row_ptr entries [vtx_off[g] + g, vtx_off[g+1] + g] (local offsets 0..len_g) and
+// col entries [adj_off[g], adj_off[g+1]) (local ids, rows strictly ascending).  In the disjoint
+// union, vertex x of graph g has id vtx_off[g] + x.
+//
+// Preprocessing needs no sort: the degree of a vertex is its row length, and keeping in every
+// row only the neighbours that come later in the order of Section 2.2 ((degree, id)
+// ascending) is a stable filter, so the oriented rows stay sorted by id.  The counting kernel
+// (k_count_u) then stages N+(u) and streams N+(v) for the out-neighbours v.
+//
+// Every kernel reads the sizes and the caller's pointers from an argument block at the start
+// of the workspace and runs over the plan's capacities, so one captured graph serves every
+// batch that fits the plan.
+#include <stdlib.h>
+#include <string.h>
+
+#include "internal.h"
+
+namespace tc {
+
+struct BatchArgs {
+    const int64_t *vtx_off;
+    const int64_t *adj_off;
+    const int32_t *row_ptr;
+    const int32_t *col;
+    unsigned long long *totals;
+    unsigned long long *per_vertex;
+    int32_t *status;  // per graph, may be null
+    uint32_t G, N, kitem;
+    uint32_t A;  // adjacency entries in total
+};
+
+__device__ __forceinline__ void graph_error(const BatchArgs &a, uint32_t g, int32_t code,
+                                            int32_t *gstat) {
+    atomicCAS(&gstat[g], 0, code);
+}
+
+// graph of union vertex x: the last g with vtx_off[g] <= x
+__device__ __forceinline__ uint32_t graph_of(const int64_t *vtx_off, uint32_t G, uint32_t x) {
+    uint32_t lo = 0, len = G;
+    while (len > 1) {
+        const uint32_t half = len >> 1;
+        if (vtx_off[lo + half] <= (int64_t)x) lo += half;
+        len -= half;
+    }
+    return lo;
+}
+
+__global__ void k_b_set_args(BatchArgs *dst, BatchArgs a) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = a;
+}
+
+// zero the outputs and the internal status / queue
+__global__ void k_b_clear(const BatchArgs *__restrict__ args, int32_t *__restrict__ gstat,
+                          uint32_t *__restrict__ queue, uint32_t cap) {
+    const BatchArgs a = *args;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *queue = 0;
+    for (uint32_t x = i; x < cap; x += gridDim.x * blockDim.x) {
+        if (x < a.G) {
+            a.totals[x] = 0;
+            gstat[x] = 0;
+        }
+        if (a.per_vertex && x < a.N) a.per_vertex[x] = 0;
+    }
+}
+
+// degrees (row lengths), graph ids, checks of every row: offsets in range, ids in range, no
+// self-loop, strictly ascending
+__global__ void k_b_setup(const BatchArgs *__restrict__ args, uint32_t ncap,
+                          uint32_t *__restrict__ gid, uint32_t *__restrict__ deg,
+                          int32_t *__restrict__ gstat) {
+    const BatchArgs a = *args;
+    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= ncap) return;
+    if (x >= a.N) {
+        deg[x] = 0;
+        return;
+    }
+    const uint32_t g = graph_of(a.vtx_off, a.G, x);
+    gid[x] = g;
+    const int64_t v0 = a.vtx_off[g], ng = a.vtx_off[g + 1] - v0;
+    const int64_t a0 = a.adj_off[g], alen = a.adj_off[g + 1] - a0;
+    const int64_t local = (int64_t)x - v0;
+    // offsets arrays must be prefix sums: check what this vertex relies on
+    if (v0 < 0 || local < 0 || local >= ng || a0 < 0 || alen < 0 || a0 + alen > (int64_t)a.A) {
+        graph_error(a, g, TC_E_ARG, gstat);
+        deg[x] = 0;
+        return;
+    }
+    const int32_t *rp = a.row_ptr + v0 + g;
+    const int64_t r0 = rp[local], r1 = rp[local + 1];
+    uint32_t d = 0;
+    if (r0 < 0 || r1 < r0 || r1 > alen) {
+        graph_error(a, g, TC_E_ARG, gstat);
+    } else {
+        d = (uint32_t)(r1 - r0);
+        const int32_t *row = a.col + a0 + r0;
+        int64_t prev = -1;
+        for (uint32_t j = 0; j < d; ++j) {
+            const int32_t y = row[j];
+            if (y < 0 || y >= ng) {
+                graph_error(a, g, TC_E_RANGE, gstat);
+            } else if (y == local) {
+                graph_error(a, g, TC_E_SELF_LOOP, gstat);
+            } else if (y <= prev) {
+                graph_error(a, g, y == prev ? TC_E_DUP_EDGE : TC_E_UNSORTED, gstat);
+            }
+            prev = y;
+        }
+    }
+    deg[x] = d;
+}
+
+__device__ __forceinline__ bool b_forward(uint32_t x, uint32_t y, const uint32_t *deg) {
+    return deg[y] > deg[x] || (deg[y] == deg[x] && y > x);
+}
+
+// forward out-degrees (entries ncap.. stay zero for the scan)
+__global__ void k_b_fcount(const BatchArgs *__restrict__ args, uint32_t ncap,
+                           const uint32_t *__restrict__ gid, const uint32_t *__restrict__ deg,
+                           uint32_t *__restrict__ fdeg) {
+    const BatchArgs a = *args;
+    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x > ncap) return;
+    uint32_t c = 0;
+    if (x < a.N && deg[x] > 0) {
+        const uint32_t g = gid[x];
+        const int64_t v0 = a.vtx_off[g], ng = a.vtx_off[g + 1] - v0;
+        const int32_t *row = a.col + a.adj_off[g] + a.row_ptr[x + g];
+        for (uint32_t j = 0; j < deg[x]; ++j) {
+            const int32_t y = row[j];
+            if (y >= 0 && y < ng && y != (int64_t)x - v0 &&
+                b_forward(x, (uint32_t)(v0 + y), deg))
+                ++c;
+        }
+    }
+    fdeg[x] = c;
+}
+
+// the forward rows (union ids, input order kept), and the symmetry check: every forward
+// entry (x, y) needs its mirror in row y
+__global__ void k_b_ffill(const BatchArgs *__restrict__ args, const uint32_t *__restrict__ gid,
+                          const uint32_t *__restrict__ deg, const uint32_t *__restrict__ frp,
+                          uint32_t *__restrict__ fcol, int32_t *__restrict__ gstat) {
+    const BatchArgs a = *args;
+    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= a.N || deg[x] == 0) return;
+    const uint32_t g = gid[x];
+    const int64_t v0 = a.vtx_off[g], ng = a.vtx_off[g + 1] - v0;
+    const int32_t *cg = a.col + a.adj_off[g];
+    const int32_t *rp = a.row_ptr + v0 + g;
+    const int32_t lx = (int32_t)((int64_t)x - v0);
+    const int32_t *row = cg + rp[lx];
+    uint32_t o = frp[x];
+    for (uint32_t j = 0; j < deg[x]; ++j) {
+        const int32_t y = row[j];
+        if (y < 0 || y >= ng || y == lx) continue;
+        const uint32_t Y = (uint32_t)(v0 + y);
+        if (!b_forward(x, Y, deg)) continue;
+        fcol[o++] = Y;
+        // mirror: binary search for lx in row y (rows of invalid graphs may be unsorted;
+        // the search stays inside the row either way)
+        const int32_t *ry = cg + rp[y];
+        uint32_t lo = 0, len = deg[Y];
+        while (len > 0) {
+            const uint32_t half = len >> 1;
+            if (ry[lo + half] < lx) {
+                lo += half + 1;
+                len -= half + 1;
+            } else {
+                len = half;
+            }
+        }
+        if (lo >= deg[Y] || ry[lo] != lx) graph_error(a, g, TC_E_ASYMMETRIC, gstat);
+    }
+}
+
+// work items: rows with at least two forward neighbours, in chunks of kitem
+__global__ void k_b_items(const BatchArgs *__restrict__ args, uint32_t ncap,
+                          const uint32_t *__restrict__ fdeg, uint32_t *__restrict__ items) {
+    const BatchArgs a = *args;
+    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x > ncap) return;
+    const uint32_t d = (x < a.N) ? fdeg[x] : 0u;
+    items[x] = d >= 2 ? (d + a.kitem - 1) / a.kitem : 0u;
+}
+
+__global__ void k_b_item_fill(const uint32_t *__restrict__ items,
+                              const uint32_t *__restrict__ off, uint32_t ncap,
+                              uint32_t *__restrict__ item_u) {
+    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= ncap) return;
+    const uint32_t k = items[x], o = off[x];
+    for (uint32_t j = 0; j < k; ++j) item_u[o + j] = x;
+}
+
+// per-graph status out (the caller's array, when given); kitem for the counting kernel
+__global__ void k_b_finish(const BatchArgs *__restrict__ args,
+                           const int32_t *__restrict__ gstat) {
+    const BatchArgs a = *args;
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a.status && g < a.G) a.status[g] = gstat[g];
+}
+
+// ------------------------------------------------------------------ workspace + plan
+
+struct BatchLayout {
+    size_t args, ctl, gstat, gid, deg, fdeg, frp, fcol, items, ioff, item_u, scan, total;
+};
+
+constexpr uint32_t kMinItemEdges = 16;
+
+static BatchLayout batch_layout(uint32_t gcap, uint32_t ncap, uint64_t acap) {
+    BatchLayout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align_up(off + (bytes ? bytes : 1), 256);
+        return at;
+    };
+    const uint64_t n1 = (uint64_t)ncap + 1;
+    L.args = take(sizeof(BatchArgs));
+    L.ctl = take(64 * 4);
+    L.gstat = take((size_t)gcap * 4);
+    L.gid = take((size_t)ncap * 4);
+    L.deg = take((size_t)ncap * 4);
+    L.fdeg = take(n1 * 4);
+    L.frp = take(n1 * 4);
+    L.fcol = take((size_t)acap * 4 + 64);
+    L.items = take(n1 * 4);
+    L.ioff = take(n1 * 4);
+    L.item_u = take(((size_t)acap / kMinItemEdges + n1 + 1) * 4);
+    L.scan = take(scan_scratch_words(n1) * 4);
+    L.total = off;
+    return L;
+}
+
+}  // namespace tc
+
+using namespace tc;
+
+struct tc_plan {
+    uint32_t gcap, ncap;
+    uint64_t acap;
+    uint32_t kitem, wgs_per_cu;
+    void *ws;
+    size_t ws_bytes;
+    BatchLayout L;
+    hipGraph_t graph[2];
+    hipGraphExec_t exec[2];
+};
+
+static uint32_t parse_tuning(const char *json, const char *key, uint32_t dflt) {
+    if (!json) return dflt;
+    const char *p = strstr(json, key);
+    if (!p) return dflt;
+    p = strchr(p + strlen(key), ':');
+    if (!p) return dflt;
+    long v = strtol(p + 1, nullptr, 10);
+    return v > 0 ? (uint32_t)v : dflt;
+}
+
+// enqueue the whole sequence (this is what gets captured)
+static int batch_enqueue(tc_plan *p, bool pv, hipStream_t s) {
+    const BatchLayout &L = p->L;
+    char *ws = (char *)p->ws;
+    const BatchArgs *args = (const BatchArgs *)(ws + L.args);
+    uint32_t *ctl = (uint32_t *)(ws + L.ctl);
+    int32_t *gstat = (int32_t *)(ws + L.gstat);
+    uint32_t *gid = (uint32_t *)(ws + L.gid), *deg = (uint32_t *)(ws + L.deg);
+    uint32_t *fdeg = (uint32_t *)(ws + L.fdeg), *frp = (uint32_t *)(ws + L.frp);
+    uint32_t *fcol = (uint32_t *)(ws + L.fcol), *items = (uint32_t *)(ws + L.items);
+    uint32_t *ioff = (uint32_t *)(ws + L.ioff), *item_u = (uint32_t *)(ws + L.item_u);
+    uint32_t *scan = (uint32_t *)(ws + L.scan);
+    const uint32_t ncap = p->ncap, n1 = ncap + 1;
+    const uint32_t cap = ncap > p->gcap ? ncap : p->gcap;
+    auto grid = [](uint64_t n) { return dim3((uint32_t)((n + 255) / 256)); };
+    hipLaunchKernelGGL(k_b_clear, dim3(1024), dim3(256), 0, s, args, gstat, ctl, cap);
+    hipLaunchKernelGGL(k_b_setup, grid(ncap), dim3(256), 0, s, args, ncap, gid, deg, gstat);
+    hipLaunchKernelGGL(k_b_fcount, grid(n1), dim3(256), 0, s, args, ncap, gid, deg, fdeg);
+    if (hipGetLastError() != hipSuccess) return TC_E_HIP;
+    if (scan_exclusive_u32(fdeg, frp, n1, scan, s) != hipSuccess) return TC_E_HIP;
+    hipLaunchKernelGGL(k_b_ffill, grid(ncap), dim3(256), 0, s, args, gid, deg, frp, fcol, gstat);
+    hipLaunchKernelGGL(k_b_items, grid(n1), dim3(256), 0, s, args, ncap, fdeg, items);
+    if (hipGetLastError() != hipSuccess) return TC_E_HIP;
+    if (scan_exclusive_u32(items, ioff, n1, scan, s) != hipSuccess) return TC_E_HIP;
+    hipLaunchKernelGGL(k_b_item_fill, grid(ncap), dim3(256), 0, s, items, ioff, ncap, item_u);
+    if (hipGetLastError() != hipSuccess) return TC_E_HIP;
+    const BatchArgs *dev_args = args;
+    if (launch_count_u(frp, fcol, gid, item_u, ioff, ioff + ncap, &dev_args->kitem, ctl, &dev_args->totals,
+                       &dev_args->per_vertex, pv, device_cu_count() * p->wgs_per_cu,
+                       s) != hipSuccess)
+        return TC_E_HIP;
+    hipLaunchKernelGGL(k_b_finish, grid(p->gcap), dim3(256), 0, s, args, gstat);
+    return hipGetLastError() == hipSuccess ? TC_OK : TC_E_HIP;
+}
+
+static int batch_capture(tc_plan *p, bool pv) {
+    const int k = pv ? 1 : 0;
+    if (p->exec[k]) return TC_OK;
+    hipStream_t cs;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return TC_E_HIP;
+    int st = TC_OK;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        return TC_E_HIP;
+    }
+    st = batch_enqueue(p, pv, cs);
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(cs, &g) != hipSuccess || !g) st = TC_E_HIP;
+    (void)hipStreamDestroy(cs);
+    if (st != TC_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    hipGraphExec_t ex = nullptr;
+    if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return TC_E_HIP;
+    }
+    p->graph[k] = g;
+    p->exec[k] = ex;
+    return TC_OK;
+}
+
+static int plan_set_args(tc_plan *p, int32_t G, const int64_t *d_vtx_off,
+                         const int64_t *d_adj_off, const int32_t *d_row_ptr,
+                         const int32_t *d_col, int64_t n_total, int64_t adj_total,
+                         hipStream_t s, uint64_t *d_totals, uint64_t *d_per_vertex,
+                         int32_t *d_status) {
+    if (G <= 0 || !d_vtx_off || !d_adj_off || !d_row_ptr || !d_totals) return TC_E_ARG;
+    if ((uint32_t)G > p->gcap || n_total < 0 || (uint64_t)n_total > p->ncap || adj_total < 0 ||
+        (uint64_t)adj_total > p->acap)
+        return TC_E_TOO_LARGE;
+    if (adj_total > 0 && !d_col) return TC_E_ARG;
+    BatchArgs a;
+    a.vtx_off = d_vtx_off;
+    a.adj_off = d_adj_off;
+    a.row_ptr = d_row_ptr;
+    a.col = d_col;
+    a.totals = (unsigned long long *)d_totals;
+    a.per_vertex = (unsigned long long *)d_per_vertex;
+    a.status = d_status;
+    a.G = (uint32_t)G;
+    a.N = (uint32_t)n_total;
+    a.kitem = p->kitem;
+    a.A = (uint32_t)adj_total;
+    hipLaunchKernelGGL(k_b_set_args, dim3(1), dim3(64), 0, s,
+                       (BatchArgs *)((char *)p->ws + p->L.args), a);
+    return hipGetLastError() == hipSuccess ? TC_OK : TC_E_HIP;
+}
+
+extern "C" {
+
+size_t tc_batched_workspace_size(int32_t g_cap, int64_t n_cap, int64_t adj_cap) {
+    if (g_cap <= 0 || n_cap < 0 || adj_cap < 0 || n_cap >= (1ll << 31) ||
+        adj_cap >= (1ll << 32))
+        return 0;
+    return batch_layout((uint32_t)g_cap, (uint32_t)n_cap, (uint64_t)adj_cap).total;
+}
+
+int tc_batched_plan_create(int32_t g_cap, int64_t n_cap, int64_t adj_cap, uint32_t flags,
+                           const char *tuning_json, void *d_ws, size_t ws_bytes,
+                           tc_plan **out) {
+    if (!out) return TC_E_ARG;
+    *out = nullptr;
+    if (g_cap <= 0 || n_cap < 0 || adj_cap < 0 || flags != 0) return TC_E_ARG;
+    if (n_cap >= (1ll << 31) || adj_cap >= (1ll << 32)) return TC_E_TOO_LARGE;
+    const BatchLayout L = batch_layout((uint32_t)g_cap, (uint32_t)n_cap, (uint64_t)adj_cap);
+    if (!d_ws || ((uintptr_t)d_ws & 255) || ws_bytes < L.total) return TC_E_WORKSPACE;
+    tc_plan *p = (tc_plan *)calloc(1, sizeof(tc_plan));
+    if (!p) return TC_E_ARG;
+    p->gcap = (uint32_t)g_cap;
+    p->ncap = (uint32_t)n_cap;
+    p->acap = (uint64_t)adj_cap;
+    p->kitem = parse_tuning(tuning_json, "\"items_k\"", 256);
+    if (p->kitem < kMinItemEdges) p->kitem = kMinItemEdges;
+    p->wgs_per_cu = parse_tuning(tuning_json, "\"wgs_per_cu\"", 2);
+    if (p->wgs_per_cu > 2) p->wgs_per_cu = 2;  // LDS holds two workgroups per CU
+    p->ws = d_ws;
+    p->ws_bytes = ws_bytes;
+    p->L = L;
+    *out = p;
+    return TC_OK;
+}
+
+int tc_batched_plan_run(tc_plan *p, int32_t G, const int64_t *d_vtx_off,
+                        const int64_t *d_adj_off, const int32_t *d_row_ptr, const int32_t *d_col,
+                        int64_t n_total, int64_t adj_total, void *stream, uint64_t *d_totals,
+                        uint64_t *d_per_vertex, int32_t *d_status) {
+    if (!p) return TC_E_ARG;
+    const bool pv = d_per_vertex != nullptr;
+    int st = batch_capture(p, pv);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    st = plan_set_args(p, G, d_vtx_off, d_adj_off, d_row_ptr, d_col, n_total, adj_total, s,
+                       d_totals, d_per_vertex, d_status);
+    if (st) return st;
+    if (hipGraphLaunch(p->exec[pv ? 1 : 0], s) != hipSuccess) return TC_E_HIP;
+    return TC_OK;
+}
+
+void tc_batched_plan_destroy(tc_plan *p) {
+    if (!p) return;
+    for (int k = 0; k < 2; ++k) {
+        if (p->exec[k]) (void)hipGraphExecDestroy(p->exec[k]);
+        if (p->graph[k]) (void)hipGraphDestroy(p->graph[k]);
+    }
+    free(p);
+}
+
+int tc_count_batched(int32_t G, const int64_t *d_vtx_off, const int64_t *d_adj_off,
+                     const int32_t *d_row_ptr, const int32_t *d_col, int64_t n_total,
+                     int64_t adj_total, void *d_ws, size_t ws_bytes, void *stream,
+                     uint64_t *d_totals, uint64_t *d_per_vertex, int32_t *d_status) {
+    tc_plan *p = nullptr;
+    int st = tc_batched_plan_create(G, n_total, adj_total, 0, nullptr, d_ws, ws_bytes, &p);
+    if (st) return st;
+    st = plan_set_args(p, G, d_vtx_off, d_adj_off, d_row_ptr, d_col, n_total, adj_total,
+                       (hipStream_t)stream, d_totals, d_per_vertex, d_status);
+    if (st == TC_OK) st = batch_enqueue(p, d_per_vertex != nullptr, (hipStream_t)stream);
+    tc_batched_plan_destroy(p);
+    return st;
+}
+
+}  // extern "C"

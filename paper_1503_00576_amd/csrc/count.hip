@@ -24,7 +24,7 @@
 
 namespace tc {
 
-constexpr uint32_t kPiece = 16;
+constexpr uint32_t kPiece = 32;
 constexpr int kThreads = 512;
 constexpr int kWaves = kThreads / kWave;
 constexpr uint32_t kLdsWords = 16384;                 // 64 KiB per workgroup
@@ -81,14 +81,33 @@ struct WaveScratch {
     uint32_t off[kWave], beg[kWave], first[kWave], end[kWave], cnt[kWave], u[kWave];
 };
 
-// The calling wave processes in-edges [eb, min(eb + 64, e1)) of the current item and returns
-// this lane's hits.  PV: per-vertex accumulation -- LDS counters `tcnt` indexed by the probe's
-// position when `tcnt` is non-null, global atomics on `tpv` otherwise.
-template <bool PV, class Probe>
-__device__ __forceinline__ uint32_t run_batch(uint32_t eb, uint32_t e1,
-                                              const uint32_t *__restrict__ cbeg,
-                                              const uint32_t *__restrict__ cend,
-                                              const uint32_t *__restrict__ cu,
+// Segment sources: segment e is a range [b, en) of `col` streamed through the staged list,
+// and `owner` is the vertex credited with the segment's hits in per-vertex counts.
+struct InEdgeSegs {  // middle-vertex kernel: suffix of N+(u) after v, owner u
+    const uint32_t *cbeg, *cend, *cu;
+    __device__ __forceinline__ void get(uint32_t e, uint32_t &b, uint32_t &en) const {
+        b = cbeg[e];
+        en = cend[e];
+    }
+    __device__ __forceinline__ uint32_t owner(uint32_t e) const { return cu[e]; }
+};
+
+struct OutEdgeSegs {  // u-centric kernel: the whole list N+(v) of out-neighbour v, owner v
+    const uint32_t *row_ptr, *col;
+    __device__ __forceinline__ void get(uint32_t e, uint32_t &b, uint32_t &en) const {
+        const uint32_t v = col[e];
+        b = row_ptr[v];
+        en = row_ptr[v + 1];
+    }
+    __device__ __forceinline__ uint32_t owner(uint32_t e) const { return col[e]; }
+};
+
+// The calling wave streams segments [eb, min(eb + 64, e1)) of the current item through the
+// probe and returns this lane's hits.  PV: per-vertex accumulation -- LDS counters `tcnt`
+// indexed by the probe's position when `tcnt` is non-null, global atomics on `tpv` otherwise;
+// every segment's hits go to its owner.
+template <bool PV, class Probe, class Segs>
+__device__ __forceinline__ uint32_t run_batch(uint32_t eb, uint32_t e1, const Segs &segs,
                                               const uint32_t *__restrict__ col, const Probe &probe,
                                               WaveScratch &ws, uint32_t *tcnt,
                                               unsigned long long *__restrict__ tpv) {
@@ -96,14 +115,11 @@ __device__ __forceinline__ uint32_t run_batch(uint32_t eb, uint32_t e1,
     const uint32_t e = eb + lane;
     const bool valid = e < e1;
     uint32_t b = 0, en = 0;
-    if (valid) {
-        b = cbeg[e];
-        en = cend[e];
-    }
+    if (valid) segs.get(e, b, en);
     // pieces are 16-element windows starting at 4-element (16-byte) boundaries, so each lane
     // reads its piece with four aligned 16-byte loads; elements outside [b, en) are masked
     const uint32_t a0 = b & ~3u;
-    const uint32_t p = valid ? (en - a0 + kPiece - 1) / kPiece : 0u;
+    const uint32_t p = (valid && en > b) ? (en - a0 + kPiece - 1) / kPiece : 0u;
     const uint32_t incl = wave_incl_scan(p);
     const uint32_t Q = wave_bcast(incl, kWave - 1);
     ws.off[lane] = incl - p;
@@ -112,7 +128,7 @@ __device__ __forceinline__ uint32_t run_batch(uint32_t eb, uint32_t e1,
     ws.end[lane] = en;
     if (PV) {
         ws.cnt[lane] = 0;
-        ws.u[lane] = valid ? cu[e] : 0u;
+        ws.u[lane] = valid ? segs.owner(e) : 0u;
     }
     wave_lds_sync();
     uint32_t hits_total = 0;
@@ -147,7 +163,8 @@ __device__ __forceinline__ uint32_t run_batch(uint32_t eb, uint32_t e1,
                 for (uint32_t i = 0; i < kPiece; ++i) packed |= probe.bit(wv[i]) << i;
                 const uint32_t lo_i = first > start ? first - start : 0u;
                 const uint32_t hi_i = min(stop - start, kPiece);
-                const uint32_t mask = ((1u << hi_i) - 1u) & ~((1u << lo_i) - 1u);
+                const uint32_t hmask = hi_i >= 32u ? ~0u : ((1u << hi_i) - 1u);
+                const uint32_t mask = hmask & ~((1u << lo_i) - 1u);
                 hits = __popc(packed & mask);
             } else {
 #pragma unroll
@@ -217,6 +234,7 @@ __global__ __launch_bounds__(kThreads) void k_count(
     if (*status) return;
     const uint32_t t = threadIdx.x, w = t / kWave, lane = lane_id();
     WaveScratch &ws = s_ws[w];
+    const InEdgeSegs segs{cbeg, cend, cu};
     for (uint32_t i = t; i < kLdsWords; i += kThreads) s_mem[i] = 0;
     uint64_t acc = 0;
 
@@ -250,16 +268,16 @@ __global__ __launch_bounds__(kThreads) void k_count(
         if (mode == 0) {
             const BitmapProbe probe{s_mem, lo, span};
             for (uint32_t eb = first; eb < it.e1; eb += step)
-                cnt += run_batch<PV>(eb, it.e1, cbeg, cend, cu, col, probe, ws, nullptr, tpv);
+                cnt += run_batch<PV>(eb, it.e1, segs, col, probe, ws, nullptr, tpv);
         } else if (mode == 1) {
             const ListProbe probe{s_mem, it.d};
             uint32_t *tc = PV ? s_mem + kBlockListPV : nullptr;
             for (uint32_t eb = first; eb < it.e1; eb += step)
-                cnt += run_batch<PV>(eb, it.e1, cbeg, cend, cu, col, probe, ws, tc, tpv);
+                cnt += run_batch<PV>(eb, it.e1, segs, col, probe, ws, tc, tpv);
         } else {
             const ListProbe probe{col + it.r0, it.d};
             for (uint32_t eb = first; eb < it.e1; eb += step)
-                cnt += run_batch<PV>(eb, it.e1, cbeg, cend, cu, col, probe, ws, nullptr, tpv);
+                cnt += run_batch<PV>(eb, it.e1, segs, col, probe, ws, nullptr, tpv);
         }
         if (PV) {
             uint64_t wave_hits = wave_sum_u64(cnt);
@@ -306,7 +324,7 @@ __global__ __launch_bounds__(kThreads) void k_count(
             wave_lds_sync();
             const BitmapProbe probe{mem, lo, span};
             for (uint32_t eb = it.e0; eb < it.e1; eb += kWave)
-                cnt += run_batch<false>(eb, it.e1, cbeg, cend, cu, col, probe, ws, nullptr, tpv);
+                cnt += run_batch<false>(eb, it.e1, segs, col, probe, ws, nullptr, tpv);
             for (uint32_t i = lane; i < it.d; i += kWave) mem[(col[it.r0 + i] - lo) >> 5] = 0;
             wave_lds_sync();
         } else {
@@ -315,7 +333,7 @@ __global__ __launch_bounds__(kThreads) void k_count(
             wave_lds_sync();
             const ListProbe probe{list, it.d};
             for (uint32_t eb = it.e0; eb < it.e1; eb += kWave)
-                cnt += run_batch<true>(eb, it.e1, cbeg, cend, cu, col, probe, ws, tc, tpv);
+                cnt += run_batch<true>(eb, it.e1, segs, col, probe, ws, tc, tpv);
             for (uint32_t i = lane; i < it.d; i += kWave) {
                 uint32_t c = tc[i];
                 if (c) {
@@ -331,6 +349,111 @@ __global__ __launch_bounds__(kThreads) void k_count(
     }
     acc = wave_sum_u64(acc);
     if (lane == 0 && acc) atomicAdd(total, (unsigned long long)acc);
+}
+
+// ------------------------------------------------------------------ batched kernel
+
+// Batched counting over a disjoint union of small graphs in id space (their oriented lists
+// keep the input's id order, no relabelling): item = (u, chunk of up to kitem out-neighbours
+// of u).  N+(u) is staged in the wave's LDS slice (bitmap over its id span, or a sorted list)
+// and the whole list N+(v) of every out-neighbour v streams through it: every common element
+// w closes the triangle (u, v, w) once.  Hits go to the graph of u; per-vertex counts credit
+// u (per item), v (per segment) and w (LDS counters by list position).
+template <bool PV>
+__global__ __launch_bounds__(kThreads) void k_count_u(
+    const uint32_t *__restrict__ frp, const uint32_t *__restrict__ fcol,
+    const uint32_t *__restrict__ gid, const uint32_t *__restrict__ item_u,
+    const uint32_t *__restrict__ item_off, const uint32_t *__restrict__ n_items_ptr,
+    const uint32_t *__restrict__ kitem_ptr, uint32_t *__restrict__ queue,
+    unsigned long long *const *__restrict__ totals_pp,
+    unsigned long long *const *__restrict__ tpv_pp) {
+    __shared__ uint32_t s_mem[kLdsWords];
+    __shared__ WaveScratch s_ws[kWaves];
+    const uint32_t t = threadIdx.x, w = t / kWave, lane = lane_id();
+    WaveScratch &ws = s_ws[w];
+    uint32_t *mem = s_mem + w * kSliceWords;
+    for (uint32_t i = t; i < kLdsWords; i += kThreads) s_mem[i] = 0;
+    __syncthreads();
+    const uint32_t n_items = *n_items_ptr, kitem = *kitem_ptr;
+    unsigned long long *totals = *totals_pp;
+    unsigned long long *tpv = PV ? *tpv_pp : nullptr;
+    const OutEdgeSegs segs{frp, fcol};
+    for (;;) {
+        uint32_t q = 0;
+        if (lane == 0) q = atomicAdd(queue, 1u);
+        q = wave_bcast(q, 0);
+        if (q >= n_items) break;
+        q = n_items - 1 - q;
+        const uint32_t u = item_u[q];
+        const uint32_t r0 = frp[u], d = frp[u + 1] - r0;
+        const uint32_t e0 = r0 + (q - item_off[u]) * kitem;
+        const uint32_t e1 = min(e0 + kitem, r0 + d);
+        uint32_t lo = ~0u, hi = 0;  // the id span of N+(u) (rows of invalid graphs may be
+        for (uint32_t i = lane; i < d; i += kWave) {  // unsorted, so take min and max)
+            const uint32_t x = fcol[r0 + i];
+            lo = min(lo, x);
+            hi = max(hi, x);
+        }
+        for (int o = kWave / 2; o >= 1; o >>= 1) {
+            lo = min(lo, (uint32_t)__shfl_xor((int)lo, o, kWave));
+            hi = max(hi, (uint32_t)__shfl_xor((int)hi, o, kWave));
+        }
+        const uint32_t span = hi - lo;
+        // 0 = bitmap in the slice, 1 = sorted list in the slice, 2 = sorted list in memory
+        const int mode = (!PV && span < kWaveBits) ? 0
+                         : (d <= (PV ? kWaveListPV : kSliceWords)) ? 1 : 2;
+        uint32_t cnt = 0;
+        if (mode == 0) {
+            for (uint32_t i = lane; i < d; i += kWave) {
+                const uint32_t o = fcol[r0 + i] - lo;
+                atomicOr(&mem[o >> 5], 1u << (o & 31u));
+            }
+            wave_lds_sync();
+            const BitmapProbe probe{mem, lo, span};
+            for (uint32_t eb = e0; eb < e1; eb += kWave)
+                cnt += run_batch<PV>(eb, e1, segs, fcol, probe, ws, nullptr, tpv);
+            for (uint32_t i = lane; i < d; i += kWave) mem[(fcol[r0 + i] - lo) >> 5] = 0;
+        } else if (mode == 1) {
+            uint32_t *list = mem, *tc = PV ? mem + kWaveListPV : nullptr;
+            for (uint32_t i = lane; i < d; i += kWave) list[i] = fcol[r0 + i];
+            wave_lds_sync();
+            const ListProbe probe{list, d};
+            for (uint32_t eb = e0; eb < e1; eb += kWave)
+                cnt += run_batch<PV>(eb, e1, segs, fcol, probe, ws, tc, tpv);
+            for (uint32_t i = lane; i < d; i += kWave) {
+                list[i] = 0;
+                if (PV && tc[i]) {
+                    atomicAdd(&tpv[fcol[r0 + i]], (unsigned long long)tc[i]);
+                    tc[i] = 0;
+                }
+            }
+        } else {
+            const ListProbe probe{fcol + r0, d};
+            for (uint32_t eb = e0; eb < e1; eb += kWave)
+                cnt += run_batch<PV>(eb, e1, segs, fcol, probe, ws, nullptr, tpv);
+        }
+        wave_lds_sync();
+        const uint64_t item_hits = wave_sum_u64(cnt);
+        if (lane == 0 && item_hits) {
+            atomicAdd(&totals[gid[u]], (unsigned long long)item_hits);
+            if (PV) atomicAdd(&tpv[u], (unsigned long long)item_hits);
+        }
+    }
+}
+
+hipError_t launch_count_u(const uint32_t *frp, const uint32_t *fcol, const uint32_t *gid,
+                          const uint32_t *item_u, const uint32_t *item_off,
+                          const uint32_t *n_items, const uint32_t *kitem, uint32_t *queue,
+                          unsigned long long *const *totals_pp,
+                          unsigned long long *const *tpv_pp, bool per_vertex, uint32_t grid,
+                          hipStream_t s) {
+    if (per_vertex)
+        hipLaunchKernelGGL(k_count_u<true>, dim3(grid), dim3(kThreads), 0, s, frp, fcol, gid,
+                           item_u, item_off, n_items, kitem, queue, totals_pp, tpv_pp);
+    else
+        hipLaunchKernelGGL(k_count_u<false>, dim3(grid), dim3(kThreads), 0, s, frp, fcol, gid,
+                           item_u, item_off, n_items, kitem, queue, totals_pp, tpv_pp);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ host side

@@ -93,5 +93,11 @@ uint32_t count_wave_span(bool per_vertex);
 uint32_t count_wave_list(bool per_vertex);
 uint32_t count_item_edges_wave();
 uint32_t count_item_edges_block();
+hipError_t launch_count_u(const uint32_t *frp, const uint32_t *fcol, const uint32_t *gid,
+                          const uint32_t *item_u, const uint32_t *item_off,
+                          const uint32_t *n_items, const uint32_t *kitem, uint32_t *queue,
+                          unsigned long long *const *totals_pp,
+                          unsigned long long *const *tpv_pp, bool per_vertex, uint32_t grid,
+                          hipStream_t s);
 
 }  // namespace tc

@@ -288,6 +288,43 @@ def symmetric_csr(edges: torch.Tensor, n: int):
     return row_ptr.to(torch.int32), col
 
 
+def pack_symmetric(graphs, device="cpu") -> dict:
+    """Concatenate graphs [(edges int32 [m, 2], n), ...] into the batched input format: per
+    graph a symmetric CSR (both directions, rows ascending, local ids), plus vertex and
+    adjacency offsets.  Returns dict(vtx_off int64 [G+1], adj_off int64 [G+1],
+    row_ptr int32 [N+G], col int32 [2 sum m], G, n_total, adj_total)."""
+    G = len(graphs)
+    ns = torch.tensor([int(n) for _, n in graphs], dtype=torch.int64)
+    vtx_off = torch.zeros(G + 1, dtype=torch.int64)
+    vtx_off[1:] = torch.cumsum(ns, 0)
+    N = int(vtx_off[-1])
+    parts = [e.to("cpu", torch.int64) + vtx_off[g] for g, (e, _) in enumerate(graphs)]
+    E = torch.cat(parts).to(device) if parts else torch.zeros((0, 2), dtype=torch.int64,
+                                                              device=device)
+    src = torch.cat([E[:, 0], E[:, 1]])
+    dst = torch.cat([E[:, 1], E[:, 0]])
+    order = torch.argsort(src * max(N, 1) + dst)
+    src, dst = src[order], dst[order]
+    grow = torch.zeros(N + 1, dtype=torch.int64, device=device)
+    if src.numel():
+        grow[1:] = torch.cumsum(torch.bincount(src, minlength=N), 0)
+    vo = vtx_off.to(device)
+    adj_off = grow[vo]
+    gidx = torch.repeat_interleave(torch.arange(G, device=device), (ns + 1).to(device))
+    pos = torch.arange(N + G, device=device) - gidx
+    row_ptr = (grow[pos] - adj_off[gidx]).to(torch.int32)
+    g_of = torch.searchsorted(vo[1:], src, right=True)
+    col = (dst - vo[g_of]).to(torch.int32)
+    return {"vtx_off": vo, "adj_off": adj_off, "row_ptr": row_ptr, "col": col, "G": G,
+            "n_total": N, "adj_total": int(col.numel())}
+
+
+def batch_graphs(spec: BatchSpec, device="cpu"):
+    """The graphs of a BatchSpec as [(edges, n), ...]."""
+    return [(batch_graph(kind, n, k, seed, spec.beta, device), n)
+            for kind, n, k, seed in batch_graph_params(spec)]
+
+
 def poisson_trace(rate: float, duration: float, seed: int):
     """Arrival times of a Poisson process (exponential gaps) plus one uniform draw per
     arrival for the caller's request mix; returns (times float64[k], u float64[k])."""

@@ -1,0 +1,158 @@
+"""GPU parity of the batched entry points (tc_count_batched, tc_batched_plan_*) against the
+CPU oracle, graph by graph, bit-exact: per-graph totals and per-vertex counts, invalid graphs
+reported per graph without disturbing the others, and a captured plan replayed several times
+with other GPU work in between."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1503_00576_amd import api, synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def as_batch(packed) -> api.Batch:
+    return api.Batch(packed["vtx_off"].to(DEV), packed["adj_off"].to(DEV),
+                     packed["row_ptr"].to(DEV), packed["col"].to(DEV), packed["G"],
+                     packed["n_total"], packed["adj_total"])
+
+
+def mixed_graphs(seed=0, count=48):
+    rng = np.random.default_rng(seed)
+    gs = []
+    for i in range(count):
+        kind = i % 4
+        n = int(rng.integers(2, 3000))
+        if kind == 0:
+            gs.append((synth.barabasi_albert(n, int(rng.integers(1, 12)), seed * 1000 + i), n))
+        elif kind == 1:
+            gs.append((synth.watts_strogatz(max(n, 3), int(rng.integers(1, 10)), 0.1, i), max(n, 3)))
+        elif kind == 2:
+            gs.append((synth.erdos_renyi(min(n, 400), float(rng.choice([0.02, 0.1, 0.5])), i), min(n, 400)))
+        else:
+            s = int(rng.integers(4, 11))
+            gs.append(synth.rmat_graph(s, 16, seed=i))
+    gs.append((torch.zeros((0, 2), dtype=torch.int32), 7))      # isolated vertices only
+    gs.append((torch.zeros((0, 2), dtype=torch.int32), 1))
+    k = 40
+    gs.append((torch.tensor([(i, j) for i in range(k) for j in range(i + 1, k)], dtype=torch.int32), k))
+    return gs
+
+
+def oracle_per_graph(gs):
+    out = []
+    for e, n in gs:
+        t, pv = oracle.count(e, n, per_vertex=True)
+        out.append((t, pv))
+    return out
+
+
+def check(res: api.BatchResult, gs, want, per_vertex=True):
+    tot = res.totals.cpu().numpy().astype(np.uint64)
+    assert not res.status.cpu().numpy().any()
+    for g, (t, _) in enumerate(want):
+        assert tot[g] == t, g
+    if per_vertex:
+        pv = res.per_vertex.cpu().numpy().astype(np.uint64)
+        assert np.array_equal(pv, np.concatenate([p for _, p in want]))
+
+
+def test_batched_one_shot():
+    gs = mixed_graphs(1)
+    want = oracle_per_graph(gs)
+    b = as_batch(synth.pack_symmetric(gs))
+    check(api.count_batched(b, per_vertex=True), gs, want)
+    check(api.count_batched(b, per_vertex=False), gs, want, per_vertex=False)
+
+
+def test_batched_union_additive():
+    gs = mixed_graphs(2, 24)
+    b = as_batch(synth.pack_symmetric(gs))
+    res = api.count_batched(b)
+    off, parts = 0, []
+    for e, n in gs:
+        parts.append(e.numpy().astype(np.int64) + off)
+        off += n
+    assert int(res.totals.sum()) == oracle.count(np.concatenate(parts), off)
+
+
+@pytest.mark.parametrize("tuning", [None, {"items_k": 16, "wgs_per_cu": 1}, {"items_k": 1024}])
+def test_plan_replays(tuning):
+    """A captured plan replayed several times, with eager GPU work in between, every replay
+    equal to the one-shot result; then a smaller batch through the same plan."""
+    gs = mixed_graphs(3)
+    want = oracle_per_graph(gs)
+    b = as_batch(synth.pack_symmetric(gs))
+    plan = api.BatchPlan(b.G + 5, b.n_total + 100, b.adj_total + 1000, tuning, device=DEV)
+    for rep in range(4):
+        res = plan.run_async(b, per_vertex=(rep % 2 == 1))
+        x = torch.randn(1 << 20, device=DEV)          # unrelated eager work
+        (x * 2).sum().item()
+        torch.cuda.synchronize()
+        check(res, gs, want, per_vertex=(rep % 2 == 1))
+    small = gs[5:17]
+    b2 = as_batch(synth.pack_symmetric(small))
+    res2 = plan.run_async(b2, per_vertex=True)
+    torch.cuda.synchronize()
+    check(res2, small, oracle_per_graph(small))
+    res3 = plan.run_async(b, per_vertex=False)
+    torch.cuda.synchronize()
+    check(res3, gs, want, per_vertex=False)
+    plan.close()
+
+
+def test_batched_bad_graphs_reported_per_graph():
+    gs = mixed_graphs(4, 8)
+    packed = synth.pack_symmetric(gs)
+    col = packed["col"].clone()
+    vo, ao = packed["vtx_off"], packed["adj_off"]
+    rp = packed["row_ptr"]
+    # graph 1: swap two entries of a row with at least two entries -> unsorted
+    g = 1
+    v0 = int(vo[g]); n = int(vo[g + 1] - v0)
+    base = int(ao[g])
+    for x in range(n):
+        r0, r1 = int(rp[v0 + g + x]), int(rp[v0 + g + x + 1])
+        if r1 - r0 >= 2:
+            a, c = base + r0, base + r0 + 1
+            col[a], col[c] = col[c].clone(), col[a].clone()
+            break
+    # graph 3: an id out of range
+    g3 = 3
+    col[int(ao[g3])] = int(vo[g3 + 1] - vo[g3]) + 5
+    packed["col"] = col
+    b = as_batch(packed)
+    res = api.BatchPlan(b.G, b.n_total, b.adj_total, device=DEV).run_async(b)
+    torch.cuda.synchronize()
+    st = res.status.cpu().numpy()
+    assert st[1] == api.E_UNSORTED and st[3] == api.E_RANGE
+    want = oracle_per_graph(gs)
+    tot = res.totals.cpu().numpy().astype(np.uint64)
+    for gg in range(len(gs)):
+        if gg not in (1, 3):
+            assert st[gg] == 0 and tot[gg] == want[gg][0]
+
+
+def test_batched_asymmetric():
+    gs = [(torch.tensor([(0, 1), (1, 2), (0, 2)], dtype=torch.int32), 3)]
+    packed = synth.pack_symmetric(gs)
+    # drop the mirror (2 -> 0): rows 0:[1,2] 1:[0,2] 2:[1] ; rebuild by hand
+    packed["row_ptr"] = torch.tensor([0, 2, 4, 5], dtype=torch.int32)
+    packed["col"] = torch.tensor([1, 2, 0, 2, 1], dtype=torch.int32)
+    packed["adj_off"] = torch.tensor([0, 5], dtype=torch.int64)
+    packed["adj_total"] = 5
+    b = as_batch(packed)
+    with pytest.raises(api.TCError) as ei:
+        api.count_batched(b)
+    assert ei.value.name == "asymmetric"
+
+
+def test_batch_spec_sample():
+    """A slice of the 4096-graph benchmark batch (Barabasi-Albert / Watts-Strogatz mix)."""
+    spec = synth.BatchSpec(graphs=32, seed=7)
+    gs = synth.batch_graphs(spec)
+    want = oracle_per_graph(gs)
+    b = as_batch(synth.pack_symmetric(gs, device=DEV))
+    check(api.count_batched(b, per_vertex=True), gs, want)
