@@ -145,6 +145,81 @@ def batched_section(dev, steps: int):
             "tuning_ms": [[t, round(ms, 3)] for t, ms in timings]}
 
 
+def serve_section(dev, duration: float, rate: float, seed: int = 0):
+    """Poisson arrivals (rate per second, `duration` seconds); 90% R-MAT scale 10-14, 9% scale
+    17-19, 1% scale 21, edgefactor 16.  Each request carries its edge array in pinned host
+    memory and is processed in full (copy to the device, preprocessing, count).  Graphs are
+    drawn from a seeded pool per scale to bound generation time."""
+    import threading
+    import torch
+    from paper_1503_00576_amd import serve, synth
+    times, u = synth.poisson_trace(rate, duration, seed)
+    times, u = times.tolist(), u.tolist()
+    pool_size = {s: 16 for s in range(10, 15)}
+    pool_size.update({17: 6, 18: 4, 19: 3, 21: 2})
+    pool = {}
+    t0 = time.perf_counter()
+    for sc, k in pool_size.items():
+        pool[sc] = []
+        for i in range(k):
+            e, n = synth.rmat_graph(sc, 16, seed=1000 * sc + i, device=dev)
+            pool[sc].append((e.cpu().pin_memory(), n))
+    torch.cuda.synchronize()
+    log(f"serve: {len(times)} arrivals, pool generated in {time.perf_counter() - t0:.1f} s")
+
+    def pick(i, x):
+        if x < 0.9:
+            sc = 10 + min(4, int(x / 0.9 * 5))
+        elif x < 0.99:
+            sc = 17 + min(2, int((x - 0.9) / 0.09 * 3))
+        else:
+            sc = 21
+        return pool[sc][i % len(pool[sc])]
+
+    reqs = [pick(i, x) for i, x in enumerate(u)]
+    futs = [None] * len(reqs)
+    srv = serve.Server(dev, budget_bytes=32 << 30, streams=4, small_edges=1 << 18,
+                       batch_graphs=512, max_inflight=8)
+    start = time.perf_counter() + 0.5
+
+    def producer():
+        for i, ((e, n), t) in enumerate(zip(reqs, times)):
+            delay = start + t - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            futs[i] = srv.submit(serve.Request(e, n, arrival=start + t))
+
+    th = threading.Thread(target=producer)
+    th.start()
+    last_log = time.perf_counter()
+    while th.is_alive():
+        th.join(timeout=5.0)
+        if time.perf_counter() - last_log > 10:
+            log(f"serve: {srv.stats['completed']} completed")
+            last_log = time.perf_counter()
+    lat, ok, failed = [], 0, 0
+    for f in futs:
+        try:
+            _, l = f.result(timeout=300)
+            lat.append(l)
+            ok += 1
+        except Exception:
+            failed += 1
+    makespan = time.perf_counter() - start
+    stats = dict(srv.stats)
+    srv.close()
+    edges = sum(int(e.shape[0]) for e, _ in reqs)
+    return {"requests": len(reqs), "completed": ok, "failed": failed,
+            "duration_s": duration, "rate_per_s": rate, "makespan_s": round(makespan, 3),
+            "graphs_per_s": ok / makespan, "edges_per_s": edges / makespan,
+            "p50_ms": round(1e3 * serve.percentile(lat, 50), 3),
+            "p99_ms": round(1e3 * serve.percentile(lat, 99), 3),
+            "max_ms": round(1e3 * max(lat), 3) if lat else None,
+            "batches": stats.get("batches", 0),
+            "batched_requests": stats.get("batched_requests", 0),
+            "single_requests": stats.get("single", 0), "rejected": stats.get("rejected", 0)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -155,6 +230,10 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched measurement (4096 small graphs)")
     ap.add_argument("--batched-only", action="store_true")
+    ap.add_argument("--serve", action="store_true",
+                    help="only run the serving trace (Poisson arrivals of mixed R-MAT graphs)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run three plain 1 GiB device-to-device copies (counter scale)")
     args = ap.parse_args()
@@ -176,6 +255,10 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         log("copied 3 x 1 GiB")
+        return
+    if args.serve:
+        print(json.dumps({"serve": serve_section(dev, args.serve_seconds, args.serve_rate)}),
+              flush=True)
         return
     if args.batched_only:
         print(json.dumps({"batched": batched_section(dev, args.steps)}), flush=True)

@@ -296,11 +296,12 @@ class BatchPlan:
             pass
 
 
-def count_batched(b: Batch, per_vertex: bool = False) -> BatchResult:
-    """One-shot batched count (no graph capture); returns checked results."""
+def count_batched_async(b: Batch, per_vertex: bool = False,
+                        workspace: torch.Tensor | None = None) -> BatchResult:
+    """Enqueue a one-shot batched count (no graph capture) on the current stream."""
     dev = b.vtx_off.device
-    ws = torch.empty(batched_workspace_size(b.G, b.n_total, b.adj_total), dtype=torch.uint8,
-                     device=dev)
+    ws = workspace if workspace is not None else torch.empty(
+        batched_workspace_size(b.G, b.n_total, b.adj_total), dtype=torch.uint8, device=dev)
     out = BatchResult(torch.empty(b.G, dtype=torch.int64, device=dev),
                       torch.empty(b.G, dtype=torch.int32, device=dev),
                       torch.empty(b.n_total, dtype=torch.int64, device=dev) if per_vertex else None)
@@ -308,4 +309,10 @@ def count_batched(b: Batch, per_vertex: bool = False) -> BatchResult:
         b.G, _ptr(b.vtx_off), _ptr(b.adj_off), _ptr(b.row_ptr), _ptr(b.col), b.n_total,
         b.adj_total, _ptr(ws), ws.numel(), _stream(dev), _ptr(out.totals),
         _ptr(out.per_vertex) if per_vertex else None, _ptr(out.status)), "tc_count_batched")
-    return out.check()
+    out.workspace = ws  # keep alive until the work has run
+    return out
+
+
+def count_batched(b: Batch, per_vertex: bool = False) -> BatchResult:
+    """One-shot batched count (no graph capture); returns checked results."""
+    return count_batched_async(b, per_vertex).check()

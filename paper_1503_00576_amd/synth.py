@@ -292,31 +292,37 @@ def pack_symmetric(graphs, device="cpu") -> dict:
     """Concatenate graphs [(edges int32 [m, 2], n), ...] into the batched input format: per
     graph a symmetric CSR (both directions, rows ascending, local ids), plus vertex and
     adjacency offsets.  Returns dict(vtx_off int64 [G+1], adj_off int64 [G+1],
-    row_ptr int32 [N+G], col int32 [2 sum m], G, n_total, adj_total)."""
+    row_ptr int32 [N+G], col int32 [2 sum m], G, n_total, adj_total).  Runs on `device`
+    without host synchronisation (sizes come from the host-side graph list)."""
     G = len(graphs)
-    ns = torch.tensor([int(n) for _, n in graphs], dtype=torch.int64)
-    vtx_off = torch.zeros(G + 1, dtype=torch.int64)
-    vtx_off[1:] = torch.cumsum(ns, 0)
-    N = int(vtx_off[-1])
-    parts = [e.to("cpu", torch.int64) + vtx_off[g] for g, (e, _) in enumerate(graphs)]
-    E = torch.cat(parts).to(device) if parts else torch.zeros((0, 2), dtype=torch.int64,
-                                                              device=device)
+    ns = [int(n) for _, n in graphs]
+    ms = [int(e.shape[0]) for e, _ in graphs]
+    offs = [0]
+    for n in ns:
+        offs.append(offs[-1] + n)
+    N, M = offs[-1], sum(ms)
+    vo = torch.tensor(offs, dtype=torch.int64, device=device)
+    if M:
+        E = torch.cat([e.to(device=device, dtype=torch.int64) + offs[g]
+                       for g, (e, _) in enumerate(graphs) if e.shape[0]])
+    else:
+        E = torch.zeros((0, 2), dtype=torch.int64, device=device)
     src = torch.cat([E[:, 0], E[:, 1]])
     dst = torch.cat([E[:, 1], E[:, 0]])
     order = torch.argsort(src * max(N, 1) + dst)
     src, dst = src[order], dst[order]
     grow = torch.zeros(N + 1, dtype=torch.int64, device=device)
-    if src.numel():
-        grow[1:] = torch.cumsum(torch.bincount(src, minlength=N), 0)
-    vo = vtx_off.to(device)
+    grow.index_add_(0, src + 1, torch.ones_like(src))
+    grow = torch.cumsum(grow, 0)
     adj_off = grow[vo]
-    gidx = torch.repeat_interleave(torch.arange(G, device=device), (ns + 1).to(device))
+    reps = torch.tensor([n + 1 for n in ns], dtype=torch.int64, device=device)
+    gidx = torch.repeat_interleave(torch.arange(G, device=device), reps, output_size=N + G)
     pos = torch.arange(N + G, device=device) - gidx
     row_ptr = (grow[pos] - adj_off[gidx]).to(torch.int32)
     g_of = torch.searchsorted(vo[1:], src, right=True)
     col = (dst - vo[g_of]).to(torch.int32)
     return {"vtx_off": vo, "adj_off": adj_off, "row_ptr": row_ptr, "col": col, "G": G,
-            "n_total": N, "adj_total": int(col.numel())}
+            "n_total": N, "adj_total": 2 * M}
 
 
 def batch_graphs(spec: BatchSpec, device="cpu"):

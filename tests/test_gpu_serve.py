@@ -1,0 +1,69 @@
+"""Serving loop on the GPU: every result equals the oracle's and is the same alone and in a
+mix of concurrent requests (exact integers, tolerance 0), with memory-budget queueing,
+batching of small graphs, overlapping large graphs and resident-CSR reuse."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1503_00576_amd import api, serve, synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def make_requests():
+    reqs = []
+    rng = np.random.default_rng(3)
+    for i in range(60):
+        s = int(rng.choice([8, 9, 10, 11, 12]))
+        e, n = synth.rmat_graph(s, 16, seed=100 + i)
+        reqs.append((e.pin_memory(), n, None))
+    for i in range(6):
+        e, n = synth.rmat_graph(15, 16, seed=200 + i)
+        reqs.append((e.pin_memory(), n, ("big", i % 3)))   # keys repeat: resident reuse
+    e, n = synth.er_1000()
+    reqs.append((e.pin_memory(), n, None))
+    return reqs
+
+
+def test_alone_equals_mix_equals_oracle():
+    reqs = make_requests()
+    want = [oracle.count(e, n) for e, n, _ in reqs]
+    # alone: one request at a time
+    alone = []
+    with serve.Server(DEV, max_inflight=1) as srv:
+        for e, n, key in reqs:
+            alone.append(srv.submit(serve.Request(e, n, key)).result(timeout=120)[0])
+    assert alone == want
+    # mix: everything at once, budget small enough that requests queue, small ones batched,
+    # large ones overlapping on several streams, repeated keys served from resident CSRs
+    budget = 2 * api.workspace_size(1 << 15, 600000) + (64 << 20)
+    with serve.Server(DEV, budget_bytes=budget, streams=4, small_edges=1 << 16,
+                      batch_graphs=16, max_inflight=6, resident_bytes=budget // 2) as srv:
+        futs = [srv.submit(serve.Request(e, n, key)) for e, n, key in reqs]
+        mix = [f.result(timeout=300)[0] for f in futs]
+        stats = dict(srv.stats)
+    assert mix == want
+    assert stats.get("batches", 0) >= 2
+    assert stats.get("completed", 0) == len(reqs)
+
+
+def test_request_larger_than_budget_is_rejected():
+    e, n = synth.rmat_graph(12, 16, seed=1)
+    with serve.Server(DEV, budget_bytes=4096, small_edges=0) as srv:
+        f = srv.submit(serve.Request(e, n))
+        with pytest.raises(MemoryError):
+            f.result(timeout=60)
+        assert srv.stats["rejected"] == 1
+
+
+def test_bad_request_reports_error():
+    bad = torch.tensor([(0, 1), (1, 1)], dtype=torch.int32)
+    good, n = synth.er_1000()
+    with serve.Server(DEV, small_edges=1 << 20) as srv:
+        fb = srv.submit(serve.Request(bad, 4))
+        fg = srv.submit(serve.Request(good, n))
+        with pytest.raises(api.TCError):
+            fb.result(timeout=60)
+        assert fg.result(timeout=60)[0] == oracle.count(good, n)
