@@ -147,7 +147,7 @@ static bool make_layout(int64_t n, int64_t m, uint32_t flags, Layout &L) {
     L.re = take(n1 * 4);
     L.rowlen = take(n1 * 4);
     L.row_ptr = take(n1 * 4);
-    L.col = take((size_t)L.mf * 4 + 64);  // padded: aligned 16-element reads may pass the end
+    L.col = take((size_t)L.mf * 4 + count_col_pad_bytes());  // piece reads may pass the end
     L.src = take((size_t)L.mf * 4);
     L.vrange = take((size_t)n * 8);
     L.eu = take((size_t)L.mf * 8);

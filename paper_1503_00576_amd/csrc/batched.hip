@@ -230,7 +230,7 @@ static BatchLayout batch_layout(uint32_t gcap, uint32_t ncap, uint64_t acap) {
     L.deg = take((size_t)ncap * 4);
     L.fdeg = take(n1 * 4);
     L.frp = take(n1 * 4);
-    L.fcol = take((size_t)acap * 4 + 64);
+    L.fcol = take((size_t)acap * 4 + count_col_pad_bytes());
     L.items = take(n1 * 4);
     L.ioff = take(n1 * 4);
     L.item_u = take(((size_t)acap / kMinItemEdges + n1 + 1) * 4);

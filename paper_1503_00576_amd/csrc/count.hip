@@ -116,8 +116,8 @@ __device__ __forceinline__ uint32_t run_batch(uint32_t eb, uint32_t e1, const Se
     const bool valid = e < e1;
     uint32_t b = 0, en = 0;
     if (valid) segs.get(e, b, en);
-    // pieces are 16-element windows starting at 4-element (16-byte) boundaries, so each lane
-    // reads its piece with four aligned 16-byte loads; elements outside [b, en) are masked
+    // pieces are kPiece-element windows starting at 4-element (16-byte) boundaries, so a lane
+    // reads its piece with kPiece / 4 aligned 16-byte loads; elements outside [b, en) are masked
     const uint32_t a0 = b & ~3u;
     const uint32_t p = (valid && en > b) ? (en - a0 + kPiece - 1) / kPiece : 0u;
     const uint32_t incl = wave_incl_scan(p);
@@ -462,6 +462,7 @@ uint32_t count_wave_span(bool per_vertex) { return per_vertex ? 0u : kWaveBits; 
 uint32_t count_wave_list(bool per_vertex) { return per_vertex ? kWaveListPV : 0u; }
 uint32_t count_item_edges_wave() { return kItemEdgesWave; }
 uint32_t count_item_edges_block() { return kItemEdgesBlock; }
+uint32_t count_col_pad_bytes() { return kPiece * 4; }
 
 hipError_t launch_count(const CountArgs &x, bool per_vertex, hipStream_t s) {
     const dim3 grid(device_cu_count() * 2), block(kThreads);

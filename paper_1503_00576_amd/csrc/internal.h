@@ -93,6 +93,9 @@ uint32_t count_wave_span(bool per_vertex);
 uint32_t count_wave_list(bool per_vertex);
 uint32_t count_item_edges_wave();
 uint32_t count_item_edges_block();
+// bytes of padding `col` needs after its last element: a lane's aligned piece reads may run
+// up to one piece past the end of a list
+uint32_t count_col_pad_bytes();
 hipError_t launch_count_u(const uint32_t *frp, const uint32_t *fcol, const uint32_t *gid,
                           const uint32_t *item_u, const uint32_t *item_off,
                           const uint32_t *n_items, const uint32_t *kitem, uint32_t *queue,
