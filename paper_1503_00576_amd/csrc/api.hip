@@ -26,14 +26,18 @@ __global__ void k_csr(const uint64_t *, uint32_t, uint32_t, int, uint32_t *, uin
                       uint32_t *, uint32_t *, int32_t *);
 __global__ void k_rowlen(const uint32_t *, const uint32_t *, uint32_t, uint32_t *);
 __global__ void k_vrange(const uint32_t *, const uint32_t *, uint32_t, uint64_t *);
+__global__ void k_panel_range(const uint64_t *, uint32_t, uint32_t, uint32_t, uint32_t,
+                              uint64_t *);
 __global__ void k_csc_keys(const uint32_t *, const uint32_t *, const uint32_t *, const uint64_t *,
-                           uint32_t, uint32_t, uint32_t, uint64_t *, uint2 *, const int32_t *);
+                           const uint64_t *, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t,
+                           uint64_t *, uint2 *, const int32_t *);
 __global__ void k_csc_bounds(const uint64_t *, uint32_t, uint64_t, uint32_t *, uint32_t *,
                              const int32_t *);
-__global__ void k_csc_final(const uint64_t *, uint32_t, uint64_t, const uint2 *, uint32_t *,
-                            uint32_t *, uint32_t *, const int32_t *);
+__global__ void k_csc_final(const uint64_t *, uint32_t, uint64_t, const uint2 *,
+                            const uint32_t *, uint32_t, uint32_t, uint32_t, uint32_t *,
+                            uint32_t *, uint32_t *, uint32_t *, const int32_t *);
 __global__ void k_items(const uint32_t *, const uint32_t *, const uint32_t *, uint32_t, uint32_t,
-                        uint32_t, uint32_t, uint32_t, uint32_t, uint32_t *, uint32_t *,
+                        uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t *, uint32_t *,
                         uint32_t *, uint32_t *, const int32_t *);
 __global__ void k_item_fill(const uint32_t *, const uint32_t *, uint64_t, uint32_t *,
                             const int32_t *);
@@ -63,12 +67,13 @@ int device_cu_count() {
 
 struct Layout {
     size_t ctl, part_hist, part_offs, part_scan, deg, perm, rank, keys_a, keys_b, sort_scratch,
-        rs, re, rowlen, row_ptr, col, src, vrange, eu, lrs, lre, cnt, cptr, cbeg, cend, cu,
-        items[4], off[4], item_v[4], scan_scratch, tpv, total_bytes;
+        rs, re, rowlen, row_ptr, col, src, vrange, prange, eu, lrs, lre, cnt, cptr, cbeg, cend,
+        cu, cmask, items[4], off[4], item_v[4], scan_scratch, tpv, total_bytes;
     uint32_t part_tiles;  // 0: degrees by atomics (inputs too large for the partition)
     int part_shift;
     uint32_t n, m, mf, kcap, id_bits, nblk;
-    uint64_t lists;  // in-edge lists: nblk * (n + 1)
+    uint32_t p0, panels;  // panel region: ranks [p0, n) in panels of count_panel() ranks
+    uint64_t lists;       // in-edge lists: nblk * (n + 1)
 };
 
 // item spaces: [0] wave / [1] workgroup items for total counts, [2] / [3] for per-vertex counts
@@ -90,6 +95,17 @@ static uint32_t row_blocks_for(uint32_t n, uint32_t mf) {
     if (k > 8) k = 8;
     while (k > 1 && k * ((uint64_t)n + 1) >= (1ull << 32)) --k;
     return (uint32_t)k;
+}
+
+// Middle-vertex panels over the top TC_PANEL_RANKS ranks (default and maximum: what the
+// counting kernel's LDS table holds; 0 switches panels off).
+static uint32_t panel_ranks_for(uint32_t n) {
+    uint64_t x = count_panel_ranks();
+    if (const char *env = getenv("TC_PANEL_RANKS")) {  // tuning / testing override
+        unsigned long long v = strtoull(env, nullptr, 10);
+        if (v < x) x = v;
+    }
+    return (uint32_t)(x < n ? x : n);
 }
 
 static int id_bits_for(uint32_t n) {
@@ -114,6 +130,8 @@ static bool make_layout(int64_t n, int64_t m, uint32_t flags, Layout &L) {
     L.kcap = L.m > L.n ? L.m : L.n;
     L.id_bits = (uint32_t)id_bits_for(L.n);
     L.nblk = row_blocks_for(L.n, L.mf);
+    L.p0 = L.n - panel_ranks_for(L.n);
+    L.panels = ceil_div(L.n - L.p0, count_panel());
     const uint64_t n1 = (uint64_t)n + 1;
     L.lists = (uint64_t)L.nblk * n1;
     const uint64_t l1 = L.lists + 1;
@@ -150,6 +168,7 @@ static bool make_layout(int64_t n, int64_t m, uint32_t flags, Layout &L) {
     L.col = take((size_t)L.mf * 4 + count_col_pad_bytes());  // piece reads may pass the end
     L.src = take((size_t)L.mf * 4);
     L.vrange = take((size_t)n * 8);
+    L.prange = take((size_t)L.panels * 8);
     L.eu = take((size_t)L.mf * 8);
     L.lrs = take(l1 * 4);
     L.lre = take(l1 * 4);
@@ -158,6 +177,7 @@ static bool make_layout(int64_t n, int64_t m, uint32_t flags, Layout &L) {
     L.cbeg = take((size_t)L.mf * 4);
     L.cend = take((size_t)L.mf * 4);
     L.cu = take((size_t)L.mf * 4);
+    L.cmask = take((size_t)L.mf * 4);
     for (int k = 0; k < 4; ++k) {
         const uint32_t per = (k & 1) ? count_item_edges_block() : count_item_edges_wave();
         L.items[k] = take(l1 * 4);
@@ -303,8 +323,14 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
     uint64_t *ck = (sorted == ka) ? kb : ka;  // the sorted edge keys are no longer needed
     uint64_t *ck2 = (sorted == ka) ? ka : kb;
     uint2 *eu = at<uint2>(ws, L.eu);
+    uint64_t *pr = at<uint64_t>(ws, L.prange);
+    if (L.panels) {
+        hipLaunchKernelGGL(k_panel_range, dim3(grid_for(L.panels, 256)), dim3(256), 0, s, vr, n,
+                           L.p0, count_panel(), L.panels, pr);
+        TC_LAUNCH_CHECK();
+    }
     hipLaunchKernelGGL(k_csc_keys, dim3(grid_for(mf, 256)), dim3(256), 0, s, col, src, row_ptr, vr,
-                       mf, n, L.nblk, ck, eu, status);
+                       pr, mf, n, L.nblk, L.p0, count_panel(), ck, eu, status);
     TC_LAUNCH_CHECK();
     uint64_t *cks = ck;
     TC_HIP(sort_u64(ck, ck2, mf, 32, 32 + id_bits_for64(l1), sort_scr, status, s, &cks));
@@ -318,11 +344,12 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
     TC_LAUNCH_CHECK();
     TC_HIP(scan_exclusive_u32(cnt, cptr, l1, scan_scr, s));
     hipLaunchKernelGGL(k_csc_final, dim3(grid_for(mf, 256)), dim3(256), 0, s, cks, mf, L.lists,
-                       eu, at<uint32_t>(ws, L.cbeg), at<uint32_t>(ws, L.cend),
-                       at<uint32_t>(ws, L.cu), status);
+                       eu, col, n, L.p0, count_panel(), at<uint32_t>(ws, L.cbeg),
+                       at<uint32_t>(ws, L.cend), at<uint32_t>(ws, L.cu),
+                       at<uint32_t>(ws, L.cmask), status);
     TC_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_items, dim3(grid_for(l1, 256)), dim3(256), 0, s, row_ptr, col, cnt, n,
-                       L.nblk, count_wave_span(false), count_wave_list(true),
+                       L.nblk, L.p0, count_wave_span(false), count_wave_list(true),
                        count_item_edges_wave(), count_item_edges_block(), items[0], items[1],
                        items[2], items[3], status);
     TC_LAUNCH_CHECK();
@@ -361,6 +388,7 @@ static int run_count_prepared(void *ws, const Layout &L, hipStream_t s, uint64_t
         a.cbeg = at<uint32_t>(ws, L.cbeg);
         a.cend = at<uint32_t>(ws, L.cend);
         a.cu = at<uint32_t>(ws, L.cu);
+        a.cmask = at<uint32_t>(ws, L.cmask);
         a.item_v_a = at<uint32_t>(ws, L.item_v[a0]);
         a.item_off_a = at<uint32_t>(ws, L.off[a0]);
         a.n_items_a = a.item_off_a + L.lists;
@@ -372,6 +400,7 @@ static int run_count_prepared(void *ws, const Layout &L, hipStream_t s, uint64_t
         a.total = total;
         a.tpv = tpv;
         a.n1 = n + 1;
+        a.p0 = L.p0;
         a.status = status;
         TC_HIP(launch_count(a, pv, s));
     }

@@ -17,6 +17,15 @@
 // runs whole pieces, so one load and one lookup per element are the per-element costs,
 // whatever the spread of suffix lengths.
 //
+// Panels.  Most of the tests sit at the highest ranks (the highest degrees), where a list N+(u)
+// holds several consecutive middle vertices and its suffix would be streamed once for each.
+// The top ranks are therefore grouped into panels of kPanel consecutive middle vertices
+// P .. P + kPanel - 1: a panel's table M in LDS holds, for every rank w, the kPanel-bit mask
+// of the panel vertices whose out-list contains w, and a segment is a pair (u, panel) with
+// the mask R(u) of the panel vertices in N+(u).  Its suffix after the first of them is
+// streamed once and each element w adds popcount(M[w] & R(u)): every panel vertex v with
+// v in N+(u) and w in N+(v) closes one triangle (w > v holds because w is in N+(v)).
+//
 // Per-vertex counts (T(x) = triangles through x) use sorted lists in LDS instead of bitmaps
 // so that a hit's position indexes an LDS counter: T(w) for the third vertex is flushed once
 // per item, T(u) once per in-edge, T(v) once per item and wave.
@@ -36,6 +45,8 @@ constexpr uint32_t kBlockList = kLdsWords;            // workgroup sorted list
 constexpr uint32_t kBlockListPV = kLdsWords / 2;      // per-vertex: list + counters
 constexpr uint32_t kItemEdgesWave = 256;
 constexpr uint32_t kItemEdgesBlock = 2048;
+constexpr uint32_t kPanel = 32;                       // one bit per panel vertex in a mask
+constexpr uint32_t kPanelRanks = kLdsWords - 32;      // mask table: one word per rank
 
 // ------------------------------------------------------------------ membership probes
 
@@ -51,6 +62,19 @@ struct BitmapProbe {
         return __builtin_amdgcn_ubfe(bm[__builtin_amdgcn_ubfe(o, 5u, 27u)], o, 1u);
     }
     __device__ __forceinline__ bool operator()(uint32_t w, uint32_t &) const { return bit(w); }
+    static constexpr bool kMasked = false;
+};
+
+// Panel table M over ranks [lo, lo + span]: word w - lo holds the mask of the panel vertices
+// whose out-list contains w.  Word span + 1 is always zero, so out-of-range ids clamp onto it.
+struct PanelProbe {
+    const uint32_t *m;
+    uint32_t lo, span;
+    static constexpr bool kBranchFree = true;
+    static constexpr bool kMasked = true;
+    __device__ __forceinline__ uint32_t count(uint32_t w, uint32_t r) const {
+        return __popc(m[min(w - lo, span + 1u)] & r);
+    }
 };
 
 // lower_bound with a lane-independent trip count (d is uniform)
@@ -69,6 +93,7 @@ struct ListProbe {  // sorted list in LDS or in global memory
     const uint32_t *list;
     uint32_t d;
     static constexpr bool kBranchFree = false;
+    static constexpr bool kMasked = false;
     __device__ __forceinline__ bool operator()(uint32_t w, uint32_t &pos) const {
         pos = lower_bound_u32(list, d, w);
         return pos < d && list[pos] == w;
@@ -77,8 +102,8 @@ struct ListProbe {  // sorted list in LDS or in global memory
 
 // ------------------------------------------------------------------ per-batch streaming
 
-struct WaveScratch {
-    uint32_t off[kWave], beg[kWave], first[kWave], end[kWave], cnt[kWave], u[kWave];
+struct WaveScratch {  // tag: the segment's owner (per-vertex counts) or its panel mask
+    uint32_t off[kWave], beg[kWave], first[kWave], end[kWave], cnt[kWave], tag[kWave];
 };
 
 // Segment sources: segment e is a range [b, en) of `col` streamed through the staged list,
@@ -90,6 +115,39 @@ struct InEdgeSegs {  // middle-vertex kernel: suffix of N+(u) after v, owner u
         en = cend[e];
     }
     __device__ __forceinline__ uint32_t owner(uint32_t e) const { return cu[e]; }
+    __device__ __forceinline__ uint32_t mask(uint32_t) const { return 0u; }
+};
+
+// Panel segment (u, panel): the suffix of N+(u) after u's first panel vertex, tagged with the
+// mask R(u) of u's panel vertices.
+struct PanelSegs {
+    const uint32_t *cbeg, *cend, *cmask;
+    __device__ __forceinline__ void get(uint32_t e, uint32_t &b, uint32_t &en) const {
+        b = cbeg[e];
+        en = cend[e];
+    }
+    __device__ __forceinline__ uint32_t owner(uint32_t) const { return 0u; }
+    __device__ __forceinline__ uint32_t mask(uint32_t e) const { return cmask[e]; }
+};
+
+// Per-vertex counts over a panel, one panel vertex P + j at a time: segment (u, panel) stands
+// for the in-edge u -> P + j when bit j of R(u) is set.  u's panel vertices are consecutive in
+// N+(u) starting right before cbeg, so the suffix after P + j starts popcount(R(u) below j)
+// elements later; segments without bit j are empty.
+struct PanelVertexSegs {
+    const uint32_t *cbeg, *cend, *cu, *cmask;
+    uint32_t j;
+    __device__ __forceinline__ void get(uint32_t e, uint32_t &b, uint32_t &en) const {
+        const uint32_t r = cmask[e];
+        b = 0;
+        en = 0;
+        if ((r >> j) & 1u) {
+            b = cbeg[e] + __popc(r & ((1u << j) - 1u));
+            en = cend[e];
+        }
+    }
+    __device__ __forceinline__ uint32_t owner(uint32_t e) const { return cu[e]; }
+    __device__ __forceinline__ uint32_t mask(uint32_t) const { return 0u; }
 };
 
 struct OutEdgeSegs {  // u-centric kernel: the whole list N+(v) of out-neighbour v, owner v
@@ -100,6 +158,7 @@ struct OutEdgeSegs {  // u-centric kernel: the whole list N+(v) of out-neighbour
         en = row_ptr[v + 1];
     }
     __device__ __forceinline__ uint32_t owner(uint32_t e) const { return col[e]; }
+    __device__ __forceinline__ uint32_t mask(uint32_t) const { return 0u; }
 };
 
 // The calling wave streams segments [eb, min(eb + 64, e1)) of the current item through the
@@ -128,7 +187,9 @@ __device__ __forceinline__ uint32_t run_batch(uint32_t eb, uint32_t e1, const Se
     ws.end[lane] = en;
     if (PV) {
         ws.cnt[lane] = 0;
-        ws.u[lane] = valid ? segs.owner(e) : 0u;
+        ws.tag[lane] = valid ? segs.owner(e) : 0u;
+    } else if (Probe::kMasked) {
+        ws.tag[lane] = valid ? segs.mask(e) : 0u;
     }
     wave_lds_sync();
     uint32_t hits_total = 0;
@@ -156,7 +217,17 @@ __device__ __forceinline__ uint32_t run_batch(uint32_t eb, uint32_t e1, const Se
             uint32_t hits = 0;
             // element i of the piece belongs to the suffix iff start + i - first < stop - first
             const uint32_t rel0 = start - first, len = stop - first;
-            if constexpr (!PV && Probe::kBranchFree) {
+            if constexpr (!PV && Probe::kMasked) {
+                // hits of element i: panel vertices of the owner whose lists hold it
+                const uint32_t r = ws.tag[k];
+                const uint32_t lo_i = first > start ? first - start : 0u;
+                const uint32_t hi_i = min(stop - start, kPiece);
+#pragma unroll
+                for (uint32_t i = 0; i < kPiece; ++i) {
+                    const uint32_t c = probe.count(wv[i], r);
+                    hits += (i >= lo_i && i < hi_i) ? c : 0u;
+                }
+            } else if constexpr (!PV && Probe::kBranchFree) {
                 // the piece's valid elements are the contiguous range [lo_i, hi_i) of positions
                 uint32_t packed = 0;
 #pragma unroll
@@ -188,7 +259,7 @@ __device__ __forceinline__ uint32_t run_batch(uint32_t eb, uint32_t e1, const Se
     }
     wave_lds_sync();
     if (PV) {
-        if (ws.cnt[lane]) atomicAdd(&tpv[ws.u[lane]], (unsigned long long)ws.cnt[lane]);
+        if (ws.cnt[lane]) atomicAdd(&tpv[ws.tag[lane]], (unsigned long long)ws.cnt[lane]);
         wave_lds_sync();
     }
     return hits_total;
@@ -222,11 +293,12 @@ __global__ __launch_bounds__(kThreads) void k_count(
     const uint32_t *__restrict__ row_ptr, const uint32_t *__restrict__ col,
     const uint32_t *__restrict__ cptr, const uint32_t *__restrict__ cbeg,
     const uint32_t *__restrict__ cend, const uint32_t *__restrict__ cu,
-    const uint32_t *__restrict__ item_v_a, const uint32_t *__restrict__ item_off_a,
-    const uint32_t *__restrict__ n_items_a_ptr, const uint32_t *__restrict__ item_v_b,
-    const uint32_t *__restrict__ item_off_b, const uint32_t *__restrict__ n_items_b_ptr,
-    uint32_t *__restrict__ queue_a, uint32_t *__restrict__ queue_b,
-    unsigned long long *__restrict__ total, unsigned long long *__restrict__ tpv, uint32_t n1,
+    const uint32_t *__restrict__ cmask, const uint32_t *__restrict__ item_v_a,
+    const uint32_t *__restrict__ item_off_a, const uint32_t *__restrict__ n_items_a_ptr,
+    const uint32_t *__restrict__ item_v_b, const uint32_t *__restrict__ item_off_b,
+    const uint32_t *__restrict__ n_items_b_ptr, uint32_t *__restrict__ queue_a,
+    uint32_t *__restrict__ queue_b, unsigned long long *__restrict__ total,
+    unsigned long long *__restrict__ tpv, uint32_t n1, uint32_t p0,
     const int32_t *__restrict__ status) {
     __shared__ uint32_t s_mem[kLdsWords];
     __shared__ WaveScratch s_ws[kWaves];
@@ -249,6 +321,64 @@ __global__ __launch_bounds__(kThreads) void k_count(
         q = n_items_b - 1 - q;
         const ItemRange it =
             item_range(q, kItemEdgesBlock, n1, item_v_b, item_off_b, cptr, row_ptr);
+        const uint32_t first = it.e0 + w * kWave, step = kWaves * kWave;
+        if (it.v >= p0) {  // a panel of middle vertices P = it.v, ...
+            const uint32_t P = it.v, np = min(kPanel, n1 - 1 - P);
+            if (!PV) {
+                for (uint32_t j = w; j < np; j += kWaves)
+                    for (uint32_t i = row_ptr[P + j] + lane; i < row_ptr[P + j + 1]; i += kWave)
+                        atomicOr(&s_mem[col[i] - P], 1u << j);
+                __syncthreads();
+                const PanelProbe probe{s_mem, P, n1 - 2 - P};
+                const PanelSegs psegs{cbeg, cend, cmask};
+                uint32_t cnt = 0;
+                for (uint32_t eb = first; eb < it.e1; eb += step)
+                    cnt += run_batch<false>(eb, it.e1, psegs, col, probe, ws, nullptr, tpv);
+                acc += cnt;
+                __syncthreads();
+                for (uint32_t j = w; j < np; j += kWaves)
+                    for (uint32_t i = row_ptr[P + j] + lane; i < row_ptr[P + j + 1]; i += kWave)
+                        s_mem[col[i] - P] = 0;
+            } else {
+                for (uint32_t j = 0; j < np; ++j) {  // one panel vertex at a time
+                    const uint32_t r0 = row_ptr[P + j], d = row_ptr[P + j + 1] - r0;
+                    if (d == 0) continue;
+                    const bool in_lds = d <= kBlockListPV;
+                    if (in_lds)
+                        for (uint32_t i = t; i < d; i += kThreads) s_mem[i] = col[r0 + i];
+                    __syncthreads();
+                    const PanelVertexSegs vsegs{cbeg, cend, cu, cmask, j};
+                    uint32_t cnt = 0;
+                    if (in_lds) {
+                        const ListProbe probe{s_mem, d};
+                        for (uint32_t eb = first; eb < it.e1; eb += step)
+                            cnt += run_batch<true>(eb, it.e1, vsegs, col, probe, ws,
+                                                   s_mem + kBlockListPV, tpv);
+                    } else {
+                        const ListProbe probe{col + r0, d};
+                        for (uint32_t eb = first; eb < it.e1; eb += step)
+                            cnt += run_batch<true>(eb, it.e1, vsegs, col, probe, ws, nullptr,
+                                                   tpv);
+                    }
+                    const uint64_t wave_hits = wave_sum_u64(cnt);
+                    if (lane == 0 && wave_hits)
+                        atomicAdd(&tpv[P + j], (unsigned long long)wave_hits);
+                    acc += cnt;
+                    __syncthreads();
+                    if (in_lds) {
+                        for (uint32_t i = t; i < d; i += kThreads) {
+                            s_mem[i] = 0;
+                            const uint32_t c = s_mem[kBlockListPV + i];
+                            if (c) {
+                                atomicAdd(&tpv[col[r0 + i]], (unsigned long long)c);
+                                s_mem[kBlockListPV + i] = 0;
+                            }
+                        }
+                    }
+                }
+            }
+            continue;
+        }
         const uint32_t lo = col[it.r0];
         const uint32_t span = col[it.r0 + it.d - 1] - lo;
         // 0 = bitmap, 1 = LDS list, 2 = global list
@@ -264,7 +394,6 @@ __global__ __launch_bounds__(kThreads) void k_count(
         }
         __syncthreads();
         uint32_t cnt = 0;
-        const uint32_t first = it.e0 + w * kWave, step = kWaves * kWave;
         if (mode == 0) {
             const BitmapProbe probe{s_mem, lo, span};
             for (uint32_t eb = first; eb < it.e1; eb += step)
@@ -463,19 +592,21 @@ uint32_t count_wave_list(bool per_vertex) { return per_vertex ? kWaveListPV : 0u
 uint32_t count_item_edges_wave() { return kItemEdgesWave; }
 uint32_t count_item_edges_block() { return kItemEdgesBlock; }
 uint32_t count_col_pad_bytes() { return kPiece * 4; }
+uint32_t count_panel() { return kPanel; }
+uint32_t count_panel_ranks() { return kPanelRanks; }
 
 hipError_t launch_count(const CountArgs &x, bool per_vertex, hipStream_t s) {
     const dim3 grid(device_cu_count() * 2), block(kThreads);
     if (per_vertex)
         hipLaunchKernelGGL(k_count<true>, grid, block, 0, s, x.row_ptr, x.col, x.cptr, x.cbeg,
-                           x.cend, x.cu, x.item_v_a, x.item_off_a, x.n_items_a, x.item_v_b,
-                           x.item_off_b, x.n_items_b, x.queue_a, x.queue_b, x.total, x.tpv,
-                           x.n1, x.status);
+                           x.cend, x.cu, x.cmask, x.item_v_a, x.item_off_a, x.n_items_a,
+                           x.item_v_b, x.item_off_b, x.n_items_b, x.queue_a, x.queue_b, x.total,
+                           x.tpv, x.n1, x.p0, x.status);
     else
         hipLaunchKernelGGL(k_count<false>, grid, block, 0, s, x.row_ptr, x.col, x.cptr, x.cbeg,
-                           x.cend, x.cu, x.item_v_a, x.item_off_a, x.n_items_a, x.item_v_b,
-                           x.item_off_b, x.n_items_b, x.queue_a, x.queue_b, x.total, x.tpv,
-                           x.n1, x.status);
+                           x.cend, x.cu, x.cmask, x.item_v_a, x.item_off_a, x.n_items_a,
+                           x.item_v_b, x.item_off_b, x.n_items_b, x.queue_a, x.queue_b, x.total,
+                           x.tpv, x.n1, x.p0, x.status);
     return hipGetLastError();
 }
 

@@ -80,12 +80,13 @@ int device_cu_count();
 
 // counting kernels (count.hip)
 struct CountArgs {
-    const uint32_t *row_ptr, *col, *cptr, *cbeg, *cend, *cu;
+    const uint32_t *row_ptr, *col, *cptr, *cbeg, *cend, *cu, *cmask;
     const uint32_t *item_v_a, *item_off_a, *n_items_a;
     const uint32_t *item_v_b, *item_off_b, *n_items_b;
     uint32_t *queue_a, *queue_b;
     unsigned long long *total, *tpv;
     uint32_t n1;
+    uint32_t p0;  // first rank of the panel region (n: no panels)
     const int32_t *status;
 };
 hipError_t launch_count(const CountArgs &a, bool per_vertex, hipStream_t s);
@@ -96,6 +97,10 @@ uint32_t count_item_edges_block();
 // bytes of padding `col` needs after its last element: a lane's aligned piece reads may run
 // up to one piece past the end of a list
 uint32_t count_col_pad_bytes();
+// middle-vertex panels: consecutive ranks per panel, and the largest rank region the
+// counting kernel can handle as panels (its mask table must fit the workgroup's LDS)
+uint32_t count_panel();
+uint32_t count_panel_ranks();
 hipError_t launch_count_u(const uint32_t *frp, const uint32_t *fcol, const uint32_t *gid,
                           const uint32_t *item_u, const uint32_t *item_off,
                           const uint32_t *n_items, const uint32_t *kitem, uint32_t *queue,

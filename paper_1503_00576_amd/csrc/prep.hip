@@ -12,7 +12,9 @@
 //                (steps 4/8: row_ptr[x] = first key whose source is >= x), duplicate check
 //   k_csc_*      for every vertex v the list of in-edges u -> v that can close a triangle
 //                through v: the suffix of N+(u) after v, stored as a [begin, end) range;
-//                built by a radix sort of (list << 32 | e) keys, so no atomics are needed
+//                built by a radix sort of (list << 32 | e) keys, so no atomics are needed;
+//                from rank p0 on, one list per panel of consecutive middle vertices, with the
+//                mask of u's panel vertices per entry
 //   k_items_*    work items of the counting kernels (see count.hip)
 //
 // Working with ranks instead of ids makes the order test a plain comparison, groups the
@@ -262,15 +264,38 @@ __global__ void k_vrange(const uint32_t *__restrict__ row_ptr, const uint32_t *_
     vr[v] = r1 > r0 ? ((uint64_t)col[r0] << 32) | col[r1 - 1] : 0xFFFFFFFF00000000ull;
 }
 
+// Rank span of the union of the out-lists of every panel (ranks p0 + i * kp .. + kp - 1), in
+// the format of k_vrange.
+__global__ void k_panel_range(const uint64_t *__restrict__ vr, uint32_t n, uint32_t p0,
+                              uint32_t kp, uint32_t panels, uint64_t *__restrict__ pr) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= panels) return;
+    const uint32_t P = p0 + i * kp, pe = min(P + kp, n);
+    uint32_t lo = 0xFFFFFFFFu, hi = 0;
+    for (uint32_t v = P; v < pe; ++v) {
+        const uint64_t r = vr[v];
+        const uint32_t l = (uint32_t)(r >> 32), h = (uint32_t)r;
+        if (l <= h) {
+            lo = min(lo, l);
+            hi = max(hi, h);
+        }
+    }
+    pr[i] = ((uint64_t)lo << 32) | hi;
+}
+
 // In-edge u -> v (CSR position e) can close a triangle u < v < w only through an element w of
 // N+(u) after v that also lies in N+(v): the suffix must be non-empty and its rank range must
 // overlap that of N+(v).  Such in-edges are keyed by their list c = row block * (n + 1) + v
 // (row blocks: contiguous CSR ranges, see the host code), the others by `lists` (sorted last);
 // the low 32 bits hold e, so a stable sort on the list bits groups every list in CSR order.
+// From rank p0 on, middle vertices form panels of kp consecutive ranks with one list per
+// panel, keyed by its first rank P: only the first in-edge of each run of u's out-neighbours
+// inside the panel is kept (it stands for the whole run), tested against the panel's span.
 __global__ void k_csc_keys(const uint32_t *__restrict__ col, const uint32_t *__restrict__ src,
                            const uint32_t *__restrict__ row_ptr,
-                           const uint64_t *__restrict__ vr, uint32_t mf, uint32_t n,
-                           uint32_t nblk, uint64_t *__restrict__ keys, uint2 *__restrict__ eu,
+                           const uint64_t *__restrict__ vr, const uint64_t *__restrict__ pr,
+                           uint32_t mf, uint32_t n, uint32_t nblk, uint32_t p0, uint32_t kp,
+                           uint64_t *__restrict__ keys, uint2 *__restrict__ eu,
                            const int32_t *__restrict__ status) {
     if (*status) return;
     uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -279,10 +304,17 @@ __global__ void k_csc_keys(const uint32_t *__restrict__ col, const uint32_t *__r
     const uint32_t end_u = row_ptr[u + 1];
     uint64_t c = (uint64_t)nblk * (n + 1);
     if (e + 1 < end_u) {
-        const uint64_t r = vr[v];
+        uint32_t list = v;
+        uint64_t r = vr[v];
+        if (v >= p0) {
+            const uint32_t i = (v - p0) / kp;
+            list = p0 + i * kp;
+            const bool run_start = e == row_ptr[u] || col[e - 1] < list;
+            r = run_start ? pr[i] : 0xFFFFFFFF00000000ull;
+        }
         const uint32_t lo = (uint32_t)(r >> 32), hi = (uint32_t)r;
         if (lo <= hi && col[e + 1] <= hi && col[end_u - 1] >= lo)
-            c = (uint64_t)(((uint64_t)e * nblk) / mf) * (n + 1) + v;
+            c = (uint64_t)(((uint64_t)e * nblk) / mf) * (n + 1) + list;
     }
     keys[e] = (c << 32) | e;
     eu[e] = make_uint2(end_u, u);
@@ -301,21 +333,36 @@ __global__ void k_csc_bounds(const uint64_t *__restrict__ keys, uint32_t mf, uin
     if (j == mf - 1 || (keys[j + 1] >> 32) != c) re[c] = j + 1;
 }
 
-// the lists themselves: in-edge u -> v at CSR position e contributes the suffix [e + 1, end_u)
+// the lists themselves: in-edge u -> v at CSR position e contributes the suffix [e + 1, end_u);
+// for a panel list (first rank P >= p0) also the mask of u's run of panel vertices, which
+// starts at e
 __global__ void k_csc_final(const uint64_t *__restrict__ keys, uint32_t mf, uint64_t lists,
-                            const uint2 *__restrict__ eu, uint32_t *__restrict__ cbeg,
+                            const uint2 *__restrict__ eu, const uint32_t *__restrict__ col,
+                            uint32_t n, uint32_t p0, uint32_t kp, uint32_t *__restrict__ cbeg,
                             uint32_t *__restrict__ cend, uint32_t *__restrict__ cu,
-                            const int32_t *__restrict__ status) {
+                            uint32_t *__restrict__ cmask, const int32_t *__restrict__ status) {
     if (*status) return;
     uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= mf) return;
     const uint64_t k = keys[j];
-    if ((k >> 32) >= lists) return;
+    const uint64_t c = k >> 32;
+    if (c >= lists) return;
     const uint32_t e = (uint32_t)k;
     const uint2 x = eu[e];
     cbeg[j] = e + 1;
     cend[j] = x.x;
     cu[j] = x.y;
+    const uint32_t P = (uint32_t)(c % ((uint64_t)n + 1));
+    uint32_t r = 1u;
+    if (P >= p0) {
+        r = 0;
+        for (uint32_t i = e; i < x.x; ++i) {
+            const uint32_t w = col[i];
+            if (w >= P + kp) break;
+            r |= 1u << (w - P);
+        }
+    }
+    cmask[j] = r;
 }
 
 // Work items of the counting kernel.  A vertex's in-edges are cut into chunks; the chunks go
@@ -323,8 +370,9 @@ __global__ void k_csc_final(const uint64_t *__restrict__ keys, uint32_t mf, uint
 // its rank span, or for per-vertex counts as a list with counters), otherwise to the
 // per-workgroup queue.  Both classifications are prepared, so a prepared graph can be
 // counted either way.
+// Panel lists (first rank >= p0) always go to the per-workgroup queue.
 __global__ void k_items(const uint32_t *__restrict__ row_ptr, const uint32_t *__restrict__ col,
-                        const uint32_t *__restrict__ cnt, uint32_t n, uint32_t nblk,
+                        const uint32_t *__restrict__ cnt, uint32_t n, uint32_t nblk, uint32_t p0,
                         uint32_t wave_span, uint32_t wave_list_pv, uint32_t ka, uint32_t kb,
                         uint32_t *__restrict__ ia, uint32_t *__restrict__ ib,
                         uint32_t *__restrict__ ia_pv, uint32_t *__restrict__ ib_pv,
@@ -335,7 +383,9 @@ __global__ void k_items(const uint32_t *__restrict__ row_ptr, const uint32_t *__
     if (c > total) return;
     uint32_t a = 0, b = 0, apv = 0, bpv = 0;
     const uint32_t v = c < total ? (uint32_t)(c % (n + 1)) : n;
-    if (v < n && cnt[c] > 0) {
+    if (v < n && cnt[c] > 0 && v >= p0) {
+        b = bpv = (cnt[c] + kb - 1) / kb;
+    } else if (v < n && cnt[c] > 0) {
         const uint32_t r0 = row_ptr[v], d = row_ptr[v + 1] - r0;
         const uint32_t span = col[r0 + d - 1] - col[r0];
         const uint32_t na = (cnt[c] + ka - 1) / ka, nb = (cnt[c] + kb - 1) / kb;

@@ -135,6 +135,19 @@ def test_row_blocks_forced(monkeypatch):
     check_vs_oracle(e.cpu().numpy(), n)
 
 
+@pytest.mark.parametrize("ranks", ["0", "1", "31", "33", "517", "4000"])
+def test_panel_thresholds(monkeypatch, ranks):
+    """The top-ranks panel region of every size: off (per-vertex lists only), one partial
+    panel, one panel plus a ragged one, and many panels over graphs of every family."""
+    monkeypatch.setenv("TC_PANEL_RANKS", ranks)
+    for e, n in [synth.er_1000(), (synth.barabasi_albert(2000, 8, 2), 2000),
+                 (synth.watts_strogatz(1500, 6, 0.1, 3), 1500), synth.rmat_graph(11, 8, seed=4),
+                 synth.rmat_graph(14, 16, seed=6)]:
+        check_vs_oracle(e.numpy(), n)
+    for k in [3, 40, 130]:
+        assert check_vs_oracle(complete(k), k) == math.comb(k, 3)
+
+
 def test_prepared_recount():
     """A resident preprocessed graph counted repeatedly, with and without per-vertex counts."""
     e, n = synth.rmat_graph(13, 16, seed=12, device=DEV)
