@@ -198,12 +198,28 @@ __global__ void k_b_item_fill(const uint32_t *__restrict__ items,
     for (uint32_t j = 0; j < k; ++j) item_u[o + j] = x;
 }
 
-// per-graph status out (the caller's array, when given); kitem for the counting kernel
-__global__ void k_b_finish(const BatchArgs *__restrict__ args,
-                           const int32_t *__restrict__ gstat) {
+// per-graph checks that need the whole graph, and the per-graph status out (the caller's
+// array, when given).  Offsets: the graph's vertex and adjacency ranges must lie inside the
+// batch (k_b_setup checked them only for graphs that have vertices).  Symmetry: k_b_ffill
+// found a mirror for every forward entry, so the entries are symmetric exactly when the
+// backward entries are no more than the forward ones, i.e. entries == 2 * forward entries
+// (mirroring maps forward entries one-to-one into the backward ones).
+__global__ void k_b_finish(const BatchArgs *__restrict__ args, const uint32_t *__restrict__ frp,
+                           int32_t *__restrict__ gstat) {
     const BatchArgs a = *args;
     const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (a.status && g < a.G) a.status[g] = gstat[g];
+    if (g >= a.G) return;
+    int32_t st = gstat[g];
+    if (st == 0) {
+        const int64_t v0 = a.vtx_off[g], v1 = a.vtx_off[g + 1];
+        const int64_t a0 = a.adj_off[g], a1 = a.adj_off[g + 1];
+        if (v0 < 0 || v1 < v0 || v1 > (int64_t)a.N || a0 < 0 || a1 < a0 || a1 > (int64_t)a.A)
+            st = TC_E_ARG;
+        else if (2 * (int64_t)(frp[v1] - frp[v0]) != a1 - a0)
+            st = TC_E_ASYMMETRIC;
+        gstat[g] = st;
+    }
+    if (a.status) a.status[g] = st;
 }
 
 // ------------------------------------------------------------------ workspace + plan
@@ -295,7 +311,7 @@ static int batch_enqueue(tc_plan *p, bool pv, hipStream_t s) {
                        &dev_args->per_vertex, pv, device_cu_count() * p->wgs_per_cu,
                        s) != hipSuccess)
         return TC_E_HIP;
-    hipLaunchKernelGGL(k_b_finish, grid(p->gcap), dim3(256), 0, s, args, gstat);
+    hipLaunchKernelGGL(k_b_finish, grid(p->gcap), dim3(256), 0, s, args, frp, gstat);
     return hipGetLastError() == hipSuccess ? TC_OK : TC_E_HIP;
 }
 
