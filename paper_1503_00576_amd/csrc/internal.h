@@ -64,6 +64,16 @@ __device__ __forceinline__ void set_status(int32_t *st, int32_t code) {
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 inline uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
+// Workgroups are dispatched round-robin over the chip's 8 XCDs, each with its own L2.  Tiled
+// kernels whose neighbouring tiles share cache lines (per-tile tables stored tile-minor) map
+// workgroup b of nb to tile xcd_tile(b, nb), so that every XCD works through one contiguous
+// range of tiles.  A bijection of [0, nb).
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nb) {
+    const uint32_t x = b % kXcds, i = b / kXcds, q = nb / kXcds, r = nb % kXcds;
+    return x * q + (x < r ? x : r) + i;
+}
+
 // exclusive scan of uint32 (in may equal out); scratch: scan_scratch_words(N) words
 size_t scan_scratch_words(uint64_t N);
 hipError_t scan_exclusive_u32(const uint32_t *in, uint32_t *out, uint64_t N, uint32_t *scratch,

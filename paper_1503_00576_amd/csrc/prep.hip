@@ -45,7 +45,8 @@ __global__ __launch_bounds__(kPartThreads) void k_part_hist(
     const uint32_t t = threadIdx.x;
     h[t] = 0;
     __syncthreads();
-    const uint64_t base = (uint64_t)blockIdx.x * kPartTile;
+    const uint32_t tile = xcd_tile(blockIdx.x, tiles);
+    const uint64_t base = (uint64_t)tile * kPartTile;
     int2 ed[kPartEdges];
 #pragma unroll
     for (int r = 0; r < kPartEdges; ++r) {
@@ -66,7 +67,7 @@ __global__ __launch_bounds__(kPartThreads) void k_part_hist(
         if (!both) atomicAdd(&h[(uint32_t)e.y >> sh], 1u);
     }
     __syncthreads();
-    hist[(uint64_t)t * tiles + blockIdx.x] = h[t];
+    hist[(uint64_t)t * tiles + tile] = h[t];
 }
 
 // endpoints of one tile placed bucket by bucket in LDS, then written as contiguous runs
@@ -77,7 +78,8 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scatter(
     __shared__ uint32_t s_stage[2 * kPartTile];
     __shared__ uint32_t s_fill[256], s_glob[256], s_wsum[kPartThreads / kWave];
     const uint32_t t = threadIdx.x, w = t / kWave;
-    const uint32_t c = hist[(uint64_t)t * tiles + blockIdx.x];
+    const uint32_t tile = xcd_tile(blockIdx.x, tiles);
+    const uint32_t c = hist[(uint64_t)t * tiles + tile];
     const uint32_t incl = wave_incl_scan(c);
     if (lane_id() == kWave - 1) s_wsum[w] = incl;
     __syncthreads();
@@ -85,9 +87,9 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scatter(
     for (uint32_t k = 0; k < w; ++k) before += s_wsum[k];
     const uint32_t loc = before + incl - c;
     s_fill[t] = loc;
-    s_glob[t] = offs[(uint64_t)t * tiles + blockIdx.x] - loc;
+    s_glob[t] = offs[(uint64_t)t * tiles + tile] - loc;
     __syncthreads();
-    const uint64_t base = (uint64_t)blockIdx.x * kPartTile;
+    const uint64_t base = (uint64_t)tile * kPartTile;
     int2 ed[kPartEdges];
 #pragma unroll
     for (int r = 0; r < kPartEdges; ++r) {

@@ -144,7 +144,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t *__r
     for (int k = 0; k < kSortWaves; ++k) h[k][t] = 0;
     __syncthreads();
     const uint32_t mask = (1u << nbits) - 1u;
-    const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+    const uint32_t tile = xcd_tile(blockIdx.x, tiles);
+    const uint64_t base = (uint64_t)tile * kSortTile;
     uint32_t dg[kSortItems];  // all loads in flight before any ranking
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
@@ -161,7 +162,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t *__r
     __syncthreads();
     uint32_t sum = 0;
     for (int k = 0; k < kSortWaves; ++k) sum += h[k][t];
-    hist[(uint64_t)t * tiles + blockIdx.x] = sum;
+    hist[(uint64_t)t * tiles + tile] = sum;
 }
 
 // Stable scatter of one 4096-key tile: the keys are first ranked and placed in LDS in digit
@@ -179,8 +180,9 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     __shared__ uint32_t s_wcnt[kSortWaves][256];
     __shared__ uint32_t s_wsum[kSortWaves];
     const uint32_t t = threadIdx.x, w = t / kWave;
+    const uint32_t tile = xcd_tile(blockIdx.x, tiles);
     // tile-local exclusive offsets of the digits
-    const uint32_t c = hist[(uint64_t)t * tiles + blockIdx.x];
+    const uint32_t c = hist[(uint64_t)t * tiles + tile];
     const uint32_t incl = wave_incl_scan(c);
     if (lane_id() == kWave - 1) s_wsum[w] = incl;
     for (int k = 0; k < kSortWaves; ++k) s_wcnt[k][t] = 0;
@@ -189,10 +191,10 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     for (uint32_t k = 0; k < w; ++k) before += s_wsum[k];
     const uint32_t loc = before + incl - c;
     s_loc[t] = loc;
-    s_glob[t] = offs[(uint64_t)t * tiles + blockIdx.x] - loc;
+    s_glob[t] = offs[(uint64_t)t * tiles + tile] - loc;
     __syncthreads();
     const uint32_t mask = (1u << nbits) - 1u;
-    const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+    const uint64_t base = (uint64_t)tile * kSortTile;
     uint64_t keys[kSortItems];  // all loads in flight before any ranking
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
