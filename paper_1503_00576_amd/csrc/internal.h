@@ -82,7 +82,7 @@ hipError_t scan_exclusive_u32(const uint32_t *in, uint32_t *out, uint64_t N, uin
 // radix sort: result lands in *result (== keys or tmp); scratch: sort_scratch_bytes(count)
 size_t sort_scratch_bytes(uint64_t count);
 hipError_t sort_u64(uint64_t *keys, uint64_t *tmp, uint32_t count, int lo_bit, int hi_bit,
-                    void *scratch, const int32_t *status, hipStream_t s, uint64_t **result);
+                    void *scratch, int32_t *status, hipStream_t s, uint64_t **result);
 
 hipError_t fill_u32(uint32_t *p, uint32_t value, uint64_t count, hipStream_t s);
 

@@ -148,6 +148,15 @@ def test_panel_thresholds(monkeypatch, ranks):
         assert check_vs_oracle(complete(k), k) == math.comb(k, 3)
 
 
+def test_single_sweep_sort(monkeypatch):
+    """The single-sweep radix variant (look-back instead of a histogram pass) in the edge and
+    in-edge sorts of graphs above its 2^20-key threshold, with ragged last tiles."""
+    monkeypatch.setenv("TC_SORT_ONESWEEP", "1")
+    for e, n in [synth.rmat_graph(17, 16, seed=21), synth.rmat_graph(18, 6, seed=22)]:
+        assert e.shape[0] >= (1 << 20) and e.shape[0] % 4096
+        check_vs_oracle(e.numpy(), n)
+
+
 def test_prepared_recount():
     """A resident preprocessed graph counted repeatedly, with and without per-vertex counts."""
     e, n = synth.rmat_graph(13, 16, seed=12, device=DEV)
