@@ -390,7 +390,11 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_onesweep(
     for (uint32_t j = t; j < ntile; j += kSortThreads) {
         const uint64_t key = s_stage[j];
         const uint32_t d = (uint32_t)(key >> shift) & mask;
-        out[s_glob[d] + j] = key;
+        const uint32_t pos = s_glob[d] + j;
+        if (pos < count)  // holds whenever the prefixes are right; never write outside `out`
+            out[pos] = key;
+        else
+            set_status(status, TC_E_HIP);
     }
 }
 
