@@ -20,8 +20,9 @@ def make_requests():
         e, n = synth.rmat_graph(s, 16, seed=100 + i)
         reqs.append((e.pin_memory(), n, None))
     for i in range(6):
-        e, n = synth.rmat_graph(15, 16, seed=200 + i)
-        reqs.append((e.pin_memory(), n, ("big", i % 3)))   # keys repeat: resident reuse
+        # a key names one graph: requests 3..5 repeat 0..2 and are served from resident CSRs
+        e, n = synth.rmat_graph(15, 16, seed=200 + i % 3)
+        reqs.append((e.pin_memory(), n, ("big", i % 3)))
     e, n = synth.er_1000()
     reqs.append((e.pin_memory(), n, None))
     return reqs
@@ -35,7 +36,9 @@ def test_alone_equals_mix_equals_oracle():
     with serve.Server(DEV, max_inflight=1) as srv:
         for e, n, key in reqs:
             alone.append(srv.submit(serve.Request(e, n, key)).result(timeout=120)[0])
+        hits = srv.stats["resident_hits"]
     assert alone == want
+    assert hits == 3
     # mix: everything at once, budget small enough that requests queue, small ones batched,
     # large ones overlapping on several streams, repeated keys served from resident CSRs
     budget = 2 * api.workspace_size(1 << 15, 600000) + (64 << 20)
