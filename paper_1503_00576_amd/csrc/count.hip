@@ -33,7 +33,7 @@
 
 namespace tc {
 
-constexpr uint32_t kPiece = 32;
+constexpr uint32_t kPiece = 16;
 constexpr int kThreads = 512;
 constexpr int kWaves = kThreads / kWave;
 constexpr uint32_t kLdsWords = 16384;                 // 64 KiB per workgroup
