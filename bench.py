@@ -90,13 +90,13 @@ def cpu_baseline(dev, seconds_hint: float):
                       f"in {dt:.2f} s on one host core"}
 
 
-def batched_section(dev, steps: int):
+def batched_section(dev, steps: int, graphs_n: int = 4096, loop: bool = True):
     """4096 Barabasi-Albert / Watts-Strogatz graphs (50/50, n log-uniform in [50, 20000],
     average degree in [4, 32]) in one captured plan, tuned, against a loop of one tc_count
     call per graph on the same GPU."""
     import torch
     from paper_1503_00576_amd import api, autotune, synth
-    spec = synth.BatchSpec(graphs=4096, seed=0)
+    spec = synth.BatchSpec(graphs=graphs_n, seed=0)
     t0 = time.perf_counter()
     graphs = synth.batch_graphs(spec, device=dev)
     packed = synth.pack_symmetric(graphs, device=dev)
@@ -106,6 +106,7 @@ def batched_section(dev, steps: int):
     torch.cuda.synchronize()
     log(f"batch: {b.G} graphs, {b.n_total} vertices, {edges} edges in "
         f"{time.perf_counter() - t0:.1f} s")
+    log("tuning")
     best, timings = autotune.tune_batched(b)
     log(f"tuned: {best} ({min(t for _, t in timings):.3f} ms)")
     plan = api.BatchPlan(b.G, b.n_total, b.adj_total, best, device=dev)
@@ -120,6 +121,11 @@ def batched_section(dev, steps: int):
     torch.cuda.synchronize()
     batch_ms = (time.perf_counter() - t0) * 1e3 / steps
     assert torch.equal(res.totals, totals)
+    log(f"plan: {batch_ms:.3f} ms per batch")
+    if not loop:
+        return {"graphs": b.G, "vertices": b.n_total, "edges": edges,
+                "ms_per_batch": round(batch_ms, 3), "graphs_per_s": b.G / batch_ms * 1e3,
+                "tuning": best}
     # the plain per-graph loop: one tc_count per graph, workspace sized for the largest
     nmax = max(n for _, n in graphs)
     mmax = max(int(e.shape[0]) for e, _ in graphs)
@@ -230,6 +236,10 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched measurement (4096 small graphs)")
     ap.add_argument("--batched-only", action="store_true")
+    ap.add_argument("--batched-graphs", type=int, default=4096,
+                    help="graphs in the batched measurement (profiling runs use fewer)")
+    ap.add_argument("--no-loop", action="store_true",
+                    help="batched: skip the per-graph tc_count comparison loop")
     ap.add_argument("--serve", action="store_true",
                     help="only run the serving trace (Poisson arrivals of mixed R-MAT graphs)")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
@@ -261,7 +271,8 @@ def main():
               flush=True)
         return
     if args.batched_only:
-        print(json.dumps({"batched": batched_section(dev, args.steps)}), flush=True)
+        print(json.dumps({"batched": batched_section(dev, args.steps, args.batched_graphs,
+                                                     not args.no_loop)}), flush=True)
         return
     log(f"generating {WORKLOADS[args.workload]['label']}")
     t0 = time.perf_counter()
