@@ -265,6 +265,28 @@ __device__ __forceinline__ uint32_t run_batch(uint32_t eb, uint32_t e1, const Se
     return hits_total;
 }
 
+// Wave-private claims on a shared item counter: kClaim consecutive positions per atomic, so
+// that the counter (one address that every XCD's waves update) sees few operations when items
+// are small.  Items are sorted heaviest first, so a claim holds items of similar size.
+template <uint32_t kClaim>
+struct WaveQueue {
+    uint32_t next = 0, end = 0;
+    __device__ __forceinline__ bool pop(uint32_t *counter, uint32_t n_items, uint32_t &q) {
+        if (next == end) {
+            uint32_t c = 0;
+            if (lane_id() == 0) c = atomicAdd(counter, kClaim);
+            c = wave_bcast(c, 0);
+            if (c >= n_items) return false;
+            next = c;
+            end = min(c + kClaim, n_items);
+        }
+        q = next++;
+        return true;
+    }
+};
+constexpr uint32_t kClaimWave = 8;     // middle-vertex kernel, wave items
+constexpr uint32_t kClaimBatched = 64;  // batched kernel
+
 struct ItemRange {
     uint32_t v, e0, e1, r0, d;
 };
@@ -434,11 +456,8 @@ __global__ __launch_bounds__(kThreads) void k_count(
     // phase 2: wave items, each wave in its own LDS slice
     uint32_t *mem = s_mem + w * kSliceWords;
     const uint32_t n_items_a = *n_items_a_ptr;
-    for (;;) {
-        uint32_t q = 0;
-        if (lane == 0) q = atomicAdd(queue_a, 1u);
-        q = wave_bcast(q, 0);
-        if (q >= n_items_a) break;
+    WaveQueue<kClaimWave> wq;
+    for (uint32_t q; wq.pop(queue_a, n_items_a, q);) {
         q = n_items_a - 1 - q;
         const ItemRange it =
             item_range(q, kItemEdgesWave, n1, item_v_a, item_off_a, cptr, row_ptr);
@@ -507,11 +526,8 @@ __global__ __launch_bounds__(kThreads) void k_count_u(
     unsigned long long *totals = *totals_pp;
     unsigned long long *tpv = PV ? *tpv_pp : nullptr;
     const OutEdgeSegs segs{frp, fcol};
-    for (;;) {
-        uint32_t q = 0;
-        if (lane == 0) q = atomicAdd(queue, 1u);
-        q = wave_bcast(q, 0);
-        if (q >= n_items) break;
+    WaveQueue<kClaimBatched> wq;
+    for (uint32_t q; wq.pop(queue, n_items, q);) {
         q = n_items - 1 - q;
         const uint32_t u = item_u[q];
         const uint32_t r0 = frp[u], d = frp[u + 1] - r0;
