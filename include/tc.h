@@ -144,14 +144,17 @@ int tc_sort_u64(uint64_t *d_keys, uint64_t *d_tmp, int64_t count, int32_t bits, 
  * duplicate or unsorted row, missing mirror entry, inconsistent offsets).
  * Method: degree = row length; a stable per-row filter keeps the neighbours later in the
  * order of Section 2.2, so the oriented rows stay sorted without any sort; the counting kernel
- * stages N+(u) in LDS and streams the lists N+(v) of u's out-neighbours (Section 2.2's
- * intersections, grouped by u).
+ * computes Section 2.2's intersections grouped by u: for a vertex u with more than 256 forward
+ * neighbours it stages N+(u) in LDS and streams the lists N+(v) of u's out-neighbours; the
+ * other edges are taken in chunks of consecutive forward edges, one edge u -> v per lane,
+ * with the chunk's short lists N+(u) staged in LDS and N+(v) streamed through them.
  *
  * A plan binds a workspace of tc_batched_workspace_size(g_cap, n_cap, adj_cap) bytes and
  * captures the whole launch sequence once per mode (with / without per-vertex counts) into a
  * hipGraph on its first run; later runs only write a small argument block and replay the
- * graph, for any batch within the capacities.  tuning_json (nullable) may set "items_k"
- * (out-neighbours per work item, >= 16, default 256) and "wgs_per_cu" (1 or 2, default 2).
+ * graph, for any batch within the capacities.  tuning_json (nullable) may set "chunk_e"
+ * (forward edges per chunk, 64 .. 1536, default 1024), "items_k" (out-neighbours of a large
+ * vertex per work item, >= 16, default 256) and "wgs_per_cu" (1 or 2, default 2).
  * Runs of one plan must not overlap (they share the workspace); the plan must outlive its
  * last run on the GPU.  flags must be 0. */
 typedef struct tc_plan tc_plan;

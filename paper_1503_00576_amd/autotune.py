@@ -1,10 +1,11 @@
 """Autotuner for the batched counting plan.
 
-The tunables are the work-distribution tile of the batched counting kernel -- "items_k", the
-number of out-neighbours of one vertex handled by one work item -- and "wgs_per_cu", the
-persistent grid's workgroups per compute unit.  The tuner captures one plan per candidate,
-replays it on the caller's batch, keeps the fastest, and can cache the choice in a JSON file
-keyed by device and batch shape."""
+The tunables are the work distribution of the batched counting kernel -- "chunk_e", the number
+of consecutive forward edges in one work item of the edge-per-lane path (vertices with at most
+256 forward neighbours), "items_k", the number of out-neighbours of one larger vertex handled
+by one work item -- and "wgs_per_cu", the persistent grid's workgroups per compute unit.  The
+tuner captures one plan per candidate, replays it on the caller's batch, keeps the fastest,
+and can cache the choice in a JSON file keyed by device and batch shape."""
 from __future__ import annotations
 
 import json
@@ -14,7 +15,8 @@ import torch
 
 from . import api
 
-ITEMS_K = (32, 64, 128, 256, 512, 1024)
+CHUNK_E = (256, 512, 1024, 1536)
+ITEMS_K = (64, 256, 1024)
 WGS_PER_CU = (1, 2)
 
 
@@ -50,7 +52,8 @@ def tune_batched(b: api.Batch, reps: int = 3, cache: str | None = None,
             saved = json.load(f)
         if key in saved:
             return saved[key]["best"], saved[key]["timings"]
-    cands = candidates or [{"items_k": k, "wgs_per_cu": w} for k in ITEMS_K for w in WGS_PER_CU]
+    cands = candidates or [{"chunk_e": c, "items_k": k, "wgs_per_cu": w}
+                           for c in CHUNK_E for k in ITEMS_K for w in WGS_PER_CU]
     timings = []
     for t in cands:
         plan = api.BatchPlan(b.G, b.n_total, b.adj_total, t, device=device)

@@ -30,7 +30,8 @@ struct BatchArgs {
     unsigned long long *per_vertex;
     int32_t *status;  // per graph, may be null
     uint32_t G, N, kitem;
-    uint32_t A;  // adjacency entries in total
+    uint32_t A;      // adjacency entries in total
+    uint32_t chunk;  // forward edges per light chunk
 };
 
 __device__ __forceinline__ void graph_error(const BatchArgs &a, uint32_t g, int32_t code,
@@ -53,12 +54,12 @@ __global__ void k_b_set_args(BatchArgs *dst, BatchArgs a) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *dst = a;
 }
 
-// zero the outputs and the internal status / queue
+// zero the outputs and the internal status / queues
 __global__ void k_b_clear(const BatchArgs *__restrict__ args, int32_t *__restrict__ gstat,
                           uint32_t *__restrict__ queue, uint32_t cap) {
     const BatchArgs a = *args;
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) *queue = 0;
+    if (i < 2) queue[i] = 0;
     for (uint32_t x = i; x < cap; x += gridDim.x * blockDim.x) {
         if (x < a.G) {
             a.totals[x] = 0;
@@ -141,11 +142,12 @@ __global__ void k_b_fcount(const BatchArgs *__restrict__ args, uint32_t ncap,
     fdeg[x] = c;
 }
 
-// the forward rows (union ids, input order kept), and the symmetry check: every forward
-// entry (x, y) needs its mirror in row y
+// the forward rows (union ids, input order kept) with the row of every entry, and the
+// symmetry check: every forward entry (x, y) needs its mirror in row y
 __global__ void k_b_ffill(const BatchArgs *__restrict__ args, const uint32_t *__restrict__ gid,
                           const uint32_t *__restrict__ deg, const uint32_t *__restrict__ frp,
-                          uint32_t *__restrict__ fcol, int32_t *__restrict__ gstat) {
+                          uint32_t *__restrict__ fcol, uint32_t *__restrict__ fsrc,
+                          int32_t *__restrict__ gstat) {
     const BatchArgs a = *args;
     const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= a.N || deg[x] == 0) return;
@@ -161,6 +163,7 @@ __global__ void k_b_ffill(const BatchArgs *__restrict__ args, const uint32_t *__
         if (y < 0 || y >= ng || y == lx) continue;
         const uint32_t Y = (uint32_t)(v0 + y);
         if (!b_forward(x, Y, deg)) continue;
+        fsrc[o] = x;
         fcol[o++] = Y;
         // mirror: binary search for lx in row y (rows of invalid graphs may be unsorted;
         // the search stays inside the row either way)
@@ -179,14 +182,23 @@ __global__ void k_b_ffill(const BatchArgs *__restrict__ args, const uint32_t *__
     }
 }
 
-// work items: rows with at least two forward neighbours, in chunks of kitem
+// work items: heavy rows (more than `light_max` forward neighbours) in chunks of kitem; the
+// light rows are counted in chunks of consecutive forward edges: light[0] = forward edges,
+// light[1] = chunks
 __global__ void k_b_items(const BatchArgs *__restrict__ args, uint32_t ncap,
-                          const uint32_t *__restrict__ fdeg, uint32_t *__restrict__ items) {
+                          const uint32_t *__restrict__ fdeg, const uint32_t *__restrict__ frp,
+                          uint32_t light_max, uint32_t *__restrict__ items,
+                          uint32_t *__restrict__ light) {
     const BatchArgs a = *args;
     const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x > ncap) return;
     const uint32_t d = (x < a.N) ? fdeg[x] : 0u;
-    items[x] = d >= 2 ? (d + a.kitem - 1) / a.kitem : 0u;
+    items[x] = d > light_max ? (d + a.kitem - 1) / a.kitem : 0u;
+    if (x == ncap) {
+        const uint32_t mf = frp[ncap];
+        light[0] = mf;
+        light[1] = (mf + a.chunk - 1) / a.chunk;
+    }
 }
 
 __global__ void k_b_item_fill(const uint32_t *__restrict__ items,
@@ -225,7 +237,7 @@ __global__ void k_b_finish(const BatchArgs *__restrict__ args, const uint32_t *_
 // ------------------------------------------------------------------ workspace + plan
 
 struct BatchLayout {
-    size_t args, ctl, gstat, gid, deg, fdeg, frp, fcol, items, ioff, item_u, scan, total;
+    size_t args, ctl, gstat, gid, deg, fdeg, frp, fcol, fsrc, items, ioff, item_u, scan, total;
 };
 
 constexpr uint32_t kMinItemEdges = 16;
@@ -247,6 +259,7 @@ static BatchLayout batch_layout(uint32_t gcap, uint32_t ncap, uint64_t acap) {
     L.fdeg = take(n1 * 4);
     L.frp = take(n1 * 4);
     L.fcol = take((size_t)acap * 4 + count_col_pad_bytes());
+    L.fsrc = take((size_t)acap * 4);
     L.items = take(n1 * 4);
     L.ioff = take(n1 * 4);
     L.item_u = take(((size_t)acap / kMinItemEdges + n1 + 1) * 4);
@@ -262,7 +275,7 @@ using namespace tc;
 struct tc_plan {
     uint32_t gcap, ncap;
     uint64_t acap;
-    uint32_t kitem, wgs_per_cu;
+    uint32_t kitem, chunk, wgs_per_cu;
     void *ws;
     size_t ws_bytes;
     BatchLayout L;
@@ -290,6 +303,7 @@ static int batch_enqueue(tc_plan *p, bool pv, hipStream_t s) {
     uint32_t *gid = (uint32_t *)(ws + L.gid), *deg = (uint32_t *)(ws + L.deg);
     uint32_t *fdeg = (uint32_t *)(ws + L.fdeg), *frp = (uint32_t *)(ws + L.frp);
     uint32_t *fcol = (uint32_t *)(ws + L.fcol), *items = (uint32_t *)(ws + L.items);
+    uint32_t *fsrc = (uint32_t *)(ws + L.fsrc);
     uint32_t *ioff = (uint32_t *)(ws + L.ioff), *item_u = (uint32_t *)(ws + L.item_u);
     uint32_t *scan = (uint32_t *)(ws + L.scan);
     const uint32_t ncap = p->ncap, n1 = ncap + 1;
@@ -300,16 +314,30 @@ static int batch_enqueue(tc_plan *p, bool pv, hipStream_t s) {
     hipLaunchKernelGGL(k_b_fcount, grid(n1), dim3(256), 0, s, args, ncap, gid, deg, fdeg);
     if (hipGetLastError() != hipSuccess) return TC_E_HIP;
     if (scan_exclusive_u32(fdeg, frp, n1, scan, s) != hipSuccess) return TC_E_HIP;
-    hipLaunchKernelGGL(k_b_ffill, grid(ncap), dim3(256), 0, s, args, gid, deg, frp, fcol, gstat);
-    hipLaunchKernelGGL(k_b_items, grid(n1), dim3(256), 0, s, args, ncap, fdeg, items);
+    hipLaunchKernelGGL(k_b_ffill, grid(ncap), dim3(256), 0, s, args, gid, deg, frp, fcol, fsrc,
+                       gstat);
+    // ctl: [0] heavy-item queue, [1] light-chunk queue, [2] forward edges, [3] light chunks
+    hipLaunchKernelGGL(k_b_items, grid(n1), dim3(256), 0, s, args, ncap, fdeg, frp,
+                       count_light_max(), items, ctl + 2);
     if (hipGetLastError() != hipSuccess) return TC_E_HIP;
     if (scan_exclusive_u32(items, ioff, n1, scan, s) != hipSuccess) return TC_E_HIP;
     hipLaunchKernelGGL(k_b_item_fill, grid(ncap), dim3(256), 0, s, items, ioff, ncap, item_u);
     if (hipGetLastError() != hipSuccess) return TC_E_HIP;
-    const BatchArgs *dev_args = args;
-    if (launch_count_u(frp, fcol, gid, item_u, ioff, ioff + ncap, &dev_args->kitem, ctl, &dev_args->totals,
-                       &dev_args->per_vertex, pv, device_cu_count() * p->wgs_per_cu,
-                       s) != hipSuccess)
+    BatchKernelArgs ka;
+    ka.frp = frp;
+    ka.fcol = fcol;
+    ka.fsrc = fsrc;
+    ka.gid = gid;
+    ka.item_u = item_u;
+    ka.item_off = ioff;
+    ka.n_items = ioff + ncap;
+    ka.kitem = &args->kitem;
+    ka.chunk = &args->chunk;
+    ka.light = ctl + 2;
+    ka.queue = ctl;
+    ka.totals_pp = &args->totals;
+    ka.tpv_pp = &args->per_vertex;
+    if (launch_count_u(ka, pv, device_cu_count() * p->wgs_per_cu, s) != hipSuccess)
         return TC_E_HIP;
     hipLaunchKernelGGL(k_b_finish, grid(p->gcap), dim3(256), 0, s, args, frp, gstat);
     return hipGetLastError() == hipSuccess ? TC_OK : TC_E_HIP;
@@ -365,6 +393,7 @@ static int plan_set_args(tc_plan *p, int32_t G, const int64_t *d_vtx_off,
     a.N = (uint32_t)n_total;
     a.kitem = p->kitem;
     a.A = (uint32_t)adj_total;
+    a.chunk = p->chunk;
     hipLaunchKernelGGL(k_b_set_args, dim3(1), dim3(64), 0, s,
                        (BatchArgs *)((char *)p->ws + p->L.args), a);
     return hipGetLastError() == hipSuccess ? TC_OK : TC_E_HIP;
@@ -395,6 +424,9 @@ int tc_batched_plan_create(int32_t g_cap, int64_t n_cap, int64_t adj_cap, uint32
     p->acap = (uint64_t)adj_cap;
     p->kitem = parse_tuning(tuning_json, "\"items_k\"", 256);
     if (p->kitem < kMinItemEdges) p->kitem = kMinItemEdges;
+    p->chunk = parse_tuning(tuning_json, "\"chunk_e\"", 1024);
+    if (p->chunk < 64) p->chunk = 64;
+    if (p->chunk > count_light_chunk_max()) p->chunk = count_light_chunk_max();
     p->wgs_per_cu = parse_tuning(tuning_json, "\"wgs_per_cu\"", 2);
     if (p->wgs_per_cu > 2) p->wgs_per_cu = 2;  // LDS holds two workgroups per CU
     p->ws = d_ws;

@@ -47,6 +47,10 @@ constexpr uint32_t kItemEdgesWave = 256;
 constexpr uint32_t kItemEdgesBlock = 2048;
 constexpr uint32_t kPanel = 32;                       // one bit per panel vertex in a mask
 constexpr uint32_t kPanelRanks = kLdsWords - 32;      // mask table: one word per rank
+// batched kernel: rows with at most kLightMax forward entries are counted edge by edge; a
+// chunk of forward edges plus kLightMax entries on either side must fit one wave's slice
+constexpr uint32_t kLightMax = 256;
+constexpr uint32_t kLightChunkMax = kSliceWords - 2 * kLightMax;
 
 // ------------------------------------------------------------------ membership probes
 
@@ -102,8 +106,10 @@ struct ListProbe {  // sorted list in LDS or in global memory
 
 // ------------------------------------------------------------------ per-batch streaming
 
-struct WaveScratch {  // tag: the segment's owner (per-vertex counts) or its panel mask
-    uint32_t off[kWave], beg[kWave], first[kWave], end[kWave], cnt[kWave], tag[kWave];
+struct WaveScratch {  // tag: the segment's owner (per-vertex counts) or its panel mask;
+                     // the batched kernel's light segments keep their N+(u) in tag and aux
+    uint32_t off[kWave], beg[kWave], first[kWave], end[kWave], cnt[kWave], tag[kWave],
+        aux[kWave];
 };
 
 // Segment sources: segment e is a range [b, en) of `col` streamed through the staged list,
@@ -285,7 +291,8 @@ struct WaveQueue {
     }
 };
 constexpr uint32_t kClaimWave = 8;     // middle-vertex kernel, wave items
-constexpr uint32_t kClaimBatched = 64;  // batched kernel
+constexpr uint32_t kClaimBatched = 64;  // batched kernel, heavy items
+constexpr uint32_t kClaimLight = 4;     // batched kernel, light chunks
 
 struct ItemRange {
     uint32_t v, e0, e1, r0, d;
@@ -501,20 +508,111 @@ __global__ __launch_bounds__(kThreads) void k_count(
 
 // ------------------------------------------------------------------ batched kernel
 
-// Batched counting over a disjoint union of small graphs in id space (their oriented lists
-// keep the input's id order, no relabelling): item = (u, chunk of up to kitem out-neighbours
-// of u).  N+(u) is staged in the wave's LDS slice (bitmap over its id span, or a sorted list)
-// and the whole list N+(v) of every out-neighbour v streams through it: every common element
-// w closes the triangle (u, v, w) once.  Hits go to the graph of u; per-vertex counts credit
-// u (per item), v (per segment) and w (LDS counters by list position).
+// Light segments of the batched kernel.  Segment i of [eb, e1) is edge e = eb + i (u -> v) of
+// the forward CSR, kept when 2 <= d+(u) <= kLightMax: it streams the whole list N+(v) and
+// looks every element up in N+(u), which the caller staged in LDS (`win` holds fcol from
+// position wbase on; binary search, the list is short).  Returns the hits of this lane's own
+// segment (at most d+(u)); per-vertex counts go to global counters: T(w) per hit, T(u) and
+// T(v) per segment.
 template <bool PV>
-__global__ __launch_bounds__(kThreads) void k_count_u(
-    const uint32_t *__restrict__ frp, const uint32_t *__restrict__ fcol,
-    const uint32_t *__restrict__ gid, const uint32_t *__restrict__ item_u,
-    const uint32_t *__restrict__ item_off, const uint32_t *__restrict__ n_items_ptr,
-    const uint32_t *__restrict__ kitem_ptr, uint32_t *__restrict__ queue,
-    unsigned long long *const *__restrict__ totals_pp,
-    unsigned long long *const *__restrict__ tpv_pp) {
+__device__ __forceinline__ uint32_t run_light(uint32_t eb, uint32_t e1,
+                                              const uint32_t *__restrict__ frp,
+                                              const uint32_t *__restrict__ fcol,
+                                              const uint32_t *__restrict__ fsrc,
+                                              const uint32_t *win, uint32_t wbase,
+                                              WaveScratch &ws,
+                                              unsigned long long *__restrict__ tpv) {
+    const uint32_t lane = lane_id();
+    const uint32_t e = eb + lane;
+    uint32_t b = 0, en = 0, lo = 0, d = 0, u = 0, v = 0;
+    if (e < e1) {
+        u = fsrc[e];
+        const uint32_t r0 = frp[u];
+        d = frp[u + 1] - r0;
+        if (d >= 2 && d <= kLightMax) {
+            v = fcol[e];
+            b = frp[v];
+            en = frp[v + 1];
+            lo = r0 - wbase;
+        } else {
+            d = 0;
+        }
+    }
+    const uint32_t a0 = b & ~3u;
+    const uint32_t p = (d && en > b) ? (en - a0 + kPiece - 1) / kPiece : 0u;
+    const uint32_t incl = wave_incl_scan(p);
+    const uint32_t Q = wave_bcast(incl, kWave - 1);
+    ws.off[lane] = incl - p;
+    ws.beg[lane] = a0;
+    ws.first[lane] = b;
+    ws.end[lane] = en;
+    ws.tag[lane] = lo;
+    ws.aux[lane] = d;
+    ws.cnt[lane] = 0;
+    wave_lds_sync();
+    for (uint32_t q0 = 0; q0 < Q; q0 += kWave) {
+        const uint32_t q = q0 + lane;
+        if (q < Q) {
+            uint32_t k = 0;
+#pragma unroll
+            for (uint32_t step = 32; step; step >>= 1)
+                if (ws.off[k + step] <= q) k += step;
+            const uint32_t start = ws.beg[k] + (q - ws.off[k]) * kPiece;
+            const uint32_t first = ws.first[k], stop = ws.end[k];
+            const uint4 *p4 = reinterpret_cast<const uint4 *>(fcol + start);
+            uint32_t wv[kPiece];
+#pragma unroll
+            for (uint32_t j = 0; j < kPiece / 4; ++j) {
+                const uint4 x = p4[j];
+                wv[4 * j] = x.x;
+                wv[4 * j + 1] = x.y;
+                wv[4 * j + 2] = x.z;
+                wv[4 * j + 3] = x.w;
+            }
+            const uint32_t *list = win + ws.tag[k];
+            const uint32_t dl = ws.aux[k];
+            const uint32_t lo_i = first > start ? first - start : 0u;
+            const uint32_t hi_i = min(stop - start, kPiece);
+            uint32_t hits = 0;
+#pragma unroll
+            for (uint32_t i = 0; i < kPiece; ++i) {
+                if (i >= lo_i && i < hi_i) {
+                    const uint32_t x = wv[i];
+                    const uint32_t pos = lower_bound_u32(list, dl, x);
+                    if (pos < dl && list[pos] == x) {
+                        ++hits;
+                        if (PV) atomicAdd(&tpv[x], 1ull);
+                    }
+                }
+            }
+            if (hits) atomicAdd(&ws.cnt[k], hits);
+        }
+    }
+    wave_lds_sync();
+    const uint32_t h = ws.cnt[lane];
+    if (PV && h) {
+        atomicAdd(&tpv[u], (unsigned long long)h);
+        atomicAdd(&tpv[v], (unsigned long long)h);
+    }
+    return h;
+}
+
+// Batched counting over a disjoint union of small graphs in id space (their oriented lists
+// keep the input's id order, no relabelling).  Every triangle is found once, from its first
+// vertex u in the order of Section 2.2: for every out-neighbour v of u, the common elements of
+// N+(u) and N+(v).
+//   heavy items (u with d+(u) > kLightMax): (u, chunk of up to kitem out-neighbours of u);
+//     N+(u) is staged in the wave's LDS slice (bitmap over its id span, or a sorted list) and
+//     the whole list N+(v) of every out-neighbour v streams through it.  Hits go to the graph
+//     of u; per-vertex counts credit u (per item), v (per segment) and w (LDS counters by
+//     list position).
+//   light items: chunks of `chunk` consecutive forward edges, one edge per lane (run_light);
+//     the lists of the chunk's light rows lie inside the window [e0 - kLightMax, e1 +
+//     kLightMax) of fcol, which is staged in the wave's slice.  Graph ids are non-decreasing
+//     along the edges, so per-graph totals are summed per run of equal graph ids.
+
+template <bool PV>
+__global__ __launch_bounds__(kThreads) void k_count_u(const BatchKernelArgs a) {
     __shared__ uint32_t s_mem[kLdsWords];
     __shared__ WaveScratch s_ws[kWaves];
     const uint32_t t = threadIdx.x, w = t / kWave, lane = lane_id();
@@ -522,16 +620,18 @@ __global__ __launch_bounds__(kThreads) void k_count_u(
     uint32_t *mem = s_mem + w * kSliceWords;
     for (uint32_t i = t; i < kLdsWords; i += kThreads) s_mem[i] = 0;
     __syncthreads();
-    const uint32_t n_items = *n_items_ptr, kitem = *kitem_ptr;
-    unsigned long long *totals = *totals_pp;
-    unsigned long long *tpv = PV ? *tpv_pp : nullptr;
+    const uint32_t *__restrict__ frp = a.frp;
+    const uint32_t *__restrict__ fcol = a.fcol;
+    const uint32_t n_items = *a.n_items, kitem = *a.kitem;
+    unsigned long long *totals = *a.totals_pp;
+    unsigned long long *tpv = PV ? *a.tpv_pp : nullptr;
     const OutEdgeSegs segs{frp, fcol};
     WaveQueue<kClaimBatched> wq;
-    for (uint32_t q; wq.pop(queue, n_items, q);) {
+    for (uint32_t q; wq.pop(a.queue, n_items, q);) {
         q = n_items - 1 - q;
-        const uint32_t u = item_u[q];
+        const uint32_t u = a.item_u[q];
         const uint32_t r0 = frp[u], d = frp[u + 1] - r0;
-        const uint32_t e0 = r0 + (q - item_off[u]) * kitem;
+        const uint32_t e0 = r0 + (q - a.item_off[u]) * kitem;
         const uint32_t e1 = min(e0 + kitem, r0 + d);
         uint32_t lo = ~0u, hi = 0;  // the id span of N+(u) (rows of invalid graphs may be
         for (uint32_t i = lane; i < d; i += kWave) {  // unsorted, so take min and max)
@@ -580,24 +680,44 @@ __global__ __launch_bounds__(kThreads) void k_count_u(
         wave_lds_sync();
         const uint64_t item_hits = wave_sum_u64(cnt);
         if (lane == 0 && item_hits) {
-            atomicAdd(&totals[gid[u]], (unsigned long long)item_hits);
+            atomicAdd(&totals[a.gid[u]], (unsigned long long)item_hits);
             if (PV) atomicAdd(&tpv[u], (unsigned long long)item_hits);
         }
     }
+    // light chunks
+    const uint32_t mf = a.light[0], n_chunks = a.light[1], chunk = *a.chunk;
+    WaveQueue<kClaimLight> lq;
+    for (uint32_t q; lq.pop(a.queue + 1, n_chunks, q);) {
+        const uint32_t e0 = q * chunk, e1 = min(e0 + chunk, mf);
+        const uint32_t wbase = e0 > kLightMax ? e0 - kLightMax : 0u;
+        const uint32_t wend = min(e1 + kLightMax, mf);
+        for (uint32_t i = wbase + lane; i < wend; i += kWave) mem[i - wbase] = fcol[i];
+        wave_lds_sync();
+        for (uint32_t eb = e0; eb < e1; eb += kWave) {
+            uint32_t h = run_light<PV>(eb, e1, frp, fcol, a.fsrc, mem, wbase, ws, tpv);
+            // per-graph sums over runs of equal graph ids (non-decreasing along the edges)
+            const uint32_t e = eb + lane;
+            const uint32_t g = e < e1 ? a.gid[a.fsrc[e]] : 0xFFFFFFFFu;
+            for (int o = 1; o < kWave; o <<= 1) {
+                const uint32_t hv = (uint32_t)__shfl_up((int)h, o, kWave);
+                const uint32_t gv = (uint32_t)__shfl_up((int)g, o, kWave);
+                if (lane >= (uint32_t)o && gv == g) h += hv;
+            }
+            const uint32_t gn = (uint32_t)__shfl_down((int)g, 1, kWave);
+            if ((lane == kWave - 1 || gn != g) && g != 0xFFFFFFFFu && h)
+                atomicAdd(&totals[g], (unsigned long long)h);
+        }
+        for (uint32_t i = wbase + lane; i < wend; i += kWave) mem[i - wbase] = 0;
+        wave_lds_sync();
+    }
 }
 
-hipError_t launch_count_u(const uint32_t *frp, const uint32_t *fcol, const uint32_t *gid,
-                          const uint32_t *item_u, const uint32_t *item_off,
-                          const uint32_t *n_items, const uint32_t *kitem, uint32_t *queue,
-                          unsigned long long *const *totals_pp,
-                          unsigned long long *const *tpv_pp, bool per_vertex, uint32_t grid,
+hipError_t launch_count_u(const BatchKernelArgs &a, bool per_vertex, uint32_t grid,
                           hipStream_t s) {
     if (per_vertex)
-        hipLaunchKernelGGL(k_count_u<true>, dim3(grid), dim3(kThreads), 0, s, frp, fcol, gid,
-                           item_u, item_off, n_items, kitem, queue, totals_pp, tpv_pp);
+        hipLaunchKernelGGL(k_count_u<true>, dim3(grid), dim3(kThreads), 0, s, a);
     else
-        hipLaunchKernelGGL(k_count_u<false>, dim3(grid), dim3(kThreads), 0, s, frp, fcol, gid,
-                           item_u, item_off, n_items, kitem, queue, totals_pp, tpv_pp);
+        hipLaunchKernelGGL(k_count_u<false>, dim3(grid), dim3(kThreads), 0, s, a);
     return hipGetLastError();
 }
 
@@ -609,6 +729,8 @@ uint32_t count_item_edges_wave() { return kItemEdgesWave; }
 uint32_t count_item_edges_block() { return kItemEdgesBlock; }
 uint32_t count_col_pad_bytes() { return kPiece * 4; }
 uint32_t count_panel() { return kPanel; }
+uint32_t count_light_max() { return kLightMax; }
+uint32_t count_light_chunk_max() { return kLightChunkMax; }
 uint32_t count_panel_ranks() { return kPanelRanks; }
 
 hipError_t launch_count(const CountArgs &x, bool per_vertex, hipStream_t s) {

@@ -111,11 +111,20 @@ uint32_t count_col_pad_bytes();
 // counting kernel can handle as panels (its mask table must fit the workgroup's LDS)
 uint32_t count_panel();
 uint32_t count_panel_ranks();
-hipError_t launch_count_u(const uint32_t *frp, const uint32_t *fcol, const uint32_t *gid,
-                          const uint32_t *item_u, const uint32_t *item_off,
-                          const uint32_t *n_items, const uint32_t *kitem, uint32_t *queue,
-                          unsigned long long *const *totals_pp,
-                          unsigned long long *const *tpv_pp, bool per_vertex, uint32_t grid,
+struct BatchKernelArgs {
+    const uint32_t *frp, *fcol, *fsrc, *gid;
+    const uint32_t *item_u, *item_off, *n_items;  // heavy items
+    const uint32_t *kitem, *chunk;                // sizes (device)
+    const uint32_t *light;                        // [0] forward edges, [1] light chunks
+    uint32_t *queue;                              // [0] heavy items, [1] light chunks
+    unsigned long long *const *totals_pp;
+    unsigned long long *const *tpv_pp;
+};
+hipError_t launch_count_u(const BatchKernelArgs &a, bool per_vertex, uint32_t grid,
                           hipStream_t s);
+// batched kernel: rows with at most count_light_max() forward entries are counted edge by
+// edge in chunks of at most count_light_chunk_max() forward edges
+uint32_t count_light_max();
+uint32_t count_light_chunk_max();
 
 }  // namespace tc

@@ -38,6 +38,8 @@ def mixed_graphs(seed=0, count=48):
     gs.append((torch.zeros((0, 2), dtype=torch.int32), 1))
     k = 40
     gs.append((torch.tensor([(i, j) for i in range(k) for j in range(i + 1, k)], dtype=torch.int32), k))
+    # dense graph: forward degrees up to ~600, above the edge-per-lane path's 256
+    gs.append((synth.erdos_renyi(700, 0.9, seed * 7 + 1), 700))
     return gs
 
 
@@ -78,7 +80,8 @@ def test_batched_union_additive():
     assert int(res.totals.sum()) == oracle.count(np.concatenate(parts), off)
 
 
-@pytest.mark.parametrize("tuning", [None, {"items_k": 16, "wgs_per_cu": 1}, {"items_k": 1024}])
+@pytest.mark.parametrize("tuning", [None, {"items_k": 16, "wgs_per_cu": 1}, {"items_k": 1024},
+                                    {"chunk_e": 64, "wgs_per_cu": 1}, {"chunk_e": 1536}])
 def test_plan_replays(tuning):
     """A captured plan replayed several times, with eager GPU work in between, every replay
     equal to the one-shot result; then a smaller batch through the same plan."""
