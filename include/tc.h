@@ -49,7 +49,9 @@ typedef enum tc_status {
     TC_E_SELF_LOOP = 3,  /* an entry (u, u) */
     TC_E_DUP_EDGE = 4,   /* an undirected edge listed more often than the format allows */
     TC_E_ASYMMETRIC = 5, /* TC_EDGES_BOTH: m odd, or not exactly m/2 forward entries;
-                            batched: an entry without its mirror */
+                            batched: entries not closed under mirroring (an exact count
+                            test plus a sum of 64-bit pair hashes, which misses with
+                            probability about 2^-64) */
     TC_E_UNSORTED = 6,   /* batched input: a CSR row not strictly ascending */
     TC_E_WORKSPACE = 7,  /* d_ws smaller than tc_workspace_size() or misaligned */
     TC_E_TOO_LARGE = 8,  /* n >= 2^31 or m >= 2^32 */

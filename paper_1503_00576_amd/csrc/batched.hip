@@ -56,6 +56,7 @@ __global__ void k_b_set_args(BatchArgs *dst, BatchArgs a) {
 
 // zero the outputs and the internal status / queues
 __global__ void k_b_clear(const BatchArgs *__restrict__ args, int32_t *__restrict__ gstat,
+                          unsigned long long *__restrict__ ghash,
                           uint32_t *__restrict__ queue, uint32_t cap) {
     const BatchArgs a = *args;
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -64,121 +65,121 @@ __global__ void k_b_clear(const BatchArgs *__restrict__ args, int32_t *__restric
         if (x < a.G) {
             a.totals[x] = 0;
             gstat[x] = 0;
+            ghash[x] = 0;
         }
         if (a.per_vertex && x < a.N) a.per_vertex[x] = 0;
     }
 }
 
-// degrees (row lengths), graph ids, checks of every row: offsets in range, ids in range, no
-// self-loop, strictly ascending
+// Pair hash for the symmetry check: the 64-bit finalizer of MurmurHash3 (fmix64) applied to
+// (x << 32 | y).
+__device__ __forceinline__ uint64_t pair_hash(uint32_t x, uint32_t y) {
+    uint64_t k = ((uint64_t)x << 32) | y;
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdull;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ull;
+    k ^= k >> 33;
+    return k;
+}
+
+// The degree of local vertex y of a graph: its row length in the input.  Both kernels that
+// take the forward decision read it from the same place, so they always agree.
+__device__ __forceinline__ bool b_forward(int64_t dx, uint32_t x, const int32_t *rp, uint32_t y) {
+    const int64_t dy = (int64_t)rp[y + 1] - rp[y];
+    return dy > dx || (dy == dx && y > x);
+}
+
+// Per vertex (thread): graph id, degree (row length), forward out-degree (entries ncap.. stay
+// zero for the scan), checks of its row (offsets in range, ids in range, no self-loop, strictly
+// ascending), and its share of the graph's symmetry sum: sum over the row's entries (x, y) of
+// pair_hash(x, y) - pair_hash(y, x), which is zero over a graph whose rows are symmetric.
+// Vertices are consecutive, so graph ids are non-decreasing across a wave and the shares are
+// summed per run of equal graph ids before one atomic per run.
 __global__ void k_b_setup(const BatchArgs *__restrict__ args, uint32_t ncap,
                           uint32_t *__restrict__ gid, uint32_t *__restrict__ deg,
+                          uint32_t *__restrict__ fdeg, unsigned long long *__restrict__ ghash,
                           int32_t *__restrict__ gstat) {
     const BatchArgs a = *args;
     const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= ncap) return;
-    if (x >= a.N) {
-        deg[x] = 0;
-        return;
-    }
-    const uint32_t g = graph_of(a.vtx_off, a.G, x);
-    gid[x] = g;
-    const int64_t v0 = a.vtx_off[g], ng = a.vtx_off[g + 1] - v0;
-    const int64_t a0 = a.adj_off[g], alen = a.adj_off[g + 1] - a0;
-    const int64_t local = (int64_t)x - v0;
-    // offsets arrays must be prefix sums: check what this vertex relies on
-    if (v0 < 0 || local < 0 || local >= ng || a0 < 0 || alen < 0 || a0 + alen > (int64_t)a.A) {
-        graph_error(a, g, TC_E_ARG, gstat);
-        deg[x] = 0;
-        return;
-    }
-    const int32_t *rp = a.row_ptr + v0 + g;
-    const int64_t r0 = rp[local], r1 = rp[local + 1];
-    uint32_t d = 0;
-    if (r0 < 0 || r1 < r0 || r1 > alen) {
-        graph_error(a, g, TC_E_ARG, gstat);
-    } else {
-        d = (uint32_t)(r1 - r0);
-        const int32_t *row = a.col + a0 + r0;
-        int64_t prev = -1;
-        for (uint32_t j = 0; j < d; ++j) {
-            const int32_t y = row[j];
-            if (y < 0 || y >= ng) {
-                graph_error(a, g, TC_E_RANGE, gstat);
-            } else if (y == local) {
-                graph_error(a, g, TC_E_SELF_LOOP, gstat);
-            } else if (y <= prev) {
-                graph_error(a, g, y == prev ? TC_E_DUP_EDGE : TC_E_UNSORTED, gstat);
-            }
-            prev = y;
-        }
-    }
-    deg[x] = d;
-}
-
-__device__ __forceinline__ bool b_forward(uint32_t x, uint32_t y, const uint32_t *deg) {
-    return deg[y] > deg[x] || (deg[y] == deg[x] && y > x);
-}
-
-// forward out-degrees (entries ncap.. stay zero for the scan)
-__global__ void k_b_fcount(const BatchArgs *__restrict__ args, uint32_t ncap,
-                           const uint32_t *__restrict__ gid, const uint32_t *__restrict__ deg,
-                           uint32_t *__restrict__ fdeg) {
-    const BatchArgs a = *args;
-    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x > ncap) return;
-    uint32_t c = 0;
-    if (x < a.N && deg[x] > 0) {
-        const uint32_t g = gid[x];
+    uint32_t g = 0xFFFFFFFFu, d = 0, c = 0;
+    uint64_t hs = 0;
+    if (x < a.N) {
+        g = graph_of(a.vtx_off, a.G, x);
+        gid[x] = g;
         const int64_t v0 = a.vtx_off[g], ng = a.vtx_off[g + 1] - v0;
-        const int32_t *row = a.col + a.adj_off[g] + a.row_ptr[x + g];
-        for (uint32_t j = 0; j < deg[x]; ++j) {
-            const int32_t y = row[j];
-            if (y >= 0 && y < ng && y != (int64_t)x - v0 &&
-                b_forward(x, (uint32_t)(v0 + y), deg))
-                ++c;
+        const int64_t a0 = a.adj_off[g], alen = a.adj_off[g + 1] - a0;
+        const int64_t local = (int64_t)x - v0;
+        // offsets arrays must be prefix sums: check what this vertex relies on (the whole
+        // vertex range of its graph, whose row offsets the forward test reads)
+        if (v0 < 0 || local < 0 || local >= ng || v0 + ng > (int64_t)a.N || a0 < 0 ||
+            alen < 0 || a0 + alen > (int64_t)a.A) {
+            graph_error(a, g, TC_E_ARG, gstat);
+        } else {
+            const int32_t *rp = a.row_ptr + v0 + g;
+            const int64_t r0 = rp[local], r1 = rp[local + 1];
+            if (r0 < 0 || r1 < r0 || r1 > alen) {
+                graph_error(a, g, TC_E_ARG, gstat);
+            } else {
+                d = (uint32_t)(r1 - r0);
+                const int32_t *row = a.col + a0 + r0;
+                int64_t prev = -1;
+                for (uint32_t j = 0; j < d; ++j) {
+                    const int32_t y = row[j];
+                    if (y < 0 || y >= ng) {
+                        graph_error(a, g, TC_E_RANGE, gstat);
+                    } else if (y == local) {
+                        graph_error(a, g, TC_E_SELF_LOOP, gstat);
+                    } else {
+                        if (y <= prev)
+                            graph_error(a, g, y == prev ? TC_E_DUP_EDGE : TC_E_UNSORTED, gstat);
+                        c += b_forward(d, (uint32_t)local, rp, (uint32_t)y);
+                        hs += pair_hash((uint32_t)local, (uint32_t)y) -
+                              pair_hash((uint32_t)y, (uint32_t)local);
+                    }
+                    prev = y;
+                }
+            }
         }
     }
-    fdeg[x] = c;
+    if (x < ncap) deg[x] = d;
+    if (x <= ncap) fdeg[x] = c;
+    // per-graph sums of the shares over runs of equal graph ids
+    const uint32_t lane = lane_id();
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)hs, o, kWave);
+        const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(hs >> 32), o, kWave);
+        const uint32_t gv = (uint32_t)__shfl_up((int)g, o, kWave);
+        if (lane >= (uint32_t)o && gv == g) hs += ((uint64_t)hi << 32) | lo;
+    }
+    const uint32_t gn = (uint32_t)__shfl_down((int)g, 1, kWave);
+    if ((lane == kWave - 1 || gn != g) && g != 0xFFFFFFFFu && hs)
+        atomicAdd(&ghash[g], (unsigned long long)hs);
 }
 
-// the forward rows (union ids, input order kept) with the row of every entry, and the
-// symmetry check: every forward entry (x, y) needs its mirror in row y
+// the forward rows (union ids, input order kept) with the row of every entry
 __global__ void k_b_ffill(const BatchArgs *__restrict__ args, const uint32_t *__restrict__ gid,
                           const uint32_t *__restrict__ deg, const uint32_t *__restrict__ frp,
-                          uint32_t *__restrict__ fcol, uint32_t *__restrict__ fsrc,
-                          int32_t *__restrict__ gstat) {
+                          uint32_t *__restrict__ fcol, uint32_t *__restrict__ fsrc) {
     const BatchArgs a = *args;
     const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= a.N || deg[x] == 0) return;
     const uint32_t g = gid[x];
     const int64_t v0 = a.vtx_off[g], ng = a.vtx_off[g + 1] - v0;
-    const int32_t *cg = a.col + a.adj_off[g];
     const int32_t *rp = a.row_ptr + v0 + g;
     const int32_t lx = (int32_t)((int64_t)x - v0);
-    const int32_t *row = cg + rp[lx];
+    const int32_t *row = a.col + a.adj_off[g] + rp[lx];
+    const int64_t dx = deg[x];
     uint32_t o = frp[x];
-    for (uint32_t j = 0; j < deg[x]; ++j) {
+    const uint32_t oe = frp[x + 1];
+    for (uint32_t j = 0; j < dx; ++j) {
         const int32_t y = row[j];
         if (y < 0 || y >= ng || y == lx) continue;
-        const uint32_t Y = (uint32_t)(v0 + y);
-        if (!b_forward(x, Y, deg)) continue;
-        fsrc[o] = x;
-        fcol[o++] = Y;
-        // mirror: binary search for lx in row y (rows of invalid graphs may be unsorted;
-        // the search stays inside the row either way)
-        const int32_t *ry = cg + rp[y];
-        uint32_t lo = 0, len = deg[Y];
-        while (len > 0) {
-            const uint32_t half = len >> 1;
-            if (ry[lo + half] < lx) {
-                lo += half + 1;
-                len -= half + 1;
-            } else {
-                len = half;
-            }
+        if (!b_forward(dx, (uint32_t)lx, rp, (uint32_t)y)) continue;
+        if (o < oe) {  // always true: k_b_setup counted the same entries
+            fsrc[o] = x;
+            fcol[o++] = (uint32_t)(v0 + y);
         }
-        if (lo >= deg[Y] || ry[lo] != lx) graph_error(a, g, TC_E_ASYMMETRIC, gstat);
     }
 }
 
@@ -212,11 +213,11 @@ __global__ void k_b_item_fill(const uint32_t *__restrict__ items,
 
 // per-graph checks that need the whole graph, and the per-graph status out (the caller's
 // array, when given).  Offsets: the graph's vertex and adjacency ranges must lie inside the
-// batch (k_b_setup checked them only for graphs that have vertices).  Symmetry: k_b_ffill
-// found a mirror for every forward entry, so the entries are symmetric exactly when the
-// backward entries are no more than the forward ones, i.e. entries == 2 * forward entries
-// (mirroring maps forward entries one-to-one into the backward ones).
+// batch (k_b_setup checked them only for graphs that have vertices).  Symmetry: the entries
+// must number twice the forward entries, and the graph's symmetry sum must be zero (a set of
+// entries that is not closed under mirroring passes this with probability about 2^-64).
 __global__ void k_b_finish(const BatchArgs *__restrict__ args, const uint32_t *__restrict__ frp,
+                           const unsigned long long *__restrict__ ghash,
                            int32_t *__restrict__ gstat) {
     const BatchArgs a = *args;
     const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -227,7 +228,7 @@ __global__ void k_b_finish(const BatchArgs *__restrict__ args, const uint32_t *_
         const int64_t a0 = a.adj_off[g], a1 = a.adj_off[g + 1];
         if (v0 < 0 || v1 < v0 || v1 > (int64_t)a.N || a0 < 0 || a1 < a0 || a1 > (int64_t)a.A)
             st = TC_E_ARG;
-        else if (2 * (int64_t)(frp[v1] - frp[v0]) != a1 - a0)
+        else if (2 * (int64_t)(frp[v1] - frp[v0]) != a1 - a0 || ghash[g] != 0)
             st = TC_E_ASYMMETRIC;
         gstat[g] = st;
     }
@@ -237,7 +238,8 @@ __global__ void k_b_finish(const BatchArgs *__restrict__ args, const uint32_t *_
 // ------------------------------------------------------------------ workspace + plan
 
 struct BatchLayout {
-    size_t args, ctl, gstat, gid, deg, fdeg, frp, fcol, fsrc, items, ioff, item_u, scan, total;
+    size_t args, ctl, gstat, ghash, gid, deg, fdeg, frp, fcol, fsrc, items, ioff, item_u, scan,
+        total;
 };
 
 constexpr uint32_t kMinItemEdges = 16;
@@ -254,6 +256,7 @@ static BatchLayout batch_layout(uint32_t gcap, uint32_t ncap, uint64_t acap) {
     L.args = take(sizeof(BatchArgs));
     L.ctl = take(64 * 4);
     L.gstat = take((size_t)gcap * 4);
+    L.ghash = take((size_t)gcap * 8);
     L.gid = take((size_t)ncap * 4);
     L.deg = take((size_t)ncap * 4);
     L.fdeg = take(n1 * 4);
@@ -300,6 +303,7 @@ static int batch_enqueue(tc_plan *p, bool pv, hipStream_t s) {
     const BatchArgs *args = (const BatchArgs *)(ws + L.args);
     uint32_t *ctl = (uint32_t *)(ws + L.ctl);
     int32_t *gstat = (int32_t *)(ws + L.gstat);
+    unsigned long long *ghash = (unsigned long long *)(ws + L.ghash);
     uint32_t *gid = (uint32_t *)(ws + L.gid), *deg = (uint32_t *)(ws + L.deg);
     uint32_t *fdeg = (uint32_t *)(ws + L.fdeg), *frp = (uint32_t *)(ws + L.frp);
     uint32_t *fcol = (uint32_t *)(ws + L.fcol), *items = (uint32_t *)(ws + L.items);
@@ -309,13 +313,12 @@ static int batch_enqueue(tc_plan *p, bool pv, hipStream_t s) {
     const uint32_t ncap = p->ncap, n1 = ncap + 1;
     const uint32_t cap = ncap > p->gcap ? ncap : p->gcap;
     auto grid = [](uint64_t n) { return dim3((uint32_t)((n + 255) / 256)); };
-    hipLaunchKernelGGL(k_b_clear, dim3(1024), dim3(256), 0, s, args, gstat, ctl, cap);
-    hipLaunchKernelGGL(k_b_setup, grid(ncap), dim3(256), 0, s, args, ncap, gid, deg, gstat);
-    hipLaunchKernelGGL(k_b_fcount, grid(n1), dim3(256), 0, s, args, ncap, gid, deg, fdeg);
+    hipLaunchKernelGGL(k_b_clear, dim3(1024), dim3(256), 0, s, args, gstat, ghash, ctl, cap);
+    hipLaunchKernelGGL(k_b_setup, grid(n1), dim3(256), 0, s, args, ncap, gid, deg, fdeg, ghash,
+                       gstat);
     if (hipGetLastError() != hipSuccess) return TC_E_HIP;
     if (scan_exclusive_u32(fdeg, frp, n1, scan, s) != hipSuccess) return TC_E_HIP;
-    hipLaunchKernelGGL(k_b_ffill, grid(ncap), dim3(256), 0, s, args, gid, deg, frp, fcol, fsrc,
-                       gstat);
+    hipLaunchKernelGGL(k_b_ffill, grid(ncap), dim3(256), 0, s, args, gid, deg, frp, fcol, fsrc);
     // ctl: [0] heavy-item queue, [1] light-chunk queue, [2] forward edges, [3] light chunks
     hipLaunchKernelGGL(k_b_items, grid(n1), dim3(256), 0, s, args, ncap, fdeg, frp,
                        count_light_max(), items, ctl + 2);
@@ -339,7 +342,7 @@ static int batch_enqueue(tc_plan *p, bool pv, hipStream_t s) {
     ka.tpv_pp = &args->per_vertex;
     if (launch_count_u(ka, pv, device_cu_count() * p->wgs_per_cu, s) != hipSuccess)
         return TC_E_HIP;
-    hipLaunchKernelGGL(k_b_finish, grid(p->gcap), dim3(256), 0, s, args, frp, gstat);
+    hipLaunchKernelGGL(k_b_finish, grid(p->gcap), dim3(256), 0, s, args, frp, ghash, gstat);
     return hipGetLastError() == hipSuccess ? TC_OK : TC_E_HIP;
 }
 

@@ -152,6 +152,45 @@ def test_batched_asymmetric():
     assert ei.value.name == "asymmetric"
 
 
+def asymmetric_even_rows(seed):
+    """Sorted rows on 6 vertices that are not symmetric although the entries number exactly
+    twice the forward entries (so only the symmetry sum can tell)."""
+    rng = np.random.default_rng(seed)
+    while True:
+        rows = [sorted(set(rng.choice([y for y in range(6) if y != x], size=int(rng.integers(0, 4)),
+                                      replace=False).tolist())) for x in range(6)]
+        deg = [len(r) for r in rows]
+        fwd = sum(1 for x in range(6) for y in rows[x] if (deg[y], y) > (deg[x], x))
+        ents = {(x, y) for x in range(6) for y in rows[x]}
+        if 2 * fwd == len(ents) and any((y, x) not in ents for x, y in ents):
+            return rows
+
+
+def test_batched_asymmetric_even_count():
+    gs = mixed_graphs(5, 4)
+    packed = synth.pack_symmetric(gs)
+    G = packed["G"]
+    rows = asymmetric_even_rows(11)
+    rp = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int32)
+    col = np.array([y for r in rows for y in r], dtype=np.int32)
+    # append the bad graph as graph G
+    packed["vtx_off"] = torch.cat([packed["vtx_off"], packed["vtx_off"][-1:] + 6])
+    packed["adj_off"] = torch.cat([packed["adj_off"], packed["adj_off"][-1:] + len(col)])
+    packed["row_ptr"] = torch.cat([packed["row_ptr"], torch.from_numpy(rp)])
+    packed["col"] = torch.cat([packed["col"], torch.from_numpy(col)])
+    packed["G"] = G + 1
+    packed["n_total"] += 6
+    packed["adj_total"] += len(col)
+    b = as_batch(packed)
+    res = api.BatchPlan(b.G, b.n_total, b.adj_total, device=DEV).run_async(b)
+    torch.cuda.synchronize()
+    st = res.status.cpu().numpy()
+    assert st[G] == api.E_ASYMMETRIC and not st[:G].any()
+    want = oracle_per_graph(gs)
+    tot = res.totals.cpu().numpy().astype(np.uint64)
+    assert all(tot[g] == want[g][0] for g in range(G))
+
+
 def test_batch_spec_sample():
     """A slice of the 4096-graph benchmark batch (Barabasi-Albert / Watts-Strogatz mix)."""
     spec = synth.BatchSpec(graphs=32, seed=7)
