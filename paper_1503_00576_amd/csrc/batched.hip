@@ -83,103 +83,232 @@ __device__ __forceinline__ uint64_t pair_hash(uint32_t x, uint32_t y) {
     return k;
 }
 
-// The degree of local vertex y of a graph: its row length in the input.  Both kernels that
-// take the forward decision read it from the same place, so they always agree.
-__device__ __forceinline__ bool b_forward(int64_t dx, uint32_t x, const int32_t *rp, uint32_t y) {
-    const int64_t dy = (int64_t)rp[y + 1] - rp[y];
-    return dy > dx || (dy == dx && y > x);
+// Per-vertex work over the input rows is done wave by wave: the wave takes 64 consecutive
+// vertices (lane k: vertex xb + k), whose rows are consecutive in the input, and walks their
+// entries 64 at a time, so that loads and stores are coalesced whatever the row lengths.
+// Entry idx of the walk belongs to the last lane k whose exclusive prefix off[k] <= idx.
+struct RowWalk {
+    uint32_t off[kWave + 1];  // exclusive prefix of the row lengths; off[64] = all entries
+    uint32_t ebeg[kWave];     // position of the row in the input's col
+    uint32_t len[kWave];      // row length (0 for rows that failed their checks)
+    uint32_t local[kWave];    // local vertex id
+    uint32_t rpb[kWave];      // index of the graph's row offsets in row_ptr
+    uint32_t ng[kWave];       // vertices of the graph
+    uint32_t g[kWave];        // graph
+    uint32_t acc[kWave];      // per-row count of forward entries (counted or written)
+    uint64_t hsum[kWave];     // per-row symmetry share
+};
+
+__device__ __forceinline__ uint32_t walk_owner(const RowWalk &rw, uint32_t idx) {
+    uint32_t k = 0;
+#pragma unroll
+    for (uint32_t step = 32; step; step >>= 1)
+        if (rw.off[k + step] <= idx) k += step;
+    return k;
 }
 
-// Per vertex (thread): graph id, degree (row length), forward out-degree (entries ncap.. stay
-// zero for the scan), checks of its row (offsets in range, ids in range, no self-loop, strictly
+// lanes a .. b (inclusive) of a wave
+__device__ __forceinline__ uint64_t lane_range(uint32_t a, uint32_t b) {
+    return ((2ull << b) - 1ull) & ~((1ull << a) - 1ull);
+}
+
+// inclusive sum over the lanes up to this one that hold the same key; keys must be
+// non-decreasing across the wave
+__device__ __forceinline__ uint64_t seg_sum_u64(uint64_t v, uint32_t key) {
+    const uint32_t lane = lane_id();
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)v, o, kWave);
+        const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(v >> 32), o, kWave);
+        const uint32_t kv = (uint32_t)__shfl_up((int)key, o, kWave);
+        if (lane >= (uint32_t)o && kv == key) v += ((uint64_t)hi << 32) | lo;
+    }
+    return v;
+}
+
+__device__ __forceinline__ bool seg_last(uint32_t key) {
+    const uint32_t kn = (uint32_t)__shfl_down((int)key, 1, kWave);
+    return lane_id() == kWave - 1 || kn != key;
+}
+
+// Loads the wave's 64 rows into `rw` (lane = vertex x) from already validated per-vertex
+// values; returns the number of entries.
+__device__ __forceinline__ uint32_t walk_begin(RowWalk &rw, uint32_t d, uint32_t ebeg,
+                                               uint32_t local, uint32_t rpb, uint32_t ng,
+                                               uint32_t g) {
+    const uint32_t lane = lane_id();
+    const uint32_t incl = wave_incl_scan(d);
+    const uint32_t total = wave_bcast(incl, kWave - 1);
+    rw.off[lane] = incl - d;
+    if (lane == 0) rw.off[kWave] = total;
+    rw.ebeg[lane] = ebeg;
+    rw.len[lane] = d;
+    rw.local[lane] = local;
+    rw.rpb[lane] = rpb;
+    rw.ng[lane] = ng;
+    rw.g[lane] = g;
+    rw.acc[lane] = 0;
+    rw.hsum[lane] = 0;
+    wave_lds_sync();
+    return total;
+}
+
+// One step of the walk: the entry of this lane (if any) with its owner k, its index j in the
+// row, its value y (local id), whether it is a forward entry of an in-range id (the same
+// test in both kernels: the degree of y is its row length in the input), and the lanes of
+// the owner's row in this step [first, last].
+struct WalkEntry {
+    bool valid, ok, fwd;
+    uint32_t k, j, first, last;
+    int32_t y;
+};
+
+__device__ __forceinline__ WalkEntry walk_entry(const RowWalk &rw, uint32_t base, uint32_t total,
+                                                const int32_t *__restrict__ col,
+                                                const int32_t *__restrict__ row_ptr) {
+    WalkEntry en;
+    const uint32_t lane = lane_id(), idx = base + lane;
+    en.valid = idx < total;
+    en.ok = en.fwd = false;
+    en.k = en.j = en.first = en.last = 0;
+    en.y = 0;
+    if (en.valid) {
+        const uint32_t k = walk_owner(rw, idx);
+        en.k = k;
+        en.j = idx - rw.off[k];
+        en.y = col[rw.ebeg[k] + en.j];
+        const uint32_t lk = rw.local[k];
+        en.ok = en.y >= 0 && (uint32_t)en.y < rw.ng[k] && (uint32_t)en.y != lk;
+        if (en.ok) {
+            const int32_t *rp = row_ptr + rw.rpb[k];
+            const int64_t dy = (int64_t)rp[en.y + 1] - rp[en.y], dx = rw.len[k];
+            en.fwd = dy > dx || (dy == dx && (uint32_t)en.y > lk);
+        }
+        const uint32_t rb = rw.off[k], re = rw.off[k] + rw.len[k];
+        en.first = (rb > base ? rb : base) - base;
+        en.last = (re < base + kWave ? re : base + kWave) - 1 - base;
+    }
+    return en;
+}
+
+// Per vertex: graph id, degree (row length), forward out-degree (entries ncap.. stay zero for
+// the scan), checks of its row (offsets in range, ids in range, no self-loop, strictly
 // ascending), and its share of the graph's symmetry sum: sum over the row's entries (x, y) of
 // pair_hash(x, y) - pair_hash(y, x), which is zero over a graph whose rows are symmetric.
-// Vertices are consecutive, so graph ids are non-decreasing across a wave and the shares are
-// summed per run of equal graph ids before one atomic per run.
-__global__ void k_b_setup(const BatchArgs *__restrict__ args, uint32_t ncap,
-                          uint32_t *__restrict__ gid, uint32_t *__restrict__ deg,
-                          uint32_t *__restrict__ fdeg, unsigned long long *__restrict__ ghash,
-                          int32_t *__restrict__ gstat) {
+// Graph ids are non-decreasing across a wave, so the shares are added per run of equal ids.
+__global__ __launch_bounds__(256) void k_b_setup(const BatchArgs *__restrict__ args,
+                                                 uint32_t ncap, uint32_t *__restrict__ gid,
+                                                 uint32_t *__restrict__ deg,
+                                                 uint32_t *__restrict__ fdeg,
+                                                 unsigned long long *__restrict__ ghash,
+                                                 int32_t *__restrict__ gstat) {
+    __shared__ RowWalk s_rw[4];
     const BatchArgs a = *args;
-    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t g = 0xFFFFFFFFu, d = 0, c = 0;
-    uint64_t hs = 0;
+    const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
+    RowWalk &rw = s_rw[w];
+    const uint32_t x = (blockIdx.x * 4 + w) * kWave + lane;
+    uint32_t g = 0xFFFFFFFFu, d = 0, ebeg = 0, local = 0, rpb = 0, ng = 0;
     if (x < a.N) {
         g = graph_of(a.vtx_off, a.G, x);
         gid[x] = g;
-        const int64_t v0 = a.vtx_off[g], ng = a.vtx_off[g + 1] - v0;
+        const int64_t v0 = a.vtx_off[g], n_g = a.vtx_off[g + 1] - v0;
         const int64_t a0 = a.adj_off[g], alen = a.adj_off[g + 1] - a0;
-        const int64_t local = (int64_t)x - v0;
+        const int64_t lx = (int64_t)x - v0;
         // offsets arrays must be prefix sums: check what this vertex relies on (the whole
         // vertex range of its graph, whose row offsets the forward test reads)
-        if (v0 < 0 || local < 0 || local >= ng || v0 + ng > (int64_t)a.N || a0 < 0 ||
-            alen < 0 || a0 + alen > (int64_t)a.A) {
+        if (v0 < 0 || lx < 0 || lx >= n_g || v0 + n_g > (int64_t)a.N || a0 < 0 || alen < 0 ||
+            a0 + alen > (int64_t)a.A) {
             graph_error(a, g, TC_E_ARG, gstat);
         } else {
             const int32_t *rp = a.row_ptr + v0 + g;
-            const int64_t r0 = rp[local], r1 = rp[local + 1];
+            const int64_t r0 = rp[lx], r1 = rp[lx + 1];
             if (r0 < 0 || r1 < r0 || r1 > alen) {
                 graph_error(a, g, TC_E_ARG, gstat);
             } else {
                 d = (uint32_t)(r1 - r0);
-                const int32_t *row = a.col + a0 + r0;
-                int64_t prev = -1;
-                for (uint32_t j = 0; j < d; ++j) {
-                    const int32_t y = row[j];
-                    if (y < 0 || y >= ng) {
-                        graph_error(a, g, TC_E_RANGE, gstat);
-                    } else if (y == local) {
-                        graph_error(a, g, TC_E_SELF_LOOP, gstat);
-                    } else {
-                        if (y <= prev)
-                            graph_error(a, g, y == prev ? TC_E_DUP_EDGE : TC_E_UNSORTED, gstat);
-                        c += b_forward(d, (uint32_t)local, rp, (uint32_t)y);
-                        hs += pair_hash((uint32_t)local, (uint32_t)y) -
-                              pair_hash((uint32_t)y, (uint32_t)local);
-                    }
-                    prev = y;
-                }
+                ebeg = (uint32_t)(a0 + r0);
+                local = (uint32_t)lx;
+                rpb = (uint32_t)(v0 + g);
+                ng = (uint32_t)n_g;
             }
         }
     }
-    if (x < ncap) deg[x] = d;
-    if (x <= ncap) fdeg[x] = c;
-    // per-graph sums of the shares over runs of equal graph ids
-    const uint32_t lane = lane_id();
-    for (int o = 1; o < kWave; o <<= 1) {
-        const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)hs, o, kWave);
-        const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(hs >> 32), o, kWave);
-        const uint32_t gv = (uint32_t)__shfl_up((int)g, o, kWave);
-        if (lane >= (uint32_t)o && gv == g) hs += ((uint64_t)hi << 32) | lo;
+    const uint32_t total = walk_begin(rw, d, ebeg, local, rpb, ng, g);
+    for (uint32_t base = 0; base < total; base += kWave) {
+        const WalkEntry en = walk_entry(rw, base, total, a.col, a.row_ptr);
+        uint64_t hd = 0;
+        if (en.valid) {
+            const uint32_t gk = rw.g[en.k], lk = rw.local[en.k];
+            if (!en.ok) {
+                graph_error(a, gk, (en.y < 0 || (uint32_t)en.y >= rw.ng[en.k]) ? TC_E_RANGE
+                                                                               : TC_E_SELF_LOOP,
+                            gstat);
+            } else {
+                if (en.j > 0) {
+                    const int32_t prev = a.col[rw.ebeg[en.k] + en.j - 1];
+                    if (en.y <= prev)
+                        graph_error(a, gk, en.y == prev ? TC_E_DUP_EDGE : TC_E_UNSORTED, gstat);
+                }
+                hd = pair_hash(lk, (uint32_t)en.y) - pair_hash((uint32_t)en.y, lk);
+            }
+        }
+        const uint64_t F = __ballot(en.valid && en.fwd);
+        // per-row totals of this step, added by the row's last lane in the step
+        const uint32_t key = en.valid ? en.k : kWave;
+        const uint64_t hrow = seg_sum_u64(hd, key);
+        if (en.valid && lane == en.last) {
+            rw.acc[en.k] += (uint32_t)__popcll(F & lane_range(en.first, lane));
+            rw.hsum[en.k] += hrow;
+        }
+        wave_lds_sync();
     }
-    const uint32_t gn = (uint32_t)__shfl_down((int)g, 1, kWave);
-    if ((lane == kWave - 1 || gn != g) && g != 0xFFFFFFFFu && hs)
-        atomicAdd(&ghash[g], (unsigned long long)hs);
+    if (x < ncap) deg[x] = d;
+    if (x <= ncap) fdeg[x] = rw.acc[lane];
+    // per-graph sums of the rows' shares over runs of equal graph ids
+    const uint64_t hs = seg_sum_u64(rw.hsum[lane], g);
+    if (seg_last(g) && g != 0xFFFFFFFFu && hs) atomicAdd(&ghash[g], (unsigned long long)hs);
 }
 
 // the forward rows (union ids, input order kept) with the row of every entry
-__global__ void k_b_ffill(const BatchArgs *__restrict__ args, const uint32_t *__restrict__ gid,
-                          const uint32_t *__restrict__ deg, const uint32_t *__restrict__ frp,
-                          uint32_t *__restrict__ fcol, uint32_t *__restrict__ fsrc) {
+__global__ __launch_bounds__(256) void k_b_ffill(const BatchArgs *__restrict__ args,
+                                                 const uint32_t *__restrict__ gid,
+                                                 const uint32_t *__restrict__ deg,
+                                                 const uint32_t *__restrict__ frp,
+                                                 uint32_t *__restrict__ fcol,
+                                                 uint32_t *__restrict__ fsrc) {
+    __shared__ RowWalk s_rw[4];
     const BatchArgs a = *args;
-    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= a.N || deg[x] == 0) return;
-    const uint32_t g = gid[x];
-    const int64_t v0 = a.vtx_off[g], ng = a.vtx_off[g + 1] - v0;
-    const int32_t *rp = a.row_ptr + v0 + g;
-    const int32_t lx = (int32_t)((int64_t)x - v0);
-    const int32_t *row = a.col + a.adj_off[g] + rp[lx];
-    const int64_t dx = deg[x];
-    uint32_t o = frp[x];
-    const uint32_t oe = frp[x + 1];
-    for (uint32_t j = 0; j < dx; ++j) {
-        const int32_t y = row[j];
-        if (y < 0 || y >= ng || y == lx) continue;
-        if (!b_forward(dx, (uint32_t)lx, rp, (uint32_t)y)) continue;
-        if (o < oe) {  // always true: k_b_setup counted the same entries
-            fsrc[o] = x;
-            fcol[o++] = (uint32_t)(v0 + y);
+    const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
+    RowWalk &rw = s_rw[w];
+    const uint32_t x = (blockIdx.x * 4 + w) * kWave + lane;
+    uint32_t g = 0xFFFFFFFFu, d = 0, ebeg = 0, local = 0, rpb = 0, ng = 0;
+    if (x < a.N && deg[x] > 0) {  // rows that passed k_b_setup's checks
+        g = gid[x];
+        const int64_t v0 = a.vtx_off[g];
+        const int32_t *rp = a.row_ptr + v0 + g;
+        local = (uint32_t)((int64_t)x - v0);
+        d = deg[x];
+        ebeg = (uint32_t)(a.adj_off[g] + rp[local]);
+        rpb = (uint32_t)(v0 + g);
+        ng = (uint32_t)(a.vtx_off[g + 1] - v0);
+    }
+    const uint32_t total = walk_begin(rw, d, ebeg, local, rpb, ng, g);
+    for (uint32_t base = 0; base < total; base += kWave) {
+        const WalkEntry en = walk_entry(rw, base, total, a.col, a.row_ptr);
+        const uint64_t F = __ballot(en.valid && en.fwd);
+        if (en.valid && en.fwd) {
+            const uint32_t xk = x - lane + en.k;
+            const uint32_t pos = frp[xk] + rw.acc[en.k] +
+                                 (uint32_t)__popcll(F & lane_range(en.first, lane) &
+                                                    ~(1ull << lane));
+            if (pos < frp[xk + 1]) {  // always true: k_b_setup counted the same entries
+                fsrc[pos] = xk;
+                fcol[pos] = rw.rpb[en.k] - rw.g[en.k] + (uint32_t)en.y;
+            }
         }
+        wave_lds_sync();  // every lane has read acc before the row's last lane adds to it
+        if (en.valid && lane == en.last)
+            rw.acc[en.k] += (uint32_t)__popcll(F & lane_range(en.first, lane));
+        wave_lds_sync();
     }
 }
 
@@ -314,11 +443,13 @@ static int batch_enqueue(tc_plan *p, bool pv, hipStream_t s) {
     const uint32_t cap = ncap > p->gcap ? ncap : p->gcap;
     auto grid = [](uint64_t n) { return dim3((uint32_t)((n + 255) / 256)); };
     hipLaunchKernelGGL(k_b_clear, dim3(1024), dim3(256), 0, s, args, gstat, ghash, ctl, cap);
-    hipLaunchKernelGGL(k_b_setup, grid(n1), dim3(256), 0, s, args, ncap, gid, deg, fdeg, ghash,
+    // one wave per 64 vertices, four waves per workgroup
+    auto vgrid = [](uint64_t n) { return dim3((uint32_t)((n + 255) / 256)); };
+    hipLaunchKernelGGL(k_b_setup, vgrid(n1), dim3(256), 0, s, args, ncap, gid, deg, fdeg, ghash,
                        gstat);
     if (hipGetLastError() != hipSuccess) return TC_E_HIP;
     if (scan_exclusive_u32(fdeg, frp, n1, scan, s) != hipSuccess) return TC_E_HIP;
-    hipLaunchKernelGGL(k_b_ffill, grid(ncap), dim3(256), 0, s, args, gid, deg, frp, fcol, fsrc);
+    hipLaunchKernelGGL(k_b_ffill, vgrid(ncap), dim3(256), 0, s, args, gid, deg, frp, fcol, fsrc);
     // ctl: [0] heavy-item queue, [1] light-chunk queue, [2] forward edges, [3] light chunks
     hipLaunchKernelGGL(k_b_items, grid(n1), dim3(256), 0, s, args, ncap, fdeg, frp,
                        count_light_max(), items, ctl + 2);
