@@ -96,7 +96,6 @@ struct RowWalk {
     uint32_t ng[kWave];       // vertices of the graph
     uint32_t g[kWave];        // graph
     uint32_t acc[kWave];      // per-row count of forward entries (counted or written)
-    uint64_t hsum[kWave];     // per-row symmetry share
 };
 
 __device__ __forceinline__ uint32_t walk_owner(const RowWalk &rw, uint32_t idx) {
@@ -110,24 +109,6 @@ __device__ __forceinline__ uint32_t walk_owner(const RowWalk &rw, uint32_t idx) 
 // lanes a .. b (inclusive) of a wave
 __device__ __forceinline__ uint64_t lane_range(uint32_t a, uint32_t b) {
     return ((2ull << b) - 1ull) & ~((1ull << a) - 1ull);
-}
-
-// inclusive sum over the lanes up to this one that hold the same key; keys must be
-// non-decreasing across the wave
-__device__ __forceinline__ uint64_t seg_sum_u64(uint64_t v, uint32_t key) {
-    const uint32_t lane = lane_id();
-    for (int o = 1; o < kWave; o <<= 1) {
-        const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)v, o, kWave);
-        const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(v >> 32), o, kWave);
-        const uint32_t kv = (uint32_t)__shfl_up((int)key, o, kWave);
-        if (lane >= (uint32_t)o && kv == key) v += ((uint64_t)hi << 32) | lo;
-    }
-    return v;
-}
-
-__device__ __forceinline__ bool seg_last(uint32_t key) {
-    const uint32_t kn = (uint32_t)__shfl_down((int)key, 1, kWave);
-    return lane_id() == kWave - 1 || kn != key;
 }
 
 // Loads the wave's 64 rows into `rw` (lane = vertex x) from already validated per-vertex
@@ -147,7 +128,6 @@ __device__ __forceinline__ uint32_t walk_begin(RowWalk &rw, uint32_t d, uint32_t
     rw.ng[lane] = ng;
     rw.g[lane] = g;
     rw.acc[lane] = 0;
-    rw.hsum[lane] = 0;
     wave_lds_sync();
     return total;
 }
@@ -233,9 +213,12 @@ __global__ __launch_bounds__(256) void k_b_setup(const BatchArgs *__restrict__ a
         }
     }
     const uint32_t total = walk_begin(rw, d, ebeg, local, rpb, ng, g);
+    // this lane's symmetry shares, for graph hg (the graphs of a lane's entries never
+    // decrease; a change flushes the sum)
+    uint32_t hg = 0xFFFFFFFFu;
+    uint64_t hsum = 0;
     for (uint32_t base = 0; base < total; base += kWave) {
         const WalkEntry en = walk_entry(rw, base, total, a.col, a.row_ptr);
-        uint64_t hd = 0;
         if (en.valid) {
             const uint32_t gk = rw.g[en.k], lk = rw.local[en.k];
             if (!en.ok) {
@@ -248,24 +231,30 @@ __global__ __launch_bounds__(256) void k_b_setup(const BatchArgs *__restrict__ a
                     if (en.y <= prev)
                         graph_error(a, gk, en.y == prev ? TC_E_DUP_EDGE : TC_E_UNSORTED, gstat);
                 }
-                hd = pair_hash(lk, (uint32_t)en.y) - pair_hash((uint32_t)en.y, lk);
+                if (gk != hg) {
+                    if (hsum) atomicAdd(&ghash[hg], (unsigned long long)hsum);
+                    hg = gk;
+                    hsum = 0;
+                }
+                hsum += pair_hash(lk, (uint32_t)en.y) - pair_hash((uint32_t)en.y, lk);
             }
         }
         const uint64_t F = __ballot(en.valid && en.fwd);
-        // per-row totals of this step, added by the row's last lane in the step
-        const uint32_t key = en.valid ? en.k : kWave;
-        const uint64_t hrow = seg_sum_u64(hd, key);
-        if (en.valid && lane == en.last) {
+        // forward entries per row in this step, added by the row's last lane in the step
+        if (en.valid && lane == en.last)
             rw.acc[en.k] += (uint32_t)__popcll(F & lane_range(en.first, lane));
-            rw.hsum[en.k] += hrow;
-        }
         wave_lds_sync();
     }
     if (x < ncap) deg[x] = d;
     if (x <= ncap) fdeg[x] = rw.acc[lane];
-    // per-graph sums of the rows' shares over runs of equal graph ids
-    const uint64_t hs = seg_sum_u64(rw.hsum[lane], g);
-    if (seg_last(g) && g != 0xFFFFFFFFu && hs) atomicAdd(&ghash[g], (unsigned long long)hs);
+    // the lanes' last sums: one atomic when they all belong to one graph (the usual case)
+    const uint32_t hg0 = wave_bcast(hg, 0);
+    if (__ballot(hsum != 0 && hg != hg0) == 0) {
+        const uint64_t hs = wave_sum_u64(hsum);
+        if (lane == 0 && hs) atomicAdd(&ghash[hg0], (unsigned long long)hs);
+    } else if (hsum) {
+        atomicAdd(&ghash[hg], (unsigned long long)hsum);
+    }
 }
 
 // the forward rows (union ids, input order kept) with the row of every entry

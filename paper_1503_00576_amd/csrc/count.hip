@@ -519,24 +519,25 @@ __device__ __forceinline__ uint32_t run_light(uint32_t eb, uint32_t e1,
                                               const uint32_t *__restrict__ frp,
                                               const uint32_t *__restrict__ fcol,
                                               const uint32_t *__restrict__ fsrc,
+                                              const uint32_t *__restrict__ gid,
                                               const uint32_t *win, uint32_t wbase,
                                               WaveScratch &ws,
-                                              unsigned long long *__restrict__ tpv) {
+                                              unsigned long long *__restrict__ tpv,
+                                              uint32_t &graph) {
     const uint32_t lane = lane_id();
     const uint32_t e = eb + lane;
     uint32_t b = 0, en = 0, lo = 0, d = 0, u = 0, v = 0;
-    if (e < e1) {
+    graph = 0xFFFFFFFFu;
+    if (e < e1) {  // two rounds of independent loads
         u = fsrc[e];
-        const uint32_t r0 = frp[u];
-        d = frp[u + 1] - r0;
-        if (d >= 2 && d <= kLightMax) {
-            v = fcol[e];
-            b = frp[v];
-            en = frp[v + 1];
-            lo = r0 - wbase;
-        } else {
-            d = 0;
-        }
+        v = fcol[e];
+        const uint32_t r0 = frp[u], r1 = frp[u + 1];
+        b = frp[v];
+        en = frp[v + 1];
+        graph = gid[u];
+        d = r1 - r0;
+        lo = r0 - wbase;
+        if (d < 2 || d > kLightMax) d = b = en = lo = 0;
     }
     const uint32_t a0 = b & ~3u;
     const uint32_t p = (d && en > b) ? (en - a0 + kPiece - 1) / kPiece : 0u;
@@ -689,15 +690,17 @@ __global__ __launch_bounds__(kThreads) void k_count_u(const BatchKernelArgs a) {
     WaveQueue<kClaimLight> lq;
     for (uint32_t q; lq.pop(a.queue + 1, n_chunks, q);) {
         const uint32_t e0 = q * chunk, e1 = min(e0 + chunk, mf);
-        const uint32_t wbase = e0 > kLightMax ? e0 - kLightMax : 0u;
-        const uint32_t wend = min(e1 + kLightMax, mf);
+        // the rows of the chunk's first and last edges, clipped to kLightMax entries around
+        // the chunk (a light row that meets the chunk lies inside)
+        const uint32_t rb = frp[a.fsrc[e0]], re = frp[a.fsrc[e1 - 1] + 1];
+        const uint32_t wbase = max(rb, e0 > kLightMax ? e0 - kLightMax : 0u);
+        const uint32_t wend = min(re, e1 + kLightMax);
         for (uint32_t i = wbase + lane; i < wend; i += kWave) mem[i - wbase] = fcol[i];
         wave_lds_sync();
         for (uint32_t eb = e0; eb < e1; eb += kWave) {
-            uint32_t h = run_light<PV>(eb, e1, frp, fcol, a.fsrc, mem, wbase, ws, tpv);
+            uint32_t g;
+            uint32_t h = run_light<PV>(eb, e1, frp, fcol, a.fsrc, a.gid, mem, wbase, ws, tpv, g);
             // per-graph sums over runs of equal graph ids (non-decreasing along the edges)
-            const uint32_t e = eb + lane;
-            const uint32_t g = e < e1 ? a.gid[a.fsrc[e]] : 0xFFFFFFFFu;
             for (int o = 1; o < kWave; o <<= 1) {
                 const uint32_t hv = (uint32_t)__shfl_up((int)h, o, kWave);
                 const uint32_t gv = (uint32_t)__shfl_up((int)g, o, kWave);
@@ -707,8 +710,8 @@ __global__ __launch_bounds__(kThreads) void k_count_u(const BatchKernelArgs a) {
             if ((lane == kWave - 1 || gn != g) && g != 0xFFFFFFFFu && h)
                 atomicAdd(&totals[g], (unsigned long long)h);
         }
-        for (uint32_t i = wbase + lane; i < wend; i += kWave) mem[i - wbase] = 0;
-        wave_lds_sync();
+        wave_lds_sync();  // the next chunk's window overwrites this one (nothing after the
+                          // light chunks needs a zeroed slice)
     }
 }
 
