@@ -203,10 +203,18 @@ def serve_section(dev, duration: float, rate: float, seed: int = 0):
         if time.perf_counter() - last_log > 10:
             log(f"serve: {srv.stats['completed']} completed")
             last_log = time.perf_counter()
+    import concurrent.futures as cf
+    pending, waited = set(futs), 0.0
+    while pending and waited < 240.0:
+        done, pending = cf.wait(pending, timeout=10.0)
+        waited += 10.0 if pending else 0.0
+        log(f"serve: {len(futs) - len(pending)} of {len(futs)} finished")
+    if pending:
+        raise RuntimeError(f"serve: {len(pending)} requests unfinished after the trace")
     lat, ok, failed = [], 0, 0
     for f in futs:
         try:
-            _, l = f.result(timeout=300)
+            _, l = f.result(timeout=0)
             lat.append(l)
             ok += 1
         except Exception:

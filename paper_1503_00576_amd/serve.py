@@ -33,7 +33,7 @@ class Request:
     arrival: float = field(default_factory=time.perf_counter)
 
 
-@dataclass
+@dataclass(eq=False)  # flights compare by identity (they hold tensors)
 class _Flight:
     reqs: list
     futures: list
@@ -67,6 +67,7 @@ class Server:
         self._resident_used = 0
         self._cv = threading.Condition()
         self._stop = False
+        self._failed = None
         self.stats = collections.Counter()
         self._thread = threading.Thread(target=self._loop, name="tc-serve", daemon=True)
         self._thread.start()
@@ -76,6 +77,9 @@ class Server:
     def submit(self, req: Request) -> Future:
         fut: Future = Future()
         with self._cv:
+            if self._failed is not None:
+                fut.set_exception(RuntimeError(f"tc-serve scheduler failed: {self._failed!r}"))
+                return fut
             self._pending.append((req, fut))
             self._cv.notify()
         return fut
@@ -123,6 +127,21 @@ class Server:
             del prep
 
     def _loop(self):
+        try:
+            self._schedule()
+        except BaseException as exc:  # never leave a caller waiting on a dead scheduler
+            with self._cv:
+                self._failed = exc
+                futs = [f for _, f in self._pending] + [f for fl in self._inflight
+                                                         for f in fl.futures]
+                self._pending.clear()
+                self._inflight.clear()
+            for f in futs:
+                if not f.done():
+                    f.set_exception(RuntimeError(f"tc-serve scheduler failed: {exc!r}"))
+            raise
+
+    def _schedule(self):
         torch.cuda.set_device(self.device)
         while True:
             with self._cv:
