@@ -35,6 +35,7 @@ namespace tc {
 
 constexpr uint32_t kPiece = 16;
 constexpr int kThreads = 512;
+constexpr int kWgsPerCu = 2;  // workgroups per CU the LDS footprint allows
 constexpr int kWaves = kThreads / kWave;
 constexpr uint32_t kLdsWords = 16384;                 // 64 KiB per workgroup
 constexpr uint32_t kSliceWords = kLdsWords / kWaves;  // 8 KiB per wave
@@ -732,12 +733,13 @@ uint32_t count_item_edges_wave() { return kItemEdgesWave; }
 uint32_t count_item_edges_block() { return kItemEdgesBlock; }
 uint32_t count_col_pad_bytes() { return kPiece * 4; }
 uint32_t count_panel() { return kPanel; }
+uint32_t count_wgs_per_cu() { return kWgsPerCu; }
 uint32_t count_light_max() { return kLightMax; }
 uint32_t count_light_chunk_max() { return kLightChunkMax; }
 uint32_t count_panel_ranks() { return kPanelRanks; }
 
 hipError_t launch_count(const CountArgs &x, bool per_vertex, hipStream_t s) {
-    const dim3 grid(device_cu_count() * 2), block(kThreads);
+    const dim3 grid(device_cu_count() * kWgsPerCu), block(kThreads);
     if (per_vertex)
         hipLaunchKernelGGL(k_count<true>, grid, block, 0, s, x.row_ptr, x.col, x.cptr, x.cbeg,
                            x.cend, x.cu, x.cmask, x.item_v_a, x.item_off_a, x.n_items_a,

@@ -110,6 +110,7 @@ uint32_t count_col_pad_bytes();
 // middle-vertex panels: consecutive ranks per panel, and the largest rank region the
 // counting kernel can handle as panels (its mask table must fit the workgroup's LDS)
 uint32_t count_panel();
+uint32_t count_wgs_per_cu();  // resident workgroups per CU of the counting kernels
 uint32_t count_panel_ranks();
 struct BatchKernelArgs {
     const uint32_t *frp, *fcol, *fsrc, *gid;
