@@ -168,28 +168,6 @@ struct OutEdgeSegs {  // u-centric kernel: the whole list N+(v) of out-neighbour
     __device__ __forceinline__ uint32_t mask(uint32_t) const { return 0u; }
 };
 
-// Piece q of the current batch: its owner k (the last segment whose first piece is <= q;
-// zero-piece segments share the offset of the next one and lose to it), its first position
-// in `col`, and its kPiece elements read with aligned 16-byte loads.
-__device__ __forceinline__ void piece_fetch(uint32_t q, const WaveScratch &ws,
-                                            const uint32_t *__restrict__ col, uint32_t &k,
-                                            uint32_t &start, uint32_t (&wv)[kPiece]) {
-    k = 0;
-#pragma unroll
-    for (uint32_t step = 32; step; step >>= 1)
-        if (ws.off[k + step] <= q) k += step;
-    start = ws.beg[k] + (q - ws.off[k]) * kPiece;
-    const uint4 *p4 = reinterpret_cast<const uint4 *>(col + start);
-#pragma unroll
-    for (uint32_t j = 0; j < kPiece / 4; ++j) {
-        const uint4 x = p4[j];
-        wv[4 * j] = x.x;
-        wv[4 * j + 1] = x.y;
-        wv[4 * j + 2] = x.z;
-        wv[4 * j + 3] = x.w;
-    }
-}
-
 // The calling wave streams segments [eb, min(eb + 64, e1)) of the current item through the
 // probe and returns this lane's hits.  PV: per-vertex accumulation -- LDS counters `tcnt`
 // indexed by the probe's position when `tcnt` is non-null, global atomics on `tpv` otherwise;
@@ -222,25 +200,27 @@ __device__ __forceinline__ uint32_t run_batch(uint32_t eb, uint32_t e1, const Se
     }
     wave_lds_sync();
     uint32_t hits_total = 0;
-    // Software pipeline: the loads of a lane's next piece are issued before its current piece
-    // is looked up, so that two pieces per lane are in flight (the kernel waits on memory).
-    uint32_t k = 0, start = 0;
-    uint32_t wv[kPiece];
-    bool have = lane < Q;
-    if (have) piece_fetch(lane, ws, col, k, start, wv);
     for (uint32_t q0 = 0; q0 < Q; q0 += kWave) {
-        const uint32_t qn = q0 + kWave + lane;
-        const bool have_n = qn < Q;
-        uint32_t kn = 0, startn = 0;
-        uint32_t wn[kPiece];
-        if (have_n) {
-            piece_fetch(qn, ws, col, kn, startn, wn);
-        } else {
+        const uint32_t q = q0 + lane;
+        if (q < Q) {
+            // owner: the last in-edge whose first piece is <= q (zero-piece lanes share the
+            // offset of the next lane and lose to it)
+            uint32_t k = 0;
 #pragma unroll
-            for (uint32_t i = 0; i < kPiece; ++i) wn[i] = 0;
-        }
-        if (have) {
+            for (uint32_t step = 32; step; step >>= 1)
+                if (ws.off[k + step] <= q) k += step;
+            const uint32_t start = ws.beg[k] + (q - ws.off[k]) * kPiece;
             const uint32_t first = ws.first[k], stop = ws.end[k];
+            const uint4 *p4 = reinterpret_cast<const uint4 *>(col + start);
+            uint32_t wv[kPiece];
+#pragma unroll
+            for (uint32_t j = 0; j < kPiece / 4; ++j) {
+                const uint4 x = p4[j];
+                wv[4 * j] = x.x;
+                wv[4 * j + 1] = x.y;
+                wv[4 * j + 2] = x.z;
+                wv[4 * j + 3] = x.w;
+            }
             uint32_t hits = 0;
             // element i of the piece belongs to the suffix iff start + i - first < stop - first
             const uint32_t rel0 = start - first, len = stop - first;
@@ -283,11 +263,6 @@ __device__ __forceinline__ uint32_t run_batch(uint32_t eb, uint32_t e1, const Se
             hits_total += hits;
             if (PV && hits) atomicAdd(&ws.cnt[k], hits);
         }
-        have = have_n;
-        k = kn;
-        start = startn;
-#pragma unroll
-        for (uint32_t i = 0; i < kPiece; ++i) wv[i] = wn[i];
     }
     wave_lds_sync();
     if (PV) {
