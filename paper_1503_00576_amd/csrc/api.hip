@@ -77,9 +77,7 @@ struct Layout {
 };
 
 // item spaces: [0] wave / [1] workgroup items for total counts, [2] / [3] for per-vertex counts
-// ctl words: status, forward-entry counter, workgroup-item queue, wave-item queues (one per
-// XCD, kXcds words from kCtlQueueA)
-enum { kCtlStatus = 0, kCtlBoth = 1, kCtlQueueB = 2, kCtlQueueA = 8, kCtlWords = 64 };
+enum { kCtlStatus = 0, kCtlBoth = 1, kCtlQueueA = 2, kCtlQueueB = 3, kCtlWords = 64 };
 constexpr uint32_t kPartTileEdges = 4096;  // edges per tile of the degree partition
 
 // Row blocks of the in-edge lists: contiguous CSR ranges of at most TC_ROW_BLOCK_BYTES of
@@ -381,7 +379,7 @@ static int run_count_prepared(void *ws, const Layout &L, hipStream_t s, uint64_t
         TC_LAUNCH_CHECK();
     }
     if (L.mf > 0) {
-        TC_HIP(fill_u32(ctl + kCtlQueueB, 0u, kCtlQueueA + kXcds - kCtlQueueB, s));
+        TC_HIP(fill_u32(ctl + kCtlQueueA, 0u, 2, s));
         const int a0 = pv ? 2 : 0, b0 = pv ? 3 : 1;
         CountArgs a;
         a.row_ptr = at<uint32_t>(ws, L.row_ptr);

@@ -292,7 +292,6 @@ struct WaveQueue {
     }
 };
 constexpr uint32_t kClaimWave = 8;     // middle-vertex kernel, wave items
-constexpr uint32_t kXcdChunk = 64;     // middle-vertex kernel: wave items per XCD chunk
 constexpr uint32_t kClaimBatched = 64;  // batched kernel, heavy items
 constexpr uint32_t kClaimLight = 4;     // batched kernel, light chunks
 
@@ -465,18 +464,8 @@ __global__ __launch_bounds__(kThreads) void k_count(
     // phase 2: wave items, each wave in its own LDS slice
     uint32_t *mem = s_mem + w * kSliceWords;
     const uint32_t n_items_a = *n_items_a_ptr;
-    // The wave queue is dealt out XCD by XCD in chunks of kXcdChunk consecutive items (chunk j
-    // to XCD j % kXcds, each XCD drawing from its own counter), so that neighbouring middle
-    // vertices, which share in-neighbours and hence suffixes, run under one L2.  Workgroup b
-    // runs on XCD b % kXcds (round-robin dispatch).
-    const uint32_t xcd = blockIdx.x % kXcds;
-    const uint32_t full = n_items_a / kXcdChunk, rem = n_items_a % kXcdChunk;
-    const uint32_t n_mine = (full > xcd ? (full - xcd + kXcds - 1) / kXcds : 0u) * kXcdChunk +
-                            (full % kXcds == xcd ? rem : 0u);
     WaveQueue<kClaimWave> wq;
-    for (uint32_t p; wq.pop(queue_a + xcd, n_mine, p);) {
-        const uint32_t chunk = (p / kXcdChunk) * kXcds + xcd;
-        uint32_t q = chunk * kXcdChunk + p % kXcdChunk;
+    for (uint32_t q; wq.pop(queue_a, n_items_a, q);) {
         q = n_items_a - 1 - q;
         const ItemRange it =
             item_range(q, kItemEdgesWave, n1, item_v_a, item_off_a, cptr, row_ptr);

@@ -93,7 +93,7 @@ struct CountArgs {
     const uint32_t *row_ptr, *col, *cptr, *cbeg, *cend, *cu, *cmask;
     const uint32_t *item_v_a, *item_off_a, *n_items_a;
     const uint32_t *item_v_b, *item_off_b, *n_items_b;
-    uint32_t *queue_a, *queue_b;  // queue_a: kXcds counters, one per XCD
+    uint32_t *queue_a, *queue_b;
     unsigned long long *total, *tpv;
     uint32_t n1;
     uint32_t p0;  // first rank of the panel region (n: no panels)
