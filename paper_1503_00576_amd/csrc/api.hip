@@ -36,7 +36,8 @@ __global__ void k_csc_final(const uint64_t *, uint32_t, uint64_t, const uint2 *,
                             const uint32_t *, uint32_t, const PanelGeom, uint32_t *, uint32_t *,
                             uint32_t *, uint64_t *, const int32_t *);
 __global__ void k_items(const uint32_t *, const uint32_t *, const uint32_t *, uint32_t, uint32_t,
-                        uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t *, uint32_t *,
+                        uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t *,
+                        uint32_t *,
                         uint32_t *, uint32_t *, const int32_t *);
 __global__ void k_item_fill(const uint32_t *, const uint32_t *, uint64_t, uint32_t *,
                             const int32_t *);
@@ -361,7 +362,8 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
                        at<uint32_t>(ws, L.cu), at<uint64_t>(ws, L.cmask), status);
     TC_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_items, dim3(grid_for(l1, 256)), dim3(256), 0, s, row_ptr, col, cnt, n,
-                       L.nblk, L.pg.pb, count_wave_span(false), count_wave_list(true),
+                       L.nblk, L.pg.pb, count_wave_span(false), count_wave_list(false),
+                       count_wave_list(true),
                        count_item_edges_wave(), count_item_edges_block(), items[0], items[1],
                        items[2], items[3], status);
     TC_LAUNCH_CHECK();

@@ -502,15 +502,25 @@ __global__ __launch_bounds__(kThreads) void k_count(
         if (!PV) {
             const uint32_t lo = col[it.r0];
             const uint32_t span = col[it.r0 + it.d - 1] - lo;
-            for (uint32_t i = lane; i < it.d; i += kWave) {
-                const uint32_t o = col[it.r0 + i] - lo;
-                atomicOr(&mem[o >> 5], 1u << (o & 31u));
+            if (span < kWaveBits) {  // bitmap over the span
+                for (uint32_t i = lane; i < it.d; i += kWave) {
+                    const uint32_t o = col[it.r0 + i] - lo;
+                    atomicOr(&mem[o >> 5], 1u << (o & 31u));
+                }
+                wave_lds_sync();
+                const BitmapProbe probe{mem, lo, span};
+                for (uint32_t eb = it.e0; eb < it.e1; eb += kWave)
+                    cnt += run_batch<false>(eb, it.e1, segs, col, probe, ws, nullptr, tpv);
+                for (uint32_t i = lane; i < it.d; i += kWave)
+                    mem[(col[it.r0 + i] - lo) >> 5] = 0;
+            } else {  // a wide span, but a list that fits the slice (see k_items)
+                for (uint32_t i = lane; i < it.d; i += kWave) mem[i] = col[it.r0 + i];
+                wave_lds_sync();
+                const ListProbe probe{mem, it.d};
+                for (uint32_t eb = it.e0; eb < it.e1; eb += kWave)
+                    cnt += run_batch<false>(eb, it.e1, segs, col, probe, ws, nullptr, tpv);
+                for (uint32_t i = lane; i < it.d; i += kWave) mem[i] = 0;
             }
-            wave_lds_sync();
-            const BitmapProbe probe{mem, lo, span};
-            for (uint32_t eb = it.e0; eb < it.e1; eb += kWave)
-                cnt += run_batch<false>(eb, it.e1, segs, col, probe, ws, nullptr, tpv);
-            for (uint32_t i = lane; i < it.d; i += kWave) mem[(col[it.r0 + i] - lo) >> 5] = 0;
             wave_lds_sync();
         } else {
             uint32_t *list = mem, *tc = mem + kWaveListPV;
@@ -757,7 +767,7 @@ hipError_t launch_count_u(const BatchKernelArgs &a, bool per_vertex, uint32_t gr
 // ------------------------------------------------------------------ host side
 
 uint32_t count_wave_span(bool per_vertex) { return per_vertex ? 0u : kWaveBits; }
-uint32_t count_wave_list(bool per_vertex) { return per_vertex ? kWaveListPV : 0u; }
+uint32_t count_wave_list(bool per_vertex) { return per_vertex ? kWaveListPV : kSliceWords; }
 uint32_t count_item_edges_wave() { return kItemEdgesWave; }
 uint32_t count_item_edges_block() { return kItemEdgesBlock; }
 uint32_t count_col_pad_bytes() { return kPiece * 4; }

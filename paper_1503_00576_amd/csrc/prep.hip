@@ -369,13 +369,14 @@ __global__ void k_csc_final(const uint64_t *__restrict__ keys, uint32_t mf, uint
 
 // Work items of the counting kernel.  A vertex's in-edges are cut into chunks; the chunks go
 // to the per-wave queue when the vertex's out-list fits one wave's LDS slice (as a bitmap over
-// its rank span, or for per-vertex counts as a list with counters), otherwise to the
-// per-workgroup queue.  Both classifications are prepared, so a prepared graph can be
-// counted either way.
-// Panel lists (first rank >= pb) always go to the per-workgroup queue.
+// its rank span or as a sorted list; for per-vertex counts as a list with counters),
+// otherwise to the per-workgroup queue.  Both classifications are prepared, so a prepared
+// graph can be counted either way.  Panel lists (first rank >= pb) always go to the
+// per-workgroup queue.
 __global__ void k_items(const uint32_t *__restrict__ row_ptr, const uint32_t *__restrict__ col,
                         const uint32_t *__restrict__ cnt, uint32_t n, uint32_t nblk, uint32_t pb,
-                        uint32_t wave_span, uint32_t wave_list_pv, uint32_t ka, uint32_t kb,
+                        uint32_t wave_span, uint32_t wave_list, uint32_t wave_list_pv,
+                        uint32_t ka, uint32_t kb,
                         uint32_t *__restrict__ ia, uint32_t *__restrict__ ib,
                         uint32_t *__restrict__ ia_pv, uint32_t *__restrict__ ib_pv,
                         const int32_t *__restrict__ status) {
@@ -391,7 +392,7 @@ __global__ void k_items(const uint32_t *__restrict__ row_ptr, const uint32_t *__
         const uint32_t r0 = row_ptr[v], d = row_ptr[v + 1] - r0;
         const uint32_t span = col[r0 + d - 1] - col[r0];
         const uint32_t na = (cnt[c] + ka - 1) / ka, nb = (cnt[c] + kb - 1) / kb;
-        if (span < wave_span) a = na; else b = nb;
+        if (span < wave_span || d <= wave_list) a = na; else b = nb;
         if (d <= wave_list_pv) apv = na; else bpv = nb;
     }
     ia[c] = a;
