@@ -28,10 +28,9 @@
  *     counting phase's in-edge lists into up to 8 row blocks of at most that many bytes of
  *     neighbour ids, worked through one after another.  TC_PANEL_RANKS (unset = the
  *     largest value the counting kernel supports, 16352; 0 = off) sets how many of the
- *     highest ranks of the order of Section 2.2 are counted as panels of consecutive middle
- *     vertices, TC_PANEL64_RANKS (unset = its maximum, 8188) how many of those form panels
- *     of 64 (the rest form panels of 32).  They change tc_workspace_size and must not change
- *     between a tc_preprocess and the calls that use its workspace.
+ *     highest ranks of the order of Section 2.2 are counted as panels of 32 consecutive
+ *     middle vertices.  Both change tc_workspace_size and must not change between a
+ *     tc_preprocess and the calls that use its workspace.
  */
 #ifndef TC_H
 #define TC_H

@@ -26,15 +26,16 @@ __global__ void k_csr(const uint64_t *, uint32_t, uint32_t, int, uint32_t *, uin
                       uint32_t *, uint32_t *, int32_t *);
 __global__ void k_rowlen(const uint32_t *, const uint32_t *, uint32_t, uint32_t *);
 __global__ void k_vrange(const uint32_t *, const uint32_t *, uint32_t, uint64_t *);
-__global__ void k_panel_range(const uint64_t *, const PanelGeom, uint32_t, uint64_t *);
+__global__ void k_panel_range(const uint64_t *, uint32_t, uint32_t, uint32_t, uint32_t,
+                              uint64_t *);
 __global__ void k_csc_keys(const uint32_t *, const uint32_t *, const uint32_t *, const uint64_t *,
-                           const uint64_t *, uint32_t, uint32_t, uint32_t, const PanelGeom,
+                           const uint64_t *, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t,
                            uint64_t *, uint2 *, const int32_t *);
 __global__ void k_csc_bounds(const uint64_t *, uint32_t, uint64_t, uint32_t *, uint32_t *,
                              const int32_t *);
 __global__ void k_csc_final(const uint64_t *, uint32_t, uint64_t, const uint2 *,
-                            const uint32_t *, uint32_t, const PanelGeom, uint32_t *, uint32_t *,
-                            uint32_t *, uint64_t *, const int32_t *);
+                            const uint32_t *, uint32_t, uint32_t, uint32_t, uint32_t *,
+                            uint32_t *, uint32_t *, uint32_t *, const int32_t *);
 __global__ void k_items(const uint32_t *, const uint32_t *, const uint32_t *, uint32_t, uint32_t,
                         uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t *,
                         uint32_t *,
@@ -72,8 +73,7 @@ struct Layout {
     uint32_t part_tiles;  // 0: degrees by atomics (inputs too large for the partition)
     int part_shift;
     uint32_t n, m, mf, kcap, id_bits, nblk;
-    PanelGeom pg;         // panel regions (see PanelGeom)
-    uint32_t panels;
+    uint32_t p0, panels;  // panel region: ranks [p0, n) in panels of count_panel() ranks
     uint64_t lists;       // in-edge lists: nblk * (n + 1)
 };
 
@@ -99,27 +99,14 @@ static uint32_t row_blocks_for(uint32_t n, uint32_t mf) {
 }
 
 // Middle-vertex panels over the top TC_PANEL_RANKS ranks (default and maximum: what the
-// counting kernel's LDS table holds with 32-bit masks; 0 switches panels off), the top
-// TC_PANEL64_RANKS of them (default and maximum: the 64-bit mask table) in panels of 64.
-static uint32_t env_cap(const char *name, uint32_t cap) {  // tuning / testing overrides
-    uint64_t x = cap;
-    if (const char *env = getenv(name)) {
+// counting kernel's LDS table holds; 0 switches panels off).
+static uint32_t panel_ranks_for(uint32_t n) {
+    uint64_t x = count_panel_ranks();
+    if (const char *env = getenv("TC_PANEL_RANKS")) {  // tuning / testing override
         unsigned long long v = strtoull(env, nullptr, 10);
         if (v < x) x = v;
     }
-    return (uint32_t)x;
-}
-
-static PanelGeom panel_geom_for(uint32_t n) {
-    uint32_t x = env_cap("TC_PANEL_RANKS", count_panel_ranks());
-    if (x > n) x = n;
-    uint32_t xa = env_cap("TC_PANEL64_RANKS", count_panel64_ranks());
-    if (xa > x) xa = x;
-    PanelGeom pg;
-    pg.n = n;
-    pg.pb = n - x;
-    pg.pa = n - xa;
-    return pg;
+    return (uint32_t)(x < n ? x : n);
 }
 
 static int id_bits_for(uint32_t n) {
@@ -144,8 +131,8 @@ static bool make_layout(int64_t n, int64_t m, uint32_t flags, Layout &L) {
     L.kcap = L.m > L.n ? L.m : L.n;
     L.id_bits = (uint32_t)id_bits_for(L.n);
     L.nblk = row_blocks_for(L.n, L.mf);
-    L.pg = panel_geom_for(L.n);
-    L.panels = L.pg.nb() + L.pg.na();
+    L.p0 = L.n - panel_ranks_for(L.n);
+    L.panels = ceil_div(L.n - L.p0, count_panel());
     const uint64_t n1 = (uint64_t)n + 1;
     L.lists = (uint64_t)L.nblk * n1;
     const uint64_t l1 = L.lists + 1;
@@ -191,7 +178,7 @@ static bool make_layout(int64_t n, int64_t m, uint32_t flags, Layout &L) {
     L.cbeg = take((size_t)L.mf * 4);
     L.cend = take((size_t)L.mf * 4);
     L.cu = take((size_t)L.mf * 4);
-    L.cmask = take((size_t)L.mf * 8);
+    L.cmask = take((size_t)L.mf * 4);
     for (int k = 0; k < 4; ++k) {
         const uint32_t per = (k & 1) ? count_item_edges_block() : count_item_edges_wave();
         L.items[k] = take(l1 * 4);
@@ -339,12 +326,12 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
     uint2 *eu = at<uint2>(ws, L.eu);
     uint64_t *pr = at<uint64_t>(ws, L.prange);
     if (L.panels) {
-        hipLaunchKernelGGL(k_panel_range, dim3(grid_for(L.panels, 256)), dim3(256), 0, s, vr,
-                           L.pg, L.panels, pr);
+        hipLaunchKernelGGL(k_panel_range, dim3(grid_for(L.panels, 256)), dim3(256), 0, s, vr, n,
+                           L.p0, count_panel(), L.panels, pr);
         TC_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL(k_csc_keys, dim3(grid_for(mf, 256)), dim3(256), 0, s, col, src, row_ptr, vr,
-                       pr, mf, n, L.nblk, L.pg, ck, eu, status);
+                       pr, mf, n, L.nblk, L.p0, count_panel(), ck, eu, status);
     TC_LAUNCH_CHECK();
     uint64_t *cks = ck;
     TC_HIP(sort_u64(ck, ck2, mf, 32, 32 + id_bits_for64(l1), sort_scr, status, s, &cks));
@@ -358,11 +345,12 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
     TC_LAUNCH_CHECK();
     TC_HIP(scan_exclusive_u32(cnt, cptr, l1, scan_scr, s));
     hipLaunchKernelGGL(k_csc_final, dim3(grid_for(mf, 256)), dim3(256), 0, s, cks, mf, L.lists,
-                       eu, col, n, L.pg, at<uint32_t>(ws, L.cbeg), at<uint32_t>(ws, L.cend),
-                       at<uint32_t>(ws, L.cu), at<uint64_t>(ws, L.cmask), status);
+                       eu, col, n, L.p0, count_panel(), at<uint32_t>(ws, L.cbeg),
+                       at<uint32_t>(ws, L.cend), at<uint32_t>(ws, L.cu),
+                       at<uint32_t>(ws, L.cmask), status);
     TC_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_items, dim3(grid_for(l1, 256)), dim3(256), 0, s, row_ptr, col, cnt, n,
-                       L.nblk, L.pg.pb, count_wave_span(false), count_wave_list(false),
+                       L.nblk, L.p0, count_wave_span(false), count_wave_list(false),
                        count_wave_list(true),
                        count_item_edges_wave(), count_item_edges_block(), items[0], items[1],
                        items[2], items[3], status);
@@ -402,7 +390,7 @@ static int run_count_prepared(void *ws, const Layout &L, hipStream_t s, uint64_t
         a.cbeg = at<uint32_t>(ws, L.cbeg);
         a.cend = at<uint32_t>(ws, L.cend);
         a.cu = at<uint32_t>(ws, L.cu);
-        a.cmask = at<uint64_t>(ws, L.cmask);
+        a.cmask = at<uint32_t>(ws, L.cmask);
         a.item_v_a = at<uint32_t>(ws, L.item_v[a0]);
         a.item_off_a = at<uint32_t>(ws, L.off[a0]);
         a.n_items_a = a.item_off_a + L.lists;
@@ -414,7 +402,7 @@ static int run_count_prepared(void *ws, const Layout &L, hipStream_t s, uint64_t
         a.total = total;
         a.tpv = tpv;
         a.n1 = n + 1;
-        a.pg = L.pg;
+        a.p0 = L.p0;
         a.status = status;
         TC_HIP(launch_count(a, pv, s));
     }

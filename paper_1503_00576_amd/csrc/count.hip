@@ -19,13 +19,12 @@
 //
 // Panels.  Most of the tests sit at the highest ranks (the highest degrees), where a list N+(u)
 // holds several consecutive middle vertices and its suffix would be streamed once for each.
-// The top ranks are therefore grouped into panels of consecutive middle vertices
-// P .. P + K - 1 (K = 64 over the very top, K = 32 below): a panel's table M in LDS holds,
-// for every rank w, the K-bit mask of the panel vertices whose out-list contains w, and a
-// segment is a pair (u, panel) with the mask R(u) of the panel vertices in N+(u).  Its suffix
-// after the first of them is streamed once and each element w adds popcount(M[w] & R(u)):
-// every panel vertex v with v in N+(u) and w in N+(v) closes one triangle (w > v holds
-// because w is in N+(v)).
+// The top ranks are therefore grouped into panels of kPanel consecutive middle vertices
+// P .. P + kPanel - 1: a panel's table M in LDS holds, for every rank w, the kPanel-bit mask
+// of the panel vertices whose out-list contains w, and a segment is a pair (u, panel) with
+// the mask R(u) of the panel vertices in N+(u).  Its suffix after the first of them is
+// streamed once and each element w adds popcount(M[w] & R(u)): every panel vertex v with
+// v in N+(u) and w in N+(v) closes one triangle (w > v holds because w is in N+(v)).
 //
 // Per-vertex counts (T(x) = triangles through x) use sorted lists in LDS instead of bitmaps
 // so that a hit's position indexes an LDS counter: T(w) for the third vertex is flushed once
@@ -47,10 +46,8 @@ constexpr uint32_t kBlockList = kLdsWords;            // workgroup sorted list
 constexpr uint32_t kBlockListPV = kLdsWords / 2;      // per-vertex: list + counters
 constexpr uint32_t kItemEdgesWave = 256;
 constexpr uint32_t kItemEdgesBlock = 2048;
-// panel mask tables, one mask per rank: 32-bit masks for panels of 32 (region B), 64-bit
-// masks for panels of 64 (region A), each filling the workgroup's LDS (with a zero pad entry)
-constexpr uint32_t kPanelRanks = kLdsWords - 32;
-constexpr uint32_t kPanel64Ranks = kLdsWords / 2 - 4;
+constexpr uint32_t kPanel = 32;                       // one bit per panel vertex in a mask
+constexpr uint32_t kPanelRanks = kLdsWords - 32;      // mask table: one word per rank
 // batched kernel: rows with at most kLightMax forward entries are counted edge by edge; a
 // chunk of forward edges plus kLightMax entries on either side must fit one wave's slice
 constexpr uint32_t kLightMax = 256;
@@ -73,21 +70,15 @@ struct BitmapProbe {
     static constexpr bool kMasked = false;
 };
 
-// Panel table M over ranks [lo, lo + span]: entry w - lo holds the mask of the panel vertices
-// whose out-list contains w (T: 32- or 64-bit masks).  Entry span + 1 is always zero, so
-// out-of-range ids clamp onto it.
-template <class T>
+// Panel table M over ranks [lo, lo + span]: word w - lo holds the mask of the panel vertices
+// whose out-list contains w.  Word span + 1 is always zero, so out-of-range ids clamp onto it.
 struct PanelProbe {
-    const T *m;
+    const uint32_t *m;
     uint32_t lo, span;
     static constexpr bool kBranchFree = true;
     static constexpr bool kMasked = true;
-    __device__ __forceinline__ uint32_t count(uint32_t w, uint64_t r) const {
-        const T x = m[min(w - lo, span + 1u)];
-        if constexpr (sizeof(T) == 8)
-            return (uint32_t)__popcll(x & r);
-        else
-            return (uint32_t)__popc(x & (uint32_t)r);
+    __device__ __forceinline__ uint32_t count(uint32_t w, uint32_t r) const {
+        return __popc(m[min(w - lo, span + 1u)] & r);
     }
 };
 
@@ -116,9 +107,8 @@ struct ListProbe {  // sorted list in LDS or in global memory
 
 // ------------------------------------------------------------------ per-batch streaming
 
-struct WaveScratch {  // tag: the segment's owner (per-vertex counts) or its panel mask (low
-                     // half; high half in aux); the batched kernel's light segments keep
-                     // their N+(u) in tag and aux
+struct WaveScratch {  // tag: the segment's owner (per-vertex counts) or its panel mask;
+                     // the batched kernel's light segments keep their N+(u) in tag and aux
     uint32_t off[kWave], beg[kWave], first[kWave], end[kWave], cnt[kWave], tag[kWave],
         aux[kWave];
 };
@@ -132,20 +122,19 @@ struct InEdgeSegs {  // middle-vertex kernel: suffix of N+(u) after v, owner u
         en = cend[e];
     }
     __device__ __forceinline__ uint32_t owner(uint32_t e) const { return cu[e]; }
-    __device__ __forceinline__ uint64_t mask(uint32_t) const { return 0u; }
+    __device__ __forceinline__ uint32_t mask(uint32_t) const { return 0u; }
 };
 
 // Panel segment (u, panel): the suffix of N+(u) after u's first panel vertex, tagged with the
 // mask R(u) of u's panel vertices.
 struct PanelSegs {
-    const uint32_t *cbeg, *cend;
-    const uint64_t *cmask;
+    const uint32_t *cbeg, *cend, *cmask;
     __device__ __forceinline__ void get(uint32_t e, uint32_t &b, uint32_t &en) const {
         b = cbeg[e];
         en = cend[e];
     }
     __device__ __forceinline__ uint32_t owner(uint32_t) const { return 0u; }
-    __device__ __forceinline__ uint64_t mask(uint32_t e) const { return cmask[e]; }
+    __device__ __forceinline__ uint32_t mask(uint32_t e) const { return cmask[e]; }
 };
 
 // Per-vertex counts over a panel, one panel vertex P + j at a time: segment (u, panel) stands
@@ -153,20 +142,19 @@ struct PanelSegs {
 // N+(u) starting right before cbeg, so the suffix after P + j starts popcount(R(u) below j)
 // elements later; segments without bit j are empty.
 struct PanelVertexSegs {
-    const uint32_t *cbeg, *cend, *cu;
-    const uint64_t *cmask;
+    const uint32_t *cbeg, *cend, *cu, *cmask;
     uint32_t j;
     __device__ __forceinline__ void get(uint32_t e, uint32_t &b, uint32_t &en) const {
-        const uint64_t r = cmask[e];
+        const uint32_t r = cmask[e];
         b = 0;
         en = 0;
-        if ((r >> j) & 1ull) {
-            b = cbeg[e] + (uint32_t)__popcll(r & ((1ull << j) - 1ull));
+        if ((r >> j) & 1u) {
+            b = cbeg[e] + __popc(r & ((1u << j) - 1u));
             en = cend[e];
         }
     }
     __device__ __forceinline__ uint32_t owner(uint32_t e) const { return cu[e]; }
-    __device__ __forceinline__ uint64_t mask(uint32_t) const { return 0u; }
+    __device__ __forceinline__ uint32_t mask(uint32_t) const { return 0u; }
 };
 
 struct OutEdgeSegs {  // u-centric kernel: the whole list N+(v) of out-neighbour v, owner v
@@ -177,7 +165,7 @@ struct OutEdgeSegs {  // u-centric kernel: the whole list N+(v) of out-neighbour
         en = row_ptr[v + 1];
     }
     __device__ __forceinline__ uint32_t owner(uint32_t e) const { return col[e]; }
-    __device__ __forceinline__ uint64_t mask(uint32_t) const { return 0u; }
+    __device__ __forceinline__ uint32_t mask(uint32_t) const { return 0u; }
 };
 
 // The calling wave streams segments [eb, min(eb + 64, e1)) of the current item through the
@@ -208,9 +196,7 @@ __device__ __forceinline__ uint32_t run_batch(uint32_t eb, uint32_t e1, const Se
         ws.cnt[lane] = 0;
         ws.tag[lane] = valid ? segs.owner(e) : 0u;
     } else if (Probe::kMasked) {
-        const uint64_t r = valid ? segs.mask(e) : 0ull;
-        ws.tag[lane] = (uint32_t)r;
-        ws.aux[lane] = (uint32_t)(r >> 32);
+        ws.tag[lane] = valid ? segs.mask(e) : 0u;
     }
     wave_lds_sync();
     uint32_t hits_total = 0;
@@ -240,7 +226,7 @@ __device__ __forceinline__ uint32_t run_batch(uint32_t eb, uint32_t e1, const Se
             const uint32_t rel0 = start - first, len = stop - first;
             if constexpr (!PV && Probe::kMasked) {
                 // hits of element i: panel vertices of the owner whose lists hold it
-                const uint64_t r = ((uint64_t)ws.aux[k] << 32) | ws.tag[k];
+                const uint32_t r = ws.tag[k];
                 const uint32_t lo_i = first > start ? first - start : 0u;
                 const uint32_t hi_i = min(stop - start, kPiece);
 #pragma unroll
@@ -337,14 +323,14 @@ __global__ __launch_bounds__(kThreads) void k_count(
     const uint32_t *__restrict__ row_ptr, const uint32_t *__restrict__ col,
     const uint32_t *__restrict__ cptr, const uint32_t *__restrict__ cbeg,
     const uint32_t *__restrict__ cend, const uint32_t *__restrict__ cu,
-    const uint64_t *__restrict__ cmask, const uint32_t *__restrict__ item_v_a,
+    const uint32_t *__restrict__ cmask, const uint32_t *__restrict__ item_v_a,
     const uint32_t *__restrict__ item_off_a, const uint32_t *__restrict__ n_items_a_ptr,
     const uint32_t *__restrict__ item_v_b, const uint32_t *__restrict__ item_off_b,
     const uint32_t *__restrict__ n_items_b_ptr, uint32_t *__restrict__ queue_a,
     uint32_t *__restrict__ queue_b, unsigned long long *__restrict__ total,
-    unsigned long long *__restrict__ tpv, uint32_t n1, const PanelGeom pg,
+    unsigned long long *__restrict__ tpv, uint32_t n1, uint32_t p0,
     const int32_t *__restrict__ status) {
-    __shared__ __align__(16) uint32_t s_mem[kLdsWords];
+    __shared__ uint32_t s_mem[kLdsWords];
     __shared__ WaveScratch s_ws[kWaves];
     __shared__ uint32_t s_item;
     if (*status) return;
@@ -366,30 +352,15 @@ __global__ __launch_bounds__(kThreads) void k_count(
         const ItemRange it =
             item_range(q, kItemEdgesBlock, n1, item_v_b, item_off_b, cptr, row_ptr);
         const uint32_t first = it.e0 + w * kWave, step = kWaves * kWave;
-        if (it.v >= pg.pb) {  // a panel of middle vertices P = it.v, ...
-            const uint32_t P = it.v, np = pg.end(P) - P;
-            const PanelSegs psegs{cbeg, cend, cmask};
-            if (!PV && P >= pg.pa) {  // 64 panel vertices: 64-bit masks
-                unsigned long long *m = reinterpret_cast<unsigned long long *>(s_mem);
-                for (uint32_t j = w; j < np; j += kWaves)
-                    for (uint32_t i = row_ptr[P + j] + lane; i < row_ptr[P + j + 1]; i += kWave)
-                        atomicOr(&m[col[i] - P], 1ull << j);
-                __syncthreads();
-                const PanelProbe<unsigned long long> probe{m, P, n1 - 2 - P};
-                uint32_t cnt = 0;
-                for (uint32_t eb = first; eb < it.e1; eb += step)
-                    cnt += run_batch<false>(eb, it.e1, psegs, col, probe, ws, nullptr, tpv);
-                acc += cnt;
-                __syncthreads();
-                for (uint32_t j = w; j < np; j += kWaves)
-                    for (uint32_t i = row_ptr[P + j] + lane; i < row_ptr[P + j + 1]; i += kWave)
-                        m[col[i] - P] = 0ull;
-            } else if (!PV) {  // 32 panel vertices: 32-bit masks
+        if (it.v >= p0) {  // a panel of middle vertices P = it.v, ...
+            const uint32_t P = it.v, np = min(kPanel, n1 - 1 - P);
+            if (!PV) {
                 for (uint32_t j = w; j < np; j += kWaves)
                     for (uint32_t i = row_ptr[P + j] + lane; i < row_ptr[P + j + 1]; i += kWave)
                         atomicOr(&s_mem[col[i] - P], 1u << j);
                 __syncthreads();
-                const PanelProbe<uint32_t> probe{s_mem, P, n1 - 2 - P};
+                const PanelProbe probe{s_mem, P, n1 - 2 - P};
+                const PanelSegs psegs{cbeg, cend, cmask};
                 uint32_t cnt = 0;
                 for (uint32_t eb = first; eb < it.e1; eb += step)
                     cnt += run_batch<false>(eb, it.e1, psegs, col, probe, ws, nullptr, tpv);
@@ -771,7 +742,7 @@ uint32_t count_wave_list(bool per_vertex) { return per_vertex ? kWaveListPV : kS
 uint32_t count_item_edges_wave() { return kItemEdgesWave; }
 uint32_t count_item_edges_block() { return kItemEdgesBlock; }
 uint32_t count_col_pad_bytes() { return kPiece * 4; }
-uint32_t count_panel64_ranks() { return kPanel64Ranks; }
+uint32_t count_panel() { return kPanel; }
 uint32_t count_wgs_per_cu() { return kWgsPerCu; }
 uint32_t count_light_max() { return kLightMax; }
 uint32_t count_light_chunk_max() { return kLightChunkMax; }
@@ -783,12 +754,12 @@ hipError_t launch_count(const CountArgs &x, bool per_vertex, hipStream_t s) {
         hipLaunchKernelGGL(k_count<true>, grid, block, 0, s, x.row_ptr, x.col, x.cptr, x.cbeg,
                            x.cend, x.cu, x.cmask, x.item_v_a, x.item_off_a, x.n_items_a,
                            x.item_v_b, x.item_off_b, x.n_items_b, x.queue_a, x.queue_b, x.total,
-                           x.tpv, x.n1, x.pg, x.status);
+                           x.tpv, x.n1, x.p0, x.status);
     else
         hipLaunchKernelGGL(k_count<false>, grid, block, 0, s, x.row_ptr, x.col, x.cptr, x.cbeg,
                            x.cend, x.cu, x.cmask, x.item_v_a, x.item_off_a, x.n_items_a,
                            x.item_v_b, x.item_off_b, x.n_items_b, x.queue_a, x.queue_b, x.total,
-                           x.tpv, x.n1, x.pg, x.status);
+                           x.tpv, x.n1, x.p0, x.status);
     return hipGetLastError();
 }
 

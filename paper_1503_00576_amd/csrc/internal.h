@@ -89,36 +89,14 @@ hipError_t fill_u32(uint32_t *p, uint32_t value, uint64_t count, hipStream_t s);
 int device_cu_count();
 
 // counting kernels (count.hip)
-// Panels of middle vertices over the top ranks of the order: region B = ranks [pb, pa) in
-// panels of 32, region A = ranks [pa, n) in panels of 64 (pb <= pa <= n; pb = n: no panels).
-// A panel is named by its first rank; region B's last panel ends at pa.
-struct PanelGeom {
-    uint32_t pb, pa, n;
-    __host__ __device__ uint32_t nb() const { return (pa - pb + 31u) / 32u; }
-    __host__ __device__ uint32_t na() const { return (n - pa + 63u) / 64u; }
-    __host__ __device__ uint32_t start(uint32_t v) const {  // v >= pb
-        return v >= pa ? pa + ((v - pa) & ~63u) : pb + ((v - pb) & ~31u);
-    }
-    __host__ __device__ uint32_t index(uint32_t v) const {  // v >= pb; region B first
-        return v >= pa ? nb() + (v - pa) / 64u : (v - pb) / 32u;
-    }
-    __host__ __device__ uint32_t first_of(uint32_t i) const {  // panel i's first rank
-        return i < nb() ? pb + 32u * i : pa + 64u * (i - nb());
-    }
-    __host__ __device__ uint32_t end(uint32_t P) const {  // one past P's panel
-        return P >= pa ? (P + 64u < n ? P + 64u : n) : (P + 32u < pa ? P + 32u : pa);
-    }
-};
-
 struct CountArgs {
-    const uint32_t *row_ptr, *col, *cptr, *cbeg, *cend, *cu;
-    const uint64_t *cmask;
+    const uint32_t *row_ptr, *col, *cptr, *cbeg, *cend, *cu, *cmask;
     const uint32_t *item_v_a, *item_off_a, *n_items_a;
     const uint32_t *item_v_b, *item_off_b, *n_items_b;
     uint32_t *queue_a, *queue_b;
     unsigned long long *total, *tpv;
     uint32_t n1;
-    PanelGeom pg;  // the panel regions
+    uint32_t p0;  // first rank of the panel region (n: no panels)
     const int32_t *status;
 };
 hipError_t launch_count(const CountArgs &a, bool per_vertex, hipStream_t s);
@@ -129,11 +107,11 @@ uint32_t count_item_edges_block();
 // bytes of padding `col` needs after its last element: a lane's aligned piece reads may run
 // up to one piece past the end of a list
 uint32_t count_col_pad_bytes();
-// middle-vertex panels: the largest rank regions the counting kernel can handle with 32-bit
-// and with 64-bit masks (its mask table, one mask per rank, must fit the workgroup's LDS)
-uint32_t count_panel_ranks();
-uint32_t count_panel64_ranks();
+// middle-vertex panels: consecutive ranks per panel, and the largest rank region the
+// counting kernel can handle as panels (its mask table must fit the workgroup's LDS)
+uint32_t count_panel();
 uint32_t count_wgs_per_cu();  // resident workgroups per CU of the counting kernels
+uint32_t count_panel_ranks();
 struct BatchKernelArgs {
     const uint32_t *frp, *fcol, *fsrc, *gid;
     const uint32_t *item_u, *item_off, *n_items;  // heavy items

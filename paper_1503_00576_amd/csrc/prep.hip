@@ -266,13 +266,13 @@ __global__ void k_vrange(const uint32_t *__restrict__ row_ptr, const uint32_t *_
     vr[v] = r1 > r0 ? ((uint64_t)col[r0] << 32) | col[r1 - 1] : 0xFFFFFFFF00000000ull;
 }
 
-// Rank span of the union of the out-lists of every panel (panel i of the geometry), in the
-// format of k_vrange.
-__global__ void k_panel_range(const uint64_t *__restrict__ vr, const PanelGeom pg,
-                              uint32_t panels, uint64_t *__restrict__ pr) {
+// Rank span of the union of the out-lists of every panel (ranks p0 + i * kp .. + kp - 1), in
+// the format of k_vrange.
+__global__ void k_panel_range(const uint64_t *__restrict__ vr, uint32_t n, uint32_t p0,
+                              uint32_t kp, uint32_t panels, uint64_t *__restrict__ pr) {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= panels) return;
-    const uint32_t P = pg.first_of(i), pe = pg.end(P);
+    const uint32_t P = p0 + i * kp, pe = min(P + kp, n);
     uint32_t lo = 0xFFFFFFFFu, hi = 0;
     for (uint32_t v = P; v < pe; ++v) {
         const uint64_t r = vr[v];
@@ -290,13 +290,13 @@ __global__ void k_panel_range(const uint64_t *__restrict__ vr, const PanelGeom p
 // overlap that of N+(v).  Such in-edges are keyed by their list c = row block * (n + 1) + v
 // (row blocks: contiguous CSR ranges, see the host code), the others by `lists` (sorted last);
 // the low 32 bits hold e, so a stable sort on the list bits groups every list in CSR order.
-// From rank pg.pb on, middle vertices form panels of consecutive ranks with one list per
+// From rank p0 on, middle vertices form panels of kp consecutive ranks with one list per
 // panel, keyed by its first rank P: only the first in-edge of each run of u's out-neighbours
 // inside the panel is kept (it stands for the whole run), tested against the panel's span.
 __global__ void k_csc_keys(const uint32_t *__restrict__ col, const uint32_t *__restrict__ src,
                            const uint32_t *__restrict__ row_ptr,
                            const uint64_t *__restrict__ vr, const uint64_t *__restrict__ pr,
-                           uint32_t mf, uint32_t n, uint32_t nblk, const PanelGeom pg,
+                           uint32_t mf, uint32_t n, uint32_t nblk, uint32_t p0, uint32_t kp,
                            uint64_t *__restrict__ keys, uint2 *__restrict__ eu,
                            const int32_t *__restrict__ status) {
     if (*status) return;
@@ -308,10 +308,11 @@ __global__ void k_csc_keys(const uint32_t *__restrict__ col, const uint32_t *__r
     if (e + 1 < end_u) {
         uint32_t list = v;
         uint64_t r = vr[v];
-        if (v >= pg.pb) {
-            list = pg.start(v);
+        if (v >= p0) {
+            const uint32_t i = (v - p0) / kp;
+            list = p0 + i * kp;
             const bool run_start = e == row_ptr[u] || col[e - 1] < list;
-            r = run_start ? pr[pg.index(v)] : 0xFFFFFFFF00000000ull;
+            r = run_start ? pr[i] : 0xFFFFFFFF00000000ull;
         }
         const uint32_t lo = (uint32_t)(r >> 32), hi = (uint32_t)r;
         if (lo <= hi && col[e + 1] <= hi && col[end_u - 1] >= lo)
@@ -335,13 +336,13 @@ __global__ void k_csc_bounds(const uint64_t *__restrict__ keys, uint32_t mf, uin
 }
 
 // the lists themselves: in-edge u -> v at CSR position e contributes the suffix [e + 1, end_u);
-// for a panel list (first rank P >= pg.pb) also the mask of u's run of panel vertices, which
+// for a panel list (first rank P >= p0) also the mask of u's run of panel vertices, which
 // starts at e
 __global__ void k_csc_final(const uint64_t *__restrict__ keys, uint32_t mf, uint64_t lists,
                             const uint2 *__restrict__ eu, const uint32_t *__restrict__ col,
-                            uint32_t n, const PanelGeom pg, uint32_t *__restrict__ cbeg,
+                            uint32_t n, uint32_t p0, uint32_t kp, uint32_t *__restrict__ cbeg,
                             uint32_t *__restrict__ cend, uint32_t *__restrict__ cu,
-                            uint64_t *__restrict__ cmask, const int32_t *__restrict__ status) {
+                            uint32_t *__restrict__ cmask, const int32_t *__restrict__ status) {
     if (*status) return;
     uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= mf) return;
@@ -354,14 +355,13 @@ __global__ void k_csc_final(const uint64_t *__restrict__ keys, uint32_t mf, uint
     cend[j] = x.x;
     cu[j] = x.y;
     const uint32_t P = (uint32_t)(c % ((uint64_t)n + 1));
-    uint64_t r = 1ull;
-    if (P >= pg.pb) {
-        const uint32_t pe = pg.end(P);
+    uint32_t r = 1u;
+    if (P >= p0) {
         r = 0;
         for (uint32_t i = e; i < x.x; ++i) {
             const uint32_t w = col[i];
-            if (w >= pe) break;
-            r |= 1ull << (w - P);
+            if (w >= P + kp) break;
+            r |= 1u << (w - P);
         }
     }
     cmask[j] = r;
@@ -371,10 +371,10 @@ __global__ void k_csc_final(const uint64_t *__restrict__ keys, uint32_t mf, uint
 // to the per-wave queue when the vertex's out-list fits one wave's LDS slice (as a bitmap over
 // its rank span or as a sorted list; for per-vertex counts as a list with counters),
 // otherwise to the per-workgroup queue.  Both classifications are prepared, so a prepared
-// graph can be counted either way.  Panel lists (first rank >= pb) always go to the
+// graph can be counted either way.  Panel lists (first rank >= p0) always go to the
 // per-workgroup queue.
 __global__ void k_items(const uint32_t *__restrict__ row_ptr, const uint32_t *__restrict__ col,
-                        const uint32_t *__restrict__ cnt, uint32_t n, uint32_t nblk, uint32_t pb,
+                        const uint32_t *__restrict__ cnt, uint32_t n, uint32_t nblk, uint32_t p0,
                         uint32_t wave_span, uint32_t wave_list, uint32_t wave_list_pv,
                         uint32_t ka, uint32_t kb,
                         uint32_t *__restrict__ ia, uint32_t *__restrict__ ib,
@@ -386,7 +386,7 @@ __global__ void k_items(const uint32_t *__restrict__ row_ptr, const uint32_t *__
     if (c > total) return;
     uint32_t a = 0, b = 0, apv = 0, bpv = 0;
     const uint32_t v = c < total ? (uint32_t)(c % (n + 1)) : n;
-    if (v < n && cnt[c] > 0 && v >= pb) {
+    if (v < n && cnt[c] > 0 && v >= p0) {
         b = bpv = (cnt[c] + kb - 1) / kb;
     } else if (v < n && cnt[c] > 0) {
         const uint32_t r0 = row_ptr[v], d = row_ptr[v + 1] - r0;

@@ -135,16 +135,11 @@ def test_row_blocks_forced(monkeypatch):
     check_vs_oracle(e.cpu().numpy(), n)
 
 
-@pytest.mark.parametrize("ranks,ranks64", [("0", "0"), ("1", "1"), ("31", "0"), ("33", "33"),
-                                          ("517", "130"), ("900", "65"), ("4000", "64"),
-                                          ("4000", "0")])
-def test_panel_thresholds(monkeypatch, ranks, ranks64):
-    """The top-ranks panel regions of every size: off (per-vertex lists only), one partial
-    panel, one panel plus a ragged one, many panels, the 64-wide region alone, the 32-wide
-    region alone and both (with a ragged 32-wide panel at the border), over graphs of every
-    family."""
+@pytest.mark.parametrize("ranks", ["0", "1", "31", "33", "517", "4000"])
+def test_panel_thresholds(monkeypatch, ranks):
+    """The top-ranks panel region of every size: off (per-vertex lists only), one partial
+    panel, one panel plus a ragged one, and many panels over graphs of every family."""
     monkeypatch.setenv("TC_PANEL_RANKS", ranks)
-    monkeypatch.setenv("TC_PANEL64_RANKS", ranks64)
     for e, n in [synth.er_1000(), (synth.barabasi_albert(2000, 8, 2), 2000),
                  (synth.watts_strogatz(1500, 6, 0.1, 3), 1500), synth.rmat_graph(11, 8, seed=4),
                  synth.rmat_graph(14, 16, seed=6)]:
