@@ -109,6 +109,17 @@ static uint32_t panel_ranks_for(uint32_t n) {
     return (uint32_t)(x < n ? x : n);
 }
 
+// Rank span below which wave items use a bitmap (else a hash set or a sorted list); lowered
+// only by tests, through TC_WAVE_BITMAP_SPAN, to reach the other forms on small graphs.
+static uint32_t wave_bits_for() {
+    uint64_t x = count_wave_span(false);
+    if (const char *env = getenv("TC_WAVE_BITMAP_SPAN")) {
+        unsigned long long v = strtoull(env, nullptr, 10);
+        if (v < x) x = v;
+    }
+    return (uint32_t)x;
+}
+
 static int id_bits_for(uint32_t n) {
     int b = 1;
     while (b < 31 && (1ull << b) < n) ++b;
@@ -350,7 +361,7 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
                        at<uint32_t>(ws, L.cmask), status);
     TC_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_items, dim3(grid_for(l1, 256)), dim3(256), 0, s, row_ptr, col, cnt, n,
-                       L.nblk, L.p0, count_wave_span(false), count_wave_list(false),
+                       L.nblk, L.p0, wave_bits_for(), count_wave_list(false),
                        count_wave_list(true),
                        count_item_edges_wave(), count_item_edges_block(), items[0], items[1],
                        items[2], items[3], status);
@@ -403,6 +414,7 @@ static int run_count_prepared(void *ws, const Layout &L, hipStream_t s, uint64_t
         a.tpv = tpv;
         a.n1 = n + 1;
         a.p0 = L.p0;
+        a.wave_bits = wave_bits_for();
         a.status = status;
         TC_HIP(launch_count(a, pv, s));
     }

@@ -94,6 +94,25 @@ __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t *list, uint32
     return base + ((len == 1 && list[base] < w) ? 1u : 0u);
 }
 
+// N+(v) as an open-addressing hash set of T = 2^k slots in LDS (Fibonacci hashing, linear
+// probing, load at most 1/2).  Elements of an out-list are ranks above its vertex, so never 0:
+// a zero slot is empty, and a zeroed LDS slice is an empty table.
+struct HashProbe {
+    const uint32_t *tab;
+    uint32_t mask, shift;  // mask = T - 1, shift = 32 - k
+    static constexpr bool kBranchFree = false;
+    static constexpr bool kMasked = false;
+    __device__ __forceinline__ bool operator()(uint32_t w, uint32_t &) const {
+        uint32_t h = (w * 0x9E3779B1u) >> shift;
+        for (;;) {
+            const uint32_t y = tab[h];
+            if (y == w) return true;
+            if (y == 0u) return false;
+            h = (h + 1u) & mask;
+        }
+    }
+};
+
 struct ListProbe {  // sorted list in LDS or in global memory
     const uint32_t *list;
     uint32_t d;
@@ -328,7 +347,7 @@ __global__ __launch_bounds__(kThreads) void k_count(
     const uint32_t *__restrict__ item_v_b, const uint32_t *__restrict__ item_off_b,
     const uint32_t *__restrict__ n_items_b_ptr, uint32_t *__restrict__ queue_a,
     uint32_t *__restrict__ queue_b, unsigned long long *__restrict__ total,
-    unsigned long long *__restrict__ tpv, uint32_t n1, uint32_t p0,
+    unsigned long long *__restrict__ tpv, uint32_t n1, uint32_t p0, uint32_t wave_bits,
     const int32_t *__restrict__ status) {
     __shared__ uint32_t s_mem[kLdsWords];
     __shared__ WaveScratch s_ws[kWaves];
@@ -473,7 +492,7 @@ __global__ __launch_bounds__(kThreads) void k_count(
         if (!PV) {
             const uint32_t lo = col[it.r0];
             const uint32_t span = col[it.r0 + it.d - 1] - lo;
-            if (span < kWaveBits) {  // bitmap over the span
+            if (span < wave_bits) {  // bitmap over the span
                 for (uint32_t i = lane; i < it.d; i += kWave) {
                     const uint32_t o = col[it.r0 + i] - lo;
                     atomicOr(&mem[o >> 5], 1u << (o & 31u));
@@ -484,7 +503,25 @@ __global__ __launch_bounds__(kThreads) void k_count(
                     cnt += run_batch<false>(eb, it.e1, segs, col, probe, ws, nullptr, tpv);
                 for (uint32_t i = lane; i < it.d; i += kWave)
                     mem[(col[it.r0 + i] - lo) >> 5] = 0;
-            } else {  // a wide span, but a list that fits the slice (see k_items)
+            } else if (it.d <= kSliceWords / 2) {  // a wide span: hash set in the slice
+                uint32_t k = 6;  // T = 2^k >= 4 d slots, at most the slice
+                while ((1u << k) < 4u * it.d && (1u << k) < kSliceWords) ++k;
+                const uint32_t mask = (1u << k) - 1u, shift = 32u - k;
+                for (uint32_t i = lane; i < it.d; i += kWave) {
+                    const uint32_t x = col[it.r0 + i];
+                    uint32_t h = (x * 0x9E3779B1u) >> shift;
+                    for (;;) {  // distinct elements, and free slots remain
+                        const uint32_t old = atomicCAS(&mem[h], 0u, x);
+                        if (old == 0u || old == x) break;
+                        h = (h + 1u) & mask;
+                    }
+                }
+                wave_lds_sync();
+                const HashProbe probe{mem, mask, shift};
+                for (uint32_t eb = it.e0; eb < it.e1; eb += kWave)
+                    cnt += run_batch<false>(eb, it.e1, segs, col, probe, ws, nullptr, tpv);
+                for (uint32_t i = lane; i <= mask; i += kWave) mem[i] = 0;
+            } else {  // a wide span and a long list that still fits the slice (see k_items)
                 for (uint32_t i = lane; i < it.d; i += kWave) mem[i] = col[it.r0 + i];
                 wave_lds_sync();
                 const ListProbe probe{mem, it.d};
@@ -754,12 +791,12 @@ hipError_t launch_count(const CountArgs &x, bool per_vertex, hipStream_t s) {
         hipLaunchKernelGGL(k_count<true>, grid, block, 0, s, x.row_ptr, x.col, x.cptr, x.cbeg,
                            x.cend, x.cu, x.cmask, x.item_v_a, x.item_off_a, x.n_items_a,
                            x.item_v_b, x.item_off_b, x.n_items_b, x.queue_a, x.queue_b, x.total,
-                           x.tpv, x.n1, x.p0, x.status);
+                           x.tpv, x.n1, x.p0, x.wave_bits, x.status);
     else
         hipLaunchKernelGGL(k_count<false>, grid, block, 0, s, x.row_ptr, x.col, x.cptr, x.cbeg,
                            x.cend, x.cu, x.cmask, x.item_v_a, x.item_off_a, x.n_items_a,
                            x.item_v_b, x.item_off_b, x.n_items_b, x.queue_a, x.queue_b, x.total,
-                           x.tpv, x.n1, x.p0, x.status);
+                           x.tpv, x.n1, x.p0, x.wave_bits, x.status);
     return hipGetLastError();
 }
 

@@ -96,7 +96,8 @@ struct CountArgs {
     uint32_t *queue_a, *queue_b;
     unsigned long long *total, *tpv;
     uint32_t n1;
-    uint32_t p0;  // first rank of the panel region (n: no panels)
+    uint32_t p0;         // first rank of the panel region (n: no panels)
+    uint32_t wave_bits;  // wave items use a bitmap below this rank span (count_wave_span)
     const int32_t *status;
 };
 hipError_t launch_count(const CountArgs &a, bool per_vertex, hipStream_t s);

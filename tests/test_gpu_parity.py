@@ -157,6 +157,20 @@ def test_single_sweep_sort(monkeypatch):
         check_vs_oracle(e.numpy(), n)
 
 
+@pytest.mark.parametrize("span", ["0", "40", "600"])
+def test_wave_item_forms(monkeypatch, span):
+    """Wave items in every form (bitmap below the span limit; above it a hash set, or a
+    sorted list for the longest lists), reached on small graphs by lowering the limit, with
+    panels off so that every list is a wave or workgroup item."""
+    monkeypatch.setenv("TC_PANEL_RANKS", "0")
+    monkeypatch.setenv("TC_WAVE_BITMAP_SPAN", span)
+    for e, n in [synth.er_1000(), (synth.barabasi_albert(3000, 12, 2), 3000),
+                 synth.rmat_graph(12, 16, seed=8), (synth.erdos_renyi(1500, 0.9, 3), 1500)]:
+        check_vs_oracle(e.numpy(), n)
+    for k in [3, 40, 130]:
+        assert check_vs_oracle(complete(k), k) == math.comb(k, 3)
+
+
 def test_prepared_recount():
     """A resident preprocessed graph counted repeatedly, with and without per-vertex counts."""
     e, n = synth.rmat_graph(13, 16, seed=12, device=DEV)
