@@ -109,7 +109,7 @@ static uint32_t panel_ranks_for(uint32_t n) {
     return (uint32_t)(x < n ? x : n);
 }
 
-// Rank span below which wave items use a bitmap (else a hash set or a sorted list); lowered
+// Rank span below which wave items use a bitmap (else a sorted list); lowered
 // only by tests, through TC_WAVE_BITMAP_SPAN, to reach the other forms on small graphs.
 static uint32_t wave_bits_for() {
     uint64_t x = count_wave_span(false);

@@ -94,25 +94,6 @@ __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t *list, uint32
     return base + ((len == 1 && list[base] < w) ? 1u : 0u);
 }
 
-// N+(v) as an open-addressing hash set of T = 2^k slots in LDS (Fibonacci hashing, linear
-// probing, load at most 1/2).  Elements of an out-list are ranks above its vertex, so never 0:
-// a zero slot is empty, and a zeroed LDS slice is an empty table.
-struct HashProbe {
-    const uint32_t *tab;
-    uint32_t mask, shift;  // mask = T - 1, shift = 32 - k
-    static constexpr bool kBranchFree = false;
-    static constexpr bool kMasked = false;
-    __device__ __forceinline__ bool operator()(uint32_t w, uint32_t &) const {
-        uint32_t h = (w * 0x9E3779B1u) >> shift;
-        for (;;) {
-            const uint32_t y = tab[h];
-            if (y == w) return true;
-            if (y == 0u) return false;
-            h = (h + 1u) & mask;
-        }
-    }
-};
-
 struct ListProbe {  // sorted list in LDS or in global memory
     const uint32_t *list;
     uint32_t d;
@@ -503,25 +484,7 @@ __global__ __launch_bounds__(kThreads) void k_count(
                     cnt += run_batch<false>(eb, it.e1, segs, col, probe, ws, nullptr, tpv);
                 for (uint32_t i = lane; i < it.d; i += kWave)
                     mem[(col[it.r0 + i] - lo) >> 5] = 0;
-            } else if (it.d <= kSliceWords / 2) {  // a wide span: hash set in the slice
-                uint32_t k = 6;  // T = 2^k >= 4 d slots, at most the slice
-                while ((1u << k) < 4u * it.d && (1u << k) < kSliceWords) ++k;
-                const uint32_t mask = (1u << k) - 1u, shift = 32u - k;
-                for (uint32_t i = lane; i < it.d; i += kWave) {
-                    const uint32_t x = col[it.r0 + i];
-                    uint32_t h = (x * 0x9E3779B1u) >> shift;
-                    for (;;) {  // distinct elements, and free slots remain
-                        const uint32_t old = atomicCAS(&mem[h], 0u, x);
-                        if (old == 0u || old == x) break;
-                        h = (h + 1u) & mask;
-                    }
-                }
-                wave_lds_sync();
-                const HashProbe probe{mem, mask, shift};
-                for (uint32_t eb = it.e0; eb < it.e1; eb += kWave)
-                    cnt += run_batch<false>(eb, it.e1, segs, col, probe, ws, nullptr, tpv);
-                for (uint32_t i = lane; i <= mask; i += kWave) mem[i] = 0;
-            } else {  // a wide span and a long list that still fits the slice (see k_items)
+            } else {  // a wide span, but a list that fits the slice (see k_items)
                 for (uint32_t i = lane; i < it.d; i += kWave) mem[i] = col[it.r0 + i];
                 wave_lds_sync();
                 const ListProbe probe{mem, it.d};

@@ -159,9 +159,9 @@ def test_single_sweep_sort(monkeypatch):
 
 @pytest.mark.parametrize("span", ["0", "40", "600"])
 def test_wave_item_forms(monkeypatch, span):
-    """Wave items in every form (bitmap below the span limit; above it a hash set, or a
-    sorted list for the longest lists), reached on small graphs by lowering the limit, with
-    panels off so that every list is a wave or workgroup item."""
+    """Wave items in both forms (bitmap below the span limit, sorted list above it) and
+    workgroup items, reached on small graphs by lowering the limit, with panels off so that
+    every list is a wave or workgroup item."""
     monkeypatch.setenv("TC_PANEL_RANKS", "0")
     monkeypatch.setenv("TC_WAVE_BITMAP_SPAN", span)
     for e, n in [synth.er_1000(), (synth.barabasi_albert(3000, 12, 2), 3000),
