@@ -68,6 +68,7 @@ struct BitmapProbe {
     }
     __device__ __forceinline__ bool operator()(uint32_t w, uint32_t &) const { return bit(w); }
     static constexpr bool kMasked = false;
+    static constexpr bool kList = false;
 };
 
 // Panel table M over ranks [lo, lo + span]: word w - lo holds the mask of the panel vertices
@@ -77,6 +78,7 @@ struct PanelProbe {
     uint32_t lo, span;
     static constexpr bool kBranchFree = true;
     static constexpr bool kMasked = true;
+    static constexpr bool kList = false;
     __device__ __forceinline__ uint32_t count(uint32_t w, uint32_t r) const {
         return __popc(m[min(w - lo, span + 1u)] & r);
     }
@@ -94,11 +96,12 @@ __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t *list, uint32
     return base + ((len == 1 && list[base] < w) ? 1u : 0u);
 }
 
-struct ListProbe {  // sorted list in LDS or in global memory
+struct ListProbe {  // sorted list in LDS or in global memory (d >= 1)
     const uint32_t *list;
     uint32_t d;
     static constexpr bool kBranchFree = false;
     static constexpr bool kMasked = false;
+    static constexpr bool kList = true;
     __device__ __forceinline__ bool operator()(uint32_t w, uint32_t &pos) const {
         pos = lower_bound_u32(list, d, w);
         return pos < d && list[pos] == w;
@@ -234,6 +237,30 @@ __device__ __forceinline__ uint32_t run_batch(uint32_t eb, uint32_t e1, const Se
                     const uint32_t c = probe.count(wv[i], r);
                     hits += (i >= lo_i && i < hi_i) ? c : 0u;
                 }
+            } else if constexpr (!PV && Probe::kList) {
+                // the piece's 16 lookups as binary searches in lockstep (the list length is
+                // uniform), so that every step issues independent LDS reads; position pos is
+                // the first entry >= w, and w is in the list iff that entry equals w
+                uint32_t base[kPiece];
+#pragma unroll
+                for (uint32_t i = 0; i < kPiece; ++i) base[i] = 0;
+                for (uint32_t n_left = probe.d; n_left > 1;) {
+                    const uint32_t half = n_left >> 1;
+#pragma unroll
+                    for (uint32_t i = 0; i < kPiece; ++i)
+                        base[i] = probe.list[base[i] + half - 1] < wv[i] ? base[i] + half : base[i];
+                    n_left -= half;
+                }
+                uint32_t packed = 0;
+#pragma unroll
+                for (uint32_t i = 0; i < kPiece; ++i) {
+                    const uint32_t pos = base[i] + (probe.list[base[i]] < wv[i] ? 1u : 0u);
+                    packed |= (probe.list[min(pos, probe.d - 1u)] == wv[i] ? 1u : 0u) << i;
+                }
+                const uint32_t lo_i = first > start ? first - start : 0u;
+                const uint32_t hi_i = min(stop - start, kPiece);
+                const uint32_t hmask = hi_i >= 32u ? ~0u : ((1u << hi_i) - 1u);
+                hits = __popc(packed & hmask & ~((1u << lo_i) - 1u));
             } else if constexpr (!PV && Probe::kBranchFree) {
                 // the piece's valid elements are the contiguous range [lo_i, hi_i) of positions
                 uint32_t packed = 0;
