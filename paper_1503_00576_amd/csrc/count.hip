@@ -609,20 +609,33 @@ __device__ __forceinline__ uint32_t run_light(uint32_t eb, uint32_t e1,
                 wv[4 * j + 3] = x.w;
             }
             const uint32_t *list = win + ws.tag[k];
-            const uint32_t dl = ws.aux[k];
+            const uint32_t dl = ws.aux[k];  // >= 2
             const uint32_t lo_i = first > start ? first - start : 0u;
             const uint32_t hi_i = min(stop - start, kPiece);
-            uint32_t hits = 0;
+            // the piece's lookups as binary searches in lockstep (one list per lane)
+            uint32_t base[kPiece];
+#pragma unroll
+            for (uint32_t i = 0; i < kPiece; ++i) base[i] = 0;
+            for (uint32_t n_left = dl; n_left > 1;) {
+                const uint32_t half = n_left >> 1;
+#pragma unroll
+                for (uint32_t i = 0; i < kPiece; ++i)
+                    base[i] = list[base[i] + half - 1] < wv[i] ? base[i] + half : base[i];
+                n_left -= half;
+            }
+            uint32_t packed = 0;
 #pragma unroll
             for (uint32_t i = 0; i < kPiece; ++i) {
-                if (i >= lo_i && i < hi_i) {
-                    const uint32_t x = wv[i];
-                    const uint32_t pos = lower_bound_u32(list, dl, x);
-                    if (pos < dl && list[pos] == x) {
-                        ++hits;
-                        if (PV) atomicAdd(&tpv[x], 1ull);
-                    }
-                }
+                const uint32_t pos = base[i] + (list[base[i]] < wv[i] ? 1u : 0u);
+                packed |= (list[min(pos, dl - 1u)] == wv[i] ? 1u : 0u) << i;
+            }
+            const uint32_t hmask = hi_i >= 32u ? ~0u : ((1u << hi_i) - 1u);
+            packed &= hmask & ~((1u << lo_i) - 1u);
+            const uint32_t hits = __popc(packed);
+            if (PV) {
+#pragma unroll
+                for (uint32_t i = 0; i < kPiece; ++i)
+                    if ((packed >> i) & 1u) atomicAdd(&tpv[wv[i]], 1ull);
             }
             if (hits) atomicAdd(&ws.cnt[k], hits);
         }
