@@ -33,9 +33,8 @@ __global__ void k_csc_keys(const uint32_t *, const uint32_t *, const uint32_t *,
                            uint64_t *, uint2 *, const int32_t *);
 __global__ void k_csc_bounds(const uint64_t *, uint32_t, uint64_t, uint32_t *, uint32_t *,
                              const int32_t *);
-__global__ void k_csc_final(const uint64_t *, uint32_t, uint64_t, const uint2 *,
-                            const uint32_t *, uint32_t, uint32_t, uint32_t, uint32_t *,
-                            uint32_t *, uint32_t *, uint32_t *, const int32_t *);
+__global__ void k_csc_final(const uint64_t *, uint32_t, uint64_t, const uint2 *, uint32_t *,
+                            uint32_t *, uint32_t *, const int32_t *);
 __global__ void k_items(const uint32_t *, const uint32_t *, const uint32_t *, uint32_t, uint32_t,
                         uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t *,
                         uint32_t *,
@@ -69,7 +68,7 @@ int device_cu_count() {
 struct Layout {
     size_t ctl, part_hist, part_offs, part_scan, deg, perm, rank, keys_a, keys_b, sort_scratch,
         rs, re, rowlen, row_ptr, col, src, vrange, prange, eu, lrs, lre, cnt, cptr, cbeg, cend,
-        cu, cmask, items[4], off[4], item_v[4], scan_scratch, tpv, total_bytes;
+        cmask, items[4], off[4], item_v[4], scan_scratch, tpv, total_bytes;
     uint32_t part_tiles;  // 0: degrees by atomics (inputs too large for the partition)
     int part_shift;
     uint32_t n, m, mf, kcap, id_bits, nblk;
@@ -188,7 +187,6 @@ static bool make_layout(int64_t n, int64_t m, uint32_t flags, Layout &L) {
     L.cptr = take(l1 * 4);
     L.cbeg = take((size_t)L.mf * 4);
     L.cend = take((size_t)L.mf * 4);
-    L.cu = take((size_t)L.mf * 4);
     L.cmask = take((size_t)L.mf * 4);
     for (int k = 0; k < 4; ++k) {
         const uint32_t per = (k & 1) ? count_item_edges_block() : count_item_edges_wave();
@@ -356,8 +354,7 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
     TC_LAUNCH_CHECK();
     TC_HIP(scan_exclusive_u32(cnt, cptr, l1, scan_scr, s));
     hipLaunchKernelGGL(k_csc_final, dim3(grid_for(mf, 256)), dim3(256), 0, s, cks, mf, L.lists,
-                       eu, col, n, L.p0, count_panel(), at<uint32_t>(ws, L.cbeg),
-                       at<uint32_t>(ws, L.cend), at<uint32_t>(ws, L.cu),
+                       eu, at<uint32_t>(ws, L.cbeg), at<uint32_t>(ws, L.cend),
                        at<uint32_t>(ws, L.cmask), status);
     TC_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_items, dim3(grid_for(l1, 256)), dim3(256), 0, s, row_ptr, col, cnt, n,
@@ -400,7 +397,7 @@ static int run_count_prepared(void *ws, const Layout &L, hipStream_t s, uint64_t
         a.cptr = at<uint32_t>(ws, L.cptr);
         a.cbeg = at<uint32_t>(ws, L.cbeg);
         a.cend = at<uint32_t>(ws, L.cend);
-        a.cu = at<uint32_t>(ws, L.cu);
+        a.src = at<uint32_t>(ws, L.src);
         a.cmask = at<uint32_t>(ws, L.cmask);
         a.item_v_a = at<uint32_t>(ws, L.item_v[a0]);
         a.item_off_a = at<uint32_t>(ws, L.off[a0]);

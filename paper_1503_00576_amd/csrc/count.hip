@@ -118,13 +118,13 @@ struct WaveScratch {  // tag: the segment's owner (per-vertex counts) or its pan
 
 // Segment sources: segment e is a range [b, en) of `col` streamed through the staged list,
 // and `owner` is the vertex credited with the segment's hits in per-vertex counts.
-struct InEdgeSegs {  // middle-vertex kernel: suffix of N+(u) after v, owner u
-    const uint32_t *cbeg, *cend, *cu;
+struct InEdgeSegs {  // middle-vertex kernel: suffix of N+(u) after v, owner u = src[e]
+    const uint32_t *cbeg, *cend, *src;
     __device__ __forceinline__ void get(uint32_t e, uint32_t &b, uint32_t &en) const {
         b = cbeg[e];
         en = cend[e];
     }
-    __device__ __forceinline__ uint32_t owner(uint32_t e) const { return cu[e]; }
+    __device__ __forceinline__ uint32_t owner(uint32_t e) const { return src[cbeg[e] - 1]; }
     __device__ __forceinline__ uint32_t mask(uint32_t) const { return 0u; }
 };
 
@@ -145,7 +145,7 @@ struct PanelSegs {
 // N+(u) starting right before cbeg, so the suffix after P + j starts popcount(R(u) below j)
 // elements later; segments without bit j are empty.
 struct PanelVertexSegs {
-    const uint32_t *cbeg, *cend, *cu, *cmask;
+    const uint32_t *cbeg, *cend, *src, *cmask;
     uint32_t j;
     __device__ __forceinline__ void get(uint32_t e, uint32_t &b, uint32_t &en) const {
         const uint32_t r = cmask[e];
@@ -156,7 +156,7 @@ struct PanelVertexSegs {
             en = cend[e];
         }
     }
-    __device__ __forceinline__ uint32_t owner(uint32_t e) const { return cu[e]; }
+    __device__ __forceinline__ uint32_t owner(uint32_t e) const { return src[cbeg[e] - 1]; }
     __device__ __forceinline__ uint32_t mask(uint32_t) const { return 0u; }
 };
 
@@ -349,7 +349,7 @@ template <bool PV>
 __global__ __launch_bounds__(kThreads) void k_count(
     const uint32_t *__restrict__ row_ptr, const uint32_t *__restrict__ col,
     const uint32_t *__restrict__ cptr, const uint32_t *__restrict__ cbeg,
-    const uint32_t *__restrict__ cend, const uint32_t *__restrict__ cu,
+    const uint32_t *__restrict__ cend, const uint32_t *__restrict__ src,
     const uint32_t *__restrict__ cmask, const uint32_t *__restrict__ item_v_a,
     const uint32_t *__restrict__ item_off_a, const uint32_t *__restrict__ n_items_a_ptr,
     const uint32_t *__restrict__ item_v_b, const uint32_t *__restrict__ item_off_b,
@@ -363,7 +363,7 @@ __global__ __launch_bounds__(kThreads) void k_count(
     if (*status) return;
     const uint32_t t = threadIdx.x, w = t / kWave, lane = lane_id();
     WaveScratch &ws = s_ws[w];
-    const InEdgeSegs segs{cbeg, cend, cu};
+    const InEdgeSegs segs{cbeg, cend, src};
     for (uint32_t i = t; i < kLdsWords; i += kThreads) s_mem[i] = 0;
     uint64_t acc = 0;
 
@@ -404,7 +404,7 @@ __global__ __launch_bounds__(kThreads) void k_count(
                     if (in_lds)
                         for (uint32_t i = t; i < d; i += kThreads) s_mem[i] = col[r0 + i];
                     __syncthreads();
-                    const PanelVertexSegs vsegs{cbeg, cend, cu, cmask, j};
+                    const PanelVertexSegs vsegs{cbeg, cend, src, cmask, j};
                     uint32_t cnt = 0;
                     if (in_lds) {
                         const ListProbe probe{s_mem, d};
@@ -792,12 +792,12 @@ hipError_t launch_count(const CountArgs &x, bool per_vertex, hipStream_t s) {
     const dim3 grid(device_cu_count() * kWgsPerCu), block(kThreads);
     if (per_vertex)
         hipLaunchKernelGGL(k_count<true>, grid, block, 0, s, x.row_ptr, x.col, x.cptr, x.cbeg,
-                           x.cend, x.cu, x.cmask, x.item_v_a, x.item_off_a, x.n_items_a,
+                           x.cend, x.src, x.cmask, x.item_v_a, x.item_off_a, x.n_items_a,
                            x.item_v_b, x.item_off_b, x.n_items_b, x.queue_a, x.queue_b, x.total,
                            x.tpv, x.n1, x.p0, x.wave_bits, x.status);
     else
         hipLaunchKernelGGL(k_count<false>, grid, block, 0, s, x.row_ptr, x.col, x.cptr, x.cbeg,
-                           x.cend, x.cu, x.cmask, x.item_v_a, x.item_off_a, x.n_items_a,
+                           x.cend, x.src, x.cmask, x.item_v_a, x.item_off_a, x.n_items_a,
                            x.item_v_b, x.item_off_b, x.n_items_b, x.queue_a, x.queue_b, x.total,
                            x.tpv, x.n1, x.p0, x.wave_bits, x.status);
     return hipGetLastError();

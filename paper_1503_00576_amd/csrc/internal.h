@@ -90,7 +90,7 @@ int device_cu_count();
 
 // counting kernels (count.hip)
 struct CountArgs {
-    const uint32_t *row_ptr, *col, *cptr, *cbeg, *cend, *cu, *cmask;
+    const uint32_t *row_ptr, *col, *cptr, *cbeg, *cend, *src, *cmask;  // src: row of a CSR entry
     const uint32_t *item_v_a, *item_off_a, *n_items_a;
     const uint32_t *item_v_b, *item_off_b, *n_items_b;
     uint32_t *queue_a, *queue_b;

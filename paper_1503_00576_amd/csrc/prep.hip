@@ -194,7 +194,36 @@ __global__ void k_orient(const int2 *__restrict__ edges, uint64_t m, uint32_t bo
     if (*status) return;
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    // uniform trip count so that every lane takes part in the wave-wide ballots
+    if (!both) {
+        // four edges per thread and step, so that their eight rank gathers (random reads of
+        // `rank`) are in flight together
+        constexpr int kU = 4;
+        for (uint64_t i0 = i; i0 < m; i0 += kU * stride) {
+            int2 ed[kU];
+            uint32_t ru[kU], rv[kU];
+#pragma unroll
+            for (int k = 0; k < kU; ++k) {
+                const uint64_t j = i0 + k * stride;
+                ed[k] = j < m ? edges[j] : make_int2(0, 0);
+            }
+#pragma unroll
+            for (int k = 0; k < kU; ++k) {
+                ru[k] = rank[ed[k].x];
+                rv[k] = rank[ed[k].y];
+            }
+#pragma unroll
+            for (int k = 0; k < kU; ++k) {
+                const uint64_t j = i0 + k * stride;
+                if (j < m) {
+                    const uint32_t s = min(ru[k], rv[k]), t = max(ru[k], rv[k]);
+                    keys[j] = ((uint64_t)s << b) | t;
+                }
+            }
+        }
+        return;
+    }
+    // two-direction format: keep the forward entries, compacted per wave; a uniform trip
+    // count so that every lane takes part in the wave-wide ballots
     const uint64_t rounds = (m + stride - 1) / stride;
     for (uint64_t r = 0; r < rounds; ++r, i += stride) {
         bool in = i < m;
@@ -204,21 +233,14 @@ __global__ void k_orient(const int2 *__restrict__ edges, uint64_t m, uint32_t bo
             ru = rank[e.x];
             rv = rank[e.y];
         }
-        if (!both) {
-            if (in) {
-                uint32_t s = ru < rv ? ru : rv, t = ru < rv ? rv : ru;
-                keys[i] = ((uint64_t)s << b) | t;
-            }
-        } else {
-            bool keep = in && ru < rv;
-            uint64_t mask = __ballot(keep);
-            if (mask == 0) continue;
-            uint32_t leader = (uint32_t)__ffsll((long long)mask) - 1;
-            uint32_t base = 0;
-            if (lane_id() == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
-            base = wave_bcast(base, (int)leader);
-            if (keep) keys[base + lanes_below(mask)] = ((uint64_t)ru << b) | rv;
-        }
+        bool keep = in && ru < rv;
+        uint64_t mask = __ballot(keep);
+        if (mask == 0) continue;
+        uint32_t leader = (uint32_t)__ffsll((long long)mask) - 1;
+        uint32_t base = 0;
+        if (lane_id() == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
+        base = wave_bcast(base, (int)leader);
+        if (keep) keys[base + lanes_below(mask)] = ((uint64_t)ru << b) | rv;
     }
 }
 
@@ -293,6 +315,7 @@ __global__ void k_panel_range(const uint64_t *__restrict__ vr, uint32_t n, uint3
 // From rank p0 on, middle vertices form panels of kp consecutive ranks with one list per
 // panel, keyed by its first rank P: only the first in-edge of each run of u's out-neighbours
 // inside the panel is kept (it stands for the whole run), tested against the panel's span.
+// eu[e] = (end of u's row, mask of the run's panel vertices for a kept panel entry).
 __global__ void k_csc_keys(const uint32_t *__restrict__ col, const uint32_t *__restrict__ src,
                            const uint32_t *__restrict__ row_ptr,
                            const uint64_t *__restrict__ vr, const uint64_t *__restrict__ pr,
@@ -305,21 +328,32 @@ __global__ void k_csc_keys(const uint32_t *__restrict__ col, const uint32_t *__r
     const uint32_t u = src[e], v = col[e];
     const uint32_t end_u = row_ptr[u + 1];
     uint64_t c = (uint64_t)nblk * (n + 1);
+    uint32_t mask = 1u;
     if (e + 1 < end_u) {
         uint32_t list = v;
         uint64_t r = vr[v];
+        bool run_start = false;
         if (v >= p0) {
             const uint32_t i = (v - p0) / kp;
             list = p0 + i * kp;
-            const bool run_start = e == row_ptr[u] || col[e - 1] < list;
+            run_start = e == row_ptr[u] || col[e - 1] < list;
             r = run_start ? pr[i] : 0xFFFFFFFF00000000ull;
         }
         const uint32_t lo = (uint32_t)(r >> 32), hi = (uint32_t)r;
-        if (lo <= hi && col[e + 1] <= hi && col[end_u - 1] >= lo)
+        if (lo <= hi && col[e + 1] <= hi && col[end_u - 1] >= lo) {
             c = (uint64_t)(((uint64_t)e * nblk) / mf) * (n + 1) + list;
+            if (run_start) {  // the run's mask (its entries are in this part of col anyway)
+                mask = 0;
+                for (uint32_t x = e; x < end_u; ++x) {
+                    const uint32_t w = col[x];
+                    if (w >= list + kp) break;
+                    mask |= 1u << (w - list);
+                }
+            }
+        }
     }
     keys[e] = (c << 32) | e;
-    eu[e] = make_uint2(end_u, u);
+    eu[e] = make_uint2(end_u, mask);
 }
 
 // list boundaries of the sorted keys (useful in-edges only)
@@ -335,36 +369,22 @@ __global__ void k_csc_bounds(const uint64_t *__restrict__ keys, uint32_t mf, uin
     if (j == mf - 1 || (keys[j + 1] >> 32) != c) re[c] = j + 1;
 }
 
-// the lists themselves: in-edge u -> v at CSR position e contributes the suffix [e + 1, end_u);
-// for a panel list (first rank P >= p0) also the mask of u's run of panel vertices, which
-// starts at e
+// the lists themselves: in-edge u -> v at CSR position e contributes the suffix [e + 1, end_u)
+// and, in a panel list, the mask of u's run of panel vertices (k_csc_keys)
 __global__ void k_csc_final(const uint64_t *__restrict__ keys, uint32_t mf, uint64_t lists,
-                            const uint2 *__restrict__ eu, const uint32_t *__restrict__ col,
-                            uint32_t n, uint32_t p0, uint32_t kp, uint32_t *__restrict__ cbeg,
-                            uint32_t *__restrict__ cend, uint32_t *__restrict__ cu,
-                            uint32_t *__restrict__ cmask, const int32_t *__restrict__ status) {
+                            const uint2 *__restrict__ eu, uint32_t *__restrict__ cbeg,
+                            uint32_t *__restrict__ cend, uint32_t *__restrict__ cmask,
+                            const int32_t *__restrict__ status) {
     if (*status) return;
     uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= mf) return;
     const uint64_t k = keys[j];
-    const uint64_t c = k >> 32;
-    if (c >= lists) return;
+    if ((k >> 32) >= lists) return;
     const uint32_t e = (uint32_t)k;
     const uint2 x = eu[e];
     cbeg[j] = e + 1;
     cend[j] = x.x;
-    cu[j] = x.y;
-    const uint32_t P = (uint32_t)(c % ((uint64_t)n + 1));
-    uint32_t r = 1u;
-    if (P >= p0) {
-        r = 0;
-        for (uint32_t i = e; i < x.x; ++i) {
-            const uint32_t w = col[i];
-            if (w >= P + kp) break;
-            r |= 1u << (w - P);
-        }
-    }
-    cmask[j] = r;
+    cmask[j] = x.y;
 }
 
 // Work items of the counting kernel.  A vertex's in-edges are cut into chunks; the chunks go
