@@ -195,30 +195,10 @@ __global__ void k_orient(const int2 *__restrict__ edges, uint64_t m, uint32_t bo
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     if (!both) {
-        // four edges per thread and step, so that their eight rank gathers (random reads of
-        // `rank`) are in flight together
-        constexpr int kU = 4;
-        for (uint64_t i0 = i; i0 < m; i0 += kU * stride) {
-            int2 ed[kU];
-            uint32_t ru[kU], rv[kU];
-#pragma unroll
-            for (int k = 0; k < kU; ++k) {
-                const uint64_t j = i0 + k * stride;
-                ed[k] = j < m ? edges[j] : make_int2(0, 0);
-            }
-#pragma unroll
-            for (int k = 0; k < kU; ++k) {
-                ru[k] = rank[ed[k].x];
-                rv[k] = rank[ed[k].y];
-            }
-#pragma unroll
-            for (int k = 0; k < kU; ++k) {
-                const uint64_t j = i0 + k * stride;
-                if (j < m) {
-                    const uint32_t s = min(ru[k], rv[k]), t = max(ru[k], rv[k]);
-                    keys[j] = ((uint64_t)s << b) | t;
-                }
-            }
+        for (; i < m; i += stride) {
+            const int2 e = edges[i];
+            const uint32_t ru = rank[e.x], rv = rank[e.y];
+            keys[i] = ((uint64_t)min(ru, rv) << b) | max(ru, rv);
         }
         return;
     }
