@@ -44,8 +44,8 @@ constexpr uint32_t kWaveListPV = kSliceWords / 2;     // per-vertex: list + coun
 constexpr uint32_t kBlockBits = kLdsWords * 32 - 32;  // workgroup bitmap: span < 524256
 constexpr uint32_t kBlockList = kLdsWords;            // workgroup sorted list
 constexpr uint32_t kBlockListPV = kLdsWords / 2;      // per-vertex: list + counters
-constexpr uint32_t kItemEdgesWave = 256;
-constexpr uint32_t kItemEdgesBlock = 8192;
+constexpr uint32_t kItemEdgesWave = 512;
+constexpr uint32_t kItemEdgesBlock = 16384;
 constexpr uint32_t kPanel = 32;                       // one bit per panel vertex in a mask
 constexpr uint32_t kPanelRanks = kLdsWords - 32;      // mask table: one word per rank
 // batched kernel: rows with at most kLightMax forward entries are counted edge by edge; a
