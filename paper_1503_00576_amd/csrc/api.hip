@@ -30,7 +30,7 @@ __global__ void k_panel_range(const uint64_t *, uint32_t, uint32_t, uint32_t, ui
                               uint64_t *);
 __global__ void k_csc_keys(const uint32_t *, const uint32_t *, const uint32_t *, const uint64_t *,
                            const uint64_t *, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t,
-                           uint64_t *, uint2 *, const int32_t *);
+                           uint32_t, uint64_t *, uint2 *, const int32_t *);
 __global__ void k_csc_bounds(const uint64_t *, uint32_t, uint64_t, uint32_t *, uint32_t *,
                              const int32_t *);
 __global__ void k_csc_final(const uint64_t *, uint32_t, uint64_t, const uint2 *, uint32_t *,
@@ -68,11 +68,12 @@ int device_cu_count() {
 struct Layout {
     size_t ctl, part_hist, part_offs, part_scan, deg, perm, rank, keys_a, keys_b, sort_scratch,
         rs, re, rowlen, row_ptr, col, src, vrange, prange, eu, lrs, lre, cnt, cptr, cbeg, cend,
-        cmask, items[4], off[4], item_v[4], scan_scratch, tpv, total_bytes;
+        cmask, items[4], off[4], item_v[4], scan_scratch, tpv, hub_a, hub_at, total_bytes;
     uint32_t part_tiles;  // 0: degrees by atomics (inputs too large for the partition)
     int part_shift;
     uint32_t n, m, mf, kcap, id_bits, nblk;
     uint32_t p0, panels;  // panel region: ranks [p0, n) in panels of count_panel() ranks
+    uint32_t h0, hp;      // hubs: ranks [h0, n), matrices hp x hp (hp = 0: no hubs)
     uint64_t lists;       // in-edge lists: nblk * (n + 1)
 };
 
@@ -119,6 +120,15 @@ static uint32_t wave_bits_for() {
     return (uint32_t)x;
 }
 
+// Hubs, whose triangles are counted on the matrix cores: the top TC_HUB_RANKS ranks (0 =
+// off); by default 16384 for graphs of at least 2^24 oriented edges, none for smaller ones.
+static uint32_t hub_ranks_for(uint32_t n, uint32_t mf) {
+    uint64_t x = mf >= (1u << 24) ? 16384u : 0u;
+    if (const char *env = getenv("TC_HUB_RANKS")) x = strtoull(env, nullptr, 10);
+    if (x > (1u << 16)) x = 1u << 16;  // two matrices of at most 4 GiB each
+    return (uint32_t)(x < n ? x : n);
+}
+
 static int id_bits_for(uint32_t n) {
     int b = 1;
     while (b < 31 && (1ull << b) < n) ++b;
@@ -142,6 +152,11 @@ static bool make_layout(int64_t n, int64_t m, uint32_t flags, Layout &L) {
     L.id_bits = (uint32_t)id_bits_for(L.n);
     L.nblk = row_blocks_for(L.n, L.mf);
     L.p0 = L.n - panel_ranks_for(L.n);
+    {
+        const uint32_t h = hub_ranks_for(L.n, L.mf);
+        L.h0 = L.n - h;
+        L.hp = (h + 63u) & ~63u;
+    }
     L.panels = ceil_div(L.n - L.p0, count_panel());
     const uint64_t n1 = (uint64_t)n + 1;
     L.lists = (uint64_t)L.nblk * n1;
@@ -196,6 +211,8 @@ static bool make_layout(int64_t n, int64_t m, uint32_t flags, Layout &L) {
     }
     L.scan_scratch = take(scan_scratch_words(l1 > n1 ? l1 : n1) * 4);
     L.tpv = take((size_t)n * 8);
+    L.hub_a = take((size_t)L.hp * L.hp);
+    L.hub_at = take((size_t)L.hp * L.hp);
     L.total_bytes = off;
     return true;
 }
@@ -316,6 +333,13 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
     hipLaunchKernelGGL(k_rowlen, dim3(grid_for(n1, 256)), dim3(256), 0, s, rs, re, n, rowlen);
     TC_LAUNCH_CHECK();
     TC_HIP(scan_exclusive_u32(rowlen, row_ptr, n1, scan_scr, s));
+    // the hub matrices
+    if (L.hp) {
+        uint8_t *ha = at<uint8_t>(ws, L.hub_a), *hat = at<uint8_t>(ws, L.hub_at);
+        TC_HIP(fill_u32((uint32_t *)ha, 0u, (uint64_t)L.hp * L.hp / 4, s));
+        TC_HIP(fill_u32((uint32_t *)hat, 0u, (uint64_t)L.hp * L.hp / 4, s));
+        TC_HIP(launch_hub_fill(src, col, row_ptr, mf, L.h0, L.hp, ha, hat, status, s));
+    }
     // in-edge lists (grouped by list c = row block * (n + 1) + v) and the counting kernel's
     // work items
     const uint64_t l1 = L.lists + 1;
@@ -340,7 +364,7 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
         TC_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL(k_csc_keys, dim3(grid_for(mf, 256)), dim3(256), 0, s, col, src, row_ptr, vr,
-                       pr, mf, n, L.nblk, L.p0, count_panel(), ck, eu, status);
+                       pr, mf, n, L.nblk, L.p0, count_panel(), L.h0, ck, eu, status);
     TC_LAUNCH_CHECK();
     uint64_t *cks = ck;
     TC_HIP(sort_u64(ck, ck2, mf, 32, 32 + id_bits_for64(l1), sort_scr, status, s, &cks));
@@ -414,6 +438,8 @@ static int run_count_prepared(void *ws, const Layout &L, hipStream_t s, uint64_t
         a.wave_bits = wave_bits_for();
         a.status = status;
         TC_HIP(launch_count(a, pv, s));
+        TC_HIP(launch_hub_count(at<uint8_t>(ws, L.hub_a), at<uint8_t>(ws, L.hub_at), L.hp, L.h0,
+                                total, tpv, pv, status, s));
     }
     if (pv && n > 0) {
         hipLaunchKernelGGL(k_pv_out, dim3(grid_for(n, 256)), dim3(256), 0, s, tpv,

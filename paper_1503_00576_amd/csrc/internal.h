@@ -113,6 +113,13 @@ uint32_t count_col_pad_bytes();
 uint32_t count_panel();
 uint32_t count_wgs_per_cu();  // resident workgroups per CU of the counting kernels
 uint32_t count_panel_ranks();
+// hub triangles on the matrix cores (hub.hip): A / At are hp x hp int8, hubs = ranks h0 ..
+hipError_t launch_hub_fill(const uint32_t *src, const uint32_t *col, const uint32_t *row_ptr,
+                           uint32_t mf, uint32_t h0, uint32_t hp, uint8_t *A, uint8_t *At,
+                           const int32_t *status, hipStream_t s);
+hipError_t launch_hub_count(const uint8_t *A, const uint8_t *At, uint32_t hp, uint32_t h0,
+                            unsigned long long *total, unsigned long long *tpv, bool per_vertex,
+                            const int32_t *status, hipStream_t s);
 struct BatchKernelArgs {
     const uint32_t *frp, *fcol, *fsrc, *gid;
     const uint32_t *item_u, *item_off, *n_items;  // heavy items

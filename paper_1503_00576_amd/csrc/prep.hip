@@ -295,12 +295,13 @@ __global__ void k_panel_range(const uint64_t *__restrict__ vr, uint32_t n, uint3
 // From rank p0 on, middle vertices form panels of kp consecutive ranks with one list per
 // panel, keyed by its first rank P: only the first in-edge of each run of u's out-neighbours
 // inside the panel is kept (it stands for the whole run), tested against the panel's span.
-// eu[e] = (end of u's row, mask of the run's panel vertices for a kept panel entry).
+// eu[e] = (end of u's row, mask of the run's panel vertices for a kept panel entry).  In-edges
+// from hubs (u >= h0) are left out: their triangles are counted on the matrix cores.
 __global__ void k_csc_keys(const uint32_t *__restrict__ col, const uint32_t *__restrict__ src,
                            const uint32_t *__restrict__ row_ptr,
                            const uint64_t *__restrict__ vr, const uint64_t *__restrict__ pr,
                            uint32_t mf, uint32_t n, uint32_t nblk, uint32_t p0, uint32_t kp,
-                           uint64_t *__restrict__ keys, uint2 *__restrict__ eu,
+                           uint32_t h0, uint64_t *__restrict__ keys, uint2 *__restrict__ eu,
                            const int32_t *__restrict__ status) {
     if (*status) return;
     uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -309,7 +310,7 @@ __global__ void k_csc_keys(const uint32_t *__restrict__ col, const uint32_t *__r
     const uint32_t end_u = row_ptr[u + 1];
     uint64_t c = (uint64_t)nblk * (n + 1);
     uint32_t mask = 1u;
-    if (e + 1 < end_u) {
+    if (e + 1 < end_u && u < h0) {  // triangles whose lowest vertex is a hub: hub.hip
         uint32_t list = v;
         uint64_t r = vr[v];
         bool run_start = false;

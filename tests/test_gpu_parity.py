@@ -171,6 +171,20 @@ def test_wave_item_forms(monkeypatch, span):
         assert check_vs_oracle(complete(k), k) == math.comb(k, 3)
 
 
+@pytest.mark.parametrize("hubs", ["0", "1", "63", "64", "100", "1000", "5000"])
+def test_hub_matrix_path(monkeypatch, hubs):
+    """Triangles among the top ranks counted as a masked int8 product on the matrix cores,
+    the rest by the middle-vertex kernel, totals and per-vertex counts: no hubs, one hub, hub
+    counts that are and are not multiples of the 64-wide tiles, and graphs that are all hubs."""
+    monkeypatch.setenv("TC_HUB_RANKS", hubs)
+    for e, n in [synth.er_1000(), (synth.barabasi_albert(3000, 12, 2), 3000),
+                 synth.rmat_graph(13, 16, seed=8), (synth.erdos_renyi(700, 0.5, 3), 700),
+                 (synth.watts_strogatz(2500, 8, 0.1, 4), 2500)]:
+        check_vs_oracle(e.numpy(), n)
+    for k in [3, 40, 130]:
+        assert check_vs_oracle(complete(k), k) == math.comb(k, 3)
+
+
 def test_prepared_recount():
     """A resident preprocessed graph counted repeatedly, with and without per-vertex counts."""
     e, n = synth.rmat_graph(13, 16, seed=12, device=DEV)
