@@ -29,12 +29,11 @@
  *     neighbour ids, worked through one after another.  TC_PANEL_RANKS (unset = the
  *     largest value the counting kernel supports, 16352; 0 = off) sets how many of the
  *     highest ranks of the order of Section 2.2 are counted as panels of 32 consecutive
- *     middle vertices.  TC_HUB_RANKS (unset = 16384 for graphs of at least 2^24 oriented
- *     edges, 0 below; at most 65536) sets how many of the highest ranks are hubs, whose
- *     triangles (those whose lowest vertex is a hub) are counted as a masked int8 matrix
- *     product on the matrix cores (two hubs x hubs byte matrices in the workspace).  They
- *     change tc_workspace_size and must not change between a tc_preprocess and the calls
- *     that use its workspace.
+ *     middle vertices.  TC_HUB_RANKS (unset = 0 = off; at most 65536) sets how many of the
+ *     highest ranks are hubs, whose triangles (those whose lowest vertex is a hub) are
+ *     counted as a masked int8 matrix product on the matrix cores (two hubs x hubs byte
+ *     matrices in the workspace).  They change tc_workspace_size and must not change between
+ *     a tc_preprocess and the calls that use its workspace.
  */
 #ifndef TC_H
 #define TC_H
