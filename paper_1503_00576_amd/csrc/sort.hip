@@ -125,19 +125,166 @@ hipError_t scan_exclusive_u32(const uint32_t *in, uint32_t *out, uint64_t N, uin
 
 // ======================================================================= radix sort
 
-constexpr int kSortThreads = 256;
+// A tile is 8192 keys for 512 threads; wave w owns the contiguous keys [1024 w, 1024 (w + 1))
+// of the tile as 16 rows of 64, so that a wave ranks its keys with counters of its own and
+// the tile needs no barrier per row: the stable order of the tile is wave by wave, row by
+// row, lane by lane.
+constexpr int kSortThreads = 512;
 constexpr int kSortItems = 16;
-constexpr int kSortTile = kSortThreads * kSortItems;  // 4096 keys per tile
-constexpr int kSortWaves = kSortThreads / kWave;
+constexpr int kSortWaves = kSortThreads / kWave;     // 8
+constexpr int kSortTile = kSortThreads * kSortItems;  // 8192 keys per tile
 
-// Lanes holding the same digit: returns the mask of such (valid) lanes.
-__device__ __forceinline__ uint64_t match_digit(uint32_t d, uint32_t nbits, bool valid) {
-    uint64_t peers = __ballot(valid);
-    for (uint32_t b = 0; b < nbits; ++b) {
-        uint64_t bb = __ballot((d >> b) & 1u);
-        peers &= ((d >> b) & 1u) ? bb : ~bb;
+// Lanes holding the same 8-bit digit as the calling lane: returns the mask of such (valid)
+// lanes.  Per bit: m = all ones where the lane's bit is set, the ballot of that bit, and
+// peers &= ~(ballot ^ m) on both halves.
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
+    const uint64_t v = __ballot(valid);
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const uint32_t m = (uint32_t)((int32_t)(d << (31 - b)) >> 31);
+        const uint64_t bb = __ballot(m != 0u);
+        lo &= ~((uint32_t)bb ^ m);
+        hi &= ~((uint32_t)(bb >> 32) ^ m);
     }
-    return peers;
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t tile_key_index(uint64_t base, uint32_t w, int r) {
+    return base + (uint64_t)w * (kSortItems * kWave) + (uint64_t)r * kWave + lane_id();
+}
+
+// Loads the calling wave's 16 rows of the tile (all loads in flight before any use);
+// kFull: the whole tile lies below count.
+template <bool kFull>
+__device__ __forceinline__ void load_tile_keys(const uint64_t *__restrict__ in, uint32_t count,
+                                               uint64_t base, uint32_t w,
+                                               uint64_t (&keys)[kSortItems]) {
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const uint64_t idx = tile_key_index(base, w, r);
+        keys[r] = (kFull || idx < count) ? in[idx] : 0ull;
+    }
+}
+
+// Per-wave digit counts of the wave's rows into cnt[256] (the wave's own row of counters,
+// zero on entry), and each key's rank among the wave's earlier keys of the same digit.
+template <bool kFull>
+__device__ __forceinline__ void wave_rank_rows(const uint64_t (&keys)[kSortItems], uint32_t count,
+                                               uint64_t base, uint32_t w, int shift,
+                                               uint32_t mask, uint32_t *cnt,
+                                               uint32_t (&ranks)[kSortItems]) {
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const bool valid = kFull || tile_key_index(base, w, r) < count;
+        const uint32_t d = (uint32_t)(keys[r] >> shift) & mask;
+        const uint64_t peers = match_digit(d, valid);
+        const uint32_t below = lanes_below(peers);
+        const uint32_t prev = valid ? cnt[d] : 0u;
+        ranks[r] = prev + below;
+        if (valid && below == 0) cnt[d] = prev + (uint32_t)__popcll(peers);
+        wave_lds_sync();  // this row's counter updates before the next row's reads
+    }
+}
+
+// Shared state of one tile's stable placement in digit order.
+struct SortTileLds {
+    uint64_t stage[kSortTile];
+    uint32_t wcnt[kSortWaves][256];  // per-wave digit counts, then per-wave digit offsets
+    uint32_t loc[256];               // tile-local start of each digit
+    uint32_t glob[256];              // global start minus local start of each digit
+    uint32_t dsum[4];                // per-wave sums of the digit scan (digits by 4 waves)
+    uint32_t gsum[4];                // the same for the global digit counts (single sweep)
+};
+
+// Block part of the placement (all threads, after the waves' counts are in wcnt): turns wcnt
+// into per-wave digit offsets, fills loc, and returns the tile's count of digit t (t < 256).
+__device__ __forceinline__ uint32_t tile_digit_offsets(SortTileLds &L) {
+    const uint32_t t = threadIdx.x;
+    __syncthreads();
+    uint32_t c = 0;
+    if (t < 256) {
+#pragma unroll
+        for (int k = 0; k < kSortWaves; ++k) {
+            const uint32_t x = L.wcnt[k][t];
+            L.wcnt[k][t] = c;
+            c += x;
+        }
+    }
+    const uint32_t incl = wave_incl_scan(t < 256 ? c : 0u);
+    if (t < 256 && lane_id() == kWave - 1) L.dsum[t / kWave] = incl;
+    __syncthreads();
+    if (t < 256) {
+        uint32_t before = 0;
+        for (uint32_t k = 0; k < t / kWave; ++k) before += L.dsum[k];
+        L.loc[t] = before + incl - c;
+    }
+    return c;
+}
+
+// Places the wave's keys in L.stage (after tile_digit_offsets and a barrier).
+template <bool kFull>
+__device__ __forceinline__ void stage_keys(SortTileLds &L, const uint64_t (&keys)[kSortItems],
+                                           const uint32_t (&ranks)[kSortItems], uint32_t count,
+                                           uint64_t base, uint32_t w, int shift, uint32_t mask) {
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        if (kFull || tile_key_index(base, w, r) < count) {
+            const uint32_t d = (uint32_t)(keys[r] >> shift) & mask;
+            L.stage[L.loc[d] + L.wcnt[w][d] + ranks[r]] = keys[r];
+        }
+    }
+}
+
+// Writes the staged tile: consecutive threads write consecutive positions of one digit's run
+// (L.glob[d] + j is the output position of staged key j of digit d).
+template <bool kFull>
+__device__ __forceinline__ void write_staged(const SortTileLds &L, uint64_t *__restrict__ out,
+                                             uint32_t count, uint64_t base, int shift,
+                                             uint32_t mask, int32_t *status) {
+    const uint64_t rest = count - base;
+    const uint32_t ntile = kFull ? (uint32_t)kSortTile : (uint32_t)rest;
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        const uint32_t j = (uint32_t)i * kSortThreads + threadIdx.x;
+        if (kFull || j < ntile) {
+            const uint64_t key = L.stage[j];
+            const uint32_t d = (uint32_t)(key >> shift) & mask;
+            const uint32_t pos = L.glob[d] + j;
+            if (!status) {
+                out[pos] = key;
+            } else if (pos < count) {  // holds whenever the prefixes are right
+                out[pos] = key;
+            } else {
+                set_status(status, TC_E_HIP);
+            }
+        }
+    }
+}
+
+template <bool kFull>
+__device__ __forceinline__ void hist_tile(const uint64_t *__restrict__ in, uint32_t count,
+                                          int shift, uint32_t mask, uint32_t *__restrict__ hist,
+                                          uint32_t tiles, uint32_t tile,
+                                          uint32_t (&h)[kSortWaves][256]) {
+    const uint32_t t = threadIdx.x, w = t / kWave;
+    const uint64_t base = (uint64_t)tile * kSortTile;
+    uint64_t keys[kSortItems];
+    load_tile_keys<kFull>(in, count, base, w, keys);
+    for (uint32_t k = lane_id(); k < 256; k += kWave) h[w][k] = 0;
+    wave_lds_sync();
+    // counts only (no ranks): one LDS atomic per key into the wave's own counters
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r)
+        if (kFull || tile_key_index(base, w, r) < count)
+            atomicAdd(&h[w][(uint32_t)(keys[r] >> shift) & mask], 1u);
+    __syncthreads();
+    if (t < 256) {
+        uint32_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < kSortWaves; ++k) sum += h[k][t];
+        hist[(uint64_t)t * tiles + tile] = sum;
+    }
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t *__restrict__ in,
@@ -148,98 +295,51 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t *__r
                                                              const int32_t *__restrict__ status) {
     if (status && *status) return;
     __shared__ uint32_t h[kSortWaves][256];
-    const uint32_t t = threadIdx.x, w = t / kWave;
-    for (int k = 0; k < kSortWaves; ++k) h[k][t] = 0;
-    __syncthreads();
-    const uint32_t mask = (1u << nbits) - 1u;
     const uint32_t tile = xcd_tile(blockIdx.x, tiles);
-    const uint64_t base = (uint64_t)tile * kSortTile;
-    uint32_t dg[kSortItems];  // all loads in flight before any ranking
-#pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
-        uint64_t idx = base + (uint64_t)r * kSortThreads + t;
-        dg[r] = idx < count ? (uint32_t)(in[idx] >> shift) & mask : 0xFFFFFFFFu;
-    }
-#pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
-        bool valid = dg[r] != 0xFFFFFFFFu;
-        uint32_t d = valid ? dg[r] : 0u;
-        uint64_t peers = match_digit(d, nbits, valid);
-        if (valid && lanes_below(peers) == 0) h[w][d] += (uint32_t)__popcll(peers);
-    }
-    __syncthreads();
-    uint32_t sum = 0;
-    for (int k = 0; k < kSortWaves; ++k) sum += h[k][t];
-    hist[(uint64_t)t * tiles + tile] = sum;
+    const uint32_t mask = (1u << nbits) - 1u;
+    if ((uint64_t)(tile + 1) * kSortTile <= count)
+        hist_tile<true>(in, count, shift, mask, hist, tiles, tile, h);
+    else
+        hist_tile<false>(in, count, shift, mask, hist, tiles, tile, h);
 }
 
-// Stable scatter of one 4096-key tile: the keys are first ranked and placed in LDS in digit
-// order (tile-local counting sort), then written out so that consecutive threads write
-// consecutive positions of one digit's run.
-//   hist: raw per-tile digit counts (digit-major), offs: their exclusive scan
+// Stable scatter of one tile: the keys are ranked and placed in LDS in digit order (a
+// tile-local counting sort), then written out digit run by digit run.
+//   offs: exclusive scan of the digit-major table of per-tile digit counts
+template <bool kFull>
+__device__ __forceinline__ void scatter_tile(const uint64_t *__restrict__ in,
+                                             uint64_t *__restrict__ out, uint32_t count,
+                                             int shift, uint32_t mask,
+                                             const uint32_t *__restrict__ offs, uint32_t tiles,
+                                             uint32_t tile, SortTileLds &L) {
+    const uint32_t t = threadIdx.x, w = t / kWave;
+    const uint64_t base = (uint64_t)tile * kSortTile;
+    uint64_t keys[kSortItems];
+    load_tile_keys<kFull>(in, count, base, w, keys);
+    for (uint32_t k = lane_id(); k < 256; k += kWave) L.wcnt[w][k] = 0;
+    wave_lds_sync();
+    uint32_t ranks[kSortItems];
+    wave_rank_rows<kFull>(keys, count, base, w, shift, mask, L.wcnt[w], ranks);
+    tile_digit_offsets(L);
+    if (t < 256) L.glob[t] = offs[(uint64_t)t * tiles + tile] - L.loc[t];
+    __syncthreads();
+    stage_keys<kFull>(L, keys, ranks, count, base, w, shift, mask);
+    __syncthreads();
+    write_staged<kFull>(L, out, count, base, shift, mask, nullptr);
+}
+
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint64_t *__restrict__ in, uint64_t *__restrict__ out, uint32_t count, int shift,
-    uint32_t nbits, const uint32_t *__restrict__ hist, const uint32_t *__restrict__ offs,
-    uint32_t tiles, const int32_t *__restrict__ status) {
+    uint32_t nbits, const uint32_t *__restrict__ offs, uint32_t tiles,
+    const int32_t *__restrict__ status) {
     if (status && *status) return;
-    __shared__ uint64_t s_stage[kSortTile];
-    __shared__ uint32_t s_loc[256];   // next local position per digit
-    __shared__ uint32_t s_glob[256];  // global start minus local start per digit
-    __shared__ uint32_t s_wcnt[kSortWaves][256];
-    __shared__ uint32_t s_wsum[kSortWaves];
-    const uint32_t t = threadIdx.x, w = t / kWave;
+    __shared__ SortTileLds L;
     const uint32_t tile = xcd_tile(blockIdx.x, tiles);
-    // tile-local exclusive offsets of the digits
-    const uint32_t c = hist[(uint64_t)t * tiles + tile];
-    const uint32_t incl = wave_incl_scan(c);
-    if (lane_id() == kWave - 1) s_wsum[w] = incl;
-    for (int k = 0; k < kSortWaves; ++k) s_wcnt[k][t] = 0;
-    __syncthreads();
-    uint32_t before = 0;
-    for (uint32_t k = 0; k < w; ++k) before += s_wsum[k];
-    const uint32_t loc = before + incl - c;
-    s_loc[t] = loc;
-    s_glob[t] = offs[(uint64_t)t * tiles + tile] - loc;
-    __syncthreads();
     const uint32_t mask = (1u << nbits) - 1u;
-    const uint64_t base = (uint64_t)tile * kSortTile;
-    uint64_t keys[kSortItems];  // all loads in flight before any ranking
-#pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
-        uint64_t idx = base + (uint64_t)r * kSortThreads + t;
-        keys[r] = idx < count ? in[idx] : 0ull;
-    }
-#pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
-        uint64_t idx = base + (uint64_t)r * kSortThreads + t;
-        bool valid = idx < count;
-        uint64_t key = keys[r];
-        uint32_t d = (uint32_t)(key >> shift) & mask;
-        uint64_t peers = match_digit(d, nbits, valid);
-        uint32_t rank = lanes_below(peers);
-        if (valid && rank == 0) s_wcnt[w][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        if (valid) {
-            uint32_t pos = s_loc[d] + rank;
-            for (uint32_t k = 0; k < w; ++k) pos += s_wcnt[k][d];
-            s_stage[pos] = key;
-        }
-        __syncthreads();
-        uint32_t add = 0;
-        for (int k = 0; k < kSortWaves; ++k) {
-            add += s_wcnt[k][t];
-            s_wcnt[k][t] = 0;
-        }
-        s_loc[t] += add;
-        __syncthreads();
-    }
-    const uint64_t rest = count - base;
-    const uint32_t ntile = rest < (uint64_t)kSortTile ? (uint32_t)rest : (uint32_t)kSortTile;
-    for (uint32_t j = t; j < ntile; j += kSortThreads) {
-        const uint64_t key = s_stage[j];
-        const uint32_t d = (uint32_t)(key >> shift) & mask;
-        out[s_glob[d] + j] = key;
-    }
+    if ((uint64_t)(tile + 1) * kSortTile <= count)
+        scatter_tile<true>(in, out, count, shift, mask, offs, tiles, tile, L);
+    else
+        scatter_tile<false>(in, out, count, shift, mask, offs, tiles, tile, L);
 }
 
 // ---------------------------------------------------------------- single-sweep variant
@@ -251,7 +351,7 @@ constexpr uint32_t kLbMaxPolls = 1u << 20;  // bound on the polls of one look-ba
 constexpr int kMaxPasses = 8;
 
 // digit counts of every pass over all keys: ghist[p * 256 + d]
-__global__ __launch_bounds__(kSortThreads) void k_radix_digits(
+__global__ __launch_bounds__(256) void k_radix_digits(
     const uint64_t *__restrict__ in, uint32_t count, int lo_bit, int passes, int hi_bit,
     uint32_t *__restrict__ ghist, const int32_t *__restrict__ status) {
     if (*status) return;
@@ -259,8 +359,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_digits(
     const uint32_t t = threadIdx.x;
     for (int p = 0; p < kMaxPasses; ++p) h[p][t] = 0;
     __syncthreads();
-    const uint64_t stride = (uint64_t)gridDim.x * kSortThreads;
-    for (uint64_t i = (uint64_t)blockIdx.x * kSortThreads + t; i < count; i += stride) {
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + t; i < count; i += stride) {
         const uint64_t k = in[i];
         for (int p = 0; p < passes; ++p) {
             const int sh = lo_bit + 8 * p;
@@ -275,127 +375,84 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_digits(
 
 // One pass: tile ids in launch order; flags[tile * 256 + d] = kLbAgg | count, then
 // kLbIncl | inclusive prefix, of digit d.
+template <bool kFull>
+__device__ __forceinline__ void onesweep_tile(const uint64_t *__restrict__ in,
+                                              uint64_t *__restrict__ out, uint32_t count,
+                                              int shift, uint32_t mask,
+                                              const uint32_t *__restrict__ ghist,
+                                              uint32_t *__restrict__ flags, uint32_t tile,
+                                              int32_t *__restrict__ status, SortTileLds &L) {
+    const uint32_t t = threadIdx.x, w = t / kWave;
+    const uint64_t base = (uint64_t)tile * kSortTile;
+    uint64_t keys[kSortItems];
+    load_tile_keys<kFull>(in, count, base, w, keys);
+    for (uint32_t k = lane_id(); k < 256; k += kWave) L.wcnt[w][k] = 0;
+    wave_lds_sync();
+    uint32_t ranks[kSortItems];
+    wave_rank_rows<kFull>(keys, count, base, w, shift, mask, L.wcnt[w], ranks);
+    const uint32_t c = tile_digit_offsets(L);
+    if (t < 256)
+        __hip_atomic_store(&flags[(uint64_t)tile * 256 + t], (tile == 0 ? kLbIncl : kLbAgg) | c,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // the global start of every digit
+    const uint32_t gc = t < 256 ? ghist[t] : 0u;
+    const uint32_t gincl = wave_incl_scan(gc);
+    if (t < 256 && lane_id() == kWave - 1) L.gsum[w] = gincl;
+    __syncthreads();
+    stage_keys<kFull>(L, keys, ranks, count, base, w, shift, mask);
+    if (t < 256) {
+        uint32_t gbefore = 0;
+        for (uint32_t k = 0; k < w; ++k) gbefore += L.gsum[k];
+        const uint32_t gstart = gbefore + gincl - gc;
+        // look-back: keys of digit t in the tiles before this one
+        uint32_t excl = 0;
+        if (tile > 0) {
+            uint32_t j = tile - 1, polls = 0;
+            for (;;) {
+                const uint32_t f = __hip_atomic_load(&flags[(uint64_t)j * 256 + t],
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((f & ~kLbValue) == 0) {
+                    if (++polls >= kLbMaxPolls) {
+                        set_status(status, TC_E_HIP);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                excl += f & kLbValue;
+                if (f & kLbIncl) break;
+                --j;  // tile 0 publishes an inclusive prefix, so j never passes it
+            }
+            __hip_atomic_store(&flags[(uint64_t)tile * 256 + t], kLbIncl | (excl + c),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        L.glob[t] = gstart + excl - L.loc[t];
+    }
+    __syncthreads();
+    write_staged<kFull>(L, out, count, base, shift, mask, status);
+}
+
 __global__ __launch_bounds__(kSortThreads) void k_radix_onesweep(
     const uint64_t *__restrict__ in, uint64_t *__restrict__ out, uint32_t count, int shift,
     uint32_t nbits, const uint32_t *__restrict__ ghist, uint32_t *__restrict__ flags,
     uint32_t *__restrict__ tile_counter, int32_t *__restrict__ status) {
-    __shared__ uint64_t s_stage[kSortTile];
-    __shared__ uint32_t s_loc[256], s_glob[256];
-    __shared__ uint32_t s_wcnt[kSortWaves][256];
-    __shared__ uint32_t s_wsum[kSortWaves], s_gsum[kSortWaves];
+    __shared__ SortTileLds L;
     __shared__ uint32_t s_tile;
     __shared__ int s_stop;
-    const uint32_t t = threadIdx.x, w = t / kWave;
-    if (t == 0) {
+    if (threadIdx.x == 0) {
         s_tile = atomicAdd(tile_counter, 1u);
         s_stop = __hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
     }
-    for (int k = 0; k < kSortWaves; ++k) s_wcnt[k][t] = 0;
     __syncthreads();
     // after an error (earlier kernels, or a look-back bound reached in this one) tiles stop
     // before publishing; their successors' bounded waits end too
     if (s_stop) return;
     const uint32_t tile = s_tile;
     const uint32_t mask = (1u << nbits) - 1u;
-    const uint64_t base = (uint64_t)tile * kSortTile;
-    uint64_t keys[kSortItems];
-#pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
-        const uint64_t idx = base + (uint64_t)r * kSortThreads + t;
-        keys[r] = idx < count ? in[idx] : 0ull;
-    }
-    // this tile's digit counts
-#pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
-        const bool valid = base + (uint64_t)r * kSortThreads + t < count;
-        const uint32_t d = (uint32_t)(keys[r] >> shift) & mask;
-        const uint64_t peers = match_digit(d, nbits, valid);
-        if (valid && lanes_below(peers) == 0) s_wcnt[w][d] += (uint32_t)__popcll(peers);
-    }
-    __syncthreads();
-    uint32_t c = 0;
-    for (int k = 0; k < kSortWaves; ++k) {
-        c += s_wcnt[k][t];
-        s_wcnt[k][t] = 0;
-    }
-    __hip_atomic_store(&flags[(uint64_t)tile * 256 + t], (tile == 0 ? kLbIncl : kLbAgg) | c,
-                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    // tile-local exclusive offsets of the digits, and the global digit starts
-    const uint32_t gc = ghist[t];
-    const uint32_t incl = wave_incl_scan(c), gincl = wave_incl_scan(gc);
-    if (lane_id() == kWave - 1) {
-        s_wsum[w] = incl;
-        s_gsum[w] = gincl;
-    }
-    __syncthreads();
-    uint32_t before = 0, gbefore = 0;
-    for (uint32_t k = 0; k < w; ++k) {
-        before += s_wsum[k];
-        gbefore += s_gsum[k];
-    }
-    const uint32_t loc = before + incl - c;
-    const uint32_t gstart = gbefore + gincl - gc;
-    s_loc[t] = loc;
-    __syncthreads();
-    // stable placement of the tile in digit order (as in k_radix_scatter)
-#pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
-        const bool valid = base + (uint64_t)r * kSortThreads + t < count;
-        const uint64_t key = keys[r];
-        const uint32_t d = (uint32_t)(key >> shift) & mask;
-        const uint64_t peers = match_digit(d, nbits, valid);
-        const uint32_t rank = lanes_below(peers);
-        if (valid && rank == 0) s_wcnt[w][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        if (valid) {
-            uint32_t pos = s_loc[d] + rank;
-            for (uint32_t k = 0; k < w; ++k) pos += s_wcnt[k][d];
-            s_stage[pos] = key;
-        }
-        __syncthreads();
-        uint32_t add = 0;
-        for (int k = 0; k < kSortWaves; ++k) {
-            add += s_wcnt[k][t];
-            s_wcnt[k][t] = 0;
-        }
-        s_loc[t] += add;
-        __syncthreads();
-    }
-    // look-back: keys of digit t in the tiles before this one
-    uint32_t excl = 0;
-    if (tile > 0) {
-        uint32_t j = tile - 1, polls = 0;
-        for (;;) {
-            const uint32_t f = __hip_atomic_load(&flags[(uint64_t)j * 256 + t],
-                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if ((f & ~kLbValue) == 0) {
-                if (++polls >= kLbMaxPolls) {
-                    set_status(status, TC_E_HIP);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-                continue;
-            }
-            excl += f & kLbValue;
-            if (f & kLbIncl) break;
-            --j;  // tile 0 publishes an inclusive prefix, so j never passes it
-        }
-        __hip_atomic_store(&flags[(uint64_t)tile * 256 + t], kLbIncl | (excl + c),
-                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    s_glob[t] = gstart + excl - loc;
-    __syncthreads();
-    const uint64_t rest = count - base;
-    const uint32_t ntile = rest < (uint64_t)kSortTile ? (uint32_t)rest : (uint32_t)kSortTile;
-    for (uint32_t j = t; j < ntile; j += kSortThreads) {
-        const uint64_t key = s_stage[j];
-        const uint32_t d = (uint32_t)(key >> shift) & mask;
-        const uint32_t pos = s_glob[d] + j;
-        if (pos < count)  // holds whenever the prefixes are right; never write outside `out`
-            out[pos] = key;
-        else
-            set_status(status, TC_E_HIP);
-    }
+    if ((uint64_t)(tile + 1) * kSortTile <= count)
+        onesweep_tile<true>(in, out, count, shift, mask, ghist, flags, tile, status, L);
+    else
+        onesweep_tile<false>(in, out, count, shift, mask, ghist, flags, tile, status, L);
 }
 
 static bool onesweep_enabled() {  // TC_SORT_ONESWEEP=1 switches the variant on
@@ -427,7 +484,7 @@ hipError_t sort_u64(uint64_t *keys, uint64_t *tmp, uint32_t count, int lo_bit, i
         uint32_t *flags = hist, *ghist = offs, *counters = offs + kMaxPasses * 256;
         hipError_t e = fill_u32(ghist, 0u, kMaxPasses * 256 + kMaxPasses, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_radix_digits, dim3(2048), dim3(kSortThreads), 0, s, keys, count,
+        hipLaunchKernelGGL(k_radix_digits, dim3(2048), dim3(256), 0, s, keys, count,
                            lo_bit, passes, hi_bit, ghist, status);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         for (int p = 0; p < passes; ++p) {
@@ -454,7 +511,7 @@ hipError_t sort_u64(uint64_t *keys, uint64_t *tmp, uint32_t count, int lo_bit, i
         e = scan_exclusive_u32(hist, offs, hist_n, scan_scratch, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_radix_scatter, dim3(tiles), dim3(kSortThreads), 0, s, src, dst,
-                           count, shift, nbits, hist, offs, tiles, status);
+                           count, shift, nbits, offs, tiles, status);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         uint64_t *x = src;

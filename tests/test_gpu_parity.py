@@ -223,8 +223,9 @@ def test_preprocess_stages():
             assert sorted(perm[row].tolist()) == ocol[orp[v]:orp[v + 1]].tolist()
 
 
-@pytest.mark.parametrize("count,bits", [(1, 8), (100, 7), (4096, 64), (4097, 40), (100003, 46),
-                                        (1 << 20, 20), (3_000_001, 33)])
+@pytest.mark.parametrize("count,bits", [(1, 8), (100, 7), (4096, 64), (4097, 40), (8192, 64),
+                                        (8193, 12), (24575, 3), (100003, 46), (1 << 20, 20),
+                                        (3_000_001, 33)])
 def test_radix_sort(count, bits):
     g = torch.Generator().manual_seed(count + bits)
     keys = torch.randint(-(1 << 62), 1 << 62, (count,), generator=g, dtype=torch.int64)
