@@ -9,10 +9,10 @@
 namespace tc {
 
 // kernels of prep.hip
-__global__ void k_part_hist(const int2 *, uint64_t, uint32_t, uint32_t, int, uint32_t *, uint32_t,
-                            int32_t *);
-__global__ void k_part_scatter(const int2 *, uint64_t, uint32_t, uint32_t, int, const uint32_t *,
-                               const uint32_t *, uint32_t, uint32_t *);
+__global__ void k_part_hist(const int2 *, uint64_t, uint32_t, uint32_t, int, int, uint32_t *,
+                            uint32_t, int32_t *);
+__global__ void k_part_scatter(const int2 *, uint64_t, uint32_t, uint32_t, int, int,
+                               const uint32_t *, const uint32_t *, uint32_t, uint32_t *, int2 *);
 __global__ void k_part_count(const uint32_t *, const uint32_t *, uint32_t, int, uint32_t,
                              uint32_t, uint32_t *, const int32_t *);
 __global__ void k_degree_atomic(const int2 *, uint64_t, uint32_t, uint32_t, uint32_t *,
@@ -21,6 +21,8 @@ __global__ void k_vkeys(const uint32_t *, uint32_t, int, uint64_t *);
 __global__ void k_rank(const uint64_t *, uint32_t, int, uint32_t *, uint32_t *);
 __global__ void k_orient(const int2 *, uint64_t, uint32_t, const uint32_t *, int, uint64_t *,
                          uint32_t *, const int32_t *);
+__global__ void k_orient_cells(const int2 *, uint64_t, uint32_t, const uint32_t *, int,
+                               uint64_t *, const int32_t *);
 __global__ void k_both_check(const uint32_t *, uint32_t, int32_t *);
 __global__ void k_csr(const uint64_t *, uint32_t, uint32_t, int, uint32_t *, uint32_t *,
                       uint32_t *, uint32_t *, int32_t *);
@@ -71,6 +73,7 @@ struct Layout {
         cmask, items[4], off[4], item_v[4], scan_scratch, tpv, hub_a, hub_at, total_bytes;
     uint32_t part_tiles;  // 0: degrees by atomics (inputs too large for the partition)
     int part_shift;
+    int cell_shift;       // >= 0: edges also partitioned into cells for the orientation
     uint32_t n, m, mf, kcap, id_bits, nblk;
     uint32_t p0, panels;  // panel region: ranks [p0, n) in panels of count_panel() ranks
     uint32_t h0, hp;      // hubs: ranks [h0, n), matrices hp x hp (hp = 0: no hubs)
@@ -80,6 +83,9 @@ struct Layout {
 // item spaces: [0] wave / [1] workgroup items for total counts, [2] / [3] for per-vertex counts
 enum { kCtlStatus = 0, kCtlBoth = 1, kCtlQueueA = 2, kCtlQueueB = 3, kCtlWords = 64 };
 constexpr uint32_t kPartTileEdges = 4096;  // edges per tile of the degree partition
+// workgroups of the orientation over cell-ordered edges (a multiple of the 8 XCDs; 4 per CU
+// measured faster than 8: fewer edges in flight per XCD keep its lookups inside fewer cells)
+constexpr uint32_t kOrientGrid = 1024;
 
 // Row blocks of the in-edge lists: contiguous CSR ranges of at most TC_ROW_BLOCK_BYTES of
 // neighbour ids (at most 8 blocks), worked through one after another by the counting kernel.
@@ -179,7 +185,12 @@ static bool make_layout(int64_t n, int64_t m, uint32_t flags, Layout &L) {
         L.part_tiles = (endpoints < (1ull << 32) && L.part_shift <= 19)
                            ? ceil_div((uint64_t)m > 0 ? (uint64_t)m : 1, kPartTileEdges)
                            : 0u;
-        const uint64_t hp = 256ull * (L.part_tiles ? L.part_tiles : 1) + 1;
+        // one-direction format: the edges are also partitioned into 16 x 16 cells of id ranges
+        L.cell_shift = (L.part_tiles && !(flags & TC_EDGES_BOTH))
+                           ? (L.id_bits > 4 ? (int)L.id_bits - 4 : 0)
+                           : -1;
+        const uint64_t hp = (L.cell_shift >= 0 ? 512ull : 256ull) *
+                                (L.part_tiles ? L.part_tiles : 1) + 1;
         L.part_hist = take(hp * 4);
         L.part_offs = take(hp * 4);
         L.part_scan = take(scan_scratch_words(hp) * 4);
@@ -275,20 +286,23 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
     const bool both = flags & TC_EDGES_BOTH;
 
     uint32_t *scan_scr = at<uint32_t>(ws, L.scan_scratch);
+    // cell-ordered edges for the orientation: the in-edge payload buffer, unused until later
+    int2 *cells = L.cell_shift >= 0 ? at<int2>(ws, L.eu) : nullptr;
     TC_HIP(fill_u32(ctl, 0u, kCtlWords, s));
     TC_HIP(fill_u32(deg, 0u, n, s));
     if (m > 0 && L.part_tiles) {
         const uint32_t tiles = L.part_tiles;
-        const uint64_t hp = 256ull * tiles;
+        const uint64_t hp = (L.cell_shift >= 0 ? 512ull : 256ull) * tiles;
         uint32_t *ph = at<uint32_t>(ws, L.part_hist), *po = at<uint32_t>(ws, L.part_offs);
         uint32_t *parts = (uint32_t *)kb;  // 4-byte endpoints fit the 8-byte key buffer
         TC_HIP(fill_u32(ph + hp, 0u, 1, s));
         hipLaunchKernelGGL(k_part_hist, dim3(tiles), dim3(256), 0, s, edges, (uint64_t)m, n,
-                           (uint32_t)both, L.part_shift, ph, tiles, status);
+                           (uint32_t)both, L.part_shift, L.cell_shift, ph, tiles, status);
         TC_LAUNCH_CHECK();
         TC_HIP(scan_exclusive_u32(ph, po, hp + 1, at<uint32_t>(ws, L.part_scan), s));
         hipLaunchKernelGGL(k_part_scatter, dim3(tiles), dim3(256), 0, s, edges, (uint64_t)m, n,
-                           (uint32_t)both, L.part_shift, ph, po, tiles, parts);
+                           (uint32_t)both, L.part_shift, L.cell_shift, ph, po, tiles, parts,
+                           cells);
         TC_LAUNCH_CHECK();
         const uint32_t buckets = 1u << (L.id_bits - L.part_shift);
         const uint32_t slices = buckets >= 512 ? 1u : 512u / buckets;
@@ -311,8 +325,13 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
     }
     uint64_t *sorted = ka;
     if (m > 0) {
-        hipLaunchKernelGGL(k_orient, dim3(grid_for(m, 256, 8192)), dim3(256), 0, s, edges,
-                           (uint64_t)m, (uint32_t)both, rank, b, ka, ctl + kCtlBoth, status);
+        if (cells) {
+            hipLaunchKernelGGL(k_orient_cells, dim3(kOrientGrid), dim3(256), 0, s, cells,
+                               (uint64_t)m, n, rank, b, ka, status);
+        } else {
+            hipLaunchKernelGGL(k_orient, dim3(grid_for(m, 256, 8192)), dim3(256), 0, s, edges,
+                               (uint64_t)m, (uint32_t)both, rank, b, ka, ctl + kCtlBoth, status);
+        }
         TC_LAUNCH_CHECK();
         if (both) {
             hipLaunchKernelGGL(k_both_check, dim3(1), dim3(64), 0, s, ctl + kCtlBoth, mf, status);

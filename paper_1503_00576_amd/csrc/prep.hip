@@ -38,12 +38,22 @@ __device__ __forceinline__ bool endpoint_ok(int2 e, uint32_t n) {
     return (uint32_t)e.x < n && (uint32_t)e.y < n && e.x != e.y;
 }
 
+// Cells for the orientation's rank lookups (one-direction format): edge (a, b) goes to cell
+// (a >> cs) * 16 + (b >> cs), a pair of id ranges of 2^cs ids each, so that the lookups of
+// a run of edges of one cell touch two short stretches of the rank array.
+__device__ __forceinline__ uint32_t edge_cell(int2 e, int cs) {
+    return (((uint32_t)e.x >> cs) << 4) | ((uint32_t)e.y >> cs);
+}
+
+// hist: digit-major table of per-tile counts, digits 0..255 the endpoint buckets and, when
+// cs >= 0, digits 256..511 the edge cells
 __global__ __launch_bounds__(kPartThreads) void k_part_hist(
-    const int2 *__restrict__ edges, uint64_t m, uint32_t n, uint32_t both, int sh,
+    const int2 *__restrict__ edges, uint64_t m, uint32_t n, uint32_t both, int sh, int cs,
     uint32_t *__restrict__ hist, uint32_t tiles, int32_t *__restrict__ status) {
-    __shared__ uint32_t h[256];
+    __shared__ uint32_t h[256], hc[256];
     const uint32_t t = threadIdx.x;
     h[t] = 0;
+    hc[t] = 0;
     __syncthreads();
     const uint32_t tile = xcd_tile(blockIdx.x, tiles);
     const uint64_t base = (uint64_t)tile * kPartTile;
@@ -65,17 +75,21 @@ __global__ __launch_bounds__(kPartThreads) void k_part_hist(
         }
         atomicAdd(&h[(uint32_t)e.x >> sh], 1u);
         if (!both) atomicAdd(&h[(uint32_t)e.y >> sh], 1u);
+        if (cs >= 0) atomicAdd(&hc[edge_cell(e, cs)], 1u);
     }
     __syncthreads();
     hist[(uint64_t)t * tiles + tile] = h[t];
+    if (cs >= 0) hist[(uint64_t)(256 + t) * tiles + tile] = hc[t];
 }
 
-// endpoints of one tile placed bucket by bucket in LDS, then written as contiguous runs
+// Endpoints of one tile placed bucket by bucket in LDS, then written as contiguous runs; with
+// cs >= 0 the tile's edges then go through the same LDS buffer to their cells' runs (any
+// order inside a run).
 __global__ __launch_bounds__(kPartThreads) void k_part_scatter(
-    const int2 *__restrict__ edges, uint64_t m, uint32_t n, uint32_t both, int sh,
+    const int2 *__restrict__ edges, uint64_t m, uint32_t n, uint32_t both, int sh, int cs,
     const uint32_t *__restrict__ hist, const uint32_t *__restrict__ offs, uint32_t tiles,
-    uint32_t *__restrict__ parts) {
-    __shared__ uint32_t s_stage[2 * kPartTile];
+    uint32_t *__restrict__ parts, int2 *__restrict__ cells) {
+    __shared__ __align__(16) uint32_t s_stage[2 * kPartTile];  // endpoints, then edges (int2)
     __shared__ uint32_t s_fill[256], s_glob[256], s_wsum[kPartThreads / kWave];
     const uint32_t t = threadIdx.x, w = t / kWave;
     const uint32_t tile = xcd_tile(blockIdx.x, tiles);
@@ -108,6 +122,33 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scatter(
     for (uint32_t j = t; j < total; j += kPartThreads) {
         const uint32_t x = s_stage[j];
         parts[s_glob[x >> sh] + j] = x;
+    }
+    if (cs < 0) return;
+    // cells: the same placement with the cell digits (entries 256.. of the tables; their
+    // global positions start after all endpoints, at entry 256 * tiles of the scan)
+    const uint32_t cc = hist[(uint64_t)(256 + t) * tiles + tile];
+    const uint32_t cincl = wave_incl_scan(cc);
+    __syncthreads();  // every read of s_stage, s_fill, s_glob and s_wsum above is done
+    if (lane_id() == kWave - 1) s_wsum[w] = cincl;
+    __syncthreads();
+    uint32_t cbefore = 0;
+    for (uint32_t k = 0; k < w; ++k) cbefore += s_wsum[k];
+    const uint32_t cloc = cbefore + cincl - cc;
+    s_fill[t] = cloc;
+    s_glob[t] = offs[(uint64_t)(256 + t) * tiles + tile] - offs[(uint64_t)256 * tiles] - cloc;
+    __syncthreads();
+    int2 *s_edges = reinterpret_cast<int2 *>(s_stage);
+#pragma unroll
+    for (int r = 0; r < kPartEdges; ++r) {
+        const int2 e = ed[r];
+        if (!endpoint_ok(e, n)) continue;
+        s_edges[atomicAdd(&s_fill[edge_cell(e, cs)], 1u)] = e;
+    }
+    __syncthreads();
+    const uint32_t ctotal = s_fill[255];  // edges of this tile that are valid
+    for (uint32_t j = t; j < ctotal; j += kPartThreads) {
+        const int2 e = s_edges[j];
+        cells[s_glob[edge_cell(e, cs)] + j] = e;
     }
 }
 
@@ -221,6 +262,26 @@ __global__ void k_orient(const int2 *__restrict__ edges, uint64_t m, uint32_t bo
         if (lane_id() == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
         base = wave_bcast(base, (int)leader);
         if (keep) keys[base + lanes_below(mask)] = ((uint64_t)ru << b) | rv;
+    }
+}
+
+// One-direction format, edges in cell order: the workgroups of one XCD (workgroup b runs on
+// XCD b % 8) sweep that XCD's eighth of the array together, so the rank lookups of the
+// edges in flight on an XCD fall into one or two cells, whose two rank stretches stay in
+// that XCD's L2.  The grid is a multiple of 8; ids are checked again, since the cell array
+// holds only the valid edges (an invalid one has already set the status).
+__global__ void k_orient_cells(const int2 *__restrict__ cells, uint64_t m, uint32_t n,
+                               const uint32_t *__restrict__ rank, int b,
+                               uint64_t *__restrict__ keys, const int32_t *__restrict__ status) {
+    if (*status) return;
+    const uint32_t x = blockIdx.x % kXcds, j = blockIdx.x / kXcds, per = gridDim.x / kXcds;
+    const uint64_t lo = m * x / kXcds, hi = m * (x + 1) / kXcds;
+    const uint64_t step = (uint64_t)per * blockDim.x;
+    for (uint64_t i = lo + (uint64_t)j * blockDim.x + threadIdx.x; i < hi; i += step) {
+        const int2 e = cells[i];
+        if ((uint32_t)e.x >= n || (uint32_t)e.y >= n) continue;
+        const uint32_t ru = rank[e.x], rv = rank[e.y];
+        keys[i] = ((uint64_t)min(ru, rv) << b) | max(ru, rv);
     }
 }
 
