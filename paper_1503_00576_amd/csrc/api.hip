@@ -33,10 +33,8 @@ __global__ void k_panel_range(const uint64_t *, uint32_t, uint32_t, uint32_t, ui
 __global__ void k_csc_keys(const uint32_t *, const uint32_t *, const uint32_t *, const uint64_t *,
                            const uint64_t *, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t,
                            uint32_t, uint64_t *, uint2 *, const int32_t *);
-__global__ void k_csc_bounds(const uint64_t *, uint32_t, uint64_t, uint32_t *, uint32_t *,
-                             const int32_t *);
 __global__ void k_csc_final(const uint64_t *, uint32_t, uint64_t, const uint2 *, uint32_t *,
-                            uint32_t *, uint32_t *, const int32_t *);
+                            uint32_t *, uint32_t *, uint32_t *, uint32_t *, const int32_t *);
 __global__ void k_items(const uint32_t *, const uint32_t *, const uint32_t *, uint32_t, uint32_t,
                         uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t *,
                         uint32_t *,
@@ -83,9 +81,10 @@ struct Layout {
 // item spaces: [0] wave / [1] workgroup items for total counts, [2] / [3] for per-vertex counts
 enum { kCtlStatus = 0, kCtlBoth = 1, kCtlQueueA = 2, kCtlQueueB = 3, kCtlWords = 64 };
 constexpr uint32_t kPartTileEdges = 4096;  // edges per tile of the degree partition
-// workgroups of the orientation over cell-ordered edges (a multiple of the 8 XCDs; 4 per CU
-// measured faster than 8: fewer edges in flight per XCD keep its lookups inside fewer cells)
-constexpr uint32_t kOrientGrid = 1024;
+// workgroups of the orientation over cell-ordered edges (a multiple of the 8 XCDs; 2 per CU
+// measured faster than 4 or 8: fewer edges in flight per XCD keep its lookups inside fewer
+// cells)
+constexpr uint32_t kOrientGrid = 512;
 
 // Row blocks of the in-edge lists: contiguous CSR ranges of at most TC_ROW_BLOCK_BYTES of
 // neighbour ids (at most 8 blocks), worked through one after another by the counting kernel.
@@ -392,17 +391,14 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
     TC_HIP(sort_u64(ck, ck2, mf, 32, 32 + id_bits_for64(l1), sort_scr, status, s, &cks));
     TC_HIP(fill_u32(lrs, 0u, l1, s));
     TC_HIP(fill_u32(lre, 0u, l1, s));
-    hipLaunchKernelGGL(k_csc_bounds, dim3(grid_for(mf, 256)), dim3(256), 0, s, cks, mf, L.lists,
-                       lrs, lre, status);
+    hipLaunchKernelGGL(k_csc_final, dim3(grid_for(mf, 256)), dim3(256), 0, s, cks, mf, L.lists,
+                       eu, at<uint32_t>(ws, L.cbeg), at<uint32_t>(ws, L.cend),
+                       at<uint32_t>(ws, L.cmask), lrs, lre, status);
     TC_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_rowlen, dim3(grid_for(l1, 256)), dim3(256), 0, s, lrs, lre,
                        (uint32_t)L.lists, cnt);
     TC_LAUNCH_CHECK();
     TC_HIP(scan_exclusive_u32(cnt, cptr, l1, scan_scr, s));
-    hipLaunchKernelGGL(k_csc_final, dim3(grid_for(mf, 256)), dim3(256), 0, s, cks, mf, L.lists,
-                       eu, at<uint32_t>(ws, L.cbeg), at<uint32_t>(ws, L.cend),
-                       at<uint32_t>(ws, L.cmask), status);
-    TC_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_items, dim3(grid_for(l1, 256)), dim3(256), 0, s, row_ptr, col, cnt, n,
                        L.nblk, L.p0, wave_bits_for(), count_wave_list(false),
                        count_wave_list(true),

@@ -33,6 +33,7 @@ constexpr int kPartThreads = 256;
 constexpr int kPartEdges = 16;                               // edges per thread
 constexpr uint32_t kPartTile = kPartThreads * kPartEdges;    // 4096 edges per tile
 constexpr uint32_t kPartWindow = 32768;                      // LDS counters per workgroup
+constexpr uint32_t kPartLoads = 8;                           // loads in flight per thread
 
 __device__ __forceinline__ bool endpoint_ok(int2 e, uint32_t n) {
     return (uint32_t)e.x < n && (uint32_t)e.y < n && e.x != e.y;
@@ -176,9 +177,18 @@ __global__ __launch_bounds__(1024) void k_part_count(const uint32_t *__restrict_
         for (uint32_t i = t; i < wn; i += blockDim.x) cntr[i] = 0;
         __syncthreads();
         const uint32_t lo = (uint32_t)(id0 + w0);
-        for (uint32_t j = s0 + t; j < s1; j += blockDim.x) {
-            const uint32_t o = parts[j] - lo;
-            if (o < wn) atomicAdd(&cntr[o], 1u);
+        // kPartLoads loads in flight per thread before their LDS increments
+        const uint64_t stride = (uint64_t)blockDim.x * kPartLoads;
+        for (uint64_t j0 = s0 + t; j0 < s1; j0 += stride) {
+            uint32_t x[kPartLoads];
+#pragma unroll
+            for (uint32_t k = 0; k < kPartLoads; ++k) {
+                const uint64_t j = j0 + (uint64_t)k * blockDim.x;
+                x[k] = j < s1 ? parts[j] - lo : 0xFFFFFFFFu;
+            }
+#pragma unroll
+            for (uint32_t k = 0; k < kPartLoads; ++k)
+                if (x[k] < wn) atomicAdd(&cntr[x[k]], 1u);
         }
         __syncthreads();
         for (uint32_t i = t; i < wn; i += blockDim.x) {
@@ -268,8 +278,9 @@ __global__ void k_orient(const int2 *__restrict__ edges, uint64_t m, uint32_t bo
 // One-direction format, edges in cell order: the workgroups of one XCD (workgroup b runs on
 // XCD b % 8) sweep that XCD's eighth of the array together, so the rank lookups of the
 // edges in flight on an XCD fall into one or two cells, whose two rank stretches stay in
-// that XCD's L2.  The grid is a multiple of 8; ids are checked again, since the cell array
-// holds only the valid edges (an invalid one has already set the status).
+// that XCD's L2.  Each thread has two edges in flight (a step apart).  The grid is a multiple
+// of 8; ids are checked again, since the cell array holds only the valid edges (an invalid
+// one has already set the status).
 __global__ void k_orient_cells(const int2 *__restrict__ cells, uint64_t m, uint32_t n,
                                const uint32_t *__restrict__ rank, int b,
                                uint64_t *__restrict__ keys, const int32_t *__restrict__ status) {
@@ -277,11 +288,23 @@ __global__ void k_orient_cells(const int2 *__restrict__ cells, uint64_t m, uint3
     const uint32_t x = blockIdx.x % kXcds, j = blockIdx.x / kXcds, per = gridDim.x / kXcds;
     const uint64_t lo = m * x / kXcds, hi = m * (x + 1) / kXcds;
     const uint64_t step = (uint64_t)per * blockDim.x;
-    for (uint64_t i = lo + (uint64_t)j * blockDim.x + threadIdx.x; i < hi; i += step) {
-        const int2 e = cells[i];
-        if ((uint32_t)e.x >= n || (uint32_t)e.y >= n) continue;
-        const uint32_t ru = rank[e.x], rv = rank[e.y];
-        keys[i] = ((uint64_t)min(ru, rv) << b) | max(ru, rv);
+    for (uint64_t i0 = lo + (uint64_t)j * blockDim.x + threadIdx.x; i0 < hi; i0 += 2 * step) {
+        const uint64_t i1 = i0 + step;
+        const int2 e0 = cells[i0];
+        const int2 e1 = i1 < hi ? cells[i1] : make_int2(0, 0);
+        const bool ok0 = (uint32_t)e0.x < n && (uint32_t)e0.y < n;
+        const bool ok1 = i1 < hi && (uint32_t)e1.x < n && (uint32_t)e1.y < n;
+        uint32_t r0u = 0, r0v = 0, r1u = 0, r1v = 0;
+        if (ok0) {
+            r0u = rank[e0.x];
+            r0v = rank[e0.y];
+        }
+        if (ok1) {
+            r1u = rank[e1.x];
+            r1v = rank[e1.y];
+        }
+        if (ok0) keys[i0] = ((uint64_t)min(r0u, r0v) << b) | max(r0u, r0v);
+        if (ok1) keys[i1] = ((uint64_t)min(r1u, r1v) << b) | max(r1u, r1v);
     }
 }
 
@@ -398,30 +421,22 @@ __global__ void k_csc_keys(const uint32_t *__restrict__ col, const uint32_t *__r
     eu[e] = make_uint2(end_u, mask);
 }
 
-// list boundaries of the sorted keys (useful in-edges only)
-__global__ void k_csc_bounds(const uint64_t *__restrict__ keys, uint32_t mf, uint64_t lists,
-                             uint32_t *__restrict__ rs, uint32_t *__restrict__ re,
-                             const int32_t *__restrict__ status) {
-    if (*status) return;
-    uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= mf) return;
-    const uint64_t c = keys[j] >> 32;
-    if (c >= lists) return;
-    if (j == 0 || (keys[j - 1] >> 32) != c) rs[c] = j;
-    if (j == mf - 1 || (keys[j + 1] >> 32) != c) re[c] = j + 1;
-}
-
-// the lists themselves: in-edge u -> v at CSR position e contributes the suffix [e + 1, end_u)
-// and, in a panel list, the mask of u's run of panel vertices (k_csc_keys)
+// The lists themselves: in-edge u -> v at CSR position e contributes the suffix [e + 1, end_u)
+// and, in a panel list, the mask of u's run of panel vertices (k_csc_keys); list c occupies
+// sorted positions [rs[c], re[c]) (useful in-edges only; rs and re zeroed beforehand).
 __global__ void k_csc_final(const uint64_t *__restrict__ keys, uint32_t mf, uint64_t lists,
                             const uint2 *__restrict__ eu, uint32_t *__restrict__ cbeg,
                             uint32_t *__restrict__ cend, uint32_t *__restrict__ cmask,
+                            uint32_t *__restrict__ rs, uint32_t *__restrict__ re,
                             const int32_t *__restrict__ status) {
     if (*status) return;
     uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= mf) return;
     const uint64_t k = keys[j];
-    if ((k >> 32) >= lists) return;
+    const uint64_t c = k >> 32;
+    if (c >= lists) return;
+    if (j == 0 || (keys[j - 1] >> 32) != c) rs[c] = j;
+    if (j == mf - 1 || (keys[j + 1] >> 32) != c) re[c] = j + 1;
     const uint32_t e = (uint32_t)k;
     const uint2 x = eu[e];
     cbeg[j] = e + 1;
