@@ -125,12 +125,10 @@ static uint32_t wave_bits_for() {
     return (uint32_t)x;
 }
 
-// Hubs, whose triangles are counted on the matrix cores: the top TC_HUB_RANKS ranks (0 =
-// off); by default 16384 for graphs of at least 2^24 oriented edges, none for smaller ones.
-// Off unless asked for: at R-MAT scale 23 (1.9e8 edges) 16384 hubs take the sparse kernel from
-// 20.95 to 19.59 ms but add 3.9 ms of matrix products and 0.34 ms of matrix fill.
-static uint32_t hub_ranks_for(uint32_t n, uint32_t mf) {
-    (void)mf;
+// Hubs, whose triangles are counted on the matrix cores: the top TC_HUB_RANKS ranks (unset or
+// 0 = off).  Off unless asked for: at R-MAT scale 23 (1.9e8 edges) 16384 hubs take the sparse
+// kernel from 20.95 to 19.59 ms but add 3.9 ms of matrix products and 0.34 ms of matrix fill.
+static uint32_t hub_ranks_for(uint32_t n) {
     uint64_t x = 0;
     if (const char *env = getenv("TC_HUB_RANKS")) x = strtoull(env, nullptr, 10);
     if (x > (1u << 16)) x = 1u << 16;  // two matrices of at most 4 GiB each
@@ -161,7 +159,7 @@ static bool make_layout(int64_t n, int64_t m, uint32_t flags, Layout &L) {
     L.nblk = row_blocks_for(L.n, L.mf);
     L.p0 = L.n - panel_ranks_for(L.n);
     {
-        const uint32_t h = hub_ranks_for(L.n, L.mf);
+        const uint32_t h = hub_ranks_for(L.n);
         L.h0 = L.n - h;
         L.hp = (h + 63u) & ~63u;
     }
