@@ -95,7 +95,9 @@ struct RowWalk {
     uint32_t rpb[kWave];      // index of the graph's row offsets in row_ptr
     uint32_t ng[kWave];       // vertices of the graph
     uint32_t g[kWave];        // graph
-    uint32_t acc[kWave];      // per-row count of forward entries (counted or written)
+    uint32_t acc[kWave];      // per-row count of forward entries (counted), or the row's next
+                              // output position (written)
+    uint32_t fend[kWave];     // end of the row's forward entries in the output (written)
 };
 
 __device__ __forceinline__ uint32_t walk_owner(const RowWalk &rw, uint32_t idx) {
@@ -134,40 +136,63 @@ __device__ __forceinline__ uint32_t walk_begin(RowWalk &rw, uint32_t d, uint32_t
 
 // One step of the walk: the entry of this lane (if any) with its owner k, its index j in the
 // row, its value y (local id), whether it is a forward entry of an in-range id (the same
-// test in both kernels: the degree of y is its row length in the input), and the lanes of
-// the owner's row in this step [first, last].
+// test in both kernels: the degree of y is its row length in the input), the previous entry
+// of the row (-1 at the row start), and the lanes of the owner's row in this step
+// [first, last].
 struct WalkEntry {
     bool valid, ok, fwd;
     uint32_t k, j, first, last;
-    int32_t y;
+    int32_t y, prev;
 };
 
-__device__ __forceinline__ WalkEntry walk_entry(const RowWalk &rw, uint32_t base, uint32_t total,
-                                                const int32_t *__restrict__ col,
-                                                const int32_t *__restrict__ row_ptr) {
-    WalkEntry en;
-    const uint32_t lane = lane_id(), idx = base + lane;
-    en.valid = idx < total;
-    en.ok = en.fwd = false;
-    en.k = en.j = en.first = en.last = 0;
-    en.y = 0;
-    if (en.valid) {
-        const uint32_t k = walk_owner(rw, idx);
-        en.k = k;
-        en.j = idx - rw.off[k];
-        en.y = col[rw.ebeg[k] + en.j];
-        const uint32_t lk = rw.local[k];
-        en.ok = en.y >= 0 && (uint32_t)en.y < rw.ng[k] && (uint32_t)en.y != lk;
-        if (en.ok) {
-            const int32_t *rp = row_ptr + rw.rpb[k];
-            const int64_t dy = (int64_t)rp[en.y + 1] - rp[en.y], dx = rw.len[k];
-            en.fwd = dy > dx || (dy == dx && (uint32_t)en.y > lk);
-        }
-        const uint32_t rb = rw.off[k], re = rw.off[k] + rw.len[k];
-        en.first = (rb > base ? rb : base) - base;
-        en.last = (re < base + kWave ? re : base + kWave) - 1 - base;
+// kWalkSteps consecutive steps of the walk at once: every load of all of them (entries,
+// previous entries, the row offsets behind the degree test) is issued before any is used,
+// so a wave waits once per kWalkSteps steps instead of once per step.  Addresses of lanes
+// past the end or with an out-of-range id are clamped onto valid ones and their values
+// ignored.
+constexpr int kWalkSteps = 4;
+
+// The argument block's pointers are generic; the walk reads through global-address-space
+// views so that its loads are global loads (waited for apart from the LDS traffic).
+typedef const __attribute__((address_space(1))) int32_t *gptr_i32;
+
+__device__ __forceinline__ void walk_entries(const RowWalk &rw, uint32_t base, uint32_t total,
+                                             const int32_t *col_p, const int32_t *row_ptr_p,
+                                             WalkEntry (&en)[kWalkSteps]) {
+    const gptr_i32 col = (gptr_i32)col_p, row_ptr = (gptr_i32)row_ptr_p;
+    const uint32_t lane = lane_id();
+    int32_t r0[kWalkSteps], r1[kWalkSteps];
+#pragma unroll
+    for (int u = 0; u < kWalkSteps; ++u) {
+        const uint32_t idx = base + (uint32_t)u * kWave + lane;
+        en[u].valid = idx < total;
+        const uint32_t k = walk_owner(rw, en[u].valid ? idx : total - 1);
+        en[u].k = k;
+        en[u].j = (en[u].valid ? idx : total - 1) - rw.off[k];
+        const uint32_t at = rw.ebeg[k] + en[u].j;
+        en[u].y = col[at];
+        en[u].prev = col[at - (en[u].j > 0 ? 1u : 0u)];
     }
-    return en;
+#pragma unroll
+    for (int u = 0; u < kWalkSteps; ++u) {
+        const uint32_t k = en[u].k, lk = rw.local[k];
+        const int32_t y = en[u].y;
+        if (en[u].j == 0) en[u].prev = -1;
+        en[u].ok = en[u].valid && y >= 0 && (uint32_t)y < rw.ng[k] && (uint32_t)y != lk;
+        const uint32_t at = rw.rpb[k] + (en[u].ok ? (uint32_t)y : 0u);
+        r0[u] = row_ptr[at];
+        r1[u] = row_ptr[at + 1];
+    }
+#pragma unroll
+    for (int u = 0; u < kWalkSteps; ++u) {
+        const uint32_t k = en[u].k, lk = rw.local[k];
+        const int64_t dy = (int64_t)r1[u] - r0[u], dx = rw.len[k];
+        en[u].fwd = en[u].ok && (dy > dx || (dy == dx && (uint32_t)en[u].y > lk));
+        const uint32_t sb = base + (uint32_t)u * kWave;
+        const uint32_t rb = rw.off[k], re = rw.off[k] + rw.len[k];
+        en[u].first = (rb > sb ? rb : sb) - sb;
+        en[u].last = (re < sb + kWave ? re : sb + kWave) - 1 - sb;
+    }
 }
 
 // Per vertex: graph id, degree (row length), forward out-degree (entries ncap.. stay zero for
@@ -217,33 +242,37 @@ __global__ __launch_bounds__(256) void k_b_setup(const BatchArgs *__restrict__ a
     // decrease; a change flushes the sum)
     uint32_t hg = 0xFFFFFFFFu;
     uint64_t hsum = 0;
-    for (uint32_t base = 0; base < total; base += kWave) {
-        const WalkEntry en = walk_entry(rw, base, total, a.col, a.row_ptr);
-        if (en.valid) {
-            const uint32_t gk = rw.g[en.k], lk = rw.local[en.k];
-            if (!en.ok) {
-                graph_error(a, gk, (en.y < 0 || (uint32_t)en.y >= rw.ng[en.k]) ? TC_E_RANGE
-                                                                               : TC_E_SELF_LOOP,
-                            gstat);
-            } else {
-                if (en.j > 0) {
-                    const int32_t prev = a.col[rw.ebeg[en.k] + en.j - 1];
-                    if (en.y <= prev)
-                        graph_error(a, gk, en.y == prev ? TC_E_DUP_EDGE : TC_E_UNSORTED, gstat);
+    for (uint32_t base = 0; base < total; base += kWalkSteps * kWave) {
+        WalkEntry ens[kWalkSteps];
+        walk_entries(rw, base, total, a.col, a.row_ptr, ens);
+#pragma unroll
+        for (int u = 0; u < kWalkSteps; ++u) {
+            const WalkEntry &en = ens[u];
+            if (en.valid) {
+                const uint32_t gk = rw.g[en.k], lk = rw.local[en.k];
+                if (!en.ok) {
+                    graph_error(a, gk,
+                                (en.y < 0 || (uint32_t)en.y >= rw.ng[en.k]) ? TC_E_RANGE
+                                                                            : TC_E_SELF_LOOP,
+                                gstat);
+                } else {
+                    if (en.j > 0 && en.y <= en.prev)
+                        graph_error(a, gk, en.y == en.prev ? TC_E_DUP_EDGE : TC_E_UNSORTED,
+                                    gstat);
+                    if (gk != hg) {
+                        if (hsum) atomicAdd(&ghash[hg], (unsigned long long)hsum);
+                        hg = gk;
+                        hsum = 0;
+                    }
+                    hsum += pair_hash(lk, (uint32_t)en.y) - pair_hash((uint32_t)en.y, lk);
                 }
-                if (gk != hg) {
-                    if (hsum) atomicAdd(&ghash[hg], (unsigned long long)hsum);
-                    hg = gk;
-                    hsum = 0;
-                }
-                hsum += pair_hash(lk, (uint32_t)en.y) - pair_hash((uint32_t)en.y, lk);
             }
+            const uint64_t F = __ballot(en.valid && en.fwd);
+            // forward entries per row in this step, added by the row's last lane in the step
+            if (en.valid && lane == en.last)
+                rw.acc[en.k] += (uint32_t)__popcll(F & lane_range(en.first, lane));
+            wave_lds_sync();
         }
-        const uint64_t F = __ballot(en.valid && en.fwd);
-        // forward entries per row in this step, added by the row's last lane in the step
-        if (en.valid && lane == en.last)
-            rw.acc[en.k] += (uint32_t)__popcll(F & lane_range(en.first, lane));
-        wave_lds_sync();
     }
     if (x < ncap) deg[x] = d;
     if (x <= ncap) fdeg[x] = rw.acc[lane];
@@ -281,23 +310,31 @@ __global__ __launch_bounds__(256) void k_b_ffill(const BatchArgs *__restrict__ a
         ng = (uint32_t)(a.vtx_off[g + 1] - v0);
     }
     const uint32_t total = walk_begin(rw, d, ebeg, local, rpb, ng, g);
-    for (uint32_t base = 0; base < total; base += kWave) {
-        const WalkEntry en = walk_entry(rw, base, total, a.col, a.row_ptr);
-        const uint64_t F = __ballot(en.valid && en.fwd);
-        if (en.valid && en.fwd) {
-            const uint32_t xk = x - lane + en.k;
-            const uint32_t pos = frp[xk] + rw.acc[en.k] +
-                                 (uint32_t)__popcll(F & lane_range(en.first, lane) &
-                                                    ~(1ull << lane));
-            if (pos < frp[xk + 1]) {  // always true: k_b_setup counted the same entries
-                fsrc[pos] = xk;
-                fcol[pos] = rw.rpb[en.k] - rw.g[en.k] + (uint32_t)en.y;
+    rw.acc[lane] = x < a.N ? frp[x] : 0u;
+    rw.fend[lane] = x < a.N ? frp[x + 1] : 0u;
+    wave_lds_sync();
+    for (uint32_t base = 0; base < total; base += kWalkSteps * kWave) {
+        WalkEntry ens[kWalkSteps];
+        walk_entries(rw, base, total, a.col, a.row_ptr, ens);
+#pragma unroll
+        for (int u = 0; u < kWalkSteps; ++u) {
+            const WalkEntry &en = ens[u];
+            const uint64_t F = __ballot(en.valid && en.fwd);
+            if (en.valid && en.fwd) {
+                const uint32_t xk = x - lane + en.k;
+                const uint32_t pos = rw.acc[en.k] + (uint32_t)__popcll(
+                                                        F & lane_range(en.first, lane) &
+                                                        ~(1ull << lane));
+                if (pos < rw.fend[en.k]) {  // always true: k_b_setup counted the same entries
+                    fsrc[pos] = xk;
+                    fcol[pos] = rw.rpb[en.k] - rw.g[en.k] + (uint32_t)en.y;
+                }
             }
+            wave_lds_sync();  // every lane has read acc before the row's last lane adds to it
+            if (en.valid && lane == en.last)
+                rw.acc[en.k] += (uint32_t)__popcll(F & lane_range(en.first, lane));
+            wave_lds_sync();
         }
-        wave_lds_sync();  // every lane has read acc before the row's last lane adds to it
-        if (en.valid && lane == en.last)
-            rw.acc[en.k] += (uint32_t)__popcll(F & lane_range(en.first, lane));
-        wave_lds_sync();
     }
 }
 
