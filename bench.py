@@ -72,6 +72,17 @@ def make_graph(name: str, dev):
     return synth.er_1000(device=dev)
 
 
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
 def cpu_baseline(dev, seconds_hint: float):
     """The oracle (single-threaded C, test infrastructure) on a bounded sample of the same
     workload family: R-MAT scale 19, edgefactor 24, same (a, b, c), seed 0."""
@@ -87,7 +98,8 @@ def cpu_baseline(dev, seconds_hint: float):
             "kind": "oracle",
             "sample": f"R-MAT scale 19, edgefactor 24, seed 0 ({m} edges, {tot} triangles): "
                       f"oracle end to end (degrees, orientation, sorted lists, merges) "
-                      f"in {dt:.2f} s on one host core"}
+                      f"in {dt:.2f} s on one host core ({host_cpu_model()}, "
+                      f"{os.cpu_count()} logical CPUs visible)"}
 
 
 def batched_section(dev, steps: int, graphs_n: int = 4096, loop: bool = True):
@@ -312,17 +324,20 @@ def main():
         out.check()
         total = int(out.total.item())
 
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    # per step: start, end of preprocessing (= start of counting), end of counting, all on the
+    # stream the library enqueues on
+    ev = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3))
           for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
+        ev[i][0].record(stream)
         api._raise(L.tc_preprocess(api._ptr(edges), n, m, 0, api._ptr(ws), wsz, sp, None),
                    "tc_preprocess")
-        ev[i][0].record(stream)
+        ev[i][1].record(stream)
         api._raise(L.tc_count_prepared(n, m, 0, api._ptr(ws), wsz, sp, api._ptr(out.total),
                                        None, api._ptr(out.status)), "tc_count_prepared")
-        ev[i][1].record(stream)
+        ev[i][2].record(stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     out.check()
@@ -330,7 +345,14 @@ def main():
         total = int(out.total.item())
     assert int(out.total.item()) == total, "count changed between runs"
     ms_per_step = elapsed * 1e3 / args.steps
-    count_ms = sum(a.elapsed_time(b) for a, b in ev) / args.steps
+    count_ms = sum(b.elapsed_time(c) for _, b, c in ev) / args.steps
+    pre_ms = sum(a.elapsed_time(b) for a, b, _ in ev) / args.steps
+    step_ev = sorted(a.elapsed_time(c) for a, _, c in ev)
+    step_mean = sum(step_ev) / len(step_ev)
+    step_stats = {"mean": round(step_mean, 4), "median": round(step_ev[len(step_ev) // 2], 4),
+                  "sd": round((sum((x - step_mean) ** 2 for x in step_ev) / len(step_ev)) ** 0.5, 4),
+                  "min": round(step_ev[0], 4), "max": round(step_ev[-1], 4),
+                  "source": "HIP events around each step on the library's stream"}
     log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, counting kernel {count_ms:.3f} ms")
 
     # graph statistics for the roofline: streamed elements W = sum_u C(d+(u), 2)
@@ -354,6 +376,36 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "kernel": "k_count",
                 "kernel_ms": round(count_ms, 4), "algorithmic_bytes": alg_bytes}
+    if traffic:  # DRAM-side bytes per launch over the launch time (counter GB/s)
+        roofline["traffic_gbs"] = round(traffic / (count_ms * 1e-3) / 1e9, 1)
+        roofline["traffic_frac"] = round(traffic / (count_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+
+    # the paper's wall-clock protocol: edge array from (pinned) host memory, the step, the
+    # total back to the host; reported beside `value`, never as it
+    host_edges = torch.empty(edges.shape, dtype=edges.dtype, pin_memory=True)
+    host_edges.copy_(edges)
+    dev_edges = torch.empty_like(edges)
+    host_total = torch.empty(1, dtype=torch.int64, pin_memory=True)
+    pcie = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        dev_edges.copy_(host_edges, non_blocking=True)
+        api._raise(L.tc_preprocess(api._ptr(dev_edges), n, m, 0, api._ptr(ws), wsz, sp, None),
+                   "tc_preprocess")
+        api._raise(L.tc_count_prepared(n, m, 0, api._ptr(ws), wsz, sp, api._ptr(out.total),
+                                       None, api._ptr(out.status)), "tc_count_prepared")
+        host_total.copy_(out.total, non_blocking=True)
+        torch.cuda.synchronize()
+        pcie.append((time.perf_counter() - t1) * 1e3)
+        assert int(host_total.item()) == total
+    del host_edges, dev_edges
+    pcie_ms = sorted(pcie)[1]
+    pcie_inclusive = {"ms": round(pcie_ms, 3), "intersections_per_s": m / (pcie_ms * 1e-3),
+                      "h2d_bytes": 8 * m, "runs": [round(x, 3) for x in pcie],
+                      "note": "median of 3: host-to-device copy of the edge array from pinned "
+                              "memory, the step, the total back to the host"}
+    log(f"PCIe-inclusive step: {pcie_ms:.3f} ms")
 
     res = {
         "metric": "oriented-edge intersections/s",
@@ -367,6 +419,9 @@ def main():
                    "triangles": total, "golden_match": golden_ok, "wedges": wedges,
                    "parallelism": "single GPU"},
         "count_kernel_intersections_per_s": m / (count_ms * 1e-3),
+        "stages_ms": {"preprocess": round(pre_ms, 4), "count": round(count_ms, 4)},
+        "step_ms": step_stats,
+        "pcie_inclusive": pcie_inclusive,
         "triangles_per_s": total / (ms_per_step * 1e-3),
         "roofline": roofline,
         "cpu_baseline": None,
