@@ -31,8 +31,8 @@ __global__ void k_vrange(const uint32_t *, const uint32_t *, uint32_t, uint64_t 
 __global__ void k_panel_range(const uint64_t *, uint32_t, uint32_t, uint32_t, uint32_t,
                               uint64_t *);
 __global__ void k_csc_keys(const uint32_t *, const uint32_t *, const uint32_t *, const uint64_t *,
-                           const uint64_t *, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t,
-                           uint32_t, uint64_t *, uint2 *, const int32_t *);
+                           uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t,
+                           uint64_t *, uint2 *, const int32_t *);
 __global__ void k_csc_final(const uint64_t *, uint32_t, uint64_t, const uint2 *, uint32_t *,
                             uint32_t *, uint32_t *, uint32_t *, uint32_t *, const int32_t *);
 __global__ void k_items(const uint32_t *, const uint32_t *, const uint32_t *, uint32_t, uint32_t,
@@ -85,6 +85,7 @@ constexpr uint32_t kPartTileEdges = 4096;  // edges per tile of the degree parti
 // measured faster than 4 or 8: fewer edges in flight per XCD keep its lookups inside fewer
 // cells)
 constexpr uint32_t kOrientGrid = 512;
+constexpr uint32_t kCscPerThread = 4;  // in-edge keys per thread (prep.hip, kCscEdges)
 
 // Row blocks of the in-edge lists: contiguous CSR ranges of at most TC_ROW_BLOCK_BYTES of
 // neighbour ids (at most 8 blocks), worked through one after another by the counting kernel.
@@ -346,8 +347,8 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
     TC_HIP(fill_u32(rs, 0u, n1, s));
     TC_HIP(fill_u32(re, 0u, n1, s));
     uint32_t *src = at<uint32_t>(ws, L.src);
-    hipLaunchKernelGGL(k_csr, dim3(grid_for(mf, 256)), dim3(256), 0, s, sorted, mf, n, b, col, src,
-                       rs, re, status);
+    hipLaunchKernelGGL(k_csr, dim3(grid_for(mf, 256 * 4)), dim3(256), 0, s, sorted, mf, n, b, col,
+                       src, rs, re, status);  // 4 keys per thread (prep.hip, kCsrKeys)
     TC_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_rowlen, dim3(grid_for(n1, 256)), dim3(256), 0, s, rs, re, n, rowlen);
     TC_LAUNCH_CHECK();
@@ -382,13 +383,15 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
                            L.p0, count_panel(), L.panels, pr);
         TC_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(k_csc_keys, dim3(grid_for(mf, 256)), dim3(256), 0, s, col, src, row_ptr, vr,
+    hipLaunchKernelGGL(k_csc_keys, dim3(grid_for(mf, 256 * kCscPerThread)), dim3(256), 0, s, col,
+                       src, row_ptr,
                        pr, mf, n, L.nblk, L.p0, count_panel(), L.h0, ck, eu, status);
     TC_LAUNCH_CHECK();
     uint64_t *cks = ck;
     TC_HIP(sort_u64(ck, ck2, mf, 32, 32 + id_bits_for64(l1), sort_scr, status, s, &cks));
     TC_HIP(fill_u32(lrs, 0u, l1, s));
     TC_HIP(fill_u32(lre, 0u, l1, s));
+    // one entry per thread: its gather is bound by the random-line rate, not by latency
     hipLaunchKernelGGL(k_csc_final, dim3(grid_for(mf, 256)), dim3(256), 0, s, cks, mf, L.lists,
                        eu, at<uint32_t>(ws, L.cbeg), at<uint32_t>(ws, L.cend),
                        at<uint32_t>(ws, L.cmask), lrs, lre, status);

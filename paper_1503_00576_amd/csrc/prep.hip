@@ -315,6 +315,8 @@ __global__ void k_both_check(const uint32_t *__restrict__ counter, uint32_t expe
         set_status(status, TC_E_ASYMMETRIC);
 }
 
+constexpr uint32_t kCsrKeys = 4;
+
 // Unzip the sorted keys into the neighbour array (Section 3.2, step 7) and mark where every
 // non-empty row starts and ends; row lengths and their prefix sum give the node array.
 __global__ void k_csr(const uint64_t *__restrict__ keys, uint32_t mf, uint32_t n, int b,
@@ -322,16 +324,28 @@ __global__ void k_csr(const uint64_t *__restrict__ keys, uint32_t mf, uint32_t n
                       uint32_t *__restrict__ rs, uint32_t *__restrict__ re,
                       int32_t *__restrict__ status) {
     if (*status) return;
-    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= mf) return;
-    const uint64_t k = keys[i];
-    const uint32_t s = (uint32_t)(k >> b);
-    col[i] = (uint32_t)(k & ((1ull << b) - 1));
-    src[i] = s;
-    if (s >= n) return;  // only for invalid input, reported elsewhere
-    if (i == 0 || (uint32_t)(keys[i - 1] >> b) != s) rs[s] = i;
-    if (i > 0 && keys[i - 1] == k) set_status(status, TC_E_DUP_EDGE);
-    if (i == mf - 1 || (uint32_t)(keys[i + 1] >> b) != s) re[s] = i + 1;
+    // kCsrKeys keys a block apart per thread, all loaded before any is used
+    const uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x * kCsrKeys + threadIdx.x;
+    uint64_t k[kCsrKeys], kp[kCsrKeys], kn[kCsrKeys];
+#pragma unroll
+    for (uint32_t t = 0; t < kCsrKeys; ++t) {
+        const uint64_t i = i0 + (uint64_t)t * blockDim.x;
+        k[t] = i < mf ? keys[i] : 0ull;
+        kp[t] = (i < mf && i > 0) ? keys[i - 1] : ~0ull;
+        kn[t] = i + 1 < mf ? keys[i + 1] : ~0ull;
+    }
+#pragma unroll
+    for (uint32_t t = 0; t < kCsrKeys; ++t) {
+        const uint64_t i = i0 + (uint64_t)t * blockDim.x;
+        if (i >= mf) continue;
+        const uint32_t s = (uint32_t)(k[t] >> b);
+        col[i] = (uint32_t)(k[t] & ((1ull << b) - 1));
+        src[i] = s;
+        if (s >= n) continue;  // only for invalid input, reported elsewhere
+        if (i == 0 || (uint32_t)(kp[t] >> b) != s) rs[s] = (uint32_t)i;
+        if (i > 0 && kp[t] == k[t]) set_status(status, TC_E_DUP_EDGE);
+        if (i == mf - 1 || (uint32_t)(kn[t] >> b) != s) re[s] = (uint32_t)(i + 1);
+    }
 }
 
 // row length = end - start (both zero for empty rows); entry n is 0 so that the exclusive
@@ -372,53 +386,97 @@ __global__ void k_panel_range(const uint64_t *__restrict__ vr, uint32_t n, uint3
 }
 
 // In-edge u -> v (CSR position e) can close a triangle u < v < w only through an element w of
-// N+(u) after v that also lies in N+(v): the suffix must be non-empty and its rank range must
-// overlap that of N+(v).  Such in-edges are keyed by their list c = row block * (n + 1) + v
-// (row blocks: contiguous CSR ranges, see the host code), the others by `lists` (sorted last);
-// the low 32 bits hold e, so a stable sort on the list bits groups every list in CSR order.
-// From rank p0 on, middle vertices form panels of kp consecutive ranks with one list per
-// panel, keyed by its first rank P: only the first in-edge of each run of u's out-neighbours
-// inside the panel is kept (it stands for the whole run), tested against the panel's span.
-// eu[e] = (end of u's row, mask of the run's panel vertices for a kept panel entry).  In-edges
-// from hubs (u >= h0) are left out: their triangles are counted on the matrix cores.
+// N+(u) after v that also lies in N+(v), so only in-edges with a non-empty suffix are listed
+// (k_items skips the lists of vertices with an empty N+(v)).  They are keyed by their list
+// c = row block * (n + 1) + v (row blocks: contiguous CSR ranges, see the host code), the
+// others by `lists` (sorted last); the low 32 bits hold e, so a stable sort on the list bits
+// groups every list in CSR order.  (A test of the suffix's rank range against that of N+(v)
+// was dropped: on R-MAT graphs it rejected no in-edge and cost one random 8-byte lookup per
+// edge.)  From rank p0 on, middle vertices form panels of kp consecutive ranks with one list
+// per panel, keyed by its first rank P: only the first in-edge of each run of u's
+// out-neighbours inside the panel is kept (it stands for the whole run), tested against the
+// panel's span (a small table).  eu[e] = (end of u's row, mask of the run's panel vertices
+// for a kept panel entry).  In-edges from hubs (u >= h0) are left out: their triangles are
+// counted on the matrix cores.
+// Each thread takes kCscEdges entries a block apart and issues every stage's loads for all of
+// them before using any (the stages depend on each other: entry -> row -> row end).
+constexpr uint32_t kCscEdges = 4;
+
 __global__ void k_csc_keys(const uint32_t *__restrict__ col, const uint32_t *__restrict__ src,
                            const uint32_t *__restrict__ row_ptr,
-                           const uint64_t *__restrict__ vr, const uint64_t *__restrict__ pr,
-                           uint32_t mf, uint32_t n, uint32_t nblk, uint32_t p0, uint32_t kp,
-                           uint32_t h0, uint64_t *__restrict__ keys, uint2 *__restrict__ eu,
+                           const uint64_t *__restrict__ pr, uint32_t mf, uint32_t n,
+                           uint32_t nblk, uint32_t p0, uint32_t kp, uint32_t h0,
+                           uint64_t *__restrict__ keys, uint2 *__restrict__ eu,
                            const int32_t *__restrict__ status) {
     if (*status) return;
-    uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= mf) return;
-    const uint32_t u = src[e], v = col[e];
-    const uint32_t end_u = row_ptr[u + 1];
-    uint64_t c = (uint64_t)nblk * (n + 1);
-    uint32_t mask = 1u;
-    if (e + 1 < end_u && u < h0) {  // triangles whose lowest vertex is a hub: hub.hip
-        uint32_t list = v;
-        uint64_t r = vr[v];
-        bool run_start = false;
-        if (v >= p0) {
-            const uint32_t i = (v - p0) / kp;
-            list = p0 + i * kp;
-            run_start = e == row_ptr[u] || col[e - 1] < list;
-            r = run_start ? pr[i] : 0xFFFFFFFF00000000ull;
-        }
-        const uint32_t lo = (uint32_t)(r >> 32), hi = (uint32_t)r;
-        if (lo <= hi && col[e + 1] <= hi && col[end_u - 1] >= lo) {
-            c = (uint64_t)(((uint64_t)e * nblk) / mf) * (n + 1) + list;
-            if (run_start) {  // the run's mask (its entries are in this part of col anyway)
-                mask = 0;
-                for (uint32_t x = e; x < end_u; ++x) {
-                    const uint32_t w = col[x];
-                    if (w >= list + kp) break;
-                    mask |= 1u << (w - list);
+    // kp is a power of two; row blocks are rare (nblk > 1 only when asked for)
+    const uint32_t kp_shift = __builtin_ctz(kp);
+    const uint64_t e0 = (uint64_t)blockIdx.x * blockDim.x * kCscEdges + threadIdx.x;
+    uint32_t u[kCscEdges], v[kCscEdges], prv[kCscEdges], nxt[kCscEdges];
+#pragma unroll
+    for (uint32_t k = 0; k < kCscEdges; ++k) {
+        const uint64_t e = e0 + (uint64_t)k * blockDim.x;
+        const bool in = e < mf;
+        u[k] = in ? src[e] : 0u;
+        v[k] = in ? col[e] : 0u;
+        prv[k] = (in && e > 0) ? col[e - 1] : 0u;
+        nxt[k] = (in && e + 1 < mf) ? col[e + 1] : 0u;
+    }
+    uint32_t rb[kCscEdges], re[kCscEdges];
+#pragma unroll
+    for (uint32_t k = 0; k < kCscEdges; ++k) {
+        const bool in = e0 + (uint64_t)k * blockDim.x < mf;
+        rb[k] = in ? row_ptr[u[k]] : 0u;
+        re[k] = in ? row_ptr[u[k] + 1] : 0u;
+    }
+    uint32_t last[kCscEdges];
+    uint64_t r[kCscEdges];
+#pragma unroll
+    for (uint32_t k = 0; k < kCscEdges; ++k) {
+        const uint64_t e = e0 + (uint64_t)k * blockDim.x;
+        const bool pan = e + 1 < re[k] && u[k] < h0 && v[k] >= p0;
+        last[k] = pan ? col[re[k] - 1] : 0u;
+        r[k] = pan ? pr[(v[k] - p0) >> kp_shift] : 0xFFFFFFFF00000000ull;
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < kCscEdges; ++k) {
+        const uint64_t e = e0 + (uint64_t)k * blockDim.x;
+        if (e >= mf) continue;
+        const uint32_t end_u = re[k];
+        uint64_t c = (uint64_t)nblk * (n + 1);
+        uint32_t mask = 1u;
+        if (e + 1 < end_u && u[k] < h0) {  // triangles whose lowest vertex is a hub: hub.hip
+            uint32_t list = v[k];
+            bool keep = true, run_start = false;
+            if (v[k] >= p0) {
+                list = p0 + (((v[k] - p0) >> kp_shift) << kp_shift);
+                run_start = e == rb[k] || prv[k] < list;
+                const uint32_t lo = (uint32_t)(r[k] >> 32), hi = (uint32_t)r[k];
+                keep = run_start && lo <= hi && nxt[k] <= hi && last[k] >= lo;
+            }
+            if (keep) {
+                const uint64_t blk = nblk == 1 ? 0 : (e * nblk) / mf;
+                c = blk * (n + 1) + list;
+                if (run_start) {  // the run's mask: u's consecutive entries inside the panel
+                    mask = 1u << (v[k] - list);
+                    for (uint64_t x = e + 1; x < end_u; x += 4) {  // four loads at a time
+                        uint32_t w[4];
+#pragma unroll
+                        for (uint32_t i = 0; i < 4; ++i) w[i] = x + i < end_u ? col[x + i] : ~0u;
+                        bool out = false;
+#pragma unroll
+                        for (uint32_t i = 0; i < 4; ++i) {
+                            out = out || w[i] >= list + kp;
+                            if (!out) mask |= 1u << (w[i] - list);
+                        }
+                        if (out) break;
+                    }
                 }
             }
         }
+        keys[e] = (c << 32) | e;
+        eu[e] = make_uint2(end_u, mask);
     }
-    keys[e] = (c << 32) | e;
-    eu[e] = make_uint2(end_u, mask);
 }
 
 // The lists themselves: in-edge u -> v at CSR position e contributes the suffix [e + 1, end_u)
@@ -465,7 +523,7 @@ __global__ void k_items(const uint32_t *__restrict__ row_ptr, const uint32_t *__
     const uint32_t v = c < total ? (uint32_t)(c % (n + 1)) : n;
     if (v < n && cnt[c] > 0 && v >= p0) {
         b = bpv = (cnt[c] + kb - 1) / kb;
-    } else if (v < n && cnt[c] > 0) {
+    } else if (v < n && cnt[c] > 0 && row_ptr[v + 1] > row_ptr[v]) {  // N+(v) non-empty
         const uint32_t r0 = row_ptr[v], d = row_ptr[v + 1] - r0;
         const uint32_t span = col[r0 + d - 1] - col[r0];
         const uint32_t na = (cnt[c] + ka - 1) / ka, nb = (cnt[c] + kb - 1) / kb;
