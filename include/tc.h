@@ -33,7 +33,10 @@
  *     highest ranks are hubs, whose triangles (those whose lowest vertex is a hub) are
  *     counted as a masked int8 matrix product on the matrix cores (two hubs x hubs byte
  *     matrices in the workspace).  They change tc_workspace_size and must not change between
- *     a tc_preprocess and the calls that use its workspace.
+ *     a tc_preprocess and the calls that use its workspace.  TC_DEGREE_PARTITION=0 (for
+ *     tests) computes degrees with one atomic per endpoint and orients the edges in input
+ *     order, the path that graphs of more than 2^27 vertices or 2^32 endpoints take; it
+ *     changes tc_workspace_size like the others.
  */
 #ifndef TC_H
 #define TC_H

@@ -180,7 +180,11 @@ static bool make_layout(int64_t n, int64_t m, uint32_t flags, Layout &L) {
         const uint64_t endpoints = (flags & TC_EDGES_BOTH) ? (uint64_t)m : 2ull * (uint64_t)m;
         const int db = L.id_bits < 8 ? (int)L.id_bits : 8;
         L.part_shift = (int)L.id_bits - db;
-        L.part_tiles = (endpoints < (1ull << 32) && L.part_shift <= 19)
+        // TC_DEGREE_PARTITION=0 forces the atomic fallback (tests of the path that inputs of
+        // more than 2^27 vertices or 2^32 endpoints take)
+        const char *pe = getenv("TC_DEGREE_PARTITION");
+        const bool part_on = !(pe && pe[0] == '0');
+        L.part_tiles = (part_on && endpoints < (1ull << 32) && L.part_shift <= 19)
                            ? ceil_div((uint64_t)m > 0 ? (uint64_t)m : 1, kPartTileEdges)
                            : 0u;
         // one-direction format: the edges are also partitioned into 16 x 16 cells of id ranges

@@ -135,6 +135,26 @@ def test_row_blocks_forced(monkeypatch):
     check_vs_oracle(e.cpu().numpy(), n)
 
 
+@pytest.mark.parametrize("both", [False, True])
+def test_degree_atomic_path(monkeypatch, both):
+    """Degrees by one atomic per endpoint and orientation in input order (the path of graphs
+    beyond the bucket partition's limits), both input formats, with an invalid input."""
+    monkeypatch.setenv("TC_DEGREE_PARTITION", "0")
+    for e, n in [synth.er_1000(), synth.rmat_graph(14, 16, seed=5),
+                 (synth.barabasi_albert(3000, 12, 2), 3000)]:
+        e = e.numpy()
+        if both:
+            e = np.concatenate([e, e[:, ::-1]])
+        check_vs_oracle(e, n, both=both)
+    for k in [3, 40, 130]:
+        assert check_vs_oracle(complete(k), k) == math.comb(k, 3)
+    for edges, name in [([(0, 1), (1, 2), (2, 2)], "self_loop"), ([(0, 1), (1, 5)], "range"),
+                        ([(0, 1), (1, 2), (1, 0)], "dup_edge")]:
+        with pytest.raises(api.TCError) as ei:
+            api.count(torch.tensor(edges, dtype=torch.int32, device=DEV), 5)
+        assert ei.value.name == name
+
+
 @pytest.mark.parametrize("ranks", ["0", "1", "31", "33", "517", "4000"])
 def test_panel_thresholds(monkeypatch, ranks):
     """The top-ranks panel region of every size: off (per-vertex lists only), one partial
