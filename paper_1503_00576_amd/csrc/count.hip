@@ -52,6 +52,9 @@ constexpr uint32_t kPanelRanks = kLdsWords - 32;      // mask table: one word pe
 // chunk of forward edges plus kLightMax entries on either side must fit one wave's slice
 constexpr uint32_t kLightMax = 256;
 constexpr uint32_t kLightChunkMax = kSliceWords - 2 * kLightMax;
+// light segments' pieces: their lists are short (a few elements), so shorter pieces waste
+// fewer lookups on masked positions
+constexpr uint32_t kLightPiece = 8;
 
 // ------------------------------------------------------------------ membership probes
 
@@ -578,7 +581,7 @@ __device__ __forceinline__ uint32_t run_light(uint32_t eb, uint32_t e1,
         if (d < 2 || d > kLightMax) d = b = en = lo = 0;
     }
     const uint32_t a0 = b & ~3u;
-    const uint32_t p = (d && en > b) ? (en - a0 + kPiece - 1) / kPiece : 0u;
+    const uint32_t p = (d && en > b) ? (en - a0 + kLightPiece - 1) / kLightPiece : 0u;
     const uint32_t incl = wave_incl_scan(p);
     const uint32_t Q = wave_bcast(incl, kWave - 1);
     ws.off[lane] = incl - p;
@@ -596,12 +599,12 @@ __device__ __forceinline__ uint32_t run_light(uint32_t eb, uint32_t e1,
 #pragma unroll
             for (uint32_t step = 32; step; step >>= 1)
                 if (ws.off[k + step] <= q) k += step;
-            const uint32_t start = ws.beg[k] + (q - ws.off[k]) * kPiece;
+            const uint32_t start = ws.beg[k] + (q - ws.off[k]) * kLightPiece;
             const uint32_t first = ws.first[k], stop = ws.end[k];
             const uint4 *p4 = reinterpret_cast<const uint4 *>(fcol + start);
-            uint32_t wv[kPiece];
+            uint32_t wv[kLightPiece];
 #pragma unroll
-            for (uint32_t j = 0; j < kPiece / 4; ++j) {
+            for (uint32_t j = 0; j < kLightPiece / 4; ++j) {
                 const uint4 x = p4[j];
                 wv[4 * j] = x.x;
                 wv[4 * j + 1] = x.y;
@@ -611,21 +614,21 @@ __device__ __forceinline__ uint32_t run_light(uint32_t eb, uint32_t e1,
             const uint32_t *list = win + ws.tag[k];
             const uint32_t dl = ws.aux[k];  // >= 2
             const uint32_t lo_i = first > start ? first - start : 0u;
-            const uint32_t hi_i = min(stop - start, kPiece);
+            const uint32_t hi_i = min(stop - start, kLightPiece);
             // the piece's lookups as binary searches in lockstep (one list per lane)
-            uint32_t base[kPiece];
+            uint32_t base[kLightPiece];
 #pragma unroll
-            for (uint32_t i = 0; i < kPiece; ++i) base[i] = 0;
+            for (uint32_t i = 0; i < kLightPiece; ++i) base[i] = 0;
             for (uint32_t n_left = dl; n_left > 1;) {
                 const uint32_t half = n_left >> 1;
 #pragma unroll
-                for (uint32_t i = 0; i < kPiece; ++i)
+                for (uint32_t i = 0; i < kLightPiece; ++i)
                     base[i] = list[base[i] + half - 1] < wv[i] ? base[i] + half : base[i];
                 n_left -= half;
             }
             uint32_t packed = 0;
 #pragma unroll
-            for (uint32_t i = 0; i < kPiece; ++i) {
+            for (uint32_t i = 0; i < kLightPiece; ++i) {
                 const uint32_t pos = base[i] + (list[base[i]] < wv[i] ? 1u : 0u);
                 packed |= (list[min(pos, dl - 1u)] == wv[i] ? 1u : 0u) << i;
             }
@@ -634,7 +637,7 @@ __device__ __forceinline__ uint32_t run_light(uint32_t eb, uint32_t e1,
             const uint32_t hits = __popc(packed);
             if (PV) {
 #pragma unroll
-                for (uint32_t i = 0; i < kPiece; ++i)
+                for (uint32_t i = 0; i < kLightPiece; ++i)
                     if ((packed >> i) & 1u) atomicAdd(&tpv[wv[i]], 1ull);
             }
             if (hits) atomicAdd(&ws.cnt[k], hits);
