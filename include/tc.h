@@ -27,7 +27,7 @@
  *   - Tuning: the environment variable TC_ROW_BLOCK_BYTES (unset = one block) splits the
  *     counting phase's in-edge lists into up to 8 row blocks of at most that many bytes of
  *     neighbour ids, worked through one after another.  TC_PANEL_RANKS (unset = the
- *     largest value the counting kernel supports, 16352; 0 = off) sets how many of the
+ *     largest value the counting kernel supports, 32736; 0 = off) sets how many of the
  *     highest ranks of the order of Section 2.2 are counted as panels of 32 consecutive
  *     middle vertices.  TC_HUB_RANKS (unset = 0 = off; at most 65536) sets how many of the
  *     highest ranks are hubs, whose triangles (those whose lowest vertex is a hub) are

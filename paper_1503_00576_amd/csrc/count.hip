@@ -34,10 +34,10 @@
 namespace tc {
 
 constexpr uint32_t kPiece = 16;
-constexpr int kThreads = 512;
-constexpr int kWgsPerCu = 2;  // workgroups per CU the LDS footprint allows
+constexpr int kThreads = 1024;
+constexpr int kWgsPerCu = 1;  // workgroups per CU the LDS footprint allows
 constexpr int kWaves = kThreads / kWave;
-constexpr uint32_t kLdsWords = 16384;                 // 64 KiB per workgroup
+constexpr uint32_t kLdsWords = 32768;                 // 128 KiB per workgroup
 constexpr uint32_t kSliceWords = kLdsWords / kWaves;  // 8 KiB per wave
 constexpr uint32_t kWaveBits = kSliceWords * 32 - 32; // wave bitmap: span < 65504
 constexpr uint32_t kWaveListPV = kSliceWords / 2;     // per-vertex: list + counters per wave
