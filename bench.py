@@ -102,6 +102,36 @@ def cpu_baseline(dev, seconds_hint: float):
                       f"{os.cpu_count()} logical CPUs visible)"}
 
 
+def pcie_section(edges, n, m, total, ws, out, L, sp):
+    """The paper's wall-clock protocol: edge array from (pinned) host memory, the step, the
+    total back to the host; reported beside `value`, never as it (median of 3 runs)."""
+    import torch
+    from paper_1503_00576_amd import api
+    wsz = ws.numel()
+    host_edges = torch.empty(edges.shape, dtype=edges.dtype, pin_memory=True)
+    host_edges.copy_(edges)
+    dev_edges = torch.empty_like(edges)
+    host_total = torch.empty(1, dtype=torch.int64, pin_memory=True)
+    pcie = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        dev_edges.copy_(host_edges, non_blocking=True)
+        api._raise(L.tc_preprocess(api._ptr(dev_edges), n, m, 0, api._ptr(ws), wsz, sp, None),
+                   "tc_preprocess")
+        api._raise(L.tc_count_prepared(n, m, 0, api._ptr(ws), wsz, sp, api._ptr(out.total),
+                                       None, api._ptr(out.status)), "tc_count_prepared")
+        host_total.copy_(out.total, non_blocking=True)
+        torch.cuda.synchronize()
+        pcie.append((time.perf_counter() - t1) * 1e3)
+        assert int(host_total.item()) == total
+    pcie_ms = sorted(pcie)[1]
+    return {"ms": round(pcie_ms, 3), "intersections_per_s": m / (pcie_ms * 1e-3),
+            "h2d_bytes": 8 * m, "runs": [round(x, 3) for x in pcie],
+            "note": "median of 3: host-to-device copy of the edge array from pinned memory, the "
+                    "step, the total back to the host"}
+
+
 def batched_section(dev, steps: int, graphs_n: int = 4096, loop: bool = True):
     """4096 Barabasi-Albert / Watts-Strogatz graphs (50/50, n log-uniform in [50, 20000],
     average degree in [4, 32]) in one captured plan, tuned, against a loop of one tc_count
@@ -253,6 +283,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat23", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-pcie", action="store_true",
+                    help="skip the PCIe-inclusive runs (profiling: one counting launch per step)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched measurement (4096 small graphs)")
     ap.add_argument("--batched-only", action="store_true")
@@ -380,32 +412,10 @@ def main():
         roofline["traffic_gbs"] = round(traffic / (count_ms * 1e-3) / 1e9, 1)
         roofline["traffic_frac"] = round(traffic / (count_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
 
-    # the paper's wall-clock protocol: edge array from (pinned) host memory, the step, the
-    # total back to the host; reported beside `value`, never as it
-    host_edges = torch.empty(edges.shape, dtype=edges.dtype, pin_memory=True)
-    host_edges.copy_(edges)
-    dev_edges = torch.empty_like(edges)
-    host_total = torch.empty(1, dtype=torch.int64, pin_memory=True)
-    pcie = []
-    for _ in range(3):
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        dev_edges.copy_(host_edges, non_blocking=True)
-        api._raise(L.tc_preprocess(api._ptr(dev_edges), n, m, 0, api._ptr(ws), wsz, sp, None),
-                   "tc_preprocess")
-        api._raise(L.tc_count_prepared(n, m, 0, api._ptr(ws), wsz, sp, api._ptr(out.total),
-                                       None, api._ptr(out.status)), "tc_count_prepared")
-        host_total.copy_(out.total, non_blocking=True)
-        torch.cuda.synchronize()
-        pcie.append((time.perf_counter() - t1) * 1e3)
-        assert int(host_total.item()) == total
-    del host_edges, dev_edges
-    pcie_ms = sorted(pcie)[1]
-    pcie_inclusive = {"ms": round(pcie_ms, 3), "intersections_per_s": m / (pcie_ms * 1e-3),
-                      "h2d_bytes": 8 * m, "runs": [round(x, 3) for x in pcie],
-                      "note": "median of 3: host-to-device copy of the edge array from pinned "
-                              "memory, the step, the total back to the host"}
-    log(f"PCIe-inclusive step: {pcie_ms:.3f} ms")
+    pcie_inclusive = None
+    if not args.no_pcie:
+        pcie_inclusive = pcie_section(edges, n, m, total, ws, out, L, sp)
+        log(f"PCIe-inclusive step: {pcie_inclusive['ms']:.3f} ms")
 
     res = {
         "metric": "oriented-edge intersections/s",

@@ -162,7 +162,8 @@ int tc_sort_u64(uint64_t *d_keys, uint64_t *d_tmp, int64_t count, int32_t bits, 
  * hipGraph on its first run; later runs only write a small argument block and replay the
  * graph, for any batch within the capacities.  tuning_json (nullable) may set "chunk_e"
  * (forward edges per chunk, 64 .. 1536, default 1024), "items_k" (out-neighbours of a large
- * vertex per work item, >= 16, default 256) and "wgs_per_cu" (1 or 2, default 2).
+ * vertex per work item, >= 16, default 256) and "wgs_per_cu" (workgroups per compute unit,
+ * at least 1; values above what the counting kernel's LDS allows, currently 1, are clamped).
  * Runs of one plan must not overlap (they share the workspace); the plan must outlive its
  * last run on the GPU.  flags must be 0. */
 typedef struct tc_plan tc_plan;

@@ -17,7 +17,7 @@ from . import api
 
 CHUNK_E = (256, 512, 1024, 1536)
 ITEMS_K = (64, 256, 1024)
-WGS_PER_CU = (1, 2)
+WGS_PER_CU = (1,)  # one 1024-thread workgroup per CU is all the LDS holds
 
 
 def _key(device, b: api.Batch) -> str:

@@ -587,7 +587,7 @@ int tc_batched_plan_create(int32_t g_cap, int64_t n_cap, int64_t adj_cap, uint32
     p->chunk = parse_tuning(tuning_json, "\"chunk_e\"", 1024);
     if (p->chunk < 64) p->chunk = 64;
     if (p->chunk > count_light_chunk_max()) p->chunk = count_light_chunk_max();
-    p->wgs_per_cu = parse_tuning(tuning_json, "\"wgs_per_cu\"", 2);
+    p->wgs_per_cu = parse_tuning(tuning_json, "\"wgs_per_cu\"", count_wgs_per_cu());
     if (p->wgs_per_cu > count_wgs_per_cu()) p->wgs_per_cu = count_wgs_per_cu();  // LDS limit
     p->ws = d_ws;
     p->ws_bytes = ws_bytes;
