@@ -273,11 +273,19 @@ __device__ __forceinline__ void hist_tile(const uint64_t *__restrict__ in, uint3
     load_tile_keys<kFull>(in, count, base, w, keys);
     for (uint32_t k = lane_id(); k < 256; k += kWave) h[w][k] = 0;
     wave_lds_sync();
-    // counts only (no ranks): one LDS atomic per key into the wave's own counters
+    // counts only (no ranks): the keys of a row that share the first lane's digit are added
+    // with one LDS atomic, the others one atomic each, into the wave's own counters (skewed
+    // keys -- hub ranks, long runs of equal digits after the first pass -- would otherwise
+    // serialise many atomics on one counter)
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r)
-        if (kFull || tile_key_index(base, w, r) < count)
-            atomicAdd(&h[w][(uint32_t)(keys[r] >> shift) & mask], 1u);
+    for (int r = 0; r < kSortItems; ++r) {
+        const bool valid = kFull || tile_key_index(base, w, r) < count;
+        const uint32_t d = (uint32_t)(keys[r] >> shift) & mask;
+        const uint32_t d0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)d);
+        const uint64_t same = __ballot(valid && d == d0);
+        if (lane_id() == 0 && same) atomicAdd(&h[w][d0], (uint32_t)__popcll(same));
+        if (valid && d != d0) atomicAdd(&h[w][d], 1u);
+    }
     __syncthreads();
     if (t < 256) {
         uint32_t sum = 0;
