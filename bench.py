@@ -412,6 +412,28 @@ def main():
         roofline["traffic_gbs"] = round(traffic / (count_ms * 1e-3) / 1e9, 1)
         roofline["traffic_frac"] = round(traffic / (count_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
 
+    # per-vertex counts (T(x) for every vertex, for clustering coefficients): the counting
+    # phase with per-vertex output on the prepared graph, HIP events around each launch
+    pv_out = torch.empty(n, dtype=torch.int64, device=dev)
+    pv_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+             for _ in range(3)]
+    for a, b in pv_ev:
+        a.record(stream)
+        api._raise(L.tc_count_prepared(n, m, 0, api._ptr(ws), wsz, sp, api._ptr(out.total),
+                                       api._ptr(pv_out), api._ptr(out.status)),
+                   "tc_count_prepared")
+        b.record(stream)
+    torch.cuda.synchronize()
+    out.check()
+    pv_sum = int(pv_out.sum().item())
+    assert int(out.total.item()) == total and pv_sum == 3 * total, "per-vertex counts"
+    pv_ms = sorted(a.elapsed_time(b) for a, b in pv_ev)[1]
+    per_vertex = {"count_ms": round(pv_ms, 4), "sum_equals_3T": pv_sum == 3 * total,
+                  "note": "counting phase with per-vertex output (tc_count_prepared with "
+                          "d_per_vertex), median of 3 launches on the prepared graph"}
+    del pv_out
+    log(f"per-vertex counting: {pv_ms:.3f} ms")
+
     pcie_inclusive = None
     if not args.no_pcie:
         pcie_inclusive = pcie_section(edges, n, m, total, ws, out, L, sp)
@@ -432,6 +454,7 @@ def main():
         "stages_ms": {"preprocess": round(pre_ms, 4), "count": round(count_ms, 4)},
         "step_ms": step_stats,
         "pcie_inclusive": pcie_inclusive,
+        "per_vertex": per_vertex,
         "triangles_per_s": total / (ms_per_step * 1e-3),
         "roofline": roofline,
         "cpu_baseline": None,

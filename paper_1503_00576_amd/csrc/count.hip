@@ -240,10 +240,12 @@ __device__ __forceinline__ uint32_t run_batch(uint32_t eb, uint32_t e1, const Se
                     const uint32_t c = probe.count(wv[i], r);
                     hits += (i >= lo_i && i < hi_i) ? c : 0u;
                 }
-            } else if constexpr (!PV && Probe::kList) {
+            } else if constexpr (Probe::kList) {
                 // the piece's 16 lookups as binary searches in lockstep (the list length is
-                // uniform), so that every step issues independent LDS reads; position pos is
-                // the first entry >= w, and w is in the list iff that entry equals w
+                // uniform), so that every step issues independent reads; position pos is the
+                // first entry >= w, and w is in the list iff that entry equals w.  Per-vertex
+                // counts credit the third vertex of every hit: an LDS counter by position, or
+                // a global counter when the list is not in LDS.
                 uint32_t base[kPiece];
 #pragma unroll
                 for (uint32_t i = 0; i < kPiece; ++i) base[i] = 0;
@@ -257,13 +259,23 @@ __device__ __forceinline__ uint32_t run_batch(uint32_t eb, uint32_t e1, const Se
                 uint32_t packed = 0;
 #pragma unroll
                 for (uint32_t i = 0; i < kPiece; ++i) {
-                    const uint32_t pos = base[i] + (probe.list[base[i]] < wv[i] ? 1u : 0u);
-                    packed |= (probe.list[min(pos, probe.d - 1u)] == wv[i] ? 1u : 0u) << i;
+                    base[i] += probe.list[base[i]] < wv[i] ? 1u : 0u;
+                    packed |= (probe.list[min(base[i], probe.d - 1u)] == wv[i] ? 1u : 0u) << i;
                 }
                 const uint32_t lo_i = first > start ? first - start : 0u;
                 const uint32_t hi_i = min(stop - start, kPiece);
                 const uint32_t hmask = hi_i >= 32u ? ~0u : ((1u << hi_i) - 1u);
-                hits = __popc(packed & hmask & ~((1u << lo_i) - 1u));
+                packed &= hmask & ~((1u << lo_i) - 1u);
+                hits = __popc(packed);
+                if (PV && packed) {
+#pragma unroll
+                    for (uint32_t i = 0; i < kPiece; ++i) {
+                        if ((packed >> i) & 1u) {
+                            if (tcnt) atomicAdd(&tcnt[base[i]], 1u);
+                            else atomicAdd(&tpv[wv[i]], 1ull);
+                        }
+                    }
+                }
             } else if constexpr (!PV && Probe::kBranchFree) {
                 // the piece's valid elements are the contiguous range [lo_i, hi_i) of positions
                 uint32_t packed = 0;
