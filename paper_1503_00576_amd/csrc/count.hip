@@ -41,7 +41,7 @@ constexpr uint32_t kLdsWords = 32768;                 // 128 KiB per workgroup
 constexpr uint32_t kSliceWords = kLdsWords / kWaves;  // 8 KiB per wave
 constexpr uint32_t kWaveBits = kSliceWords * 32 - 32; // wave bitmap: span < 65504
 constexpr uint32_t kWaveListPV = kSliceWords / 2;     // per-vertex: list + counters per wave
-constexpr uint32_t kBlockBits = kLdsWords * 32 - 32;  // workgroup bitmap: span < 524256
+constexpr uint32_t kBlockBits = kLdsWords * 32 - 32;  // workgroup bitmap: span < 1048544
 constexpr uint32_t kBlockList = kLdsWords;            // workgroup sorted list
 constexpr uint32_t kBlockListPV = kLdsWords / 2;      // per-vertex: list + counters
 constexpr uint32_t kItemEdgesWave = 512;

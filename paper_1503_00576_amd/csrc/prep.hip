@@ -1,17 +1,19 @@
 // Preprocessing phase (Section 3.2) on the device, in "rank space".
 //
 //   k_part_*     degrees of the vertices (bucket partition + LDS counting) and the input
-//                checks of Section 3.1
+//                checks of Section 3.1; in the one-direction format the same pass places
+//                the edges in cells of id ranges for k_orient_cells
 //   k_vkeys      packs (degree, id) so that a stable sort yields the total order of Section 2.2
 //                (degree first, ties by id); the position of a vertex in that order is its rank
 //   k_rank       perm[r] = vertex of rank r, rank[v] = r
-//   k_orient     every edge becomes a packed key (rank s << b) | rank t with s < t, i.e. the
+//   k_orient*    every edge becomes a packed key (rank s << b) | rank t with s < t, i.e. the
 //                edge kept only in its forward direction (Section 3.2, steps 5-6); in the
 //                paper's two-direction format backward entries are dropped
 //   k_csr        the unzipped neighbour array (step 7), row boundaries for the node array
 //                (steps 4/8: row_ptr[x] = first key whose source is >= x), duplicate check
-//   k_csc_*      for every vertex v the list of in-edges u -> v that can close a triangle
-//                through v: the suffix of N+(u) after v, stored as a [begin, end) range;
+//   k_csc_*      for every vertex v the list of in-edges u -> v with a non-empty suffix of
+//                N+(u) after v (the elements that can close a triangle through v), stored
+//                as a [begin, end) range;
 //                built by a radix sort of (list << 32 | e) keys, so no atomics are needed;
 //                from rank p0 on, one list per panel of consecutive middle vertices, with the
 //                mask of u's panel vertices per entry

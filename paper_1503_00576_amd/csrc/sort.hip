@@ -4,8 +4,9 @@
 // (Section 3.2, step 3, and the note on sorting edges as 64-bit integers): keys are ordered
 // on a bit range [lo_bit, hi_bit) with 8-bit digits, least significant digit first; every
 // pass is an upsweep (per-tile digit histograms), an exclusive scan of the digit-major
-// histogram table, and a stable scatter in which a wave ranks equal digits with ballots,
-// the tile is ordered by digit in LDS, and every digit's run is written out contiguously.
+// histogram table, and a stable scatter in which every wave ranks its own contiguous part of
+// the tile with ballots, the tile is ordered by digit in LDS, and every digit's run is
+// written out contiguously.
 //
 // Single-sweep variant (large sorts that report errors through a status word): one upfront
 // kernel counts the digits of every pass over all keys; each pass is then one kernel whose
