@@ -259,6 +259,25 @@ def test_radix_sort(count, bits):
     assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("count,bits", [(8192 * 3 + 77, 24), (1 << 20, 40), (300_001, 64)])
+def test_radix_sort_skewed(count, bits):
+    """Heavily repeated digits (most keys share one value on the sorted bits, the rest spread
+    over a few values), as hub ranks and the unlisted in-edges produce: the histogram counts
+    runs of equal digits with one atomic, and the sort must stay stable."""
+    g = torch.Generator().manual_seed(count ^ bits)
+    payload = torch.randint(0, 1 << 30, (count,), generator=g, dtype=torch.int64)
+    common = torch.randint(0, 1 << 20, (1,), generator=g, dtype=torch.int64)
+    rare = torch.randint(0, 1 << 20, (count,), generator=g, dtype=torch.int64) % 7
+    pick = torch.rand(count, generator=g) < 0.9
+    low = torch.where(pick, common.expand(count), rare)
+    keys = payload << 20 | low  # the payload above the sorted bits shows the order of ties
+    ref = keys.numpy().view(np.uint64)
+    mask = np.uint64((1 << bits) - 1) if bits < 64 else np.uint64(0xFFFFFFFFFFFFFFFF)
+    want = ref[np.argsort(ref & mask, kind="stable")]
+    got = api.sort_u64(keys.to(DEV), bits).cpu().numpy().view(np.uint64)
+    assert np.array_equal(got, want)
+
+
 # ------------------------------------------------------------------ errors
 
 @pytest.mark.parametrize("edges,n,both,name", [
