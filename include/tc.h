@@ -36,7 +36,11 @@
  *     a tc_preprocess and the calls that use its workspace.  TC_DEGREE_PARTITION=0 (for
  *     tests) computes degrees with one atomic per endpoint and orients the edges in input
  *     order, the path that graphs of more than 2^27 vertices or 2^32 endpoints take; it
- *     changes tc_workspace_size like the others.
+ *     changes tc_workspace_size like the others.  TC_WAVE_BITMAP_SPAN (for tests; unset =
+ *     65504, the largest rank span a wave's LDS bitmap holds) lowers the span below which a
+ *     middle vertex's out-list is tested as a bitmap rather than a sorted list.
+ *     TC_SORT_ONESWEEP=1 switches the radix passes of sorts of at least 2^20 keys to the
+ *     single-sweep variant (decoupled look-back instead of a histogram pass and a scan).
  */
 #ifndef TC_H
 #define TC_H
