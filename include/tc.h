@@ -29,7 +29,8 @@
  *     neighbour ids, worked through one after another.  TC_PANEL_RANKS (unset = the
  *     largest value the counting kernel supports, 32736; 0 = off) sets how many of the
  *     highest ranks of the order of Section 2.2 are counted as panels of 32 consecutive
- *     middle vertices.  TC_HUB_RANKS (unset = 0 = off; at most 65536) sets how many of the
+ *     middle vertices (tc_count_per_vertex prepares without panels, whose lists per-vertex
+ *     counts would have to split again).  TC_HUB_RANKS (unset = 0 = off; at most 65536) sets how many of the
  *     highest ranks are hubs, whose triangles (those whose lowest vertex is a hub) are
  *     counted as a masked int8 matrix product on the matrix cores (two hubs x hubs byte
  *     matrices in the workspace).  They change tc_workspace_size and must not change between

@@ -164,6 +164,11 @@ def test_panel_thresholds(monkeypatch, ranks):
                  (synth.watts_strogatz(1500, 6, 0.1, 3), 1500), synth.rmat_graph(11, 8, seed=4),
                  synth.rmat_graph(14, 16, seed=6)]:
         check_vs_oracle(e.numpy(), n)
+        # per-vertex counts on a prepared graph go through the panels one panel vertex at a
+        # time (the one-shot call prepares without panels)
+        _, opv = oracle.count(e.numpy(), n, per_vertex=True)
+        r = api.Prepared(e.to(DEV), n).count_async(per_vertex=True).check()
+        assert np.array_equal(r.per_vertex.cpu().numpy().astype(np.uint64), opv)
     for k in [3, 40, 130]:
         assert check_vs_oracle(complete(k), k) == math.comb(k, 3)
 
