@@ -27,7 +27,7 @@ __global__ void k_both_check(const uint32_t *, uint32_t, int32_t *);
 __global__ void k_csr(const uint64_t *, uint32_t, uint32_t, int, uint32_t *, uint32_t *,
                       uint32_t *, uint32_t *, int32_t *);
 __global__ void k_rowlen(const uint32_t *, const uint32_t *, uint32_t, uint32_t *);
-__global__ void k_vrange(const uint32_t *, const uint32_t *, uint32_t, uint64_t *);
+__global__ void k_vrange(const uint32_t *, const uint32_t *, uint32_t, uint32_t, uint64_t *);
 __global__ void k_panel_range(const uint64_t *, uint32_t, uint32_t, uint32_t, uint32_t,
                               uint64_t *);
 __global__ void k_csc_keys(const uint32_t *, const uint32_t *, const uint32_t *, const uint64_t *,
@@ -378,8 +378,11 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
         offs[k] = at<uint32_t>(ws, L.off[k]);
         iv[k] = at<uint32_t>(ws, L.item_v[k]);
     }
-    hipLaunchKernelGGL(k_vrange, dim3(grid_for(n, 256)), dim3(256), 0, s, row_ptr, col, n, vr);
-    TC_LAUNCH_CHECK();
+    if (L.panels) {  // spans of the panel region's out-lists
+        hipLaunchKernelGGL(k_vrange, dim3(grid_for(n - L.p0, 256)), dim3(256), 0, s, row_ptr, col,
+                           L.p0, n, vr);
+        TC_LAUNCH_CHECK();
+    }
     uint64_t *ck = (sorted == ka) ? kb : ka;  // the sorted edge keys are no longer needed
     uint64_t *ck2 = (sorted == ka) ? ka : kb;
     uint2 *eu = at<uint2>(ws, L.eu);

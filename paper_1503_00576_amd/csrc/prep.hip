@@ -359,10 +359,11 @@ __global__ void k_rowlen(const uint32_t *__restrict__ rs, const uint32_t *__rest
     len[r] = r < n ? re[r] - rs[r] : 0u;
 }
 
-// Rank span of every out-list: (min << 32) | max, or 0xFFFFFFFF00000000 (min > max) if empty.
+// Rank span of every out-list from rank v0 on (the panel region, whose spans k_panel_range
+// combines): (min << 32) | max, or 0xFFFFFFFF00000000 (min > max) if empty.
 __global__ void k_vrange(const uint32_t *__restrict__ row_ptr, const uint32_t *__restrict__ col,
-                         uint32_t n, uint64_t *__restrict__ vr) {
-    uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+                         uint32_t v0, uint32_t n, uint64_t *__restrict__ vr) {
+    uint32_t v = v0 + blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
     const uint32_t r0 = row_ptr[v], r1 = row_ptr[v + 1];
     vr[v] = r1 > r0 ? ((uint64_t)col[r0] << 32) | col[r1 - 1] : 0xFFFFFFFF00000000ull;
