@@ -117,9 +117,9 @@ def pcie_section(edges, n, m, total, ws, out, L, sp):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         dev_edges.copy_(host_edges, non_blocking=True)
-        api._raise(L.tc_preprocess(api._ptr(dev_edges), n, m, 0, api._ptr(ws), wsz, sp, None),
+        api._raise(L.tc_preprocess(api._ptr(dev_edges), n, m, 0, None, api._ptr(ws), wsz, sp, None),
                    "tc_preprocess")
-        api._raise(L.tc_count_prepared(n, m, 0, api._ptr(ws), wsz, sp, api._ptr(out.total),
+        api._raise(L.tc_count_prepared(n, m, 0, None, api._ptr(ws), wsz, sp, api._ptr(out.total),
                                        None, api._ptr(out.status)), "tc_count_prepared")
         host_total.copy_(out.total, non_blocking=True)
         torch.cuda.synchronize()
@@ -342,9 +342,9 @@ def main():
     wsz = ws.numel()
 
     def step():
-        api._raise(L.tc_preprocess(api._ptr(edges), n, m, 0, api._ptr(ws), wsz, sp, None),
+        api._raise(L.tc_preprocess(api._ptr(edges), n, m, 0, None, api._ptr(ws), wsz, sp, None),
                    "tc_preprocess")
-        api._raise(L.tc_count_prepared(n, m, 0, api._ptr(ws), wsz, sp, api._ptr(out.total),
+        api._raise(L.tc_count_prepared(n, m, 0, None, api._ptr(ws), wsz, sp, api._ptr(out.total),
                                        None, api._ptr(out.status)), "tc_count_prepared")
 
     for i in range(args.warmup):
@@ -364,10 +364,10 @@ def main():
     t0 = time.perf_counter()
     for i in range(args.steps):
         ev[i][0].record(stream)
-        api._raise(L.tc_preprocess(api._ptr(edges), n, m, 0, api._ptr(ws), wsz, sp, None),
+        api._raise(L.tc_preprocess(api._ptr(edges), n, m, 0, None, api._ptr(ws), wsz, sp, None),
                    "tc_preprocess")
         ev[i][1].record(stream)
-        api._raise(L.tc_count_prepared(n, m, 0, api._ptr(ws), wsz, sp, api._ptr(out.total),
+        api._raise(L.tc_count_prepared(n, m, 0, None, api._ptr(ws), wsz, sp, api._ptr(out.total),
                                        None, api._ptr(out.status)), "tc_count_prepared")
         ev[i][2].record(stream)
     torch.cuda.synchronize()
@@ -419,7 +419,7 @@ def main():
              for _ in range(3)]
     for a, b in pv_ev:
         a.record(stream)
-        api._raise(L.tc_count_prepared(n, m, 0, api._ptr(ws), wsz, sp, api._ptr(out.total),
+        api._raise(L.tc_count_prepared(n, m, 0, None, api._ptr(ws), wsz, sp, api._ptr(out.total),
                                        api._ptr(pv_out), api._ptr(out.status)),
                    "tc_count_prepared")
         b.record(stream)
@@ -431,7 +431,7 @@ def main():
     # the one-shot call (preprocessing without panels + per-vertex counting)
     for a, b in pv_ev:
         a.record(stream)
-        api._raise(L.tc_count_per_vertex(api._ptr(edges), n, m, 0, api._ptr(ws), wsz, sp,
+        api._raise(L.tc_count_per_vertex(api._ptr(edges), n, m, 0, None, api._ptr(ws), wsz, sp,
                                          api._ptr(out.total), api._ptr(pv_out),
                                          api._ptr(out.status)), "tc_count_per_vertex")
         b.record(stream)

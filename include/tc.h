@@ -24,24 +24,8 @@
  *     kernel reads or writes outside the caller's buffers.
  *   - Vertex ids are int32 in [0, n); n < 2^31 and the number of edge entries m < 2^32.
  *     Counts are exact uint64.
- *   - Tuning: the environment variable TC_ROW_BLOCK_BYTES (unset = one block) splits the
- *     counting phase's in-edge lists into up to 8 row blocks of at most that many bytes of
- *     neighbour ids, worked through one after another.  TC_PANEL_RANKS (unset = the
- *     largest value the counting kernel supports, 32736; 0 = off) sets how many of the
- *     highest ranks of the order of Section 2.2 are counted as panels of 32 consecutive
- *     middle vertices (tc_count_per_vertex prepares without panels, whose lists per-vertex
- *     counts would have to split again).  TC_HUB_RANKS (unset = 0 = off; at most 65536) sets how many of the
- *     highest ranks are hubs, whose triangles (those whose lowest vertex is a hub) are
- *     counted as a masked int8 matrix product on the matrix cores (two hubs x hubs byte
- *     matrices in the workspace).  They change tc_workspace_size and must not change between
- *     a tc_preprocess and the calls that use its workspace.  TC_DEGREE_PARTITION=0 (for
- *     tests) computes degrees with one atomic per endpoint and orients the edges in input
- *     order, the path that graphs of more than 2^27 vertices or 2^32 endpoints take; it
- *     changes tc_workspace_size like the others.  TC_WAVE_BITMAP_SPAN (for tests; unset =
- *     65504, the largest rank span a wave's LDS bitmap holds) lowers the span below which a
- *     middle vertex's out-list is tested as a bitmap rather than a sorted list.
- *     TC_SORT_ONESWEEP=1 switches the radix passes of sorts of at least 2^20 keys to the
- *     single-sweep variant (decoupled look-back instead of a histogram pass and a scan).
+ *   - Tuning and test options of the single-graph path are explicit arguments (tc_options
+ *     below; NULL means the defaults).  The library reads no environment variables.
  */
 #ifndef TC_H
 #define TC_H
@@ -66,7 +50,9 @@ typedef enum tc_status {
     TC_E_UNSORTED = 6,   /* batched input: a CSR row not strictly ascending */
     TC_E_WORKSPACE = 7,  /* d_ws smaller than tc_workspace_size() or misaligned */
     TC_E_TOO_LARGE = 8,  /* n >= 2^31 or m >= 2^32 */
-    TC_E_HIP = 9         /* a HIP runtime call (launch) failed */
+    TC_E_HIP = 9,        /* a HIP runtime call (launch) failed */
+    TC_E_MISMATCH = 10   /* tc_count_prepared on a workspace that tc_preprocess did not fill
+                            for the same (n, m, flags, options) */
 } tc_status;
 
 /* Edge-array multiplicity (Section 3.1 reading).
@@ -79,10 +65,71 @@ typedef enum tc_status {
 /* Human-readable name of a status code (static storage). */
 const char *tc_strerror(int status);
 
+/* Options of the single-graph path (tc_workspace_size, tc_workspace_layout, tc_preprocess,
+ * tc_count, tc_count_per_vertex, tc_count_prepared).  Fill with tc_options_init() and change
+ * fields; a NULL pointer means the defaults.  Every field takes part in the workspace layout
+ * or in the work lists built by the preprocessing, so tc_workspace_size, tc_preprocess and
+ * every tc_count_prepared on one workspace must get equal options: tc_preprocess records a
+ * fingerprint of (n, m, flags, options) in the workspace, and tc_count_prepared with other
+ * values reports TC_E_MISMATCH through d_status (on the device, before any counting kernel
+ * runs).  Values are checked by every entry point (TC_E_ARG when out of range).
+ *
+ * Counting-phase structure (the intersections of Section 3.3 grouped by the middle vertex v
+ * of each triangle u < v < w: N+(v) staged in LDS, the in-neighbours' lists streamed):
+ *   panel_ranks       the top ranks of the order of Section 2.2 counted as panels of 32
+ *                     consecutive middle vertices; 0..32736, default 32736 (the largest the
+ *                     counting kernel's LDS table holds); 0 = no panels.  tc_count_per_vertex
+ *                     always prepares without panels.
+ *   hub_ranks         the top ranks whose triangles (lowest vertex a hub) are counted as a
+ *                     masked int8 matrix product on the matrix cores; 0..65536, default 0 (off).
+ *   row_blocks        the in-edge lists split into this many contiguous CSR row blocks,
+ *                     counted one after another; 1..8, default 1.
+ *   wave_item_edges   in-edges per work item of the per-wave queue; 16..65536, default 512.
+ *   block_item_edges  in-edges per work item of the per-workgroup queue; 16..1048576,
+ *                     default 16384.
+ * Per-item structure of N+(v) (the defaults are the largest values the LDS holds; lower values
+ * send items to the other forms, which the tests use to reach every form on small graphs):
+ *   wave_bitmap_span  a wave item tests membership in an LDS bitmap when the rank span of
+ *                     N+(v) is below this; 0..65504, default 65504.
+ *   wave_list_max     otherwise a sorted LDS list when N+(v) has at most this many entries
+ *                     (per-vertex counts: at most half of it); 0..2048, default 2048; a list
+ *                     that fits neither goes to the per-workgroup queue.
+ *   block_bitmap_span a workgroup item uses an LDS bitmap below this span; 0..1048544,
+ *                     default 1048544 (totals only).
+ *   block_list_max    otherwise a sorted LDS list of at most this many entries (per-vertex:
+ *                     at most half), else the list is searched in global memory; 0..32768,
+ *                     default 32768.
+ * Preprocessing:
+ *   degree_partition  1 (default): degrees by a bucket partition of the endpoints and LDS
+ *                     counting, edges also placed in cells of id ranges for the orientation;
+ *                     0: one atomic per endpoint and orientation in input order (the path that
+ *                     graphs beyond the partition's limits, 2^27 vertices or 2^32 endpoints,
+ *                     take anyway).
+ *   sort_onesweep     0 (default): every radix pass is a histogram pass, a scan and a scatter;
+ *                     1: sorts of at least 2^20 keys use single-sweep passes (decoupled
+ *                     look-back). */
+typedef struct tc_options {
+    uint32_t size; /* sizeof(tc_options); set by tc_options_init */
+    uint32_t panel_ranks;
+    uint32_t hub_ranks;
+    uint32_t row_blocks;
+    uint32_t wave_item_edges;
+    uint32_t block_item_edges;
+    uint32_t wave_bitmap_span;
+    uint32_t wave_list_max;
+    uint32_t block_bitmap_span;
+    uint32_t block_list_max;
+    uint32_t degree_partition;
+    uint32_t sort_onesweep;
+} tc_options;
+
+/* Fills *opts with the defaults.  Returns TC_E_ARG for a NULL pointer. */
+int tc_options_init(tc_options *opts);
+
 /* Bytes of device workspace tc_count / tc_count_per_vertex / tc_preprocess need for a graph
  * of n vertices and m edge-array entries in the given format.  Pure host arithmetic; returns
  * 0 when the arguments are invalid. */
-size_t tc_workspace_size(int64_t n, int64_t m, uint32_t flags);
+size_t tc_workspace_size(int64_t n, int64_t m, uint32_t flags, const tc_options *opts);
 
 /* Triangle count of an edge array (Sections 2.2, 3.2, 3.3).
  *   d_edges : int32[2*m], entry i is the pair (d_edges[2i], d_edges[2i+1])
@@ -91,15 +138,16 @@ size_t tc_workspace_size(int64_t n, int64_t m, uint32_t flags);
  *   flags   : TC_EDGES_ONCE or TC_EDGES_BOTH
  *   d_total : uint64[1], receives the number of triangles
  *   d_status: int32[1] or NULL, receives the data-error status (see above) */
-int tc_count(const int32_t *d_edges, int64_t n, int64_t m, uint32_t flags, void *d_ws,
-             size_t ws_bytes, void *stream, uint64_t *d_total, int32_t *d_status);
+int tc_count(const int32_t *d_edges, int64_t n, int64_t m, uint32_t flags,
+             const tc_options *opts, void *d_ws, size_t ws_bytes, void *stream,
+             uint64_t *d_total, int32_t *d_status);
 
 /* As tc_count, and also the number of triangles containing each vertex (the quantity behind
  * the clustering coefficient of the paper's introduction):
  *   d_per_vertex: uint64[n]; sum over v equals 3 * (*d_total). */
 int tc_count_per_vertex(const int32_t *d_edges, int64_t n, int64_t m, uint32_t flags,
-                        void *d_ws, size_t ws_bytes, void *stream, uint64_t *d_total,
-                        uint64_t *d_per_vertex, int32_t *d_status);
+                        const tc_options *opts, void *d_ws, size_t ws_bytes, void *stream,
+                        uint64_t *d_total, uint64_t *d_per_vertex, int32_t *d_status);
 
 /* Where the preprocessing results live inside the workspace (byte offsets from d_ws), so that
  * callers can inspect the intermediate arrays after tc_preprocess:
@@ -115,21 +163,25 @@ typedef struct tc_layout {
     int32_t id_bits; /* b = bits per packed vertex id in the sort keys */
 } tc_layout;
 
-int tc_workspace_layout(int64_t n, int64_t m, uint32_t flags, tc_layout *out);
+int tc_workspace_layout(int64_t n, int64_t m, uint32_t flags, const tc_options *opts,
+                        tc_layout *out);
 
 /* Run the preprocessing phase of tc_count (degrees, order, orientation, key sort, node
  * array) and build the counting phase's work lists, leaving everything in the workspace at
  * the offsets of tc_workspace_layout.  A graph preprocessed once can be counted any number
  * of times with tc_count_prepared while its workspace stays resident. */
-int tc_preprocess(const int32_t *d_edges, int64_t n, int64_t m, uint32_t flags, void *d_ws,
-                  size_t ws_bytes, void *stream, int32_t *d_status);
+int tc_preprocess(const int32_t *d_edges, int64_t n, int64_t m, uint32_t flags,
+                  const tc_options *opts, void *d_ws, size_t ws_bytes, void *stream,
+                  int32_t *d_status);
 
 /* Counting phase only (Section 3.3), on a workspace filled by tc_preprocess with the same
- * (n, m, flags) and enqueued after it (same stream, or synchronised).  d_per_vertex may be
- * NULL (total only).  A data error found by the preprocessing is reported again here. */
-int tc_count_prepared(int64_t n, int64_t m, uint32_t flags, void *d_ws, size_t ws_bytes,
-                      void *stream, uint64_t *d_total, uint64_t *d_per_vertex,
-                      int32_t *d_status);
+ * (n, m, flags, options) and enqueued after it (same stream, or synchronised); other values
+ * give TC_E_MISMATCH in d_status.  d_per_vertex may be NULL (total only).  A data error found
+ * by the preprocessing is reported again here.  Calls on one workspace must not overlap on
+ * the device (they share its work-queue counters): enqueue them on one stream. */
+int tc_count_prepared(int64_t n, int64_t m, uint32_t flags, const tc_options *opts,
+                      void *d_ws, size_t ws_bytes, void *stream, uint64_t *d_total,
+                      uint64_t *d_per_vertex, int32_t *d_status);
 
 /* Stable ascending LSD radix sort of uint64 keys on their low `bits` bits (1..64); the
  * library's sort of packed edge keys (Section 3.2, step 3), exposed for testing.
@@ -167,8 +219,14 @@ int tc_sort_u64(uint64_t *d_keys, uint64_t *d_tmp, int64_t count, int32_t bits, 
  * hipGraph on its first run; later runs only write a small argument block and replay the
  * graph, for any batch within the capacities.  tuning_json (nullable) may set "chunk_e"
  * (forward edges per chunk, 64 .. 1536, default 1024), "items_k" (out-neighbours of a large
- * vertex per work item, >= 16, default 256) and "wgs_per_cu" (workgroups per compute unit,
- * at least 1; values above what the counting kernel's LDS allows, currently 1, are clamped).
+ * vertex per work item, >= 16, default 256), "light_max" (vertices with at most this many
+ * forward neighbours take the edge-per-lane path, 0 .. 256, default 256), "bitmap_span" and
+ * "list_max" (a large vertex's N+(u) is an LDS bitmap when its id span is below bitmap_span,
+ * 0 .. 65504, default 65504, else a sorted LDS list when it has at most list_max entries,
+ * 0 .. 2048, default 2048 (per-vertex: at most 1024), else it is searched in global memory;
+ * lower values exist for tests that reach every form on small graphs) and "wgs_per_cu"
+ * (workgroups per compute unit, at least 1; values above what the counting kernel's LDS
+ * allows, currently 1, are clamped).  Values out of range are clamped.
  * Runs of one plan must not overlap (they share the workspace); the plan must outlive its
  * last run on the GPU.  flags must be 0. */
 typedef struct tc_plan tc_plan;

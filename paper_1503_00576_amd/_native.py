@@ -9,11 +9,19 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("TC_LIB", os.path.join(HERE, "libtc.so"))
 
 EXPORTS = [
-    "tc_strerror", "tc_workspace_size", "tc_count", "tc_count_per_vertex",
+    "tc_strerror", "tc_options_init", "tc_workspace_size", "tc_count", "tc_count_per_vertex",
     "tc_workspace_layout", "tc_preprocess", "tc_count_prepared", "tc_sort_workspace_size",
     "tc_sort_u64", "tc_batched_workspace_size", "tc_batched_plan_create", "tc_batched_plan_run",
     "tc_batched_plan_destroy", "tc_count_batched",
 ]
+
+
+class TcOptions(ctypes.Structure):
+    """struct tc_options (include/tc.h); fill with tc_options_init."""
+    _fields_ = [(name, ctypes.c_uint32) for name in (
+        "size", "panel_ranks", "hub_ranks", "row_blocks", "wave_item_edges", "block_item_edges",
+        "wave_bitmap_span", "wave_list_max", "block_bitmap_span", "block_list_max",
+        "degree_partition", "sort_onesweep")]
 
 
 class TcLayout(ctypes.Structure):
@@ -37,17 +45,20 @@ def lib():
     vp, i64, u32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32, ctypes.c_size_t
     L.tc_strerror.argtypes = [ctypes.c_int]
     L.tc_strerror.restype = ctypes.c_char_p
-    L.tc_workspace_size.argtypes = [i64, i64, u32]
+    op = ctypes.POINTER(TcOptions)
+    L.tc_options_init.argtypes = [op]
+    L.tc_options_init.restype = ctypes.c_int
+    L.tc_workspace_size.argtypes = [i64, i64, u32, op]
     L.tc_workspace_size.restype = sz
-    L.tc_count.argtypes = [vp, i64, i64, u32, vp, sz, vp, vp, vp]
+    L.tc_count.argtypes = [vp, i64, i64, u32, op, vp, sz, vp, vp, vp]
     L.tc_count.restype = ctypes.c_int
-    L.tc_count_per_vertex.argtypes = [vp, i64, i64, u32, vp, sz, vp, vp, vp, vp]
+    L.tc_count_per_vertex.argtypes = [vp, i64, i64, u32, op, vp, sz, vp, vp, vp, vp]
     L.tc_count_per_vertex.restype = ctypes.c_int
-    L.tc_workspace_layout.argtypes = [i64, i64, u32, ctypes.POINTER(TcLayout)]
+    L.tc_workspace_layout.argtypes = [i64, i64, u32, op, ctypes.POINTER(TcLayout)]
     L.tc_workspace_layout.restype = ctypes.c_int
-    L.tc_preprocess.argtypes = [vp, i64, i64, u32, vp, sz, vp, vp]
+    L.tc_preprocess.argtypes = [vp, i64, i64, u32, op, vp, sz, vp, vp]
     L.tc_preprocess.restype = ctypes.c_int
-    L.tc_count_prepared.argtypes = [i64, i64, u32, vp, sz, vp, vp, vp, vp]
+    L.tc_count_prepared.argtypes = [i64, i64, u32, op, vp, sz, vp, vp, vp, vp]
     L.tc_count_prepared.restype = ctypes.c_int
     L.tc_sort_workspace_size.argtypes = [i64]
     L.tc_sort_workspace_size.restype = sz

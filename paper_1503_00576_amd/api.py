@@ -11,10 +11,11 @@ import torch
 from . import _native
 
 OK, E_ARG, E_RANGE, E_SELF_LOOP, E_DUP_EDGE, E_ASYMMETRIC, E_UNSORTED, E_WORKSPACE, \
-    E_TOO_LARGE, E_HIP = range(10)
+    E_TOO_LARGE, E_HIP, E_MISMATCH = range(11)
 STATUS_NAMES = {OK: "ok", E_ARG: "arg", E_RANGE: "range", E_SELF_LOOP: "self_loop",
                 E_DUP_EDGE: "dup_edge", E_ASYMMETRIC: "asymmetric", E_UNSORTED: "unsorted",
-                E_WORKSPACE: "workspace", E_TOO_LARGE: "too_large", E_HIP: "hip"}
+                E_WORKSPACE: "workspace", E_TOO_LARGE: "too_large", E_HIP: "hip",
+                E_MISMATCH: "mismatch"}
 
 EDGES_ONCE = 0
 EDGES_BOTH = 1
@@ -50,15 +51,39 @@ def _flags(both: bool) -> int:
     return EDGES_BOTH if both else EDGES_ONCE
 
 
-def workspace_size(n: int, m: int, both: bool = False) -> int:
-    s = _native.lib().tc_workspace_size(int(n), int(m), _flags(both))
+OPTION_NAMES = tuple(name for name, _ in _native.TcOptions._fields_ if name != "size")
+
+
+def default_options() -> dict:
+    """The library's defaults for the single-graph options (struct tc_options)."""
+    o = _native.TcOptions()
+    _raise(_native.lib().tc_options_init(ctypes.byref(o)), "tc_options_init")
+    return {k: int(getattr(o, k)) for k in OPTION_NAMES}
+
+
+def _opts(options: dict | None):
+    """struct tc_options for a dict of overrides (None: the library's defaults, NULL)."""
+    if not options:
+        return None
+    o = _native.TcOptions()
+    _raise(_native.lib().tc_options_init(ctypes.byref(o)), "tc_options_init")
+    for k, v in options.items():
+        if k not in OPTION_NAMES:
+            raise KeyError(f"unknown option {k!r}")
+        setattr(o, k, int(v))
+    return ctypes.byref(o)
+
+
+def workspace_size(n: int, m: int, both: bool = False, options: dict | None = None) -> int:
+    s = _native.lib().tc_workspace_size(int(n), int(m), _flags(both), _opts(options))
     if s == 0:
         raise TCError(E_ARG, "tc_workspace_size")
     return s
 
 
-def alloc_workspace(n: int, m: int, both: bool = False, device=None) -> torch.Tensor:
-    return torch.empty(workspace_size(n, m, both), dtype=torch.uint8, device=device)
+def alloc_workspace(n: int, m: int, both: bool = False, device=None,
+                    options: dict | None = None) -> torch.Tensor:
+    return torch.empty(workspace_size(n, m, both, options), dtype=torch.uint8, device=device)
 
 
 def _raise(code: int, where: str):
@@ -80,44 +105,47 @@ class Result:
 
 
 def count_async(edges: torch.Tensor, n: int, both: bool = False, per_vertex: bool = False,
-                workspace: torch.Tensor | None = None, out: Result | None = None) -> Result:
+                workspace: torch.Tensor | None = None, out: Result | None = None,
+                options: dict | None = None) -> Result:
     """Enqueue tc_count (or tc_count_per_vertex) on the current stream; no synchronisation."""
     edges = _check_edges(edges)
     dev = edges.device
     m = edges.shape[0]
-    ws = workspace if workspace is not None else alloc_workspace(n, m, both, dev)
+    ws = workspace if workspace is not None else alloc_workspace(n, m, both, dev, options)
+    op = _opts(options)
     if out is None:
         out = Result(torch.empty(1, dtype=torch.int64, device=dev),
                      torch.empty(1, dtype=torch.int32, device=dev),
                      torch.empty(n, dtype=torch.int64, device=dev) if per_vertex else None)
     L = _native.lib()
     if per_vertex:
-        code = L.tc_count_per_vertex(_ptr(edges), n, m, _flags(both), _ptr(ws), ws.numel(),
+        code = L.tc_count_per_vertex(_ptr(edges), n, m, _flags(both), op, _ptr(ws), ws.numel(),
                                      _stream(dev), _ptr(out.total), _ptr(out.per_vertex),
                                      _ptr(out.status))
     else:
-        code = L.tc_count(_ptr(edges), n, m, _flags(both), _ptr(ws), ws.numel(), _stream(dev),
-                          _ptr(out.total), _ptr(out.status))
+        code = L.tc_count(_ptr(edges), n, m, _flags(both), op, _ptr(ws), ws.numel(),
+                          _stream(dev), _ptr(out.total), _ptr(out.status))
     _raise(code, "tc_count")
     return out
 
 
-def count(edges: torch.Tensor, n: int, both: bool = False) -> int:
+def count(edges: torch.Tensor, n: int, both: bool = False, options: dict | None = None) -> int:
     """Exact number of triangles of the graph given as an int32 [m, 2] edge array."""
-    r = count_async(edges, n, both).check()
+    r = count_async(edges, n, both, options=options).check()
     return int(r.total.item()) & 0xFFFFFFFFFFFFFFFF
 
 
-def count_per_vertex(edges: torch.Tensor, n: int, both: bool = False):
+def count_per_vertex(edges: torch.Tensor, n: int, both: bool = False,
+                     options: dict | None = None):
     """(total, per-vertex counts as int64 [n] on the device)."""
-    r = count_async(edges, n, both, per_vertex=True).check()
+    r = count_async(edges, n, both, per_vertex=True, options=options).check()
     return int(r.total.item()) & 0xFFFFFFFFFFFFFFFF, r.per_vertex
 
 
-def layout(n: int, m: int, both: bool = False) -> _native.TcLayout:
+def layout(n: int, m: int, both: bool = False, options: dict | None = None) -> _native.TcLayout:
     lay = _native.TcLayout()
-    _raise(_native.lib().tc_workspace_layout(n, m, _flags(both), ctypes.byref(lay)),
-           "tc_workspace_layout")
+    _raise(_native.lib().tc_workspace_layout(n, m, _flags(both), _opts(options),
+                                             ctypes.byref(lay)), "tc_workspace_layout")
     return lay
 
 
@@ -126,17 +154,19 @@ class Prepared:
     can be counted again with count_prepared()."""
 
     def __init__(self, edges: torch.Tensor, n: int, both: bool = False,
-                 workspace: torch.Tensor | None = None):
+                 workspace: torch.Tensor | None = None, options: dict | None = None):
         edges = _check_edges(edges)
         self.device = edges.device
         self.n, self.m, self.both = int(n), int(edges.shape[0]), bool(both)
+        self.options = dict(options) if options else None
         self.workspace = (workspace if workspace is not None
-                          else alloc_workspace(self.n, self.m, self.both, self.device))
+                          else alloc_workspace(self.n, self.m, self.both, self.device,
+                                               self.options))
         self.status = torch.zeros(1, dtype=torch.int32, device=self.device)
         _raise(_native.lib().tc_preprocess(_ptr(edges), self.n, self.m, _flags(self.both),
-                                           _ptr(self.workspace), self.workspace.numel(),
-                                           _stream(self.device), _ptr(self.status)),
-               "tc_preprocess")
+                                           _opts(self.options), _ptr(self.workspace),
+                                           self.workspace.numel(), _stream(self.device),
+                                           _ptr(self.status)), "tc_preprocess")
 
     def count_async(self, per_vertex: bool = False, out: Result | None = None) -> Result:
         dev = self.device
@@ -145,9 +175,10 @@ class Prepared:
                          torch.empty(1, dtype=torch.int32, device=dev),
                          torch.empty(self.n, dtype=torch.int64, device=dev) if per_vertex else None)
         _raise(_native.lib().tc_count_prepared(
-            self.n, self.m, _flags(self.both), _ptr(self.workspace), self.workspace.numel(),
-            _stream(dev), _ptr(out.total), _ptr(out.per_vertex) if per_vertex else None,
-            _ptr(out.status)), "tc_count_prepared")
+            self.n, self.m, _flags(self.both), _opts(self.options), _ptr(self.workspace),
+            self.workspace.numel(), _stream(dev), _ptr(out.total),
+            _ptr(out.per_vertex) if per_vertex else None, _ptr(out.status)),
+            "tc_count_prepared")
         return out
 
     def count(self) -> int:
@@ -159,7 +190,7 @@ class Prepared:
         st = int(self.status.item())
         if st:
             raise TCError(st, "device")
-        lay = layout(self.n, self.m, self.both)
+        lay = layout(self.n, self.m, self.both, self.options)
         ws = self.workspace
 
         def view(off, count):
@@ -170,9 +201,10 @@ class Prepared:
                 "col": view(lay.col, lay.m_fwd), "id_bits": lay.id_bits}
 
 
-def preprocess(edges: torch.Tensor, n: int, both: bool = False) -> dict:
+def preprocess(edges: torch.Tensor, n: int, both: bool = False,
+               options: dict | None = None) -> dict:
     """Run the preprocessing phase only and return views of its arrays (see Prepared)."""
-    p = Prepared(edges, n, both)
+    p = Prepared(edges, n, both, options=options)
     out = p.arrays()
     out["prepared"] = p
     return out

@@ -76,64 +76,85 @@ struct Layout {
     uint32_t p0, panels;  // panel region: ranks [p0, n) in panels of count_panel() ranks
     uint32_t h0, hp;      // hubs: ranks [h0, n), matrices hp x hp (hp = 0: no hubs)
     uint64_t lists;       // in-edge lists: nblk * (n + 1)
+    tc_options opt;       // resolved options
+    uint32_t finger;      // fingerprint of (n, m, flags, options, panels), never 0
 };
 
 // item spaces: [0] wave / [1] workgroup items for total counts, [2] / [3] for per-vertex counts
-enum { kCtlStatus = 0, kCtlBoth = 1, kCtlQueueA = 2, kCtlQueueB = 3, kCtlWords = 64 };
+// ctl words: status of the preprocessing, forward-entry counter (two-direction format), the
+// two item queues, the fingerprint of the prepared layout, status of the current count
+enum {
+    kCtlStatus = 0, kCtlBoth = 1, kCtlQueueA = 2, kCtlQueueB = 3, kCtlFinger = 4, kCtlRun = 5,
+    kCtlWords = 64
+};
+// start of a preprocessing: clear the control words and record the layout's fingerprint
+__global__ void k_ctl_init(uint32_t *__restrict__ ctl, uint32_t finger) {
+    const uint32_t t = threadIdx.x;
+    ctl[t] = t == kCtlFinger ? finger : 0u;  // 64 threads, one word each
+}
+
+// start of a count on a prepared workspace: its status is the preprocessing's, or a mismatch
+// when the workspace was prepared for another layout; the item queues restart
+__global__ void k_ctl_check(uint32_t *__restrict__ ctl, uint32_t finger) {
+    if (threadIdx.x != 0) return;
+    int32_t st = (int32_t)ctl[kCtlStatus];
+    if (st == 0 && ctl[kCtlFinger] != finger) st = TC_E_MISMATCH;
+    ctl[kCtlRun] = (uint32_t)st;
+    ctl[kCtlQueueA] = 0;
+    ctl[kCtlQueueB] = 0;
+}
+
 constexpr uint32_t kPartTileEdges = 4096;  // edges per tile of the degree partition
 // workgroups of the orientation over cell-ordered edges (a multiple of the 8 XCDs; 2 per CU
 // measured faster than 4 or 8: fewer edges in flight per XCD keep its lookups inside fewer
 // cells)
 constexpr uint32_t kOrientGrid = 512;
 constexpr uint32_t kCscPerThread = 4;  // in-edge keys per thread (prep.hip, kCscEdges)
+constexpr uint32_t kMaxRowBlocks = 8;
+constexpr uint32_t kMaxHubRanks = 1u << 16;  // two matrices of at most 4 GiB each
 
-// Row blocks of the in-edge lists: contiguous CSR ranges of at most TC_ROW_BLOCK_BYTES of
-// neighbour ids (at most 8 blocks), worked through one after another by the counting kernel.
-// Default: one block (blocking at the memory-side cache size measured slower on R-MAT 23).
-static uint32_t row_blocks_for(uint32_t n, uint32_t mf) {
-    uint64_t block_bytes = 0;  // one block unless overridden
-    if (const char *env = getenv("TC_ROW_BLOCK_BYTES")) {  // tuning / testing override
-        unsigned long long v = strtoull(env, nullptr, 10);
-        if (v >= 64) block_bytes = v;
-    }
-    if (block_bytes == 0) return 1;
-    uint64_t k = ((uint64_t)mf * 4 + block_bytes - 1) / block_bytes;
-    if (k < 1) k = 1;
-    if (k > 8) k = 8;
-    while (k > 1 && k * ((uint64_t)n + 1) >= (1ull << 32)) --k;
-    return (uint32_t)k;
+static void default_options(tc_options &o) {
+    memset(&o, 0, sizeof(o));
+    o.size = sizeof(tc_options);
+    o.panel_ranks = count_panel_ranks();
+    o.hub_ranks = 0;  // off: at R-MAT scale 23 (1.9e8 edges) 16384 hubs take the sparse kernel
+                      // from 20.95 to 19.59 ms but add 3.9 ms of matrix products
+    o.row_blocks = 1;  // blocking at the memory-side cache size measured slower on R-MAT 23
+    o.wave_item_edges = count_item_edges_wave();
+    o.block_item_edges = count_item_edges_block();
+    o.wave_bitmap_span = count_wave_span();
+    o.wave_list_max = count_wave_list(false);
+    o.block_bitmap_span = count_block_span();
+    o.block_list_max = count_block_list(false);
+    o.degree_partition = 1;
+    o.sort_onesweep = 0;
 }
 
-// Middle-vertex panels over the top TC_PANEL_RANKS ranks (default and maximum: what the
-// counting kernel's LDS table holds; 0 switches panels off).
-static uint32_t panel_ranks_for(uint32_t n) {
-    uint64_t x = count_panel_ranks();
-    if (const char *env = getenv("TC_PANEL_RANKS")) {  // tuning / testing override
-        unsigned long long v = strtoull(env, nullptr, 10);
-        if (v < x) x = v;
-    }
-    return (uint32_t)(x < n ? x : n);
+// the caller's options (NULL: defaults), checked against the limits the kernels are built for
+static bool resolve_options(const tc_options *in, tc_options &o) {
+    default_options(o);
+    if (!in) return true;
+    if (in->size != sizeof(tc_options)) return false;
+    o = *in;
+    return o.panel_ranks <= count_panel_ranks() && o.hub_ranks <= kMaxHubRanks &&
+           o.row_blocks >= 1 && o.row_blocks <= kMaxRowBlocks && o.wave_item_edges >= 16 &&
+           o.wave_item_edges <= (1u << 16) && o.block_item_edges >= 16 &&
+           o.block_item_edges <= (1u << 20) && o.wave_bitmap_span <= count_wave_span() &&
+           o.wave_list_max <= count_wave_list(false) &&
+           o.block_bitmap_span <= count_block_span() &&
+           o.block_list_max <= count_block_list(false) && o.degree_partition <= 1 &&
+           o.sort_onesweep <= 1;
 }
 
-// Rank span below which wave items use a bitmap (else a sorted list); lowered
-// only by tests, through TC_WAVE_BITMAP_SPAN, to reach the other forms on small graphs.
-static uint32_t wave_bits_for() {
-    uint64_t x = count_wave_span(false);
-    if (const char *env = getenv("TC_WAVE_BITMAP_SPAN")) {
-        unsigned long long v = strtoull(env, nullptr, 10);
-        if (v < x) x = v;
-    }
-    return (uint32_t)x;
-}
-
-// Hubs, whose triangles are counted on the matrix cores: the top TC_HUB_RANKS ranks (unset or
-// 0 = off).  Off unless asked for: at R-MAT scale 23 (1.9e8 edges) 16384 hubs take the sparse
-// kernel from 20.95 to 19.59 ms but add 3.9 ms of matrix products and 0.34 ms of matrix fill.
-static uint32_t hub_ranks_for(uint32_t n) {
-    uint64_t x = 0;
-    if (const char *env = getenv("TC_HUB_RANKS")) x = strtoull(env, nullptr, 10);
-    if (x > (1u << 16)) x = 1u << 16;  // two matrices of at most 4 GiB each
-    return (uint32_t)(x < n ? x : n);
+// FNV-1a over 32-bit words
+static uint32_t fnv_words(const uint32_t *w, size_t k) {
+    uint32_t h = 2166136261u;
+    for (size_t i = 0; i < k; ++i)
+        for (int b = 0; b < 4; ++b) {
+            h ^= (w[i] >> (8 * b)) & 0xFFu;
+            h *= 16777619u;
+        }
+    return h;
 }
 
 static int id_bits_for(uint32_t n) {
@@ -151,18 +172,24 @@ static int id_bits_for64(uint64_t x) {
 
 // panels = false: no panel region (every middle vertex has its own in-edge list), which needs
 // no more workspace than the default layout (only the panel range table shrinks)
-static bool make_layout(int64_t n, int64_t m, uint32_t flags, Layout &L, bool panels = true) {
+static bool make_layout(int64_t n, int64_t m, uint32_t flags, const tc_options *opts, Layout &L,
+                        bool panels = true) {
     if (n < 0 || m < 0 || n >= (1ll << 31) || m >= (1ll << 32)) return false;
     if (flags & ~TC_EDGES_BOTH) return false;
+    if (!resolve_options(opts, L.opt)) return false;
+    const tc_options &o = L.opt;
     L.n = (uint32_t)n;
     L.m = (uint32_t)m;
     L.mf = (flags & TC_EDGES_BOTH) ? (uint32_t)(m / 2) : (uint32_t)m;
     L.kcap = L.m > L.n ? L.m : L.n;
     L.id_bits = (uint32_t)id_bits_for(L.n);
-    L.nblk = row_blocks_for(L.n, L.mf);
-    L.p0 = panels ? L.n - panel_ranks_for(L.n) : L.n;
+    // row blocks: at most what 32-bit list ids (block * (n + 1) + v) allow
+    L.nblk = o.row_blocks;
+    while (L.nblk > 1 && (uint64_t)L.nblk * ((uint64_t)n + 1) >= (1ull << 32)) --L.nblk;
+    const uint32_t pr = o.panel_ranks < L.n ? o.panel_ranks : L.n;
+    L.p0 = panels ? L.n - pr : L.n;
     {
-        const uint32_t h = hub_ranks_for(L.n);
+        const uint32_t h = o.hub_ranks < L.n ? o.hub_ranks : L.n;
         L.h0 = L.n - h;
         L.hp = (h + 63u) & ~63u;
     }
@@ -182,10 +209,9 @@ static bool make_layout(int64_t n, int64_t m, uint32_t flags, Layout &L, bool pa
         const uint64_t endpoints = (flags & TC_EDGES_BOTH) ? (uint64_t)m : 2ull * (uint64_t)m;
         const int db = L.id_bits < 8 ? (int)L.id_bits : 8;
         L.part_shift = (int)L.id_bits - db;
-        // TC_DEGREE_PARTITION=0 forces the atomic fallback (tests of the path that inputs of
-        // more than 2^27 vertices or 2^32 endpoints take)
-        const char *pe = getenv("TC_DEGREE_PARTITION");
-        const bool part_on = !(pe && pe[0] == '0');
+        // degree_partition = 0 forces the atomic path (the one that inputs of more than 2^27
+        // vertices or 2^32 endpoints take)
+        const bool part_on = o.degree_partition != 0;
         L.part_tiles = (part_on && endpoints < (1ull << 32) && L.part_shift <= 19)
                            ? ceil_div((uint64_t)m > 0 ? (uint64_t)m : 1, kPartTileEdges)
                            : 0u;
@@ -222,7 +248,7 @@ static bool make_layout(int64_t n, int64_t m, uint32_t flags, Layout &L, bool pa
     L.cend = take((size_t)L.mf * 4);
     L.cmask = take((size_t)L.mf * 4);
     for (int k = 0; k < 4; ++k) {
-        const uint32_t per = (k & 1) ? count_item_edges_block() : count_item_edges_wave();
+        const uint32_t per = (k & 1) ? o.block_item_edges : o.wave_item_edges;
         L.items[k] = take(l1 * 4);
         L.off[k] = take(l1 * 4);
         L.item_v[k] = take(((size_t)L.mf / per + l1 + 1) * 4);
@@ -232,6 +258,19 @@ static bool make_layout(int64_t n, int64_t m, uint32_t flags, Layout &L, bool pa
     L.hub_a = take((size_t)L.hp * L.hp);
     L.hub_at = take((size_t)L.hp * L.hp);
     L.total_bytes = off;
+    {
+        uint32_t w[8 + sizeof(tc_options) / 4];
+        w[0] = L.n;
+        w[1] = L.m;
+        w[2] = flags;
+        w[3] = L.p0;
+        w[4] = L.h0;
+        w[5] = L.nblk;
+        w[6] = L.part_tiles;
+        w[7] = (uint32_t)L.cell_shift;
+        memcpy(w + 8, &o, sizeof(tc_options));
+        L.finger = fnv_words(w, sizeof(w) / 4) | 1u;
+    }
     return true;
 }
 
@@ -259,14 +298,15 @@ static inline uint32_t grid_for(uint64_t items, uint32_t threads, uint32_t cap =
             return TC_E_HIP;     \
     } while (0)
 
-static int check_args(const int32_t *d_edges, int64_t n, int64_t m, uint32_t flags, void *d_ws,
-                      size_t ws_bytes, Layout &L, bool panels = true) {
+static int check_args(const int32_t *d_edges, int64_t n, int64_t m, uint32_t flags,
+                      const tc_options *opts, void *d_ws, size_t ws_bytes, Layout &L,
+                      bool panels = true) {
     if (n < 0 || m < 0 || (flags & ~TC_EDGES_BOTH)) return TC_E_ARG;
     if (n >= (1ll << 31) || m >= (1ll << 32)) return TC_E_TOO_LARGE;
     if (n == 0 && m > 0) return TC_E_ARG;
     if (m > 0 && (!d_edges || ((uintptr_t)d_edges & 7))) return TC_E_ARG;
     if ((flags & TC_EDGES_BOTH) && (m & 1)) return TC_E_ASYMMETRIC;
-    if (!make_layout(n, m, flags, L, panels)) return TC_E_ARG;
+    if (!make_layout(n, m, flags, opts, L, panels)) return TC_E_ARG;
     if (!d_ws || ((uintptr_t)d_ws & 255) || ws_bytes < L.total_bytes) return TC_E_WORKSPACE;
     return TC_OK;
 }
@@ -292,7 +332,9 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
     uint32_t *scan_scr = at<uint32_t>(ws, L.scan_scratch);
     // cell-ordered edges for the orientation: the in-edge payload buffer, unused until later
     int2 *cells = L.cell_shift >= 0 ? at<int2>(ws, L.eu) : nullptr;
-    TC_HIP(fill_u32(ctl, 0u, kCtlWords, s));
+    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, s, ctl, L.finger);
+    TC_LAUNCH_CHECK();
+    const bool onesweep = L.opt.sort_onesweep != 0;
     TC_HIP(fill_u32(deg, 0u, n, s));
     if (m > 0 && L.part_tiles) {
         const uint32_t tiles = L.part_tiles;
@@ -341,7 +383,7 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
             hipLaunchKernelGGL(k_both_check, dim3(1), dim3(64), 0, s, ctl + kCtlBoth, mf, status);
             TC_LAUNCH_CHECK();
         }
-        TC_HIP(sort_u64(ka, kb, mf, 0, 2 * b, sort_scr, status, s, &sorted));
+        TC_HIP(sort_u64(ka, kb, mf, 0, 2 * b, sort_scr, status, s, &sorted, onesweep));
     }
     if (mf == 0) {
         TC_HIP(fill_u32(row_ptr, 0u, n1, s));
@@ -397,7 +439,8 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
                        pr, mf, n, L.nblk, L.p0, count_panel(), L.h0, ck, eu, status);
     TC_LAUNCH_CHECK();
     uint64_t *cks = ck;
-    TC_HIP(sort_u64(ck, ck2, mf, 32, 32 + id_bits_for64(l1), sort_scr, status, s, &cks));
+    TC_HIP(sort_u64(ck, ck2, mf, 32, 32 + id_bits_for64(l1), sort_scr, status, s, &cks,
+                    onesweep));
     TC_HIP(fill_u32(lrs, 0u, l1, s));
     TC_HIP(fill_u32(lre, 0u, l1, s));
     // one entry per thread: its gather is bound by the random-line rate, not by latency
@@ -409,11 +452,13 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
                        (uint32_t)L.lists, cnt);
     TC_LAUNCH_CHECK();
     TC_HIP(scan_exclusive_u32(cnt, cptr, l1, scan_scr, s));
+    const tc_options &o = L.opt;
+    const uint32_t wl_pv = o.wave_list_max < count_wave_list(true) ? o.wave_list_max
+                                                                     : count_wave_list(true);
     hipLaunchKernelGGL(k_items, dim3(grid_for(l1, 256)), dim3(256), 0, s, row_ptr, col, cnt, n,
-                       L.nblk, L.p0, wave_bits_for(), count_wave_list(false),
-                       count_wave_list(true),
-                       count_item_edges_wave(), count_item_edges_block(), items[0], items[1],
-                       items[2], items[3], status);
+                       L.nblk, L.p0, o.wave_bitmap_span, o.wave_list_max, wl_pv,
+                       o.wave_item_edges, o.block_item_edges, items[0], items[1], items[2],
+                       items[3], status);
     TC_LAUNCH_CHECK();
     for (int k = 0; k < 4; ++k) TC_HIP(scan_exclusive_u32(items[k], offs[k], l1, scan_scr, s));
     for (int k = 0; k < 4; ++k) {
@@ -430,7 +475,11 @@ static int run_count_prepared(void *ws, const Layout &L, hipStream_t s, uint64_t
     const bool pv = d_pv != nullptr;
     const uint32_t n = L.n;
     uint32_t *ctl = at<uint32_t>(ws, L.ctl);
-    int32_t *status = (int32_t *)ctl + kCtlStatus;
+    // this count's status: the preprocessing's, or a mismatch of the prepared layout (the
+    // check also resets the item queues)
+    int32_t *status = (int32_t *)ctl + kCtlRun;
+    hipLaunchKernelGGL(k_ctl_check, dim3(1), dim3(64), 0, s, ctl, L.finger);
+    TC_LAUNCH_CHECK();
     unsigned long long *total = (unsigned long long *)d_total;
     unsigned long long *tpv = at<unsigned long long>(ws, L.tpv);
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, total, (uint64_t)1);
@@ -441,7 +490,6 @@ static int run_count_prepared(void *ws, const Layout &L, hipStream_t s, uint64_t
         TC_LAUNCH_CHECK();
     }
     if (L.mf > 0) {
-        TC_HIP(fill_u32(ctl + kCtlQueueA, 0u, 2, s));
         const int a0 = pv ? 2 : 0, b0 = pv ? 3 : 1;
         CountArgs a;
         a.row_ptr = at<uint32_t>(ws, L.row_ptr);
@@ -463,7 +511,13 @@ static int run_count_prepared(void *ws, const Layout &L, hipStream_t s, uint64_t
         a.tpv = tpv;
         a.n1 = n + 1;
         a.p0 = L.p0;
-        a.wave_bits = wave_bits_for();
+        const tc_options &o = L.opt;
+        a.wave_bits = o.wave_bitmap_span;
+        a.block_bits = o.block_bitmap_span;
+        a.block_list = o.block_list_max < count_block_list(pv) ? o.block_list_max
+                                                                : count_block_list(pv);
+        a.kitem_a = o.wave_item_edges;
+        a.kitem_b = o.block_item_edges;
         a.status = status;
         TC_HIP(launch_count(a, pv, s));
         TC_HIP(launch_hub_count(at<uint8_t>(ws, L.hub_a), at<uint8_t>(ws, L.hub_at), L.hp, L.h0,
@@ -477,9 +531,11 @@ static int run_count_prepared(void *ws, const Layout &L, hipStream_t s, uint64_t
     return TC_OK;
 }
 
-static int copy_status(void *ws, const Layout &L, int32_t *d_status, hipStream_t s) {
+static int copy_status(void *ws, const Layout &L, int32_t *d_status, hipStream_t s,
+                       int word) {
     if (!d_status) return TC_OK;
-    hipLaunchKernelGGL(k_copy_status, dim3(1), dim3(64), 0, s, at<int32_t>(ws, L.ctl), d_status);
+    hipLaunchKernelGGL(k_copy_status, dim3(1), dim3(64), 0, s, at<int32_t>(ws, L.ctl) + word,
+                       d_status);
     TC_LAUNCH_CHECK();
     return TC_OK;
 }
@@ -487,18 +543,18 @@ static int copy_status(void *ws, const Layout &L, int32_t *d_status, hipStream_t
 // Preprocessing and counting in one call.  With per-vertex counts the graph is prepared
 // without panels: a panel's list merges the in-edges of 32 middle vertices, which per-vertex
 // counts would split again one panel vertex at a time (83 vs 150 ms at R-MAT scale 23).
-static int run_count(const int32_t *d_edges, int64_t n, int64_t m, uint32_t flags, void *ws,
-                     size_t ws_bytes, hipStream_t s, uint64_t *d_total, uint64_t *d_pv,
-                     int32_t *d_status) {
+static int run_count(const int32_t *d_edges, int64_t n, int64_t m, uint32_t flags,
+                     const tc_options *opts, void *ws, size_t ws_bytes, hipStream_t s,
+                     uint64_t *d_total, uint64_t *d_pv, int32_t *d_status) {
     Layout L;
-    int st = check_args(d_edges, n, m, flags, ws, ws_bytes, L, d_pv == nullptr);
+    int st = check_args(d_edges, n, m, flags, opts, ws, ws_bytes, L, d_pv == nullptr);
     if (st) return st;
     if (!d_total) return TC_E_ARG;
     st = run_preprocess(d_edges, flags, ws, L, s);
     if (st) return st;
     st = run_count_prepared(ws, L, s, d_total, L.n > 0 ? d_pv : nullptr);
     if (st) return st;
-    return copy_status(ws, L, d_status, s);
+    return copy_status(ws, L, d_status, s, kCtlRun);
 }
 
 }  // namespace tc
@@ -519,20 +575,28 @@ const char *tc_strerror(int status) {
         case TC_E_WORKSPACE: return "workspace too small or misaligned";
         case TC_E_TOO_LARGE: return "graph too large for 32-bit indices";
         case TC_E_HIP: return "HIP runtime error";
+        case TC_E_MISMATCH: return "workspace prepared for another graph size or other options";
         default: return "unknown status";
     }
 }
 
-size_t tc_workspace_size(int64_t n, int64_t m, uint32_t flags) {
+int tc_options_init(tc_options *opts) {
+    if (!opts) return TC_E_ARG;
+    default_options(*opts);
+    return TC_OK;
+}
+
+size_t tc_workspace_size(int64_t n, int64_t m, uint32_t flags, const tc_options *opts) {
     Layout L;
-    if (!make_layout(n, m, flags, L)) return 0;
+    if (!make_layout(n, m, flags, opts, L)) return 0;
     return L.total_bytes;
 }
 
-int tc_workspace_layout(int64_t n, int64_t m, uint32_t flags, tc_layout *out) {
+int tc_workspace_layout(int64_t n, int64_t m, uint32_t flags, const tc_options *opts,
+                        tc_layout *out) {
     Layout L;
     if (!out) return TC_E_ARG;
-    if (!make_layout(n, m, flags, L)) return TC_E_ARG;
+    if (!make_layout(n, m, flags, opts, L)) return TC_E_ARG;
     out->deg = L.deg;
     out->perm = L.perm;
     out->rank = L.rank;
@@ -543,42 +607,44 @@ int tc_workspace_layout(int64_t n, int64_t m, uint32_t flags, tc_layout *out) {
     return TC_OK;
 }
 
-int tc_count(const int32_t *d_edges, int64_t n, int64_t m, uint32_t flags, void *d_ws,
-             size_t ws_bytes, void *stream, uint64_t *d_total, int32_t *d_status) {
-    return run_count(d_edges, n, m, flags, d_ws, ws_bytes, (hipStream_t)stream, d_total,
+int tc_count(const int32_t *d_edges, int64_t n, int64_t m, uint32_t flags,
+             const tc_options *opts, void *d_ws, size_t ws_bytes, void *stream,
+             uint64_t *d_total, int32_t *d_status) {
+    return run_count(d_edges, n, m, flags, opts, d_ws, ws_bytes, (hipStream_t)stream, d_total,
                      nullptr, d_status);
 }
 
 int tc_count_per_vertex(const int32_t *d_edges, int64_t n, int64_t m, uint32_t flags,
-                        void *d_ws, size_t ws_bytes, void *stream, uint64_t *d_total,
-                        uint64_t *d_per_vertex, int32_t *d_status) {
+                        const tc_options *opts, void *d_ws, size_t ws_bytes, void *stream,
+                        uint64_t *d_total, uint64_t *d_per_vertex, int32_t *d_status) {
     if (!d_per_vertex && n > 0) return TC_E_ARG;
-    return run_count(d_edges, n, m, flags, d_ws, ws_bytes, (hipStream_t)stream, d_total,
+    return run_count(d_edges, n, m, flags, opts, d_ws, ws_bytes, (hipStream_t)stream, d_total,
                      d_per_vertex, d_status);
 }
 
-int tc_preprocess(const int32_t *d_edges, int64_t n, int64_t m, uint32_t flags, void *d_ws,
-                  size_t ws_bytes, void *stream, int32_t *d_status) {
+int tc_preprocess(const int32_t *d_edges, int64_t n, int64_t m, uint32_t flags,
+                  const tc_options *opts, void *d_ws, size_t ws_bytes, void *stream,
+                  int32_t *d_status) {
     Layout L;
-    int st = check_args(d_edges, n, m, flags, d_ws, ws_bytes, L);
+    int st = check_args(d_edges, n, m, flags, opts, d_ws, ws_bytes, L);
     if (st) return st;
     st = run_preprocess(d_edges, flags, d_ws, L, (hipStream_t)stream);
     if (st) return st;
-    return copy_status(d_ws, L, d_status, (hipStream_t)stream);
+    return copy_status(d_ws, L, d_status, (hipStream_t)stream, kCtlStatus);
 }
 
-int tc_count_prepared(int64_t n, int64_t m, uint32_t flags, void *d_ws, size_t ws_bytes,
-                      void *stream, uint64_t *d_total, uint64_t *d_per_vertex,
-                      int32_t *d_status) {
+int tc_count_prepared(int64_t n, int64_t m, uint32_t flags, const tc_options *opts,
+                      void *d_ws, size_t ws_bytes, void *stream, uint64_t *d_total,
+                      uint64_t *d_per_vertex, int32_t *d_status) {
     Layout L;
     if (n < 0 || m < 0 || (flags & ~TC_EDGES_BOTH)) return TC_E_ARG;
     if (n >= (1ll << 31) || m >= (1ll << 32)) return TC_E_TOO_LARGE;
-    if (!make_layout(n, m, flags, L) || !d_total) return TC_E_ARG;
+    if (!make_layout(n, m, flags, opts, L) || !d_total) return TC_E_ARG;
     if (!d_ws || ((uintptr_t)d_ws & 255) || ws_bytes < L.total_bytes) return TC_E_WORKSPACE;
     int st = run_count_prepared(d_ws, L, (hipStream_t)stream, d_total,
                                 L.n > 0 ? d_per_vertex : nullptr);
     if (st) return st;
-    return copy_status(d_ws, L, d_status, (hipStream_t)stream);
+    return copy_status(d_ws, L, d_status, (hipStream_t)stream, kCtlRun);
 }
 
 size_t tc_sort_workspace_size(int64_t count) {

@@ -434,6 +434,9 @@ struct tc_plan {
     uint32_t gcap, ncap;
     uint64_t acap;
     uint32_t kitem, chunk, wgs_per_cu;
+    uint32_t light_max;  // forward-degree threshold of the edge-per-lane path
+    uint32_t wave_bits;  // heavy items: bitmap below this id span
+    uint32_t wave_list;  // heavy items: sorted LDS list of at most this many entries
     void *ws;
     size_t ws_bytes;
     BatchLayout L;
@@ -449,6 +452,17 @@ static uint32_t parse_tuning(const char *json, const char *key, uint32_t dflt) {
     if (!p) return dflt;
     long v = strtol(p + 1, nullptr, 10);
     return v > 0 ? (uint32_t)v : dflt;
+}
+
+// as parse_tuning, but 0 is a value (negative values give the default)
+static uint32_t parse_tuning_or_zero(const char *json, const char *key, uint32_t dflt) {
+    if (!json) return dflt;
+    const char *p = strstr(json, key);
+    if (!p) return dflt;
+    p = strchr(p + strlen(key), ':');
+    if (!p) return dflt;
+    long v = strtol(p + 1, nullptr, 10);
+    return v >= 0 ? (uint32_t)(v > 0x7FFFFFFFl ? 0x7FFFFFFFl : v) : dflt;
 }
 
 // enqueue the whole sequence (this is what gets captured)
@@ -478,7 +492,7 @@ static int batch_enqueue(tc_plan *p, bool pv, hipStream_t s) {
     hipLaunchKernelGGL(k_b_ffill, vgrid(ncap), dim3(256), 0, s, args, gid, deg, frp, fcol, fsrc);
     // ctl: [0] heavy-item queue, [1] light-chunk queue, [2] forward edges, [3] light chunks
     hipLaunchKernelGGL(k_b_items, grid(n1), dim3(256), 0, s, args, ncap, fdeg, frp,
-                       count_light_max(), items, ctl + 2);
+                       p->light_max, items, ctl + 2);
     if (hipGetLastError() != hipSuccess) return TC_E_HIP;
     if (scan_exclusive_u32(items, ioff, n1, scan, s) != hipSuccess) return TC_E_HIP;
     hipLaunchKernelGGL(k_b_item_fill, grid(ncap), dim3(256), 0, s, items, ioff, ncap, item_u);
@@ -497,6 +511,11 @@ static int batch_enqueue(tc_plan *p, bool pv, hipStream_t s) {
     ka.queue = ctl;
     ka.totals_pp = &args->totals;
     ka.tpv_pp = &args->per_vertex;
+    ka.light_max = p->light_max;
+    ka.wave_bits = p->wave_bits;
+    ka.wave_list = pv ? (p->wave_list < count_wave_list(true) ? p->wave_list
+                                                              : count_wave_list(true))
+                      : p->wave_list;
     if (launch_count_u(ka, pv, device_cu_count() * p->wgs_per_cu, s) != hipSuccess)
         return TC_E_HIP;
     hipLaunchKernelGGL(k_b_finish, grid(p->gcap), dim3(256), 0, s, args, frp, ghash, gstat);
@@ -589,6 +608,15 @@ int tc_batched_plan_create(int32_t g_cap, int64_t n_cap, int64_t adj_cap, uint32
     if (p->chunk > count_light_chunk_max()) p->chunk = count_light_chunk_max();
     p->wgs_per_cu = parse_tuning(tuning_json, "\"wgs_per_cu\"", count_wgs_per_cu());
     if (p->wgs_per_cu > count_wgs_per_cu()) p->wgs_per_cu = count_wgs_per_cu();  // LDS limit
+    // the light/heavy threshold and the heavy items' LDS forms: the defaults are the largest
+    // values the LDS holds; lower values are accepted (tuning, and tests that reach every
+    // form on small graphs)
+    p->light_max = parse_tuning_or_zero(tuning_json, "\"light_max\"", count_light_max());
+    if (p->light_max > count_light_max()) p->light_max = count_light_max();
+    p->wave_bits = parse_tuning_or_zero(tuning_json, "\"bitmap_span\"", count_wave_span());
+    if (p->wave_bits > count_wave_span()) p->wave_bits = count_wave_span();
+    p->wave_list = parse_tuning_or_zero(tuning_json, "\"list_max\"", count_wave_list(false));
+    if (p->wave_list > count_wave_list(false)) p->wave_list = count_wave_list(false);
     p->ws = d_ws;
     p->ws_bytes = ws_bytes;
     p->L = L;

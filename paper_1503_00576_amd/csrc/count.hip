@@ -44,8 +44,8 @@ constexpr uint32_t kWaveListPV = kSliceWords / 2;     // per-vertex: list + coun
 constexpr uint32_t kBlockBits = kLdsWords * 32 - 32;  // workgroup bitmap: span < 1048544
 constexpr uint32_t kBlockList = kLdsWords;            // workgroup sorted list
 constexpr uint32_t kBlockListPV = kLdsWords / 2;      // per-vertex: list + counters
-constexpr uint32_t kItemEdgesWave = 512;
-constexpr uint32_t kItemEdgesBlock = 16384;
+constexpr uint32_t kItemEdgesWave = 512;     // default in-edges per wave item
+constexpr uint32_t kItemEdgesBlock = 16384;  // default in-edges per workgroup item
 constexpr uint32_t kPanel = 32;                       // one bit per panel vertex in a mask
 constexpr uint32_t kPanelRanks = kLdsWords - 32;      // mask table: one word per rank
 // batched kernel: rows with at most kLightMax forward entries are counted edge by edge; a
@@ -371,6 +371,7 @@ __global__ __launch_bounds__(kThreads) void k_count(
     const uint32_t *__restrict__ n_items_b_ptr, uint32_t *__restrict__ queue_a,
     uint32_t *__restrict__ queue_b, unsigned long long *__restrict__ total,
     unsigned long long *__restrict__ tpv, uint32_t n1, uint32_t p0, uint32_t wave_bits,
+    uint32_t block_bits, uint32_t block_list, uint32_t kitem_a, uint32_t kitem_b,
     const int32_t *__restrict__ status) {
     __shared__ uint32_t s_mem[kLdsWords];
     __shared__ WaveScratch s_ws[kWaves];
@@ -391,8 +392,7 @@ __global__ __launch_bounds__(kThreads) void k_count(
         uint32_t q = s_item;
         if (q >= n_items_b) break;
         q = n_items_b - 1 - q;
-        const ItemRange it =
-            item_range(q, kItemEdgesBlock, n1, item_v_b, item_off_b, cptr, row_ptr);
+        const ItemRange it = item_range(q, kitem_b, n1, item_v_b, item_off_b, cptr, row_ptr);
         const uint32_t first = it.e0 + w * kWave, step = kWaves * kWave;
         if (it.v >= p0) {  // a panel of middle vertices P = it.v, ...
             const uint32_t P = it.v, np = min(kPanel, n1 - 1 - P);
@@ -415,7 +415,7 @@ __global__ __launch_bounds__(kThreads) void k_count(
                 for (uint32_t j = 0; j < np; ++j) {  // one panel vertex at a time
                     const uint32_t r0 = row_ptr[P + j], d = row_ptr[P + j + 1] - r0;
                     if (d == 0) continue;
-                    const bool in_lds = d <= kBlockListPV;
+                    const bool in_lds = d <= block_list;  // at most kBlockListPV
                     if (in_lds)
                         for (uint32_t i = t; i < d; i += kThreads) s_mem[i] = col[r0 + i];
                     __syncthreads();
@@ -453,9 +453,9 @@ __global__ __launch_bounds__(kThreads) void k_count(
         }
         const uint32_t lo = col[it.r0];
         const uint32_t span = col[it.r0 + it.d - 1] - lo;
-        // 0 = bitmap, 1 = LDS list, 2 = global list
-        const int mode = (!PV && span < kBlockBits) ? 0
-                         : (it.d <= (PV ? kBlockListPV : kBlockList)) ? 1 : 2;
+        // 0 = bitmap, 1 = LDS list, 2 = global list (block_bits <= kBlockBits, block_list <=
+        // kBlockList, or kBlockListPV for per-vertex counts)
+        const int mode = (!PV && span < block_bits) ? 0 : (it.d <= block_list) ? 1 : 2;
         if (mode == 0) {
             for (uint32_t i = t; i < it.d; i += kThreads) {
                 const uint32_t o = col[it.r0 + i] - lo;
@@ -509,8 +509,7 @@ __global__ __launch_bounds__(kThreads) void k_count(
     WaveQueue<kClaimWave> wq;
     for (uint32_t q; wq.pop(queue_a, n_items_a, q);) {
         q = n_items_a - 1 - q;
-        const ItemRange it =
-            item_range(q, kItemEdgesWave, n1, item_v_a, item_off_a, cptr, row_ptr);
+        const ItemRange it = item_range(q, kitem_a, n1, item_v_a, item_off_a, cptr, row_ptr);
         uint32_t cnt = 0;
         if (!PV) {
             const uint32_t lo = col[it.r0];
@@ -562,7 +561,7 @@ __global__ __launch_bounds__(kThreads) void k_count(
 // ------------------------------------------------------------------ batched kernel
 
 // Light segments of the batched kernel.  Segment i of [eb, e1) is edge e = eb + i (u -> v) of
-// the forward CSR, kept when 2 <= d+(u) <= kLightMax: it streams the whole list N+(v) and
+// the forward CSR, kept when 2 <= d+(u) <= light_max: it streams the whole list N+(v) and
 // looks every element up in N+(u), which the caller staged in LDS (`win` holds fcol from
 // position wbase on; binary search, the list is short).  Returns the hits of this lane's own
 // segment (at most d+(u)); per-vertex counts go to global counters: T(w) per hit, T(u) and
@@ -576,7 +575,7 @@ __device__ __forceinline__ uint32_t run_light(uint32_t eb, uint32_t e1,
                                               const uint32_t *win, uint32_t wbase,
                                               WaveScratch &ws,
                                               unsigned long long *__restrict__ tpv,
-                                              uint32_t &graph) {
+                                              uint32_t light_max, uint32_t &graph) {
     const uint32_t lane = lane_id();
     const uint32_t e = eb + lane;
     uint32_t b = 0, en = 0, lo = 0, d = 0, u = 0, v = 0;
@@ -590,7 +589,7 @@ __device__ __forceinline__ uint32_t run_light(uint32_t eb, uint32_t e1,
         graph = gid[u];
         d = r1 - r0;
         lo = r0 - wbase;
-        if (d < 2 || d > kLightMax) d = b = en = lo = 0;
+        if (d < 2 || d > light_max) d = b = en = lo = 0;
     }
     const uint32_t a0 = b & ~3u;
     const uint32_t p = (d && en > b) ? (en - a0 + kLightPiece - 1) / kLightPiece : 0u;
@@ -668,14 +667,14 @@ __device__ __forceinline__ uint32_t run_light(uint32_t eb, uint32_t e1,
 // keep the input's id order, no relabelling).  Every triangle is found once, from its first
 // vertex u in the order of Section 2.2: for every out-neighbour v of u, the common elements of
 // N+(u) and N+(v).
-//   heavy items (u with d+(u) > kLightMax): (u, chunk of up to kitem out-neighbours of u);
+//   heavy items (u with d+(u) > light_max): (u, chunk of up to kitem out-neighbours of u);
 //     N+(u) is staged in the wave's LDS slice (bitmap over its id span, or a sorted list) and
 //     the whole list N+(v) of every out-neighbour v streams through it.  Hits go to the graph
 //     of u; per-vertex counts credit u (per item), v (per segment) and w (LDS counters by
 //     list position).
 //   light items: chunks of `chunk` consecutive forward edges, one edge per lane (run_light);
-//     the lists of the chunk's light rows lie inside the window [e0 - kLightMax, e1 +
-//     kLightMax) of fcol, which is staged in the wave's slice.  Graph ids are non-decreasing
+//     the lists of the chunk's light rows lie inside the window [e0 - light_max, e1 +
+//     light_max) of fcol, which is staged in the wave's slice.  Graph ids are non-decreasing
 //     along the edges, so per-graph totals are summed per run of equal graph ids.
 
 template <bool PV>
@@ -712,8 +711,8 @@ __global__ __launch_bounds__(kThreads) void k_count_u(const BatchKernelArgs a) {
         }
         const uint32_t span = hi - lo;
         // 0 = bitmap in the slice, 1 = sorted list in the slice, 2 = sorted list in memory
-        const int mode = (!PV && span < kWaveBits) ? 0
-                         : (d <= (PV ? kWaveListPV : kSliceWords)) ? 1 : 2;
+        // (a.wave_bits <= kWaveBits; a.wave_list <= kSliceWords, or kWaveListPV per vertex)
+        const int mode = (!PV && span < a.wave_bits) ? 0 : (d <= a.wave_list) ? 1 : 2;
         uint32_t cnt = 0;
         if (mode == 0) {
             for (uint32_t i = lane; i < d; i += kWave) {
@@ -756,16 +755,18 @@ __global__ __launch_bounds__(kThreads) void k_count_u(const BatchKernelArgs a) {
     WaveQueue<kClaimLight> lq;
     for (uint32_t q; lq.pop(a.queue + 1, n_chunks, q);) {
         const uint32_t e0 = q * chunk, e1 = min(e0 + chunk, mf);
-        // the rows of the chunk's first and last edges, clipped to kLightMax entries around
-        // the chunk (a light row that meets the chunk lies inside)
+        // the rows of the chunk's first and last edges, clipped to light_max (<= kLightMax)
+        // entries around the chunk (a light row that meets the chunk lies inside)
+        const uint32_t lm = a.light_max;
         const uint32_t rb = frp[a.fsrc[e0]], re = frp[a.fsrc[e1 - 1] + 1];
-        const uint32_t wbase = max(rb, e0 > kLightMax ? e0 - kLightMax : 0u);
-        const uint32_t wend = min(re, e1 + kLightMax);
+        const uint32_t wbase = max(rb, e0 > lm ? e0 - lm : 0u);
+        const uint32_t wend = min(re, e1 + lm);
         for (uint32_t i = wbase + lane; i < wend; i += kWave) mem[i - wbase] = fcol[i];
         wave_lds_sync();
         for (uint32_t eb = e0; eb < e1; eb += kWave) {
             uint32_t g;
-            uint32_t h = run_light<PV>(eb, e1, frp, fcol, a.fsrc, a.gid, mem, wbase, ws, tpv, g);
+            uint32_t h =
+                run_light<PV>(eb, e1, frp, fcol, a.fsrc, a.gid, mem, wbase, ws, tpv, lm, g);
             // per-graph sums over runs of equal graph ids (non-decreasing along the edges)
             for (int o = 1; o < kWave; o <<= 1) {
                 const uint32_t hv = (uint32_t)__shfl_up((int)h, o, kWave);
@@ -792,8 +793,10 @@ hipError_t launch_count_u(const BatchKernelArgs &a, bool per_vertex, uint32_t gr
 
 // ------------------------------------------------------------------ host side
 
-uint32_t count_wave_span(bool per_vertex) { return per_vertex ? 0u : kWaveBits; }
+uint32_t count_wave_span() { return kWaveBits; }
 uint32_t count_wave_list(bool per_vertex) { return per_vertex ? kWaveListPV : kSliceWords; }
+uint32_t count_block_span() { return kBlockBits; }
+uint32_t count_block_list(bool per_vertex) { return per_vertex ? kBlockListPV : kBlockList; }
 uint32_t count_item_edges_wave() { return kItemEdgesWave; }
 uint32_t count_item_edges_block() { return kItemEdgesBlock; }
 uint32_t count_col_pad_bytes() { return kPiece * 4; }
@@ -809,12 +812,14 @@ hipError_t launch_count(const CountArgs &x, bool per_vertex, hipStream_t s) {
         hipLaunchKernelGGL(k_count<true>, grid, block, 0, s, x.row_ptr, x.col, x.cptr, x.cbeg,
                            x.cend, x.src, x.cmask, x.item_v_a, x.item_off_a, x.n_items_a,
                            x.item_v_b, x.item_off_b, x.n_items_b, x.queue_a, x.queue_b, x.total,
-                           x.tpv, x.n1, x.p0, x.wave_bits, x.status);
+                           x.tpv, x.n1, x.p0, x.wave_bits, x.block_bits, x.block_list,
+                           x.kitem_a, x.kitem_b, x.status);
     else
         hipLaunchKernelGGL(k_count<false>, grid, block, 0, s, x.row_ptr, x.col, x.cptr, x.cbeg,
                            x.cend, x.src, x.cmask, x.item_v_a, x.item_off_a, x.n_items_a,
                            x.item_v_b, x.item_off_b, x.n_items_b, x.queue_a, x.queue_b, x.total,
-                           x.tpv, x.n1, x.p0, x.wave_bits, x.status);
+                           x.tpv, x.n1, x.p0, x.wave_bits, x.block_bits, x.block_list,
+                           x.kitem_a, x.kitem_b, x.status);
     return hipGetLastError();
 }
 

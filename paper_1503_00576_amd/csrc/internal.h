@@ -79,10 +79,12 @@ size_t scan_scratch_words(uint64_t N);
 hipError_t scan_exclusive_u32(const uint32_t *in, uint32_t *out, uint64_t N, uint32_t *scratch,
                               hipStream_t s);
 
-// radix sort: result lands in *result (== keys or tmp); scratch: sort_scratch_bytes(count)
+// radix sort: result lands in *result (== keys or tmp); scratch: sort_scratch_bytes(count);
+// onesweep: single-sweep passes for sorts of at least 2^20 keys (needs a status word)
 size_t sort_scratch_bytes(uint64_t count);
 hipError_t sort_u64(uint64_t *keys, uint64_t *tmp, uint32_t count, int lo_bit, int hi_bit,
-                    void *scratch, int32_t *status, hipStream_t s, uint64_t **result);
+                    void *scratch, int32_t *status, hipStream_t s, uint64_t **result,
+                    bool onesweep = false);
 
 hipError_t fill_u32(uint32_t *p, uint32_t value, uint64_t count, hipStream_t s);
 
@@ -96,15 +98,22 @@ struct CountArgs {
     uint32_t *queue_a, *queue_b;
     unsigned long long *total, *tpv;
     uint32_t n1;
-    uint32_t p0;         // first rank of the panel region (n: no panels)
-    uint32_t wave_bits;  // wave items use a bitmap below this rank span (count_wave_span)
+    uint32_t p0;          // first rank of the panel region (n: no panels)
+    uint32_t wave_bits;   // wave items use a bitmap below this rank span
+    uint32_t block_bits;  // workgroup items use a bitmap below this rank span (totals)
+    uint32_t block_list;  // ... else an LDS list of at most this many entries (<= kBlockList)
+    uint32_t kitem_a;     // in-edges per wave item
+    uint32_t kitem_b;     // in-edges per workgroup item
     const int32_t *status;
 };
 hipError_t launch_count(const CountArgs &a, bool per_vertex, hipStream_t s);
-uint32_t count_wave_span(bool per_vertex);
-uint32_t count_wave_list(bool per_vertex);
-uint32_t count_item_edges_wave();
-uint32_t count_item_edges_block();
+// LDS limits of the counting kernels' per-item structures (the defaults of the options)
+uint32_t count_wave_span();         // wave bitmap: rank span below this
+uint32_t count_wave_list(bool per_vertex);   // wave sorted list: entries
+uint32_t count_block_span();        // workgroup bitmap: rank span below this
+uint32_t count_block_list(bool per_vertex);  // workgroup sorted list: entries
+uint32_t count_item_edges_wave();   // default in-edges per wave item
+uint32_t count_item_edges_block();  // default in-edges per workgroup item
 // bytes of padding `col` needs after its last element: a lane's aligned piece reads may run
 // up to one piece past the end of a list
 uint32_t count_col_pad_bytes();
@@ -128,6 +137,9 @@ struct BatchKernelArgs {
     uint32_t *queue;                              // [0] heavy items, [1] light chunks
     unsigned long long *const *totals_pp;
     unsigned long long *const *tpv_pp;
+    uint32_t light_max;   // rows with at most this many forward entries are light (<= 256)
+    uint32_t wave_bits;   // heavy items use a bitmap below this id span (<= kWaveBits)
+    uint32_t wave_list;   // ... else a sorted LDS list of at most this many entries
 };
 hipError_t launch_count_u(const BatchKernelArgs &a, bool per_vertex, uint32_t grid,
                           hipStream_t s);

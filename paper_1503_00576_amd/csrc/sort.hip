@@ -464,11 +464,6 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_onesweep(
         onesweep_tile<false>(in, out, count, shift, mask, ghist, flags, tile, status, L);
 }
 
-static bool onesweep_enabled() {  // TC_SORT_ONESWEEP=1 switches the variant on
-    const char *env = getenv("TC_SORT_ONESWEEP");
-    return env && env[0] == '1';
-}
-
 size_t sort_scratch_bytes(uint64_t count) {
     uint64_t tiles = (count + kSortTile - 1) / kSortTile;
     if (tiles == 0) tiles = 1;
@@ -477,7 +472,8 @@ size_t sort_scratch_bytes(uint64_t count) {
 }
 
 hipError_t sort_u64(uint64_t *keys, uint64_t *tmp, uint32_t count, int lo_bit, int hi_bit,
-                    void *scratch, int32_t *status, hipStream_t s, uint64_t **result) {
+                    void *scratch, int32_t *status, hipStream_t s, uint64_t **result,
+                    bool onesweep) {
     *result = keys;
     if (count <= 1 || hi_bit <= lo_bit) return hipSuccess;
     uint32_t tiles = ceil_div(count, kSortTile);
@@ -487,7 +483,7 @@ hipError_t sort_u64(uint64_t *keys, uint64_t *tmp, uint32_t count, int lo_bit, i
     uint32_t *scan_scratch = (uint32_t *)((char *)scratch + 2 * align_up(hist_n * 4, 256));
     uint64_t *src = keys, *dst = tmp;
     const int passes = (hi_bit - lo_bit + 7) / 8;
-    if (status && onesweep_enabled() && count >= (1u << 20) && count <= kLbValue &&
+    if (status && onesweep && count >= (1u << 20) && count <= kLbValue &&
         hist_n >= (uint64_t)kMaxPasses * 256 + kMaxPasses) {
         // flags: the first table; digit counts and tile counters: the second
         uint32_t *flags = hist, *ghist = offs, *counters = offs + kMaxPasses * 256;

@@ -342,6 +342,35 @@ def poisson_trace(rate: float, duration: float, seed: int):
     return t[keep], _uniform(seed, _S_TRACE, 2 * idx + 1)[keep]
 
 
+# the serving workload's request mix -----------------------------------------------------
+
+# Graphs are drawn from a seeded pool per R-MAT scale (edgefactor 16) so that generation time
+# stays bounded: scale -> pool size.  90% of requests are scale 10-14, 9% scale 17-19 and
+# 1% scale 21.
+SERVE_POOL = {10: 16, 11: 16, 12: 16, 13: 16, 14: 16, 17: 6, 18: 4, 19: 3, 21: 2}
+SERVE_EDGEFACTOR = 16
+
+
+def serve_pool_seed(scale: int, i: int) -> int:
+    return 1000 * scale + i
+
+
+def serve_pool_graph(scale: int, i: int, device="cpu") -> tuple[torch.Tensor, int]:
+    """Graph i of the serving pool at this scale."""
+    return rmat_graph(scale, SERVE_EDGEFACTOR, seed=serve_pool_seed(scale, i), device=device)
+
+
+def serve_pick(i: int, u: float) -> tuple[int, int]:
+    """(scale, pool index) of request i, given its uniform draw u from poisson_trace."""
+    if u < 0.9:
+        sc = 10 + min(4, int(u / 0.9 * 5))
+    elif u < 0.99:
+        sc = 17 + min(2, int((u - 0.9) / 0.09 * 3))
+    else:
+        sc = 21
+    return sc, i % SERVE_POOL[sc]
+
+
 def edges_sha256(edges: torch.Tensor) -> str:
     return hashlib.sha256(edges.detach().to("cpu").contiguous().numpy().tobytes()).hexdigest()
 

@@ -37,19 +37,19 @@ def test_strerror(lib):
 
 
 def test_workspace_size_arithmetic(lib):
-    s0 = lib.tc_workspace_size(0, 0, 0)
+    s0 = lib.tc_workspace_size(0, 0, 0, None)
     assert s0 > 0
-    s1 = lib.tc_workspace_size(1000, 10000, 0)
-    s2 = lib.tc_workspace_size(1000, 20000, 0)
+    s1 = lib.tc_workspace_size(1000, 10000, 0, None)
+    s2 = lib.tc_workspace_size(1000, 20000, 0, None)
     assert s2 > s1 > s0
     # about 16 B of sort buffers + 16 B of lists per edge, plus per-vertex arrays
     assert 40 * 10000 < s1 < 200 * 10000 + 200 * 1000
-    assert lib.tc_workspace_size(-1, 0, 0) == 0
-    assert lib.tc_workspace_size(10, -1, 0) == 0
-    assert lib.tc_workspace_size(1 << 31, 0, 0) == 0
-    assert lib.tc_workspace_size(10, 1 << 32, 0) == 0
-    assert lib.tc_workspace_size(10, 10, 4) == 0
-    both = lib.tc_workspace_size(1000, 20000, 1)
+    assert lib.tc_workspace_size(-1, 0, 0, None) == 0
+    assert lib.tc_workspace_size(10, -1, 0, None) == 0
+    assert lib.tc_workspace_size(1 << 31, 0, 0, None) == 0
+    assert lib.tc_workspace_size(10, 1 << 32, 0, None) == 0
+    assert lib.tc_workspace_size(10, 10, 4, None) == 0
+    both = lib.tc_workspace_size(1000, 20000, 1, None)
     assert both > 0
 
 
@@ -61,35 +61,35 @@ def test_host_validation_before_launch(lib):
     big = 1 << 40
     out = ctypes.c_void_p(0x2000)
     # negative sizes, bad flags
-    assert lib.tc_count(fake, -1, 3, 0, ws, big, None, out, None) == api.E_ARG
-    assert lib.tc_count(fake, 5, -3, 0, ws, big, None, out, None) == api.E_ARG
-    assert lib.tc_count(fake, 5, 3, 8, ws, big, None, out, None) == api.E_ARG
+    assert lib.tc_count(fake, -1, 3, 0, None, ws, big, None, out, None) == api.E_ARG
+    assert lib.tc_count(fake, 5, -3, 0, None, ws, big, None, out, None) == api.E_ARG
+    assert lib.tc_count(fake, 5, 3, 8, None, ws, big, None, out, None) == api.E_ARG
     # too large
-    assert lib.tc_count(fake, 1 << 31, 3, 0, ws, big, None, out, None) == api.E_TOO_LARGE
-    assert lib.tc_count(fake, 5, 1 << 32, 0, ws, big, None, out, None) == api.E_TOO_LARGE
+    assert lib.tc_count(fake, 1 << 31, 3, 0, None, ws, big, None, out, None) == api.E_TOO_LARGE
+    assert lib.tc_count(fake, 5, 1 << 32, 0, None, ws, big, None, out, None) == api.E_TOO_LARGE
     # n = 0 with edges, null or misaligned edge pointer
-    assert lib.tc_count(fake, 0, 3, 0, ws, big, None, out, None) == api.E_ARG
-    assert lib.tc_count(None, 5, 3, 0, ws, big, None, out, None) == api.E_ARG
-    assert lib.tc_count(ctypes.c_void_p(0x1004), 5, 3, 0, ws, big, None, out, None) == api.E_ARG
+    assert lib.tc_count(fake, 0, 3, 0, None, ws, big, None, out, None) == api.E_ARG
+    assert lib.tc_count(None, 5, 3, 0, None, ws, big, None, out, None) == api.E_ARG
+    assert lib.tc_count(ctypes.c_void_p(0x1004), 5, 3, 0, None, ws, big, None, out, None) == api.E_ARG
     # two-direction format with an odd number of entries
-    assert lib.tc_count(fake, 5, 3, 1, ws, big, None, out, None) == api.E_ASYMMETRIC
+    assert lib.tc_count(fake, 5, 3, 1, None, ws, big, None, out, None) == api.E_ASYMMETRIC
     # workspace: null, misaligned, short
-    need = lib.tc_workspace_size(5, 3, 0)
-    assert lib.tc_count(fake, 5, 3, 0, None, big, None, out, None) == api.E_WORKSPACE
-    assert lib.tc_count(fake, 5, 3, 0, ctypes.c_void_p(0x10010), big, None, out, None) == api.E_WORKSPACE
-    assert lib.tc_count(fake, 5, 3, 0, ws, need - 1, None, out, None) == api.E_WORKSPACE
+    need = lib.tc_workspace_size(5, 3, 0, None)
+    assert lib.tc_count(fake, 5, 3, 0, None, None, big, None, out, None) == api.E_WORKSPACE
+    assert lib.tc_count(fake, 5, 3, 0, None, ctypes.c_void_p(0x10010), big, None, out, None) == api.E_WORKSPACE
+    assert lib.tc_count(fake, 5, 3, 0, None, ws, need - 1, None, out, None) == api.E_WORKSPACE
     # missing outputs
-    assert lib.tc_count(fake, 5, 3, 0, ws, big, None, None, None) == api.E_ARG
-    assert lib.tc_count_per_vertex(fake, 5, 3, 0, ws, big, None, out, None, None) == api.E_ARG
-    assert lib.tc_count_prepared(5, 3, 0, ws, need - 1, None, out, None, None) == api.E_WORKSPACE
-    assert lib.tc_count_prepared(5, 3, 0, ws, big, None, None, None, None) == api.E_ARG
-    assert lib.tc_preprocess(fake, 5, 3, 2, ws, big, None, None) == api.E_ARG
+    assert lib.tc_count(fake, 5, 3, 0, None, ws, big, None, None, None) == api.E_ARG
+    assert lib.tc_count_per_vertex(fake, 5, 3, 0, None, ws, big, None, out, None, None) == api.E_ARG
+    assert lib.tc_count_prepared(5, 3, 0, None, ws, need - 1, None, out, None, None) == api.E_WORKSPACE
+    assert lib.tc_count_prepared(5, 3, 0, None, ws, big, None, None, None, None) == api.E_ARG
+    assert lib.tc_preprocess(fake, 5, 3, 2, None, ws, big, None, None) == api.E_ARG
     # sort
     assert lib.tc_sort_u64(fake, fake, 10, 0, ws, big, None) == api.E_ARG
     assert lib.tc_sort_u64(fake, fake, 10, 65, ws, big, None) == api.E_ARG
     assert lib.tc_sort_u64(fake, fake, 10, 8, ws, 0, None) == api.E_WORKSPACE
     lay = api._native.TcLayout()
-    assert lib.tc_workspace_layout(-1, 0, 0, ctypes.byref(lay)) == api.E_ARG
+    assert lib.tc_workspace_layout(-1, 0, 0, None, ctypes.byref(lay)) == api.E_ARG
 
 
 def test_layout(lib):
@@ -98,7 +98,7 @@ def test_layout(lib):
     assert lay.m_fwd == 9000 and lay.id_bits == 10
     assert len({lay.deg, lay.perm, lay.rank, lay.row_ptr, lay.col}) == 5
     assert all(x % 256 == 0 for x in (lay.deg, lay.perm, lay.rank, lay.row_ptr, lay.col))
-    assert max(lay.deg, lay.perm, lay.rank, lay.row_ptr, lay.col) < lib.tc_workspace_size(1000, 9000, 0)
+    assert max(lay.deg, lay.perm, lay.rank, lay.row_ptr, lay.col) < lib.tc_workspace_size(1000, 9000, 0, None)
     assert api.layout(1000, 9000, both=True).m_fwd == 4500
     assert api.layout(1 << 23, 10).id_bits == 23
     assert api.layout((1 << 23) + 1, 10).id_bits == 24
@@ -115,3 +115,47 @@ def test_clustering_transitivity_helpers():
     assert np.allclose(api.clustering(np.zeros(4), np.array([3, 1, 1, 1])), 0.0)
     assert api.transitivity(0, np.array([3, 1, 1, 1])) == 0.0
     assert api.transitivity(0, np.array([1, 1])) == 0.0
+
+
+def test_options(lib):
+    """struct tc_options: defaults, validation of every field, and the fields that change the
+    workspace layout (host arithmetic only)."""
+    from paper_1503_00576_amd import _native, api
+    d = api.default_options()
+    assert d == {"panel_ranks": 32736, "hub_ranks": 0, "row_blocks": 1, "wave_item_edges": 512,
+                 "block_item_edges": 16384, "wave_bitmap_span": 65504, "wave_list_max": 2048,
+                 "block_bitmap_span": 1048544, "block_list_max": 32768, "degree_partition": 1,
+                 "sort_onesweep": 0}
+    assert lib.tc_options_init(None) == api.E_ARG
+    base = api.workspace_size(1000, 9000)
+    assert api.workspace_size(1000, 9000, options=d) == base
+    fake = ctypes.c_void_p(0x1000)
+    ws, out = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x2000)
+    bad = [("panel_ranks", 32737), ("hub_ranks", 65537), ("row_blocks", 0), ("row_blocks", 9),
+           ("wave_item_edges", 15), ("wave_item_edges", 65537), ("block_item_edges", 15),
+           ("block_item_edges", (1 << 20) + 1), ("wave_bitmap_span", 65505),
+           ("wave_list_max", 2049), ("block_bitmap_span", 1048545), ("block_list_max", 32769),
+           ("degree_partition", 2), ("sort_onesweep", 2)]
+    for k, v in bad:
+        assert lib.tc_workspace_size(1000, 9000, 0, api._opts({k: v})) == 0, k
+        assert lib.tc_count(fake, 5, 3, 0, api._opts({k: v}), ws, 1 << 40, None, out,
+                            None) == api.E_ARG, k
+        assert lib.tc_count_prepared(5, 3, 0, api._opts({k: v}), ws, 1 << 40, None, out, None,
+                                     None) == api.E_ARG, k
+    o = _native.TcOptions()
+    assert lib.tc_options_init(ctypes.byref(o)) == api.OK
+    o.size = 4
+    assert lib.tc_workspace_size(1000, 9000, 0, ctypes.byref(o)) == 0
+    # every extreme that is valid is accepted
+    for k, v in [("panel_ranks", 0), ("hub_ranks", 65536), ("row_blocks", 8),
+                 ("wave_item_edges", 16), ("block_item_edges", 1 << 20),
+                 ("wave_bitmap_span", 0), ("wave_list_max", 0), ("block_bitmap_span", 0),
+                 ("block_list_max", 0), ("degree_partition", 0), ("sort_onesweep", 1)]:
+        assert api.workspace_size(1000, 9000, options={k: v}) > 0, k
+    # the layout grows with hubs (two byte matrices), row blocks (lists per block) and smaller
+    # items (more item slots)
+    assert api.workspace_size(1000, 9000, options={"hub_ranks": 128}) >= base + 2 * 128 * 128 - 512
+    assert api.workspace_size(1000, 9000, options={"row_blocks": 4}) > base
+    assert api.workspace_size(1000, 9000, options={"wave_item_edges": 16}) > base
+    with pytest.raises(KeyError):
+        api._opts({"bogus": 1})

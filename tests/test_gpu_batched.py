@@ -198,3 +198,28 @@ def test_batch_spec_sample():
     want = oracle_per_graph(gs)
     b = as_batch(synth.pack_symmetric(gs, device=DEV))
     check(api.count_batched(b, per_vertex=True), gs, want)
+
+
+# every form of the batched counting kernel, forced on small graphs through the plan tuning:
+# all rows heavy (bitmap, sorted LDS list, sorted list in global memory), a low light/heavy
+# threshold with mixed forms, and heavy items of 16 out-neighbours
+FORCED = {
+    "heavy_bitmap": {"light_max": 0},
+    "heavy_lds_list": {"light_max": 0, "bitmap_span": 0},
+    "heavy_global_list": {"light_max": 0, "bitmap_span": 0, "list_max": 0},
+    "mixed": {"light_max": 8, "bitmap_span": 50, "list_max": 20},
+    "small_items": {"light_max": 4, "items_k": 16, "bitmap_span": 200, "list_max": 12},
+}
+
+
+@pytest.mark.parametrize("name", sorted(FORCED))
+def test_batched_forced_forms(name):
+    gs = mixed_graphs(6, 24)
+    want = oracle_per_graph(gs)
+    b = as_batch(synth.pack_symmetric(gs))
+    plan = api.BatchPlan(b.G, b.n_total, b.adj_total, FORCED[name], device=DEV)
+    for pv in (True, False):
+        res = plan.run_async(b, per_vertex=pv)
+        torch.cuda.synchronize()
+        check(res, gs, want, per_vertex=pv)
+    plan.close()

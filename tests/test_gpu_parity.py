@@ -25,22 +25,29 @@ def golden():
         return json.load(f)
 
 
-def gpu_counts(edges_np, n, both=False, per_vertex=True):
+def gpu_counts(edges_np, n, both=False, per_vertex=True, options=None):
     e = torch.as_tensor(np.ascontiguousarray(np.asarray(edges_np, dtype=np.int32).reshape(-1, 2)),
                         device=DEV)
     if per_vertex:
-        tot, pv = api.count_per_vertex(e, n, both)
+        tot, pv = api.count_per_vertex(e, n, both, options=options)
         return tot, pv.cpu().numpy().astype(np.uint64)
-    return api.count(e, n, both), None
+    return api.count(e, n, both, options=options), None
 
 
-def check_vs_oracle(edges_np, n, both=False):
+def check_vs_oracle(edges_np, n, both=False, options=None, prepared_pv=False):
+    """Totals and per-vertex counts of the one-shot calls (and, with prepared_pv, per-vertex
+    counts of tc_preprocess + tc_count_prepared, which keep the panels) against the oracle."""
     e = np.asarray(edges_np, dtype=np.int32).reshape(-1, 2)
     ot, opv = oracle.count(e, n, both=both, per_vertex=True)
-    gt, gpv = gpu_counts(e, n, both)
+    gt, gpv = gpu_counts(e, n, both, options=options)
     assert gt == ot
     assert np.array_equal(gpv, opv)
-    assert api.count(torch.as_tensor(e, device=DEV), n, both) == ot
+    assert api.count(torch.as_tensor(e, device=DEV), n, both, options=options) == ot
+    if prepared_pv:
+        p = api.Prepared(torch.as_tensor(e, device=DEV), n, both, options=options)
+        r = p.count_async(per_vertex=True).check()
+        assert int(r.total.item()) == ot
+        assert np.array_equal(r.per_vertex.cpu().numpy().astype(np.uint64), opv)
     return ot
 
 
@@ -125,89 +132,139 @@ def test_repeat_runs_identical():
         assert t == outs[0][0] and np.array_equal(pv, outs[0][1])
 
 
-def test_row_blocks_forced(monkeypatch):
-    """In-edge lists split into 8 row blocks (the layout used for the largest graphs)."""
-    monkeypatch.setenv("TC_ROW_BLOCK_BYTES", "65536")
-    for e, n in [synth.rmat_graph(16, 16, seed=2, device=DEV), synth.er_1000(device=DEV)]:
-        check_vs_oracle(e.cpu().numpy(), n)
-    monkeypatch.setenv("TC_ROW_BLOCK_BYTES", "4096")
-    e, n = synth.rmat_graph(12, 16, seed=3, device=DEV)
-    check_vs_oracle(e.cpu().numpy(), n)
+@pytest.mark.parametrize("blocks", [3, 8])
+def test_row_blocks_forced(blocks):
+    """In-edge lists split into row blocks (counted one block after another)."""
+    opt = {"row_blocks": blocks}
+    for e, n in [synth.rmat_graph(16, 16, seed=2, device=DEV), synth.er_1000(device=DEV),
+                 synth.rmat_graph(12, 16, seed=3, device=DEV)]:
+        check_vs_oracle(e.cpu().numpy(), n, options=opt, prepared_pv=True)
 
 
 @pytest.mark.parametrize("both", [False, True])
-def test_degree_atomic_path(monkeypatch, both):
+def test_degree_atomic_path(both):
     """Degrees by one atomic per endpoint and orientation in input order (the path of graphs
     beyond the bucket partition's limits), both input formats, with an invalid input."""
-    monkeypatch.setenv("TC_DEGREE_PARTITION", "0")
+    opt = {"degree_partition": 0}
     for e, n in [synth.er_1000(), synth.rmat_graph(14, 16, seed=5),
                  (synth.barabasi_albert(3000, 12, 2), 3000)]:
         e = e.numpy()
         if both:
             e = np.concatenate([e, e[:, ::-1]])
-        check_vs_oracle(e, n, both=both)
+        check_vs_oracle(e, n, both=both, options=opt)
     for k in [3, 40, 130]:
-        assert check_vs_oracle(complete(k), k) == math.comb(k, 3)
+        assert check_vs_oracle(complete(k), k, options=opt) == math.comb(k, 3)
     for edges, name in [([(0, 1), (1, 2), (2, 2)], "self_loop"), ([(0, 1), (1, 5)], "range"),
                         ([(0, 1), (1, 2), (1, 0)], "dup_edge")]:
         with pytest.raises(api.TCError) as ei:
-            api.count(torch.tensor(edges, dtype=torch.int32, device=DEV), 5)
+            api.count(torch.tensor(edges, dtype=torch.int32, device=DEV), 5, options=opt)
         assert ei.value.name == name
 
 
-@pytest.mark.parametrize("ranks", ["0", "1", "31", "33", "517", "4000"])
-def test_panel_thresholds(monkeypatch, ranks):
+@pytest.mark.parametrize("ranks", [0, 1, 31, 33, 517, 4000])
+def test_panel_thresholds(ranks):
     """The top-ranks panel region of every size: off (per-vertex lists only), one partial
-    panel, one panel plus a ragged one, and many panels over graphs of every family."""
-    monkeypatch.setenv("TC_PANEL_RANKS", ranks)
+    panel, one panel plus a ragged one, and many panels over graphs of every family; per-vertex
+    counts on a prepared graph go through the panels one panel vertex at a time (the one-shot
+    call prepares without panels)."""
+    opt = {"panel_ranks": ranks}
     for e, n in [synth.er_1000(), (synth.barabasi_albert(2000, 8, 2), 2000),
                  (synth.watts_strogatz(1500, 6, 0.1, 3), 1500), synth.rmat_graph(11, 8, seed=4),
                  synth.rmat_graph(14, 16, seed=6)]:
-        check_vs_oracle(e.numpy(), n)
-        # per-vertex counts on a prepared graph go through the panels one panel vertex at a
-        # time (the one-shot call prepares without panels)
-        _, opv = oracle.count(e.numpy(), n, per_vertex=True)
-        r = api.Prepared(e.to(DEV), n).count_async(per_vertex=True).check()
-        assert np.array_equal(r.per_vertex.cpu().numpy().astype(np.uint64), opv)
+        check_vs_oracle(e.numpy(), n, options=opt, prepared_pv=True)
     for k in [3, 40, 130]:
-        assert check_vs_oracle(complete(k), k) == math.comb(k, 3)
+        assert check_vs_oracle(complete(k), k, options=opt, prepared_pv=True) == math.comb(k, 3)
 
 
-def test_single_sweep_sort(monkeypatch):
+def test_single_sweep_sort():
     """The single-sweep radix variant (look-back instead of a histogram pass) in the edge and
     in-edge sorts of graphs above its 2^20-key threshold, with ragged last tiles."""
-    monkeypatch.setenv("TC_SORT_ONESWEEP", "1")
+    opt = {"sort_onesweep": 1}
     for e, n in [synth.rmat_graph(17, 16, seed=21), synth.rmat_graph(18, 6, seed=22)]:
         assert e.shape[0] >= (1 << 20) and e.shape[0] % 4096
-        check_vs_oracle(e.numpy(), n)
+        check_vs_oracle(e.numpy(), n, options=opt)
 
 
-@pytest.mark.parametrize("span", ["0", "40", "600"])
-def test_wave_item_forms(monkeypatch, span):
+@pytest.mark.parametrize("span", [0, 40, 600])
+def test_wave_item_forms(span):
     """Wave items in both forms (bitmap below the span limit, sorted list above it) and
     workgroup items, reached on small graphs by lowering the limit, with panels off so that
     every list is a wave or workgroup item."""
-    monkeypatch.setenv("TC_PANEL_RANKS", "0")
-    monkeypatch.setenv("TC_WAVE_BITMAP_SPAN", span)
+    opt = {"panel_ranks": 0, "wave_bitmap_span": span}
     for e, n in [synth.er_1000(), (synth.barabasi_albert(3000, 12, 2), 3000),
                  synth.rmat_graph(12, 16, seed=8), (synth.erdos_renyi(1500, 0.9, 3), 1500)]:
-        check_vs_oracle(e.numpy(), n)
+        check_vs_oracle(e.numpy(), n, options=opt)
     for k in [3, 40, 130]:
-        assert check_vs_oracle(complete(k), k) == math.comb(k, 3)
+        assert check_vs_oracle(complete(k), k, options=opt) == math.comb(k, 3)
 
 
-@pytest.mark.parametrize("hubs", ["0", "1", "63", "64", "100", "1000", "5000"])
-def test_hub_matrix_path(monkeypatch, hubs):
+# every form of every item, forced on small graphs through the options: wave items (bitmap,
+# sorted LDS list), workgroup items (bitmap, sorted LDS list, sorted list in global memory),
+# for totals, per-vertex counts and the per-vertex panel path, with items of 16 in-edges so
+# that lists span many items
+FORCED = {
+    "wave_list": {"panel_ranks": 0, "wave_bitmap_span": 0, "wave_list_max": 40},
+    "block_bitmap": {"panel_ranks": 0, "wave_bitmap_span": 0, "wave_list_max": 0},
+    "block_lds_list": {"panel_ranks": 0, "wave_bitmap_span": 0, "wave_list_max": 0,
+                       "block_bitmap_span": 0},
+    "block_global_list": {"panel_ranks": 0, "wave_bitmap_span": 0, "wave_list_max": 0,
+                          "block_bitmap_span": 0, "block_list_max": 0},
+    "block_mixed": {"panel_ranks": 0, "wave_bitmap_span": 0, "wave_list_max": 10,
+                    "block_bitmap_span": 100, "block_list_max": 30},
+    "panels_global_pv": {"panel_ranks": 600, "block_list_max": 0},
+    "small_items": {"panel_ranks": 300, "wave_item_edges": 16, "block_item_edges": 16,
+                    "wave_list_max": 20, "block_list_max": 25},
+}
+
+
+@pytest.mark.parametrize("name", sorted(FORCED))
+def test_forced_item_forms(name):
+    opt = FORCED[name]
+    for e, n in [synth.er_1000(), (synth.barabasi_albert(3000, 12, 2), 3000),
+                 synth.rmat_graph(12, 16, seed=8), (synth.erdos_renyi(700, 0.9, 3), 700),
+                 (synth.watts_strogatz(2500, 8, 0.1, 4), 2500)]:
+        check_vs_oracle(e.numpy(), n, options=opt, prepared_pv=True)
+    for k in [3, 40, 130]:
+        assert check_vs_oracle(complete(k), k, options=opt, prepared_pv=True) == math.comb(k, 3)
+
+
+def test_prepared_options_mismatch():
+    """tc_count_prepared with options (or sizes) other than the preprocessing's reports a
+    mismatch on the device; the workspace stays usable with the right ones."""
+    e, n = synth.rmat_graph(12, 16, seed=3, device=DEV)
+    want = oracle.count(e.cpu().numpy(), n)
+    # room for every layout below, so that only the device-side check can object
+    ws = torch.empty(2 * api.workspace_size(n, e.shape[0]) + (1 << 20), dtype=torch.uint8,
+                     device=DEV)
+    p = api.Prepared(e, n, workspace=ws, options={"panel_ranks": 64})
+    assert p.count() == want
+    other = api.Prepared.__new__(api.Prepared)
+    other.__dict__.update(p.__dict__)
+    for opts in [None, {"panel_ranks": 32}, {"panel_ranks": 64, "wave_item_edges": 256}]:
+        other.options = opts
+        with pytest.raises(api.TCError) as ei:
+            other.count()
+        assert ei.value.name == "mismatch"
+    other.options = {"panel_ranks": 64}
+    other.m = p.m - 1
+    with pytest.raises(api.TCError) as ei:
+        other.count()
+    assert ei.value.name == "mismatch"
+    assert p.count() == want
+
+
+@pytest.mark.parametrize("hubs", [0, 1, 63, 64, 100, 1000, 5000])
+def test_hub_matrix_path(hubs):
     """Triangles among the top ranks counted as a masked int8 product on the matrix cores,
     the rest by the middle-vertex kernel, totals and per-vertex counts: no hubs, one hub, hub
     counts that are and are not multiples of the 64-wide tiles, and graphs that are all hubs."""
-    monkeypatch.setenv("TC_HUB_RANKS", hubs)
+    opt = {"hub_ranks": hubs}
     for e, n in [synth.er_1000(), (synth.barabasi_albert(3000, 12, 2), 3000),
                  synth.rmat_graph(13, 16, seed=8), (synth.erdos_renyi(700, 0.5, 3), 700),
                  (synth.watts_strogatz(2500, 8, 0.1, 4), 2500)]:
-        check_vs_oracle(e.numpy(), n)
+        check_vs_oracle(e.numpy(), n, options=opt)
     for k in [3, 40, 130]:
-        assert check_vs_oracle(complete(k), k) == math.comb(k, 3)
+        assert check_vs_oracle(complete(k), k, options=opt) == math.comb(k, 3)
 
 
 def test_prepared_recount():
