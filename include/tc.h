@@ -247,6 +247,28 @@ int tc_count_batched(int32_t G, const int64_t *d_vtx_off, const int64_t *d_adj_o
                      int64_t adj_total, void *d_ws, size_t ws_bytes, void *stream,
                      uint64_t *d_totals, uint64_t *d_per_vertex, int32_t *d_status);
 
+/* Packs G small graphs given as edge arrays (Section 3.1's input, every undirected edge once,
+ * either orientation, local ids) into the batched input format above, on the device: one
+ * radix sort of two keys per edge (row id in the union, neighbour's local id) orders every
+ * row of every graph, and the row boundaries give the offsets.  Serving uses it to turn the
+ * edge arrays of the small requests it batches into one tc_count_batched input.
+ *   d_vtx_off : int64[G+1], vertex offsets as in tc_count_batched (graph g has n_g vertices)
+ *   d_edge_off: int64[G+1], graph g's edges are entries d_edge_off[g] .. d_edge_off[g+1]-1
+ *   d_edges   : int32[2*m_total], (u, v) pairs of local ids in [0, n_g)
+ * Outputs (overwritten): d_adj_off int64[G+1], d_row_ptr int32[n_total+G], d_col
+ * int32[2*m_total] (the first d_adj_off[G] entries used), d_status int32[G]: per graph
+ * TC_E_RANGE (an id outside [0, n_g)) or TC_E_SELF_LOOP, in which case only that graph's
+ * valid entries are packed, or TC_E_ARG for every graph when the offsets are not prefix sums
+ * from 0 to n_total and m_total.  Duplicate edges are packed as they are (tc_count_batched
+ * reports them).  Limits: 2*m_total < 2^31 and n_total + G < 2^31 (TC_E_TOO_LARGE).  The
+ * workspace holds the sort: tc_batched_pack_workspace_size(G, n_total, m_total) bytes,
+ * 256-byte aligned.  Nothing is allocated; the call only enqueues work on `stream`. */
+size_t tc_batched_pack_workspace_size(int32_t G, int64_t n_total, int64_t m_total);
+int tc_batched_pack(int32_t G, const int64_t *d_vtx_off, const int64_t *d_edge_off,
+                    const int32_t *d_edges, int64_t n_total, int64_t m_total, void *d_ws,
+                    size_t ws_bytes, void *stream, int64_t *d_adj_off, int32_t *d_row_ptr,
+                    int32_t *d_col, int32_t *d_status);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,7 +12,8 @@ EXPORTS = [
     "tc_strerror", "tc_options_init", "tc_workspace_size", "tc_count", "tc_count_per_vertex",
     "tc_workspace_layout", "tc_preprocess", "tc_count_prepared", "tc_sort_workspace_size",
     "tc_sort_u64", "tc_batched_workspace_size", "tc_batched_plan_create", "tc_batched_plan_run",
-    "tc_batched_plan_destroy", "tc_count_batched",
+    "tc_batched_plan_destroy", "tc_count_batched", "tc_batched_pack_workspace_size",
+    "tc_batched_pack",
 ]
 
 
@@ -76,5 +77,9 @@ def lib():
     L.tc_batched_plan_destroy.restype = None
     L.tc_count_batched.argtypes = [i32, vp, vp, vp, vp, i64, i64, vp, sz, vp, vp, vp, vp]
     L.tc_count_batched.restype = ctypes.c_int
+    L.tc_batched_pack_workspace_size.argtypes = [i32, i64, i64]
+    L.tc_batched_pack_workspace_size.restype = sz
+    L.tc_batched_pack.argtypes = [i32, vp, vp, vp, i64, i64, vp, sz, vp, vp, vp, vp, vp]
+    L.tc_batched_pack.restype = ctypes.c_int
     _lib = L
     return L

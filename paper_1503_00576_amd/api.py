@@ -348,3 +348,39 @@ def count_batched_async(b: Batch, per_vertex: bool = False,
 def count_batched(b: Batch, per_vertex: bool = False) -> BatchResult:
     """One-shot batched count (no graph capture); returns checked results."""
     return count_batched_async(b, per_vertex).check()
+
+
+@dataclass
+class Packed:
+    """Result of tc_batched_pack: the batched input plus the pack's per-graph status."""
+    batch: Batch
+    status: torch.Tensor        # int32 [G]: range / self-loop / offset errors found by the pack
+    workspace: torch.Tensor     # the sort's workspace (kept until the work has run)
+
+
+def pack_edges_async(edges: torch.Tensor, vtx_off: torch.Tensor, edge_off: torch.Tensor,
+                     n_total: int) -> Packed:
+    """Enqueue tc_batched_pack on the current stream: G graphs' edge arrays, concatenated
+    (int32 [m_total, 2] of local ids, graph g's at rows edge_off[g] .. edge_off[g+1]), with
+    int64 [G+1] vertex and edge offsets, all on the device -> the batched input format."""
+    edges = _check_edges(edges)
+    dev = edges.device
+    G = int(vtx_off.numel()) - 1
+    M = int(edges.shape[0])
+    for t in (vtx_off, edge_off):
+        if t.device != dev or t.dtype != torch.int64 or t.numel() != G + 1 or \
+                not t.is_contiguous():
+            raise TypeError("offsets must be contiguous int64 [G+1] tensors on the edges' device")
+    L = _native.lib()
+    wsz = L.tc_batched_pack_workspace_size(G, int(n_total), M)
+    if wsz == 0:
+        raise TCError(E_TOO_LARGE if G > 0 else E_ARG, "tc_batched_pack_workspace_size")
+    ws = torch.empty(wsz, dtype=torch.uint8, device=dev)
+    adj_off = torch.empty(G + 1, dtype=torch.int64, device=dev)
+    row_ptr = torch.empty(int(n_total) + G, dtype=torch.int32, device=dev)
+    col = torch.empty(max(2 * M, 1), dtype=torch.int32, device=dev)
+    status = torch.empty(G, dtype=torch.int32, device=dev)
+    _raise(L.tc_batched_pack(G, _ptr(vtx_off), _ptr(edge_off), _ptr(edges), int(n_total), M,
+                             _ptr(ws), ws.numel(), _stream(dev), _ptr(adj_off), _ptr(row_ptr),
+                             _ptr(col), _ptr(status)), "tc_batched_pack")
+    return Packed(Batch(vtx_off, adj_off, row_ptr, col, G, int(n_total), 2 * M), status, ws)

@@ -2,14 +2,21 @@
 
 Continuous batching: a scheduler thread admits waiting requests whenever their HBM footprint
 (edge array + workspace + outputs) fits the free part of the memory budget and an execution
-slot is free.  Small graphs admitted together are packed into one batched launch
-(tc_count_batched); larger graphs run tc_count on their own stream, so several requests'
-kernels overlap on the device.  A finished request's memory returns to the budget, except the
-prepared CSR of a graph that carries a key, which stays resident (least recently used first
-out) so that the next request for the same key only runs the counting kernel.
+slot is free.  Small graphs admitted together are packed into one batched input on the device
+(tc_batched_pack) and counted by one batched launch (tc_count_batched); larger graphs run
+tc_preprocess + tc_count_prepared on their own stream, so several requests' kernels overlap
+on the device.  A finished request's memory returns to the budget, except the prepared CSR of
+a graph that carries a key, which stays resident (least recently used first out) so that the
+next request for the same key only runs the counting kernel.
+
+A key names one graph: a request whose key is resident but whose graph differs (vertex count,
+edge count or a sample of its edges) is counted from scratch and replaces the resident entry.
+Counts on one resident workspace are enqueued on the stream that prepared it, so they run one
+after another on the device (they share the workspace's work-queue counters).
 
 Every result is exact and independent of what else is in flight (each request has its own
-outputs and workspace), so a result alone and in the mix are equal."""
+outputs), so a result alone and in the mix are equal.  This module only moves data and
+marshals calls: every step of the counting runs in libtc's HIP kernels."""
 from __future__ import annotations
 
 import collections
@@ -20,9 +27,20 @@ from dataclasses import dataclass, field
 
 import torch
 
-from . import api, synth
+from . import api
 
 _EDGE_BYTES = 8
+_SIG_SAMPLES = 64
+
+
+def graph_signature(edges: torch.Tensor, n: int) -> tuple:
+    """(n, m, a sample of edges at evenly spaced rows): what a resident-key hit must match."""
+    m = int(edges.shape[0])
+    if m == 0:
+        return (int(n), 0, ())
+    idx = torch.linspace(0, m - 1, min(m, _SIG_SAMPLES)).round().to(torch.int64)
+    sample = edges[idx.to(edges.device)].to("cpu").flatten().tolist()
+    return (int(n), m, tuple(sample))
 
 
 @dataclass
@@ -31,6 +49,7 @@ class Request:
     n: int
     key: object = None           # graphs with a key keep their prepared CSR resident
     arrival: float = field(default_factory=time.perf_counter)
+    signature: tuple = None      # filled in by Server.submit for keyed requests
 
 
 @dataclass(eq=False)  # flights compare by identity (they hold tensors)
@@ -38,13 +57,21 @@ class _Flight:
     reqs: list
     futures: list
     event: torch.cuda.Event
-    result: object               # api.Result or api.BatchResult
+    result: object               # api.Result, or (api.BatchResult, pack status)
     nbytes: int
     stream: torch.cuda.Stream
     keep: list                   # tensors that must live until the event
     kind: str
-    resident: object = None      # (key, Prepared) to cache after completion
+    resident: object = None      # _Resident to cache after completion
     busy_key: object = None      # resident key this flight uses
+
+
+@dataclass(eq=False)
+class _Resident:
+    prep: api.Prepared
+    nbytes: int
+    stream: torch.cuda.Stream    # every count on this workspace is enqueued here
+    signature: tuple
 
 
 class Server:
@@ -61,7 +88,7 @@ class Server:
         self._next_stream = 0
         self._pending: collections.deque = collections.deque()
         self._inflight: list[_Flight] = []
-        self._resident: collections.OrderedDict = collections.OrderedDict()  # key -> (Prepared, bytes)
+        self._resident: collections.OrderedDict = collections.OrderedDict()  # key -> _Resident
         self._busy: collections.Counter = collections.Counter()  # resident keys in flight
         self._used = 0
         self._resident_used = 0
@@ -76,6 +103,8 @@ class Server:
 
     def submit(self, req: Request) -> Future:
         fut: Future = Future()
+        if req.key is not None and req.signature is None:
+            req.signature = graph_signature(req.edges, req.n)
         with self._cv:
             if self._failed is not None:
                 fut.set_exception(RuntimeError(f"tc-serve scheduler failed: {self._failed!r}"))
@@ -98,13 +127,20 @@ class Server:
 
     # ------------------------------------------------------------------ footprint
 
+    def _hit(self, req: Request) -> bool:
+        if req.key is None:
+            return False
+        r = self._resident.get(req.key)
+        return r is not None and r.signature == req.signature
+
     def footprint(self, req: Request) -> int:
         m = int(req.edges.shape[0])
-        if req.key is not None and req.key in self._resident:
+        if self._hit(req):
             return 64
         if m <= self.small_edges:
-            # packed symmetric CSR (row_ptr + 2m col) + batched workspace share
-            return 16 * m + 12 * req.n + 4096
+            # edge array, packed symmetric CSR (row_ptr + 2m col), the pack's sort keys and
+            # the batched workspace's share
+            return 48 * m + 24 * req.n + 4096
         return _EDGE_BYTES * m + api.workspace_size(req.n, m) + 64
 
     # ------------------------------------------------------------------ scheduler
@@ -114,17 +150,19 @@ class Server:
         self._next_stream += 1
         return s
 
+    def _drop_resident(self, key):
+        r = self._resident.pop(key)
+        self._used -= r.nbytes
+        self._resident_used -= r.nbytes
+        self.stats["evicted"] += 1
+
     def _evict_resident(self, need: int):
         for key in list(self._resident):
             if self._used + need <= self.budget:
                 break
             if self._busy[key]:
-                continue  # in use by a request in flight
-            prep, nb = self._resident.pop(key)
-            self._used -= nb
-            self._resident_used -= nb
-            self.stats["evicted"] += 1
-            del prep
+                continue  # a request in flight (or admitted in this round) uses it
+            self._drop_resident(key)
 
     def _loop(self):
         try:
@@ -166,18 +204,22 @@ class Server:
                         break  # wait for memory to free up
                     self._pending.popleft()
                     self._used += need
-                    hit = req.key is not None and req.key in self._resident
-                    if not hit and int(req.edges.shape[0]) <= self.small_edges:
+                    hit = self._hit(req)
+                    if hit:
+                        # held from admission on, so that no later admission evicts it
+                        self._busy[req.key] += 1
+                        admitted_large.append((req, fut, need, True))
+                    elif int(req.edges.shape[0]) <= self.small_edges:
                         admitted_small.append((req, fut, need))
                         if len(admitted_small) >= self.batch_graphs:
                             break
                     else:
-                        admitted_large.append((req, fut, need))
+                        admitted_large.append((req, fut, need, False))
                 if not admitted_small and not admitted_large:
                     self._cv.wait(timeout=0.0002)
                     continue
-            for req, fut, need in admitted_large:
-                self._launch_single(req, fut, need)
+            for req, fut, need, hit in admitted_large:
+                self._launch_single(req, fut, need, hit)
             if admitted_small:
                 self._launch_batch(admitted_small)
 
@@ -192,13 +234,16 @@ class Server:
         now = time.perf_counter()
         try:
             if f.kind == "batch":
-                st = f.result.status.cpu()
-                tot = f.result.totals.cpu()
+                res, pack_status = f.result
+                pst = pack_status.cpu().tolist()
+                st = res.status.cpu().tolist()
+                tot = res.totals.cpu().tolist()
                 for i, (req, fut) in enumerate(zip(f.reqs, f.futures)):
-                    if int(st[i]):
-                        fut.set_exception(api.TCError(int(st[i]), "request"))
+                    code = pst[i] or st[i]  # the pack's finding first
+                    if code:
+                        fut.set_exception(api.TCError(code, "request"))
                     else:
-                        fut.set_result((int(tot[i]) & 0xFFFFFFFFFFFFFFFF, now - req.arrival))
+                        fut.set_result((tot[i] & 0xFFFFFFFFFFFFFFFF, now - req.arrival))
             else:
                 st = int(f.result.status.item())
                 req, fut = f.reqs[0], f.futures[0]
@@ -212,46 +257,55 @@ class Server:
                 if not fut.done():
                     fut.set_exception(exc)
         self.stats["completed"] += len(f.reqs)
-        if f.busy_key is not None:
-            self._busy[f.busy_key] -= 1
-        released = f.nbytes
-        if f.resident is not None:
-            key, prep = f.resident
-            nb = int(prep.workspace.numel())
-            if nb <= self.resident_budget - self._resident_used and key not in self._resident:
-                self._resident[key] = (prep, nb)
-                self._resident_used += nb
-                released -= min(released, nb)
         with self._cv:
+            if f.busy_key is not None:
+                self._busy[f.busy_key] -= 1
+            released = f.nbytes
+            if f.resident is not None and int(f.result.status.item()) == 0:
+                key, r = f.resident
+                old = self._resident.get(key)
+                if old is not None and old.signature != r.signature and not self._busy[key]:
+                    self._drop_resident(key)  # the key now names another graph
+                    old = None
+                if old is None and r.nbytes <= self.resident_budget - self._resident_used:
+                    self._resident[key] = r
+                    self._resident_used += r.nbytes
+                    released -= min(released, r.nbytes)
             self._used -= released
             self._cv.notify()
 
-    def _launch_single(self, req: Request, fut: Future, need: int):
-        s = self._stream()
+    def _launch_single(self, req: Request, fut: Future, need: int, hit: bool):
         keep = []
-        with torch.cuda.stream(s):
-            res = api.Result(torch.empty(1, dtype=torch.int64, device=self.device),
-                             torch.empty(1, dtype=torch.int32, device=self.device))
-            resident, busy = None, None
-            if req.key is not None and req.key in self._resident:
-                prep, _ = self._resident[req.key]
-                self._resident.move_to_end(req.key)
-                self._busy[req.key] += 1
-                busy = req.key
-                prep.count_async(out=res)
-                self.stats["resident_hits"] += 1
-                kind = "resident"
-            else:
+        resident, busy = None, None
+        if hit:
+            r = self._resident[req.key]
+            self._resident.move_to_end(req.key)
+            s = r.stream  # after every earlier count on this workspace
+            busy = req.key
+            with torch.cuda.stream(s):
+                res = api.Result(torch.empty(1, dtype=torch.int64, device=self.device),
+                                 torch.empty(1, dtype=torch.int32, device=self.device))
+                r.prep.count_async(out=res)
+                ev = torch.cuda.Event()
+                ev.record(s)
+            kind = "resident"
+            self.stats["resident_hits"] += 1
+        else:
+            s = self._stream()
+            with torch.cuda.stream(s):
+                res = api.Result(torch.empty(1, dtype=torch.int64, device=self.device),
+                                 torch.empty(1, dtype=torch.int32, device=self.device))
                 e = req.edges.to(self.device, non_blocking=True)
                 keep.append(e)
                 prep = api.Prepared(e, req.n)
                 prep.count_async(out=res)
                 if req.key is not None:
-                    resident = (req.key, prep)
+                    resident = (req.key, _Resident(prep, int(prep.workspace.numel()), s,
+                                                   req.signature))
                 keep.append(prep.workspace)
-                kind = "single"
-            ev = torch.cuda.Event()
-            ev.record(s)
+                ev = torch.cuda.Event()
+                ev.record(s)
+            kind = "single"
         self._inflight.append(_Flight([req], [fut], ev, res, need, s, keep, kind, resident, busy))
         self.stats[kind] += 1
 
@@ -259,17 +313,33 @@ class Server:
         s = self._stream()
         reqs = [r for r, _, _ in items]
         futs = [f for _, f, _ in items]
+        ns = [int(r.n) for r in reqs]
+        ms = [int(r.edges.shape[0]) for r in reqs]
+        vo, eo = [0], [0]
+        for n, m in zip(ns, ms):
+            vo.append(vo[-1] + n)
+            eo.append(eo[-1] + m)
+        G, N, M = len(reqs), vo[-1], eo[-1]
+        keep = []
         with torch.cuda.stream(s):
-            graphs = [(r.edges.to(self.device, non_blocking=True), r.n) for r in reqs]
-            packed = synth.pack_symmetric(graphs, device=self.device)
-            b = api.Batch(packed["vtx_off"], packed["adj_off"], packed["row_ptr"],
-                          packed["col"], packed["G"], packed["n_total"], packed["adj_total"])
-            res = api.count_batched_async(b)
+            # one upload of the offsets and one of the concatenated edge arrays
+            offs_h = torch.tensor(vo + eo, dtype=torch.int64).pin_memory()
+            if all(not r.edges.is_cuda for r in reqs):
+                edges_h = torch.empty((M, 2), dtype=torch.int32, pin_memory=True)
+                if M:
+                    torch.cat([r.edges for r in reqs], out=edges_h)
+                edges = edges_h.to(self.device, non_blocking=True)
+                keep.append(edges_h)
+            else:
+                edges = torch.cat([r.edges.to(self.device, non_blocking=True) for r in reqs])
+            offs = offs_h.to(self.device, non_blocking=True)
+            packed = api.pack_edges_async(edges, offs[:G + 1], offs[G + 1:], N)
+            res = api.count_batched_async(packed.batch)
             ev = torch.cuda.Event()
             ev.record(s)
-        keep = [g for g, _ in graphs] + [packed, res]
-        self._inflight.append(_Flight(reqs, futs, ev, res, sum(n for _, _, n in items), s, keep,
-                                      "batch"))
+        keep += [offs_h, offs, edges, packed, res]
+        self._inflight.append(_Flight(reqs, futs, ev, (res, packed.status),
+                                      sum(n for _, _, n in items), s, keep, "batch"))
         self.stats["batches"] += 1
         self.stats["batched_requests"] += len(items)
 

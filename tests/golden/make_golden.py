@@ -111,11 +111,13 @@ def main():
         with open(PATH, "w") as f:
             json.dump(out, f, indent=1, sort_keys=True)
     if "--batch" in sys.argv:
+        rec = batch_entry(synth.BatchSpec(graphs=4096, seed=0))
         with open(BATCH_PATH, "w") as f:
-            json.dump(batch_entry(synth.BatchSpec(graphs=4096, seed=0)), f, indent=0)
+            json.dump(rec, f, indent=0)
     if "--pool" in sys.argv:
+        rec = pool_entry()
         with open(POOL_PATH, "w") as f:
-            json.dump(pool_entry(), f, indent=1)
+            json.dump(rec, f, indent=1)
 
 
 if __name__ == "__main__":

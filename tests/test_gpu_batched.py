@@ -223,3 +223,74 @@ def test_batched_forced_forms(name):
         torch.cuda.synchronize()
         check(res, gs, want, per_vertex=pv)
     plan.close()
+
+
+# ------------------------------------------------------------------ edge arrays -> batch
+
+
+def pack_on_device(gs):
+    """tc_batched_pack of graphs [(edges int32 [m, 2], n), ...] (edges may hold bad ids)."""
+    ns = [n for _, n in gs]
+    ms = [int(e.shape[0]) for e, _ in gs]
+    vo = torch.tensor(np.concatenate([[0], np.cumsum(ns)]), dtype=torch.int64, device=DEV)
+    eo = torch.tensor(np.concatenate([[0], np.cumsum(ms)]), dtype=torch.int64, device=DEV)
+    edges = torch.cat([e.to(torch.int32) for e, _ in gs]).reshape(-1, 2).to(DEV)
+    return api.pack_edges_async(edges, vo, eo, int(sum(ns)))
+
+
+def test_pack_matches_symmetric_csr():
+    """The device pack gives exactly the symmetric CSR (rows ascending, local ids) that the
+    input generator's host-side formatter builds, including empty graphs and graphs without
+    edges."""
+    gs = mixed_graphs(7, 20)
+    gs.insert(3, (torch.zeros((0, 2), dtype=torch.int32), 0))   # a graph without vertices
+    gs.append((torch.zeros((0, 2), dtype=torch.int32), 0))
+    p = pack_on_device(gs)
+    torch.cuda.synchronize()
+    assert not p.status.cpu().numpy().any()
+    want = synth.pack_symmetric(gs)
+    A = int(want["adj_total"])
+    assert torch.equal(p.batch.adj_off.cpu(), want["adj_off"])
+    assert torch.equal(p.batch.row_ptr.cpu(), want["row_ptr"])
+    assert torch.equal(p.batch.col.cpu()[:A], want["col"])
+    res = api.count_batched(p.batch, per_vertex=True)
+    check(res, gs, oracle_per_graph(gs))
+
+
+@pytest.mark.parametrize("where", ["first", "middle", "last"])
+def test_pack_bad_ids_reported_per_graph(where):
+    """An id outside [0, n_g) or a self-loop fails only its own graph (pack status), whatever
+    its position; the other graphs' counts are exact."""
+    gs = mixed_graphs(8, 10)
+    bad = {"first": 0, "middle": 5, "last": len(gs) - 1}[where]
+    e, n = gs[bad]
+    gs[bad] = (torch.cat([e, torch.tensor([[0, n + 3]], dtype=torch.int32)]), n)
+    gs[(bad + 2) % len(gs)] = (torch.tensor([[1, 1], [0, 1]], dtype=torch.int32), 3)
+    p = pack_on_device(gs)
+    res = api.count_batched_async(p.batch)
+    torch.cuda.synchronize()
+    pst = p.status.cpu().numpy()
+    assert pst[bad] == api.E_RANGE
+    assert pst[(bad + 2) % len(gs)] == api.E_SELF_LOOP
+    st = res.status.cpu().numpy()
+    tot = res.totals.cpu().numpy().astype(np.uint64)
+    for g, (e, n) in enumerate(gs):
+        if g in (bad, (bad + 2) % len(gs)):
+            continue
+        assert pst[g] == 0 and st[g] == 0
+        assert tot[g] == oracle.count(e, n)
+
+
+def test_pack_offsets_not_prefix_sums():
+    """Offsets that are not prefix sums mark every graph of the batch; nothing else breaks."""
+    gs = mixed_graphs(9, 4)
+    ns = [n for _, n in gs]
+    ms = [int(e.shape[0]) for e, _ in gs]
+    vo = np.concatenate([[0], np.cumsum(ns)]).astype(np.int64)
+    vo[2] = vo[3] + 5  # decreasing
+    eo = np.concatenate([[0], np.cumsum(ms)]).astype(np.int64)
+    edges = torch.cat([e for e, _ in gs]).to(DEV)
+    p = api.pack_edges_async(edges, torch.from_numpy(vo).to(DEV), torch.from_numpy(eo).to(DEV),
+                             int(sum(ns)))
+    torch.cuda.synchronize()
+    assert (p.status.cpu().numpy() == api.E_ARG).all()

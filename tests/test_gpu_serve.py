@@ -70,3 +70,46 @@ def test_bad_request_reports_error():
         with pytest.raises(api.TCError):
             fb.result(timeout=60)
         assert fg.result(timeout=60)[0] == oracle.count(good, n)
+
+
+def test_resident_key_concurrent_and_reused():
+    """The same resident key submitted many times with several requests in flight (counts
+    on one workspace run in stream order), and a key reused for another graph (counted from
+    scratch, then resident in its place): every result equals the oracle's."""
+    g1, n1 = synth.rmat_graph(14, 16, seed=301)
+    g2, n2 = synth.rmat_graph(14, 16, seed=302)
+    w1, w2 = oracle.count(g1, n1), oracle.count(g2, n2)
+    g1, g2 = g1.pin_memory(), g2.pin_memory()
+    with serve.Server(DEV, small_edges=1 << 10, max_inflight=6, streams=3) as srv:
+        assert srv.submit(serve.Request(g1, n1, "k")).result(timeout=120)[0] == w1
+        futs = [srv.submit(serve.Request(g1, n1, "k")) for _ in range(12)]
+        other, _ = synth.rmat_graph(10, 16, seed=5)
+        futs += [srv.submit(serve.Request(other.pin_memory(), 1 << 10)) for _ in range(4)]
+        assert [f.result(timeout=120)[0] for f in futs[:12]] == [w1] * 12
+        for f in futs[12:]:
+            f.result(timeout=120)
+        assert srv.stats["resident_hits"] >= 12
+        # the key now names another graph
+        assert srv.submit(serve.Request(g2, n2, "k")).result(timeout=120)[0] == w2
+        futs = [srv.submit(serve.Request(g2, n2, "k")) for _ in range(6)]
+        assert [f.result(timeout=120)[0] for f in futs] == [w2] * 6
+        # and back
+        assert srv.submit(serve.Request(g1, n1, "k")).result(timeout=120)[0] == w1
+
+
+def test_bad_ids_in_a_batch_fail_only_their_request():
+    """Small requests packed together: one with an id outside [0, n) (first, middle and last
+    position of the batch) fails alone; the others' counts are exact."""
+    goods = [synth.rmat_graph(9, 8, seed=400 + i) for i in range(7)]
+    want = [oracle.count(e, n) for e, n in goods]
+    for pos in (0, 3, 7):
+        bad = torch.tensor([[0, 1], [1, 9]], dtype=torch.int32)
+        reqs = [serve.Request(e.pin_memory(), n) for e, n in goods]
+        reqs.insert(pos, serve.Request(bad.pin_memory(), 4))
+        with serve.Server(DEV, small_edges=1 << 20, batch_graphs=64, max_inflight=2) as srv:
+            futs = [srv.submit(r) for r in reqs]
+            with pytest.raises(api.TCError) as ei:
+                futs[pos].result(timeout=120)
+            assert ei.value.name == "range"
+            got = [f.result(timeout=120)[0] for i, f in enumerate(futs) if i != pos]
+        assert got == want
