@@ -33,22 +33,30 @@ WORKLOADS = {
 }
 GOLDEN_KEYS = {"rmat23": "rmat_s23_ef24_s0", "rmat20": "rmat_s20_ef16_s0",
                "er1000": "er_1000_p0.02_s0"}
-COUNT_SRC = os.path.join(ROOT, "paper_1503_00576_amd", "csrc", "count.hip")
+GOLDEN_DIR = os.path.join(ROOT, "tests", "golden")
+# the sources whose change invalidates a committed counter summary of the counting kernel
+# (the kernel itself, and the preprocessing that lays out its work items and segments)
+COUNT_SOURCES = [os.path.join(ROOT, "paper_1503_00576_amd", "csrc", f)
+                 for f in ("count.hip", "prep.hip", "api.hip", "internal.h")]
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_sha() -> str:
-    with open(COUNT_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def sources_sha(paths=COUNT_SOURCES) -> str:
+    h = hashlib.sha256()
+    for p in paths:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
-def load_traffic(workload: str):
-    """HBM bytes per launch of the counting kernel from the committed rocprofv3 counter
-    summary, or None when absent or taken on a different kernel source."""
-    path = os.path.join(ROOT, "profiles", f"traffic_k_count_{workload}.txt")
+def load_counters(kernel: str, workload: str) -> dict | None:
+    """key = value pairs of the committed rocprofv3 counter summary of a kernel on a workload
+    (profiles/counters_<kernel>_<workload>.txt), or None when absent or taken on other
+    sources than the current ones."""
+    path = os.path.join(ROOT, "profiles", f"counters_{kernel}_{workload}.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -56,12 +64,56 @@ def load_traffic(workload: str):
         if "=" in line and not line.lstrip().startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("kernel_sha") != kernel_sha():
+    if kv.get("sources_sha") != sources_sha():
         return None
-    try:
-        return float(kv["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
+    out = {}
+    for k, v in kv.items():
+        try:
+            out[k] = float(v)
+        except ValueError:
+            out[k] = v
+    return out
+
+
+def golden(name: str):
+    path = os.path.join(GOLDEN_DIR, name)
+    if not os.path.exists(path) or os.path.getsize(path) == 0:
         return None
+    with open(path) as f:
+        return json.load(f)
+
+
+def pv_digest(pv) -> str:
+    """sha256 of per-vertex counts as little-endian uint64 (the stored goldens' digest)."""
+    return hashlib.sha256(pv.detach().cpu().numpy().astype("<u8").tobytes()).hexdigest()
+
+
+def streamed_elements(row_ptr, col, p0: int, panel: int = 32):
+    """Elements the counting kernel streams through its LDS structures, and its segments:
+    for a middle vertex v below the panel region, the suffix of N+(u) after v for every
+    in-edge u -> v (when N+(v) is not empty); in the panel region (ranks >= p0, panels of 32
+    consecutive middle vertices), one suffix per (u, panel), after u's first panel vertex."""
+    import torch
+    rp = row_ptr.to(torch.int64)
+    c = col.to(torch.int64)
+    n = rp.numel() - 1
+    deg = rp[1:] - rp[:-1]
+    src = torch.repeat_interleave(torch.arange(n, device=rp.device), deg)
+    e = torch.arange(c.numel(), device=rp.device)
+    suffix = rp[src + 1] - e - 1
+    mid = (c < p0) & (suffix > 0) & (deg[c] > 0)
+    streamed = int(suffix[mid].sum().item())
+    segments = int(mid.sum().item())
+    del mid
+    pan = c >= p0
+    if bool(pan.any()):
+        first = p0 + torch.div(c - p0, panel, rounding_mode="floor") * panel
+        prev = torch.roll(c, 1)
+        run_start = (e == rp[src]) | (prev < first)
+        sel = pan & run_start & (suffix > 0)
+        streamed += int(suffix[sel].sum().item())
+        segments += int(sel.sum().item())
+    return streamed, segments
 
 
 def make_graph(name: str, dev):
@@ -83,9 +135,10 @@ def host_cpu_model() -> str:
     return "unknown CPU"
 
 
-def cpu_baseline(dev, seconds_hint: float):
+def cpu_baseline(dev):
     """The oracle (single-threaded C, test infrastructure) on a bounded sample of the same
-    workload family: R-MAT scale 19, edgefactor 24, same (a, b, c), seed 0."""
+    workload family: R-MAT scale 19, edgefactor 24, same (a, b, c), seed 0.  The stored oracle
+    run of the full headline graph (tests/golden/workloads.json) is reported beside it."""
     import oracle
     from paper_1503_00576_amd import synth
     e, n = synth.rmat_graph(19, 24, seed=0, device=dev)
@@ -94,12 +147,21 @@ def cpu_baseline(dev, seconds_hint: float):
     t0 = time.perf_counter()
     tot = oracle.count(eh, n)
     dt = time.perf_counter() - t0
-    return {"value": m / dt, "unit": "oriented-edge intersections/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"R-MAT scale 19, edgefactor 24, seed 0 ({m} edges, {tot} triangles): "
-                      f"oracle end to end (degrees, orientation, sorted lists, merges) "
-                      f"in {dt:.2f} s on one host core ({host_cpu_model()}, "
-                      f"{os.cpu_count()} logical CPUs visible)"}
+    out = {"value": m / dt, "unit": "oriented-edge intersections/s", "cores": 1,
+           "kind": "oracle",
+           "sample": f"R-MAT scale 19, edgefactor 24, seed 0 ({m} edges, {tot} triangles): "
+                     f"oracle end to end (degrees, orientation, sorted lists, merges) "
+                     f"in {dt:.2f} s on one host core ({host_cpu_model()}, "
+                     f"{os.cpu_count()} logical CPUs visible)"}
+    g = (golden("workloads.json") or {}).get("rmat_s23_ef24_s0")
+    if g is not None:
+        out["headline_graph_oracle"] = {
+            "seconds": g["oracle_seconds"], "edges": g["m"],
+            "intersections_per_s": g["m"] / g["oracle_seconds"],
+            "note": "the stored oracle run of the full R-MAT scale 23 graph (total and "
+                    "per-vertex counts), one core of the container that wrote the goldens "
+                    "(tests/golden/make_golden.py --c3), not of the GPU box's host"}
+    return out
 
 
 def pcie_section(edges, n, m, total, ws, out, L, sp):
@@ -135,7 +197,8 @@ def pcie_section(edges, n, m, total, ws, out, L, sp):
 def batched_section(dev, steps: int, graphs_n: int = 4096, loop: bool = True):
     """4096 Barabasi-Albert / Watts-Strogatz graphs (50/50, n log-uniform in [50, 20000],
     average degree in [4, 32]) in one captured plan, tuned, against a loop of one tc_count
-    call per graph on the same GPU."""
+    call per graph on the same GPU; per-graph totals and the per-vertex digest checked against
+    the oracle's stored values."""
     import torch
     from paper_1503_00576_amd import api, autotune, synth
     spec = synth.BatchSpec(graphs=graphs_n, seed=0)
@@ -164,10 +227,24 @@ def batched_section(dev, steps: int, graphs_n: int = 4096, loop: bool = True):
     batch_ms = (time.perf_counter() - t0) * 1e3 / steps
     assert torch.equal(res.totals, totals)
     log(f"plan: {batch_ms:.3f} ms per batch")
+    # per-vertex counts of the same batch (one replay of the per-vertex plan)
+    pv_res = plan.run_async(b, per_vertex=True)
+    torch.cuda.synchronize()
+    pv_res.check()
+    ref = golden("batch4096.json") if graphs_n == 4096 else None
+    gmatch = None
+    if ref is not None:
+        gmatch = {"totals": totals.cpu().tolist() == ref["totals"],
+                  "per_vertex_sha256": pv_digest(pv_res.per_vertex) == ref["per_vertex_sha256"]}
+        log(f"batched golden match: {gmatch}")
+    out = {"graphs": b.G, "vertices": b.n_total, "edges": edges,
+           "triangles": int(totals.sum().item()), "ms_per_batch": round(batch_ms, 3),
+           "graphs_per_s": b.G / (batch_ms * 1e-3), "edges_per_s": edges / (batch_ms * 1e-3),
+           "golden_match": gmatch, "tuning": best,
+           "tuning_ms": [[t, round(ms, 3)] for t, ms in timings]}
     if not loop:
-        return {"graphs": b.G, "vertices": b.n_total, "edges": edges,
-                "ms_per_batch": round(batch_ms, 3), "graphs_per_s": b.G / batch_ms * 1e3,
-                "tuning": best}
+        plan.close()
+        return out
     # the plain per-graph loop: one tc_count per graph, workspace sized for the largest
     nmax = max(n for _, n in graphs)
     mmax = max(int(e.shape[0]) for e, _ in graphs)
@@ -185,46 +262,35 @@ def batched_section(dev, steps: int, graphs_n: int = 4096, loop: bool = True):
     torch.cuda.synchronize()
     loop_ms = (time.perf_counter() - t0) * 1e3
     plan.close()
-    return {"graphs": b.G, "vertices": b.n_total, "edges": edges,
-            "triangles": int(totals.sum().item()), "ms_per_batch": round(batch_ms, 3),
-            "graphs_per_s": b.G / (batch_ms * 1e-3), "edges_per_s": edges / (batch_ms * 1e-3),
-            "loop_ms": round(loop_ms, 3), "loop_graphs_per_s": b.G / (loop_ms * 1e-3),
-            "speedup_vs_loop": round(loop_ms / batch_ms, 2), "tuning": best,
-            "tuning_ms": [[t, round(ms, 3)] for t, ms in timings]}
+    out.update({"loop_ms": round(loop_ms, 3), "loop_graphs_per_s": b.G / (loop_ms * 1e-3),
+                "speedup_vs_loop": round(loop_ms / batch_ms, 2)})
+    return out
 
 
 def serve_section(dev, duration: float, rate: float, seed: int = 0):
     """Poisson arrivals (rate per second, `duration` seconds); 90% R-MAT scale 10-14, 9% scale
-    17-19, 1% scale 21, edgefactor 16.  Each request carries its edge array in pinned host
-    memory and is processed in full (copy to the device, preprocessing, count).  Graphs are
-    drawn from a seeded pool per scale to bound generation time."""
+    17-19, 1% scale 21, edgefactor 16, drawn from a seeded pool per scale (bounded generation
+    time).  Each request carries its edge array in pinned host memory and is processed in full
+    (copy to the device, preprocessing, count); every result is checked against the oracle's
+    stored count of its pool graph."""
+    import concurrent.futures as cf
     import threading
     import torch
     from paper_1503_00576_amd import serve, synth
     times, u = synth.poisson_trace(rate, duration, seed)
     times, u = times.tolist(), u.tolist()
-    pool_size = {s: 16 for s in range(10, 15)}
-    pool_size.update({17: 6, 18: 4, 19: 3, 21: 2})
+    ref = golden("serve_pool.json")
     pool = {}
     t0 = time.perf_counter()
-    for sc, k in pool_size.items():
+    for sc, k in synth.SERVE_POOL.items():
         pool[sc] = []
         for i in range(k):
-            e, n = synth.rmat_graph(sc, 16, seed=1000 * sc + i, device=dev)
+            e, n = synth.serve_pool_graph(sc, i, device=dev)
             pool[sc].append((e.cpu().pin_memory(), n))
     torch.cuda.synchronize()
     log(f"serve: {len(times)} arrivals, pool generated in {time.perf_counter() - t0:.1f} s")
-
-    def pick(i, x):
-        if x < 0.9:
-            sc = 10 + min(4, int(x / 0.9 * 5))
-        elif x < 0.99:
-            sc = 17 + min(2, int((x - 0.9) / 0.09 * 3))
-        else:
-            sc = 21
-        return pool[sc][i % len(pool[sc])]
-
-    reqs = [pick(i, x) for i, x in enumerate(u)]
+    picks = [synth.serve_pick(i, x) for i, x in enumerate(u)]
+    reqs = [pool[sc][i] for sc, i in picks]
     futs = [None] * len(reqs)
     srv = serve.Server(dev, budget_bytes=32 << 30, streams=4, small_edges=1 << 18,
                        batch_graphs=512, max_inflight=8)
@@ -245,7 +311,6 @@ def serve_section(dev, duration: float, rate: float, seed: int = 0):
         if time.perf_counter() - last_log > 10:
             log(f"serve: {srv.stats['completed']} completed")
             last_log = time.perf_counter()
-    import concurrent.futures as cf
     pending, waited = set(futs), 0.0
     while pending and waited < 240.0:
         done, pending = cf.wait(pending, timeout=10.0)
@@ -253,12 +318,15 @@ def serve_section(dev, duration: float, rate: float, seed: int = 0):
         log(f"serve: {len(futs) - len(pending)} of {len(futs)} finished")
     if pending:
         raise RuntimeError(f"serve: {len(pending)} requests unfinished after the trace")
-    lat, ok, failed = [], 0, 0
-    for f in futs:
+    lat, ok, failed, checked, wrong = [], 0, 0, 0, 0
+    for f, (sc, i) in zip(futs, picks):
         try:
-            _, l = f.result(timeout=0)
+            tot, l = f.result(timeout=0)
             lat.append(l)
             ok += 1
+            if ref is not None:
+                checked += 1
+                wrong += int(tot != ref[str(sc)][i]["total"])
         except Exception:
             failed += 1
     makespan = time.perf_counter() - start
@@ -266,6 +334,8 @@ def serve_section(dev, duration: float, rate: float, seed: int = 0):
     srv.close()
     edges = sum(int(e.shape[0]) for e, _ in reqs)
     return {"requests": len(reqs), "completed": ok, "failed": failed,
+            "golden_match": (wrong == 0 and checked == ok) if ref is not None else None,
+            "checked": checked, "mismatches": wrong,
             "duration_s": duration, "rate_per_s": rate, "makespan_s": round(makespan, 3),
             "graphs_per_s": ok / makespan, "edges_per_s": edges / makespan,
             "p50_ms": round(1e3 * serve.percentile(lat, 50), 3),
@@ -294,6 +364,8 @@ def main():
                     help="batched: skip the per-graph tc_count comparison loop")
     ap.add_argument("--serve", action="store_true",
                     help="only run the serving trace (Poisson arrivals of mixed R-MAT graphs)")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the serving trace (profiling runs)")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -387,30 +459,47 @@ def main():
                   "source": "HIP events around each step on the library's stream"}
     log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, counting kernel {count_ms:.3f} ms")
 
-    # graph statistics for the roofline: streamed elements W = sum_u C(d+(u), 2)
-    arrs = api.Prepared(edges, n).arrays()
+    # graph statistics for the roofline: wedges of the oriented graph W = sum_u C(d+(u), 2)
+    # (one membership test each in the middle-vertex formulation), and the elements the
+    # kernel actually streams (panels merge the tests of 32 middle vertices)
+    prep = api.Prepared(edges, n)
+    arrs = prep.arrays()
     dplus = (arrs["row_ptr"][1:] - arrs["row_ptr"][:-1]).to(torch.int64)
     wedges = int((dplus * (dplus - 1) // 2).sum().item())
-    del arrs
-    golden_ok = None
-    gpath = os.path.join(ROOT, "tests", "golden", "workloads.json")
-    if os.path.exists(gpath):
-        g = json.load(open(gpath)).get(GOLDEN_KEYS[args.workload])
-        if g is not None:
-            golden_ok = (g["total"] == total)
+    p0 = n - min(api.default_options()["panel_ranks"], n)
+    streamed, segments = streamed_elements(arrs["row_ptr"], arrs["col"], p0)
+    del arrs, prep, dplus
+    torch.cuda.empty_cache()
+    g = (golden("workloads.json") or {}).get(GOLDEN_KEYS[args.workload])
+    golden_ok = None if g is None else (g["total"] == total)
 
-    # counting kernel: algorithmic bytes = 4 B per streamed element + 8 B per oriented edge
-    # (its in-edge range) + the node array and out-lists once
-    alg_bytes = 4.0 * wedges + 8.0 * m + 4.0 * (n + 1) + 4.0 * m
-    achieved = alg_bytes / (count_ms * 1e-3) / 1e9
-    traffic = load_traffic(args.workload)
+    # Roofline of the counting kernel.  achieved / frac: the DRAM-side bytes of one launch
+    # (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated, committed under
+    # profiles/) over the launch time measured here with HIP events; null when the committed
+    # counters were taken on other sources.  algorithmic: 4 B per element the kernel streams
+    # + 12 B per segment (its range and panel mask) + the node array and out-lists once.
+    ctr = load_counters("k_count", args.workload)
+    t_s = count_ms * 1e-3
+    alg_bytes = 4.0 * streamed + 12.0 * segments + 4.0 * (n + 1) + 4.0 * m
+    alg_gbs = alg_bytes / t_s / 1e9
+    traffic = ctr["hbm_bytes_per_launch"] if ctr else None
+    if traffic:
+        achieved, basis = traffic / t_s / 1e9, "counter bytes (FETCH_SIZE, WRITE_SIZE) / kernel time"
+    else:
+        achieved, basis = alg_gbs, "algorithmic bytes / kernel time (no current counters)"
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "kernel": "k_count",
-                "kernel_ms": round(count_ms, 4), "algorithmic_bytes": alg_bytes}
-    if traffic:  # DRAM-side bytes per launch over the launch time (counter GB/s)
-        roofline["traffic_gbs"] = round(traffic / (count_ms * 1e-3) / 1e9, 1)
-        roofline["traffic_frac"] = round(traffic / (count_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "basis": basis, "kernel": "k_count<false>", "kernel_ms": round(count_ms, 4),
+                "l2_hit_rate": (round(ctr["l2_hit_rate"], 4)
+                                if ctr and "l2_hit_rate" in ctr else None),
+                "algorithmic": {"bytes": alg_bytes, "gbs": round(alg_gbs, 1),
+                                "frac": round(alg_gbs / HBM_PEAK_GBS, 4),
+                                "streamed_elements": streamed, "segments": segments,
+                                "unit": "4 B per streamed element + 12 B per segment + "
+                                        "4 B per CSR entry and row offset"},
+                "logical_wvtx": {"bytes": 4.0 * wedges, "gbs": round(4.0 * wedges / t_s / 1e9, 1),
+                                 "note": "4 B per wedge of the oriented graph (one membership "
+                                         "test each without panels); context, not a bandwidth"}}
 
     # per-vertex counts (T(x) for every vertex, for clustering coefficients): the counting
     # phase with per-vertex output on the prepared graph, HIP events around each launch
@@ -428,6 +517,8 @@ def main():
     pv_sum = int(pv_out.sum().item())
     assert int(out.total.item()) == total and pv_sum == 3 * total, "per-vertex counts"
     pv_ms = sorted(a.elapsed_time(b) for a, b in pv_ev)[1]
+    pv_golden = None if g is None or "per_vertex_sha256" not in g else \
+        (pv_digest(pv_out) == g["per_vertex_sha256"])
     # the one-shot call (preprocessing without panels + per-vertex counting)
     for a, b in pv_ev:
         a.record(stream)
@@ -440,7 +531,7 @@ def main():
     assert int(out.total.item()) == total and int(pv_out.sum().item()) == 3 * total
     pv1_ms = sorted(a.elapsed_time(b) for a, b in pv_ev)[1]
     per_vertex = {"count_ms": round(pv_ms, 4), "one_shot_ms": round(pv1_ms, 4),
-                  "sum_equals_3T": pv_sum == 3 * total,
+                  "sum_equals_3T": pv_sum == 3 * total, "golden_match": pv_golden,
                   "note": "count_ms: counting phase with per-vertex output on the prepared "
                           "graph (tc_count_prepared with d_per_vertex); one_shot_ms: "
                           "tc_count_per_vertex, preprocessing included; medians of 3"}
@@ -472,14 +563,25 @@ def main():
         "roofline": roofline,
         "cpu_baseline": None,
         "batched": None,
+        "serve": None,
     }
+    del ws
+    torch.cuda.empty_cache()
     if not args.no_batched:
         log("batched: 4096 graphs ...")
         res["batched"] = batched_section(dev, args.steps)
         log("batched done")
+    if not args.no_serve:
+        log(f"serving: {args.serve_seconds:.0f} s of Poisson arrivals at {args.serve_rate:.0f}/s")
+        res["serve"] = serve_section(dev, args.serve_seconds, args.serve_rate)
+        log("serving done")
+    res["golden_match"] = {"headline_total": golden_ok,
+                           "headline_per_vertex": per_vertex["golden_match"],
+                           "batched": (res["batched"] or {}).get("golden_match"),
+                           "serve": (res["serve"] or {}).get("golden_match")}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample) ...")
-        res["cpu_baseline"] = cpu_baseline(dev, 20.0)
+        res["cpu_baseline"] = cpu_baseline(dev)
         log("cpu baseline done")
     print(json.dumps(res), flush=True)
 

@@ -2,6 +2,10 @@
 CPU oracle, graph by graph, bit-exact: per-graph totals and per-vertex counts, invalid graphs
 reported per graph without disturbing the others, and a captured plan replayed several times
 with other GPU work in between."""
+import hashlib
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -294,3 +298,31 @@ def test_pack_offsets_not_prefix_sums():
                              int(sum(ns)))
     torch.cuda.synchronize()
     assert (p.status.cpu().numpy() == api.E_ARG).all()
+
+
+def test_batch4096_golden():
+    """The benchmark's full batch (4096 Barabasi-Albert / Watts-Strogatz graphs, 13.7M
+    vertices, 122M edges) through a tuned-size plan: every graph's total and the whole
+    per-vertex array (digest) against the oracle's stored values."""
+    with open(os.path.join(os.path.dirname(__file__), "golden", "batch4096.json")) as f:
+        ref = json.load(f)
+    graphs = synth.batch_graphs(synth.BatchSpec(graphs=4096, seed=0), device=DEV)
+    h = hashlib.sha256()
+    for e, n in graphs:
+        h.update(np.int64(n).tobytes())
+        h.update(np.ascontiguousarray(e.cpu().numpy()).tobytes())
+    assert h.hexdigest() == ref["inputs_sha256"]
+    b = as_batch(synth.pack_symmetric(graphs, device=DEV))
+    del graphs
+    plan = api.BatchPlan(b.G, b.n_total, b.adj_total, {"chunk_e": 512}, device=DEV)
+    res = plan.run_async(b, per_vertex=True)
+    torch.cuda.synchronize()
+    res.check()
+    assert res.totals.cpu().tolist() == ref["totals"]
+    pv = res.per_vertex.cpu().numpy()
+    assert int(pv.sum()) == ref["per_vertex_sum"]
+    assert hashlib.sha256(pv.astype("<u8").tobytes()).hexdigest() == ref["per_vertex_sha256"]
+    res2 = plan.run_async(b)
+    torch.cuda.synchronize()
+    assert res2.totals.cpu().tolist() == ref["totals"]
+    plan.close()

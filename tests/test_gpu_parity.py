@@ -4,6 +4,7 @@ Integer results, so the bar is equality: totals, per-vertex counts, the degree a
 order, the oriented sorted lists, the sort.  Sizes span several tiles and ragged tails; the
 full-size R-MAT case is checked against the oracle's stored total and sampled per-vertex
 values computed one vertex at a time from the definition."""
+import hashlib
 import json
 import math
 import os
@@ -377,7 +378,14 @@ def test_host_errors():
 
 # ------------------------------------------------------------------ full-size workloads
 
+def pv_digest(pv) -> str:
+    """sha256 of per-vertex counts as little-endian uint64, the stored goldens' digest."""
+    return hashlib.sha256(np.ascontiguousarray(pv, dtype="<u8").tobytes()).hexdigest()
+
+
 def test_rmat20_golden():
+    """R-MAT scale 20: total and the whole per-vertex array (digest) against the oracle's
+    stored values, one-shot and through a prepared graph with panels."""
     g = golden()["rmat_s20_ef16_s0"]
     e, n = synth.rmat_graph(20, 16, seed=0, device=DEV)
     assert synth.edges_sha256(e) == g["sha256"]
@@ -387,7 +395,11 @@ def test_rmat20_golden():
     assert int(pv.sum()) == g["per_vertex_sum"] == 3 * tot
     for v, want in g["per_vertex_sample"].items():
         assert pv[int(v)] == want
+    assert pv_digest(pv) == g["per_vertex_sha256"]
     assert api.count(e, n) == tot
+    r = api.Prepared(e, n).count_async(per_vertex=True).check()
+    assert int(r.total.item()) == tot
+    assert pv_digest(r.per_vertex.cpu().numpy()) == g["per_vertex_sha256"]
 
 
 def test_rmat23_full_size():
@@ -405,6 +417,7 @@ def test_rmat23_full_size():
         pvh = pv.cpu().numpy()
         for v, want in gd["per_vertex_sample"].items():
             assert pvh[int(v)] == want
+        assert pv_digest(pvh) == gd["per_vertex_sha256"]
     # sampled per-vertex counts from the definition, one vertex at a time
     pvh = pv.cpu().numpy()
     deg = api.preprocess(e, n)["deg"].cpu().numpy()

@@ -1,6 +1,9 @@
 """Serving loop on the GPU: every result equals the oracle's and is the same alone and in a
 mix of concurrent requests (exact integers, tolerance 0), with memory-budget queueing,
 batching of small graphs, overlapping large graphs and resident-CSR reuse."""
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -113,3 +116,29 @@ def test_bad_ids_in_a_batch_fail_only_their_request():
             assert ei.value.name == "range"
             got = [f.result(timeout=120)[0] for i, f in enumerate(futs) if i != pos]
         assert got == want
+
+
+def test_serving_workload_pool():
+    """The serving workload's request mix at its own sizes: every graph of the request pool
+    (R-MAT scales 10-14, 17-19 and 21, edgefactor 16) submitted at once, in the trace's
+    order of scales, plus a slice of the Poisson trace; every count equals the oracle's
+    stored one."""
+    with open(os.path.join(os.path.dirname(__file__), "golden", "serve_pool.json")) as f:
+        ref = json.load(f)
+    pool = {}
+    for sc, k in synth.SERVE_POOL.items():
+        pool[sc] = []
+        for i in range(k):
+            e, n = synth.serve_pool_graph(sc, i, device=DEV)
+            assert synth.edges_sha256(e) == ref[str(sc)][i]["sha256"]
+            pool[sc].append((e.cpu().pin_memory(), n))
+    _, u = synth.poisson_trace(200.0, 2.0, 0)
+    picks = [(sc, i) for sc, k in synth.SERVE_POOL.items() for i in range(k)]
+    picks += [synth.serve_pick(j, x) for j, x in enumerate(u.tolist())]
+    with serve.Server(DEV, budget_bytes=32 << 30, streams=4, small_edges=1 << 18,
+                      batch_graphs=512, max_inflight=8) as srv:
+        futs = [srv.submit(serve.Request(*pool[sc][i])) for sc, i in picks]
+        got = [f.result(timeout=240)[0] for f in futs]
+        stats = dict(srv.stats)
+    assert got == [ref[str(sc)][i]["total"] for sc, i in picks]
+    assert stats.get("batches", 0) >= 1 and stats.get("single", 0) >= 1

@@ -103,3 +103,28 @@ def test_poisson_trace():
     assert abs(t.numel() - 12000) < 5 * np.sqrt(12000)
     assert (torch.diff(t) > 0).all() and float(t[-1]) < 60.0
     assert 0.0 <= float(u.min()) and float(u.max()) < 1.0
+
+
+def test_serve_pool_hashes():
+    """The serving pool's small graphs regenerate the bytes whose counts are stored."""
+    with open(os.path.join(HERE, "golden", "serve_pool.json")) as f:
+        ref = json.load(f)
+    for sc in (10, 12, 14):
+        for i in (0, synth.SERVE_POOL[sc] - 1):
+            e, n = synth.serve_pool_graph(sc, i)
+            assert n == ref[str(sc)][i]["n"] and e.shape[0] == ref[str(sc)][i]["m"]
+            assert synth.edges_sha256(e) == ref[str(sc)][i]["sha256"]
+
+
+def test_serve_pick_mix():
+    """Request i's scale follows the stated mix (90% scales 10-14, 9% 17-19, 1% 21)."""
+    assert synth.serve_pick(0, 0.0) == (10, 0)
+    assert synth.serve_pick(5, 0.899)[0] == 14
+    assert synth.serve_pick(5, 0.9)[0] == 17
+    assert synth.serve_pick(5, 0.989)[0] == 19
+    assert synth.serve_pick(3, 0.995) == (21, 1)
+    _, u = synth.poisson_trace(200.0, 60.0, 0)
+    scales = np.array([synth.serve_pick(i, x)[0] for i, x in enumerate(u.tolist())])
+    assert 11000 < scales.size < 13000
+    assert abs((scales <= 14).mean() - 0.9) < 0.02
+    assert abs((scales == 21).mean() - 0.01) < 0.005
