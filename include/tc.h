@@ -51,8 +51,10 @@ typedef enum tc_status {
     TC_E_WORKSPACE = 7,  /* d_ws smaller than tc_workspace_size() or misaligned */
     TC_E_TOO_LARGE = 8,  /* n >= 2^31 or m >= 2^32 */
     TC_E_HIP = 9,        /* a HIP runtime call (launch) failed */
-    TC_E_MISMATCH = 10   /* tc_count_prepared on a workspace that tc_preprocess did not fill
+    TC_E_MISMATCH = 10,  /* tc_count_prepared on a workspace that tc_preprocess did not fill
                             for the same (n, m, flags, options) */
+    TC_E_SCRATCH = 11    /* tc_count_noalloc: the graph's workspace exceeds the static
+                            scratch (TC_NOALLOC_SCRATCH_BYTES) */
 } tc_status;
 
 /* Edge-array multiplicity (Section 3.1 reading).
@@ -148,6 +150,23 @@ int tc_count(const int32_t *d_edges, int64_t n, int64_t m, uint32_t flags,
 int tc_count_per_vertex(const int32_t *d_edges, int64_t n, int64_t m, uint32_t flags,
                         const tc_options *opts, void *d_ws, size_t ws_bytes, void *stream,
                         uint64_t *d_total, uint64_t *d_per_vertex, int32_t *d_status);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): tc_count with the workspace in a static
+ * device array of TC_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends.  Nothing is allocated, by the library or anything it calls; the
+ * caller passes only the edges and the outputs, with the arguments and results of tc_count.
+ * Graphs whose tc_workspace_size(n, m, flags, opts) exceeds TC_NOALLOC_SCRATCH_BYTES
+ * (64 MiB: about 10^6 edges) are rejected with TC_E_SCRATCH before anything is enqueued.
+ * The array's address on the current device is looked up once per device on the first call
+ * (TC_E_HIP if that fails).  Every call on one GPU shares that GPU's array, which keeps the
+ * last call's contents (each call clears what it needs): calls that overlap on one GPU (on
+ * different streams, or from several threads without ordering) race and give unspecified
+ * results; calls on one stream are ordered and safe. */
+#define TC_NOALLOC_SCRATCH_BYTES (64u << 20)
+int tc_count_noalloc(const int32_t *d_edges, int64_t n, int64_t m, uint32_t flags,
+                     const tc_options *opts, void *stream, uint64_t *d_total,
+                     int32_t *d_status);
 
 /* Where the preprocessing results live inside the workspace (byte offsets from d_ws), so that
  * callers can inspect the intermediate arrays after tc_preprocess:

@@ -10,6 +10,7 @@ LIB_PATH = os.environ.get("TC_LIB", os.path.join(HERE, "libtc.so"))
 
 EXPORTS = [
     "tc_strerror", "tc_options_init", "tc_workspace_size", "tc_count", "tc_count_per_vertex",
+    "tc_count_noalloc",
     "tc_workspace_layout", "tc_preprocess", "tc_count_prepared", "tc_sort_workspace_size",
     "tc_sort_u64", "tc_batched_workspace_size", "tc_batched_plan_create", "tc_batched_plan_run",
     "tc_batched_plan_destroy", "tc_count_batched", "tc_batched_pack_workspace_size",
@@ -55,6 +56,8 @@ def lib():
     L.tc_count.restype = ctypes.c_int
     L.tc_count_per_vertex.argtypes = [vp, i64, i64, u32, op, vp, sz, vp, vp, vp, vp]
     L.tc_count_per_vertex.restype = ctypes.c_int
+    L.tc_count_noalloc.argtypes = [vp, i64, i64, u32, op, vp, vp, vp]
+    L.tc_count_noalloc.restype = ctypes.c_int
     L.tc_workspace_layout.argtypes = [i64, i64, u32, op, ctypes.POINTER(TcLayout)]
     L.tc_workspace_layout.restype = ctypes.c_int
     L.tc_preprocess.argtypes = [vp, i64, i64, u32, op, vp, sz, vp, vp]

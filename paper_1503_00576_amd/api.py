@@ -11,11 +11,11 @@ import torch
 from . import _native
 
 OK, E_ARG, E_RANGE, E_SELF_LOOP, E_DUP_EDGE, E_ASYMMETRIC, E_UNSORTED, E_WORKSPACE, \
-    E_TOO_LARGE, E_HIP, E_MISMATCH = range(11)
+    E_TOO_LARGE, E_HIP, E_MISMATCH, E_SCRATCH = range(12)
 STATUS_NAMES = {OK: "ok", E_ARG: "arg", E_RANGE: "range", E_SELF_LOOP: "self_loop",
                 E_DUP_EDGE: "dup_edge", E_ASYMMETRIC: "asymmetric", E_UNSORTED: "unsorted",
                 E_WORKSPACE: "workspace", E_TOO_LARGE: "too_large", E_HIP: "hip",
-                E_MISMATCH: "mismatch"}
+                E_MISMATCH: "mismatch", E_SCRATCH: "scratch"}
 
 EDGES_ONCE = 0
 EDGES_BOTH = 1

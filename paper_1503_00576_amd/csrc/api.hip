@@ -4,6 +4,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "internal.h"
 
 namespace tc {
@@ -557,6 +559,33 @@ static int run_count(const int32_t *d_edges, int64_t n, int64_t m, uint32_t flag
     return copy_status(ws, L, d_status, s, kCtlRun);
 }
 
+// ------------------------------------------------------------------ static scratch
+
+// The workspace of tc_count_noalloc: a file-scope device array that every GPU the library
+// runs on holds until the process ends.  Host code never passes the array's name to a kernel
+// (on the host it is only a stand-in for the symbol): each device's own address comes from
+// hipGetSymbolAddress, taken once per device with that device current, and is the workspace
+// pointer the kernels get.
+constexpr size_t kScratchBytes = TC_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+// this device's address of `scratch` (nullptr on a HIP error)
+static void *scratch_on_current_device() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
 }  // namespace tc
 
 using namespace tc;
@@ -576,6 +605,9 @@ const char *tc_strerror(int status) {
         case TC_E_TOO_LARGE: return "graph too large for 32-bit indices";
         case TC_E_HIP: return "HIP runtime error";
         case TC_E_MISMATCH: return "workspace prepared for another graph size or other options";
+        case TC_E_SCRATCH:
+            return "graph needs more workspace than tc_count_noalloc's static scratch "
+                   "(TC_NOALLOC_SCRATCH_BYTES)";
         default: return "unknown status";
     }
 }
@@ -631,6 +663,20 @@ int tc_preprocess(const int32_t *d_edges, int64_t n, int64_t m, uint32_t flags,
     st = run_preprocess(d_edges, flags, d_ws, L, (hipStream_t)stream);
     if (st) return st;
     return copy_status(d_ws, L, d_status, (hipStream_t)stream, kCtlStatus);
+}
+
+int tc_count_noalloc(const int32_t *d_edges, int64_t n, int64_t m, uint32_t flags,
+                     const tc_options *opts, void *stream, uint64_t *d_total,
+                     int32_t *d_status) {
+    Layout L;
+    if (n < 0 || m < 0 || (flags & ~TC_EDGES_BOTH)) return TC_E_ARG;
+    if (n >= (1ll << 31) || m >= (1ll << 32)) return TC_E_TOO_LARGE;
+    if (!make_layout(n, m, flags, opts, L)) return TC_E_ARG;
+    if (L.total_bytes > kScratchBytes) return TC_E_SCRATCH;
+    void *ws = scratch_on_current_device();
+    if (!ws) return TC_E_HIP;
+    return run_count(d_edges, n, m, flags, opts, ws, kScratchBytes, (hipStream_t)stream, d_total,
+                     nullptr, d_status);
 }
 
 int tc_count_prepared(int64_t n, int64_t m, uint32_t flags, const tc_options *opts,
