@@ -164,7 +164,7 @@ def cpu_baseline(dev):
     return out
 
 
-def pcie_section(edges, n, m, total, ws, out, L, sp):
+def pcie_section(edges, n, m, total, ws, out, L, sp, op):
     """The paper's wall-clock protocol: edge array from (pinned) host memory, the step, the
     total back to the host; reported beside `value`, never as it (median of 3 runs)."""
     import torch
@@ -179,9 +179,9 @@ def pcie_section(edges, n, m, total, ws, out, L, sp):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         dev_edges.copy_(host_edges, non_blocking=True)
-        api._raise(L.tc_preprocess(api._ptr(dev_edges), n, m, 0, None, api._ptr(ws), wsz, sp, None),
-                   "tc_preprocess")
-        api._raise(L.tc_count_prepared(n, m, 0, None, api._ptr(ws), wsz, sp, api._ptr(out.total),
+        api._raise(L.tc_preprocess(api._ptr(dev_edges), n, m, 0, op, api._ptr(ws), wsz, sp,
+                                   None), "tc_preprocess")
+        api._raise(L.tc_count_prepared(n, m, 0, op, api._ptr(ws), wsz, sp, api._ptr(out.total),
                                        None, api._ptr(out.status)), "tc_count_prepared")
         host_total.copy_(out.total, non_blocking=True)
         torch.cuda.synchronize()
@@ -346,6 +346,130 @@ def serve_section(dev, duration: float, rate: float, seed: int = 0):
             "single_requests": stats.get("single", 0), "rejected": stats.get("rejected", 0)}
 
 
+def _time(fn, reps: int = 3) -> float:
+    """Median milliseconds of fn() (enqueues work on the current stream), HIP events."""
+    import torch
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    return sorted(ts)[len(ts) // 2]
+
+
+def ablation_section(dev, workloads=("rmat20", "rmat23")):
+    """The paper's own counting design (Section 3.3: one thread per oriented edge, two-pointer
+    merge) and its Section 3.4 optimisations on this GPU, beside the shipped kernels: every
+    yardstick count is checked against the stored oracle total."""
+    import torch
+    from paper_1503_00576_amd import ablation as ab
+    from paper_1503_00576_amd import api
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    out = {}
+    for wl in workloads:
+        edges, n = make_graph(wl, dev)
+        m = int(edges.shape[0])
+        g = (golden("workloads.json") or {}).get(GOLDEN_KEYS[wl])
+        want = g["total"] if g else None
+        prep = api.Prepared(edges, n)
+        shipped_total = prep.count()
+        res = api.Result(torch.empty(1, dtype=torch.int64, device=dev),
+                         torch.empty(1, dtype=torch.int32, device=dev))
+        shipped_ms = _time(lambda: prep.count_async(out=res))
+        pre_ms = _time(lambda: api.Prepared(edges, n, workspace=prep.workspace), reps=3)
+        em = ab.EdgeMerge(prep)
+        em.zip()
+        rows = {}
+        variants = [("final loop, SoA, const restrict, 64 x 8/CU", 0, 64, 8),
+                    ("two reads per step (preliminary loop)", ab.TWO_READS, 64, 8),
+                    ("array of (u, v) structures (not unzipped)", ab.AOS, 64, 8),
+                    ("plain pointers (no const restrict)", ab.PLAIN_PTRS, 64, 8),
+                    ("half waves (32 of 64 lanes work)", ab.HALF_WAVE, 64, 16),
+                    ("256 threads x 2/CU", 0, 256, 2), ("256 threads x 8/CU", 0, 256, 8),
+                    ("1024 threads x 1/CU", 0, 1024, 1), ("128 threads x 16/CU", 0, 128, 16)]
+        for name, flags, threads, per_cu in variants:
+            blocks = per_cu * cus
+            tot = em.count(flags, threads, blocks)
+            ms = _time(lambda: em.run_async(flags, threads, blocks), reps=2)
+            rows[name] = {"ms": round(ms, 3), "match": tot == want if want else None,
+                          "vs_shipped": round(ms / shipped_ms, 2)}
+            log(f"ablation {wl}: {name}: {ms:.2f} ms")
+        # edge sorts of the oriented keys (u, v ranks) in a shuffled order
+        a = prep.arrays()
+        b = a["id_bits"]
+        perm = torch.randperm(m, device=dev, generator=torch.Generator(device=dev).manual_seed(0))
+        u0 = a["src"][perm].contiguous()
+        v0 = a["col"][perm].contiguous()
+        del perm
+        sorts = {}
+        pairs = torch.empty(2 * m, dtype=torch.int32, device=dev)
+        pv = pairs.view(m, 2)
+
+        def fill_pairs():
+            pv[:, 0].copy_(u0)
+            pv[:, 1].copy_(v0)
+        fill_pairs()
+        temp = ab.sort_async(ab.SORT_PAIRS_COMPARE, b, pairs)
+        ts = []
+        for _ in range(2):
+            fill_pairs()
+            torch.cuda.synchronize()
+            ts.append(_time(lambda: ab.sort_async(ab.SORT_PAIRS_COMPARE, b, pairs, temp=temp),
+                            reps=1))
+        sorts["pairs, comparison merge sort (library)"] = round(min(ts), 3)
+        del pairs, pv, temp
+        ua, va = torch.empty_like(u0), torch.empty_like(v0)
+        ua2, va2 = torch.empty_like(u0), torch.empty_like(v0)
+        ua.copy_(u0)
+        va.copy_(v0)
+        temp = ab.sort_async(ab.SORT_PAIRS_RADIX, b, ua, va, ua2, va2)
+        ts = []
+        for _ in range(3):
+            ua.copy_(u0)
+            va.copy_(v0)
+            torch.cuda.synchronize()
+            ts.append(_time(lambda: ab.sort_async(ab.SORT_PAIRS_RADIX, b, ua, va, ua2, va2, temp),
+                            reps=1))
+        sorts["pairs, two radix passes over (key, value) arrays (library)"] = round(sorted(ts)[1], 3)
+        del ua, va, ua2, va2, temp
+        keys = (u0.to(torch.int64) << b) | v0.to(torch.int64)
+        work, out_k = torch.empty_like(keys), torch.empty_like(keys)
+        temp = ab.sort_async(ab.SORT_PACKED_RADIX, b, keys, None, out_k)
+        sorts["packed 64-bit keys, radix (library)"] = round(
+            _time(lambda: ab.sort_async(ab.SORT_PACKED_RADIX, b, keys, None, out_k, temp=temp)), 3)
+        ts = []
+        for _ in range(3):
+            work.copy_(keys)
+            torch.cuda.synchronize()
+            ts.append(_time(lambda: api.sort_u64(work, 2 * b), reps=1))
+        sorts["packed 64-bit keys, libtc radix sort (tc_sort_u64)"] = round(sorted(ts)[1], 3)
+        del keys, work, out_k, temp, u0, v0, a
+        out[wl] = {"n": n, "m": m, "triangles_shipped": shipped_total,
+                   "shipped_count_ms": round(shipped_ms, 3),
+                   "shipped_preprocess_ms": round(pre_ms, 3),
+                   "golden_match": (shipped_total == want) if want else None,
+                   "edge_merge": rows, "edge_sort_ms": sorts}
+        del em, prep, edges
+        torch.cuda.empty_cache()
+    # random-gather rate (lines per second) by table size and element width
+    gather = {}
+    sink = torch.empty(1, dtype=torch.int64, device=dev)
+    count = 1 << 27
+    for mb in (0.03125, 2, 4, 8, 32, 256, 2048):
+        table = torch.ones(int(mb * (1 << 20)) // 4, dtype=torch.int32, device=dev)
+        row = {}
+        for eb in (4, 8, 16):
+            ms = _time(lambda: ab.gather_async(table, eb, count, 7, sink))
+            row[f"{eb}B"] = round(count / (ms * 1e-3) / 1e9, 1)
+        gather[f"{mb:g}MB"] = row
+        del table
+    out["gather_G_per_s"] = gather
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -353,6 +477,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat23", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="count with the library's default options instead of tuning them")
+    ap.add_argument("--options", default=None,
+                    help="JSON dict of tc_options fields to count with (no tuning)")
     ap.add_argument("--no-pcie", action="store_true",
                     help="skip the PCIe-inclusive runs (profiling: one counting launch per step)")
     ap.add_argument("--no-batched", action="store_true",
@@ -368,6 +496,10 @@ def main():
                     help="skip the serving trace (profiling runs)")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--ablation", action="store_true",
+                    help="only run the yardstick: the paper's thread-per-edge merge and its "
+                         "Section 3.4 variants at R-MAT scales 20 and 23, edge sorts, and the "
+                         "random-gather rate of the chip")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run three plain 1 GiB device-to-device copies (counter scale)")
     args = ap.parse_args()
@@ -394,6 +526,9 @@ def main():
         print(json.dumps({"serve": serve_section(dev, args.serve_seconds, args.serve_rate)}),
               flush=True)
         return
+    if args.ablation:
+        print(json.dumps({"ablation": ablation_section(dev)}), flush=True)
+        return
     if args.batched_only:
         print(json.dumps({"batched": batched_section(dev, args.steps, args.batched_graphs,
                                                      not args.no_loop)}), flush=True)
@@ -405,7 +540,22 @@ def main():
     m = int(edges.shape[0])
     log(f"n={n} m={m} generated in {time.perf_counter() - t0:.1f} s")
 
-    ws = api.alloc_workspace(n, m, False, dev)
+    # the counting-phase options: given, or picked by the autotuner on this graph
+    if args.options:
+        opts = json.loads(args.options)
+        tuning = {"source": "given", "options": opts}
+    elif args.no_tune:
+        opts, tuning = None, {"source": "library defaults", "options": api.default_options()}
+    else:
+        from paper_1503_00576_amd import autotune
+        log("tuning the counting-phase options")
+        opts, timings = autotune.tune_single(edges, n)
+        tuning = {"source": "autotune.tune_single on this graph", "options": opts,
+                  "timings_ms": [[t, round(ms, 3)] for t, ms in timings]}
+        torch.cuda.empty_cache()
+        log(f"tuned: {opts}")
+    op = api._opts(opts)
+    ws = api.alloc_workspace(n, m, False, dev, opts)
     out = api.Result(torch.empty(1, dtype=torch.int64, device=dev),
                      torch.empty(1, dtype=torch.int32, device=dev))
     L = api._native.lib()
@@ -414,9 +564,9 @@ def main():
     wsz = ws.numel()
 
     def step():
-        api._raise(L.tc_preprocess(api._ptr(edges), n, m, 0, None, api._ptr(ws), wsz, sp, None),
+        api._raise(L.tc_preprocess(api._ptr(edges), n, m, 0, op, api._ptr(ws), wsz, sp, None),
                    "tc_preprocess")
-        api._raise(L.tc_count_prepared(n, m, 0, None, api._ptr(ws), wsz, sp, api._ptr(out.total),
+        api._raise(L.tc_count_prepared(n, m, 0, op, api._ptr(ws), wsz, sp, api._ptr(out.total),
                                        None, api._ptr(out.status)), "tc_count_prepared")
 
     for i in range(args.warmup):
@@ -436,10 +586,10 @@ def main():
     t0 = time.perf_counter()
     for i in range(args.steps):
         ev[i][0].record(stream)
-        api._raise(L.tc_preprocess(api._ptr(edges), n, m, 0, None, api._ptr(ws), wsz, sp, None),
+        api._raise(L.tc_preprocess(api._ptr(edges), n, m, 0, op, api._ptr(ws), wsz, sp, None),
                    "tc_preprocess")
         ev[i][1].record(stream)
-        api._raise(L.tc_count_prepared(n, m, 0, None, api._ptr(ws), wsz, sp, api._ptr(out.total),
+        api._raise(L.tc_count_prepared(n, m, 0, op, api._ptr(ws), wsz, sp, api._ptr(out.total),
                                        None, api._ptr(out.status)), "tc_count_prepared")
         ev[i][2].record(stream)
     torch.cuda.synchronize()
@@ -462,11 +612,11 @@ def main():
     # graph statistics for the roofline: wedges of the oriented graph W = sum_u C(d+(u), 2)
     # (one membership test each in the middle-vertex formulation), and the elements the
     # kernel actually streams (panels merge the tests of 32 middle vertices)
-    prep = api.Prepared(edges, n)
+    prep = api.Prepared(edges, n, options=opts)
     arrs = prep.arrays()
     dplus = (arrs["row_ptr"][1:] - arrs["row_ptr"][:-1]).to(torch.int64)
     wedges = int((dplus * (dplus - 1) // 2).sum().item())
-    p0 = n - min(api.default_options()["panel_ranks"], n)
+    p0 = n - min(dict(api.default_options(), **(opts or {}))["panel_ranks"], n)
     streamed, segments = streamed_elements(arrs["row_ptr"], arrs["col"], p0)
     del arrs, prep, dplus
     torch.cuda.empty_cache()
@@ -508,7 +658,7 @@ def main():
              for _ in range(3)]
     for a, b in pv_ev:
         a.record(stream)
-        api._raise(L.tc_count_prepared(n, m, 0, None, api._ptr(ws), wsz, sp, api._ptr(out.total),
+        api._raise(L.tc_count_prepared(n, m, 0, op, api._ptr(ws), wsz, sp, api._ptr(out.total),
                                        api._ptr(pv_out), api._ptr(out.status)),
                    "tc_count_prepared")
         b.record(stream)
@@ -522,7 +672,7 @@ def main():
     # the one-shot call (preprocessing without panels + per-vertex counting)
     for a, b in pv_ev:
         a.record(stream)
-        api._raise(L.tc_count_per_vertex(api._ptr(edges), n, m, 0, None, api._ptr(ws), wsz, sp,
+        api._raise(L.tc_count_per_vertex(api._ptr(edges), n, m, 0, op, api._ptr(ws), wsz, sp,
                                          api._ptr(out.total), api._ptr(pv_out),
                                          api._ptr(out.status)), "tc_count_per_vertex")
         b.record(stream)
@@ -540,7 +690,7 @@ def main():
 
     pcie_inclusive = None
     if not args.no_pcie:
-        pcie_inclusive = pcie_section(edges, n, m, total, ws, out, L, sp)
+        pcie_inclusive = pcie_section(edges, n, m, total, ws, out, L, sp, op)
         log(f"PCIe-inclusive step: {pcie_inclusive['ms']:.3f} ms")
 
     res = {
@@ -554,6 +704,7 @@ def main():
         "config": {"workload": WORKLOADS[args.workload]["label"], "n": n, "m": m,
                    "triangles": total, "golden_match": golden_ok, "wedges": wedges,
                    "parallelism": "single GPU"},
+        "tuning": tuning,
         "count_kernel_intersections_per_s": m / (count_ms * 1e-3),
         "stages_ms": {"preprocess": round(pre_ms, 4), "count": round(count_ms, 4)},
         "step_ms": step_stats,

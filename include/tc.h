@@ -174,12 +174,15 @@ int tc_count_noalloc(const int32_t *d_edges, int64_t n, int64_t m, uint32_t flag
  *   perm     uint32[n]    perm[r] = the vertex of rank r in the order (degree, id)
  *   rank     uint32[n]    rank[v] = position of v in that order (inverse of perm)
  *   row_ptr  uint32[n+1]  node array of the oriented graph, rows indexed by rank
- *   col      uint32[m_fwd] forward neighbours by rank, every row strictly ascending
+ *   col      uint32[m_fwd] forward neighbours by rank, every row strictly ascending, followed
+ *            by at least 16 entries of padding
+ *   src      uint32[m_fwd] the row (source rank) of every entry of col
  *   m_fwd    number of oriented edges (m for TC_EDGES_ONCE, m/2 for TC_EDGES_BOTH) */
 typedef struct tc_layout {
     size_t deg, perm, rank, row_ptr, col;
     int64_t m_fwd;
     int32_t id_bits; /* b = bits per packed vertex id in the sort keys */
+    size_t src;
 } tc_layout;
 
 int tc_workspace_layout(int64_t n, int64_t m, uint32_t flags, const tc_options *opts,

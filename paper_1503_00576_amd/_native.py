@@ -29,7 +29,8 @@ class TcOptions(ctypes.Structure):
 class TcLayout(ctypes.Structure):
     _fields_ = [("deg", ctypes.c_size_t), ("perm", ctypes.c_size_t), ("rank", ctypes.c_size_t),
                 ("row_ptr", ctypes.c_size_t), ("col", ctypes.c_size_t),
-                ("m_fwd", ctypes.c_int64), ("id_bits", ctypes.c_int32)]
+                ("m_fwd", ctypes.c_int64), ("id_bits", ctypes.c_int32),
+                ("src", ctypes.c_size_t)]
 
 
 _lib = None

@@ -198,7 +198,8 @@ class Prepared:
 
         return {"deg": view(lay.deg, self.n), "perm": view(lay.perm, self.n),
                 "rank": view(lay.rank, self.n), "row_ptr": view(lay.row_ptr, self.n + 1),
-                "col": view(lay.col, lay.m_fwd), "id_bits": lay.id_bits}
+                "col": view(lay.col, lay.m_fwd), "src": view(lay.src, lay.m_fwd),
+                "col_padded": view(lay.col, lay.m_fwd + 16), "id_bits": lay.id_bits}
 
 
 def preprocess(edges: torch.Tensor, n: int, both: bool = False,

@@ -25,9 +25,18 @@ FLAGS = [
 ]
 
 
+# the yardstick kernels for the ablation of the paper's own design (not the counting path)
+ABLATION_SOURCES = ["ablation.hip"]
+ABLATION_LIB = os.path.join(HERE, "libtc_ablation.so")
+
+
 def build(verbose: bool = False, extra: tuple[str, ...] = ()) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
+    _compile([os.path.join(CSRC, s) for s in ABLATION_SOURCES], ABLATION_LIB, verbose, extra)
+    return _compile([os.path.join(CSRC, s) for s in SOURCES], LIB, verbose, extra)
+
+
+def _compile(srcs, lib, verbose, extra) -> str:
+    tmp = lib + ".tmp"
     cmd = [HIPCC, *FLAGS, *extra, *srcs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
@@ -39,8 +48,8 @@ def build(verbose: bool = False, extra: tuple[str, ...] = ()) -> str:
         print(err, file=sys.stderr)
     if r.returncode != 0:
         raise subprocess.CalledProcessError(r.returncode, cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -634,6 +634,7 @@ int tc_workspace_layout(int64_t n, int64_t m, uint32_t flags, const tc_options *
     out->rank = L.rank;
     out->row_ptr = L.row_ptr;
     out->col = L.col;
+    out->src = L.src;
     out->m_fwd = L.mf;
     out->id_bits = (int32_t)L.id_bits;
     return TC_OK;

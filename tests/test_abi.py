@@ -159,3 +159,30 @@ def test_options(lib):
     assert api.workspace_size(1000, 9000, options={"wave_item_edges": 16}) > base
     with pytest.raises(KeyError):
         api._opts({"bogus": 1})
+
+
+def ablation_header_functions():
+    src = open(os.path.join(ROOT, "include", "tc_ablation.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tca_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_ablation_library_exports_and_validation():
+    from paper_1503_00576_amd import ablation, api
+    L = ablation.lib()
+    names = ablation_header_functions()
+    assert names == sorted(ablation.EXPORTS)
+    for name in names:
+        assert hasattr(L, name), name
+    fake = ctypes.c_void_p(0x1000)
+    out = ctypes.c_void_p(0x2000)
+    # bad shapes and flags are rejected before anything is enqueued
+    assert L.tca_edge_merge(fake, fake, fake, fake, None, 10, 0, 96, 1, out, None) == api.E_ARG
+    assert L.tca_edge_merge(fake, fake, fake, fake, None, 10, 16, 64, 1, out, None) == api.E_ARG
+    assert L.tca_edge_merge(fake, fake, fake, fake, None, 10, 0, 64, 0, out, None) == api.E_ARG
+    assert L.tca_edge_merge(fake, fake, fake, fake, None, 10, ablation.AOS, 64, 1, out,
+                            None) == api.E_ARG
+    assert L.tca_sort(3, 10, 8, fake, fake, fake, fake, fake, 1 << 20, None) == api.E_ARG
+    assert L.tca_sort(0, 10, 33, fake, fake, fake, fake, fake, 1 << 20, None) == api.E_ARG
+    assert L.tca_gather(fake, 1 << 20, 12, 10, 0, out, None) == api.E_ARG
+    assert L.tca_gather(fake, 2, 4, 10, 0, out, None) == api.E_ARG

@@ -326,3 +326,23 @@ def test_batch4096_golden():
     torch.cuda.synchronize()
     assert res2.totals.cpu().tolist() == ref["totals"]
     plan.close()
+
+
+def test_autotune_batched(tmp_path):
+    """The batched tuner (chunk size, heavy item size, light/heavy threshold) returns one of
+    its candidates, which counts exactly, and caches it by device, sizes and degree profile."""
+    from paper_1503_00576_amd import autotune
+    gs = mixed_graphs(10, 16)
+    want = oracle_per_graph(gs)
+    b = as_batch(synth.pack_symmetric(gs))
+    cands = [{"chunk_e": 256, "items_k": 64, "light_max": 64},
+             {"chunk_e": 1024, "items_k": 256, "light_max": 256}]
+    cache = str(tmp_path / "tune.json")
+    best, timings = autotune.tune_batched(b, reps=1, cache=cache, candidates=cands)
+    assert best in cands and len(timings) == 2
+    plan = api.BatchPlan(b.G, b.n_total, b.adj_total, best, device=DEV)
+    res = plan.run_async(b, per_vertex=True)
+    torch.cuda.synchronize()
+    check(res, gs, want)
+    plan.close()
+    assert autotune.tune_batched(b, cache=cache, candidates=cands[:1])[0] == best

@@ -426,3 +426,20 @@ def test_rmat23_full_size():
     q = rng.choice(cand, size=min(64, cand.size), replace=False)
     want = oracle.vertex_triangles(e.cpu().numpy(), n, q)
     assert np.array_equal(pvh[q].astype(np.uint64), want)
+
+
+def test_autotune_single(tmp_path):
+    """The single-graph tuner times its candidates on the caller's graph, returns one of them,
+    counts exactly with it, and answers later calls of the same size class from its cache."""
+    from paper_1503_00576_amd import autotune
+    e, n = synth.rmat_graph(13, 16, seed=14, device=DEV)
+    want = oracle.count(e.cpu().numpy(), n)
+    cands = [{"panel_ranks": 0, "wave_item_edges": 256, "block_item_edges": 4096},
+             {"panel_ranks": 2048, "wave_item_edges": 512, "block_item_edges": 16384},
+             {"panel_ranks": 8192, "wave_item_edges": 1024, "block_item_edges": 65536}]
+    cache = str(tmp_path / "tune.json")
+    best, timings = autotune.tune_single(e, n, reps=1, cache=cache, candidates=cands)
+    assert best in cands and len(timings) == 3 and all(ms > 0 for _, ms in timings)
+    assert api.count(e, n, options=best) == want
+    again, _ = autotune.tune_single(e, n, cache=cache, candidates=cands[:1])
+    assert again == best
