@@ -214,6 +214,86 @@ size_t tc_sort_workspace_size(int64_t count);
 int tc_sort_u64(uint64_t *d_keys, uint64_t *d_tmp, int64_t count, int32_t bits, void *d_ws,
                 size_t ws_bytes, void *stream);
 
+/* ---------------------------------------------------------------- graphs beyond the GPU
+ *
+ * Two extensions for graphs whose working set does not fit in device memory.
+ *
+ * The host pre-pass of Section 3.4 ("CPU preprocessing for very large graphs"): for
+ * two-direction input (TC_EDGES_BOTH) the host computes the degrees and drops the backward
+ * entries, so that only half of the array ever reaches the device.
+ *
+ * Subgraph splitting (the direction Section 6 proposes for graphs that do not fit the GPU),
+ * as an exact partition scheme.  The vertices are cut into K parts by a hash of their ids;
+ * E_xy (x <= y) are the edges between parts x and y.  The subgraphs G_abc = E_ab + E_ac + E_bc
+ * (a < b < c), G_ac = E_aa + E_ac + E_cc (a < c) and E_aa are ordinary graphs counted one after
+ * another by tc_count (tc_count_per_vertex) on the device, and
+ *     T = sum T(G_abc) + sum T(G_ac) - (K - 2) * sum T(E_aa)      (K >= 2; K = 1: T(E_00)),
+ * the same identity holding vertex by vertex.  A subgraph holds about 6m/K^2 edges, so the
+ * device working set shrinks about K^2/6 times; the edges cross the host-device link about
+ * K + 2 times in all.
+ *
+ * Usage: tc_split_prepare (host only: checks, pre-filter, partition, edges bucketed by block
+ * into the host workspace), then tc_split_count (device).  The host workspace must stay
+ * unchanged and alive until the device work of tc_split_count has finished; it should be
+ * pinned (hipHostMalloc) for the copies to overlap the counting. */
+#define TC_SPLIT_MAX_PARTS 64u
+
+typedef struct tc_split_info {
+    uint32_t parts;       /* K */
+    uint32_t subgraphs;   /* subgraphs with at least one edge (the ones counted) */
+    int64_t m_kept;       /* undirected edges kept: m, or m/2 for TC_EDGES_BOTH */
+    int64_t max_sub_n;    /* largest subgraph: vertices */
+    int64_t max_sub_m;    /*                   edges */
+    size_t device_bytes;  /* device workspace tc_split_count needs */
+    size_t host_bytes;    /* host workspace in use */
+} tc_split_info;
+
+/* Host workspace bytes for a graph of n vertices and m entries (enough for any K). */
+size_t tc_split_host_workspace_size(int64_t n, int64_t m, uint32_t flags);
+
+/* Host pass over the edge array:
+ *   h_edges      : int32[2*m] in host memory, the format of tc_count (flags as there)
+ *   parts        : K in 1..TC_SPLIT_MAX_PARTS, or 0 = the smallest K (never 2, which splits
+ *                  nothing) whose device workspace is at most device_budget bytes
+ *   opts         : the options the subgraphs will be counted with (they size the workspace)
+ *   h_ws         : at least tc_split_host_workspace_size(n, m, flags) bytes, 64-byte aligned
+ *   info         : nullable; receives K, the subgraph count and the device bytes needed
+ * Data errors are found here, on the host, and returned directly: TC_E_RANGE, TC_E_SELF_LOOP,
+ * TC_E_ASYMMETRIC (two-direction input whose forward entries are not exactly half).  A
+ * repeated edge lands in one block and is reported by the device count (TC_E_DUP_EDGE).
+ * TC_E_TOO_LARGE: no K fits the budget (or a subgraph exceeds tc_count's limits).
+ * Multi-threaded; touches no GPU. */
+int tc_split_prepare(const int32_t *h_edges, int64_t n, int64_t m, uint32_t flags,
+                     uint32_t parts, size_t device_budget, const tc_options *opts, void *h_ws,
+                     size_t h_ws_bytes, tc_split_info *info);
+
+/* Triangle count (and per-vertex counts) of the graph prepared in h_ws, on the device.
+ *   d_ws        : at least info.device_bytes, 256-byte aligned
+ *   stream      : the counting stream; copy_stream: nullable, a second stream for the
+ *                 host-to-device copies of the next subgraph while one is counted (the call
+ *                 makes `stream` wait for it at the end)
+ *   d_total     : uint64[1]; d_per_vertex: uint64[n] or NULL; d_status: int32[1] or NULL
+ *                 (the first data error of any subgraph's count)
+ *   opts        : the options given to tc_split_prepare (TC_E_WORKSPACE when they need more)
+ * Only enqueues work. */
+int tc_split_count(const void *h_ws, const tc_options *opts, void *d_ws, size_t d_ws_bytes,
+                   void *stream, void *copy_stream, uint64_t *d_total, uint64_t *d_per_vertex,
+                   int32_t *d_status);
+
+/* Inspection of a prepared split (host only, for tests and tools). */
+typedef struct tc_split_subgraph_info {
+    int64_t n, m;       /* local vertices (the parts' vertices) and edges */
+    int64_t coef;       /* +1, or -(K - 2) for a one-part subgraph E_aa */
+    uint32_t nparts;    /* 1..3 */
+    uint32_t parts[3];  /* ascending */
+} tc_split_subgraph_info;
+
+int tc_split_subgraph(const void *h_ws, uint32_t index, tc_split_subgraph_info *out);
+/* The subgraph's edge array with local ids (h_out: int32[2*m], nullable) and the global id of
+ * every local vertex (h_vertex: int32[n], nullable), exactly as tc_split_count counts it. */
+int tc_split_subgraph_edges(const void *h_ws, uint32_t index, int32_t *h_out,
+                            int32_t *h_vertex);
+
 /* ---------------------------------------------------------------- batched counting
  *
  * Many independent graphs counted by one launch sequence.  Input: the graphs' symmetric

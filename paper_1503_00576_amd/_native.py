@@ -14,7 +14,8 @@ EXPORTS = [
     "tc_workspace_layout", "tc_preprocess", "tc_count_prepared", "tc_sort_workspace_size",
     "tc_sort_u64", "tc_batched_workspace_size", "tc_batched_plan_create", "tc_batched_plan_run",
     "tc_batched_plan_destroy", "tc_count_batched", "tc_batched_pack_workspace_size",
-    "tc_batched_pack",
+    "tc_batched_pack", "tc_split_host_workspace_size", "tc_split_prepare", "tc_split_count",
+    "tc_split_subgraph", "tc_split_subgraph_edges",
 ]
 
 
@@ -31,6 +32,20 @@ class TcLayout(ctypes.Structure):
                 ("row_ptr", ctypes.c_size_t), ("col", ctypes.c_size_t),
                 ("m_fwd", ctypes.c_int64), ("id_bits", ctypes.c_int32),
                 ("src", ctypes.c_size_t)]
+
+
+class TcSplitInfo(ctypes.Structure):
+    """struct tc_split_info (include/tc.h)."""
+    _fields_ = [("parts", ctypes.c_uint32), ("subgraphs", ctypes.c_uint32),
+                ("m_kept", ctypes.c_int64), ("max_sub_n", ctypes.c_int64),
+                ("max_sub_m", ctypes.c_int64), ("device_bytes", ctypes.c_size_t),
+                ("host_bytes", ctypes.c_size_t)]
+
+
+class TcSplitSubgraph(ctypes.Structure):
+    """struct tc_split_subgraph_info (include/tc.h)."""
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("coef", ctypes.c_int64),
+                ("nparts", ctypes.c_uint32), ("parts", ctypes.c_uint32 * 3)]
 
 
 _lib = None
@@ -85,5 +100,16 @@ def lib():
     L.tc_batched_pack_workspace_size.restype = sz
     L.tc_batched_pack.argtypes = [i32, vp, vp, vp, i64, i64, vp, sz, vp, vp, vp, vp, vp]
     L.tc_batched_pack.restype = ctypes.c_int
+    L.tc_split_host_workspace_size.argtypes = [i64, i64, u32]
+    L.tc_split_host_workspace_size.restype = sz
+    L.tc_split_prepare.argtypes = [vp, i64, i64, u32, u32, sz, op, vp, sz,
+                                   ctypes.POINTER(TcSplitInfo)]
+    L.tc_split_prepare.restype = ctypes.c_int
+    L.tc_split_count.argtypes = [vp, op, vp, sz, vp, vp, vp, vp, vp]
+    L.tc_split_count.restype = ctypes.c_int
+    L.tc_split_subgraph.argtypes = [vp, u32, ctypes.POINTER(TcSplitSubgraph)]
+    L.tc_split_subgraph.restype = ctypes.c_int
+    L.tc_split_subgraph_edges.argtypes = [vp, u32, vp, vp]
+    L.tc_split_subgraph_edges.restype = ctypes.c_int
     _lib = L
     return L

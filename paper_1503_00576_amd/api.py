@@ -225,6 +225,113 @@ def sort_u64(keys: torch.Tensor, bits: int) -> torch.Tensor:
     return keys
 
 
+# ------------------------------------------------------------------ graphs beyond the GPU
+
+def _host_edges(edges):
+    """int32 [m, 2] edges in host memory as a contiguous numpy array."""
+    import numpy as np
+    if isinstance(edges, torch.Tensor):
+        if edges.is_cuda:
+            raise TypeError("split counting takes the edge array in host memory")
+        edges = edges.numpy()
+    a = np.ascontiguousarray(edges)
+    if a.dtype != np.int32 or a.ndim != 2 or (a.size and a.shape[1] != 2):
+        raise TypeError("edges must be int32 [m, 2]")
+    return a
+
+
+class Split:
+    """A graph prepared for counting in subgraphs (tc_split_prepare: host only).  The edges
+    stay in host memory; the host workspace holds them bucketed by block of the vertex
+    partition and is pinned when a GPU is present, so that tc_split_count's copies overlap
+    the counting.  parts = 0 picks the smallest number of parts whose device workspace fits
+    device_budget bytes (default: 90% of the free device memory)."""
+
+    def __init__(self, edges, n: int, both: bool = False, parts: int = 0,
+                 device_budget: int | None = None, options: dict | None = None,
+                 pin: bool | None = None):
+        e = _host_edges(edges)
+        self.n, self.m, self.both = int(n), int(e.shape[0]), bool(both)
+        self.options = dict(options) if options else None
+        L = _native.lib()
+        hsz = L.tc_split_host_workspace_size(self.n, self.m, _flags(self.both))
+        if hsz == 0:
+            raise TCError(E_ARG, "tc_split_host_workspace_size")
+        if pin is None:
+            pin = torch.cuda.is_available()
+        self.host_ws = torch.empty(hsz + 64, dtype=torch.uint8, pin_memory=bool(pin))
+        # 64-byte alignment inside the buffer
+        skip = (-self.host_ws.data_ptr()) % 64
+        self.host_ws = self.host_ws[skip: skip + hsz]
+        if parts == 0 and device_budget is None:
+            free, _ = torch.cuda.mem_get_info()
+            device_budget = int(free * 0.9)
+        info = _native.TcSplitInfo()
+        _raise(L.tc_split_prepare(e.ctypes.data_as(ctypes.c_void_p) if e.size else None,
+                                  self.n, self.m, _flags(self.both), int(parts),
+                                  int(device_budget or 0), _opts(self.options),
+                                  _ptr(self.host_ws), hsz, ctypes.byref(info)),
+               "tc_split_prepare")
+        self.info = {k: int(getattr(info, k)) for k, _ in info._fields_}
+
+    def subgraph(self, i: int):
+        """(info dict, local edge array int32 [m_i, 2], global id of every local vertex) of
+        subgraph i, exactly as the device counts it."""
+        import numpy as np
+        L = _native.lib()
+        si = _native.TcSplitSubgraph()
+        _raise(L.tc_split_subgraph(_ptr(self.host_ws), int(i), ctypes.byref(si)),
+               "tc_split_subgraph")
+        d = {"n": si.n, "m": si.m, "coef": si.coef, "parts": list(si.parts)[: si.nparts]}
+        e = np.empty((si.m, 2), dtype=np.int32)
+        v = np.empty(si.n, dtype=np.int32)
+        _raise(L.tc_split_subgraph_edges(_ptr(self.host_ws), int(i),
+                                         e.ctypes.data_as(ctypes.c_void_p),
+                                         v.ctypes.data_as(ctypes.c_void_p)),
+               "tc_split_subgraph_edges")
+        return d, e, v
+
+    def count_async(self, device=None, per_vertex: bool = False, overlap: bool = True,
+                    workspace: torch.Tensor | None = None) -> Result:
+        """Enqueue tc_split_count on the device's current stream (the copies on a second
+        stream when overlap is set)."""
+        dev = torch.device(device if device is not None else "cuda")
+        ws = workspace if workspace is not None else torch.empty(
+            max(self.info["device_bytes"], 256), dtype=torch.uint8, device=dev)
+        out = Result(torch.empty(1, dtype=torch.int64, device=dev),
+                     torch.empty(1, dtype=torch.int32, device=dev),
+                     torch.empty(self.n, dtype=torch.int64, device=dev) if per_vertex else None)
+        cs = None
+        if overlap:
+            self._copy_stream = torch.cuda.Stream(dev)  # default priority
+            cs = ctypes.c_void_p(self._copy_stream.cuda_stream)
+        _raise(_native.lib().tc_split_count(
+            _ptr(self.host_ws), _opts(self.options), _ptr(ws), ws.numel(), _stream(dev), cs,
+            _ptr(out.total), _ptr(out.per_vertex) if per_vertex else None, _ptr(out.status)),
+            "tc_split_count")
+        out.workspace = ws  # kept until the work has run
+        return out
+
+    def count(self, device=None, overlap: bool = True) -> int:
+        return int(self.count_async(device, overlap=overlap).check().total.item()) & \
+            0xFFFFFFFFFFFFFFFF
+
+    def count_per_vertex(self, device=None, overlap: bool = True):
+        r = self.count_async(device, per_vertex=True, overlap=overlap).check()
+        return int(r.total.item()) & 0xFFFFFFFFFFFFFFFF, r.per_vertex
+
+
+def count_split(edges, n: int, both: bool = False, parts: int = 0,
+                device_budget: int | None = None, per_vertex: bool = False,
+                options: dict | None = None, device=None):
+    """Triangle count of a graph held in host memory, counted in subgraphs that fit the
+    device (tc_split_prepare + tc_split_count).  Returns the total, or (total, per-vertex)."""
+    sp = Split(edges, n, both, parts, device_budget, options)
+    if per_vertex:
+        return sp.count_per_vertex(device)
+    return sp.count(device)
+
+
 # ------------------------------------------------------------------ derived quantities
 
 def clustering(per_vertex, degree):

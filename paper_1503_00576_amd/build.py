@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtc.so")
-SOURCES = ["sort.hip", "prep.hip", "count.hip", "hub.hip", "api.hip", "batched.hip", "pack.hip"]
+SOURCES = ["sort.hip", "prep.hip", "count.hip", "hub.hip", "api.hip", "batched.hip", "pack.hip",
+           "split.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
