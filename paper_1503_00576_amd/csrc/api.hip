@@ -87,7 +87,7 @@ struct Layout {
 // two item queues, the fingerprint of the prepared layout, status of the current count
 enum {
     kCtlStatus = 0, kCtlBoth = 1, kCtlQueueA = 2, kCtlQueueB = 3, kCtlFinger = 4, kCtlRun = 5,
-    kCtlWords = 64
+    kCtlQueueC = 6, kCtlWords = 64
 };
 // start of a preprocessing: clear the control words and record the layout's fingerprint
 __global__ void k_ctl_init(uint32_t *__restrict__ ctl, uint32_t finger) {
@@ -104,6 +104,7 @@ __global__ void k_ctl_check(uint32_t *__restrict__ ctl, uint32_t finger) {
     ctl[kCtlRun] = (uint32_t)st;
     ctl[kCtlQueueA] = 0;
     ctl[kCtlQueueB] = 0;
+    ctl[kCtlQueueC] = 0;
 }
 
 constexpr uint32_t kPartTileEdges = 4096;  // edges per tile of the degree partition
@@ -172,10 +173,10 @@ static int id_bits_for64(uint64_t x) {
     return b;
 }
 
-// panels = false: no panel region (every middle vertex has its own in-edge list), which needs
-// no more workspace than the default layout (only the panel range table shrinks)
+// panel_cap: at most this many panel ranks whatever the options say (a smaller panel region
+// needs no more workspace than the default layout: only the panel range table shrinks)
 static bool make_layout(int64_t n, int64_t m, uint32_t flags, const tc_options *opts, Layout &L,
-                        bool panels = true) {
+                        uint32_t panel_cap = ~0u) {
     if (n < 0 || m < 0 || n >= (1ll << 31) || m >= (1ll << 32)) return false;
     if (flags & ~TC_EDGES_BOTH) return false;
     if (!resolve_options(opts, L.opt)) return false;
@@ -188,8 +189,9 @@ static bool make_layout(int64_t n, int64_t m, uint32_t flags, const tc_options *
     // row blocks: at most what 32-bit list ids (block * (n + 1) + v) allow
     L.nblk = o.row_blocks;
     while (L.nblk > 1 && (uint64_t)L.nblk * ((uint64_t)n + 1) >= (1ull << 32)) --L.nblk;
-    const uint32_t pr = o.panel_ranks < L.n ? o.panel_ranks : L.n;
-    L.p0 = panels ? L.n - pr : L.n;
+    uint32_t pr = o.panel_ranks < panel_cap ? o.panel_ranks : panel_cap;
+    pr = pr < L.n ? pr : L.n;
+    L.p0 = L.n - pr;
     {
         const uint32_t h = o.hub_ranks < L.n ? o.hub_ranks : L.n;
         L.h0 = L.n - h;
@@ -302,13 +304,13 @@ static inline uint32_t grid_for(uint64_t items, uint32_t threads, uint32_t cap =
 
 static int check_args(const int32_t *d_edges, int64_t n, int64_t m, uint32_t flags,
                       const tc_options *opts, void *d_ws, size_t ws_bytes, Layout &L,
-                      bool panels = true) {
+                      uint32_t panel_cap = ~0u) {
     if (n < 0 || m < 0 || (flags & ~TC_EDGES_BOTH)) return TC_E_ARG;
     if (n >= (1ll << 31) || m >= (1ll << 32)) return TC_E_TOO_LARGE;
     if (n == 0 && m > 0) return TC_E_ARG;
     if (m > 0 && (!d_edges || ((uintptr_t)d_edges & 7))) return TC_E_ARG;
     if ((flags & TC_EDGES_BOTH) && (m & 1)) return TC_E_ASYMMETRIC;
-    if (!make_layout(n, m, flags, opts, L, panels)) return TC_E_ARG;
+    if (!make_layout(n, m, flags, opts, L, panel_cap)) return TC_E_ARG;
     if (!d_ws || ((uintptr_t)d_ws & 255) || ws_bytes < L.total_bytes) return TC_E_WORKSPACE;
     return TC_OK;
 }
@@ -509,6 +511,7 @@ static int run_count_prepared(void *ws, const Layout &L, hipStream_t s, uint64_t
         a.n_items_b = a.item_off_b + L.lists;
         a.queue_a = ctl + kCtlQueueA;
         a.queue_b = ctl + kCtlQueueB;
+        a.queue_c = ctl + kCtlQueueC;
         a.total = total;
         a.tpv = tpv;
         a.n1 = n + 1;
@@ -542,14 +545,15 @@ static int copy_status(void *ws, const Layout &L, int32_t *d_status, hipStream_t
     return TC_OK;
 }
 
-// Preprocessing and counting in one call.  With per-vertex counts the graph is prepared
-// without panels: a panel's list merges the in-edges of 32 middle vertices, which per-vertex
-// counts would split again one panel vertex at a time (83 vs 150 ms at R-MAT scale 23).
+// Preprocessing and counting in one call.  With per-vertex counts the panel region is capped
+// at what the per-vertex panel kernel holds in LDS (a wider panel would be counted one panel
+// vertex at a time).
 static int run_count(const int32_t *d_edges, int64_t n, int64_t m, uint32_t flags,
                      const tc_options *opts, void *ws, size_t ws_bytes, hipStream_t s,
                      uint64_t *d_total, uint64_t *d_pv, int32_t *d_status) {
     Layout L;
-    int st = check_args(d_edges, n, m, flags, opts, ws, ws_bytes, L, d_pv == nullptr);
+    int st = check_args(d_edges, n, m, flags, opts, ws, ws_bytes, L,
+                        d_pv == nullptr ? ~0u : count_pv_panel_ranks());
     if (st) return st;
     if (!d_total) return TC_E_ARG;
     st = run_preprocess(d_edges, flags, ws, L, s);

@@ -48,6 +48,15 @@ constexpr uint32_t kItemEdgesWave = 512;     // default in-edges per wave item
 constexpr uint32_t kItemEdgesBlock = 16384;  // default in-edges per workgroup item
 constexpr uint32_t kPanel = 32;                       // one bit per panel vertex in a mask
 constexpr uint32_t kPanelRanks = kLdsWords - 32;      // mask table: one word per rank
+// per-vertex counts over a panel keep a third-vertex counter beside every mask word, so the
+// panel's rank span must fit half of the workgroup's LDS
+constexpr uint32_t kPvPanelWords = kLdsWords / 2;
+constexpr uint32_t kPvPanelRanks = kPvPanelWords - 32;
+// the panel starting at rank P (of n1 - 1 ranks) has its mask table and counters in LDS:
+// words 0 .. n1 - P - 1, the last one always zero
+__device__ __forceinline__ bool pv_panel_fits(uint32_t P, uint32_t n1) {
+    return n1 - P <= kPvPanelWords;
+}
 // batched kernel: rows with at most kLightMax forward entries are counted edge by edge; a
 // chunk of forward edges plus kLightMax entries on either side must fit one wave's slice
 constexpr uint32_t kLightMax = 256;
@@ -358,6 +367,237 @@ __device__ __forceinline__ ItemRange item_range(uint32_t q, uint32_t kitem, uint
     return it;
 }
 
+// ------------------------------------------------------------------ per-vertex panels
+//
+// Per-vertex counts over a panel P .. P+31 in one pass, with the panel table of the totals.
+// Element w of segment (u, panel) closes one triangle u -> P+j -> w for every bit j of
+// c = M[w] & R(u); each is credited three times:
+//   the first vertex u: popcount(c), summed per segment (one atomic per segment);
+//   the third vertex w: popcount(c) into an LDS counter beside M[w] (flushed once per item);
+//   the middle vertex P+j: bit j of c, summed per lane in bit-sliced counters (bit j of
+//   plane k is bit k of the count of panel vertex j), with a carry-save adder tree over the
+//   16 elements of a piece, and flushed once per item.
+
+// carry-save adder: (h, l) with 2h + l = l + b + c bitwise
+__device__ __forceinline__ void csa(uint32_t &h, uint32_t &l, uint32_t b, uint32_t c) {
+    const uint32_t u = l ^ b;
+    h = (l & b) | (u & c);
+    l = u ^ c;
+}
+
+// 32 counters (one per panel vertex) of one lane in bit slices: the count of vertex j is
+// ones_j + 2 twos_j + 4 fours_j + 8 eights_j + 16 * (sum_k hi[k]_j 2^k)
+struct MidCounters {
+    // counts up to 4095 per lane between flushes: a flush every 255 pieces costs a few percent
+    // of the pieces' work, and the largest panels reach it (the flush path runs in practice)
+    static constexpr int kHi = 8;
+    uint32_t ones, twos, fours, eights, hi[kHi];
+    __device__ __forceinline__ void clear() {
+        ones = twos = fours = eights = 0;
+#pragma unroll
+        for (int k = 0; k < kHi; ++k) hi[k] = 0;
+    }
+    // adds the 16 masks d[0..15] (Harley-Seal tree)
+    __device__ __forceinline__ void add16(const uint32_t (&d)[16]) {
+        uint32_t tA, tB, fA, fB, eA, eB, sx;
+        csa(tA, ones, d[0], d[1]);
+        csa(tB, ones, d[2], d[3]);
+        csa(fA, twos, tA, tB);
+        csa(tA, ones, d[4], d[5]);
+        csa(tB, ones, d[6], d[7]);
+        csa(fB, twos, tA, tB);
+        csa(eA, fours, fA, fB);
+        csa(tA, ones, d[8], d[9]);
+        csa(tB, ones, d[10], d[11]);
+        csa(fA, twos, tA, tB);
+        csa(tA, ones, d[12], d[13]);
+        csa(tB, ones, d[14], d[15]);
+        csa(fB, twos, tA, tB);
+        csa(eB, fours, fA, fB);
+        csa(sx, eights, eA, eB);
+        uint32_t carry = sx;
+#pragma unroll
+        for (int k = 0; k < kHi; ++k) {
+            const uint32_t t = hi[k] & carry;
+            hi[k] ^= carry;
+            carry = t;
+        }
+    }
+    __device__ __forceinline__ uint32_t count(uint32_t j) const {
+        uint32_t h = 0;
+#pragma unroll
+        for (int k = kHi - 1; k >= 0; --k) h = (h << 1) | ((hi[k] >> j) & 1u);
+        return ((ones >> j) & 1u) + 2u * ((twos >> j) & 1u) + 4u * ((fours >> j) & 1u) +
+               8u * ((eights >> j) & 1u) + 16u * h;
+    }
+    // wave sums into the workgroup's 32 middle-vertex counters, then restart
+    __device__ __forceinline__ void flush(unsigned long long *mid) {
+#pragma unroll 1
+        for (uint32_t j = 0; j < kPanel; ++j) {
+            const uint64_t s = wave_sum_u64(count(j));
+            if (lane_id() == 0 && s) atomicAdd(&mid[j], (unsigned long long)s);
+        }
+        clear();
+    }
+};
+// pieces one lane may add between flushes (16 per piece per counter, kHi + 4 bits)
+constexpr uint32_t kMidPieces = (1u << (MidCounters::kHi + 4)) / kPiece - 1;
+
+// The calling wave streams panel segments [eb, min(eb + 64, e1)) of the current item through
+// the mask table m (and third-vertex counters cnt3 at the same offsets) and returns this
+// lane's hits; `pieces` is the wave's bound on the pieces any lane added to mc since its last
+// flush.
+__device__ __forceinline__ uint32_t run_panel_pv(uint32_t eb, uint32_t e1,
+                                                 const uint32_t *__restrict__ cbeg,
+                                                 const uint32_t *__restrict__ cend,
+                                                 const uint32_t *__restrict__ cmask,
+                                                 const uint32_t *__restrict__ src,
+                                                 const uint32_t *__restrict__ col,
+                                                 const uint32_t *m, uint32_t *cnt3, uint32_t lo,
+                                                 uint32_t span, WaveScratch &ws,
+                                                 MidCounters &mc, uint32_t &pieces,
+                                                 unsigned long long *mid,
+                                                 unsigned long long *__restrict__ tpv) {
+    const uint32_t lane = lane_id();
+    const uint32_t e = eb + lane;
+    const bool valid = e < e1;
+    uint32_t b = 0, en = 0;
+    if (valid) {
+        b = cbeg[e];
+        en = cend[e];
+    }
+    const uint32_t a0 = b & ~3u;
+    const uint32_t p = (valid && en > b) ? (en - a0 + kPiece - 1) / kPiece : 0u;
+    const uint32_t incl = wave_incl_scan(p);
+    const uint32_t Q = wave_bcast(incl, kWave - 1);
+    ws.off[lane] = incl - p;
+    ws.beg[lane] = a0;
+    ws.first[lane] = b;
+    ws.end[lane] = en;
+    ws.cnt[lane] = 0;
+    ws.tag[lane] = valid ? cmask[e] : 0u;
+    ws.aux[lane] = valid ? src[b - 1] : 0u;  // u: its first panel vertex sits right before b
+    wave_lds_sync();
+    const uint32_t per_lane = (Q + kWave - 1) / kWave;
+    if (pieces + per_lane > kMidPieces) {
+        mc.flush(mid);
+        pieces = 0;
+    }
+    pieces += per_lane;
+    uint32_t hits_total = 0;
+    for (uint32_t q0 = 0; q0 < Q; q0 += kWave) {
+        const uint32_t q = q0 + lane;
+        uint32_t c[kPiece];
+#pragma unroll
+        for (uint32_t i = 0; i < kPiece; ++i) c[i] = 0;
+        if (q < Q) {
+            uint32_t k = 0;
+#pragma unroll
+            for (uint32_t step = 32; step; step >>= 1)
+                if (ws.off[k + step] <= q) k += step;
+            const uint32_t start = ws.beg[k] + (q - ws.off[k]) * kPiece;
+            const uint32_t first = ws.first[k], stop = ws.end[k];
+            const uint4 *p4 = reinterpret_cast<const uint4 *>(col + start);
+            uint32_t wv[kPiece];
+#pragma unroll
+            for (uint32_t j = 0; j < kPiece / 4; ++j) {
+                const uint4 x = p4[j];
+                wv[4 * j] = x.x;
+                wv[4 * j + 1] = x.y;
+                wv[4 * j + 2] = x.z;
+                wv[4 * j + 3] = x.w;
+            }
+            const uint32_t r = ws.tag[k];
+            const uint32_t lo_i = first > start ? first - start : 0u;
+            const uint32_t hi_i = min(stop - start, kPiece);
+            uint32_t hits = 0;
+#pragma unroll
+            for (uint32_t i = 0; i < kPiece; ++i) {
+                // an id outside the table clamps onto word span + 1, which is always zero
+                const uint32_t o = min(wv[i] - lo, span + 1u);
+                const uint32_t ci = (i >= lo_i && i < hi_i) ? (m[o] & r) : 0u;
+                c[i] = ci;
+                const uint32_t h = __popc(ci);
+                hits += h;
+                if (h) atomicAdd(&cnt3[o], h);
+            }
+            hits_total += hits;
+            if (hits) atomicAdd(&ws.cnt[k], hits);
+        }
+        mc.add16(c);
+    }
+    wave_lds_sync();
+    if (ws.cnt[lane]) atomicAdd(&tpv[ws.aux[lane]], (unsigned long long)ws.cnt[lane]);
+    wave_lds_sync();
+    return hits_total;
+}
+
+// Per-vertex counts of the panels whose table and counters fit the LDS (P + kPvPanelWords
+// > n): the workgroup items of those panels, from their own queue counter; every other item
+// is left to k_count<true>.
+__global__ __launch_bounds__(kThreads) void k_count_panel_pv(
+    const uint32_t *__restrict__ row_ptr, const uint32_t *__restrict__ col,
+    const uint32_t *__restrict__ cptr, const uint32_t *__restrict__ cbeg,
+    const uint32_t *__restrict__ cend, const uint32_t *__restrict__ src,
+    const uint32_t *__restrict__ cmask, const uint32_t *__restrict__ item_v_b,
+    const uint32_t *__restrict__ item_off_b, const uint32_t *__restrict__ n_items_b_ptr,
+    uint32_t *__restrict__ queue_c, unsigned long long *__restrict__ total,
+    unsigned long long *__restrict__ tpv, uint32_t n1, uint32_t p0, uint32_t kitem_b,
+    const int32_t *__restrict__ status) {
+    __shared__ uint32_t s_mem[kLdsWords];
+    __shared__ WaveScratch s_ws[kWaves];
+    __shared__ unsigned long long s_mid[kPanel];
+    __shared__ uint32_t s_item;
+    if (*status) return;
+    const uint32_t t = threadIdx.x, w = t / kWave, lane = lane_id();
+    WaveScratch &ws = s_ws[w];
+    uint32_t *m = s_mem, *cnt3 = s_mem + kPvPanelWords;
+    for (uint32_t i = t; i < kLdsWords; i += kThreads) s_mem[i] = 0;
+    if (t < kPanel) s_mid[t] = 0;
+    uint64_t acc = 0;
+    MidCounters mc;
+    mc.clear();
+    const uint32_t n_items_b = *n_items_b_ptr;
+    for (;;) {
+        __syncthreads();
+        if (t == 0) s_item = atomicAdd(queue_c, 1u);
+        __syncthreads();
+        uint32_t q = s_item;
+        if (q >= n_items_b) break;
+        q = n_items_b - 1 - q;
+        const ItemRange it = item_range(q, kitem_b, n1, item_v_b, item_off_b, cptr, row_ptr);
+        if (it.v < p0 || !pv_panel_fits(it.v, n1)) continue;  // left to k_count<true>
+        const uint32_t P = it.v, np = min(kPanel, n1 - 1 - P), span = n1 - 2 - P;
+        for (uint32_t j = w; j < np; j += kWaves)
+            for (uint32_t i = row_ptr[P + j] + lane; i < row_ptr[P + j + 1]; i += kWave)
+                atomicOr(&m[col[i] - P], 1u << j);
+        __syncthreads();
+        uint32_t cnt = 0, pieces = 0;
+        for (uint32_t eb = it.e0 + w * kWave; eb < it.e1; eb += kWaves * kWave)
+            cnt += run_panel_pv(eb, it.e1, cbeg, cend, cmask, src, col, m, cnt3, P, span, ws,
+                                mc, pieces, s_mid, tpv);
+        mc.flush(s_mid);
+        acc += cnt;
+        __syncthreads();
+        for (uint32_t j = w; j < np; j += kWaves)
+            for (uint32_t i = row_ptr[P + j] + lane; i < row_ptr[P + j + 1]; i += kWave)
+                m[col[i] - P] = 0;
+        for (uint32_t i = t; i <= span; i += kThreads) {
+            const uint32_t c3 = cnt3[i];
+            if (c3) {
+                atomicAdd(&tpv[P + i], (unsigned long long)c3);
+                cnt3[i] = 0;
+            }
+        }
+        if (t < np && s_mid[t]) {
+            atomicAdd(&tpv[P + t], s_mid[t]);
+            s_mid[t] = 0;
+        }
+    }
+    acc = wave_sum_u64(acc);
+    if (lane == 0 && acc) atomicAdd(total, (unsigned long long)acc);
+}
+
 // ------------------------------------------------------------------ the kernel
 
 template <bool PV>
@@ -411,8 +651,11 @@ __global__ __launch_bounds__(kThreads) void k_count(
                 for (uint32_t j = w; j < np; j += kWaves)
                     for (uint32_t i = row_ptr[P + j] + lane; i < row_ptr[P + j + 1]; i += kWave)
                         s_mem[col[i] - P] = 0;
+            } else if (pv_panel_fits(P, n1)) {
+                continue;  // counted by k_count_panel_pv
             } else {
-                for (uint32_t j = 0; j < np; ++j) {  // one panel vertex at a time
+                // a panel too wide for the per-vertex table: one panel vertex at a time
+                for (uint32_t j = 0; j < np; ++j) {
                     const uint32_t r0 = row_ptr[P + j], d = row_ptr[P + j + 1] - r0;
                     if (d == 0) continue;
                     const bool in_lds = d <= block_list;  // at most kBlockListPV
@@ -805,9 +1048,18 @@ uint32_t count_wgs_per_cu() { return kWgsPerCu; }
 uint32_t count_light_max() { return kLightMax; }
 uint32_t count_light_chunk_max() { return kLightChunkMax; }
 uint32_t count_panel_ranks() { return kPanelRanks; }
+uint32_t count_pv_panel_ranks() { return kPvPanelRanks; }
 
 hipError_t launch_count(const CountArgs &x, bool per_vertex, hipStream_t s) {
     const dim3 grid(device_cu_count() * kWgsPerCu), block(kThreads);
+    if (per_vertex && x.p0 + 1 < x.n1) {  // panels: those that fit first, on their own queue
+        hipLaunchKernelGGL(k_count_panel_pv, grid, block, 0, s, x.row_ptr, x.col, x.cptr,
+                           x.cbeg, x.cend, x.src, x.cmask, x.item_v_b, x.item_off_b,
+                           x.n_items_b, x.queue_c, x.total, x.tpv, x.n1, x.p0, x.kitem_b,
+                           x.status);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     if (per_vertex)
         hipLaunchKernelGGL(k_count<true>, grid, block, 0, s, x.row_ptr, x.col, x.cptr, x.cbeg,
                            x.cend, x.src, x.cmask, x.item_v_a, x.item_off_a, x.n_items_a,

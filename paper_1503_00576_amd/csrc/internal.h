@@ -96,6 +96,7 @@ struct CountArgs {
     const uint32_t *item_v_a, *item_off_a, *n_items_a;
     const uint32_t *item_v_b, *item_off_b, *n_items_b;
     uint32_t *queue_a, *queue_b;
+    uint32_t *queue_c;  // per-vertex counts: the panels of k_count_panel_pv
     unsigned long long *total, *tpv;
     uint32_t n1;
     uint32_t p0;          // first rank of the panel region (n: no panels)
@@ -122,6 +123,8 @@ uint32_t count_col_pad_bytes();
 uint32_t count_panel();
 uint32_t count_wgs_per_cu();  // resident workgroups per CU of the counting kernels
 uint32_t count_panel_ranks();
+// the largest panel region whose panels all fit the per-vertex panel kernel's LDS
+uint32_t count_pv_panel_ranks();
 // hub triangles on the matrix cores (hub.hip): A / At are hp x hp int8, hubs = ranks h0 ..
 hipError_t launch_hub_fill(const uint32_t *src, const uint32_t *col, const uint32_t *row_ptr,
                            uint32_t mf, uint32_t h0, uint32_t hp, uint8_t *A, uint8_t *At,

@@ -117,6 +117,36 @@ def test_clustering_transitivity_helpers():
     assert api.transitivity(0, np.array([1, 1])) == 0.0
 
 
+@pytest.mark.parametrize("graph", ["er_1000", "rmat10", "ba", "ws"])
+def test_clustering_transitivity_vs_networkx(graph):
+    """The derived quantities from exact per-vertex counts (here the oracle's, on the host)
+    against networkx's own clustering and transitivity of the same graph."""
+    import networkx as nx
+    import numpy as np
+
+    import oracle
+    from paper_1503_00576_amd import api, synth
+    if graph == "er_1000":
+        e, n = synth.er_1000()
+    elif graph == "rmat10":
+        e, n = synth.rmat_graph(10, 8, seed=2)
+    elif graph == "ba":
+        e, n = synth.barabasi_albert(800, 5, 3), 800
+    else:
+        e, n = synth.watts_strogatz(700, 4, 0.1, 5), 700
+    e = e.numpy()
+    total, pv = oracle.count(e, n, per_vertex=True)
+    deg = oracle.degrees(e, n)
+    G = nx.Graph()
+    G.add_nodes_from(range(n))
+    G.add_edges_from(map(tuple, e.tolist()))
+    c = api.clustering(pv, deg)
+    want = nx.clustering(G)
+    assert np.allclose(c, [want[v] for v in range(n)], rtol=1e-12, atol=0)
+    assert abs(float(np.mean(c)) - nx.average_clustering(G)) < 1e-12
+    assert abs(api.transitivity(total, deg) - nx.transitivity(G)) < 1e-12
+
+
 def test_options(lib):
     """struct tc_options: defaults, validation of every field, and the fields that change the
     workspace layout (host arithmetic only)."""

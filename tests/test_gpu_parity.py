@@ -165,9 +165,8 @@ def test_degree_atomic_path(both):
 @pytest.mark.parametrize("ranks", [0, 1, 31, 33, 517, 4000])
 def test_panel_thresholds(ranks):
     """The top-ranks panel region of every size: off (per-vertex lists only), one partial
-    panel, one panel plus a ragged one, and many panels over graphs of every family; per-vertex
-    counts on a prepared graph go through the panels one panel vertex at a time (the one-shot
-    call prepares without panels)."""
+    panel, one panel plus a ragged one, and many panels over graphs of every family, for totals
+    and for per-vertex counts (one-shot and on a prepared graph: the per-vertex panel kernel)."""
     opt = {"panel_ranks": ranks}
     for e, n in [synth.er_1000(), (synth.barabasi_albert(2000, 8, 2), 2000),
                  (synth.watts_strogatz(1500, 6, 0.1, 3), 1500), synth.rmat_graph(11, 8, seed=4),
@@ -175,6 +174,16 @@ def test_panel_thresholds(ranks):
         check_vs_oracle(e.numpy(), n, options=opt, prepared_pv=True)
     for k in [3, 40, 130]:
         assert check_vs_oracle(complete(k), k, options=opt, prepared_pv=True) == math.comb(k, 3)
+
+
+def test_wide_panels_per_vertex():
+    """Per-vertex counts on a graph prepared with more panel ranks than the per-vertex panel
+    kernel holds: the lower panels are counted one panel vertex at a time by the other
+    kernel, the upper ones by the panel kernel; the one-shot call caps its panel region."""
+    e, n = synth.rmat_graph(15, 16, seed=12)
+    assert n > 16384 + 64
+    for ranks in (32736, 20000):
+        check_vs_oracle(e.numpy(), n, options={"panel_ranks": ranks}, prepared_pv=True)
 
 
 def test_single_sweep_sort():
