@@ -109,7 +109,11 @@ const char *tc_strerror(int status);
  *                     take anyway).
  *   sort_onesweep     0 (default): every radix pass is a histogram pass, a scan and a scatter;
  *                     1: sorts of at least 2^20 keys use single-sweep passes (decoupled
- *                     look-back). */
+ *                     look-back).
+ *   high_ranks        the node array's entries among the top high_ranks ranks (at least the
+ *                     panel region) are also kept as 16-bit offsets, and total counts stream
+ *                     them at two bytes instead of four; 0..65536, default 65536 (on R-MAT
+ *                     graphs nearly all streamed entries are such ranks). */
 typedef struct tc_options {
     uint32_t size; /* sizeof(tc_options); set by tc_options_init */
     uint32_t panel_ranks;
@@ -123,6 +127,7 @@ typedef struct tc_options {
     uint32_t block_list_max;
     uint32_t degree_partition;
     uint32_t sort_onesweep;
+    uint32_t high_ranks;
 } tc_options;
 
 /* Fills *opts with the defaults.  Returns TC_E_ARG for a NULL pointer. */

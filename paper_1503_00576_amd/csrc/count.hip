@@ -131,10 +131,16 @@ struct WaveScratch {  // tag: the segment's owner (per-vertex counts) or its pan
 // Segment sources: segment e is a range [b, en) of `col` streamed through the staged list,
 // and `owner` is the vertex credited with the segment's hits in per-vertex counts.
 struct InEdgeSegs {  // middle-vertex kernel: suffix of N+(u) after v, owner u = src[e]
-    const uint32_t *cbeg, *cend, *src;
+    const uint32_t *cbeg, *cend, *src, *chigh;  // chigh: where the entries >= hbase start
     __device__ __forceinline__ void get(uint32_t e, uint32_t &b, uint32_t &en) const {
         b = cbeg[e];
         en = cend[e];
+    }
+    __device__ __forceinline__ void get_high(uint32_t e, uint32_t &b, uint32_t &en,
+                                             uint32_t &hb) const {
+        b = cbeg[e];
+        en = cend[e];
+        hb = chigh[e];
     }
     __device__ __forceinline__ uint32_t owner(uint32_t e) const { return src[cbeg[e] - 1]; }
     __device__ __forceinline__ uint32_t mask(uint32_t) const { return 0u; }
@@ -147,6 +153,13 @@ struct PanelSegs {
     __device__ __forceinline__ void get(uint32_t e, uint32_t &b, uint32_t &en) const {
         b = cbeg[e];
         en = cend[e];
+    }
+    // every entry after a panel vertex is a rank >= p0 >= hbase
+    __device__ __forceinline__ void get_high(uint32_t e, uint32_t &b, uint32_t &en,
+                                             uint32_t &hb) const {
+        b = cbeg[e];
+        en = cend[e];
+        hb = b;
     }
     __device__ __forceinline__ uint32_t owner(uint32_t) const { return 0u; }
     __device__ __forceinline__ uint32_t mask(uint32_t e) const { return cmask[e]; }
@@ -186,21 +199,35 @@ struct OutEdgeSegs {  // u-centric kernel: the whole list N+(v) of out-neighbour
 // The calling wave streams segments [eb, min(eb + 64, e1)) of the current item through the
 // probe and returns this lane's hits.  PV: per-vertex accumulation -- LDS counters `tcnt`
 // indexed by the probe's position when `tcnt` is non-null, global atomics on `tpv` otherwise;
-// every segment's hits go to its owner.
-template <bool PV, class Probe, class Segs>
+// every segment's hits go to its owner.  kHigh (totals): a segment [b, en) whose entries from
+// hb on are ranks >= hbase streams [b, hb) from col and [hb, en) from col16, half the bytes.
+template <bool PV, bool kHigh = false, class Probe, class Segs>
 __device__ __forceinline__ uint32_t run_batch(uint32_t eb, uint32_t e1, const Segs &segs,
                                               const uint32_t *__restrict__ col, const Probe &probe,
                                               WaveScratch &ws, uint32_t *tcnt,
-                                              unsigned long long *__restrict__ tpv) {
+                                              unsigned long long *__restrict__ tpv,
+                                              const uint16_t *__restrict__ col16 = nullptr,
+                                              uint32_t hbase = 0) {
+    static_assert(!(PV && kHigh), "per-vertex counts stream 32-bit entries only");
     const uint32_t lane = lane_id();
     const uint32_t e = eb + lane;
     const bool valid = e < e1;
-    uint32_t b = 0, en = 0;
-    if (valid) segs.get(e, b, en);
-    // pieces are kPiece-element windows starting at 4-element (16-byte) boundaries, so a lane
-    // reads its piece with kPiece / 4 aligned 16-byte loads; elements outside [b, en) are masked
+    uint32_t b = 0, en = 0, hb = 0;
+    if (valid) {
+        if constexpr (kHigh)
+            segs.get_high(e, b, en, hb);
+        else
+            segs.get(e, b, en);
+    }
+    if constexpr (!kHigh) hb = en;
+    // pieces are kPiece-element windows starting at 16-byte boundaries (4 entries of col, 8 of
+    // col16), so a lane reads its piece with aligned 16-byte loads; entries outside the
+    // segment's part are masked.  The 32-bit pieces of [b, hb) come first, then the 16-bit
+    // pieces of [hb, en).
     const uint32_t a0 = b & ~3u;
-    const uint32_t p = (valid && en > b) ? (en - a0 + kPiece - 1) / kPiece : 0u;
+    const uint32_t pl = (valid && hb > b) ? (hb - a0 + kPiece - 1) / kPiece : 0u;
+    uint32_t p = pl;
+    if constexpr (kHigh) p += (valid && en > hb) ? (en - (hb & ~7u) + kPiece - 1) / kPiece : 0u;
     const uint32_t incl = wave_incl_scan(p);
     const uint32_t Q = wave_bcast(incl, kWave - 1);
     ws.off[lane] = incl - p;
@@ -213,6 +240,10 @@ __device__ __forceinline__ uint32_t run_batch(uint32_t eb, uint32_t e1, const Se
     } else if (Probe::kMasked) {
         ws.tag[lane] = valid ? segs.mask(e) : 0u;
     }
+    if constexpr (kHigh) {
+        ws.aux[lane] = hb;
+        ws.cnt[lane] = pl;
+    }
     wave_lds_sync();
     uint32_t hits_total = 0;
     for (uint32_t q0 = 0; q0 < Q; q0 += kWave) {
@@ -224,17 +255,37 @@ __device__ __forceinline__ uint32_t run_batch(uint32_t eb, uint32_t e1, const Se
 #pragma unroll
             for (uint32_t step = 32; step; step >>= 1)
                 if (ws.off[k + step] <= q) k += step;
-            const uint32_t start = ws.beg[k] + (q - ws.off[k]) * kPiece;
-            const uint32_t first = ws.first[k], stop = ws.end[k];
-            const uint4 *p4 = reinterpret_cast<const uint4 *>(col + start);
+            const uint32_t j = q - ws.off[k];
+            uint32_t start, first, stop;
             uint32_t wv[kPiece];
+            if (!kHigh || j < ws.cnt[k]) {
+                start = ws.beg[k] + j * kPiece;
+                first = ws.first[k];
+                stop = kHigh ? ws.aux[k] : ws.end[k];
+                const uint4 *p4 = reinterpret_cast<const uint4 *>(col + start);
 #pragma unroll
-            for (uint32_t j = 0; j < kPiece / 4; ++j) {
-                const uint4 x = p4[j];
-                wv[4 * j] = x.x;
-                wv[4 * j + 1] = x.y;
-                wv[4 * j + 2] = x.z;
-                wv[4 * j + 3] = x.w;
+                for (uint32_t i = 0; i < kPiece / 4; ++i) {
+                    const uint4 x = p4[i];
+                    wv[4 * i] = x.x;
+                    wv[4 * i + 1] = x.y;
+                    wv[4 * i + 2] = x.z;
+                    wv[4 * i + 3] = x.w;
+                }
+            } else {
+                first = ws.aux[k];
+                stop = ws.end[k];
+                start = (first & ~7u) + (j - ws.cnt[k]) * kPiece;
+                const uint4 *p4 = reinterpret_cast<const uint4 *>(col16 + start);
+#pragma unroll
+                for (uint32_t i = 0; i < kPiece / 8; ++i) {
+                    const uint4 x = p4[i];
+                    const uint32_t h[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+                    for (uint32_t t = 0; t < 4; ++t) {
+                        wv[8 * i + 2 * t] = hbase + (h[t] & 0xFFFFu);
+                        wv[8 * i + 2 * t + 1] = hbase + (h[t] >> 16);
+                    }
+                }
             }
             uint32_t hits = 0;
             // element i of the piece belongs to the suffix iff start + i - first < stop - first
@@ -612,14 +663,15 @@ __global__ __launch_bounds__(kThreads) void k_count(
     uint32_t *__restrict__ queue_b, unsigned long long *__restrict__ total,
     unsigned long long *__restrict__ tpv, uint32_t n1, uint32_t p0, uint32_t wave_bits,
     uint32_t block_bits, uint32_t block_list, uint32_t kitem_a, uint32_t kitem_b,
-    const int32_t *__restrict__ status) {
+    const uint16_t *__restrict__ col16, uint32_t hbase, const int32_t *__restrict__ status) {
     __shared__ uint32_t s_mem[kLdsWords];
     __shared__ WaveScratch s_ws[kWaves];
     __shared__ uint32_t s_item;
     if (*status) return;
     const uint32_t t = threadIdx.x, w = t / kWave, lane = lane_id();
     WaveScratch &ws = s_ws[w];
-    const InEdgeSegs segs{cbeg, cend, src};
+    // totals: outside the panels cmask holds where a suffix's entries >= hbase start
+    const InEdgeSegs segs{cbeg, cend, src, cmask};
     for (uint32_t i = t; i < kLdsWords; i += kThreads) s_mem[i] = 0;
     uint64_t acc = 0;
 
@@ -645,7 +697,8 @@ __global__ __launch_bounds__(kThreads) void k_count(
                 const PanelSegs psegs{cbeg, cend, cmask};
                 uint32_t cnt = 0;
                 for (uint32_t eb = first; eb < it.e1; eb += step)
-                    cnt += run_batch<false>(eb, it.e1, psegs, col, probe, ws, nullptr, tpv);
+                    cnt += run_batch<false, true>(eb, it.e1, psegs, col, probe, ws, nullptr,
+                                                  tpv, col16, hbase);
                 acc += cnt;
                 __syncthreads();
                 for (uint32_t j = w; j < np; j += kWaves)
@@ -712,16 +765,19 @@ __global__ __launch_bounds__(kThreads) void k_count(
         if (mode == 0) {
             const BitmapProbe probe{s_mem, lo, span};
             for (uint32_t eb = first; eb < it.e1; eb += step)
-                cnt += run_batch<PV>(eb, it.e1, segs, col, probe, ws, nullptr, tpv);
+                cnt += run_batch<PV, !PV>(eb, it.e1, segs, col, probe, ws, nullptr, tpv, col16,
+                                          hbase);
         } else if (mode == 1) {
             const ListProbe probe{s_mem, it.d};
             uint32_t *tc = PV ? s_mem + kBlockListPV : nullptr;
             for (uint32_t eb = first; eb < it.e1; eb += step)
-                cnt += run_batch<PV>(eb, it.e1, segs, col, probe, ws, tc, tpv);
+                cnt += run_batch<PV, !PV>(eb, it.e1, segs, col, probe, ws, tc, tpv, col16,
+                                          hbase);
         } else {
             const ListProbe probe{col + it.r0, it.d};
             for (uint32_t eb = first; eb < it.e1; eb += step)
-                cnt += run_batch<PV>(eb, it.e1, segs, col, probe, ws, nullptr, tpv);
+                cnt += run_batch<PV, !PV>(eb, it.e1, segs, col, probe, ws, nullptr, tpv, col16,
+                                          hbase);
         }
         if (PV) {
             uint64_t wave_hits = wave_sum_u64(cnt);
@@ -765,7 +821,8 @@ __global__ __launch_bounds__(kThreads) void k_count(
                 wave_lds_sync();
                 const BitmapProbe probe{mem, lo, span};
                 for (uint32_t eb = it.e0; eb < it.e1; eb += kWave)
-                    cnt += run_batch<false>(eb, it.e1, segs, col, probe, ws, nullptr, tpv);
+                    cnt += run_batch<false, true>(eb, it.e1, segs, col, probe, ws, nullptr, tpv,
+                                                  col16, hbase);
                 for (uint32_t i = lane; i < it.d; i += kWave)
                     mem[(col[it.r0 + i] - lo) >> 5] = 0;
             } else {  // a wide span, but a list that fits the slice (see k_items)
@@ -773,7 +830,8 @@ __global__ __launch_bounds__(kThreads) void k_count(
                 wave_lds_sync();
                 const ListProbe probe{mem, it.d};
                 for (uint32_t eb = it.e0; eb < it.e1; eb += kWave)
-                    cnt += run_batch<false>(eb, it.e1, segs, col, probe, ws, nullptr, tpv);
+                    cnt += run_batch<false, true>(eb, it.e1, segs, col, probe, ws, nullptr, tpv,
+                                                  col16, hbase);
                 for (uint32_t i = lane; i < it.d; i += kWave) mem[i] = 0;
             }
             wave_lds_sync();
@@ -1042,7 +1100,7 @@ uint32_t count_block_span() { return kBlockBits; }
 uint32_t count_block_list(bool per_vertex) { return per_vertex ? kBlockListPV : kBlockList; }
 uint32_t count_item_edges_wave() { return kItemEdgesWave; }
 uint32_t count_item_edges_block() { return kItemEdgesBlock; }
-uint32_t count_col_pad_bytes() { return kPiece * 4; }
+uint32_t count_col_pad_bytes() { return kPiece * 4; }  // also covers col16's kPiece * 2
 uint32_t count_panel() { return kPanel; }
 uint32_t count_wgs_per_cu() { return kWgsPerCu; }
 uint32_t count_light_max() { return kLightMax; }
@@ -1065,13 +1123,13 @@ hipError_t launch_count(const CountArgs &x, bool per_vertex, hipStream_t s) {
                            x.cend, x.src, x.cmask, x.item_v_a, x.item_off_a, x.n_items_a,
                            x.item_v_b, x.item_off_b, x.n_items_b, x.queue_a, x.queue_b, x.total,
                            x.tpv, x.n1, x.p0, x.wave_bits, x.block_bits, x.block_list,
-                           x.kitem_a, x.kitem_b, x.status);
+                           x.kitem_a, x.kitem_b, x.col16, x.hbase, x.status);
     else
         hipLaunchKernelGGL(k_count<false>, grid, block, 0, s, x.row_ptr, x.col, x.cptr, x.cbeg,
                            x.cend, x.src, x.cmask, x.item_v_a, x.item_off_a, x.n_items_a,
                            x.item_v_b, x.item_off_b, x.n_items_b, x.queue_a, x.queue_b, x.total,
                            x.tpv, x.n1, x.p0, x.wave_bits, x.block_bits, x.block_list,
-                           x.kitem_a, x.kitem_b, x.status);
+                           x.kitem_a, x.kitem_b, x.col16, x.hbase, x.status);
     return hipGetLastError();
 }
 

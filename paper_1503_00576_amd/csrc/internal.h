@@ -93,6 +93,10 @@ int device_cu_count();
 // counting kernels (count.hip)
 struct CountArgs {
     const uint32_t *row_ptr, *col, *cptr, *cbeg, *cend, *src, *cmask;  // src: row of a CSR entry
+    // col as 16-bit offsets from rank hbase (meaningful for entries >= hbase); totals stream
+    // every in-edge suffix's entries >= hbase from here (cmask: where they start)
+    const uint16_t *col16;
+    uint32_t hbase;
     const uint32_t *item_v_a, *item_off_a, *n_items_a;
     const uint32_t *item_v_b, *item_off_b, *n_items_b;
     uint32_t *queue_a, *queue_b;

@@ -320,10 +320,14 @@ __global__ void k_both_check(const uint32_t *__restrict__ counter, uint32_t expe
 constexpr uint32_t kCsrKeys = 4;
 
 // Unzip the sorted keys into the neighbour array (Section 3.2, step 7) and mark where every
-// non-empty row starts and ends; row lengths and their prefix sum give the node array.
+// non-empty row starts and ends; row lengths and their prefix sum give the node array.  The
+// neighbours are also written as 16-bit offsets from rank hbase (col16; only entries >= hbase
+// are meaningful), and hrow[u] receives the position of the first entry >= hbase of row u
+// (left untouched, all ones from the caller's fill, when the row has none).
 __global__ void k_csr(const uint64_t *__restrict__ keys, uint32_t mf, uint32_t n, int b,
-                      uint32_t *__restrict__ col, uint32_t *__restrict__ src,
-                      uint32_t *__restrict__ rs, uint32_t *__restrict__ re,
+                      uint32_t hbase, uint32_t *__restrict__ col, uint16_t *__restrict__ col16,
+                      uint32_t *__restrict__ src, uint32_t *__restrict__ rs,
+                      uint32_t *__restrict__ re, uint32_t *__restrict__ hrow,
                       int32_t *__restrict__ status) {
     if (*status) return;
     // kCsrKeys keys a block apart per thread, all loaded before any is used
@@ -341,10 +345,15 @@ __global__ void k_csr(const uint64_t *__restrict__ keys, uint32_t mf, uint32_t n
         const uint64_t i = i0 + (uint64_t)t * blockDim.x;
         if (i >= mf) continue;
         const uint32_t s = (uint32_t)(k[t] >> b);
-        col[i] = (uint32_t)(k[t] & ((1ull << b) - 1));
+        const uint32_t c = (uint32_t)(k[t] & ((1ull << b) - 1));
+        col[i] = c;
+        col16[i] = (uint16_t)(c - hbase);
         src[i] = s;
         if (s >= n) continue;  // only for invalid input, reported elsewhere
-        if (i == 0 || (uint32_t)(kp[t] >> b) != s) rs[s] = (uint32_t)i;
+        const bool row_start = i == 0 || (uint32_t)(kp[t] >> b) != s;
+        if (row_start) rs[s] = (uint32_t)i;
+        if (c >= hbase && (row_start || (uint32_t)(kp[t] & ((1ull << b) - 1)) < hbase))
+            hrow[s] = (uint32_t)i;
         if (i > 0 && kp[t] == k[t]) set_status(status, TC_E_DUP_EDGE);
         if (i == mf - 1 || (uint32_t)(kn[t] >> b) != s) re[s] = (uint32_t)(i + 1);
     }
@@ -399,14 +408,16 @@ __global__ void k_panel_range(const uint64_t *__restrict__ vr, uint32_t n, uint3
 // per panel, keyed by its first rank P: only the first in-edge of each run of u's
 // out-neighbours inside the panel is kept (it stands for the whole run), tested against the
 // panel's span (a small table).  eu[e] = (end of u's row, mask of the run's panel vertices
-// for a kept panel entry).  In-edges from hubs (u >= h0) are left out: their triangles are
-// counted on the matrix cores.
+// for a kept panel entry; for any other kept entry the position where the suffix's entries
+// >= hbase start, hrow[u] from k_csr).  In-edges from hubs (u >= h0) are left out: their
+// triangles are counted on the matrix cores.
 // Each thread takes kCscEdges entries a block apart and issues every stage's loads for all of
 // them before using any (the stages depend on each other: entry -> row -> row end).
 constexpr uint32_t kCscEdges = 4;
 
 __global__ void k_csc_keys(const uint32_t *__restrict__ col, const uint32_t *__restrict__ src,
                            const uint32_t *__restrict__ row_ptr,
+                           const uint32_t *__restrict__ hrow, uint32_t hbase,
                            const uint64_t *__restrict__ pr, uint32_t mf, uint32_t n,
                            uint32_t nblk, uint32_t p0, uint32_t kp, uint32_t h0,
                            uint64_t *__restrict__ keys, uint2 *__restrict__ eu,
@@ -425,12 +436,13 @@ __global__ void k_csc_keys(const uint32_t *__restrict__ col, const uint32_t *__r
         prv[k] = (in && e > 0) ? col[e - 1] : 0u;
         nxt[k] = (in && e + 1 < mf) ? col[e + 1] : 0u;
     }
-    uint32_t rb[kCscEdges], re[kCscEdges];
+    uint32_t rb[kCscEdges], re[kCscEdges], hr[kCscEdges];
 #pragma unroll
     for (uint32_t k = 0; k < kCscEdges; ++k) {
         const bool in = e0 + (uint64_t)k * blockDim.x < mf;
         rb[k] = in ? row_ptr[u[k]] : 0u;
         re[k] = in ? row_ptr[u[k] + 1] : 0u;
+        hr[k] = (in && v[k] < hbase) ? hrow[u[k]] : 0u;
     }
     uint32_t last[kCscEdges];
     uint64_t r[kCscEdges];
@@ -460,6 +472,8 @@ __global__ void k_csc_keys(const uint32_t *__restrict__ col, const uint32_t *__r
             if (keep) {
                 const uint64_t blk = nblk == 1 ? 0 : (e * nblk) / mf;
                 c = blk * (n + 1) + list;
+                // outside the panels: where the suffix's entries >= hbase start
+                if (v[k] < p0) mask = v[k] >= hbase ? (uint32_t)e + 1u : min(hr[k], end_u);
                 if (run_start) {  // the run's mask: u's consecutive entries inside the panel
                     mask = 1u << (v[k] - list);
                     for (uint64_t x = e + 1; x < end_u; x += 4) {  // four loads at a time

@@ -238,6 +238,32 @@ def test_forced_item_forms(name):
         assert check_vs_oracle(complete(k), k, options=opt, prepared_pv=True) == math.comb(k, 3)
 
 
+@pytest.mark.parametrize("high", [0, 100])
+@pytest.mark.parametrize("name", sorted(FORCED))
+def test_forced_item_forms_high_region(name, high):
+    """Every item form with the 16-bit region of the node array cut to the top `high` ranks
+    (0: only the panel region), so that total counts stream suffixes that start in 32-bit
+    entries and continue in 16-bit ones, or stay 32-bit throughout."""
+    opt = dict(FORCED[name], high_ranks=high)
+    for e, n in [synth.er_1000(), (synth.barabasi_albert(3000, 12, 2), 3000),
+                 synth.rmat_graph(12, 16, seed=8), (synth.erdos_renyi(700, 0.9, 3), 700)]:
+        check_vs_oracle(e.numpy(), n, options=opt)
+    for k in [3, 40, 130]:
+        assert check_vs_oracle(complete(k), k, options=opt) == math.comb(k, 3)
+
+
+@pytest.mark.parametrize("high", [0, 1, 7, 33, 517, 4000])
+def test_high_region_sizes(high):
+    """16-bit region of every size against panel regions below, inside and above it: pieces
+    whose 32-bit part ends mid-piece, one-entry 16-bit parts, and the region clamped to the
+    panel region when that is larger."""
+    for panels in (0, 64, 2000):
+        opt = {"high_ranks": high, "panel_ranks": panels}
+        for e, n in [synth.er_1000(), synth.rmat_graph(13, 16, seed=9),
+                     (synth.barabasi_albert(2500, 10, 5), 2500)]:
+            check_vs_oracle(e.numpy(), n, options=opt)
+
+
 def test_prepared_options_mismatch():
     """tc_count_prepared with options (or sizes) other than the preprocessing's reports a
     mismatch on the device; the workspace stays usable with the right ones."""
