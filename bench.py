@@ -88,11 +88,13 @@ def pv_digest(pv) -> str:
     return hashlib.sha256(pv.detach().cpu().numpy().astype("<u8").tobytes()).hexdigest()
 
 
-def streamed_elements(row_ptr, col, p0: int, panel: int = 32):
+def streamed_elements(row_ptr, col, p0: int, hbase: int, panel: int = 32):
     """Elements the counting kernel streams through its LDS structures, and its segments:
     for a middle vertex v below the panel region, the suffix of N+(u) after v for every
     in-edge u -> v (when N+(v) is not empty); in the panel region (ranks >= p0, panels of 32
-    consecutive middle vertices), one suffix per (u, panel), after u's first panel vertex."""
+    consecutive middle vertices), one suffix per (u, panel), after u's first panel vertex.
+    Also the streamed elements below rank hbase (4 bytes each; the others are read as 16-bit
+    offsets from hbase)."""
     import torch
     rp = row_ptr.to(torch.int64)
     c = col.to(torch.int64)
@@ -100,11 +102,19 @@ def streamed_elements(row_ptr, col, p0: int, panel: int = 32):
     deg = rp[1:] - rp[:-1]
     src = torch.repeat_interleave(torch.arange(n, device=rp.device), deg)
     e = torch.arange(c.numel(), device=rp.device)
-    suffix = rp[src + 1] - e - 1
+    row_end = rp[src + 1]
+    suffix = row_end - e - 1
     mid = (c < p0) & (suffix > 0) & (deg[c] > 0)
     streamed = int(suffix[mid].sum().item())
     segments = int(mid.sum().item())
-    del mid
+    # the first entry >= hbase of every row (the row end when there is none)
+    first_high = rp[1:].clone()
+    hi = c >= hbase
+    first_high.scatter_reduce_(0, src[hi], e[hi], reduce="amin", include_self=True)
+    low_end = torch.minimum(first_high[src], row_end)
+    low = torch.clamp(low_end - e - 1, min=0)
+    streamed_low = int(low[mid & (c < hbase)].sum().item())
+    del mid, first_high, hi, low_end, low
     pan = c >= p0
     if bool(pan.any()):
         first = p0 + torch.div(c - p0, panel, rounding_mode="floor") * panel
@@ -113,7 +123,7 @@ def streamed_elements(row_ptr, col, p0: int, panel: int = 32):
         sel = pan & run_start & (suffix > 0)
         streamed += int(suffix[sel].sum().item())
         segments += int(sel.sum().item())
-    return streamed, segments
+    return streamed, segments, streamed_low
 
 
 def make_graph(name: str, dev):
@@ -616,8 +626,10 @@ def main():
     arrs = prep.arrays()
     dplus = (arrs["row_ptr"][1:] - arrs["row_ptr"][:-1]).to(torch.int64)
     wedges = int((dplus * (dplus - 1) // 2).sum().item())
-    p0 = n - min(dict(api.default_options(), **(opts or {}))["panel_ranks"], n)
-    streamed, segments = streamed_elements(arrs["row_ptr"], arrs["col"], p0)
+    full_opts = dict(api.default_options(), **(opts or {}))
+    p0 = n - min(full_opts["panel_ranks"], n)
+    hbase = min(max(n - full_opts["high_ranks"], 0), p0)
+    streamed, segments, streamed_low = streamed_elements(arrs["row_ptr"], arrs["col"], p0, hbase)
     del arrs, prep, dplus
     torch.cuda.empty_cache()
     g = (golden("workloads.json") or {}).get(GOLDEN_KEYS[args.workload])
@@ -630,7 +642,8 @@ def main():
     # + 12 B per segment (its range and panel mask) + the node array and out-lists once.
     ctr = load_counters("k_count", args.workload)
     t_s = count_ms * 1e-3
-    alg_bytes = 4.0 * streamed + 12.0 * segments + 4.0 * (n + 1) + 4.0 * m
+    alg_bytes = (4.0 * streamed_low + 2.0 * (streamed - streamed_low) + 12.0 * segments +
+                 4.0 * (n + 1) + 4.0 * m)
     alg_gbs = alg_bytes / t_s / 1e9
     traffic = ctr["hbm_bytes_per_launch"] if ctr else None
     if traffic:
@@ -644,9 +657,11 @@ def main():
                                 if ctr and "l2_hit_rate" in ctr else None),
                 "algorithmic": {"bytes": alg_bytes, "gbs": round(alg_gbs, 1),
                                 "frac": round(alg_gbs / HBM_PEAK_GBS, 4),
-                                "streamed_elements": streamed, "segments": segments,
-                                "unit": "4 B per streamed element + 12 B per segment + "
-                                        "4 B per CSR entry and row offset"},
+                                "streamed_elements": streamed,
+                                "streamed_below_hbase": streamed_low, "segments": segments,
+                                "unit": "2 B per streamed element (4 B below the 16-bit "
+                                        "region) + 12 B per segment + 4 B per CSR entry and "
+                                        "row offset"},
                 "logical_wvtx": {"bytes": 4.0 * wedges, "gbs": round(4.0 * wedges / t_s / 1e9, 1),
                                  "note": "4 B per wedge of the oriented graph (one membership "
                                          "test each without panels); context, not a bandwidth"}}
