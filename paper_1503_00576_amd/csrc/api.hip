@@ -27,17 +27,19 @@ __global__ void k_orient_cells(const int2 *, uint64_t, uint32_t, const uint32_t 
                                uint64_t *, const int32_t *);
 __global__ void k_both_check(const uint32_t *, uint32_t, int32_t *);
 __global__ void k_csr(const uint64_t *, uint32_t, uint32_t, int, uint32_t, uint32_t *,
-                      uint16_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t *, int32_t *);
+                      uint32_t *, uint32_t *, uint32_t *, uint32_t *, int32_t *);
+__global__ void k_hlen(const uint32_t *, const uint32_t *, uint32_t, uint32_t *);
 __global__ void k_rowlen(const uint32_t *, const uint32_t *, uint32_t, uint32_t *);
 __global__ void k_vrange(const uint32_t *, const uint32_t *, uint32_t, uint32_t, uint64_t *);
 __global__ void k_panel_range(const uint64_t *, uint32_t, uint32_t, uint32_t, uint32_t,
                               uint64_t *);
 __global__ void k_csc_keys(const uint32_t *, const uint32_t *, const uint32_t *,
-                           const uint32_t *, uint32_t, const uint64_t *, uint32_t, uint32_t,
-                           uint32_t, uint32_t, uint32_t, uint32_t, uint64_t *, uint2 *,
-                           const int32_t *);
-__global__ void k_csc_final(const uint64_t *, uint32_t, uint64_t, const uint2 *, uint32_t *,
-                            uint32_t *, uint32_t *, uint32_t *, uint32_t *, const int32_t *);
+                           const uint32_t *, const uint32_t *, uint32_t, const uint64_t *,
+                           uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t,
+                           uint64_t *, uint4 *, uint16_t *, const int32_t *);
+__global__ void k_csc_final(const uint64_t *, uint32_t, uint64_t, const uint4 *, uint32_t *,
+                            uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t *,
+                            const int32_t *);
 __global__ void k_items(const uint32_t *, const uint32_t *, const uint32_t *, uint32_t, uint32_t,
                         uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t *,
                         uint32_t *,
@@ -70,16 +72,17 @@ int device_cu_count() {
 
 struct Layout {
     size_t ctl, part_hist, part_offs, part_scan, deg, perm, rank, keys_a, keys_b, sort_scratch,
-        rs, re, rowlen, row_ptr, col, col16, hrow, src, vrange, prange, eu, lrs, lre, cnt, cptr,
-        cbeg, cend, cmask, items[4], off[4], item_v[4], scan_scratch, tpv, hub_a, hub_at,
-        total_bytes;
+        rs, re, rowlen, row_ptr, col, hcol, hrow, hstart, src, vrange, prange, eu, lrs, lre, cnt,
+        cptr, cbeg, cend, cmask, chigh, items[4], off[4], item_v[4], scan_scratch, tpv, hub_a,
+        hub_at, total_bytes;
     uint32_t part_tiles;  // 0: degrees by atomics (inputs too large for the partition)
     int part_shift;
     int cell_shift;       // >= 0: edges also partitioned into cells for the orientation
     uint32_t n, m, mf, kcap, id_bits, nblk;
     uint32_t p0, panels;  // panel region: ranks [p0, n) in panels of count_panel() ranks
     uint32_t h0, hp;      // hubs: ranks [h0, n), matrices hp x hp (hp = 0: no hubs)
-    uint32_t hbase;       // ranks >= hbase are also held as 16-bit offsets (col16)
+    uint32_t hbase;       // ranks >= hbase are also held as 16-bit offsets (hcol); n: none
+    uint64_t hcap;        // hcol entries
     uint64_t lists;       // in-edge lists: nblk * (n + 1)
     tc_options opt;       // resolved options
     uint32_t finger;      // fingerprint of (n, m, flags, options, panels), never 0
@@ -205,10 +208,21 @@ static bool make_layout(int64_t n, int64_t m, uint32_t flags, const tc_options *
         L.hp = (h + 63u) & ~63u;
     }
     L.panels = ceil_div(L.n - L.p0, count_panel());
-    // the 16-bit region holds the panel region (whose streamed entries are all panel ranks or
-    // higher) and spans at most 2^16 ranks (panel regions are smaller)
-    L.hbase = L.n > o.high_ranks ? L.n - o.high_ranks : 0u;
-    L.hbase = L.hbase < L.p0 ? L.hbase : L.p0;
+    // The 16-bit region holds the panel region (whose streamed entries are all panel ranks or
+    // higher) and spans at most 2^16 ranks (panel regions are smaller).  Its rows' parts in
+    // hcol take at most 15 padding entries each; 32-bit positions must address them all, or
+    // there is no region (as for high_ranks = 0).
+    {
+        const uint64_t rows = (uint64_t)n < L.mf ? (uint64_t)n : L.mf;
+        L.hcap = ((uint64_t)L.mf + 15 * rows + 64 + 7) & ~7ull;
+        if (o.high_ranks == 0 || L.hcap >= (1ull << 32)) {
+            L.hbase = L.n;
+            L.hcap = 64;
+        } else {
+            L.hbase = L.n > o.high_ranks ? L.n - o.high_ranks : 0u;
+            L.hbase = L.hbase < L.p0 ? L.hbase : L.p0;
+        }
+    }
     const uint64_t n1 = (uint64_t)n + 1;
     L.lists = (uint64_t)L.nblk * n1;
     const uint64_t l1 = L.lists + 1;
@@ -251,12 +265,13 @@ static bool make_layout(int64_t n, int64_t m, uint32_t flags, const tc_options *
     L.rowlen = take(n1 * 4);
     L.row_ptr = take(n1 * 4);
     L.col = take((size_t)L.mf * 4 + count_col_pad_bytes());  // piece reads may pass the end
-    L.col16 = take((size_t)L.mf * 2 + count_col_pad_bytes());
+    L.hcol = take((size_t)L.hcap * 2);
     L.hrow = take((size_t)n * 4);
+    L.hstart = take(n1 * 4);
     L.src = take((size_t)L.mf * 4);
     L.vrange = take((size_t)n * 8);
     L.prange = take((size_t)L.panels * 8);
-    L.eu = take((size_t)L.mf * 8);
+    L.eu = take((size_t)L.mf * 16);  // also the cell-ordered edges (8 bytes per entry)
     L.lrs = take(l1 * 4);
     L.lre = take(l1 * 4);
     L.cnt = take(l1 * 4);
@@ -264,6 +279,7 @@ static bool make_layout(int64_t n, int64_t m, uint32_t flags, const tc_options *
     L.cbeg = take((size_t)L.mf * 4);
     L.cend = take((size_t)L.mf * 4);
     L.cmask = take((size_t)L.mf * 4);
+    L.chigh = take((size_t)L.mf * 4);
     for (int k = 0; k < 4; ++k) {
         const uint32_t per = (k & 1) ? o.block_item_edges : o.wave_item_edges;
         L.items[k] = take(l1 * 4);
@@ -412,16 +428,24 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
     TC_HIP(fill_u32(rs, 0u, n1, s));
     TC_HIP(fill_u32(re, 0u, n1, s));
     uint32_t *src = at<uint32_t>(ws, L.src);
-    uint16_t *col16 = at<uint16_t>(ws, L.col16);
     uint32_t *hrow = at<uint32_t>(ws, L.hrow);
     TC_HIP(fill_u32(hrow, ~0u, n, s));
     hipLaunchKernelGGL(k_csr, dim3(grid_for(mf, 256 * 4)), dim3(256), 0, s, sorted, mf, n, b,
-                       L.hbase, col, col16, src, rs, re, hrow,
+                       L.hbase, col, src, rs, re, hrow,
                        status);  // 4 keys per thread (prep.hip, kCsrKeys)
     TC_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_rowlen, dim3(grid_for(n1, 256)), dim3(256), 0, s, rs, re, n, rowlen);
     TC_LAUNCH_CHECK();
     TC_HIP(scan_exclusive_u32(rowlen, row_ptr, n1, scan_scr, s));
+    // every row's part of hcol (row lengths are no longer needed: their array takes the parts'
+    // sizes); hcol starts as zeros, the parts' padding
+    uint32_t *hstart = at<uint32_t>(ws, L.hstart);
+    uint16_t *hcol = at<uint16_t>(ws, L.hcol);
+    hipLaunchKernelGGL(k_hlen, dim3(grid_for(n1, 256)), dim3(256), 0, s, row_ptr, hrow, n,
+                       rowlen);
+    TC_LAUNCH_CHECK();
+    TC_HIP(scan_exclusive_u32(rowlen, hstart, n1, scan_scr, s));
+    TC_HIP(fill_u32((uint32_t *)hcol, 0u, L.hcap / 2, s));
     // the hub matrices
     if (L.hp) {
         uint8_t *ha = at<uint8_t>(ws, L.hub_a), *hat = at<uint8_t>(ws, L.hub_at);
@@ -448,7 +472,7 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
     }
     uint64_t *ck = (sorted == ka) ? kb : ka;  // the sorted edge keys are no longer needed
     uint64_t *ck2 = (sorted == ka) ? ka : kb;
-    uint2 *eu = at<uint2>(ws, L.eu);
+    uint4 *eu = at<uint4>(ws, L.eu);
     uint64_t *pr = at<uint64_t>(ws, L.prange);
     if (L.panels) {
         hipLaunchKernelGGL(k_panel_range, dim3(grid_for(L.panels, 256)), dim3(256), 0, s, vr, n,
@@ -456,8 +480,8 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
         TC_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL(k_csc_keys, dim3(grid_for(mf, 256 * kCscPerThread)), dim3(256), 0, s, col,
-                       src, row_ptr, hrow, L.hbase, pr, mf, n, L.nblk, L.p0, count_panel(), L.h0,
-                       ck, eu, status);
+                       src, row_ptr, hrow, hstart, L.hbase, pr, mf, n, L.nblk, L.p0,
+                       count_panel(), L.h0, ck, eu, hcol, status);
     TC_LAUNCH_CHECK();
     uint64_t *cks = ck;
     TC_HIP(sort_u64(ck, ck2, mf, 32, 32 + id_bits_for64(l1), sort_scr, status, s, &cks,
@@ -467,7 +491,7 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
     // one entry per thread: its gather is bound by the random-line rate, not by latency
     hipLaunchKernelGGL(k_csc_final, dim3(grid_for(mf, 256)), dim3(256), 0, s, cks, mf, L.lists,
                        eu, at<uint32_t>(ws, L.cbeg), at<uint32_t>(ws, L.cend),
-                       at<uint32_t>(ws, L.cmask), lrs, lre, status);
+                       at<uint32_t>(ws, L.cmask), at<uint32_t>(ws, L.chigh), lrs, lre, status);
     TC_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_rowlen, dim3(grid_for(l1, 256)), dim3(256), 0, s, lrs, lre,
                        (uint32_t)L.lists, cnt);
@@ -515,7 +539,8 @@ static int run_count_prepared(void *ws, const Layout &L, hipStream_t s, uint64_t
         CountArgs a;
         a.row_ptr = at<uint32_t>(ws, L.row_ptr);
         a.col = at<uint32_t>(ws, L.col);
-        a.col16 = at<uint16_t>(ws, L.col16);
+        a.hcol = at<uint16_t>(ws, L.hcol);
+        a.chigh = at<uint32_t>(ws, L.chigh);
         a.hbase = L.hbase;
         a.cptr = at<uint32_t>(ws, L.cptr);
         a.cbeg = at<uint32_t>(ws, L.cbeg);

@@ -81,6 +81,10 @@ struct BitmapProbe {
     __device__ __forceinline__ bool operator()(uint32_t w, uint32_t &) const { return bit(w); }
     static constexpr bool kMasked = false;
     static constexpr bool kList = false;
+    // totals streamer (run_batch_t): both parts of a segment, positions tested
+    static constexpr bool kLow = true;
+    static constexpr bool kMaskHigh = true;
+    static constexpr bool kPanel = false;
 };
 
 // Panel table M over ranks [lo, lo + span]: word w - lo holds the mask of the panel vertices
@@ -114,6 +118,9 @@ struct ListProbe {  // sorted list in LDS or in global memory (d >= 1)
     static constexpr bool kBranchFree = false;
     static constexpr bool kMasked = false;
     static constexpr bool kList = true;
+    static constexpr bool kLow = true;
+    static constexpr bool kMaskHigh = true;
+    static constexpr bool kPanel = false;
     __device__ __forceinline__ bool operator()(uint32_t w, uint32_t &pos) const {
         pos = lower_bound_u32(list, d, w);
         return pos < d && list[pos] == w;
@@ -131,16 +138,19 @@ struct WaveScratch {  // tag: the segment's owner (per-vertex counts) or its pan
 // Segment sources: segment e is a range [b, en) of `col` streamed through the staged list,
 // and `owner` is the vertex credited with the segment's hits in per-vertex counts.
 struct InEdgeSegs {  // middle-vertex kernel: suffix of N+(u) after v, owner u = src[e]
-    const uint32_t *cbeg, *cend, *src, *chigh;  // chigh: where the entries >= hbase start
+    // totals: the suffix's entries >= hbase start at col position csplit[e], and at hcol
+    // position chigh[e]
+    const uint32_t *cbeg, *cend, *src, *csplit, *chigh;
     __device__ __forceinline__ void get(uint32_t e, uint32_t &b, uint32_t &en) const {
         b = cbeg[e];
         en = cend[e];
     }
-    __device__ __forceinline__ void get_high(uint32_t e, uint32_t &b, uint32_t &en,
-                                             uint32_t &hb) const {
+    __device__ __forceinline__ void get_t(uint32_t e, uint32_t &b, uint32_t &hb, uint32_t &en,
+                                          uint32_t &h) const {
         b = cbeg[e];
         en = cend[e];
-        hb = chigh[e];
+        hb = csplit[e];
+        h = chigh[e];
     }
     __device__ __forceinline__ uint32_t owner(uint32_t e) const { return src[cbeg[e] - 1]; }
     __device__ __forceinline__ uint32_t mask(uint32_t) const { return 0u; }
@@ -149,17 +159,18 @@ struct InEdgeSegs {  // middle-vertex kernel: suffix of N+(u) after v, owner u =
 // Panel segment (u, panel): the suffix of N+(u) after u's first panel vertex, tagged with the
 // mask R(u) of u's panel vertices.
 struct PanelSegs {
-    const uint32_t *cbeg, *cend, *cmask;
+    const uint32_t *cbeg, *cend, *cmask, *chigh;
     __device__ __forceinline__ void get(uint32_t e, uint32_t &b, uint32_t &en) const {
         b = cbeg[e];
         en = cend[e];
     }
-    // every entry after a panel vertex is a rank >= p0 >= hbase
-    __device__ __forceinline__ void get_high(uint32_t e, uint32_t &b, uint32_t &en,
-                                             uint32_t &hb) const {
+    // with a high region, every entry after a panel vertex is a rank >= p0 >= hbase
+    __device__ __forceinline__ void get_t(uint32_t e, uint32_t &b, uint32_t &hb, uint32_t &en,
+                                          uint32_t &h) const {
         b = cbeg[e];
         en = cend[e];
         hb = b;
+        h = chigh[e];
     }
     __device__ __forceinline__ uint32_t owner(uint32_t) const { return 0u; }
     __device__ __forceinline__ uint32_t mask(uint32_t e) const { return cmask[e]; }
@@ -199,35 +210,21 @@ struct OutEdgeSegs {  // u-centric kernel: the whole list N+(v) of out-neighbour
 // The calling wave streams segments [eb, min(eb + 64, e1)) of the current item through the
 // probe and returns this lane's hits.  PV: per-vertex accumulation -- LDS counters `tcnt`
 // indexed by the probe's position when `tcnt` is non-null, global atomics on `tpv` otherwise;
-// every segment's hits go to its owner.  kHigh (totals): a segment [b, en) whose entries from
-// hb on are ranks >= hbase streams [b, hb) from col and [hb, en) from col16, half the bytes.
-template <bool PV, bool kHigh = false, class Probe, class Segs>
+// every segment's hits go to its owner.
+template <bool PV, class Probe, class Segs>
 __device__ __forceinline__ uint32_t run_batch(uint32_t eb, uint32_t e1, const Segs &segs,
                                               const uint32_t *__restrict__ col, const Probe &probe,
                                               WaveScratch &ws, uint32_t *tcnt,
-                                              unsigned long long *__restrict__ tpv,
-                                              const uint16_t *__restrict__ col16 = nullptr,
-                                              uint32_t hbase = 0) {
-    static_assert(!(PV && kHigh), "per-vertex counts stream 32-bit entries only");
+                                              unsigned long long *__restrict__ tpv) {
     const uint32_t lane = lane_id();
     const uint32_t e = eb + lane;
     const bool valid = e < e1;
-    uint32_t b = 0, en = 0, hb = 0;
-    if (valid) {
-        if constexpr (kHigh)
-            segs.get_high(e, b, en, hb);
-        else
-            segs.get(e, b, en);
-    }
-    if constexpr (!kHigh) hb = en;
-    // pieces are kPiece-element windows starting at 16-byte boundaries (4 entries of col, 8 of
-    // col16), so a lane reads its piece with aligned 16-byte loads; entries outside the
-    // segment's part are masked.  The 32-bit pieces of [b, hb) come first, then the 16-bit
-    // pieces of [hb, en).
+    uint32_t b = 0, en = 0;
+    if (valid) segs.get(e, b, en);
+    // pieces are kPiece-element windows starting at 4-element (16-byte) boundaries, so a lane
+    // reads its piece with kPiece / 4 aligned 16-byte loads; elements outside [b, en) are masked
     const uint32_t a0 = b & ~3u;
-    const uint32_t pl = (valid && hb > b) ? (hb - a0 + kPiece - 1) / kPiece : 0u;
-    uint32_t p = pl;
-    if constexpr (kHigh) p += (valid && en > hb) ? (en - (hb & ~7u) + kPiece - 1) / kPiece : 0u;
+    const uint32_t p = (valid && en > b) ? (en - a0 + kPiece - 1) / kPiece : 0u;
     const uint32_t incl = wave_incl_scan(p);
     const uint32_t Q = wave_bcast(incl, kWave - 1);
     ws.off[lane] = incl - p;
@@ -240,10 +237,6 @@ __device__ __forceinline__ uint32_t run_batch(uint32_t eb, uint32_t e1, const Se
     } else if (Probe::kMasked) {
         ws.tag[lane] = valid ? segs.mask(e) : 0u;
     }
-    if constexpr (kHigh) {
-        ws.aux[lane] = hb;
-        ws.cnt[lane] = pl;
-    }
     wave_lds_sync();
     uint32_t hits_total = 0;
     for (uint32_t q0 = 0; q0 < Q; q0 += kWave) {
@@ -255,37 +248,17 @@ __device__ __forceinline__ uint32_t run_batch(uint32_t eb, uint32_t e1, const Se
 #pragma unroll
             for (uint32_t step = 32; step; step >>= 1)
                 if (ws.off[k + step] <= q) k += step;
-            const uint32_t j = q - ws.off[k];
-            uint32_t start, first, stop;
+            const uint32_t start = ws.beg[k] + (q - ws.off[k]) * kPiece;
+            const uint32_t first = ws.first[k], stop = ws.end[k];
+            const uint4 *p4 = reinterpret_cast<const uint4 *>(col + start);
             uint32_t wv[kPiece];
-            if (!kHigh || j < ws.cnt[k]) {
-                start = ws.beg[k] + j * kPiece;
-                first = ws.first[k];
-                stop = kHigh ? ws.aux[k] : ws.end[k];
-                const uint4 *p4 = reinterpret_cast<const uint4 *>(col + start);
 #pragma unroll
-                for (uint32_t i = 0; i < kPiece / 4; ++i) {
-                    const uint4 x = p4[i];
-                    wv[4 * i] = x.x;
-                    wv[4 * i + 1] = x.y;
-                    wv[4 * i + 2] = x.z;
-                    wv[4 * i + 3] = x.w;
-                }
-            } else {
-                first = ws.aux[k];
-                stop = ws.end[k];
-                start = (first & ~7u) + (j - ws.cnt[k]) * kPiece;
-                const uint4 *p4 = reinterpret_cast<const uint4 *>(col16 + start);
-#pragma unroll
-                for (uint32_t i = 0; i < kPiece / 8; ++i) {
-                    const uint4 x = p4[i];
-                    const uint32_t h[4] = {x.x, x.y, x.z, x.w};
-#pragma unroll
-                    for (uint32_t t = 0; t < 4; ++t) {
-                        wv[8 * i + 2 * t] = hbase + (h[t] & 0xFFFFu);
-                        wv[8 * i + 2 * t + 1] = hbase + (h[t] >> 16);
-                    }
-                }
+            for (uint32_t j = 0; j < kPiece / 4; ++j) {
+                const uint4 x = p4[j];
+                wv[4 * j] = x.x;
+                wv[4 * j + 1] = x.y;
+                wv[4 * j + 2] = x.z;
+                wv[4 * j + 3] = x.w;
             }
             uint32_t hits = 0;
             // element i of the piece belongs to the suffix iff start + i - first < stop - first
@@ -371,6 +344,203 @@ __device__ __forceinline__ uint32_t run_batch(uint32_t eb, uint32_t e1, const Se
         if (ws.cnt[lane]) atomicAdd(&tpv[ws.tag[lane]], (unsigned long long)ws.cnt[lane]);
         wave_lds_sync();
     }
+    return hits_total;
+}
+
+// LDS access by byte address (32-bit LDS pointers)
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+__device__ __forceinline__ uint32_t lds_word(uint32_t addr) {
+    return *(const lds_u32 *)(uintptr_t)addr;
+}
+__device__ __forceinline__ uint32_t lds_addr(const uint32_t *p) {
+    return (uint32_t)(uintptr_t)(const lds_u32 *)p;
+}
+
+// ------------------------------------------------------------------ totals streaming
+//
+// Total counts stream a segment in two parts: its entries below rank hbase from col (32-bit
+// pieces of kPiece entries from 4-aligned positions), and its entries >= hbase from hcol as
+// 16-bit offsets from hbase (pieces of kPiece entries from 8-aligned positions).  In hcol every
+// row's part starts at an 8-aligned position and is followed by zeros up to the next multiple
+// of 8 and 8 more, so a piece never reaches another row.
+//
+// Masked probes test only the entries inside the segment.  Unmasked probes test every entry
+// of a piece: the entries of u's row before the segment are ranks up to the middle vertex
+// (or up to u's first panel vertex), and the padding zeros stand for rank hbase; the probes
+// below are built so that none of these can hit.
+
+// Bitmap over the whole high region: bit x for rank hbase + x (x < 2^16, the wave's LDS
+// slice).  For middle vertices v >= hbase only: N+(v) lies in (v, n), so neither a rank <= v
+// nor hbase is ever set.
+struct HighBitmapProbe {
+    uint32_t base;  // LDS byte address of the slice: a multiple of its 8 KiB
+    static constexpr bool kLow = false;
+    static constexpr bool kMaskHigh = false;
+    static constexpr bool kPanel = false;
+    // bits of the two entries of a packed pair of 16-bit entries: word x >> 5 is at byte
+    // ((x >> 3) & 0x1ffc) | base, and the bit offset of v_bfe is the low 5 bits of its
+    // operand, so the low entry needs no extraction
+    __device__ __forceinline__ uint32_t bits2(uint32_t pr) const {
+        const uint32_t lo = __builtin_amdgcn_ubfe(lds_word(((pr >> 3) & 0x1ffcu) | base), pr, 1u);
+        const uint32_t hi =
+            __builtin_amdgcn_ubfe(lds_word(((pr >> 19) & 0x1ffcu) | base), pr >> 16, 1u);
+        return lo + hi;
+    }
+};
+
+// Panel table over ranks [P, n) (as PanelProbe) read with 16-bit entries: rank hbase + x is
+// word x - c (c = P - hbase), ranks below P saturate onto word 0 (rank P, in no out-list of
+// the panel), and no entry exceeds word n - 1 - P.  An entry of u's row up to u's first panel
+// vertex P + j only matches panel vertices below P + j, none of which is in u's mask.
+struct PanelHighProbe {
+    const uint32_t *m;
+    uint32_t c;
+    static constexpr bool kLow = false;
+    static constexpr bool kMaskHigh = false;
+    static constexpr bool kPanel = true;
+    __device__ __forceinline__ uint32_t count(uint32_t x, uint32_t r) const {
+        const uint32_t o = x > c ? x - c : 0u;
+        return __popc(m[o] & r);
+    }
+};
+
+// hits of the entries wv[i] at positions start + i that lie in [first, stop)
+template <class Probe>
+__device__ __forceinline__ uint32_t masked_hits(const Probe &probe, const uint32_t (&wv)[kPiece],
+                                                uint32_t start, uint32_t first, uint32_t stop) {
+    const uint32_t lo_i = first > start ? first - start : 0u;
+    const uint32_t hi_i = min(stop - start, kPiece);
+    const uint32_t hmask = hi_i >= 32u ? ~0u : ((1u << hi_i) - 1u);
+    const uint32_t mask = hmask & ~((1u << lo_i) - 1u);
+    uint32_t packed = 0;
+    if constexpr (Probe::kList) {
+        // the piece's lookups as binary searches in lockstep (the list length is uniform)
+        uint32_t base[kPiece];
+#pragma unroll
+        for (uint32_t i = 0; i < kPiece; ++i) base[i] = 0;
+        for (uint32_t n_left = probe.d; n_left > 1;) {
+            const uint32_t half = n_left >> 1;
+#pragma unroll
+            for (uint32_t i = 0; i < kPiece; ++i)
+                base[i] = probe.list[base[i] + half - 1] < wv[i] ? base[i] + half : base[i];
+            n_left -= half;
+        }
+#pragma unroll
+        for (uint32_t i = 0; i < kPiece; ++i) {
+            base[i] += probe.list[base[i]] < wv[i] ? 1u : 0u;
+            packed |= (probe.list[min(base[i], probe.d - 1u)] == wv[i] ? 1u : 0u) << i;
+        }
+    } else {
+#pragma unroll
+        for (uint32_t i = 0; i < kPiece; ++i) packed |= probe.bit(wv[i]) << i;
+    }
+    return __popc(packed & mask);
+}
+
+// The calling wave streams segments [eb, min(eb + 64, e1)) of the current item through the
+// probe for total counts and returns this lane's hits.  A segment is the col range [b, en)
+// whose entries from hb on are ranks >= hbase, found in hcol from position h; probes without
+// kLow are only given segments with hb == b.
+template <class Probe, class Segs>
+__device__ __forceinline__ uint32_t run_batch_t(uint32_t eb, uint32_t e1, const Segs &segs,
+                                                const uint32_t *__restrict__ col,
+                                                const uint16_t *__restrict__ hcol,
+                                                uint32_t hbase, const Probe &probe,
+                                                WaveScratch &ws) {
+    const uint32_t lane = lane_id();
+    const uint32_t e = eb + lane;
+    uint32_t b = 0, hb = 0, en = 0, h = 0;
+    if (e < e1) segs.get_t(e, b, hb, en, h);
+    const uint32_t a0 = b & ~3u;
+    const uint32_t pl = (Probe::kLow && hb > b) ? (hb - a0 + kPiece - 1) / kPiece : 0u;
+    const uint32_t hl = en - hb;
+    const uint32_t ph = hl ? (h + hl - (h & ~7u) + kPiece - 1) / kPiece : 0u;
+    const uint32_t p = pl + ph;
+    const uint32_t incl = wave_incl_scan(p);
+    const uint32_t Q = wave_bcast(incl, kWave - 1);
+    ws.off[lane] = incl - p;
+    ws.cnt[lane] = pl;
+    ws.aux[lane] = h;
+    if constexpr (Probe::kLow) {
+        ws.beg[lane] = a0;
+        ws.first[lane] = b;
+        ws.end[lane] = hb;
+    }
+    if constexpr (Probe::kMaskHigh) ws.tag[lane] = h + hl;
+    if constexpr (Probe::kPanel) ws.tag[lane] = e < e1 ? segs.mask(e) : 0u;
+    wave_lds_sync();
+    uint32_t hits_total = 0;
+    for (uint32_t q0 = 0; q0 < Q; q0 += kWave) {
+        const uint32_t q = q0 + lane;
+        if (q < Q) {
+            uint32_t k = 0;
+#pragma unroll
+            for (uint32_t step = 32; step; step >>= 1)
+                if (ws.off[k + step] <= q) k += step;
+            const uint32_t j = q - ws.off[k];
+            const uint32_t pk = ws.cnt[k];
+            uint32_t hits = 0;
+            if constexpr (Probe::kMaskHigh) {
+                // masked probes: the loads of either part, then one evaluation of the piece
+                uint32_t start, first, stop;
+                uint32_t wv[kPiece];
+                if (Probe::kLow && j < pk) {
+                    start = ws.beg[k] + j * kPiece;
+                    first = ws.first[k];
+                    stop = ws.end[k];
+                    const uint4 *p4 = reinterpret_cast<const uint4 *>(col + start);
+#pragma unroll
+                    for (uint32_t i = 0; i < kPiece / 4; ++i) {
+                        const uint4 x = p4[i];
+                        wv[4 * i] = x.x;
+                        wv[4 * i + 1] = x.y;
+                        wv[4 * i + 2] = x.z;
+                        wv[4 * i + 3] = x.w;
+                    }
+                } else {
+                    first = ws.aux[k];
+                    stop = ws.tag[k];
+                    start = (first & ~7u) + (j - pk) * kPiece;
+                    const uint4 *p4 = reinterpret_cast<const uint4 *>(hcol + start);
+#pragma unroll
+                    for (uint32_t i = 0; i < kPiece / 8; ++i) {
+                        const uint4 x = p4[i];
+                        const uint32_t h2[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+                        for (uint32_t t = 0; t < 4; ++t) {
+                            wv[8 * i + 2 * t] = hbase + (h2[t] & 0xFFFFu);
+                            wv[8 * i + 2 * t + 1] = hbase + (h2[t] >> 16);
+                        }
+                    }
+                }
+                hits = masked_hits(probe, wv, start, first, stop);
+            } else {
+                // unmasked probes: 16-bit pieces only
+                const uint32_t start = (ws.aux[k] & ~7u) + (j - pk) * kPiece;
+                const uint4 *p4 = reinterpret_cast<const uint4 *>(hcol + start);
+                uint32_t pr[kPiece / 2];
+#pragma unroll
+                for (uint32_t i = 0; i < kPiece / 8; ++i) {
+                    const uint4 x = p4[i];
+                    pr[4 * i] = x.x;
+                    pr[4 * i + 1] = x.y;
+                    pr[4 * i + 2] = x.z;
+                    pr[4 * i + 3] = x.w;
+                }
+                if constexpr (Probe::kPanel) {
+                    const uint32_t r = ws.tag[k];
+#pragma unroll
+                    for (uint32_t i = 0; i < kPiece / 2; ++i)
+                        hits += probe.count(pr[i] & 0xFFFFu, r) + probe.count(pr[i] >> 16, r);
+                } else {
+#pragma unroll
+                    for (uint32_t i = 0; i < kPiece / 2; ++i) hits += probe.bits2(pr[i]);
+                }
+            }
+            hits_total += hits;
+        }
+    }
+    wave_lds_sync();
     return hits_total;
 }
 
@@ -663,15 +833,17 @@ __global__ __launch_bounds__(kThreads) void k_count(
     uint32_t *__restrict__ queue_b, unsigned long long *__restrict__ total,
     unsigned long long *__restrict__ tpv, uint32_t n1, uint32_t p0, uint32_t wave_bits,
     uint32_t block_bits, uint32_t block_list, uint32_t kitem_a, uint32_t kitem_b,
-    const uint16_t *__restrict__ col16, uint32_t hbase, const int32_t *__restrict__ status) {
-    __shared__ uint32_t s_mem[kLdsWords];
+    const uint16_t *__restrict__ hcol, const uint32_t *__restrict__ chigh, uint32_t hbase,
+    const int32_t *__restrict__ status) {
+    // 8 KiB aligned: a wave slice's base has zero low bits, so bitmap addresses OR it in
+    __shared__ __attribute__((aligned(kSliceWords * 4))) uint32_t s_mem[kLdsWords];
     __shared__ WaveScratch s_ws[kWaves];
     __shared__ uint32_t s_item;
     if (*status) return;
     const uint32_t t = threadIdx.x, w = t / kWave, lane = lane_id();
     WaveScratch &ws = s_ws[w];
     // totals: outside the panels cmask holds where a suffix's entries >= hbase start
-    const InEdgeSegs segs{cbeg, cend, src, cmask};
+    const InEdgeSegs segs{cbeg, cend, src, cmask, chigh};
     for (uint32_t i = t; i < kLdsWords; i += kThreads) s_mem[i] = 0;
     uint64_t acc = 0;
 
@@ -693,12 +865,17 @@ __global__ __launch_bounds__(kThreads) void k_count(
                     for (uint32_t i = row_ptr[P + j] + lane; i < row_ptr[P + j + 1]; i += kWave)
                         atomicOr(&s_mem[col[i] - P], 1u << j);
                 __syncthreads();
-                const PanelProbe probe{s_mem, P, n1 - 2 - P};
-                const PanelSegs psegs{cbeg, cend, cmask};
+                const PanelSegs psegs{cbeg, cend, cmask, chigh};
                 uint32_t cnt = 0;
-                for (uint32_t eb = first; eb < it.e1; eb += step)
-                    cnt += run_batch<false, true>(eb, it.e1, psegs, col, probe, ws, nullptr,
-                                                  tpv, col16, hbase);
+                if (P >= hbase) {  // the suffixes are in hcol
+                    const PanelHighProbe probe{s_mem, P - hbase};
+                    for (uint32_t eb = first; eb < it.e1; eb += step)
+                        cnt += run_batch_t(eb, it.e1, psegs, col, hcol, hbase, probe, ws);
+                } else {  // no high region: 32-bit entries
+                    const PanelProbe probe{s_mem, P, n1 - 2 - P};
+                    for (uint32_t eb = first; eb < it.e1; eb += step)
+                        cnt += run_batch<false>(eb, it.e1, psegs, col, probe, ws, nullptr, tpv);
+                }
                 acc += cnt;
                 __syncthreads();
                 for (uint32_t j = w; j < np; j += kWaves)
@@ -764,20 +941,29 @@ __global__ __launch_bounds__(kThreads) void k_count(
         uint32_t cnt = 0;
         if (mode == 0) {
             const BitmapProbe probe{s_mem, lo, span};
-            for (uint32_t eb = first; eb < it.e1; eb += step)
-                cnt += run_batch<PV, !PV>(eb, it.e1, segs, col, probe, ws, nullptr, tpv, col16,
-                                          hbase);
+            for (uint32_t eb = first; eb < it.e1; eb += step) {
+                if constexpr (PV)
+                    cnt += run_batch<true>(eb, it.e1, segs, col, probe, ws, nullptr, tpv);
+                else
+                    cnt += run_batch_t(eb, it.e1, segs, col, hcol, hbase, probe, ws);
+            }
         } else if (mode == 1) {
             const ListProbe probe{s_mem, it.d};
             uint32_t *tc = PV ? s_mem + kBlockListPV : nullptr;
-            for (uint32_t eb = first; eb < it.e1; eb += step)
-                cnt += run_batch<PV, !PV>(eb, it.e1, segs, col, probe, ws, tc, tpv, col16,
-                                          hbase);
+            for (uint32_t eb = first; eb < it.e1; eb += step) {
+                if constexpr (PV)
+                    cnt += run_batch<true>(eb, it.e1, segs, col, probe, ws, tc, tpv);
+                else
+                    cnt += run_batch_t(eb, it.e1, segs, col, hcol, hbase, probe, ws);
+            }
         } else {
             const ListProbe probe{col + it.r0, it.d};
-            for (uint32_t eb = first; eb < it.e1; eb += step)
-                cnt += run_batch<PV, !PV>(eb, it.e1, segs, col, probe, ws, nullptr, tpv, col16,
-                                          hbase);
+            for (uint32_t eb = first; eb < it.e1; eb += step) {
+                if constexpr (PV)
+                    cnt += run_batch<true>(eb, it.e1, segs, col, probe, ws, nullptr, tpv);
+                else
+                    cnt += run_batch_t(eb, it.e1, segs, col, hcol, hbase, probe, ws);
+            }
         }
         if (PV) {
             uint64_t wave_hits = wave_sum_u64(cnt);
@@ -804,6 +990,9 @@ __global__ __launch_bounds__(kThreads) void k_count(
 
     // phase 2: wave items, each wave in its own LDS slice
     uint32_t *mem = s_mem + w * kSliceWords;
+    // the high-region bitmap ORs the slice's address into its word offsets (requested by the
+    // alignment of s_mem; otherwise the span bitmap takes its items)
+    const bool slices_aligned = (lds_addr(s_mem) & (kSliceWords * 4 - 1)) == 0;
     const uint32_t n_items_a = *n_items_a_ptr;
     WaveQueue<kClaimWave> wq;
     for (uint32_t q; wq.pop(queue_a, n_items_a, q);) {
@@ -813,7 +1002,20 @@ __global__ __launch_bounds__(kThreads) void k_count(
         if (!PV) {
             const uint32_t lo = col[it.r0];
             const uint32_t span = col[it.r0 + it.d - 1] - lo;
-            if (span < wave_bits) {  // bitmap over the span
+            if (span < wave_bits && it.v >= hbase && slices_aligned) {
+                // bitmap over the whole high region (N+(v) lies in it; the slice holds 2^16
+                // bits); every in-edge suffix is high
+                for (uint32_t i = lane; i < it.d; i += kWave) {
+                    const uint32_t x = col[it.r0 + i] - hbase;
+                    atomicOr(&mem[x >> 5], 1u << (x & 31u));
+                }
+                wave_lds_sync();
+                const HighBitmapProbe probe{lds_addr(mem)};
+                for (uint32_t eb = it.e0; eb < it.e1; eb += kWave)
+                    cnt += run_batch_t(eb, it.e1, segs, col, hcol, hbase, probe, ws);
+                for (uint32_t i = lane; i < it.d; i += kWave)
+                    mem[(col[it.r0 + i] - hbase) >> 5] = 0;
+            } else if (span < wave_bits) {  // bitmap over the span
                 for (uint32_t i = lane; i < it.d; i += kWave) {
                     const uint32_t o = col[it.r0 + i] - lo;
                     atomicOr(&mem[o >> 5], 1u << (o & 31u));
@@ -821,8 +1023,7 @@ __global__ __launch_bounds__(kThreads) void k_count(
                 wave_lds_sync();
                 const BitmapProbe probe{mem, lo, span};
                 for (uint32_t eb = it.e0; eb < it.e1; eb += kWave)
-                    cnt += run_batch<false, true>(eb, it.e1, segs, col, probe, ws, nullptr, tpv,
-                                                  col16, hbase);
+                    cnt += run_batch_t(eb, it.e1, segs, col, hcol, hbase, probe, ws);
                 for (uint32_t i = lane; i < it.d; i += kWave)
                     mem[(col[it.r0 + i] - lo) >> 5] = 0;
             } else {  // a wide span, but a list that fits the slice (see k_items)
@@ -830,8 +1031,7 @@ __global__ __launch_bounds__(kThreads) void k_count(
                 wave_lds_sync();
                 const ListProbe probe{mem, it.d};
                 for (uint32_t eb = it.e0; eb < it.e1; eb += kWave)
-                    cnt += run_batch<false, true>(eb, it.e1, segs, col, probe, ws, nullptr, tpv,
-                                                  col16, hbase);
+                    cnt += run_batch_t(eb, it.e1, segs, col, hcol, hbase, probe, ws);
                 for (uint32_t i = lane; i < it.d; i += kWave) mem[i] = 0;
             }
             wave_lds_sync();
@@ -1100,7 +1300,7 @@ uint32_t count_block_span() { return kBlockBits; }
 uint32_t count_block_list(bool per_vertex) { return per_vertex ? kBlockListPV : kBlockList; }
 uint32_t count_item_edges_wave() { return kItemEdgesWave; }
 uint32_t count_item_edges_block() { return kItemEdgesBlock; }
-uint32_t count_col_pad_bytes() { return kPiece * 4; }  // also covers col16's kPiece * 2
+uint32_t count_col_pad_bytes() { return kPiece * 4; }
 uint32_t count_panel() { return kPanel; }
 uint32_t count_wgs_per_cu() { return kWgsPerCu; }
 uint32_t count_light_max() { return kLightMax; }
@@ -1123,13 +1323,13 @@ hipError_t launch_count(const CountArgs &x, bool per_vertex, hipStream_t s) {
                            x.cend, x.src, x.cmask, x.item_v_a, x.item_off_a, x.n_items_a,
                            x.item_v_b, x.item_off_b, x.n_items_b, x.queue_a, x.queue_b, x.total,
                            x.tpv, x.n1, x.p0, x.wave_bits, x.block_bits, x.block_list,
-                           x.kitem_a, x.kitem_b, x.col16, x.hbase, x.status);
+                           x.kitem_a, x.kitem_b, x.hcol, x.chigh, x.hbase, x.status);
     else
         hipLaunchKernelGGL(k_count<false>, grid, block, 0, s, x.row_ptr, x.col, x.cptr, x.cbeg,
                            x.cend, x.src, x.cmask, x.item_v_a, x.item_off_a, x.n_items_a,
                            x.item_v_b, x.item_off_b, x.n_items_b, x.queue_a, x.queue_b, x.total,
                            x.tpv, x.n1, x.p0, x.wave_bits, x.block_bits, x.block_list,
-                           x.kitem_a, x.kitem_b, x.col16, x.hbase, x.status);
+                           x.kitem_a, x.kitem_b, x.hcol, x.chigh, x.hbase, x.status);
     return hipGetLastError();
 }
 

@@ -93,10 +93,12 @@ int device_cu_count();
 // counting kernels (count.hip)
 struct CountArgs {
     const uint32_t *row_ptr, *col, *cptr, *cbeg, *cend, *src, *cmask;  // src: row of a CSR entry
-    // col as 16-bit offsets from rank hbase (meaningful for entries >= hbase); totals stream
-    // every in-edge suffix's entries >= hbase from here (cmask: where they start)
-    const uint16_t *col16;
-    uint32_t hbase;
+    // every row's entries >= rank hbase as 16-bit offsets from hbase, each row's part 8-aligned
+    // and followed by at least 8 zeros; totals stream every in-edge suffix's entries >= hbase
+    // from here (outside the panels cmask holds where they start in col; chigh: in hcol)
+    const uint16_t *hcol;
+    const uint32_t *chigh;
+    uint32_t hbase;  // n: no high region
     const uint32_t *item_v_a, *item_off_a, *n_items_a;
     const uint32_t *item_v_b, *item_off_b, *n_items_b;
     uint32_t *queue_a, *queue_b;

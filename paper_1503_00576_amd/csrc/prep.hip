@@ -320,15 +320,13 @@ __global__ void k_both_check(const uint32_t *__restrict__ counter, uint32_t expe
 constexpr uint32_t kCsrKeys = 4;
 
 // Unzip the sorted keys into the neighbour array (Section 3.2, step 7) and mark where every
-// non-empty row starts and ends; row lengths and their prefix sum give the node array.  The
-// neighbours are also written as 16-bit offsets from rank hbase (col16; only entries >= hbase
-// are meaningful), and hrow[u] receives the position of the first entry >= hbase of row u
-// (left untouched, all ones from the caller's fill, when the row has none).
+// non-empty row starts and ends; row lengths and their prefix sum give the node array.
+// hrow[u] receives the position of the first entry >= hbase of row u (left untouched, all
+// ones from the caller's fill, when the row has none).
 __global__ void k_csr(const uint64_t *__restrict__ keys, uint32_t mf, uint32_t n, int b,
-                      uint32_t hbase, uint32_t *__restrict__ col, uint16_t *__restrict__ col16,
-                      uint32_t *__restrict__ src, uint32_t *__restrict__ rs,
-                      uint32_t *__restrict__ re, uint32_t *__restrict__ hrow,
-                      int32_t *__restrict__ status) {
+                      uint32_t hbase, uint32_t *__restrict__ col, uint32_t *__restrict__ src,
+                      uint32_t *__restrict__ rs, uint32_t *__restrict__ re,
+                      uint32_t *__restrict__ hrow, int32_t *__restrict__ status) {
     if (*status) return;
     // kCsrKeys keys a block apart per thread, all loaded before any is used
     const uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x * kCsrKeys + threadIdx.x;
@@ -347,7 +345,6 @@ __global__ void k_csr(const uint64_t *__restrict__ keys, uint32_t mf, uint32_t n
         const uint32_t s = (uint32_t)(k[t] >> b);
         const uint32_t c = (uint32_t)(k[t] & ((1ull << b) - 1));
         col[i] = c;
-        col16[i] = (uint16_t)(c - hbase);
         src[i] = s;
         if (s >= n) continue;  // only for invalid input, reported elsewhere
         const bool row_start = i == 0 || (uint32_t)(kp[t] >> b) != s;
@@ -366,6 +363,19 @@ __global__ void k_rowlen(const uint32_t *__restrict__ rs, const uint32_t *__rest
     uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r > n) return;
     len[r] = r < n ? re[r] - rs[r] : 0u;
+}
+
+// Room of every row's entries >= hbase in hcol: none for a row without such entries, else
+// their number rounded up to a multiple of 8, plus 8 zeros (a 16-entry piece read from an
+// 8-aligned position inside the row's part never leaves it).  Entry n is 0, so that the
+// exclusive scan ends with the total.
+__global__ void k_hlen(const uint32_t *__restrict__ row_ptr, const uint32_t *__restrict__ hrow,
+                       uint32_t n, uint32_t *__restrict__ hlen) {
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r > n) return;
+    uint32_t len = 0;
+    if (r < n && hrow[r] != ~0u) len = ((row_ptr[r + 1] - hrow[r] + 7u) & ~7u) + 8u;
+    hlen[r] = len;
 }
 
 // Rank span of every out-list from rank v0 on (the panel region, whose spans k_panel_range
@@ -408,20 +418,22 @@ __global__ void k_panel_range(const uint64_t *__restrict__ vr, uint32_t n, uint3
 // per panel, keyed by its first rank P: only the first in-edge of each run of u's
 // out-neighbours inside the panel is kept (it stands for the whole run), tested against the
 // panel's span (a small table).  eu[e] = (end of u's row, mask of the run's panel vertices
-// for a kept panel entry; for any other kept entry the position where the suffix's entries
-// >= hbase start, hrow[u] from k_csr).  In-edges from hubs (u >= h0) are left out: their
-// triangles are counted on the matrix cores.
+// for a kept panel entry or, for any other kept entry, the col position where the suffix's
+// entries >= hbase start, the hcol position where they start).  In-edges from hubs (u >= h0)
+// are left out: their triangles are counted on the matrix cores.  Every entry >= hbase is
+// also written to its row's part of hcol (hrow and hstart: k_csr, k_hlen and a scan).
 // Each thread takes kCscEdges entries a block apart and issues every stage's loads for all of
 // them before using any (the stages depend on each other: entry -> row -> row end).
 constexpr uint32_t kCscEdges = 4;
 
 __global__ void k_csc_keys(const uint32_t *__restrict__ col, const uint32_t *__restrict__ src,
                            const uint32_t *__restrict__ row_ptr,
-                           const uint32_t *__restrict__ hrow, uint32_t hbase,
+                           const uint32_t *__restrict__ hrow,
+                           const uint32_t *__restrict__ hstart, uint32_t hbase,
                            const uint64_t *__restrict__ pr, uint32_t mf, uint32_t n,
                            uint32_t nblk, uint32_t p0, uint32_t kp, uint32_t h0,
-                           uint64_t *__restrict__ keys, uint2 *__restrict__ eu,
-                           const int32_t *__restrict__ status) {
+                           uint64_t *__restrict__ keys, uint4 *__restrict__ eu,
+                           uint16_t *__restrict__ hcol, const int32_t *__restrict__ status) {
     if (*status) return;
     // kp is a power of two; row blocks are rare (nblk > 1 only when asked for)
     const uint32_t kp_shift = __builtin_ctz(kp);
@@ -436,13 +448,14 @@ __global__ void k_csc_keys(const uint32_t *__restrict__ col, const uint32_t *__r
         prv[k] = (in && e > 0) ? col[e - 1] : 0u;
         nxt[k] = (in && e + 1 < mf) ? col[e + 1] : 0u;
     }
-    uint32_t rb[kCscEdges], re[kCscEdges], hr[kCscEdges];
+    uint32_t rb[kCscEdges], re[kCscEdges], hr[kCscEdges], hs[kCscEdges];
 #pragma unroll
     for (uint32_t k = 0; k < kCscEdges; ++k) {
         const bool in = e0 + (uint64_t)k * blockDim.x < mf;
         rb[k] = in ? row_ptr[u[k]] : 0u;
         re[k] = in ? row_ptr[u[k] + 1] : 0u;
-        hr[k] = (in && v[k] < hbase) ? hrow[u[k]] : 0u;
+        hr[k] = in ? hrow[u[k]] : 0u;
+        hs[k] = in ? hstart[u[k]] : 0u;
     }
     uint32_t last[kCscEdges];
     uint64_t r[kCscEdges];
@@ -458,8 +471,10 @@ __global__ void k_csc_keys(const uint32_t *__restrict__ col, const uint32_t *__r
         const uint64_t e = e0 + (uint64_t)k * blockDim.x;
         if (e >= mf) continue;
         const uint32_t end_u = re[k];
+        // the row's entries >= hbase in hcol (hr[k] <= e: the row is ascending)
+        if (v[k] >= hbase) hcol[hs[k] + ((uint32_t)e - hr[k])] = (uint16_t)(v[k] - hbase);
         uint64_t c = (uint64_t)nblk * (n + 1);
-        uint32_t mask = 1u;
+        uint32_t mask = 1u, hpos = hs[k];
         if (e + 1 < end_u && u[k] < h0) {  // triangles whose lowest vertex is a hub: hub.hip
             uint32_t list = v[k];
             bool keep = true, run_start = false;
@@ -472,8 +487,11 @@ __global__ void k_csc_keys(const uint32_t *__restrict__ col, const uint32_t *__r
             if (keep) {
                 const uint64_t blk = nblk == 1 ? 0 : (e * nblk) / mf;
                 c = blk * (n + 1) + list;
-                // outside the panels: where the suffix's entries >= hbase start
-                if (v[k] < p0) mask = v[k] >= hbase ? (uint32_t)e + 1u : min(hr[k], end_u);
+                // where the suffix's entries >= hbase start, in col (outside the panels, in
+                // place of the mask) and in hcol; a panel suffix is high throughout
+                const uint32_t hb = v[k] >= hbase ? (uint32_t)e + 1u : min(hr[k], end_u);
+                if (v[k] < p0) mask = hb;
+                if (hb < end_u) hpos = hs[k] + (hb - hr[k]);
                 if (run_start) {  // the run's mask: u's consecutive entries inside the panel
                     mask = 1u << (v[k] - list);
                     for (uint64_t x = e + 1; x < end_u; x += 4) {  // four loads at a time
@@ -492,18 +510,20 @@ __global__ void k_csc_keys(const uint32_t *__restrict__ col, const uint32_t *__r
             }
         }
         keys[e] = (c << 32) | e;
-        eu[e] = make_uint2(end_u, mask);
+        eu[e] = make_uint4(end_u, mask, hpos, 0u);
     }
 }
 
-// The lists themselves: in-edge u -> v at CSR position e contributes the suffix [e + 1, end_u)
-// and, in a panel list, the mask of u's run of panel vertices (k_csc_keys); list c occupies
-// sorted positions [rs[c], re[c]) (useful in-edges only; rs and re zeroed beforehand).
+// The lists themselves: in-edge u -> v at CSR position e contributes the suffix [e + 1, end_u),
+// in a panel list the mask of u's run of panel vertices and otherwise the col position where
+// the suffix's entries >= hbase start, and the hcol position where they start (k_csc_keys);
+// list c occupies sorted positions [rs[c], re[c]) (useful in-edges only; rs and re zeroed
+// beforehand).
 __global__ void k_csc_final(const uint64_t *__restrict__ keys, uint32_t mf, uint64_t lists,
-                            const uint2 *__restrict__ eu, uint32_t *__restrict__ cbeg,
+                            const uint4 *__restrict__ eu, uint32_t *__restrict__ cbeg,
                             uint32_t *__restrict__ cend, uint32_t *__restrict__ cmask,
-                            uint32_t *__restrict__ rs, uint32_t *__restrict__ re,
-                            const int32_t *__restrict__ status) {
+                            uint32_t *__restrict__ chigh, uint32_t *__restrict__ rs,
+                            uint32_t *__restrict__ re, const int32_t *__restrict__ status) {
     if (*status) return;
     uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= mf) return;
@@ -513,10 +533,11 @@ __global__ void k_csc_final(const uint64_t *__restrict__ keys, uint32_t mf, uint
     if (j == 0 || (keys[j - 1] >> 32) != c) rs[c] = j;
     if (j == mf - 1 || (keys[j + 1] >> 32) != c) re[c] = j + 1;
     const uint32_t e = (uint32_t)k;
-    const uint2 x = eu[e];
+    const uint4 x = eu[e];
     cbeg[j] = e + 1;
     cend[j] = x.x;
     cmask[j] = x.y;
+    chigh[j] = x.z;
 }
 
 // Work items of the counting kernel.  A vertex's in-edges are cut into chunks; the chunks go
