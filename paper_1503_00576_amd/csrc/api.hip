@@ -28,7 +28,7 @@ __global__ void k_orient_cells(const int2 *, uint64_t, uint32_t, const uint32_t 
 __global__ void k_both_check(const uint32_t *, uint32_t, int32_t *);
 __global__ void k_csr(const uint64_t *, uint32_t, uint32_t, int, uint32_t, uint32_t *,
                       uint32_t *, uint32_t *, uint32_t *, uint32_t *, int32_t *);
-__global__ void k_hlen(const uint32_t *, const uint32_t *, uint32_t, uint32_t *);
+__global__ void k_hlen(const uint32_t *, const uint32_t *, uint32_t, uint32_t, uint32_t *);
 __global__ void k_rowlen(const uint32_t *, const uint32_t *, uint32_t, uint32_t *);
 __global__ void k_vrange(const uint32_t *, const uint32_t *, uint32_t, uint32_t, uint64_t *);
 __global__ void k_panel_range(const uint64_t *, uint32_t, uint32_t, uint32_t, uint32_t,
@@ -210,11 +210,11 @@ static bool make_layout(int64_t n, int64_t m, uint32_t flags, const tc_options *
     L.panels = ceil_div(L.n - L.p0, count_panel());
     // The 16-bit region holds the panel region (whose streamed entries are all panel ranks or
     // higher) and spans at most 2^16 ranks (panel regions are smaller).  Its rows' parts in
-    // hcol take at most 15 padding entries each; 32-bit positions must address them all, or
-    // there is no region (as for high_ranks = 0).
+    // hcol take at most 7 + count_hcol_pad() padding entries each; 32-bit positions must
+    // address them all, or there is no region (as for high_ranks = 0).
     {
         const uint64_t rows = (uint64_t)n < L.mf ? (uint64_t)n : L.mf;
-        L.hcap = ((uint64_t)L.mf + 15 * rows + 64 + 7) & ~7ull;
+        L.hcap = ((uint64_t)L.mf + (7 + count_hcol_pad()) * rows + 64 + 7) & ~7ull;
         if (o.high_ranks == 0 || L.hcap >= (1ull << 32)) {
             L.hbase = L.n;
             L.hcap = 64;
@@ -442,7 +442,7 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
     uint32_t *hstart = at<uint32_t>(ws, L.hstart);
     uint16_t *hcol = at<uint16_t>(ws, L.hcol);
     hipLaunchKernelGGL(k_hlen, dim3(grid_for(n1, 256)), dim3(256), 0, s, row_ptr, hrow, n,
-                       rowlen);
+                       count_hcol_pad(), rowlen);
     TC_LAUNCH_CHECK();
     TC_HIP(scan_exclusive_u32(rowlen, hstart, n1, scan_scr, s));
     TC_HIP(fill_u32((uint32_t *)hcol, 0u, L.hcap / 2, s));

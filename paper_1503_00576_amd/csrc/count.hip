@@ -34,6 +34,8 @@
 namespace tc {
 
 constexpr uint32_t kPiece = 16;
+// pieces of the unmasked 16-bit probes (hcol rows carry the padding they need)
+constexpr uint32_t kPieceHigh = 32;
 constexpr int kThreads = 1024;
 constexpr int kWgsPerCu = 1;  // workgroups per CU the LDS footprint allows
 constexpr int kWaves = kThreads / kWave;
@@ -360,9 +362,10 @@ __device__ __forceinline__ uint32_t lds_addr(const uint32_t *p) {
 //
 // Total counts stream a segment in two parts: its entries below rank hbase from col (32-bit
 // pieces of kPiece entries from 4-aligned positions), and its entries >= hbase from hcol as
-// 16-bit offsets from hbase (pieces of kPiece entries from 8-aligned positions).  In hcol every
-// row's part starts at an 8-aligned position and is followed by zeros up to the next multiple
-// of 8 and 8 more, so a piece never reaches another row.
+// 16-bit offsets from hbase (pieces of kPiece, or kPieceHigh for unmasked probes, entries from
+// 8-aligned positions).  In hcol every row's part starts at an 8-aligned position and is
+// followed by zeros up to the next multiple of 8 and kPieceHigh - 8 more, so a piece never
+// reaches another row.
 //
 // Masked probes test only the entries inside the segment.  Unmasked probes test every entry
 // of a piece: the entries of u's row before the segment are ranks up to the middle vertex
@@ -453,8 +456,10 @@ __device__ __forceinline__ uint32_t run_batch_t(uint32_t eb, uint32_t e1, const 
     if (e < e1) segs.get_t(e, b, hb, en, h);
     const uint32_t a0 = b & ~3u;
     const uint32_t pl = (Probe::kLow && hb > b) ? (hb - a0 + kPiece - 1) / kPiece : 0u;
+    // unmasked probes read longer pieces (the per-piece search and setup is their overhead)
+    constexpr uint32_t kPh = Probe::kMaskHigh ? kPiece : kPieceHigh;
     const uint32_t hl = en - hb;
-    const uint32_t ph = hl ? (h + hl - (h & ~7u) + kPiece - 1) / kPiece : 0u;
+    const uint32_t ph = hl ? (h + hl - (h & ~7u) + kPh - 1) / kPh : 0u;
     const uint32_t p = pl + ph;
     const uint32_t incl = wave_incl_scan(p);
     const uint32_t Q = wave_bcast(incl, kWave - 1);
@@ -516,11 +521,11 @@ __device__ __forceinline__ uint32_t run_batch_t(uint32_t eb, uint32_t e1, const 
                 hits = masked_hits(probe, wv, start, first, stop);
             } else {
                 // unmasked probes: 16-bit pieces only
-                const uint32_t start = (ws.aux[k] & ~7u) + (j - pk) * kPiece;
+                const uint32_t start = (ws.aux[k] & ~7u) + (j - pk) * kPh;
                 const uint4 *p4 = reinterpret_cast<const uint4 *>(hcol + start);
-                uint32_t pr[kPiece / 2];
+                uint32_t pr[kPh / 2];
 #pragma unroll
-                for (uint32_t i = 0; i < kPiece / 8; ++i) {
+                for (uint32_t i = 0; i < kPh / 8; ++i) {
                     const uint4 x = p4[i];
                     pr[4 * i] = x.x;
                     pr[4 * i + 1] = x.y;
@@ -530,11 +535,11 @@ __device__ __forceinline__ uint32_t run_batch_t(uint32_t eb, uint32_t e1, const 
                 if constexpr (Probe::kPanel) {
                     const uint32_t r = ws.tag[k];
 #pragma unroll
-                    for (uint32_t i = 0; i < kPiece / 2; ++i)
+                    for (uint32_t i = 0; i < kPh / 2; ++i)
                         hits += probe.count(pr[i] & 0xFFFFu, r) + probe.count(pr[i] >> 16, r);
                 } else {
 #pragma unroll
-                    for (uint32_t i = 0; i < kPiece / 2; ++i) hits += probe.bits2(pr[i]);
+                    for (uint32_t i = 0; i < kPh / 2; ++i) hits += probe.bits2(pr[i]);
                 }
             }
             hits_total += hits;
@@ -1301,6 +1306,7 @@ uint32_t count_block_list(bool per_vertex) { return per_vertex ? kBlockListPV : 
 uint32_t count_item_edges_wave() { return kItemEdgesWave; }
 uint32_t count_item_edges_block() { return kItemEdgesBlock; }
 uint32_t count_col_pad_bytes() { return kPiece * 4; }
+uint32_t count_hcol_pad() { return kPieceHigh - 8; }
 uint32_t count_panel() { return kPanel; }
 uint32_t count_wgs_per_cu() { return kWgsPerCu; }
 uint32_t count_light_max() { return kLightMax; }

@@ -124,6 +124,9 @@ uint32_t count_item_edges_block();  // default in-edges per workgroup item
 // bytes of padding `col` needs after its last element: a lane's aligned piece reads may run
 // up to one piece past the end of a list
 uint32_t count_col_pad_bytes();
+// zeros after every row's part of hcol beyond its rounding to 8 entries (a piece of the
+// unmasked probes read from an 8-aligned position inside the part never leaves it)
+uint32_t count_hcol_pad();
 // middle-vertex panels: consecutive ranks per panel, and the largest rank region the
 // counting kernel can handle as panels (its mask table must fit the workgroup's LDS)
 uint32_t count_panel();

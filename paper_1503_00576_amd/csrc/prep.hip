@@ -366,15 +366,15 @@ __global__ void k_rowlen(const uint32_t *__restrict__ rs, const uint32_t *__rest
 }
 
 // Room of every row's entries >= hbase in hcol: none for a row without such entries, else
-// their number rounded up to a multiple of 8, plus 8 zeros (a 16-entry piece read from an
-// 8-aligned position inside the row's part never leaves it).  Entry n is 0, so that the
-// exclusive scan ends with the total.
+// their number rounded up to a multiple of 8, plus `pad` zeros (the counting kernel's pieces,
+// read from 8-aligned positions inside the row's part, never leave it).  Entry n is 0, so that
+// the exclusive scan ends with the total.
 __global__ void k_hlen(const uint32_t *__restrict__ row_ptr, const uint32_t *__restrict__ hrow,
-                       uint32_t n, uint32_t *__restrict__ hlen) {
+                       uint32_t n, uint32_t pad, uint32_t *__restrict__ hlen) {
     const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r > n) return;
     uint32_t len = 0;
-    if (r < n && hrow[r] != ~0u) len = ((row_ptr[r + 1] - hrow[r] + 7u) & ~7u) + 8u;
+    if (r < n && hrow[r] != ~0u) len = ((row_ptr[r + 1] - hrow[r] + 7u) & ~7u) + pad;
     hlen[r] = len;
 }
 
