@@ -37,9 +37,8 @@ __global__ void k_csc_keys(const uint32_t *, const uint32_t *, const uint32_t *,
                            const uint32_t *, const uint32_t *, uint32_t, const uint64_t *,
                            uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t,
                            uint64_t *, uint4 *, uint16_t *, const int32_t *);
-__global__ void k_csc_final(const uint64_t *, uint32_t, uint64_t, const uint4 *, uint32_t *,
-                            uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t *,
-                            const int32_t *);
+__global__ void k_csc_final(const uint64_t *, uint32_t, uint64_t, uint32_t *, uint32_t *,
+                            uint32_t *, const int32_t *);
 __global__ void k_items(const uint32_t *, const uint32_t *, const uint32_t *, uint32_t, uint32_t,
                         uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t *,
                         uint32_t *,
@@ -73,8 +72,7 @@ int device_cu_count() {
 struct Layout {
     size_t ctl, part_hist, part_offs, part_scan, deg, perm, rank, keys_a, keys_b, sort_scratch,
         rs, re, rowlen, row_ptr, col, hcol, hrow, hstart, src, vrange, prange, eu, lrs, lre, cnt,
-        cptr, cbeg, cend, cmask, chigh, items[4], off[4], item_v[4], scan_scratch, tpv, hub_a,
-        hub_at, total_bytes;
+        cptr, cbeg, items[4], off[4], item_v[4], scan_scratch, tpv, hub_a, hub_at, total_bytes;
     uint32_t part_tiles;  // 0: degrees by atomics (inputs too large for the partition)
     int part_shift;
     int cell_shift;       // >= 0: edges also partitioned into cells for the orientation
@@ -277,9 +275,6 @@ static bool make_layout(int64_t n, int64_t m, uint32_t flags, const tc_options *
     L.cnt = take(l1 * 4);
     L.cptr = take(l1 * 4);
     L.cbeg = take((size_t)L.mf * 4);
-    L.cend = take((size_t)L.mf * 4);
-    L.cmask = take((size_t)L.mf * 4);
-    L.chigh = take((size_t)L.mf * 4);
     for (int k = 0; k < 4; ++k) {
         const uint32_t per = (k & 1) ? o.block_item_edges : o.wave_item_edges;
         L.items[k] = take(l1 * 4);
@@ -488,10 +483,8 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
                     onesweep));
     TC_HIP(fill_u32(lrs, 0u, l1, s));
     TC_HIP(fill_u32(lre, 0u, l1, s));
-    // one entry per thread: its gather is bound by the random-line rate, not by latency
     hipLaunchKernelGGL(k_csc_final, dim3(grid_for(mf, 256)), dim3(256), 0, s, cks, mf, L.lists,
-                       eu, at<uint32_t>(ws, L.cbeg), at<uint32_t>(ws, L.cend),
-                       at<uint32_t>(ws, L.cmask), at<uint32_t>(ws, L.chigh), lrs, lre, status);
+                       at<uint32_t>(ws, L.cbeg), lrs, lre, status);
     TC_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_rowlen, dim3(grid_for(l1, 256)), dim3(256), 0, s, lrs, lre,
                        (uint32_t)L.lists, cnt);
@@ -540,13 +533,10 @@ static int run_count_prepared(void *ws, const Layout &L, hipStream_t s, uint64_t
         a.row_ptr = at<uint32_t>(ws, L.row_ptr);
         a.col = at<uint32_t>(ws, L.col);
         a.hcol = at<uint16_t>(ws, L.hcol);
-        a.chigh = at<uint32_t>(ws, L.chigh);
         a.hbase = L.hbase;
         a.cptr = at<uint32_t>(ws, L.cptr);
         a.cbeg = at<uint32_t>(ws, L.cbeg);
-        a.cend = at<uint32_t>(ws, L.cend);
-        a.src = at<uint32_t>(ws, L.src);
-        a.cmask = at<uint32_t>(ws, L.cmask);
+        a.er = at<uint4>(ws, L.eu);
         a.item_v_a = at<uint32_t>(ws, L.item_v[a0]);
         a.item_off_a = at<uint32_t>(ws, L.off[a0]);
         a.n_items_a = a.item_off_a + L.lists;

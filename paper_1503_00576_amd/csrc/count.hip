@@ -138,44 +138,40 @@ struct WaveScratch {  // tag: the segment's owner (per-vertex counts) or its pan
 };
 
 // Segment sources: segment e is a range [b, en) of `col` streamed through the staged list,
-// and `owner` is the vertex credited with the segment's hits in per-vertex counts.
-struct InEdgeSegs {  // middle-vertex kernel: suffix of N+(u) after v, owner u = src[e]
-    // totals: the suffix's entries >= hbase start at col position csplit[e], and at hcol
-    // position chigh[e]
-    const uint32_t *cbeg, *cend, *src, *csplit, *chigh;
-    __device__ __forceinline__ void get(uint32_t e, uint32_t &b, uint32_t &en) const {
-        b = cbeg[e];
-        en = cend[e];
+// and `owner` is the vertex credited with the segment's hits in per-vertex counts.  rec(e)
+// fetches everything a streamer needs of segment e at once.
+struct SegRec {
+    uint32_t b, en;  // the range of col
+    uint32_t y;      // panel mask, or where the entries >= hbase start in col
+    uint32_t h;      // where the entries >= hbase start in hcol
+    uint32_t owner;
+};
+
+// In-edge records: the in-edge u -> v at CSR position e (list entry j holds cbeg[j] = e + 1)
+// has its record at er[e] = (end of u's row, panel mask of u's run in a panel list or else
+// where the suffix's entries >= hbase start in col, where they start in hcol, u); reading
+// it is one random 16-byte gather per segment.
+struct InEdgeSegs {  // middle-vertex kernel: suffix of N+(u) after v, owner u
+    const uint32_t *cbeg;
+    const uint4 *er;
+    __device__ __forceinline__ SegRec rec_from(uint32_t b) const {
+        const uint4 x = er[b - 1];
+        return SegRec{b, x.x, x.y, x.z, x.w};
     }
-    __device__ __forceinline__ void get_t(uint32_t e, uint32_t &b, uint32_t &hb, uint32_t &en,
-                                          uint32_t &h) const {
-        b = cbeg[e];
-        en = cend[e];
-        hb = csplit[e];
-        h = chigh[e];
-    }
-    __device__ __forceinline__ uint32_t owner(uint32_t e) const { return src[cbeg[e] - 1]; }
-    __device__ __forceinline__ uint32_t mask(uint32_t) const { return 0u; }
+    __device__ __forceinline__ SegRec rec(uint32_t e) const { return rec_from(cbeg[e]); }
 };
 
 // Panel segment (u, panel): the suffix of N+(u) after u's first panel vertex, tagged with the
-// mask R(u) of u's panel vertices.
+// mask R(u) of u's panel vertices; with a high region every entry after a panel vertex is a
+// rank >= p0 >= hbase.
 struct PanelSegs {
-    const uint32_t *cbeg, *cend, *cmask, *chigh;
-    __device__ __forceinline__ void get(uint32_t e, uint32_t &b, uint32_t &en) const {
-        b = cbeg[e];
-        en = cend[e];
+    const uint32_t *cbeg;
+    const uint4 *er;
+    __device__ __forceinline__ SegRec rec_from(uint32_t b) const {
+        const uint4 x = er[b - 1];
+        return SegRec{b, x.x, x.y, x.z, x.w};
     }
-    // with a high region, every entry after a panel vertex is a rank >= p0 >= hbase
-    __device__ __forceinline__ void get_t(uint32_t e, uint32_t &b, uint32_t &hb, uint32_t &en,
-                                          uint32_t &h) const {
-        b = cbeg[e];
-        en = cend[e];
-        hb = b;
-        h = chigh[e];
-    }
-    __device__ __forceinline__ uint32_t owner(uint32_t) const { return 0u; }
-    __device__ __forceinline__ uint32_t mask(uint32_t e) const { return cmask[e]; }
+    __device__ __forceinline__ SegRec rec(uint32_t e) const { return rec_from(cbeg[e]); }
 };
 
 // Per-vertex counts over a panel, one panel vertex P + j at a time: segment (u, panel) stands
@@ -183,30 +179,27 @@ struct PanelSegs {
 // N+(u) starting right before cbeg, so the suffix after P + j starts popcount(R(u) below j)
 // elements later; segments without bit j are empty.
 struct PanelVertexSegs {
-    const uint32_t *cbeg, *cend, *src, *cmask;
+    const uint32_t *cbeg;
+    const uint4 *er;
     uint32_t j;
-    __device__ __forceinline__ void get(uint32_t e, uint32_t &b, uint32_t &en) const {
-        const uint32_t r = cmask[e];
-        b = 0;
-        en = 0;
-        if ((r >> j) & 1u) {
-            b = cbeg[e] + __popc(r & ((1u << j) - 1u));
-            en = cend[e];
+    __device__ __forceinline__ SegRec rec(uint32_t e) const {
+        const uint32_t b0 = cbeg[e];
+        const uint4 x = er[b0 - 1];
+        SegRec r{0u, 0u, 0u, 0u, x.w};
+        if ((x.y >> j) & 1u) {
+            r.b = b0 + __popc(x.y & ((1u << j) - 1u));
+            r.en = x.x;
         }
+        return r;
     }
-    __device__ __forceinline__ uint32_t owner(uint32_t e) const { return src[cbeg[e] - 1]; }
-    __device__ __forceinline__ uint32_t mask(uint32_t) const { return 0u; }
 };
 
 struct OutEdgeSegs {  // u-centric kernel: the whole list N+(v) of out-neighbour v, owner v
     const uint32_t *row_ptr, *col;
-    __device__ __forceinline__ void get(uint32_t e, uint32_t &b, uint32_t &en) const {
+    __device__ __forceinline__ SegRec rec(uint32_t e) const {
         const uint32_t v = col[e];
-        b = row_ptr[v];
-        en = row_ptr[v + 1];
+        return SegRec{row_ptr[v], row_ptr[v + 1], 0u, 0u, v};
     }
-    __device__ __forceinline__ uint32_t owner(uint32_t e) const { return col[e]; }
-    __device__ __forceinline__ uint32_t mask(uint32_t) const { return 0u; }
 };
 
 // The calling wave streams segments [eb, min(eb + 64, e1)) of the current item through the
@@ -221,8 +214,9 @@ __device__ __forceinline__ uint32_t run_batch(uint32_t eb, uint32_t e1, const Se
     const uint32_t lane = lane_id();
     const uint32_t e = eb + lane;
     const bool valid = e < e1;
-    uint32_t b = 0, en = 0;
-    if (valid) segs.get(e, b, en);
+    SegRec r{0u, 0u, 0u, 0u, 0u};
+    if (valid) r = segs.rec(e);
+    const uint32_t b = r.b, en = r.en;
     // pieces are kPiece-element windows starting at 4-element (16-byte) boundaries, so a lane
     // reads its piece with kPiece / 4 aligned 16-byte loads; elements outside [b, en) are masked
     const uint32_t a0 = b & ~3u;
@@ -235,9 +229,9 @@ __device__ __forceinline__ uint32_t run_batch(uint32_t eb, uint32_t e1, const Se
     ws.end[lane] = en;
     if (PV) {
         ws.cnt[lane] = 0;
-        ws.tag[lane] = valid ? segs.owner(e) : 0u;
+        ws.tag[lane] = r.owner;
     } else if (Probe::kMasked) {
-        ws.tag[lane] = valid ? segs.mask(e) : 0u;
+        ws.tag[lane] = r.y;
     }
     wave_lds_sync();
     uint32_t hits_total = 0;
@@ -440,20 +434,20 @@ __device__ __forceinline__ uint32_t masked_hits(const Probe &probe, const uint32
     return __popc(packed & mask);
 }
 
-// The calling wave streams segments [eb, min(eb + 64, e1)) of the current item through the
-// probe for total counts and returns this lane's hits.  A segment is the col range [b, en)
-// whose entries from hb on are ranks >= hbase, found in hcol from position h; probes without
-// kLow are only given segments with hb == b.
-template <class Probe, class Segs>
-__device__ __forceinline__ uint32_t run_batch_t(uint32_t eb, uint32_t e1, const Segs &segs,
+// The calling wave streams one batch of up to 64 segments (r: this lane's record, all zero
+// for no segment) through the probe for total counts and returns this lane's hits.  A segment
+// is the col range [b, en) whose entries from hb on are ranks >= hbase, found in hcol from
+// position h; probes without kLow are only given segments with hb == b.
+template <class Probe>
+__device__ __forceinline__ uint32_t run_batch_t(const SegRec &r,
                                                 const uint32_t *__restrict__ col,
                                                 const uint16_t *__restrict__ hcol,
                                                 uint32_t hbase, const Probe &probe,
                                                 WaveScratch &ws) {
     const uint32_t lane = lane_id();
-    const uint32_t e = eb + lane;
-    uint32_t b = 0, hb = 0, en = 0, h = 0;
-    if (e < e1) segs.get_t(e, b, hb, en, h);
+    // panel segments are high throughout; other segments switch to high entries at r.y
+    const uint32_t b = r.b, en = r.en, h = r.h;
+    const uint32_t hb = Probe::kPanel ? b : r.y;
     const uint32_t a0 = b & ~3u;
     const uint32_t pl = (Probe::kLow && hb > b) ? (hb - a0 + kPiece - 1) / kPiece : 0u;
     // unmasked probes read longer pieces (the per-piece search and setup is their overhead)
@@ -472,7 +466,7 @@ __device__ __forceinline__ uint32_t run_batch_t(uint32_t eb, uint32_t e1, const 
         ws.end[lane] = hb;
     }
     if constexpr (Probe::kMaskHigh) ws.tag[lane] = h + hl;
-    if constexpr (Probe::kPanel) ws.tag[lane] = e < e1 ? segs.mask(e) : 0u;
+    if constexpr (Probe::kPanel) ws.tag[lane] = r.y;
     wave_lds_sync();
     uint32_t hits_total = 0;
     for (uint32_t q0 = 0; q0 < Q; q0 += kWave) {
@@ -547,6 +541,25 @@ __device__ __forceinline__ uint32_t run_batch_t(uint32_t eb, uint32_t e1, const 
     }
     wave_lds_sync();
     return hits_total;
+}
+
+// The calling wave streams the segments first, first + step, ... (its batches of 64: lanes
+// take consecutive segments) of an item ending at e1 for total counts.  (Fetching the
+// records a batch or two ahead measured no faster: the gathers' lines, not their latency,
+// are the cost.)
+template <class Probe, class Segs>
+__device__ __forceinline__ uint32_t stream_t(uint32_t first, uint32_t e1, uint32_t step,
+                                             const Segs &segs,
+                                             const uint32_t *__restrict__ col,
+                                             const uint16_t *__restrict__ hcol, uint32_t hbase,
+                                             const Probe &probe, WaveScratch &ws) {
+    const uint32_t lane = lane_id();
+    uint32_t hits = 0;
+    for (uint32_t eb = first; eb < e1; eb += step) {
+        const SegRec r = eb + lane < e1 ? segs.rec(eb + lane) : SegRec{0u, 0u, 0u, 0u, 0u};
+        hits += run_batch_t(r, col, hcol, hbase, probe, ws);
+    }
+    return hits;
 }
 
 // Wave-private claims on a shared item counter: kClaim consecutive positions per atomic, so
@@ -674,10 +687,7 @@ constexpr uint32_t kMidPieces = (1u << (MidCounters::kHi + 4)) / kPiece - 1;
 // lane's hits; `pieces` is the wave's bound on the pieces any lane added to mc since its last
 // flush.
 __device__ __forceinline__ uint32_t run_panel_pv(uint32_t eb, uint32_t e1,
-                                                 const uint32_t *__restrict__ cbeg,
-                                                 const uint32_t *__restrict__ cend,
-                                                 const uint32_t *__restrict__ cmask,
-                                                 const uint32_t *__restrict__ src,
+                                                 const PanelSegs &segs,
                                                  const uint32_t *__restrict__ col,
                                                  const uint32_t *m, uint32_t *cnt3, uint32_t lo,
                                                  uint32_t span, WaveScratch &ws,
@@ -687,11 +697,9 @@ __device__ __forceinline__ uint32_t run_panel_pv(uint32_t eb, uint32_t e1,
     const uint32_t lane = lane_id();
     const uint32_t e = eb + lane;
     const bool valid = e < e1;
-    uint32_t b = 0, en = 0;
-    if (valid) {
-        b = cbeg[e];
-        en = cend[e];
-    }
+    SegRec r{0u, 0u, 0u, 0u, 0u};
+    if (valid) r = segs.rec(e);
+    const uint32_t b = r.b, en = r.en;
     const uint32_t a0 = b & ~3u;
     const uint32_t p = (valid && en > b) ? (en - a0 + kPiece - 1) / kPiece : 0u;
     const uint32_t incl = wave_incl_scan(p);
@@ -701,8 +709,8 @@ __device__ __forceinline__ uint32_t run_panel_pv(uint32_t eb, uint32_t e1,
     ws.first[lane] = b;
     ws.end[lane] = en;
     ws.cnt[lane] = 0;
-    ws.tag[lane] = valid ? cmask[e] : 0u;
-    ws.aux[lane] = valid ? src[b - 1] : 0u;  // u: its first panel vertex sits right before b
+    ws.tag[lane] = r.y;      // the panel mask R(u)
+    ws.aux[lane] = r.owner;  // u
     wave_lds_sync();
     const uint32_t per_lane = (Q + kWave - 1) / kWave;
     if (pieces + per_lane > kMidPieces) {
@@ -764,8 +772,7 @@ __device__ __forceinline__ uint32_t run_panel_pv(uint32_t eb, uint32_t e1,
 __global__ __launch_bounds__(kThreads) void k_count_panel_pv(
     const uint32_t *__restrict__ row_ptr, const uint32_t *__restrict__ col,
     const uint32_t *__restrict__ cptr, const uint32_t *__restrict__ cbeg,
-    const uint32_t *__restrict__ cend, const uint32_t *__restrict__ src,
-    const uint32_t *__restrict__ cmask, const uint32_t *__restrict__ item_v_b,
+    const uint4 *__restrict__ er, const uint32_t *__restrict__ item_v_b,
     const uint32_t *__restrict__ item_off_b, const uint32_t *__restrict__ n_items_b_ptr,
     uint32_t *__restrict__ queue_c, unsigned long long *__restrict__ total,
     unsigned long long *__restrict__ tpv, uint32_t n1, uint32_t p0, uint32_t kitem_b,
@@ -777,6 +784,7 @@ __global__ __launch_bounds__(kThreads) void k_count_panel_pv(
     if (*status) return;
     const uint32_t t = threadIdx.x, w = t / kWave, lane = lane_id();
     WaveScratch &ws = s_ws[w];
+    const PanelSegs psegs{cbeg, er};
     uint32_t *m = s_mem, *cnt3 = s_mem + kPvPanelWords;
     for (uint32_t i = t; i < kLdsWords; i += kThreads) s_mem[i] = 0;
     if (t < kPanel) s_mid[t] = 0;
@@ -800,8 +808,8 @@ __global__ __launch_bounds__(kThreads) void k_count_panel_pv(
         __syncthreads();
         uint32_t cnt = 0, pieces = 0;
         for (uint32_t eb = it.e0 + w * kWave; eb < it.e1; eb += kWaves * kWave)
-            cnt += run_panel_pv(eb, it.e1, cbeg, cend, cmask, src, col, m, cnt3, P, span, ws,
-                                mc, pieces, s_mid, tpv);
+            cnt += run_panel_pv(eb, it.e1, psegs, col, m, cnt3, P, span, ws, mc, pieces, s_mid,
+                                tpv);
         mc.flush(s_mid);
         acc += cnt;
         __syncthreads();
@@ -830,16 +838,14 @@ template <bool PV>
 __global__ __launch_bounds__(kThreads) void k_count(
     const uint32_t *__restrict__ row_ptr, const uint32_t *__restrict__ col,
     const uint32_t *__restrict__ cptr, const uint32_t *__restrict__ cbeg,
-    const uint32_t *__restrict__ cend, const uint32_t *__restrict__ src,
-    const uint32_t *__restrict__ cmask, const uint32_t *__restrict__ item_v_a,
+    const uint4 *__restrict__ er, const uint32_t *__restrict__ item_v_a,
     const uint32_t *__restrict__ item_off_a, const uint32_t *__restrict__ n_items_a_ptr,
     const uint32_t *__restrict__ item_v_b, const uint32_t *__restrict__ item_off_b,
     const uint32_t *__restrict__ n_items_b_ptr, uint32_t *__restrict__ queue_a,
     uint32_t *__restrict__ queue_b, unsigned long long *__restrict__ total,
     unsigned long long *__restrict__ tpv, uint32_t n1, uint32_t p0, uint32_t wave_bits,
     uint32_t block_bits, uint32_t block_list, uint32_t kitem_a, uint32_t kitem_b,
-    const uint16_t *__restrict__ hcol, const uint32_t *__restrict__ chigh, uint32_t hbase,
-    const int32_t *__restrict__ status) {
+    const uint16_t *__restrict__ hcol, uint32_t hbase, const int32_t *__restrict__ status) {
     // 8 KiB aligned: a wave slice's base has zero low bits, so bitmap addresses OR it in
     __shared__ __attribute__((aligned(kSliceWords * 4))) uint32_t s_mem[kLdsWords];
     __shared__ WaveScratch s_ws[kWaves];
@@ -847,8 +853,7 @@ __global__ __launch_bounds__(kThreads) void k_count(
     if (*status) return;
     const uint32_t t = threadIdx.x, w = t / kWave, lane = lane_id();
     WaveScratch &ws = s_ws[w];
-    // totals: outside the panels cmask holds where a suffix's entries >= hbase start
-    const InEdgeSegs segs{cbeg, cend, src, cmask, chigh};
+    const InEdgeSegs segs{cbeg, er};
     for (uint32_t i = t; i < kLdsWords; i += kThreads) s_mem[i] = 0;
     uint64_t acc = 0;
 
@@ -870,12 +875,11 @@ __global__ __launch_bounds__(kThreads) void k_count(
                     for (uint32_t i = row_ptr[P + j] + lane; i < row_ptr[P + j + 1]; i += kWave)
                         atomicOr(&s_mem[col[i] - P], 1u << j);
                 __syncthreads();
-                const PanelSegs psegs{cbeg, cend, cmask, chigh};
+                const PanelSegs psegs{cbeg, er};
                 uint32_t cnt = 0;
                 if (P >= hbase) {  // the suffixes are in hcol
                     const PanelHighProbe probe{s_mem, P - hbase};
-                    for (uint32_t eb = first; eb < it.e1; eb += step)
-                        cnt += run_batch_t(eb, it.e1, psegs, col, hcol, hbase, probe, ws);
+                    cnt += stream_t(first, it.e1, step, psegs, col, hcol, hbase, probe, ws);
                 } else {  // no high region: 32-bit entries
                     const PanelProbe probe{s_mem, P, n1 - 2 - P};
                     for (uint32_t eb = first; eb < it.e1; eb += step)
@@ -897,7 +901,7 @@ __global__ __launch_bounds__(kThreads) void k_count(
                     if (in_lds)
                         for (uint32_t i = t; i < d; i += kThreads) s_mem[i] = col[r0 + i];
                     __syncthreads();
-                    const PanelVertexSegs vsegs{cbeg, cend, src, cmask, j};
+                    const PanelVertexSegs vsegs{cbeg, er, j};
                     uint32_t cnt = 0;
                     if (in_lds) {
                         const ListProbe probe{s_mem, d};
@@ -946,28 +950,28 @@ __global__ __launch_bounds__(kThreads) void k_count(
         uint32_t cnt = 0;
         if (mode == 0) {
             const BitmapProbe probe{s_mem, lo, span};
-            for (uint32_t eb = first; eb < it.e1; eb += step) {
-                if constexpr (PV)
+            if constexpr (PV) {
+                for (uint32_t eb = first; eb < it.e1; eb += step)
                     cnt += run_batch<true>(eb, it.e1, segs, col, probe, ws, nullptr, tpv);
-                else
-                    cnt += run_batch_t(eb, it.e1, segs, col, hcol, hbase, probe, ws);
+            } else {
+                cnt += stream_t(first, it.e1, step, segs, col, hcol, hbase, probe, ws);
             }
         } else if (mode == 1) {
             const ListProbe probe{s_mem, it.d};
             uint32_t *tc = PV ? s_mem + kBlockListPV : nullptr;
-            for (uint32_t eb = first; eb < it.e1; eb += step) {
-                if constexpr (PV)
+            if constexpr (PV) {
+                for (uint32_t eb = first; eb < it.e1; eb += step)
                     cnt += run_batch<true>(eb, it.e1, segs, col, probe, ws, tc, tpv);
-                else
-                    cnt += run_batch_t(eb, it.e1, segs, col, hcol, hbase, probe, ws);
+            } else {
+                cnt += stream_t(first, it.e1, step, segs, col, hcol, hbase, probe, ws);
             }
         } else {
             const ListProbe probe{col + it.r0, it.d};
-            for (uint32_t eb = first; eb < it.e1; eb += step) {
-                if constexpr (PV)
+            if constexpr (PV) {
+                for (uint32_t eb = first; eb < it.e1; eb += step)
                     cnt += run_batch<true>(eb, it.e1, segs, col, probe, ws, nullptr, tpv);
-                else
-                    cnt += run_batch_t(eb, it.e1, segs, col, hcol, hbase, probe, ws);
+            } else {
+                cnt += stream_t(first, it.e1, step, segs, col, hcol, hbase, probe, ws);
             }
         }
         if (PV) {
@@ -1016,8 +1020,7 @@ __global__ __launch_bounds__(kThreads) void k_count(
                 }
                 wave_lds_sync();
                 const HighBitmapProbe probe{lds_addr(mem)};
-                for (uint32_t eb = it.e0; eb < it.e1; eb += kWave)
-                    cnt += run_batch_t(eb, it.e1, segs, col, hcol, hbase, probe, ws);
+                cnt += stream_t(it.e0, it.e1, kWave, segs, col, hcol, hbase, probe, ws);
                 for (uint32_t i = lane; i < it.d; i += kWave)
                     mem[(col[it.r0 + i] - hbase) >> 5] = 0;
             } else if (span < wave_bits) {  // bitmap over the span
@@ -1027,16 +1030,14 @@ __global__ __launch_bounds__(kThreads) void k_count(
                 }
                 wave_lds_sync();
                 const BitmapProbe probe{mem, lo, span};
-                for (uint32_t eb = it.e0; eb < it.e1; eb += kWave)
-                    cnt += run_batch_t(eb, it.e1, segs, col, hcol, hbase, probe, ws);
+                cnt += stream_t(it.e0, it.e1, kWave, segs, col, hcol, hbase, probe, ws);
                 for (uint32_t i = lane; i < it.d; i += kWave)
                     mem[(col[it.r0 + i] - lo) >> 5] = 0;
             } else {  // a wide span, but a list that fits the slice (see k_items)
                 for (uint32_t i = lane; i < it.d; i += kWave) mem[i] = col[it.r0 + i];
                 wave_lds_sync();
                 const ListProbe probe{mem, it.d};
-                for (uint32_t eb = it.e0; eb < it.e1; eb += kWave)
-                    cnt += run_batch_t(eb, it.e1, segs, col, hcol, hbase, probe, ws);
+                cnt += stream_t(it.e0, it.e1, kWave, segs, col, hcol, hbase, probe, ws);
                 for (uint32_t i = lane; i < it.d; i += kWave) mem[i] = 0;
             }
             wave_lds_sync();
@@ -1318,7 +1319,7 @@ hipError_t launch_count(const CountArgs &x, bool per_vertex, hipStream_t s) {
     const dim3 grid(device_cu_count() * kWgsPerCu), block(kThreads);
     if (per_vertex && x.p0 + 1 < x.n1) {  // panels: those that fit first, on their own queue
         hipLaunchKernelGGL(k_count_panel_pv, grid, block, 0, s, x.row_ptr, x.col, x.cptr,
-                           x.cbeg, x.cend, x.src, x.cmask, x.item_v_b, x.item_off_b,
+                           x.cbeg, x.er, x.item_v_b, x.item_off_b,
                            x.n_items_b, x.queue_c, x.total, x.tpv, x.n1, x.p0, x.kitem_b,
                            x.status);
         const hipError_t e = hipGetLastError();
@@ -1326,16 +1327,16 @@ hipError_t launch_count(const CountArgs &x, bool per_vertex, hipStream_t s) {
     }
     if (per_vertex)
         hipLaunchKernelGGL(k_count<true>, grid, block, 0, s, x.row_ptr, x.col, x.cptr, x.cbeg,
-                           x.cend, x.src, x.cmask, x.item_v_a, x.item_off_a, x.n_items_a,
+                           x.er, x.item_v_a, x.item_off_a, x.n_items_a,
                            x.item_v_b, x.item_off_b, x.n_items_b, x.queue_a, x.queue_b, x.total,
                            x.tpv, x.n1, x.p0, x.wave_bits, x.block_bits, x.block_list,
-                           x.kitem_a, x.kitem_b, x.hcol, x.chigh, x.hbase, x.status);
+                           x.kitem_a, x.kitem_b, x.hcol, x.hbase, x.status);
     else
         hipLaunchKernelGGL(k_count<false>, grid, block, 0, s, x.row_ptr, x.col, x.cptr, x.cbeg,
-                           x.cend, x.src, x.cmask, x.item_v_a, x.item_off_a, x.n_items_a,
+                           x.er, x.item_v_a, x.item_off_a, x.n_items_a,
                            x.item_v_b, x.item_off_b, x.n_items_b, x.queue_a, x.queue_b, x.total,
                            x.tpv, x.n1, x.p0, x.wave_bits, x.block_bits, x.block_list,
-                           x.kitem_a, x.kitem_b, x.hcol, x.chigh, x.hbase, x.status);
+                           x.kitem_a, x.kitem_b, x.hcol, x.hbase, x.status);
     return hipGetLastError();
 }
 

@@ -92,12 +92,15 @@ int device_cu_count();
 
 // counting kernels (count.hip)
 struct CountArgs {
-    const uint32_t *row_ptr, *col, *cptr, *cbeg, *cend, *src, *cmask;  // src: row of a CSR entry
+    // in-edge lists: entry j of list c (cptr[c] <= j < cptr[c + 1]) is the in-edge at CSR
+    // position cbeg[j] - 1, whose record er[cbeg[j] - 1] = (end of its row, panel mask or where
+    // the suffix's entries >= hbase start in col, where they start in hcol, its row)
+    const uint32_t *row_ptr, *col, *cptr, *cbeg;
+    const uint4 *er;
     // every row's entries >= rank hbase as 16-bit offsets from hbase, each row's part 8-aligned
-    // and followed by at least 8 zeros; totals stream every in-edge suffix's entries >= hbase
-    // from here (outside the panels cmask holds where they start in col; chigh: in hcol)
+    // and followed by zeros (count_hcol_pad()); totals stream every in-edge suffix's entries
+    // >= hbase from here
     const uint16_t *hcol;
-    const uint32_t *chigh;
     uint32_t hbase;  // n: no high region
     const uint32_t *item_v_a, *item_off_a, *n_items_a;
     const uint32_t *item_v_b, *item_off_b, *n_items_b;

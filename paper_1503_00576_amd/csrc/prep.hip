@@ -417,10 +417,11 @@ __global__ void k_panel_range(const uint64_t *__restrict__ vr, uint32_t n, uint3
 // edge.)  From rank p0 on, middle vertices form panels of kp consecutive ranks with one list
 // per panel, keyed by its first rank P: only the first in-edge of each run of u's
 // out-neighbours inside the panel is kept (it stands for the whole run), tested against the
-// panel's span (a small table).  eu[e] = (end of u's row, mask of the run's panel vertices
-// for a kept panel entry or, for any other kept entry, the col position where the suffix's
-// entries >= hbase start, the hcol position where they start).  In-edges from hubs (u >= h0)
-// are left out: their triangles are counted on the matrix cores.  Every entry >= hbase is
+// panel's span (a small table).  eu[e], the in-edge's record read by the counting kernels,
+// = (end of u's row, mask of the run's panel vertices for a kept panel entry or, for any
+// other kept entry, the col position where the suffix's entries >= hbase start, the hcol
+// position where they start, u).  In-edges from hubs (u >= h0) are left out: their
+// triangles are counted on the matrix cores.  Every entry >= hbase is
 // also written to its row's part of hcol (hrow and hstart: k_csr, k_hlen and a scan).
 // Each thread takes kCscEdges entries a block apart and issues every stage's loads for all of
 // them before using any (the stages depend on each other: entry -> row -> row end).
@@ -510,19 +511,15 @@ __global__ void k_csc_keys(const uint32_t *__restrict__ col, const uint32_t *__r
             }
         }
         keys[e] = (c << 32) | e;
-        eu[e] = make_uint4(end_u, mask, hpos, 0u);
+        eu[e] = make_uint4(end_u, mask, hpos, u[k]);
     }
 }
 
-// The lists themselves: in-edge u -> v at CSR position e contributes the suffix [e + 1, end_u),
-// in a panel list the mask of u's run of panel vertices and otherwise the col position where
-// the suffix's entries >= hbase start, and the hcol position where they start (k_csc_keys);
-// list c occupies sorted positions [rs[c], re[c]) (useful in-edges only; rs and re zeroed
-// beforehand).
+// The lists themselves: list c occupies sorted positions [rs[c], re[c]) (useful in-edges
+// only; rs and re zeroed beforehand), and entry j names its in-edge by cbeg[j] = e + 1, the
+// start of the suffix; the counting kernels read the in-edge's record (k_csc_keys) from there.
 __global__ void k_csc_final(const uint64_t *__restrict__ keys, uint32_t mf, uint64_t lists,
-                            const uint4 *__restrict__ eu, uint32_t *__restrict__ cbeg,
-                            uint32_t *__restrict__ cend, uint32_t *__restrict__ cmask,
-                            uint32_t *__restrict__ chigh, uint32_t *__restrict__ rs,
+                            uint32_t *__restrict__ cbeg, uint32_t *__restrict__ rs,
                             uint32_t *__restrict__ re, const int32_t *__restrict__ status) {
     if (*status) return;
     uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -532,12 +529,7 @@ __global__ void k_csc_final(const uint64_t *__restrict__ keys, uint32_t mf, uint
     if (c >= lists) return;
     if (j == 0 || (keys[j - 1] >> 32) != c) rs[c] = j;
     if (j == mf - 1 || (keys[j + 1] >> 32) != c) re[c] = j + 1;
-    const uint32_t e = (uint32_t)k;
-    const uint4 x = eu[e];
-    cbeg[j] = e + 1;
-    cend[j] = x.x;
-    cmask[j] = x.y;
-    chigh[j] = x.z;
+    cbeg[j] = (uint32_t)k + 1;
 }
 
 // Work items of the counting kernel.  A vertex's in-edges are cut into chunks; the chunks go

@@ -357,6 +357,7 @@ constexpr uint32_t kLbAgg = 1u << 30;       // published: this tile's own count
 constexpr uint32_t kLbIncl = 2u << 30;      // published: inclusive prefix up to this tile
 constexpr uint32_t kLbValue = (1u << 30) - 1u;
 constexpr uint32_t kLbMaxPolls = 1u << 20;  // bound on the polls of one look-back
+constexpr uint32_t kLbWindow = 16;          // predecessors' flags read per round trip
 constexpr int kMaxPasses = 8;
 
 // digit counts of every pass over all keys: ghist[p * 256 + d]
@@ -413,24 +414,42 @@ __device__ __forceinline__ void onesweep_tile(const uint64_t *__restrict__ in,
         uint32_t gbefore = 0;
         for (uint32_t k = 0; k < w; ++k) gbefore += L.gsum[k];
         const uint32_t gstart = gbefore + gincl - gc;
-        // look-back: keys of digit t in the tiles before this one
+        // look-back: keys of digit t in the tiles before this one.  The flags of kLbWindow
+        // predecessors are read together (one memory round trip instead of one per tile) and
+        // taken nearest first until an inclusive prefix; an unpublished flag is waited for
         uint32_t excl = 0;
         if (tile > 0) {
             uint32_t j = tile - 1, polls = 0;
-            for (;;) {
-                const uint32_t f = __hip_atomic_load(&flags[(uint64_t)j * 256 + t],
-                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if ((f & ~kLbValue) == 0) {
+            bool done = false;
+            while (!done) {
+                uint32_t f[kLbWindow];
+#pragma unroll
+                for (uint32_t i = 0; i < kLbWindow; ++i)
+                    f[i] = i <= j ? __hip_atomic_load(&flags[(uint64_t)(j - i) * 256 + t],
+                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                  : kLbIncl;  // never reached: tile 0 is inclusive
+                uint32_t taken = 0;
+                bool wait = false;
+#pragma unroll
+                for (uint32_t i = 0; i < kLbWindow; ++i) {
+                    if (done || wait) continue;
+                    if ((f[i] & ~kLbValue) == 0) {
+                        wait = true;
+                        continue;
+                    }
+                    excl += f[i] & kLbValue;
+                    ++taken;
+                    if (f[i] & kLbIncl) done = true;
+                }
+                if (done) break;
+                j -= taken;  // tile 0 publishes an inclusive prefix, so j never passes it
+                if (wait) {
                     if (++polls >= kLbMaxPolls) {
                         set_status(status, TC_E_HIP);
                         break;
                     }
                     __builtin_amdgcn_s_sleep(1);
-                    continue;
                 }
-                excl += f & kLbValue;
-                if (f & kLbIncl) break;
-                --j;  // tile 0 publishes an inclusive prefix, so j never passes it
             }
             __hip_atomic_store(&flags[(uint64_t)tile * 256 + t], kLbIncl | (excl + c),
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
