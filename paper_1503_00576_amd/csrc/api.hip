@@ -533,6 +533,7 @@ static int run_count_prepared(void *ws, const Layout &L, hipStream_t s, uint64_t
         a.row_ptr = at<uint32_t>(ws, L.row_ptr);
         a.col = at<uint32_t>(ws, L.col);
         a.hcol = at<uint16_t>(ws, L.hcol);
+        a.hrow = at<uint32_t>(ws, L.hrow);
         a.hbase = L.hbase;
         a.cptr = at<uint32_t>(ws, L.cptr);
         a.cbeg = at<uint32_t>(ws, L.cbeg);

@@ -377,12 +377,26 @@ struct HighBitmapProbe {
     // bits of the two entries of a packed pair of 16-bit entries: word x >> 5 is at byte
     // ((x >> 3) & 0x1ffc) | base, and the bit offset of v_bfe is the low 5 bits of its
     // operand, so the low entry needs no extraction
-    __device__ __forceinline__ uint32_t bits2(uint32_t pr) const {
-        const uint32_t lo = __builtin_amdgcn_ubfe(lds_word(((pr >> 3) & 0x1ffcu) | base), pr, 1u);
-        const uint32_t hi =
-            __builtin_amdgcn_ubfe(lds_word(((pr >> 19) & 0x1ffcu) | base), pr >> 16, 1u);
-        return lo + hi;
+    __device__ __forceinline__ uint32_t bit_lo(uint32_t pr) const {
+        return __builtin_amdgcn_ubfe(lds_word(((pr >> 3) & 0x1ffcu) | base), pr, 1u);
     }
+    __device__ __forceinline__ uint32_t bit_hi(uint32_t pr) const {
+        return __builtin_amdgcn_ubfe(lds_word(((pr >> 19) & 0x1ffcu) | base), pr >> 16, 1u);
+    }
+    __device__ __forceinline__ uint32_t bits2(uint32_t pr) const { return bit_lo(pr) + bit_hi(pr); }
+};
+
+// N+(v) of a middle vertex below hbase whose rank span is too wide for a bitmap: its entries
+// >= hbase in a high-region bitmap (as HighBitmapProbe), its entries below hbase as a sorted
+// list in global memory (d may be 0).  Masked: a high piece of a suffix that starts below
+// hbase begins at its row's part of hcol, but the padding zeros (rank hbase) may be in N+(v).
+struct SplitProbe {
+    HighBitmapProbe hi;
+    const uint32_t *lo;
+    uint32_t dlo;
+    static constexpr bool kLow = true;
+    static constexpr bool kMaskHigh = true;
+    static constexpr bool kPanel = false;
 };
 
 // Panel table over ranks [P, n) (as PanelProbe) read with 16-bit entries: rank hbase + x is
@@ -401,14 +415,19 @@ struct PanelHighProbe {
     }
 };
 
+// bit i set when position start + i of a piece lies in [first, stop) (start < stop)
+__device__ __forceinline__ uint32_t piece_mask(uint32_t start, uint32_t first, uint32_t stop) {
+    const uint32_t lo_i = first > start ? first - start : 0u;
+    const uint32_t hi_i = min(stop - start, kPiece);
+    const uint32_t hmask = hi_i >= 32u ? ~0u : ((1u << hi_i) - 1u);
+    return hmask & ~((1u << lo_i) - 1u);
+}
+
 // hits of the entries wv[i] at positions start + i that lie in [first, stop)
 template <class Probe>
 __device__ __forceinline__ uint32_t masked_hits(const Probe &probe, const uint32_t (&wv)[kPiece],
                                                 uint32_t start, uint32_t first, uint32_t stop) {
-    const uint32_t lo_i = first > start ? first - start : 0u;
-    const uint32_t hi_i = min(stop - start, kPiece);
-    const uint32_t hmask = hi_i >= 32u ? ~0u : ((1u << hi_i) - 1u);
-    const uint32_t mask = hmask & ~((1u << lo_i) - 1u);
+    const uint32_t mask = piece_mask(start, first, stop);
     uint32_t packed = 0;
     if constexpr (Probe::kList) {
         // the piece's lookups as binary searches in lockstep (the list length is uniform)
@@ -434,10 +453,82 @@ __device__ __forceinline__ uint32_t masked_hits(const Probe &probe, const uint32
     return __popc(packed & mask);
 }
 
+// Piece evaluations of the totals streamer.  Masked probes: a 32-bit piece (entries wv) and a
+// 16-bit piece (packed pairs pr of offsets from hbase), positions start + i, counted inside
+// [first, stop).  Unmasked probes: a 16-bit piece of kPieceHigh entries, all counted.
+template <class Probe>
+__device__ __forceinline__ uint32_t low_hits(const Probe &probe, const uint32_t (&wv)[kPiece],
+                                             uint32_t start, uint32_t first, uint32_t stop) {
+    return masked_hits(probe, wv, start, first, stop);
+}
+template <class Probe>
+__device__ __forceinline__ uint32_t high_hits(const Probe &probe,
+                                              const uint32_t (&pr)[kPiece / 2], uint32_t hbase,
+                                              uint32_t start, uint32_t first, uint32_t stop) {
+    uint32_t wv[kPiece];
+#pragma unroll
+    for (uint32_t i = 0; i < kPiece / 2; ++i) {
+        wv[2 * i] = hbase + (pr[i] & 0xFFFFu);
+        wv[2 * i + 1] = hbase + (pr[i] >> 16);
+    }
+    return masked_hits(probe, wv, start, first, stop);
+}
+__device__ __forceinline__ uint32_t low_hits(const SplitProbe &probe,
+                                             const uint32_t (&wv)[kPiece], uint32_t start,
+                                             uint32_t first, uint32_t stop) {
+    if (probe.dlo == 0) return 0u;
+    return masked_hits(ListProbe{probe.lo, probe.dlo}, wv, start, first, stop);
+}
+__device__ __forceinline__ uint32_t high_hits(const SplitProbe &probe,
+                                              const uint32_t (&pr)[kPiece / 2], uint32_t,
+                                              uint32_t start, uint32_t first, uint32_t stop) {
+    uint32_t packed = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < kPiece / 2; ++i)
+        packed |= (probe.hi.bit_lo(pr[i]) << (2 * i)) | (probe.hi.bit_hi(pr[i]) << (2 * i + 1));
+    return __popc(packed & piece_mask(start, first, stop));
+}
+__device__ __forceinline__ uint32_t high_hits_u(const HighBitmapProbe &probe,
+                                                const uint32_t (&pr)[kPieceHigh / 2], uint32_t) {
+    uint32_t hits = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < kPieceHigh / 2; ++i) hits += probe.bits2(pr[i]);
+    return hits;
+}
+__device__ __forceinline__ uint32_t high_hits_u(const PanelHighProbe &probe,
+                                                const uint32_t (&pr)[kPieceHigh / 2], uint32_t r) {
+    uint32_t hits = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < kPieceHigh / 2; ++i)
+        hits += probe.count(pr[i] & 0xFFFFu, r) + probe.count(pr[i] >> 16, r);
+    return hits;
+}
+
+// Owner of piece q0 + lane in a round of a piece sequence: every segment whose first piece
+// (my_off, of this lane's segment, which has p pieces) falls in the round marks that lane in
+// the wave's table (tagged with the round number, so older marks read as none), and the
+// running maximum over the lanes carries the last mark forward; lanes before the round's
+// first mark belong to carry, the previous round's last segment (plus one).  Returns the
+// owner plus one (all lanes active).
+__device__ __forceinline__ uint32_t round_owner(uint32_t *mark, uint32_t my_off, uint32_t p,
+                                                uint32_t q0, uint32_t round, uint32_t &carry) {
+    const uint32_t lane = lane_id();
+    const uint32_t pos = my_off - q0;
+    if (p && pos < kWave) mark[pos] = (round << 7) | (lane + 1u);
+    wave_lds_sync();
+    const uint32_t mv = mark[lane];
+    const uint32_t m1 = wave_incl_max((mv >> 7) == round ? (mv & 127u) : 0u);
+    const uint32_t owner1 = m1 ? m1 : carry;
+    carry = (uint32_t)__builtin_amdgcn_readlane((int)owner1, kWave - 1);
+    return owner1;
+}
+
 // The calling wave streams one batch of up to 64 segments (r: this lane's record, all zero
 // for no segment) through the probe for total counts and returns this lane's hits.  A segment
 // is the col range [b, en) whose entries from hb on are ranks >= hbase, found in hcol from
-// position h; probes without kLow are only given segments with hb == b.
+// position h; probes without kLow are only given segments with hb == b.  The batch's 32-bit
+// pieces (of [b, hb)) run first, then its 16-bit pieces, each as its own sequence of rounds,
+// so that a round holds pieces of one kind.
 template <class Probe>
 __device__ __forceinline__ uint32_t run_batch_t(const SegRec &r,
                                                 const uint32_t *__restrict__ col,
@@ -454,11 +545,7 @@ __device__ __forceinline__ uint32_t run_batch_t(const SegRec &r,
     constexpr uint32_t kPh = Probe::kMaskHigh ? kPiece : kPieceHigh;
     const uint32_t hl = en - hb;
     const uint32_t ph = hl ? (h + hl - (h & ~7u) + kPh - 1) / kPh : 0u;
-    const uint32_t p = pl + ph;
-    const uint32_t incl = wave_incl_scan(p);
-    const uint32_t Q = wave_bcast(incl, kWave - 1);
-    ws.off[lane] = incl - p;
-    ws.cnt[lane] = pl;
+    ws.off[lane] = 0u;  // the rounds' marker table
     ws.aux[lane] = h;
     if constexpr (Probe::kLow) {
         ws.beg[lane] = a0;
@@ -467,55 +554,45 @@ __device__ __forceinline__ uint32_t run_batch_t(const SegRec &r,
     }
     if constexpr (Probe::kMaskHigh) ws.tag[lane] = h + hl;
     if constexpr (Probe::kPanel) ws.tag[lane] = r.y;
-    wave_lds_sync();
-    uint32_t hits_total = 0;
-    for (uint32_t q0 = 0; q0 < Q; q0 += kWave) {
-        const uint32_t q = q0 + lane;
-        if (q < Q) {
-            uint32_t k = 0;
-#pragma unroll
-            for (uint32_t step = 32; step; step >>= 1)
-                if (ws.off[k + step] <= q) k += step;
-            const uint32_t j = q - ws.off[k];
-            const uint32_t pk = ws.cnt[k];
-            uint32_t hits = 0;
-            if constexpr (Probe::kMaskHigh) {
-                // masked probes: the loads of either part, then one evaluation of the piece
-                uint32_t start, first, stop;
+    uint32_t hits_total = 0, carry = 0, round = 0;
+    if constexpr (Probe::kLow) {  // the 32-bit pieces
+        const uint32_t incl = wave_incl_scan(pl);
+        const uint32_t Q = wave_bcast(incl, kWave - 1);
+        const uint32_t my_off = incl - pl;
+        wave_lds_sync();
+        for (uint32_t q0 = 0; q0 < Q; q0 += kWave) {
+            const uint32_t k = round_owner(ws.off, my_off, pl, q0, ++round, carry) - 1u;
+            const uint32_t off_k = wave_bcast_from(my_off, k);
+            const uint32_t q = q0 + lane;
+            if (q < Q) {
+                const uint32_t start = ws.beg[k] + (q - off_k) * kPiece;
+                const uint4 *p4 = reinterpret_cast<const uint4 *>(col + start);
                 uint32_t wv[kPiece];
-                if (Probe::kLow && j < pk) {
-                    start = ws.beg[k] + j * kPiece;
-                    first = ws.first[k];
-                    stop = ws.end[k];
-                    const uint4 *p4 = reinterpret_cast<const uint4 *>(col + start);
 #pragma unroll
-                    for (uint32_t i = 0; i < kPiece / 4; ++i) {
-                        const uint4 x = p4[i];
-                        wv[4 * i] = x.x;
-                        wv[4 * i + 1] = x.y;
-                        wv[4 * i + 2] = x.z;
-                        wv[4 * i + 3] = x.w;
-                    }
-                } else {
-                    first = ws.aux[k];
-                    stop = ws.tag[k];
-                    start = (first & ~7u) + (j - pk) * kPiece;
-                    const uint4 *p4 = reinterpret_cast<const uint4 *>(hcol + start);
-#pragma unroll
-                    for (uint32_t i = 0; i < kPiece / 8; ++i) {
-                        const uint4 x = p4[i];
-                        const uint32_t h2[4] = {x.x, x.y, x.z, x.w};
-#pragma unroll
-                        for (uint32_t t = 0; t < 4; ++t) {
-                            wv[8 * i + 2 * t] = hbase + (h2[t] & 0xFFFFu);
-                            wv[8 * i + 2 * t + 1] = hbase + (h2[t] >> 16);
-                        }
-                    }
+                for (uint32_t i = 0; i < kPiece / 4; ++i) {
+                    const uint4 x = p4[i];
+                    wv[4 * i] = x.x;
+                    wv[4 * i + 1] = x.y;
+                    wv[4 * i + 2] = x.z;
+                    wv[4 * i + 3] = x.w;
                 }
-                hits = masked_hits(probe, wv, start, first, stop);
-            } else {
-                // unmasked probes: 16-bit pieces only
-                const uint32_t start = (ws.aux[k] & ~7u) + (j - pk) * kPh;
+                hits_total += low_hits(probe, wv, start, ws.first[k], ws.end[k]);
+            }
+        }
+        carry = 0;
+    }
+    {  // the 16-bit pieces
+        const uint32_t incl = wave_incl_scan(ph);
+        const uint32_t Q = wave_bcast(incl, kWave - 1);
+        const uint32_t my_off = incl - ph;
+        wave_lds_sync();
+        for (uint32_t q0 = 0; q0 < Q; q0 += kWave) {
+            const uint32_t k = round_owner(ws.off, my_off, ph, q0, ++round, carry) - 1u;
+            const uint32_t off_k = wave_bcast_from(my_off, k);
+            const uint32_t q = q0 + lane;
+            if (q < Q) {
+                const uint32_t hs = ws.aux[k];
+                const uint32_t start = (hs & ~7u) + (q - off_k) * kPh;
                 const uint4 *p4 = reinterpret_cast<const uint4 *>(hcol + start);
                 uint32_t pr[kPh / 2];
 #pragma unroll
@@ -526,17 +603,11 @@ __device__ __forceinline__ uint32_t run_batch_t(const SegRec &r,
                     pr[4 * i + 2] = x.z;
                     pr[4 * i + 3] = x.w;
                 }
-                if constexpr (Probe::kPanel) {
-                    const uint32_t r = ws.tag[k];
-#pragma unroll
-                    for (uint32_t i = 0; i < kPh / 2; ++i)
-                        hits += probe.count(pr[i] & 0xFFFFu, r) + probe.count(pr[i] >> 16, r);
-                } else {
-#pragma unroll
-                    for (uint32_t i = 0; i < kPh / 2; ++i) hits += probe.bits2(pr[i]);
-                }
+                if constexpr (Probe::kMaskHigh)
+                    hits_total += high_hits(probe, pr, hbase, start, hs, ws.tag[k]);
+                else
+                    hits_total += high_hits_u(probe, pr, ws.tag[k]);
             }
-            hits_total += hits;
         }
     }
     wave_lds_sync();
@@ -845,7 +916,8 @@ __global__ __launch_bounds__(kThreads) void k_count(
     uint32_t *__restrict__ queue_b, unsigned long long *__restrict__ total,
     unsigned long long *__restrict__ tpv, uint32_t n1, uint32_t p0, uint32_t wave_bits,
     uint32_t block_bits, uint32_t block_list, uint32_t kitem_a, uint32_t kitem_b,
-    const uint16_t *__restrict__ hcol, uint32_t hbase, const int32_t *__restrict__ status) {
+    const uint16_t *__restrict__ hcol, const uint32_t *__restrict__ hrow, uint32_t hbase,
+    const int32_t *__restrict__ status) {
     // 8 KiB aligned: a wave slice's base has zero low bits, so bitmap addresses OR it in
     __shared__ __attribute__((aligned(kSliceWords * 4))) uint32_t s_mem[kLdsWords];
     __shared__ WaveScratch s_ws[kWaves];
@@ -1033,6 +1105,20 @@ __global__ __launch_bounds__(kThreads) void k_count(
                 cnt += stream_t(it.e0, it.e1, kWave, segs, col, hcol, hbase, probe, ws);
                 for (uint32_t i = lane; i < it.d; i += kWave)
                     mem[(col[it.r0 + i] - lo) >> 5] = 0;
+            } else if (hbase + 1 < n1 && slices_aligned) {
+                // a wide span: N+(v)'s entries >= hbase in the high-region bitmap, the ones
+                // below (sorted, in col) searched where suffixes have entries below hbase
+                const uint32_t hr = hrow[it.v];
+                const uint32_t dlo = hr == ~0u ? it.d : hr - it.r0;
+                for (uint32_t i = dlo + lane; i < it.d; i += kWave) {
+                    const uint32_t x = col[it.r0 + i] - hbase;
+                    atomicOr(&mem[x >> 5], 1u << (x & 31u));
+                }
+                wave_lds_sync();
+                const SplitProbe probe{HighBitmapProbe{lds_addr(mem)}, col + it.r0, dlo};
+                cnt += stream_t(it.e0, it.e1, kWave, segs, col, hcol, hbase, probe, ws);
+                for (uint32_t i = dlo + lane; i < it.d; i += kWave)
+                    mem[(col[it.r0 + i] - hbase) >> 5] = 0;
             } else {  // a wide span, but a list that fits the slice (see k_items)
                 for (uint32_t i = lane; i < it.d; i += kWave) mem[i] = col[it.r0 + i];
                 wave_lds_sync();
@@ -1330,13 +1416,13 @@ hipError_t launch_count(const CountArgs &x, bool per_vertex, hipStream_t s) {
                            x.er, x.item_v_a, x.item_off_a, x.n_items_a,
                            x.item_v_b, x.item_off_b, x.n_items_b, x.queue_a, x.queue_b, x.total,
                            x.tpv, x.n1, x.p0, x.wave_bits, x.block_bits, x.block_list,
-                           x.kitem_a, x.kitem_b, x.hcol, x.hbase, x.status);
+                           x.kitem_a, x.kitem_b, x.hcol, x.hrow, x.hbase, x.status);
     else
         hipLaunchKernelGGL(k_count<false>, grid, block, 0, s, x.row_ptr, x.col, x.cptr, x.cbeg,
                            x.er, x.item_v_a, x.item_off_a, x.n_items_a,
                            x.item_v_b, x.item_off_b, x.n_items_b, x.queue_a, x.queue_b, x.total,
                            x.tpv, x.n1, x.p0, x.wave_bits, x.block_bits, x.block_list,
-                           x.kitem_a, x.kitem_b, x.hcol, x.hbase, x.status);
+                           x.kitem_a, x.kitem_b, x.hcol, x.hrow, x.hbase, x.status);
     return hipGetLastError();
 }
 

@@ -34,6 +34,11 @@ __device__ __forceinline__ uint32_t wave_bcast(uint32_t x, int src) {
     return (uint32_t)__shfl((int)x, src, kWave);
 }
 
+// x of lane src (a per-lane index; all lanes active)
+__device__ __forceinline__ uint32_t wave_bcast_from(uint32_t x, uint32_t src) {
+    return (uint32_t)__builtin_amdgcn_ds_bpermute((int)(src << 2), (int)x);
+}
+
 // inclusive prefix sum over the 64 lanes (inactive lanes must hold 0 and be active)
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
     const uint32_t l = lane_id();
@@ -43,6 +48,23 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
         if (l >= (uint32_t)d) x += y;
     }
     return x;
+}
+
+// inclusive prefix maximum over the 64 lanes (all lanes active): row shifts by 1, 2, 4, 8
+// inside each 16-lane row (lanes shifted in from outside read 0), then the last lane of rows
+// 0 and 2 into rows 1 and 3, and lane 31 into rows 2 and 3
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ uint32_t dpp_max_step(uint32_t v) {
+    return max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kCtrl, kRowMask, 0xf, false));
+}
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t v) {
+    v = dpp_max_step<0x111, 0xf>(v);  // row_shr:1
+    v = dpp_max_step<0x112, 0xf>(v);  // row_shr:2
+    v = dpp_max_step<0x114, 0xf>(v);  // row_shr:4
+    v = dpp_max_step<0x118, 0xf>(v);  // row_shr:8
+    v = dpp_max_step<0x142, 0xa>(v);  // row_bcast:15
+    v = dpp_max_step<0x143, 0xc>(v);  // row_bcast:31
+    return v;
 }
 
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
@@ -101,7 +123,8 @@ struct CountArgs {
     // and followed by zeros (count_hcol_pad()); totals stream every in-edge suffix's entries
     // >= hbase from here
     const uint16_t *hcol;
-    uint32_t hbase;  // n: no high region
+    const uint32_t *hrow;  // first position >= hbase of every row, all ones for none
+    uint32_t hbase;        // n: no high region
     const uint32_t *item_v_a, *item_off_a, *n_items_a;
     const uint32_t *item_v_b, *item_off_b, *n_items_b;
     uint32_t *queue_a, *queue_b;
