@@ -386,15 +386,13 @@ struct HighBitmapProbe {
     __device__ __forceinline__ uint32_t bits2(uint32_t pr) const { return bit_lo(pr) + bit_hi(pr); }
 };
 
-// N+(v) of a middle vertex below hbase whose rank span is too wide for a bitmap: its entries
-// >= hbase in a high-region bitmap (as HighBitmapProbe), its entries below hbase as a sorted
-// list in global memory (d may be 0).  Masked: a high piece of a suffix that starts below
-// hbase begins at its row's part of hcol, but the padding zeros (rank hbase) may be in N+(v).
-struct SplitProbe {
+// The entries >= hbase of N+(v) for a middle vertex below hbase (a rank span too wide for a
+// bitmap) in a high-region bitmap (as HighBitmapProbe), for the 16-bit pieces only.  Masked:
+// such a suffix's high part starts at its row's part of hcol, but the padding zeros (rank
+// hbase) may be in N+(v).
+struct HighMaskedProbe {
     HighBitmapProbe hi;
-    const uint32_t *lo;
-    uint32_t dlo;
-    static constexpr bool kLow = true;
+    static constexpr bool kLow = true;  // the segments have 32-bit parts (not streamed here)
     static constexpr bool kMaskHigh = true;
     static constexpr bool kPanel = false;
 };
@@ -473,13 +471,7 @@ __device__ __forceinline__ uint32_t high_hits(const Probe &probe,
     }
     return masked_hits(probe, wv, start, first, stop);
 }
-__device__ __forceinline__ uint32_t low_hits(const SplitProbe &probe,
-                                             const uint32_t (&wv)[kPiece], uint32_t start,
-                                             uint32_t first, uint32_t stop) {
-    if (probe.dlo == 0) return 0u;
-    return masked_hits(ListProbe{probe.lo, probe.dlo}, wv, start, first, stop);
-}
-__device__ __forceinline__ uint32_t high_hits(const SplitProbe &probe,
+__device__ __forceinline__ uint32_t high_hits(const HighMaskedProbe &probe,
                                               const uint32_t (&pr)[kPiece / 2], uint32_t,
                                               uint32_t start, uint32_t first, uint32_t stop) {
     uint32_t packed = 0;
@@ -529,7 +521,7 @@ __device__ __forceinline__ uint32_t round_owner(uint32_t *mark, uint32_t my_off,
 // position h; probes without kLow are only given segments with hb == b.  The batch's 32-bit
 // pieces (of [b, hb)) run first, then its 16-bit pieces, each as its own sequence of rounds,
 // so that a round holds pieces of one kind.
-template <class Probe>
+template <class Probe, int kParts = 3>
 __device__ __forceinline__ uint32_t run_batch_t(const SegRec &r,
                                                 const uint32_t *__restrict__ col,
                                                 const uint16_t *__restrict__ hcol,
@@ -545,6 +537,7 @@ __device__ __forceinline__ uint32_t run_batch_t(const SegRec &r,
     constexpr uint32_t kPh = Probe::kMaskHigh ? kPiece : kPieceHigh;
     const uint32_t hl = en - hb;
     const uint32_t ph = hl ? (h + hl - (h & ~7u) + kPh - 1) / kPh : 0u;
+    static_assert(kParts >= 1 && kParts <= 3, "kParts: 1 the 32-bit pieces, 2 the 16-bit ones");
     ws.off[lane] = 0u;  // the rounds' marker table
     ws.aux[lane] = h;
     if constexpr (Probe::kLow) {
@@ -555,7 +548,7 @@ __device__ __forceinline__ uint32_t run_batch_t(const SegRec &r,
     if constexpr (Probe::kMaskHigh) ws.tag[lane] = h + hl;
     if constexpr (Probe::kPanel) ws.tag[lane] = r.y;
     uint32_t hits_total = 0, carry = 0, round = 0;
-    if constexpr (Probe::kLow) {  // the 32-bit pieces
+    if constexpr (Probe::kLow && (kParts & 1)) {  // the 32-bit pieces
         const uint32_t incl = wave_incl_scan(pl);
         const uint32_t Q = wave_bcast(incl, kWave - 1);
         const uint32_t my_off = incl - pl;
@@ -581,7 +574,7 @@ __device__ __forceinline__ uint32_t run_batch_t(const SegRec &r,
         }
         carry = 0;
     }
-    {  // the 16-bit pieces
+    if constexpr ((kParts & 2) != 0) {  // the 16-bit pieces
         const uint32_t incl = wave_incl_scan(ph);
         const uint32_t Q = wave_bcast(incl, kWave - 1);
         const uint32_t my_off = incl - ph;
@@ -618,7 +611,7 @@ __device__ __forceinline__ uint32_t run_batch_t(const SegRec &r,
 // take consecutive segments) of an item ending at e1 for total counts.  (Fetching the
 // records a batch or two ahead measured no faster: the gathers' lines, not their latency,
 // are the cost.)
-template <class Probe, class Segs>
+template <int kParts = 3, class Probe, class Segs>
 __device__ __forceinline__ uint32_t stream_t(uint32_t first, uint32_t e1, uint32_t step,
                                              const Segs &segs,
                                              const uint32_t *__restrict__ col,
@@ -628,7 +621,7 @@ __device__ __forceinline__ uint32_t stream_t(uint32_t first, uint32_t e1, uint32
     uint32_t hits = 0;
     for (uint32_t eb = first; eb < e1; eb += step) {
         const SegRec r = eb + lane < e1 ? segs.rec(eb + lane) : SegRec{0u, 0u, 0u, 0u, 0u};
-        hits += run_batch_t(r, col, hcol, hbase, probe, ws);
+        hits += run_batch_t<Probe, kParts>(r, col, hcol, hbase, probe, ws);
     }
     return hits;
 }
@@ -1106,17 +1099,29 @@ __global__ __launch_bounds__(kThreads) void k_count(
                 for (uint32_t i = lane; i < it.d; i += kWave)
                     mem[(col[it.r0 + i] - lo) >> 5] = 0;
             } else if (hbase + 1 < n1 && slices_aligned) {
-                // a wide span: N+(v)'s entries >= hbase in the high-region bitmap, the ones
-                // below (sorted, in col) searched where suffixes have entries below hbase
+                // a wide span (a list of at most wave_list_max <= kSliceWords entries, see
+                // k_items): the suffixes' entries below hbase against N+(v)'s entries below
+                // hbase as a sorted list in the slice, then their entries >= hbase against
+                // N+(v)'s in the high-region bitmap (no pass for a part N+(v) lacks)
                 const uint32_t hr = hrow[it.v];
                 const uint32_t dlo = hr == ~0u ? it.d : hr - it.r0;
+                if (dlo > 0) {
+                    for (uint32_t i = lane; i < dlo; i += kWave) mem[i] = col[it.r0 + i];
+                    wave_lds_sync();
+                    const ListProbe lp{mem, dlo};
+                    cnt += stream_t<1>(it.e0, it.e1, kWave, segs, col, hcol, hbase, lp, ws);
+                    for (uint32_t i = lane; i < dlo; i += kWave) mem[i] = 0;
+                    wave_lds_sync();
+                }
                 for (uint32_t i = dlo + lane; i < it.d; i += kWave) {
                     const uint32_t x = col[it.r0 + i] - hbase;
                     atomicOr(&mem[x >> 5], 1u << (x & 31u));
                 }
                 wave_lds_sync();
-                const SplitProbe probe{HighBitmapProbe{lds_addr(mem)}, col + it.r0, dlo};
-                cnt += stream_t(it.e0, it.e1, kWave, segs, col, hcol, hbase, probe, ws);
+                if (dlo < it.d) {
+                    const HighMaskedProbe probe{HighBitmapProbe{lds_addr(mem)}};
+                    cnt += stream_t<2>(it.e0, it.e1, kWave, segs, col, hcol, hbase, probe, ws);
+                }
                 for (uint32_t i = dlo + lane; i < it.d; i += kWave)
                     mem[(col[it.r0 + i] - hbase) >> 5] = 0;
             } else {  // a wide span, but a list that fits the slice (see k_items)
