@@ -641,6 +641,9 @@ def main():
     # counters were taken on other sources.  algorithmic: 4 B per element the kernel streams
     # + 12 B per segment (its range and panel mask) + the node array and out-lists once.
     ctr = load_counters("k_count", args.workload)
+    if ctr and json.loads(ctr.get("options", "{}")) != {k: full_opts[k] for k in
+                                                        json.loads(ctr.get("options", "{}"))}:
+        ctr = None  # taken with other counting-phase options than the ones timed here
     t_s = count_ms * 1e-3
     alg_bytes = (4.0 * streamed_low + 2.0 * (streamed - streamed_low) + 12.0 * segments +
                  4.0 * (n + 1) + 4.0 * m)
@@ -649,7 +652,8 @@ def main():
     if traffic:
         achieved, basis = traffic / t_s / 1e9, "counter bytes (FETCH_SIZE, WRITE_SIZE) / kernel time"
     else:
-        achieved, basis = alg_gbs, "algorithmic bytes / kernel time (no current counters)"
+        achieved, basis = alg_gbs, ("algorithmic bytes / kernel time (no counters for these "
+                                    "sources and options)")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "basis": basis, "kernel": "k_count<false>", "kernel_ms": round(count_ms, 4),

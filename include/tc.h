@@ -110,10 +110,13 @@ const char *tc_strerror(int status);
  *   sort_onesweep     0 (default): every radix pass is a histogram pass, a scan and a scatter;
  *                     1: sorts of at least 2^20 keys use single-sweep passes (decoupled
  *                     look-back).
- *   high_ranks        the node array's entries among the top high_ranks ranks (at least the
- *                     panel region) are also kept as 16-bit offsets, and total counts stream
- *                     them at two bytes instead of four; 0..65536, default 65536 (on R-MAT
- *                     graphs nearly all streamed entries are such ranks). */
+ *   high_ranks        the node array's entries among the top high_ranks ranks are also kept
+ *                     as 16-bit offsets, and total counts stream them at two bytes instead of
+ *                     four (on R-MAT graphs nearly all streamed entries are such ranks); the
+ *                     region is widened to take in the whole panel region.  1..65536, default
+ *                     65536; 0: no 16-bit region (panels and totals read 32-bit ranks only).
+ *                     The region is also dropped when its padded copy of the node array would
+ *                     need 2^32 or more entries. */
 typedef struct tc_options {
     uint32_t size; /* sizeof(tc_options); set by tc_options_init */
     uint32_t panel_ranks;
