@@ -81,14 +81,17 @@ const char *tc_strerror(int status);
  *   panel_ranks       the top ranks of the order of Section 2.2 counted as panels of 32
  *                     consecutive middle vertices; 0..32736, default 32736 (the largest the
  *                     counting kernel's LDS table holds); 0 = no panels.  tc_count_per_vertex
- *                     always prepares without panels.
+ *                     caps the region at 16352 ranks, the panels whose table and per-vertex
+ *                     counters fit the per-vertex panel kernel's LDS (a workspace prepared by
+ *                     tc_preprocess keeps its region; per-vertex counts on it take the wider
+ *                     panels one panel vertex at a time).
  *   hub_ranks         the top ranks whose triangles (lowest vertex a hub) are counted as a
  *                     masked int8 matrix product on the matrix cores; 0..65536, default 0 (off).
  *   row_blocks        the in-edge lists split into this many contiguous CSR row blocks,
  *                     counted one after another; 1..8, default 1.
  *   wave_item_edges   in-edges per work item of the per-wave queue; 16..65536, default 512.
  *   block_item_edges  in-edges per work item of the per-workgroup queue; 16..1048576,
- *                     default 16384.
+ *                     default 65536.
  * Per-item structure of N+(v) (the defaults are the largest values the LDS holds; lower values
  * send items to the other forms, which the tests use to reach every form on small graphs):
  *   wave_bitmap_span  a wave item tests membership in an LDS bitmap when the rank span of

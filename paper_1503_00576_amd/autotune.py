@@ -12,7 +12,8 @@ Single graphs (tune_single): the options of tc_options that shape the counting p
 per-workgroup queue).  The tuner times the whole step (tc_preprocess + tc_count_prepared) on
 the caller's graph for every candidate, in one workspace large enough for all of them.
 
-Both keep the fastest candidate and can cache the choice in a JSON file, keyed by the device
+Both keep the fastest candidate (for single graphs the library defaults when they come within
+TIE of it) and can cache the choice in a JSON file, keyed by the device
 and a size class of the input (sizes by powers of two, and the share of the work in the
 heaviest rows, which decides how much the panel region and the heavy path matter)."""
 from __future__ import annotations
@@ -33,6 +34,7 @@ LIGHT_MAX = (64, 128, 256)
 PANEL_RANKS = (0, 8192, 16384, 32736)
 WAVE_ITEM_EDGES = (256, 512, 1024)
 BLOCK_ITEM_EDGES = (4096, 16384, 65536)
+TIE = 0.003  # relative margin within which the library defaults are kept
 
 
 def _device_key(device) -> str:
@@ -155,6 +157,17 @@ def tune_single(edges: torch.Tensor, n: int, reps: int = 2, cache: str | None = 
     ws = torch.empty(need, dtype=torch.uint8, device=device)
     timings = [(c, time_step(edges, n, c, ws, reps)) for c in uniq]
     del ws
-    best = min(timings, key=lambda x: x[1])[0]
+    best = _prefer_defaults(timings)
     _store(cache, key, best, timings)
     return best, timings
+
+
+def _prefer_defaults(timings, tie: float = TIE) -> dict:
+    """The fastest candidate, or the library defaults when they are within `tie` of it (the
+    candidates near the top often differ by less than the run-to-run spread)."""
+    best, best_ms = min(timings, key=lambda x: x[1])
+    defaults = api.default_options()
+    for c, ms in timings:
+        if all(defaults.get(k) == v for k, v in c.items()) and ms <= best_ms * (1.0 + tie):
+            return c
+    return best

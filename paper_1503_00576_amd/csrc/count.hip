@@ -47,7 +47,7 @@ constexpr uint32_t kBlockBits = kLdsWords * 32 - 32;  // workgroup bitmap: span 
 constexpr uint32_t kBlockList = kLdsWords;            // workgroup sorted list
 constexpr uint32_t kBlockListPV = kLdsWords / 2;      // per-vertex: list + counters
 constexpr uint32_t kItemEdgesWave = 512;     // default in-edges per wave item
-constexpr uint32_t kItemEdgesBlock = 16384;  // default in-edges per workgroup item
+constexpr uint32_t kItemEdgesBlock = 65536;  // default in-edges per workgroup item
 constexpr uint32_t kPanel = 32;                       // one bit per panel vertex in a mask
 constexpr uint32_t kPanelRanks = kLdsWords - 32;      // mask table: one word per rank
 // per-vertex counts over a panel keep a third-vertex counter beside every mask word, so the

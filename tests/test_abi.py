@@ -153,7 +153,7 @@ def test_options(lib):
     from paper_1503_00576_amd import _native, api
     d = api.default_options()
     assert d == {"panel_ranks": 32736, "hub_ranks": 0, "row_blocks": 1, "wave_item_edges": 512,
-                 "block_item_edges": 16384, "wave_bitmap_span": 65504, "wave_list_max": 2048,
+                 "block_item_edges": 65536, "wave_bitmap_span": 65504, "wave_list_max": 2048,
                  "block_bitmap_span": 1048544, "block_list_max": 32768, "degree_partition": 1,
                  "sort_onesweep": 0, "high_ranks": 65536}
     assert lib.tc_options_init(None) == api.E_ARG
@@ -190,6 +190,19 @@ def test_options(lib):
     assert api.workspace_size(1000, 9000, options={"wave_item_edges": 16}) > base
     with pytest.raises(KeyError):
         api._opts({"bogus": 1})
+
+
+def test_single_tuner_prefers_defaults_on_ties(lib):
+    """The single-graph tuner keeps the library defaults when they time within its tie margin
+    of the fastest candidate, and the fastest candidate otherwise (host logic)."""
+    from paper_1503_00576_amd import api, autotune
+    d = api.default_options()
+    dflt = {k: d[k] for k in ("panel_ranks", "wave_item_edges", "block_item_edges")}
+    other = dict(dflt, wave_item_edges=1024)
+    slow = dict(dflt, panel_ranks=0)
+    assert autotune._prefer_defaults([(slow, 40.0), (other, 32.0), (dflt, 32.05)]) == dflt
+    assert autotune._prefer_defaults([(slow, 40.0), (other, 32.0), (dflt, 33.0)]) == other
+    assert autotune._prefer_defaults([(slow, 40.0), (other, 32.0)]) == other
 
 
 def ablation_header_functions():
