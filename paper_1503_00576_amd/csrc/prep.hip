@@ -35,7 +35,7 @@ constexpr int kPartThreads = 256;
 constexpr int kPartEdges = 16;                               // edges per thread
 constexpr uint32_t kPartTile = kPartThreads * kPartEdges;    // 4096 edges per tile
 constexpr uint32_t kPartWindow = 32768;                      // LDS counters per workgroup
-constexpr uint32_t kPartLoads = 8;                           // loads in flight per thread
+constexpr uint32_t kPartLoads = 4;                           // 16-byte loads in flight per thread
 
 __device__ __forceinline__ bool endpoint_ok(int2 e, uint32_t n) {
     return (uint32_t)e.x < n && (uint32_t)e.y < n && e.x != e.y;
@@ -179,18 +179,36 @@ __global__ __launch_bounds__(1024) void k_part_count(const uint32_t *__restrict_
         for (uint32_t i = t; i < wn; i += blockDim.x) cntr[i] = 0;
         __syncthreads();
         const uint32_t lo = (uint32_t)(id0 + w0);
-        // kPartLoads loads in flight per thread before their LDS increments
-        const uint64_t stride = (uint64_t)blockDim.x * kPartLoads;
-        for (uint64_t j0 = s0 + t; j0 < s1; j0 += stride) {
-            uint32_t x[kPartLoads];
+        // the slice's 16-byte aligned body as uint4 loads, kPartLoads of them in flight per
+        // thread before their LDS increments; the unaligned ends one endpoint per thread
+        const uint32_t q0 = (s0 + 3u) >> 2, q1 = s1 >> 2;  // body: endpoints [4 q0, 4 q1)
+        const uint32_t e0 = q0 < q1 ? 4u * q0 : s1, e1 = q0 < q1 ? 4u * q1 : s1;
+        if (t < e0 - s0) {
+            const uint32_t x = parts[s0 + t] - lo;
+            if (x < wn) atomicAdd(&cntr[x], 1u);
+        }
+        if (t < s1 - e1) {
+            const uint32_t x = parts[e1 + t] - lo;
+            if (x < wn) atomicAdd(&cntr[x], 1u);
+        }
+        const uint4 *__restrict__ parts4 = reinterpret_cast<const uint4 *>(parts);
+        const uint32_t stride = blockDim.x * kPartLoads;
+        for (uint32_t j0 = q0 + t; j0 < q1; j0 += stride) {
+            uint4 x[kPartLoads];
 #pragma unroll
             for (uint32_t k = 0; k < kPartLoads; ++k) {
-                const uint64_t j = j0 + (uint64_t)k * blockDim.x;
-                x[k] = j < s1 ? parts[j] - lo : 0xFFFFFFFFu;
+                const uint32_t j = j0 + k * blockDim.x;
+                x[k] = j < q1 ? parts4[j] : make_uint4(~0u, ~0u, ~0u, ~0u);
             }
 #pragma unroll
-            for (uint32_t k = 0; k < kPartLoads; ++k)
-                if (x[k] < wn) atomicAdd(&cntr[x[k]], 1u);
+            for (uint32_t k = 0; k < kPartLoads; ++k) {
+                const uint32_t a = x[k].x - lo, b = x[k].y - lo, c = x[k].z - lo,
+                               d = x[k].w - lo;
+                if (a < wn) atomicAdd(&cntr[a], 1u);
+                if (b < wn) atomicAdd(&cntr[b], 1u);
+                if (c < wn) atomicAdd(&cntr[c], 1u);
+                if (d < wn) atomicAdd(&cntr[d], 1u);
+            }
         }
         __syncthreads();
         for (uint32_t i = t; i < wn; i += blockDim.x) {
