@@ -195,6 +195,37 @@ __device__ __forceinline__ void walk_entries(const RowWalk &rw, uint32_t base, u
     }
 }
 
+// The steps of k_b_ffill's walk: the entries and their forward flags from k_b_setup (no degree
+// lookups); fills valid, fwd, k, first, last and y.
+__device__ __forceinline__ void walk_entries_flagged(const RowWalk &rw, uint32_t base,
+                                                     uint32_t total, const int32_t *col_p,
+                                                     const uint8_t *__restrict__ fflag,
+                                                     WalkEntry (&en)[kWalkSteps]) {
+    const gptr_i32 col = (gptr_i32)col_p;
+    const uint32_t lane = lane_id();
+    uint32_t f[kWalkSteps];
+#pragma unroll
+    for (int u = 0; u < kWalkSteps; ++u) {
+        const uint32_t idx = base + (uint32_t)u * kWave + lane;
+        en[u].valid = idx < total;
+        const uint32_t k = walk_owner(rw, en[u].valid ? idx : total - 1);
+        en[u].k = k;
+        en[u].j = (en[u].valid ? idx : total - 1) - rw.off[k];
+        const uint32_t at = rw.ebeg[k] + en[u].j;
+        en[u].y = col[at];
+        f[u] = fflag[at];
+    }
+#pragma unroll
+    for (int u = 0; u < kWalkSteps; ++u) {
+        const uint32_t k = en[u].k;
+        en[u].fwd = en[u].valid && f[u] != 0u;
+        const uint32_t sb = base + (uint32_t)u * kWave;
+        const uint32_t rb = rw.off[k], re = rw.off[k] + rw.len[k];
+        en[u].first = (rb > sb ? rb : sb) - sb;
+        en[u].last = (re < sb + kWave ? re : sb + kWave) - 1 - sb;
+    }
+}
+
 // Per vertex: graph id, degree (row length), forward out-degree (entries ncap.. stay zero for
 // the scan), checks of its row (offsets in range, ids in range, no self-loop, strictly
 // ascending), and its share of the graph's symmetry sum: sum over the row's entries (x, y) of
@@ -204,6 +235,7 @@ __global__ __launch_bounds__(256) void k_b_setup(const BatchArgs *__restrict__ a
                                                  uint32_t ncap, uint32_t *__restrict__ gid,
                                                  uint32_t *__restrict__ deg,
                                                  uint32_t *__restrict__ fdeg,
+                                                 uint8_t *__restrict__ fflag,
                                                  unsigned long long *__restrict__ ghash,
                                                  int32_t *__restrict__ gstat) {
     __shared__ RowWalk s_rw[4];
@@ -267,6 +299,7 @@ __global__ __launch_bounds__(256) void k_b_setup(const BatchArgs *__restrict__ a
                     hsum += pair_hash(lk, (uint32_t)en.y) - pair_hash((uint32_t)en.y, lk);
                 }
             }
+            if (en.valid) fflag[rw.ebeg[en.k] + en.j] = en.fwd ? 1u : 0u;
             const uint64_t F = __ballot(en.valid && en.fwd);
             // forward entries per row in this step, added by the row's last lane in the step
             if (en.valid && lane == en.last)
@@ -291,6 +324,7 @@ __global__ __launch_bounds__(256) void k_b_ffill(const BatchArgs *__restrict__ a
                                                  const uint32_t *__restrict__ gid,
                                                  const uint32_t *__restrict__ deg,
                                                  const uint32_t *__restrict__ frp,
+                                                 const uint8_t *__restrict__ fflag,
                                                  uint32_t *__restrict__ fcol,
                                                  uint32_t *__restrict__ fsrc) {
     __shared__ RowWalk s_rw[4];
@@ -315,7 +349,7 @@ __global__ __launch_bounds__(256) void k_b_ffill(const BatchArgs *__restrict__ a
     wave_lds_sync();
     for (uint32_t base = 0; base < total; base += kWalkSteps * kWave) {
         WalkEntry ens[kWalkSteps];
-        walk_entries(rw, base, total, a.col, a.row_ptr, ens);
+        walk_entries_flagged(rw, base, total, a.col, fflag, ens);
 #pragma unroll
         for (int u = 0; u < kWalkSteps; ++u) {
             const WalkEntry &en = ens[u];
@@ -393,8 +427,8 @@ __global__ void k_b_finish(const BatchArgs *__restrict__ args, const uint32_t *_
 // ------------------------------------------------------------------ workspace + plan
 
 struct BatchLayout {
-    size_t args, ctl, gstat, ghash, gid, deg, fdeg, frp, fcol, fsrc, items, ioff, item_u, scan,
-        total;
+    size_t args, ctl, gstat, ghash, gid, deg, fdeg, frp, fcol, fsrc, fflag, items, ioff, item_u,
+        scan, total;
 };
 
 constexpr uint32_t kMinItemEdges = 16;
@@ -418,6 +452,7 @@ static BatchLayout batch_layout(uint32_t gcap, uint32_t ncap, uint64_t acap) {
     L.frp = take(n1 * 4);
     L.fcol = take((size_t)acap * 4 + count_col_pad_bytes());
     L.fsrc = take((size_t)acap * 4);
+    L.fflag = take((size_t)acap);  // one byte per input entry: forward (k_b_setup)
     L.items = take(n1 * 4);
     L.ioff = take(n1 * 4);
     L.item_u = take(((size_t)acap / kMinItemEdges + n1 + 1) * 4);
@@ -485,11 +520,13 @@ static int batch_enqueue(tc_plan *p, bool pv, hipStream_t s) {
     hipLaunchKernelGGL(k_b_clear, dim3(1024), dim3(256), 0, s, args, gstat, ghash, ctl, cap);
     // one wave per 64 vertices, four waves per workgroup
     auto vgrid = [](uint64_t n) { return dim3((uint32_t)((n + 255) / 256)); };
-    hipLaunchKernelGGL(k_b_setup, vgrid(n1), dim3(256), 0, s, args, ncap, gid, deg, fdeg, ghash,
-                       gstat);
+    uint8_t *fflag = (uint8_t *)(ws + L.fflag);
+    hipLaunchKernelGGL(k_b_setup, vgrid(n1), dim3(256), 0, s, args, ncap, gid, deg, fdeg, fflag,
+                       ghash, gstat);
     if (hipGetLastError() != hipSuccess) return TC_E_HIP;
     if (scan_exclusive_u32(fdeg, frp, n1, scan, s) != hipSuccess) return TC_E_HIP;
-    hipLaunchKernelGGL(k_b_ffill, vgrid(ncap), dim3(256), 0, s, args, gid, deg, frp, fcol, fsrc);
+    hipLaunchKernelGGL(k_b_ffill, vgrid(ncap), dim3(256), 0, s, args, gid, deg, frp, fflag, fcol,
+                       fsrc);
     // ctl: [0] heavy-item queue, [1] light-chunk queue, [2] forward edges, [3] light chunks
     hipLaunchKernelGGL(k_b_items, grid(n1), dim3(256), 0, s, args, ncap, fdeg, frp,
                        p->light_max, items, ctl + 2);
