@@ -80,11 +80,7 @@ const char *tc_strerror(int status);
  * of each triangle u < v < w: N+(v) staged in LDS, the in-neighbours' lists streamed):
  *   panel_ranks       the top ranks of the order of Section 2.2 counted as panels of 32
  *                     consecutive middle vertices; 0..32736, default 32736 (the largest the
- *                     counting kernel's LDS table holds); 0 = no panels.  tc_count_per_vertex
- *                     caps the region at 16352 ranks, the panels whose table and per-vertex
- *                     counters fit the per-vertex panel kernel's LDS (a workspace prepared by
- *                     tc_preprocess keeps its region; per-vertex counts on it take the wider
- *                     panels one panel vertex at a time).
+ *                     counting kernel's LDS table holds); 0 = no panels.
  *   hub_ranks         the top ranks whose triangles (lowest vertex a hub) are counted as a
  *                     masked int8 matrix product on the matrix cores; 0..65536, default 0 (off).
  *   row_blocks        the in-edge lists split into this many contiguous CSR row blocks,

@@ -181,10 +181,8 @@ static int id_bits_for64(uint64_t x) {
     return b;
 }
 
-// panel_cap: at most this many panel ranks whatever the options say (a smaller panel region
-// needs no more workspace than the default layout: only the panel range table shrinks)
-static bool make_layout(int64_t n, int64_t m, uint32_t flags, const tc_options *opts, Layout &L,
-                        uint32_t panel_cap = ~0u) {
+static bool make_layout(int64_t n, int64_t m, uint32_t flags, const tc_options *opts,
+                        Layout &L) {
     if (n < 0 || m < 0 || n >= (1ll << 31) || m >= (1ll << 32)) return false;
     if (flags & ~TC_EDGES_BOTH) return false;
     if (!resolve_options(opts, L.opt)) return false;
@@ -197,8 +195,7 @@ static bool make_layout(int64_t n, int64_t m, uint32_t flags, const tc_options *
     // row blocks: at most what 32-bit list ids (block * (n + 1) + v) allow
     L.nblk = o.row_blocks;
     while (L.nblk > 1 && (uint64_t)L.nblk * ((uint64_t)n + 1) >= (1ull << 32)) --L.nblk;
-    uint32_t pr = o.panel_ranks < panel_cap ? o.panel_ranks : panel_cap;
-    pr = pr < L.n ? pr : L.n;
+    const uint32_t pr = o.panel_ranks < L.n ? o.panel_ranks : L.n;
     L.p0 = L.n - pr;
     {
         const uint32_t h = o.hub_ranks < L.n ? o.hub_ranks : L.n;
@@ -327,14 +324,13 @@ static inline uint32_t grid_for(uint64_t items, uint32_t threads, uint32_t cap =
     } while (0)
 
 static int check_args(const int32_t *d_edges, int64_t n, int64_t m, uint32_t flags,
-                      const tc_options *opts, void *d_ws, size_t ws_bytes, Layout &L,
-                      uint32_t panel_cap = ~0u) {
+                      const tc_options *opts, void *d_ws, size_t ws_bytes, Layout &L) {
     if (n < 0 || m < 0 || (flags & ~TC_EDGES_BOTH)) return TC_E_ARG;
     if (n >= (1ll << 31) || m >= (1ll << 32)) return TC_E_TOO_LARGE;
     if (n == 0 && m > 0) return TC_E_ARG;
     if (m > 0 && (!d_edges || ((uintptr_t)d_edges & 7))) return TC_E_ARG;
     if ((flags & TC_EDGES_BOTH) && (m & 1)) return TC_E_ASYMMETRIC;
-    if (!make_layout(n, m, flags, opts, L, panel_cap)) return TC_E_ARG;
+    if (!make_layout(n, m, flags, opts, L)) return TC_E_ARG;
     if (!d_ws || ((uintptr_t)d_ws & 255) || ws_bytes < L.total_bytes) return TC_E_WORKSPACE;
     return TC_OK;
 }
@@ -580,15 +576,12 @@ static int copy_status(void *ws, const Layout &L, int32_t *d_status, hipStream_t
     return TC_OK;
 }
 
-// Preprocessing and counting in one call.  With per-vertex counts the panel region is capped
-// at what the per-vertex panel kernel holds in LDS (a wider panel would be counted one panel
-// vertex at a time).
+// Preprocessing and counting in one call.
 static int run_count(const int32_t *d_edges, int64_t n, int64_t m, uint32_t flags,
                      const tc_options *opts, void *ws, size_t ws_bytes, hipStream_t s,
                      uint64_t *d_total, uint64_t *d_pv, int32_t *d_status) {
     Layout L;
-    int st = check_args(d_edges, n, m, flags, opts, ws, ws_bytes, L,
-                        d_pv == nullptr ? ~0u : count_pv_panel_ranks());
+    int st = check_args(d_edges, n, m, flags, opts, ws, ws_bytes, L);
     if (st) return st;
     if (!d_total) return TC_E_ARG;
     st = run_preprocess(d_edges, flags, ws, L, s);

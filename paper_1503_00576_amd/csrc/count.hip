@@ -50,15 +50,11 @@ constexpr uint32_t kItemEdgesWave = 512;     // default in-edges per wave item
 constexpr uint32_t kItemEdgesBlock = 65536;  // default in-edges per workgroup item
 constexpr uint32_t kPanel = 32;                       // one bit per panel vertex in a mask
 constexpr uint32_t kPanelRanks = kLdsWords - 32;      // mask table: one word per rank
-// per-vertex counts over a panel keep a third-vertex counter beside every mask word, so the
-// panel's rank span must fit half of the workgroup's LDS
+// per-vertex counts over a panel keep a third-vertex counter beside every mask word, so a
+// panel's ranks are taken in windows of kPvWindow ranks, each with its table and counters in
+// half of the workgroup's LDS (words 0 .. kPvWindow - 1, and word kPvWindow always zero)
 constexpr uint32_t kPvPanelWords = kLdsWords / 2;
-constexpr uint32_t kPvPanelRanks = kPvPanelWords - 32;
-// the panel starting at rank P (of n1 - 1 ranks) has its mask table and counters in LDS:
-// words 0 .. n1 - P - 1, the last one always zero
-__device__ __forceinline__ bool pv_panel_fits(uint32_t P, uint32_t n1) {
-    return n1 - P <= kPvPanelWords;
-}
+constexpr uint32_t kPvWindow = kPvPanelWords - 1;
 // batched kernel: rows with at most kLightMax forward entries are counted edge by edge; a
 // chunk of forward edges plus kLightMax entries on either side must fit one wave's slice
 constexpr uint32_t kLightMax = 256;
@@ -172,26 +168,6 @@ struct PanelSegs {
         return SegRec{b, x.x, x.y, x.z, x.w};
     }
     __device__ __forceinline__ SegRec rec(uint32_t e) const { return rec_from(cbeg[e]); }
-};
-
-// Per-vertex counts over a panel, one panel vertex P + j at a time: segment (u, panel) stands
-// for the in-edge u -> P + j when bit j of R(u) is set.  u's panel vertices are consecutive in
-// N+(u) starting right before cbeg, so the suffix after P + j starts popcount(R(u) below j)
-// elements later; segments without bit j are empty.
-struct PanelVertexSegs {
-    const uint32_t *cbeg;
-    const uint4 *er;
-    uint32_t j;
-    __device__ __forceinline__ SegRec rec(uint32_t e) const {
-        const uint32_t b0 = cbeg[e];
-        const uint4 x = er[b0 - 1];
-        SegRec r{0u, 0u, 0u, 0u, x.w};
-        if ((x.y >> j) & 1u) {
-            r.b = b0 + __popc(x.y & ((1u << j) - 1u));
-            r.en = x.x;
-        }
-        return r;
-    }
 };
 
 struct OutEdgeSegs {  // u-centric kernel: the whole list N+(v) of out-neighbour v, owner v
@@ -830,9 +806,12 @@ __device__ __forceinline__ uint32_t run_panel_pv(uint32_t eb, uint32_t e1,
     return hits_total;
 }
 
-// Per-vertex counts of the panels whose table and counters fit the LDS (P + kPvPanelWords
-// > n): the workgroup items of those panels, from their own queue counter; every other item
-// is left to k_count<true>.
+// Per-vertex counts of the panels: the workgroup items of the panel region, from their own
+// queue counter (every other item is left to k_count<true>).  The ranks above P are taken in
+// windows of kPvWindow: per window, the table and the third-vertex counters cover its ranks,
+// every segment is streamed whole, and entries outside the window clamp onto the zero word
+// (one window for panels within kPvWindow ranks of the top, two for the rest of a region of
+// up to 32,736 ranks).
 __global__ __launch_bounds__(kThreads) void k_count_panel_pv(
     const uint32_t *__restrict__ row_ptr, const uint32_t *__restrict__ col,
     const uint32_t *__restrict__ cptr, const uint32_t *__restrict__ cbeg,
@@ -864,29 +843,39 @@ __global__ __launch_bounds__(kThreads) void k_count_panel_pv(
         if (q >= n_items_b) break;
         q = n_items_b - 1 - q;
         const ItemRange it = item_range(q, kitem_b, n1, item_v_b, item_off_b, cptr, row_ptr);
-        if (it.v < p0 || !pv_panel_fits(it.v, n1)) continue;  // left to k_count<true>
-        const uint32_t P = it.v, np = min(kPanel, n1 - 1 - P), span = n1 - 2 - P;
-        for (uint32_t j = w; j < np; j += kWaves)
-            for (uint32_t i = row_ptr[P + j] + lane; i < row_ptr[P + j + 1]; i += kWave)
-                atomicOr(&m[col[i] - P], 1u << j);
-        __syncthreads();
+        if (it.v < p0) continue;  // left to k_count<true>
+        const uint32_t P = it.v, np = min(kPanel, n1 - 1 - P);
         uint32_t cnt = 0, pieces = 0;
-        for (uint32_t eb = it.e0 + w * kWave; eb < it.e1; eb += kWaves * kWave)
-            cnt += run_panel_pv(eb, it.e1, psegs, col, m, cnt3, P, span, ws, mc, pieces, s_mid,
-                                tpv);
+        // window of ranks [lo, lo + wn) above P (rank P itself is in no out-list of the panel)
+        for (uint32_t lo = P; lo < n1 - 1; lo += kPvWindow) {
+            const uint32_t wn = min(kPvWindow, n1 - 1 - lo);
+            for (uint32_t j = w; j < np; j += kWaves)
+                for (uint32_t i = row_ptr[P + j] + lane; i < row_ptr[P + j + 1]; i += kWave) {
+                    const uint32_t o = col[i] - lo;
+                    if (o < wn) atomicOr(&m[o], 1u << j);
+                }
+            __syncthreads();
+            for (uint32_t eb = it.e0 + w * kWave; eb < it.e1; eb += kWaves * kWave)
+                cnt += run_panel_pv(eb, it.e1, psegs, col, m, cnt3, lo, wn - 1, ws, mc, pieces,
+                                    s_mid, tpv);
+            __syncthreads();
+            for (uint32_t j = w; j < np; j += kWaves)
+                for (uint32_t i = row_ptr[P + j] + lane; i < row_ptr[P + j + 1]; i += kWave) {
+                    const uint32_t o = col[i] - lo;
+                    if (o < wn) m[o] = 0;
+                }
+            for (uint32_t i = t; i < wn; i += kThreads) {
+                const uint32_t c3 = cnt3[i];
+                if (c3) {
+                    atomicAdd(&tpv[lo + i], (unsigned long long)c3);
+                    cnt3[i] = 0;
+                }
+            }
+            __syncthreads();
+        }
         mc.flush(s_mid);
         acc += cnt;
         __syncthreads();
-        for (uint32_t j = w; j < np; j += kWaves)
-            for (uint32_t i = row_ptr[P + j] + lane; i < row_ptr[P + j + 1]; i += kWave)
-                m[col[i] - P] = 0;
-        for (uint32_t i = t; i <= span; i += kThreads) {
-            const uint32_t c3 = cnt3[i];
-            if (c3) {
-                atomicAdd(&tpv[P + i], (unsigned long long)c3);
-                cnt3[i] = 0;
-            }
-        }
         if (t < np && s_mid[t]) {
             atomicAdd(&tpv[P + t], s_mid[t]);
             s_mid[t] = 0;
@@ -955,46 +944,6 @@ __global__ __launch_bounds__(kThreads) void k_count(
                 for (uint32_t j = w; j < np; j += kWaves)
                     for (uint32_t i = row_ptr[P + j] + lane; i < row_ptr[P + j + 1]; i += kWave)
                         s_mem[col[i] - P] = 0;
-            } else if (pv_panel_fits(P, n1)) {
-                continue;  // counted by k_count_panel_pv
-            } else {
-                // a panel too wide for the per-vertex table: one panel vertex at a time
-                for (uint32_t j = 0; j < np; ++j) {
-                    const uint32_t r0 = row_ptr[P + j], d = row_ptr[P + j + 1] - r0;
-                    if (d == 0) continue;
-                    const bool in_lds = d <= block_list;  // at most kBlockListPV
-                    if (in_lds)
-                        for (uint32_t i = t; i < d; i += kThreads) s_mem[i] = col[r0 + i];
-                    __syncthreads();
-                    const PanelVertexSegs vsegs{cbeg, er, j};
-                    uint32_t cnt = 0;
-                    if (in_lds) {
-                        const ListProbe probe{s_mem, d};
-                        for (uint32_t eb = first; eb < it.e1; eb += step)
-                            cnt += run_batch<true>(eb, it.e1, vsegs, col, probe, ws,
-                                                   s_mem + kBlockListPV, tpv);
-                    } else {
-                        const ListProbe probe{col + r0, d};
-                        for (uint32_t eb = first; eb < it.e1; eb += step)
-                            cnt += run_batch<true>(eb, it.e1, vsegs, col, probe, ws, nullptr,
-                                                   tpv);
-                    }
-                    const uint64_t wave_hits = wave_sum_u64(cnt);
-                    if (lane == 0 && wave_hits)
-                        atomicAdd(&tpv[P + j], (unsigned long long)wave_hits);
-                    acc += cnt;
-                    __syncthreads();
-                    if (in_lds) {
-                        for (uint32_t i = t; i < d; i += kThreads) {
-                            s_mem[i] = 0;
-                            const uint32_t c = s_mem[kBlockListPV + i];
-                            if (c) {
-                                atomicAdd(&tpv[col[r0 + i]], (unsigned long long)c);
-                                s_mem[kBlockListPV + i] = 0;
-                            }
-                        }
-                    }
-                }
             }
             continue;
         }
@@ -1404,7 +1353,6 @@ uint32_t count_wgs_per_cu() { return kWgsPerCu; }
 uint32_t count_light_max() { return kLightMax; }
 uint32_t count_light_chunk_max() { return kLightChunkMax; }
 uint32_t count_panel_ranks() { return kPanelRanks; }
-uint32_t count_pv_panel_ranks() { return kPvPanelRanks; }
 
 hipError_t launch_count(const CountArgs &x, bool per_vertex, hipStream_t s) {
     const dim3 grid(device_cu_count() * kWgsPerCu), block(kThreads);

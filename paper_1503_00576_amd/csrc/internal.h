@@ -158,8 +158,6 @@ uint32_t count_hcol_pad();
 uint32_t count_panel();
 uint32_t count_wgs_per_cu();  // resident workgroups per CU of the counting kernels
 uint32_t count_panel_ranks();
-// the largest panel region whose panels all fit the per-vertex panel kernel's LDS
-uint32_t count_pv_panel_ranks();
 // hub triangles on the matrix cores (hub.hip): A / At are hp x hp int8, hubs = ranks h0 ..
 hipError_t launch_hub_fill(const uint32_t *src, const uint32_t *col, const uint32_t *row_ptr,
                            uint32_t mf, uint32_t h0, uint32_t hp, uint8_t *A, uint8_t *At,

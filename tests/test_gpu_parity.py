@@ -177,9 +177,9 @@ def test_panel_thresholds(ranks):
 
 
 def test_wide_panels_per_vertex():
-    """Per-vertex counts on a graph prepared with more panel ranks than the per-vertex panel
-    kernel holds: the lower panels are counted one panel vertex at a time by the other
-    kernel, the upper ones by the panel kernel; the one-shot call caps its panel region."""
+    """Per-vertex counts with more panel ranks than one window of the per-vertex panel kernel
+    holds: the lower panels take their ranks in two windows (every segment streamed once per
+    window), the upper ones in one; both on a prepared graph and in the one-shot call."""
     e, n = synth.rmat_graph(15, 16, seed=12)
     assert n > 16384 + 64
     for ranks in (32736, 20000):
