@@ -806,6 +806,86 @@ __device__ __forceinline__ uint32_t run_panel_pv(uint32_t eb, uint32_t e1,
     return hits_total;
 }
 
+// The same for panels in the high region: every suffix entry is read from hcol as a 16-bit
+// offset from hbase, in unmasked pieces of kPieceHigh entries (entries of u's row up to its
+// first panel vertex only match panel vertices below it, none of which is in its mask, and
+// padding zeros, rank hbase, lie below the window), with the owners found as in the totals
+// streamer.  The window's table covers offsets [c, c + wn) from hbase.
+__device__ __forceinline__ uint32_t run_panel_pv_high(const SegRec &r,
+                                                      const uint16_t *__restrict__ hcol,
+                                                      const uint32_t *m, uint32_t *cnt3,
+                                                      uint32_t c, uint32_t wn, WaveScratch &ws,
+                                                      MidCounters &mc, uint32_t &pieces,
+                                                      unsigned long long *mid,
+                                                      unsigned long long *__restrict__ tpv) {
+    const uint32_t lane = lane_id();
+    const uint32_t hl = r.en - r.b, h = r.h;
+    const uint32_t ph = hl ? (h + hl - (h & ~7u) + kPieceHigh - 1) / kPieceHigh : 0u;
+    ws.off[lane] = 0u;  // the rounds' marker table
+    ws.aux[lane] = h;
+    ws.tag[lane] = r.y;      // the panel mask R(u)
+    ws.beg[lane] = r.owner;  // u
+    ws.cnt[lane] = 0u;
+    const uint32_t incl = wave_incl_scan(ph);
+    const uint32_t Q = wave_bcast(incl, kWave - 1);
+    const uint32_t my_off = incl - ph;
+    wave_lds_sync();
+    // a piece adds kPieceHigh / kPiece groups of kPiece masks to the middle-vertex counters
+    const uint32_t per_lane = (Q + kWave - 1) / kWave * (kPieceHigh / kPiece);
+    if (pieces + per_lane > kMidPieces) {
+        mc.flush(mid);
+        pieces = 0;
+    }
+    pieces += per_lane;
+    uint32_t hits_total = 0, carry = 0, round = 0;
+    for (uint32_t q0 = 0; q0 < Q; q0 += kWave) {
+        const uint32_t k = round_owner(ws.off, my_off, ph, q0, ++round, carry) - 1u;
+        const uint32_t off_k = wave_bcast_from(my_off, k);
+        const uint32_t q = q0 + lane;
+        uint32_t cm[kPieceHigh];
+#pragma unroll
+        for (uint32_t i = 0; i < kPieceHigh; ++i) cm[i] = 0;
+        if (q < Q) {
+            const uint32_t start = (ws.aux[k] & ~7u) + (q - off_k) * kPieceHigh;
+            const uint4 *p4 = reinterpret_cast<const uint4 *>(hcol + start);
+            uint32_t pr[kPieceHigh / 2];
+#pragma unroll
+            for (uint32_t i = 0; i < kPieceHigh / 8; ++i) {
+                const uint4 x = p4[i];
+                pr[4 * i] = x.x;
+                pr[4 * i + 1] = x.y;
+                pr[4 * i + 2] = x.z;
+                pr[4 * i + 3] = x.w;
+            }
+            const uint32_t rm = ws.tag[k];
+            uint32_t hits = 0;
+#pragma unroll
+            for (uint32_t i = 0; i < kPieceHigh; ++i) {
+                const uint32_t x = (i & 1u) ? (pr[i >> 1] >> 16) : (pr[i >> 1] & 0xFFFFu);
+                const uint32_t o = min(x - c, wn);  // outside the window: the zero word
+                const uint32_t ci = m[o] & rm;
+                cm[i] = ci;
+                const uint32_t hh = __popc(ci);
+                hits += hh;
+                if (hh) atomicAdd(&cnt3[o], hh);
+            }
+            hits_total += hits;
+            if (hits) atomicAdd(&ws.cnt[k], hits);
+        }
+#pragma unroll
+        for (uint32_t g = 0; g < kPieceHigh / kPiece; ++g) {
+            uint32_t d[kPiece];
+#pragma unroll
+            for (uint32_t i = 0; i < kPiece; ++i) d[i] = cm[g * kPiece + i];
+            mc.add16(d);
+        }
+    }
+    wave_lds_sync();
+    if (ws.cnt[lane]) atomicAdd(&tpv[ws.beg[lane]], (unsigned long long)ws.cnt[lane]);
+    wave_lds_sync();
+    return hits_total;
+}
+
 // Per-vertex counts of the panels: the workgroup items of the panel region, from their own
 // queue counter (every other item is left to k_count<true>).  The ranks above P are taken in
 // windows of kPvWindow: per window, the table and the third-vertex counters cover its ranks,
@@ -819,7 +899,7 @@ __global__ __launch_bounds__(kThreads) void k_count_panel_pv(
     const uint32_t *__restrict__ item_off_b, const uint32_t *__restrict__ n_items_b_ptr,
     uint32_t *__restrict__ queue_c, unsigned long long *__restrict__ total,
     unsigned long long *__restrict__ tpv, uint32_t n1, uint32_t p0, uint32_t kitem_b,
-    const int32_t *__restrict__ status) {
+    const uint16_t *__restrict__ hcol, uint32_t hbase, const int32_t *__restrict__ status) {
     __shared__ uint32_t s_mem[kLdsWords];
     __shared__ WaveScratch s_ws[kWaves];
     __shared__ unsigned long long s_mid[kPanel];
@@ -855,9 +935,18 @@ __global__ __launch_bounds__(kThreads) void k_count_panel_pv(
                     if (o < wn) atomicOr(&m[o], 1u << j);
                 }
             __syncthreads();
-            for (uint32_t eb = it.e0 + w * kWave; eb < it.e1; eb += kWaves * kWave)
-                cnt += run_panel_pv(eb, it.e1, psegs, col, m, cnt3, lo, wn - 1, ws, mc, pieces,
-                                    s_mid, tpv);
+            if (P >= hbase) {  // the suffixes are in hcol
+                for (uint32_t eb = it.e0 + w * kWave; eb < it.e1; eb += kWaves * kWave) {
+                    const SegRec r = eb + lane < it.e1 ? psegs.rec(eb + lane)
+                                                       : SegRec{0u, 0u, 0u, 0u, 0u};
+                    cnt += run_panel_pv_high(r, hcol, m, cnt3, lo - hbase, wn, ws, mc, pieces,
+                                             s_mid, tpv);
+                }
+            } else {
+                for (uint32_t eb = it.e0 + w * kWave; eb < it.e1; eb += kWaves * kWave)
+                    cnt += run_panel_pv(eb, it.e1, psegs, col, m, cnt3, lo, wn - 1, ws, mc,
+                                        pieces, s_mid, tpv);
+            }
             __syncthreads();
             for (uint32_t j = w; j < np; j += kWaves)
                 for (uint32_t i = row_ptr[P + j] + lane; i < row_ptr[P + j + 1]; i += kWave) {
@@ -1360,7 +1449,7 @@ hipError_t launch_count(const CountArgs &x, bool per_vertex, hipStream_t s) {
         hipLaunchKernelGGL(k_count_panel_pv, grid, block, 0, s, x.row_ptr, x.col, x.cptr,
                            x.cbeg, x.er, x.item_v_b, x.item_off_b,
                            x.n_items_b, x.queue_c, x.total, x.tpv, x.n1, x.p0, x.kitem_b,
-                           x.status);
+                           x.hcol, x.hbase, x.status);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
