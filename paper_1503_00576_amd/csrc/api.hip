@@ -479,8 +479,9 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
                     onesweep));
     TC_HIP(fill_u32(lrs, 0u, l1, s));
     TC_HIP(fill_u32(lre, 0u, l1, s));
-    hipLaunchKernelGGL(k_csc_final, dim3(grid_for(mf, 256)), dim3(256), 0, s, cks, mf, L.lists,
-                       at<uint32_t>(ws, L.cbeg), lrs, lre, status);
+    hipLaunchKernelGGL(k_csc_final, dim3(grid_for(mf, 256 * 4)), dim3(256), 0, s, cks, mf,
+                       L.lists, at<uint32_t>(ws, L.cbeg), lrs, lre,
+                       status);  // 4 keys per thread (prep.hip, kCscFinalKeys)
     TC_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_rowlen, dim3(grid_for(l1, 256)), dim3(256), 0, s, lrs, lre,
                        (uint32_t)L.lists, cnt);

@@ -536,18 +536,30 @@ __global__ void k_csc_keys(const uint32_t *__restrict__ col, const uint32_t *__r
 // The lists themselves: list c occupies sorted positions [rs[c], re[c]) (useful in-edges
 // only; rs and re zeroed beforehand), and entry j names its in-edge by cbeg[j] = e + 1, the
 // start of the suffix; the counting kernels read the in-edge's record (k_csc_keys) from there.
+// kCscFinalKeys keys a block apart per thread, all loaded before any is used.
+constexpr uint32_t kCscFinalKeys = 4;
 __global__ void k_csc_final(const uint64_t *__restrict__ keys, uint32_t mf, uint64_t lists,
                             uint32_t *__restrict__ cbeg, uint32_t *__restrict__ rs,
                             uint32_t *__restrict__ re, const int32_t *__restrict__ status) {
     if (*status) return;
-    uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= mf) return;
-    const uint64_t k = keys[j];
-    const uint64_t c = k >> 32;
-    if (c >= lists) return;
-    if (j == 0 || (keys[j - 1] >> 32) != c) rs[c] = j;
-    if (j == mf - 1 || (keys[j + 1] >> 32) != c) re[c] = j + 1;
-    cbeg[j] = (uint32_t)k + 1;
+    const uint64_t j0 = (uint64_t)blockIdx.x * blockDim.x * kCscFinalKeys + threadIdx.x;
+    uint64_t k[kCscFinalKeys], kp[kCscFinalKeys], kn[kCscFinalKeys];
+#pragma unroll
+    for (uint32_t t = 0; t < kCscFinalKeys; ++t) {
+        const uint64_t j = j0 + (uint64_t)t * blockDim.x;
+        k[t] = j < mf ? keys[j] : ~0ull;
+        kp[t] = (j < mf && j > 0) ? keys[j - 1] : ~0ull;
+        kn[t] = j + 1 < mf ? keys[j + 1] : ~0ull;
+    }
+#pragma unroll
+    for (uint32_t t = 0; t < kCscFinalKeys; ++t) {
+        const uint64_t j = j0 + (uint64_t)t * blockDim.x;
+        const uint64_t c = k[t] >> 32;
+        if (j >= mf || c >= lists) continue;
+        if (j == 0 || (kp[t] >> 32) != c) rs[c] = (uint32_t)j;
+        if (j == mf - 1 || (kn[t] >> 32) != c) re[c] = (uint32_t)j + 1;
+        cbeg[j] = (uint32_t)k[t] + 1;
+    }
 }
 
 // Work items of the counting kernel.  A vertex's in-edges are cut into chunks; the chunks go
