@@ -179,11 +179,14 @@ def test_panel_thresholds(ranks):
 def test_wide_panels_per_vertex():
     """Per-vertex counts with more panel ranks than one window of the per-vertex panel kernel
     holds: the lower panels take their ranks in two windows (every segment streamed once per
-    window), the upper ones in one; both on a prepared graph and in the one-shot call."""
+    window), the upper ones in one; both on a prepared graph and in the one-shot call, with
+    the suffixes read as 16-bit offsets and, without a 16-bit region, as 32-bit ranks."""
     e, n = synth.rmat_graph(15, 16, seed=12)
     assert n > 16384 + 64
     for ranks in (32736, 20000):
         check_vs_oracle(e.numpy(), n, options={"panel_ranks": ranks}, prepared_pv=True)
+    check_vs_oracle(e.numpy(), n, options={"panel_ranks": 32736, "high_ranks": 0},
+                    prepared_pv=True)
 
 
 def test_single_sweep_sort():
