@@ -151,6 +151,7 @@ struct WalkEntry {
 // past the end or with an out-of-range id are clamped onto valid ones and their values
 // ignored.
 constexpr int kWalkSteps = 4;
+constexpr int kFillSteps = 8;  // the forward fill's walk needs fewer registers per step
 
 // The argument block's pointers are generic; the walk reads through global-address-space
 // views so that its loads are global loads (waited for apart from the LDS traffic).
@@ -200,12 +201,12 @@ __device__ __forceinline__ void walk_entries(const RowWalk &rw, uint32_t base, u
 __device__ __forceinline__ void walk_entries_flagged(const RowWalk &rw, uint32_t base,
                                                      uint32_t total, const int32_t *col_p,
                                                      const uint8_t *__restrict__ fflag,
-                                                     WalkEntry (&en)[kWalkSteps]) {
+                                                     WalkEntry (&en)[kFillSteps]) {
     const gptr_i32 col = (gptr_i32)col_p;
     const uint32_t lane = lane_id();
-    uint32_t f[kWalkSteps];
+    uint32_t f[kFillSteps];
 #pragma unroll
-    for (int u = 0; u < kWalkSteps; ++u) {
+    for (int u = 0; u < kFillSteps; ++u) {
         const uint32_t idx = base + (uint32_t)u * kWave + lane;
         en[u].valid = idx < total;
         const uint32_t k = walk_owner(rw, en[u].valid ? idx : total - 1);
@@ -216,7 +217,7 @@ __device__ __forceinline__ void walk_entries_flagged(const RowWalk &rw, uint32_t
         f[u] = fflag[at];
     }
 #pragma unroll
-    for (int u = 0; u < kWalkSteps; ++u) {
+    for (int u = 0; u < kFillSteps; ++u) {
         const uint32_t k = en[u].k;
         en[u].fwd = en[u].valid && f[u] != 0u;
         const uint32_t sb = base + (uint32_t)u * kWave;
@@ -347,11 +348,11 @@ __global__ __launch_bounds__(256) void k_b_ffill(const BatchArgs *__restrict__ a
     rw.acc[lane] = x < a.N ? frp[x] : 0u;
     rw.fend[lane] = x < a.N ? frp[x + 1] : 0u;
     wave_lds_sync();
-    for (uint32_t base = 0; base < total; base += kWalkSteps * kWave) {
-        WalkEntry ens[kWalkSteps];
+    for (uint32_t base = 0; base < total; base += kFillSteps * kWave) {
+        WalkEntry ens[kFillSteps];
         walk_entries_flagged(rw, base, total, a.col, fflag, ens);
 #pragma unroll
-        for (int u = 0; u < kWalkSteps; ++u) {
+        for (int u = 0; u < kFillSteps; ++u) {
             const WalkEntry &en = ens[u];
             const uint64_t F = __ballot(en.valid && en.fwd);
             if (en.valid && en.fwd) {
