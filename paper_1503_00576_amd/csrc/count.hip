@@ -806,20 +806,37 @@ __device__ __forceinline__ uint32_t run_panel_pv(uint32_t eb, uint32_t e1,
     return hits_total;
 }
 
+// first position in hcol[b, e) (ascending) whose entry is >= x
+__device__ __forceinline__ uint32_t hcol_lower_bound(const uint16_t *__restrict__ hcol,
+                                                     uint32_t b, uint32_t e, uint32_t x) {
+    while (b < e) {
+        const uint32_t mid = b + ((e - b) >> 1);
+        if (hcol[mid] < x) b = mid + 1;
+        else e = mid;
+    }
+    return b;
+}
+
 // The same for panels in the high region: every suffix entry is read from hcol as a 16-bit
 // offset from hbase, in unmasked pieces of kPieceHigh entries (entries of u's row up to its
 // first panel vertex only match panel vertices below it, none of which is in its mask, and
-// padding zeros, rank hbase, lie below the window), with the owners found as in the totals
-// streamer.  The window's table covers offsets [c, c + wn) from hbase.
+// padding zeros, rank hbase, lie below the window; entries outside the window clamp onto the
+// zero word), with the owners found as in the totals streamer.  The window's table covers
+// offsets [c, c + wn) from hbase; with cut_lo / cut_hi the segment's entries below / above
+// the window are found by a binary search and not streamed.
 __device__ __forceinline__ uint32_t run_panel_pv_high(const SegRec &r,
                                                       const uint16_t *__restrict__ hcol,
                                                       const uint32_t *m, uint32_t *cnt3,
-                                                      uint32_t c, uint32_t wn, WaveScratch &ws,
+                                                      uint32_t c, uint32_t wn, bool cut_lo,
+                                                      bool cut_hi, WaveScratch &ws,
                                                       MidCounters &mc, uint32_t &pieces,
                                                       unsigned long long *mid,
                                                       unsigned long long *__restrict__ tpv) {
     const uint32_t lane = lane_id();
-    const uint32_t hl = r.en - r.b, h = r.h;
+    uint32_t h0 = r.h, h1 = r.h + (r.en - r.b);
+    if (h1 > h0 && cut_lo) h0 = hcol_lower_bound(hcol, h0, h1, c);
+    if (h1 > h0 && cut_hi) h1 = hcol_lower_bound(hcol, h0, h1, c + wn);
+    const uint32_t hl = h1 > h0 ? h1 - h0 : 0u, h = h0;
     const uint32_t ph = hl ? (h + hl - (h & ~7u) + kPieceHigh - 1) / kPieceHigh : 0u;
     ws.off[lane] = 0u;  // the rounds' marker table
     ws.aux[lane] = h;
@@ -939,8 +956,8 @@ __global__ __launch_bounds__(kThreads) void k_count_panel_pv(
                 for (uint32_t eb = it.e0 + w * kWave; eb < it.e1; eb += kWaves * kWave) {
                     const SegRec r = eb + lane < it.e1 ? psegs.rec(eb + lane)
                                                        : SegRec{0u, 0u, 0u, 0u, 0u};
-                    cnt += run_panel_pv_high(r, hcol, m, cnt3, lo - hbase, wn, ws, mc, pieces,
-                                             s_mid, tpv);
+                    cnt += run_panel_pv_high(r, hcol, m, cnt3, lo - hbase, wn, lo > P,
+                                             lo + wn < n1 - 1, ws, mc, pieces, s_mid, tpv);
                 }
             } else {
                 for (uint32_t eb = it.e0 + w * kWave; eb < it.e1; eb += kWaves * kWave)
