@@ -115,7 +115,13 @@ const char *tc_strerror(int status);
  *                     region is widened to take in the whole panel region.  1..65536, default
  *                     65536; 0: no 16-bit region (panels and totals read 32-bit ranks only).
  *                     The region is also dropped when its padded copy of the node array would
- *                     need 2^32 or more entries. */
+ *                     need 2^32 or more entries.
+ *   row_sort          1 (default): the oriented edges are sorted by source only and every
+ *                     adjacency list is then sorted in place (per thread, per wave or per
+ *                     workgroup by its length), with the duplicate check; graphs of 2^29 or
+ *                     more oriented edges, whose lists may exceed the workgroup form's 32768
+ *                     entries, take the full sort anyway.  0: the oriented edges are sorted by
+ *                     (source, target). */
 typedef struct tc_options {
     uint32_t size; /* sizeof(tc_options); set by tc_options_init */
     uint32_t panel_ranks;
@@ -130,6 +136,7 @@ typedef struct tc_options {
     uint32_t degree_partition;
     uint32_t sort_onesweep;
     uint32_t high_ranks;
+    uint32_t row_sort;
 } tc_options;
 
 /* Fills *opts with the defaults.  Returns TC_E_ARG for a NULL pointer. */

@@ -24,7 +24,7 @@ class TcOptions(ctypes.Structure):
     _fields_ = [(name, ctypes.c_uint32) for name in (
         "size", "panel_ranks", "hub_ranks", "row_blocks", "wave_item_edges", "block_item_edges",
         "wave_bitmap_span", "wave_list_max", "block_bitmap_span", "block_list_max",
-        "degree_partition", "sort_onesweep", "high_ranks")]
+        "degree_partition", "sort_onesweep", "high_ranks", "row_sort")]
 
 
 class TcLayout(ctypes.Structure):

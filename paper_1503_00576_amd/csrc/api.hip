@@ -27,7 +27,11 @@ __global__ void k_orient_cells(const int2 *, uint64_t, uint32_t, const uint32_t 
                                uint64_t *, const int32_t *);
 __global__ void k_both_check(const uint32_t *, uint32_t, int32_t *);
 __global__ void k_csr(const uint64_t *, uint32_t, uint32_t, int, uint32_t, uint32_t *,
-                      uint32_t *, uint32_t *, uint32_t *, uint32_t *, int32_t *);
+                      uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t *, int32_t *);
+__global__ void k_row_sort(uint32_t *, const uint32_t *, const uint32_t *, uint32_t, uint32_t,
+                           uint32_t, uint32_t *, uint32_t *, uint32_t *, int32_t *);
+__global__ void k_row_sort_long(uint32_t *, const uint32_t *, const uint32_t *,
+                                const uint32_t *, uint32_t, uint32_t *, int32_t *);
 __global__ void k_hlen(const uint32_t *, const uint32_t *, uint32_t, uint32_t, uint32_t *);
 __global__ void k_rowlen(const uint32_t *, const uint32_t *, uint32_t, uint32_t *);
 __global__ void k_vrange(const uint32_t *, const uint32_t *, uint32_t, uint32_t, uint64_t *);
@@ -72,7 +76,8 @@ int device_cu_count() {
 struct Layout {
     size_t ctl, part_hist, part_offs, part_scan, deg, perm, rank, keys_a, keys_b, sort_scratch,
         rs, re, rowlen, row_ptr, col, hcol, hrow, hstart, src, vrange, prange, eu, lrs, lre, cnt,
-        cptr, cbeg, items[4], off[4], item_v[4], scan_scratch, tpv, hub_a, hub_at, total_bytes;
+        cptr, cbeg, items[4], off[4], item_v[4], scan_scratch, tpv, hub_a, hub_at, rchunk,
+        long_rows, total_bytes;
     uint32_t part_tiles;  // 0: degrees by atomics (inputs too large for the partition)
     int part_shift;
     int cell_shift;       // >= 0: edges also partitioned into cells for the orientation
@@ -91,7 +96,7 @@ struct Layout {
 // two item queues, the fingerprint of the prepared layout, status of the current count
 enum {
     kCtlStatus = 0, kCtlBoth = 1, kCtlQueueA = 2, kCtlQueueB = 3, kCtlFinger = 4, kCtlRun = 5,
-    kCtlQueueC = 6, kCtlWords = 64
+    kCtlQueueC = 6, kCtlLongRows = 7, kCtlWords = 64
 };
 // start of a preprocessing: clear the control words and record the layout's fingerprint
 __global__ void k_ctl_init(uint32_t *__restrict__ ctl, uint32_t finger) {
@@ -117,6 +122,9 @@ constexpr uint32_t kPartTileEdges = 4096;  // edges per tile of the degree parti
 // cells)
 constexpr uint32_t kOrientGrid = 512;
 constexpr uint32_t kCscPerThread = 4;  // in-edge keys per thread (prep.hip, kCscEdges)
+// the per-row sort (prep.hip) is used when every row of a simple graph fits its long-row
+// kernel: m_fwd < 2^29, so that d+ < sqrt(2 m_fwd) <= 2^15
+constexpr uint32_t kRowSortMaxEdges = 1u << 29;
 constexpr uint32_t kMaxRowBlocks = 8;
 constexpr uint32_t kMaxHubRanks = 1u << 16;  // two matrices of at most 4 GiB each
 // the top ranks, whose entries of the node array are also stored as 16-bit offsets: on R-MAT
@@ -139,6 +147,7 @@ static void default_options(tc_options &o) {
     o.degree_partition = 1;
     o.sort_onesweep = 0;
     o.high_ranks = kHighRanks;
+    o.row_sort = 1;
 }
 
 // the caller's options (NULL: defaults), checked against the limits the kernels are built for
@@ -154,7 +163,7 @@ static bool resolve_options(const tc_options *in, tc_options &o) {
            o.wave_list_max <= count_wave_list(false) &&
            o.block_bitmap_span <= count_block_span() &&
            o.block_list_max <= count_block_list(false) && o.degree_partition <= 1 &&
-           o.sort_onesweep <= 1 && o.high_ranks <= kHighRanks;
+           o.sort_onesweep <= 1 && o.high_ranks <= kHighRanks && o.row_sort <= 1;
 }
 
 // FNV-1a over 32-bit words
@@ -264,6 +273,9 @@ static bool make_layout(int64_t n, int64_t m, uint32_t flags, const tc_options *
     L.hrow = take((size_t)n * 4);
     L.hstart = take(n1 * 4);
     L.src = take((size_t)L.mf * 4);
+    // rows sorted in place after a sort by source only: chunk table and the long rows' list
+    L.rchunk = take(((size_t)L.mf / row_sort_chunk() + 2) * 4);
+    L.long_rows = take(((size_t)L.mf / (row_sort_wave() + 1) + 2) * 4);
     L.vrange = take((size_t)n * 8);
     L.prange = take((size_t)L.panels * 8);
     L.eu = take((size_t)L.mf * 16);  // also the cell-ordered edges (8 bytes per entry)
@@ -359,6 +371,7 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
     hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, s, ctl, L.finger);
     TC_LAUNCH_CHECK();
     const bool onesweep = L.opt.sort_onesweep != 0;
+    const bool row_sort = L.opt.row_sort && L.mf < kRowSortMaxEdges;
     TC_HIP(fill_u32(deg, 0u, n, s));
     if (m > 0 && L.part_tiles) {
         const uint32_t tiles = L.part_tiles;
@@ -407,7 +420,9 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
             hipLaunchKernelGGL(k_both_check, dim3(1), dim3(64), 0, s, ctl + kCtlBoth, mf, status);
             TC_LAUNCH_CHECK();
         }
-        TC_HIP(sort_u64(ka, kb, mf, 0, 2 * b, sort_scr, status, s, &sorted, onesweep));
+        // by source only when the rows can be sorted in place afterwards (k_row_sort)
+        TC_HIP(sort_u64(ka, kb, mf, row_sort ? b : 0, 2 * b, sort_scr, status, s, &sorted,
+                        onesweep));
     }
     if (mf == 0) {
         TC_HIP(fill_u32(row_ptr, 0u, n1, s));
@@ -421,13 +436,24 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
     uint32_t *src = at<uint32_t>(ws, L.src);
     uint32_t *hrow = at<uint32_t>(ws, L.hrow);
     TC_HIP(fill_u32(hrow, ~0u, n, s));
+    uint32_t *rchunk = at<uint32_t>(ws, L.rchunk);
     hipLaunchKernelGGL(k_csr, dim3(grid_for(mf, 256 * 4)), dim3(256), 0, s, sorted, mf, n, b,
-                       L.hbase, col, src, rs, re, hrow,
+                       L.hbase, col, src, rs, re, hrow, row_sort ? rchunk : nullptr,
                        status);  // 4 keys per thread (prep.hip, kCsrKeys)
     TC_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_rowlen, dim3(grid_for(n1, 256)), dim3(256), 0, s, rs, re, n, rowlen);
     TC_LAUNCH_CHECK();
     TC_HIP(scan_exclusive_u32(rowlen, row_ptr, n1, scan_scr, s));
+    if (row_sort) {  // every row sorted in place, with the duplicate check and hrow
+        const uint32_t chunks = ceil_div(mf, row_sort_chunk());
+        uint32_t *long_rows = at<uint32_t>(ws, L.long_rows);
+        hipLaunchKernelGGL(k_row_sort, dim3(chunks), dim3(256), 0, s, col, row_ptr, rchunk,
+                           chunks, n, L.hbase, hrow, long_rows, ctl + kCtlLongRows, status);
+        TC_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_row_sort_long, dim3(device_cu_count()), dim3(1024), 0, s, col,
+                           row_ptr, long_rows, ctl + kCtlLongRows, L.hbase, hrow, status);
+        TC_LAUNCH_CHECK();
+    }
     // every row's part of hcol (row lengths are no longer needed: their array takes the parts'
     // sizes); hcol starts as zeros, the parts' padding
     uint32_t *hstart = at<uint32_t>(ws, L.hstart);

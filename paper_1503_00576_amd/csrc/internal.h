@@ -150,6 +150,10 @@ uint32_t count_item_edges_block();  // default in-edges per workgroup item
 // bytes of padding `col` needs after its last element: a lane's aligned piece reads may run
 // up to one piece past the end of a list
 uint32_t count_col_pad_bytes();
+// the per-row sort after a sort of the edge keys by source only: CSR positions per chunk
+// (k_row_sort's workgroups), and the longest row one wave sorts (longer rows are listed)
+uint32_t row_sort_chunk();
+uint32_t row_sort_wave();
 // zeros after every row's part of hcol beyond its rounding to 8 entries (a piece of the
 // unmasked probes read from an 8-aligned position inside the part never leaves it)
 uint32_t count_hcol_pad();

@@ -336,15 +336,20 @@ __global__ void k_both_check(const uint32_t *__restrict__ counter, uint32_t expe
 }
 
 constexpr uint32_t kCsrKeys = 4;
+constexpr uint32_t kRowChunk = 4096;  // CSR positions per workgroup of k_row_sort
 
 // Unzip the sorted keys into the neighbour array (Section 3.2, step 7) and mark where every
 // non-empty row starts and ends; row lengths and their prefix sum give the node array.
 // hrow[u] receives the position of the first entry >= hbase of row u (left untouched, all
-// ones from the caller's fill, when the row has none).
+// ones from the caller's fill, when the row has none).  With keys sorted by their source only
+// (rchunk non-null) the rows are not yet ordered: the duplicate check and hrow are left to
+// k_row_sort, and rchunk[c] receives the first row starting at or after position
+// c * kRowChunk (the chunks of k_row_sort).
 __global__ void k_csr(const uint64_t *__restrict__ keys, uint32_t mf, uint32_t n, int b,
                       uint32_t hbase, uint32_t *__restrict__ col, uint32_t *__restrict__ src,
                       uint32_t *__restrict__ rs, uint32_t *__restrict__ re,
-                      uint32_t *__restrict__ hrow, int32_t *__restrict__ status) {
+                      uint32_t *__restrict__ hrow, uint32_t *__restrict__ rchunk,
+                      int32_t *__restrict__ status) {
     if (*status) return;
     // kCsrKeys keys a block apart per thread, all loaded before any is used
     const uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x * kCsrKeys + threadIdx.x;
@@ -367,12 +372,227 @@ __global__ void k_csr(const uint64_t *__restrict__ keys, uint32_t mf, uint32_t n
         if (s >= n) continue;  // only for invalid input, reported elsewhere
         const bool row_start = i == 0 || (uint32_t)(kp[t] >> b) != s;
         if (row_start) rs[s] = (uint32_t)i;
-        if (c >= hbase && (row_start || (uint32_t)(kp[t] & ((1ull << b) - 1)) < hbase))
-            hrow[s] = (uint32_t)i;
-        if (i > 0 && kp[t] == k[t]) set_status(status, TC_E_DUP_EDGE);
+        if (rchunk) {
+            if ((i & (kRowChunk - 1)) == 0) rchunk[i / kRowChunk] = row_start ? s : s + 1;
+        } else {
+            if (c >= hbase && (row_start || (uint32_t)(kp[t] & ((1ull << b) - 1)) < hbase))
+                hrow[s] = (uint32_t)i;
+            if (i > 0 && kp[t] == k[t]) set_status(status, TC_E_DUP_EDGE);
+        }
         if (i == mf - 1 || (uint32_t)(kn[t] >> b) != s) re[s] = (uint32_t)(i + 1);
     }
 }
+
+// ---------------------------------------------------------------- rows sorted in place
+//
+// With the edge keys sorted by source only (three radix passes instead of six), every row of
+// col holds its targets in input order; these kernels sort each row ascending, then check it
+// for duplicates and record hrow (as k_csr does for fully sorted keys).  A workgroup takes
+// the rows starting in one chunk of kRowChunk positions: rows of at most kRowSmall entries
+// one per lane (a sorting network in registers), rows of at most kRowWave entries one per
+// wave (a bitonic network over the wave's registers, kRowWave / 64 entries per lane, the
+// strides of 64 and more in registers and the smaller ones across lanes), longer rows are
+// listed for k_row_sort_long (a bitonic network in a workgroup's LDS).  Rows of a simple
+// graph hold fewer than sqrt(2 m) entries (Section 2.2), below kRowLong for the graphs this
+// path is used on; a longer row means repeated edges and is reported as TC_E_DUP_EDGE.
+constexpr uint32_t kRowSmall = 16;
+constexpr uint32_t kRowWave = 1024;
+constexpr uint32_t kRowWaveLong = 2048;  // listed rows up to this length: one wave each
+constexpr uint32_t kRowLong = 32768;
+
+__device__ __forceinline__ void cswap(uint32_t &a, uint32_t &b) {
+    const uint32_t lo = min(a, b), hi = max(a, b);
+    a = lo;
+    b = hi;
+}
+
+// duplicates and the first entry >= hbase of a sorted row, from a lane's view of consecutive
+// positions: entries v[0..k) at positions p .. p + k - 1 of the row, the entry before them
+// (prev, valid when p > 0)
+__device__ __forceinline__ void row_checks(const uint32_t *v, uint32_t k, uint32_t p,
+                                           uint32_t prev, uint32_t rb, uint32_t hbase,
+                                           uint32_t *__restrict__ hrow, uint32_t r,
+                                           int32_t *__restrict__ status) {
+    for (uint32_t j = 0; j < k; ++j) {
+        const uint32_t before = j ? v[j - 1] : prev;
+        const bool has_before = j > 0 || p > 0;
+        if (has_before && before == v[j]) set_status(status, TC_E_DUP_EDGE);
+        if (v[j] >= hbase && (!has_before || before < hbase)) hrow[r] = rb + p + j;
+    }
+}
+
+// a row of at most kRowSmall entries, sorted by the calling lane alone
+__device__ __forceinline__ void sort_row_lane(uint32_t *__restrict__ col, uint32_t rb,
+                                              uint32_t len, uint32_t hbase,
+                                              uint32_t *__restrict__ hrow, uint32_t r,
+                                              int32_t *__restrict__ status) {
+    uint32_t v[kRowSmall];
+#pragma unroll
+    for (uint32_t j = 0; j < kRowSmall; ++j) v[j] = j < len ? col[rb + j] : ~0u;
+    // bitonic network on 16 entries, ascending
+#pragma unroll
+    for (uint32_t k = 2; k <= kRowSmall; k <<= 1)
+#pragma unroll
+        for (uint32_t st = k >> 1; st; st >>= 1)
+#pragma unroll
+            for (uint32_t i = 0; i < kRowSmall; ++i) {
+                const uint32_t q = i ^ st;
+                if (q > i) {
+                    if ((i & k) == 0) cswap(v[i], v[q]);
+                    else cswap(v[q], v[i]);
+                }
+            }
+#pragma unroll
+    for (uint32_t j = 0; j < kRowSmall; ++j)
+        if (j < len) col[rb + j] = v[j];
+    row_checks(v, len, 0, 0, rb, hbase, hrow, r, status);
+}
+
+// a row of kRowSmall < len <= kRowWave entries, sorted by the calling wave: a bitonic network
+// on P = 64 E entries (P the smallest such power of two >= len), lane l holding positions
+// l E .. l E + E - 1
+template <uint32_t E>
+__device__ __forceinline__ void sort_row_wave(uint32_t *__restrict__ col, uint32_t rb,
+                                              uint32_t len, uint32_t hbase,
+                                              uint32_t *__restrict__ hrow, uint32_t r,
+                                              int32_t *__restrict__ status) {
+    constexpr uint32_t P = 64 * E;
+    const uint32_t lane = lane_id();
+    uint32_t v[E];
+#pragma unroll
+    for (uint32_t j = 0; j < E; ++j) {
+        const uint32_t i = lane * E + j;
+        v[j] = i < len ? col[rb + i] : ~0u;
+    }
+#pragma unroll
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+#pragma unroll
+        for (uint32_t st = k >> 1; st; st >>= 1) {
+            if (st >= E) {  // across lanes: partner lane ^ (st / E), same slot
+                const uint32_t ls = st / E;
+#pragma unroll
+                for (uint32_t j = 0; j < E; ++j) {
+                    const uint32_t i = lane * E + j;
+                    const uint32_t y = (uint32_t)__shfl_xor((int)v[j], (int)ls, kWave);
+                    const bool lower = (i & st) == 0, asc = (i & k) == 0;
+                    v[j] = (lower == asc) ? min(v[j], y) : max(v[j], y);
+                }
+            } else {  // inside the lane
+#pragma unroll
+                for (uint32_t j = 0; j < E; ++j) {
+                    const uint32_t q = j ^ st;
+                    if (q > j) {
+                        const uint32_t i = lane * E + j;
+                        if ((i & k) == 0) cswap(v[j], v[q]);
+                        else cswap(v[q], v[j]);
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < E; ++j) {
+        const uint32_t i = lane * E + j;
+        if (i < len) col[rb + i] = v[j];
+    }
+    const uint32_t prev = (uint32_t)__shfl_up((int)v[E - 1], 1, kWave);
+    const uint32_t p = lane * E;
+    const uint32_t k = p < len ? min(E, len - p) : 0u;
+    row_checks(v, k, p, prev, rb, hbase, hrow, r, status);
+}
+
+// Rows starting in chunk c (rows rchunk[c] .. rchunk[c + 1] - 1): short rows per lane, then
+// medium rows per wave; long rows go to the list for k_row_sort_long.
+__global__ __launch_bounds__(256) void k_row_sort(uint32_t *__restrict__ col,
+                                                  const uint32_t *__restrict__ row_ptr,
+                                                  const uint32_t *__restrict__ rchunk,
+                                                  uint32_t chunks, uint32_t n, uint32_t hbase,
+                                                  uint32_t *__restrict__ hrow,
+                                                  uint32_t *__restrict__ long_rows,
+                                                  uint32_t *__restrict__ n_long,
+                                                  int32_t *__restrict__ status) {
+    if (*status) return;
+    const uint32_t c = blockIdx.x;
+    const uint32_t r0 = rchunk[c], r1 = c + 1 < chunks ? rchunk[c + 1] : n;
+    const uint32_t t = threadIdx.x, w = t / kWave;
+    for (uint32_t r = r0 + t; r < r1; r += blockDim.x) {
+        const uint32_t rb = row_ptr[r], len = row_ptr[r + 1] - rb;
+        if (len == 0 || len > kRowSmall) continue;
+        sort_row_lane(col, rb, len, hbase, hrow, r, status);
+    }
+    for (uint32_t r = r0 + w; r < r1; r += blockDim.x / kWave) {
+        const uint32_t rb = row_ptr[r], len = row_ptr[r + 1] - rb;
+        if (len <= kRowSmall) continue;
+        if (len <= 64) sort_row_wave<1>(col, rb, len, hbase, hrow, r, status);
+        else if (len <= 128) sort_row_wave<2>(col, rb, len, hbase, hrow, r, status);
+        else if (len <= 256) sort_row_wave<4>(col, rb, len, hbase, hrow, r, status);
+        else if (len <= 512) sort_row_wave<8>(col, rb, len, hbase, hrow, r, status);
+        else if (len <= kRowWave) sort_row_wave<16>(col, rb, len, hbase, hrow, r, status);
+        else if (lane_id() == 0) long_rows[atomicAdd(n_long, 1u)] = r;
+    }
+}
+
+// The listed long rows: those of at most kRowWaveLong entries one per wave (the register
+// network with 32 entries per lane, kept out of k_row_sort so that its other rows run at a
+// higher occupancy), longer ones one per workgroup of 1024 threads in a bitonic network in LDS
+// on the row padded to a power of two (at most kRowLong entries).
+__global__ __launch_bounds__(1024) void k_row_sort_long(uint32_t *__restrict__ col,
+                                                        const uint32_t *__restrict__ row_ptr,
+                                                        const uint32_t *__restrict__ long_rows,
+                                                        const uint32_t *__restrict__ n_long,
+                                                        uint32_t hbase,
+                                                        uint32_t *__restrict__ hrow,
+                                                        int32_t *__restrict__ status) {
+    if (*status) return;
+    __shared__ uint32_t a[kRowLong];
+    const uint32_t t = threadIdx.x, nl = *n_long;
+    const uint32_t waves = blockDim.x / kWave;
+    for (uint32_t q = blockIdx.x * waves + t / kWave; q < nl; q += gridDim.x * waves) {
+        const uint32_t r = long_rows[q];
+        const uint32_t rb = row_ptr[r], len = row_ptr[r + 1] - rb;
+        if (len <= kRowWaveLong) sort_row_wave<32>(col, rb, len, hbase, hrow, r, status);
+    }
+    for (uint32_t q = blockIdx.x; q < nl; q += gridDim.x) {
+        const uint32_t r = long_rows[q];
+        const uint32_t rb = row_ptr[r], len = row_ptr[r + 1] - rb;
+        if (len <= kRowWaveLong) continue;  // sorted above
+        if (len > kRowLong) {  // only with repeated edges
+            if (t == 0) set_status(status, TC_E_DUP_EDGE);
+            continue;
+        }
+        uint32_t P = kRowWave;
+        while (P < len) P <<= 1;
+        __syncthreads();
+        for (uint32_t i = t; i < P; i += blockDim.x) a[i] = i < len ? col[rb + i] : ~0u;
+        __syncthreads();
+        for (uint32_t k = 2; k <= P; k <<= 1)
+            for (uint32_t st = k >> 1; st; st >>= 1) {
+                for (uint32_t i = t; i < P; i += blockDim.x) {
+                    const uint32_t q2 = i ^ st;
+                    if (q2 > i) {
+                        const uint32_t x = a[i], y = a[q2];
+                        const bool asc = (i & k) == 0;
+                        if ((x > y) == asc) {
+                            a[i] = y;
+                            a[q2] = x;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        for (uint32_t i = t; i < len; i += blockDim.x) {
+            const uint32_t x = a[i];
+            col[rb + i] = x;
+            const bool has_before = i > 0;
+            const uint32_t before = has_before ? a[i - 1] : 0u;
+            if (has_before && before == x) set_status(status, TC_E_DUP_EDGE);
+            if (x >= hbase && (!has_before || before < hbase)) hrow[r] = rb + i;
+        }
+    }
+}
+
+uint32_t row_sort_chunk() { return kRowChunk; }
+uint32_t row_sort_wave() { return kRowWave; }
 
 // row length = end - start (both zero for empty rows); entry n is 0 so that the exclusive
 // scan over n + 1 entries ends with row_ptr[n] = m_fwd

@@ -155,7 +155,7 @@ def test_options(lib):
     assert d == {"panel_ranks": 32736, "hub_ranks": 0, "row_blocks": 1, "wave_item_edges": 512,
                  "block_item_edges": 65536, "wave_bitmap_span": 65504, "wave_list_max": 2048,
                  "block_bitmap_span": 1048544, "block_list_max": 32768, "degree_partition": 1,
-                 "sort_onesweep": 0, "high_ranks": 65536}
+                 "sort_onesweep": 0, "high_ranks": 65536, "row_sort": 1}
     assert lib.tc_options_init(None) == api.E_ARG
     base = api.workspace_size(1000, 9000)
     assert api.workspace_size(1000, 9000, options=d) == base
@@ -165,7 +165,8 @@ def test_options(lib):
            ("wave_item_edges", 15), ("wave_item_edges", 65537), ("block_item_edges", 15),
            ("block_item_edges", (1 << 20) + 1), ("wave_bitmap_span", 65505),
            ("wave_list_max", 2049), ("block_bitmap_span", 1048545), ("block_list_max", 32769),
-           ("degree_partition", 2), ("sort_onesweep", 2), ("high_ranks", 65537)]
+           ("degree_partition", 2), ("sort_onesweep", 2), ("high_ranks", 65537),
+           ("row_sort", 2)]
     for k, v in bad:
         assert lib.tc_workspace_size(1000, 9000, 0, api._opts({k: v})) == 0, k
         assert lib.tc_count(fake, 5, 3, 0, api._opts({k: v}), ws, 1 << 40, None, out,
@@ -181,7 +182,7 @@ def test_options(lib):
                  ("wave_item_edges", 16), ("block_item_edges", 1 << 20),
                  ("wave_bitmap_span", 0), ("wave_list_max", 0), ("block_bitmap_span", 0),
                  ("block_list_max", 0), ("degree_partition", 0), ("sort_onesweep", 1),
-                 ("high_ranks", 0)]:
+                 ("high_ranks", 0), ("row_sort", 0)]:
         assert api.workspace_size(1000, 9000, options={k: v}) > 0, k
     # the layout grows with hubs (two byte matrices), row blocks (lists per block) and smaller
     # items (more item slots)

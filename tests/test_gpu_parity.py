@@ -198,6 +198,51 @@ def test_single_sweep_sort():
         check_vs_oracle(e.numpy(), n, options=opt)
 
 
+def hub_fan(L, seed, dup=False):
+    """L hubs (ids 2 .. L + 1) forming a clique, and vertices 0 and 1 joined to every hub:
+    0 and 1 have degree L and the hubs L + 1, so in the order of Section 2.2 the oriented list
+    of 0 (and of 1) holds all L hubs and hub i's list the hubs above it, lengths 0 .. L - 1.
+    Edges in random order and orientation; dup repeats the edge (0, 2) (reversed), which puts
+    a repeated entry in the list of 0, then of L + 1 entries."""
+    hi, hj = np.triu_indices(L, 1)
+    e = [np.stack([hi + 2, hj + 2], 1), np.stack([np.zeros(L, np.int64), np.arange(2, L + 2)], 1),
+         np.stack([np.ones(L, np.int64), np.arange(2, L + 2)], 1)]
+    if dup:
+        e.append(np.array([[2, 0]]))
+    e = np.concatenate(e)
+    rng = np.random.default_rng(seed)
+    flip = rng.random(len(e)) < 0.5
+    e[flip] = e[flip][:, ::-1]
+    return np.ascontiguousarray(e[rng.permutation(len(e))].astype(np.int32)), L + 2
+
+
+@pytest.mark.parametrize("row_sort", [1, 0])
+def test_row_sort_lengths(row_sort):
+    """Oriented lists of every length class of the in-place row sort (per lane up to 16
+    entries, per wave up to 1024 and up to 2048, per workgroup above), and the full sort of
+    the oriented edges (row_sort 0), on hub fans checked against closed forms: C(L, 3) +
+    2 C(L, 2) triangles, each hub in C(L - 1, 2) + 2 (L - 1), vertices 0 and 1 in C(L, 2).  A
+    repeated edge in a list of each class is reported, and so is a list of more than 32768
+    entries (possible only with repeated edges below 2^29 oriented edges)."""
+    opt = {"row_sort": row_sort}
+    for L in (10, 40, 100, 700, 1500, 2600):
+        e, n = hub_fan(L, seed=L)
+        tot, pv = gpu_counts(e, n, options=opt)
+        want = np.full(n, math.comb(L - 1, 2) + 2 * (L - 1), dtype=np.uint64)
+        want[:2] = math.comb(L, 2)
+        assert tot == math.comb(L, 3) + 2 * math.comb(L, 2), L
+        assert np.array_equal(pv, want), L
+        e, n = hub_fan(L, seed=L + 1, dup=True)
+        for pv_call in (api.count, api.count_per_vertex):
+            with pytest.raises(api.TCError) as ei:
+                pv_call(torch.as_tensor(e, device=DEV), n, options=opt)
+            assert ei.value.name == "dup_edge", L
+    e = torch.tensor([[0, 1]] * 33000, dtype=torch.int32, device=DEV)
+    with pytest.raises(api.TCError) as ei:
+        api.count(e, 2, options=opt)
+    assert ei.value.name == "dup_edge"
+
+
 @pytest.mark.parametrize("span", [0, 40, 600])
 def test_wave_item_forms(span):
     """Wave items in both forms (bitmap below the span limit, sorted list above it) and
