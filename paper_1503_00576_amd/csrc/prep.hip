@@ -448,6 +448,31 @@ __device__ __forceinline__ void sort_row_lane(uint32_t *__restrict__ col, uint32
     row_checks(v, len, 0, 0, rb, hbase, hrow, r, status);
 }
 
+// x of lane (lane ^ ls) for ls a power of two below 64 (a constant once the networks are
+// unrolled): DPP moves inside rows of 16 lanes (quad permutations; a half-row or row mirror
+// followed by a second mirror gives xor 4 and xor 8), a swizzle across the 32-lane halves'
+// rows for 16, a permute through the LDS crossbar for 32.
+__device__ __forceinline__ uint32_t lane_xor(uint32_t x, uint32_t ls) {
+    switch (ls) {
+    case 1:  // quad_perm [1, 0, 3, 2]
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false);
+    case 2:  // quad_perm [2, 3, 0, 1]
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false);
+    case 4: {  // row_half_mirror (lane ^ 7), then quad_perm [3, 2, 1, 0] (lane ^ 3)
+        const int y = __builtin_amdgcn_update_dpp(0, (int)x, 0x141, 0xF, 0xF, false);
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, y, 0x1B, 0xF, 0xF, false);
+    }
+    case 8: {  // row_mirror (lane ^ 15), then row_half_mirror (lane ^ 7)
+        const int y = __builtin_amdgcn_update_dpp(0, (int)x, 0x140, 0xF, 0xF, false);
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, y, 0x141, 0xF, 0xF, false);
+    }
+    case 16:  // swizzle, bit mode: and 0x1f, or 0, xor 0x10
+        return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x401F);
+    default:
+        return (uint32_t)__shfl_xor((int)x, (int)ls, kWave);
+    }
+}
+
 // a row of kRowSmall < len <= kRowWave entries, sorted by the calling wave: a bitonic network
 // on P = 64 E entries (P the smallest such power of two >= len), lane l holding positions
 // l E .. l E + E - 1
@@ -473,7 +498,9 @@ __device__ __forceinline__ void sort_row_wave(uint32_t *__restrict__ col, uint32
 #pragma unroll
                 for (uint32_t j = 0; j < E; ++j) {
                     const uint32_t i = lane * E + j;
-                    const uint32_t y = (uint32_t)__shfl_xor((int)v[j], (int)ls, kWave);
+                    // (32 entries per lane: the permutes through the crossbar measured faster)
+                    const uint32_t y = E <= 16 ? lane_xor(v[j], ls)
+                                               : (uint32_t)__shfl_xor((int)v[j], (int)ls, kWave);
                     const bool lower = (i & st) == 0, asc = (i & k) == 0;
                     v[j] = (lower == asc) ? min(v[j], y) : max(v[j], y);
                 }
