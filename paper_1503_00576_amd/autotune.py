@@ -34,7 +34,7 @@ LIGHT_MAX = (64, 128, 256)
 PANEL_RANKS = (0, 8192, 16384, 32736)
 WAVE_ITEM_EDGES = (256, 512, 1024)
 BLOCK_ITEM_EDGES = (4096, 16384, 65536)
-TIE = 0.003  # relative margin within which the library defaults are kept
+TIE = 0.005  # relative margin within which the library defaults are kept
 
 
 def _device_key(device) -> str:
