@@ -308,10 +308,15 @@ __global__ void k_orient_cells(const int2 *__restrict__ cells, uint64_t m, uint3
     const uint32_t x = blockIdx.x % kXcds, j = blockIdx.x / kXcds, per = gridDim.x / kXcds;
     const uint64_t lo = m * x / kXcds, hi = m * (x + 1) / kXcds;
     const uint64_t step = (uint64_t)per * blockDim.x;
+    // the edge stream is read and the keys written with non-temporal hints, so that they do
+    // not push the two rank stretches out of the XCD's L2
+    const uint64_t *cw = reinterpret_cast<const uint64_t *>(cells);
     for (uint64_t i0 = lo + (uint64_t)j * blockDim.x + threadIdx.x; i0 < hi; i0 += 2 * step) {
         const uint64_t i1 = i0 + step;
-        const int2 e0 = cells[i0];
-        const int2 e1 = i1 < hi ? cells[i1] : make_int2(0, 0);
+        const uint64_t w0 = __builtin_nontemporal_load(cw + i0);
+        const uint64_t w1 = i1 < hi ? __builtin_nontemporal_load(cw + i1) : 0ull;
+        const int2 e0 = make_int2((int)(uint32_t)w0, (int)(uint32_t)(w0 >> 32));
+        const int2 e1 = make_int2((int)(uint32_t)w1, (int)(uint32_t)(w1 >> 32));
         const bool ok0 = (uint32_t)e0.x < n && (uint32_t)e0.y < n;
         const bool ok1 = i1 < hi && (uint32_t)e1.x < n && (uint32_t)e1.y < n;
         uint32_t r0u = 0, r0v = 0, r1u = 0, r1v = 0;
@@ -323,8 +328,8 @@ __global__ void k_orient_cells(const int2 *__restrict__ cells, uint64_t m, uint3
             r1u = rank[e1.x];
             r1v = rank[e1.y];
         }
-        if (ok0) keys[i0] = ((uint64_t)min(r0u, r0v) << b) | max(r0u, r0v);
-        if (ok1) keys[i1] = ((uint64_t)min(r1u, r1v) << b) | max(r1u, r1v);
+        if (ok0) __builtin_nontemporal_store(((uint64_t)min(r0u, r0v) << b) | max(r0u, r0v), keys + i0);
+        if (ok1) __builtin_nontemporal_store(((uint64_t)min(r1u, r1v) << b) | max(r1u, r1v), keys + i1);
     }
 }
 

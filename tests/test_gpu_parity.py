@@ -365,10 +365,22 @@ def test_prepared_recount():
 
 # ------------------------------------------------------------------ intermediate stages
 
-def test_preprocess_stages():
-    for e, n in [synth.er_1000(), synth.rmat_graph(13, 16, seed=5), (synth.watts_strogatz(5000, 6, 0.1, 2), 5000)]:
+@pytest.mark.parametrize("row_sort", [1, 0])
+def test_preprocess_stages(row_sort):
+    """Degrees, the order, and the oriented CSR against the oracle, through both sorts of the
+    oriented edges (by source, then each row in place; by (source, target)), which must give
+    the same arrays, the per-entry source array included."""
+    opt = {"row_sort": row_sort}
+    for e, n in [synth.er_1000(), synth.rmat_graph(13, 16, seed=5),
+                 (synth.watts_strogatz(5000, 6, 0.1, 2), 5000), synth.rmat_graph(16, 24, seed=9)]:
         en = e.numpy()
-        out = api.preprocess(e.to(DEV), n)
+        out = api.preprocess(e.to(DEV), n, options=opt)
+        other = api.preprocess(e.to(DEV), n, options={"row_sort": 1 - row_sort})
+        for k in ("deg", "perm", "rank", "row_ptr", "col", "src"):
+            assert torch.equal(out[k], other[k]), k
+        rp_ = out["row_ptr"].cpu().numpy().astype(np.int64)
+        src_ = out["src"].cpu().numpy().astype(np.int64)
+        assert np.array_equal(src_, np.repeat(np.arange(n), np.diff(rp_)))
         deg = out["deg"].cpu().numpy().astype(np.int64)
         assert np.array_equal(deg, oracle.degrees(en, n))
         perm = out["perm"].cpu().numpy().astype(np.int64)
