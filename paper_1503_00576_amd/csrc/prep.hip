@@ -393,14 +393,14 @@ __global__ void k_csr(const uint64_t *__restrict__ keys, uint32_t mf, uint32_t n
 // With the edge keys sorted by source only (three radix passes instead of six), every row of
 // col holds its targets in input order; these kernels sort each row ascending, then check it
 // for duplicates and record hrow (as k_csr does for fully sorted keys).  A workgroup takes
-// the rows starting in one chunk of kRowChunk positions: rows of at most kRowSmall entries
-// one per lane (a sorting network in registers), rows of at most kRowWave entries one per
-// wave (a bitonic network over the wave's registers, kRowWave / 64 entries per lane, the
-// strides of 64 and more in registers and the smaller ones across lanes), longer rows are
-// listed for k_row_sort_long (a bitonic network in a workgroup's LDS).  Rows of a simple
-// graph hold fewer than sqrt(2 m) entries (Section 2.2), below kRowLong for the graphs this
-// path is used on; a longer row means repeated edges and is reported as TC_E_DUP_EDGE.
-constexpr uint32_t kRowSmall = 16;
+// the rows starting in one chunk of kRowChunk positions: rows of at most kRowWave entries by
+// groups of lanes sized to the row (a bitonic network over the group's registers, 16 entries
+// per lane, the smaller strides in registers and the others across the group's lanes; a
+// short row takes one lane, so that small rows do not pay for a whole wave's network),
+// longer rows are listed for k_row_sort_long (a wave's registers, or a bitonic network in a
+// workgroup's LDS).  Rows of a simple graph hold fewer than sqrt(2 m) entries (Section 2.2),
+// below kRowLong for the graphs this path is used on; a longer row means repeated edges and
+// is reported as TC_E_DUP_EDGE.
 constexpr uint32_t kRowWave = 1024;
 constexpr uint32_t kRowWaveLong = 2048;  // listed rows up to this length: one wave each
 constexpr uint32_t kRowLong = 32768;
@@ -424,33 +424,6 @@ __device__ __forceinline__ void row_checks(const uint32_t *v, uint32_t k, uint32
         if (has_before && before == v[j]) set_status(status, TC_E_DUP_EDGE);
         if (v[j] >= hbase && (!has_before || before < hbase)) hrow[r] = rb + p + j;
     }
-}
-
-// a row of at most kRowSmall entries, sorted by the calling lane alone
-__device__ __forceinline__ void sort_row_lane(uint32_t *__restrict__ col, uint32_t rb,
-                                              uint32_t len, uint32_t hbase,
-                                              uint32_t *__restrict__ hrow, uint32_t r,
-                                              int32_t *__restrict__ status) {
-    uint32_t v[kRowSmall];
-#pragma unroll
-    for (uint32_t j = 0; j < kRowSmall; ++j) v[j] = j < len ? col[rb + j] : ~0u;
-    // bitonic network on 16 entries, ascending
-#pragma unroll
-    for (uint32_t k = 2; k <= kRowSmall; k <<= 1)
-#pragma unroll
-        for (uint32_t st = k >> 1; st; st >>= 1)
-#pragma unroll
-            for (uint32_t i = 0; i < kRowSmall; ++i) {
-                const uint32_t q = i ^ st;
-                if (q > i) {
-                    if ((i & k) == 0) cswap(v[i], v[q]);
-                    else cswap(v[q], v[i]);
-                }
-            }
-#pragma unroll
-    for (uint32_t j = 0; j < kRowSmall; ++j)
-        if (j < len) col[rb + j] = v[j];
-    row_checks(v, len, 0, 0, rb, hbase, hrow, r, status);
 }
 
 // x of lane (lane ^ ls) for ls a power of two below 64 (a constant once the networks are
@@ -478,20 +451,21 @@ __device__ __forceinline__ uint32_t lane_xor(uint32_t x, uint32_t ls) {
     }
 }
 
-// a row of kRowSmall < len <= kRowWave entries, sorted by the calling wave: a bitonic network
-// on P = 64 E entries (P the smallest such power of two >= len), lane l holding positions
-// l E .. l E + E - 1
-template <uint32_t E>
-__device__ __forceinline__ void sort_row_wave(uint32_t *__restrict__ col, uint32_t rb,
-                                              uint32_t len, uint32_t hbase,
-                                              uint32_t *__restrict__ hrow, uint32_t r,
-                                              int32_t *__restrict__ status) {
-    constexpr uint32_t P = 64 * E;
-    const uint32_t lane = lane_id();
+// A row of at most G E entries, sorted by an aligned group of G lanes (G a power of two up to
+// 64; every lane of the wave takes part, each group with its own row, len 0 for none): a
+// bitonic network on P = G E entries, the group's lane g holding positions g E .. g E + E - 1.
+// Strides below E compare registers of one lane, the others exchange with lane g ^ (stride /
+// E), which stays inside the group.
+template <uint32_t E, uint32_t G>
+__device__ __forceinline__ void sort_row_group(uint32_t *__restrict__ col, uint32_t rb,
+                                               uint32_t len, uint32_t g, uint32_t hbase,
+                                               uint32_t *__restrict__ hrow, uint32_t r,
+                                               int32_t *__restrict__ status) {
+    constexpr uint32_t P = G * E;
     uint32_t v[E];
 #pragma unroll
     for (uint32_t j = 0; j < E; ++j) {
-        const uint32_t i = lane * E + j;
+        const uint32_t i = g * E + j;
         v[j] = i < len ? col[rb + i] : ~0u;
     }
 #pragma unroll
@@ -502,7 +476,7 @@ __device__ __forceinline__ void sort_row_wave(uint32_t *__restrict__ col, uint32
                 const uint32_t ls = st / E;
 #pragma unroll
                 for (uint32_t j = 0; j < E; ++j) {
-                    const uint32_t i = lane * E + j;
+                    const uint32_t i = g * E + j;
                     // (32 entries per lane: the permutes through the crossbar measured faster)
                     const uint32_t y = E <= 16 ? lane_xor(v[j], ls)
                                                : (uint32_t)__shfl_xor((int)v[j], (int)ls, kWave);
@@ -514,7 +488,7 @@ __device__ __forceinline__ void sort_row_wave(uint32_t *__restrict__ col, uint32
                 for (uint32_t j = 0; j < E; ++j) {
                     const uint32_t q = j ^ st;
                     if (q > j) {
-                        const uint32_t i = lane * E + j;
+                        const uint32_t i = g * E + j;
                         if ((i & k) == 0) cswap(v[j], v[q]);
                         else cswap(v[q], v[j]);
                     }
@@ -524,17 +498,48 @@ __device__ __forceinline__ void sort_row_wave(uint32_t *__restrict__ col, uint32
     }
 #pragma unroll
     for (uint32_t j = 0; j < E; ++j) {
-        const uint32_t i = lane * E + j;
+        const uint32_t i = g * E + j;
         if (i < len) col[rb + i] = v[j];
     }
-    const uint32_t prev = (uint32_t)__shfl_up((int)v[E - 1], 1, kWave);
-    const uint32_t p = lane * E;
+    // the entry before this lane's: the previous lane's last (used only when g > 0)
+    const uint32_t prev = G > 1 ? (uint32_t)__shfl_up((int)v[E - 1], 1, kWave) : 0u;
+    const uint32_t p = g * E;
     const uint32_t k = p < len ? min(E, len - p) : 0u;
     row_checks(v, k, p, prev, rb, hbase, hrow, r, status);
 }
 
-// Rows starting in chunk c (rows rchunk[c] .. rchunk[c + 1] - 1): short rows per lane, then
-// medium rows per wave; long rows go to the list for k_row_sort_long.
+// Rows of the chunk's class C (G = 2^C lanes of kRowLane entries per row), 64 / G rows per
+// wave at a time.
+constexpr uint32_t kRowLane = 16;  // entries per lane in k_row_sort
+constexpr uint32_t kRowClasses = 7;  // G = 1 .. 64
+template <uint32_t C>
+__device__ __forceinline__ void sort_row_class(uint32_t *__restrict__ col,
+                                               const uint32_t *__restrict__ row_ptr,
+                                               const uint32_t *list, uint32_t off, uint32_t cnt,
+                                               uint32_t hbase, uint32_t *__restrict__ hrow,
+                                               int32_t *__restrict__ status) {
+    constexpr uint32_t G = 1u << C, per = kWave / G;
+    const uint32_t lane = lane_id(), w = threadIdx.x / kWave, waves = blockDim.x / kWave;
+    for (uint32_t base = w * per; base < cnt; base += waves * per) {
+        const uint32_t q = base + lane / G;
+        uint32_t r = 0, rb = 0, len = 0;
+        if (q < cnt) {
+            r = list[off + q];
+            rb = row_ptr[r];
+            len = row_ptr[r + 1] - rb;
+        }
+        sort_row_group<kRowLane, G>(col, rb, len, lane % G, hbase, hrow, r, status);
+    }
+}
+
+// Rows starting in chunk c (rows rchunk[c] .. rchunk[c + 1] - 1), listed in LDS by class:
+// the non-empty rows of at most kRowWave entries by G = the smallest power of two with
+// G kRowLane >= length (C = log2 G), each class sorted by groups of G lanes; longer rows go
+// to the list for k_row_sort_long.  At most kRowChunk non-empty rows start in a chunk.
+__device__ __forceinline__ uint32_t row_class(uint32_t len) {  // len >= 1
+    if (len > kRowWave) return kRowClasses;
+    return len <= kRowLane ? 0u : 32u - (uint32_t)__builtin_clz(len - 1) - 4u;
+}
 __global__ __launch_bounds__(256) void k_row_sort(uint32_t *__restrict__ col,
                                                   const uint32_t *__restrict__ row_ptr,
                                                   const uint32_t *__restrict__ rchunk,
@@ -544,24 +549,44 @@ __global__ __launch_bounds__(256) void k_row_sort(uint32_t *__restrict__ col,
                                                   uint32_t *__restrict__ n_long,
                                                   int32_t *__restrict__ status) {
     if (*status) return;
+    static_assert(kRowLane << (kRowClasses - 1) == kRowWave, "classes cover the wave rows");
+    __shared__ uint32_t list[kRowChunk];
+    __shared__ uint32_t ccount[kRowClasses], coff[kRowClasses], ccur[kRowClasses];
     const uint32_t c = blockIdx.x;
     const uint32_t r0 = rchunk[c], r1 = c + 1 < chunks ? rchunk[c + 1] : n;
-    const uint32_t t = threadIdx.x, w = t / kWave;
+    const uint32_t t = threadIdx.x;
+    if (t < kRowClasses) ccount[t] = 0;
+    __syncthreads();
     for (uint32_t r = r0 + t; r < r1; r += blockDim.x) {
-        const uint32_t rb = row_ptr[r], len = row_ptr[r + 1] - rb;
-        if (len == 0 || len > kRowSmall) continue;
-        sort_row_lane(col, rb, len, hbase, hrow, r, status);
+        const uint32_t len = row_ptr[r + 1] - row_ptr[r];
+        if (len == 0) continue;
+        const uint32_t cls = row_class(len);
+        if (cls < kRowClasses) atomicAdd(&ccount[cls], 1u);
+        else long_rows[atomicAdd(n_long, 1u)] = r;
     }
-    for (uint32_t r = r0 + w; r < r1; r += blockDim.x / kWave) {
-        const uint32_t rb = row_ptr[r], len = row_ptr[r + 1] - rb;
-        if (len <= kRowSmall) continue;
-        if (len <= 64) sort_row_wave<1>(col, rb, len, hbase, hrow, r, status);
-        else if (len <= 128) sort_row_wave<2>(col, rb, len, hbase, hrow, r, status);
-        else if (len <= 256) sort_row_wave<4>(col, rb, len, hbase, hrow, r, status);
-        else if (len <= 512) sort_row_wave<8>(col, rb, len, hbase, hrow, r, status);
-        else if (len <= kRowWave) sort_row_wave<16>(col, rb, len, hbase, hrow, r, status);
-        else if (lane_id() == 0) long_rows[atomicAdd(n_long, 1u)] = r;
+    __syncthreads();
+    if (t == 0) {
+        uint32_t o = 0;
+        for (uint32_t k = 0; k < kRowClasses; ++k) {
+            coff[k] = ccur[k] = o;
+            o += ccount[k];
+        }
     }
+    __syncthreads();
+    for (uint32_t r = r0 + t; r < r1; r += blockDim.x) {
+        const uint32_t len = row_ptr[r + 1] - row_ptr[r];
+        if (len == 0) continue;
+        const uint32_t cls = row_class(len);
+        if (cls < kRowClasses) list[atomicAdd(&ccur[cls], 1u)] = r;
+    }
+    __syncthreads();
+    sort_row_class<0>(col, row_ptr, list, coff[0], ccount[0], hbase, hrow, status);
+    sort_row_class<1>(col, row_ptr, list, coff[1], ccount[1], hbase, hrow, status);
+    sort_row_class<2>(col, row_ptr, list, coff[2], ccount[2], hbase, hrow, status);
+    sort_row_class<3>(col, row_ptr, list, coff[3], ccount[3], hbase, hrow, status);
+    sort_row_class<4>(col, row_ptr, list, coff[4], ccount[4], hbase, hrow, status);
+    sort_row_class<5>(col, row_ptr, list, coff[5], ccount[5], hbase, hrow, status);
+    sort_row_class<6>(col, row_ptr, list, coff[6], ccount[6], hbase, hrow, status);
 }
 
 // The listed long rows: those of at most kRowWaveLong entries one per wave (the register
@@ -582,7 +607,8 @@ __global__ __launch_bounds__(1024) void k_row_sort_long(uint32_t *__restrict__ c
     for (uint32_t q = blockIdx.x * waves + t / kWave; q < nl; q += gridDim.x * waves) {
         const uint32_t r = long_rows[q];
         const uint32_t rb = row_ptr[r], len = row_ptr[r + 1] - rb;
-        if (len <= kRowWaveLong) sort_row_wave<32>(col, rb, len, hbase, hrow, r, status);
+        if (len <= kRowWaveLong)
+            sort_row_group<32, kWave>(col, rb, len, lane_id(), hbase, hrow, r, status);
     }
     for (uint32_t q = blockIdx.x; q < nl; q += gridDim.x) {
         const uint32_t r = long_rows[q];
