@@ -40,7 +40,7 @@ __global__ void k_panel_range(const uint64_t *, uint32_t, uint32_t, uint32_t, ui
 __global__ void k_csc_keys(const uint32_t *, const uint32_t *, const uint32_t *,
                            const uint32_t *, const uint32_t *, uint32_t, const uint64_t *,
                            uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t,
-                           uint64_t *, uint4 *, uint16_t *, const int32_t *);
+                           uint32_t *, uint4 *, uint16_t *, const int32_t *);
 __global__ void k_csc_final(const uint64_t *, uint32_t, uint64_t, uint32_t *, uint32_t *,
                             uint32_t *, const int32_t *);
 __global__ void k_items(const uint32_t *, const uint32_t *, const uint32_t *, uint32_t, uint32_t,
@@ -487,8 +487,11 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
                            L.p0, n, vr);
         TC_LAUNCH_CHECK();
     }
-    uint64_t *ck = (sorted == ka) ? kb : ka;  // the sorted edge keys are no longer needed
+    // the in-edge keys: 32-bit list ids in the buffer of the sorted edge keys (no longer
+    // needed), sorted into 64-bit (list, position) keys in the other buffer
+    uint64_t *ck = (sorted == ka) ? kb : ka;
     uint64_t *ck2 = (sorted == ka) ? ka : kb;
+    uint32_t *cid = (uint32_t *)ck2;
     uint4 *eu = at<uint4>(ws, L.eu);
     uint64_t *pr = at<uint64_t>(ws, L.prange);
     if (L.panels) {
@@ -498,11 +501,11 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
     }
     hipLaunchKernelGGL(k_csc_keys, dim3(grid_for(mf, 256 * kCscPerThread)), dim3(256), 0, s, col,
                        src, row_ptr, hrow, hstart, L.hbase, pr, mf, n, L.nblk, L.p0,
-                       count_panel(), L.h0, ck, eu, hcol, status);
+                       count_panel(), L.h0, cid, eu, hcol, status);
     TC_LAUNCH_CHECK();
     uint64_t *cks = ck;
-    TC_HIP(sort_u64(ck, ck2, mf, 32, 32 + id_bits_for64(l1), sort_scr, status, s, &cks,
-                    onesweep));
+    TC_HIP(sort_hi32_u64(cid, ck, ck2, mf, id_bits_for64(l1), sort_scr, status, s, &cks,
+                         onesweep));
     TC_HIP(fill_u32(lrs, 0u, l1, s));
     TC_HIP(fill_u32(lre, 0u, l1, s));
     hipLaunchKernelGGL(k_csc_final, dim3(grid_for(mf, 256 * 4)), dim3(256), 0, s, cks, mf,

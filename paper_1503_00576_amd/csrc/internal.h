@@ -107,6 +107,12 @@ size_t sort_scratch_bytes(uint64_t count);
 hipError_t sort_u64(uint64_t *keys, uint64_t *tmp, uint32_t count, int lo_bit, int hi_bit,
                     void *scratch, int32_t *status, hipStream_t s, uint64_t **result,
                     bool onesweep = false);
+// the keys (hi[i] << 32) | i sorted (stably) on their bits 32 .. 32 + hi_bits: the first pass
+// reads the 32-bit values and writes 64-bit keys to out, the others ping-pong between out and
+// tmp (hi may alias tmp, not out); same scratch as sort_u64
+hipError_t sort_hi32_u64(const uint32_t *hi, uint64_t *out, uint64_t *tmp, uint32_t count,
+                         int hi_bits, void *scratch, int32_t *status, hipStream_t s,
+                         uint64_t **result, bool onesweep = false);
 
 hipError_t fill_u32(uint32_t *p, uint32_t value, uint64_t count, hipStream_t s);
 

@@ -707,8 +707,8 @@ __global__ void k_panel_range(const uint64_t *__restrict__ vr, uint32_t n, uint3
 // N+(u) after v that also lies in N+(v), so only in-edges with a non-empty suffix are listed
 // (k_items skips the lists of vertices with an empty N+(v)).  They are keyed by their list
 // c = row block * (n + 1) + v (row blocks: contiguous CSR ranges, see the host code), the
-// others by `lists` (sorted last); the low 32 bits hold e, so a stable sort on the list bits
-// groups every list in CSR order.  (A test of the suffix's rank range against that of N+(v)
+// others by `lists` (sorted last); written as 32-bit list ids ckey[e], whose sort on the keys
+// (ckey[e] << 32) | e groups every list in CSR order.  (A test of the suffix's rank range against that of N+(v)
 // was dropped: on R-MAT graphs it rejected no in-edge and cost one random 8-byte lookup per
 // edge.)  From rank p0 on, middle vertices form panels of kp consecutive ranks with one list
 // per panel, keyed by its first rank P: only the first in-edge of each run of u's
@@ -729,7 +729,7 @@ __global__ void k_csc_keys(const uint32_t *__restrict__ col, const uint32_t *__r
                            const uint32_t *__restrict__ hstart, uint32_t hbase,
                            const uint64_t *__restrict__ pr, uint32_t mf, uint32_t n,
                            uint32_t nblk, uint32_t p0, uint32_t kp, uint32_t h0,
-                           uint64_t *__restrict__ keys, uint4 *__restrict__ eu,
+                           uint32_t *__restrict__ ckey, uint4 *__restrict__ eu,
                            uint16_t *__restrict__ hcol, const int32_t *__restrict__ status) {
     if (*status) return;
     // kp is a power of two; row blocks are rare (nblk > 1 only when asked for)
@@ -806,7 +806,7 @@ __global__ void k_csc_keys(const uint32_t *__restrict__ col, const uint32_t *__r
                 }
             }
         }
-        keys[e] = (c << 32) | e;
+        ckey[e] = (uint32_t)c;  // list ids are below 2^32 (the host bounds the row blocks)
         eu[e] = make_uint4(end_u, mask, hpos, u[k]);
     }
 }

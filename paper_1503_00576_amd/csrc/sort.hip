@@ -155,16 +155,29 @@ __device__ __forceinline__ uint64_t tile_key_index(uint64_t base, uint32_t w, in
     return base + (uint64_t)w * (kSortItems * kWave) + (uint64_t)r * kWave + lane_id();
 }
 
+// Where a pass reads its keys: 64-bit keys, or (for the first pass of a sort of keys
+// (value << 32) | position) 32-bit values whose key is formed with the value's own index, so
+// that the producer writes and the first pass reads 4 bytes per key instead of 8.
+struct Keys64 {
+    const uint64_t *p;
+    __device__ __forceinline__ uint64_t operator()(uint64_t i) const { return p[i]; }
+};
+struct KeysHiIndex {
+    const uint32_t *p;
+    __device__ __forceinline__ uint64_t operator()(uint64_t i) const {
+        return ((uint64_t)p[i] << 32) | (uint32_t)i;
+    }
+};
+
 // Loads the calling wave's 16 rows of the tile (all loads in flight before any use);
 // kFull: the whole tile lies below count.
-template <bool kFull>
-__device__ __forceinline__ void load_tile_keys(const uint64_t *__restrict__ in, uint32_t count,
-                                               uint64_t base, uint32_t w,
-                                               uint64_t (&keys)[kSortItems]) {
+template <bool kFull, class Src>
+__device__ __forceinline__ void load_tile_keys(const Src in, uint32_t count, uint64_t base,
+                                               uint32_t w, uint64_t (&keys)[kSortItems]) {
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         const uint64_t idx = tile_key_index(base, w, r);
-        keys[r] = (kFull || idx < count) ? in[idx] : 0ull;
+        keys[r] = (kFull || idx < count) ? in(idx) : 0ull;
     }
 }
 
@@ -263,9 +276,9 @@ __device__ __forceinline__ void write_staged(const SortTileLds &L, uint64_t *__r
     }
 }
 
-template <bool kFull>
-__device__ __forceinline__ void hist_tile(const uint64_t *__restrict__ in, uint32_t count,
-                                          int shift, uint32_t mask, uint32_t *__restrict__ hist,
+template <bool kFull, class Src>
+__device__ __forceinline__ void hist_tile(const Src in, uint32_t count, int shift,
+                                          uint32_t mask, uint32_t *__restrict__ hist,
                                           uint32_t tiles, uint32_t tile,
                                           uint32_t (&h)[kSortWaves][256]) {
     const uint32_t t = threadIdx.x, w = t / kWave;
@@ -296,9 +309,9 @@ __device__ __forceinline__ void hist_tile(const uint64_t *__restrict__ in, uint3
     }
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t *__restrict__ in,
-                                                             uint32_t count, int shift,
-                                                             uint32_t nbits,
+template <class Src>
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const Src in, uint32_t count,
+                                                             int shift, uint32_t nbits,
                                                              uint32_t *__restrict__ hist,
                                                              uint32_t tiles,
                                                              const int32_t *__restrict__ status) {
@@ -315,9 +328,9 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t *__r
 // Stable scatter of one tile: the keys are ranked and placed in LDS in digit order (a
 // tile-local counting sort), then written out digit run by digit run.
 //   offs: exclusive scan of the digit-major table of per-tile digit counts
-template <bool kFull>
-__device__ __forceinline__ void scatter_tile(const uint64_t *__restrict__ in,
-                                             uint64_t *__restrict__ out, uint32_t count,
+template <bool kFull, class Src>
+__device__ __forceinline__ void scatter_tile(const Src in, uint64_t *__restrict__ out,
+                                             uint32_t count,
                                              int shift, uint32_t mask,
                                              const uint32_t *__restrict__ offs, uint32_t tiles,
                                              uint32_t tile, SortTileLds &L) {
@@ -337,8 +350,9 @@ __device__ __forceinline__ void scatter_tile(const uint64_t *__restrict__ in,
     write_staged<kFull>(L, out, count, base, shift, mask, nullptr);
 }
 
+template <class Src>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
-    const uint64_t *__restrict__ in, uint64_t *__restrict__ out, uint32_t count, int shift,
+    const Src in, uint64_t *__restrict__ out, uint32_t count, int shift,
     uint32_t nbits, const uint32_t *__restrict__ offs, uint32_t tiles,
     const int32_t *__restrict__ status) {
     if (status && *status) return;
@@ -395,7 +409,7 @@ __device__ __forceinline__ void onesweep_tile(const uint64_t *__restrict__ in,
     const uint32_t t = threadIdx.x, w = t / kWave;
     const uint64_t base = (uint64_t)tile * kSortTile;
     uint64_t keys[kSortItems];
-    load_tile_keys<kFull>(in, count, base, w, keys);
+    load_tile_keys<kFull>(Keys64{in}, count, base, w, keys);
     for (uint32_t k = lane_id(); k < 256; k += kWave) L.wcnt[w][k] = 0;
     wave_lds_sync();
     uint32_t ranks[kSortItems];
@@ -490,6 +504,28 @@ size_t sort_scratch_bytes(uint64_t count) {
     return 2 * align_up(hist * 4, 256) + align_up(scan_scratch_words(hist) * 4, 256);
 }
 
+// One stable two-kernel pass on the digit at `shift` (at most 8 bits, below hi_bit) from the
+// keys `in` yields to dst.
+template <class Src>
+static hipError_t radix_pass(const Src in, uint64_t *dst, uint32_t count, int shift, int hi_bit,
+                             void *scratch, int32_t *status, hipStream_t s) {
+    const uint32_t tiles = ceil_div(count, kSortTile);
+    const uint64_t hist_n = 256ull * tiles;
+    uint32_t *hist = (uint32_t *)scratch;
+    uint32_t *offs = (uint32_t *)((char *)scratch + align_up(hist_n * 4, 256));
+    uint32_t *scan_scratch = (uint32_t *)((char *)scratch + 2 * align_up(hist_n * 4, 256));
+    const uint32_t nbits = (uint32_t)((hi_bit - shift) < 8 ? (hi_bit - shift) : 8);
+    hipLaunchKernelGGL(k_radix_hist<Src>, dim3(tiles), dim3(kSortThreads), 0, s, in, count,
+                       shift, nbits, hist, tiles, status);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = scan_exclusive_u32(hist, offs, hist_n, scan_scratch, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_radix_scatter<Src>, dim3(tiles), dim3(kSortThreads), 0, s, in, dst,
+                       count, shift, nbits, offs, tiles, status);
+    return hipGetLastError();
+}
+
 hipError_t sort_u64(uint64_t *keys, uint64_t *tmp, uint32_t count, int lo_bit, int hi_bit,
                     void *scratch, int32_t *status, hipStream_t s, uint64_t **result,
                     bool onesweep) {
@@ -499,7 +535,6 @@ hipError_t sort_u64(uint64_t *keys, uint64_t *tmp, uint32_t count, int lo_bit, i
     uint64_t hist_n = 256ull * tiles;
     uint32_t *hist = (uint32_t *)scratch;
     uint32_t *offs = (uint32_t *)((char *)scratch + align_up(hist_n * 4, 256));
-    uint32_t *scan_scratch = (uint32_t *)((char *)scratch + 2 * align_up(hist_n * 4, 256));
     uint64_t *src = keys, *dst = tmp;
     const int passes = (hi_bit - lo_bit + 7) / 8;
     if (status && onesweep && count >= (1u << 20) && count <= kLbValue &&
@@ -527,16 +562,7 @@ hipError_t sort_u64(uint64_t *keys, uint64_t *tmp, uint32_t count, int lo_bit, i
         return hipSuccess;
     }
     for (int shift = lo_bit; shift < hi_bit; shift += 8) {
-        uint32_t nbits = (uint32_t)((hi_bit - shift) < 8 ? (hi_bit - shift) : 8);
-        hipLaunchKernelGGL(k_radix_hist, dim3(tiles), dim3(kSortThreads), 0, s, src, count,
-                           shift, nbits, hist, tiles, status);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        e = scan_exclusive_u32(hist, offs, hist_n, scan_scratch, s);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_radix_scatter, dim3(tiles), dim3(kSortThreads), 0, s, src, dst,
-                           count, shift, nbits, offs, tiles, status);
-        e = hipGetLastError();
+        hipError_t e = radix_pass(Keys64{src}, dst, count, shift, hi_bit, scratch, status, s);
         if (e != hipSuccess) return e;
         uint64_t *x = src;
         src = dst;
@@ -544,6 +570,22 @@ hipError_t sort_u64(uint64_t *keys, uint64_t *tmp, uint32_t count, int lo_bit, i
     }
     *result = src;
     return hipSuccess;
+}
+
+hipError_t sort_hi32_u64(const uint32_t *hi, uint64_t *out, uint64_t *tmp, uint32_t count,
+                         int hi_bits, void *scratch, int32_t *status, hipStream_t s,
+                         uint64_t **result, bool onesweep) {
+    *result = out;
+    if (count == 0) return hipSuccess;
+    if (count == 1 || hi_bits <= 0) {  // no pass to form the keys: one pass on no bits
+        hipError_t e = radix_pass(KeysHiIndex{hi}, out, count, 32, 32, scratch, status, s);
+        return e;
+    }
+    const int hi_bit = 32 + hi_bits;
+    const int first = hi_bits < 8 ? hi_bit : 40;
+    hipError_t e = radix_pass(KeysHiIndex{hi}, out, count, 32, hi_bit, scratch, status, s);
+    if (e != hipSuccess) return e;
+    return sort_u64(out, tmp, count, first, hi_bit, scratch, status, s, result, onesweep);
 }
 
 }  // namespace tc
