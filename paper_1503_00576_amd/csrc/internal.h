@@ -107,12 +107,13 @@ size_t sort_scratch_bytes(uint64_t count);
 hipError_t sort_u64(uint64_t *keys, uint64_t *tmp, uint32_t count, int lo_bit, int hi_bit,
                     void *scratch, int32_t *status, hipStream_t s, uint64_t **result,
                     bool onesweep = false);
-// the keys (hi[i] << 32) | i sorted (stably) on their bits 32 .. 32 + hi_bits: the first pass
-// reads the 32-bit values and writes 64-bit keys to out, the others ping-pong between out and
-// tmp (hi may alias tmp, not out); same scratch as sort_u64
-hipError_t sort_hi32_u64(const uint32_t *hi, uint64_t *out, uint64_t *tmp, uint32_t count,
-                         int hi_bits, void *scratch, int32_t *status, hipStream_t s,
-                         uint64_t **result, bool onesweep = false);
+// The in-edge lists: the keys (cid[i] << 32) | i sorted (stably) on their bits 32 .. 32 +
+// bits, written split: *list (list ids, in a or b, whichever the last pass does not read)
+// and cbeg (position + 1).  The first pass reads the 32-bit ids, the middle ones ping-pong
+// between a and b (cid may alias b, not a); same scratch as sort_u64.
+hipError_t sort_lists(const uint32_t *cid, uint32_t count, int bits, uint64_t *a, uint64_t *b,
+                      uint32_t *cbeg, void *scratch, int32_t *status, hipStream_t s,
+                      uint32_t **list, bool onesweep = false);
 
 hipError_t fill_u32(uint32_t *p, uint32_t value, uint64_t count, hipStream_t s);
 

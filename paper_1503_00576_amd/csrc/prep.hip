@@ -328,8 +328,10 @@ __global__ void k_orient_cells(const int2 *__restrict__ cells, uint64_t m, uint3
             r1u = rank[e1.x];
             r1v = rank[e1.y];
         }
-        if (ok0) __builtin_nontemporal_store(((uint64_t)min(r0u, r0v) << b) | max(r0u, r0v), keys + i0);
-        if (ok1) __builtin_nontemporal_store(((uint64_t)min(r1u, r1v) << b) | max(r1u, r1v), keys + i1);
+        const uint64_t k0 = ((uint64_t)min(r0u, r0v) << b) | max(r0u, r0v);
+        const uint64_t k1 = ((uint64_t)min(r1u, r1v) << b) | max(r1u, r1v);
+        if (ok0) __builtin_nontemporal_store(k0, keys + i0);
+        if (ok1) __builtin_nontemporal_store(k1, keys + i1);
     }
 }
 
@@ -708,17 +710,17 @@ __global__ void k_panel_range(const uint64_t *__restrict__ vr, uint32_t n, uint3
 // (k_items skips the lists of vertices with an empty N+(v)).  They are keyed by their list
 // c = row block * (n + 1) + v (row blocks: contiguous CSR ranges, see the host code), the
 // others by `lists` (sorted last); written as 32-bit list ids ckey[e], whose sort on the keys
-// (ckey[e] << 32) | e groups every list in CSR order.  (A test of the suffix's rank range against that of N+(v)
-// was dropped: on R-MAT graphs it rejected no in-edge and cost one random 8-byte lookup per
-// edge.)  From rank p0 on, middle vertices form panels of kp consecutive ranks with one list
-// per panel, keyed by its first rank P: only the first in-edge of each run of u's
-// out-neighbours inside the panel is kept (it stands for the whole run), tested against the
-// panel's span (a small table).  eu[e], the in-edge's record read by the counting kernels,
-// = (end of u's row, mask of the run's panel vertices for a kept panel entry or, for any
-// other kept entry, the col position where the suffix's entries >= hbase start, the hcol
-// position where they start, u).  In-edges from hubs (u >= h0) are left out: their
-// triangles are counted on the matrix cores.  Every entry >= hbase is
-// also written to its row's part of hcol (hrow and hstart: k_csr, k_hlen and a scan).
+// (ckey[e] << 32) | e groups every list in CSR order.  (A test of the suffix's rank range
+// against that of N+(v) was dropped: on R-MAT graphs it rejected no in-edge and cost one
+// random 8-byte lookup per edge.)  From rank p0 on, middle vertices form panels of kp
+// consecutive ranks with one list per panel, keyed by its first rank P: only the first
+// in-edge of each run of u's out-neighbours inside the panel is kept (it stands for the whole
+// run), tested against the panel's span (a small table).  eu[e], the in-edge's record read by
+// the counting kernels, = (end of u's row, mask of the run's panel vertices for a kept panel
+// entry or, for any other kept entry, the col position where the suffix's entries >= hbase
+// start, the hcol position where they start, u).  In-edges from hubs (u >= h0) are left out:
+// their triangles are counted on the matrix cores.  Every entry >= hbase is also written to
+// its row's part of hcol (hrow and hstart: k_csr, k_hlen and a scan).
 // Each thread takes kCscEdges entries a block apart and issues every stage's loads for all of
 // them before using any (the stages depend on each other: entry -> row -> row end).
 constexpr uint32_t kCscEdges = 4;
@@ -812,31 +814,31 @@ __global__ void k_csc_keys(const uint32_t *__restrict__ col, const uint32_t *__r
 }
 
 // The lists themselves: list c occupies sorted positions [rs[c], re[c]) (useful in-edges
-// only; rs and re zeroed beforehand), and entry j names its in-edge by cbeg[j] = e + 1, the
-// start of the suffix; the counting kernels read the in-edge's record (k_csc_keys) from there.
-// kCscFinalKeys keys a block apart per thread, all loaded before any is used.
+// only; rs and re zeroed beforehand), found from the sorted list ids; entry j names its
+// in-edge by cbeg[j] = e + 1, the start of the suffix (written by the sort's last pass); the
+// counting kernels read the in-edge's record (k_csc_keys) from there.  kCscFinalKeys ids a
+// block apart per thread, all loaded before any is used.
 constexpr uint32_t kCscFinalKeys = 4;
-__global__ void k_csc_final(const uint64_t *__restrict__ keys, uint32_t mf, uint64_t lists,
-                            uint32_t *__restrict__ cbeg, uint32_t *__restrict__ rs,
-                            uint32_t *__restrict__ re, const int32_t *__restrict__ status) {
+__global__ void k_csc_final(const uint32_t *__restrict__ list, uint32_t mf, uint64_t lists,
+                            uint32_t *__restrict__ rs, uint32_t *__restrict__ re,
+                            const int32_t *__restrict__ status) {
     if (*status) return;
     const uint64_t j0 = (uint64_t)blockIdx.x * blockDim.x * kCscFinalKeys + threadIdx.x;
-    uint64_t k[kCscFinalKeys], kp[kCscFinalKeys], kn[kCscFinalKeys];
+    uint32_t k[kCscFinalKeys], kp[kCscFinalKeys], kn[kCscFinalKeys];
 #pragma unroll
     for (uint32_t t = 0; t < kCscFinalKeys; ++t) {
         const uint64_t j = j0 + (uint64_t)t * blockDim.x;
-        k[t] = j < mf ? keys[j] : ~0ull;
-        kp[t] = (j < mf && j > 0) ? keys[j - 1] : ~0ull;
-        kn[t] = j + 1 < mf ? keys[j + 1] : ~0ull;
+        k[t] = j < mf ? list[j] : ~0u;
+        kp[t] = (j < mf && j > 0) ? list[j - 1] : ~0u;
+        kn[t] = j + 1 < mf ? list[j + 1] : ~0u;
     }
 #pragma unroll
     for (uint32_t t = 0; t < kCscFinalKeys; ++t) {
         const uint64_t j = j0 + (uint64_t)t * blockDim.x;
-        const uint64_t c = k[t] >> 32;
+        const uint32_t c = k[t];
         if (j >= mf || c >= lists) continue;
-        if (j == 0 || (kp[t] >> 32) != c) rs[c] = (uint32_t)j;
-        if (j == mf - 1 || (kn[t] >> 32) != c) re[c] = (uint32_t)j + 1;
-        cbeg[j] = (uint32_t)k[t] + 1;
+        if (j == 0 || kp[t] != c) rs[c] = (uint32_t)j;
+        if (j == mf - 1 || kn[t] != c) re[c] = (uint32_t)j + 1;
     }
 }
 

@@ -169,6 +169,20 @@ struct KeysHiIndex {
     }
 };
 
+// Where a pass writes its keys: 64-bit keys, or split for the last pass of the in-edge list
+// sort into the list id (high half) and the list entry cbeg = position + 1 (low half + 1).
+struct Out64 {
+    uint64_t *p;
+    __device__ __forceinline__ void operator()(uint64_t pos, uint64_t key) const { p[pos] = key; }
+};
+struct OutListBeg {
+    uint32_t *list, *beg;
+    __device__ __forceinline__ void operator()(uint64_t pos, uint64_t key) const {
+        list[pos] = (uint32_t)(key >> 32);
+        beg[pos] = (uint32_t)key + 1u;
+    }
+};
+
 // Loads the calling wave's 16 rows of the tile (all loads in flight before any use);
 // kFull: the whole tile lies below count.
 template <bool kFull, class Src>
@@ -252,10 +266,10 @@ __device__ __forceinline__ void stage_keys(SortTileLds &L, const uint64_t (&keys
 
 // Writes the staged tile: consecutive threads write consecutive positions of one digit's run
 // (L.glob[d] + j is the output position of staged key j of digit d).
-template <bool kFull>
-__device__ __forceinline__ void write_staged(const SortTileLds &L, uint64_t *__restrict__ out,
-                                             uint32_t count, uint64_t base, int shift,
-                                             uint32_t mask, int32_t *status) {
+template <bool kFull, class Dst>
+__device__ __forceinline__ void write_staged(const SortTileLds &L, const Dst out, uint32_t count,
+                                             uint64_t base, int shift, uint32_t mask,
+                                             int32_t *status) {
     const uint64_t rest = count - base;
     const uint32_t ntile = kFull ? (uint32_t)kSortTile : (uint32_t)rest;
 #pragma unroll
@@ -266,9 +280,9 @@ __device__ __forceinline__ void write_staged(const SortTileLds &L, uint64_t *__r
             const uint32_t d = (uint32_t)(key >> shift) & mask;
             const uint32_t pos = L.glob[d] + j;
             if (!status) {
-                out[pos] = key;
+                out(pos, key);
             } else if (pos < count) {  // holds whenever the prefixes are right
-                out[pos] = key;
+                out(pos, key);
             } else {
                 set_status(status, TC_E_HIP);
             }
@@ -328,9 +342,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const Src in, uint3
 // Stable scatter of one tile: the keys are ranked and placed in LDS in digit order (a
 // tile-local counting sort), then written out digit run by digit run.
 //   offs: exclusive scan of the digit-major table of per-tile digit counts
-template <bool kFull, class Src>
-__device__ __forceinline__ void scatter_tile(const Src in, uint64_t *__restrict__ out,
-                                             uint32_t count,
+template <bool kFull, class Src, class Dst>
+__device__ __forceinline__ void scatter_tile(const Src in, const Dst out, uint32_t count,
                                              int shift, uint32_t mask,
                                              const uint32_t *__restrict__ offs, uint32_t tiles,
                                              uint32_t tile, SortTileLds &L) {
@@ -350,9 +363,9 @@ __device__ __forceinline__ void scatter_tile(const Src in, uint64_t *__restrict_
     write_staged<kFull>(L, out, count, base, shift, mask, nullptr);
 }
 
-template <class Src>
+template <class Src, class Dst>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
-    const Src in, uint64_t *__restrict__ out, uint32_t count, int shift,
+    const Src in, const Dst out, uint32_t count, int shift,
     uint32_t nbits, const uint32_t *__restrict__ offs, uint32_t tiles,
     const int32_t *__restrict__ status) {
     if (status && *status) return;
@@ -471,7 +484,7 @@ __device__ __forceinline__ void onesweep_tile(const uint64_t *__restrict__ in,
         L.glob[t] = gstart + excl - L.loc[t];
     }
     __syncthreads();
-    write_staged<kFull>(L, out, count, base, shift, mask, status);
+    write_staged<kFull>(L, Out64{out}, count, base, shift, mask, status);
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_radix_onesweep(
@@ -506,8 +519,8 @@ size_t sort_scratch_bytes(uint64_t count) {
 
 // One stable two-kernel pass on the digit at `shift` (at most 8 bits, below hi_bit) from the
 // keys `in` yields to dst.
-template <class Src>
-static hipError_t radix_pass(const Src in, uint64_t *dst, uint32_t count, int shift, int hi_bit,
+template <class Src, class Dst>
+static hipError_t radix_pass(const Src in, const Dst dst, uint32_t count, int shift, int hi_bit,
                              void *scratch, int32_t *status, hipStream_t s) {
     const uint32_t tiles = ceil_div(count, kSortTile);
     const uint64_t hist_n = 256ull * tiles;
@@ -521,8 +534,8 @@ static hipError_t radix_pass(const Src in, uint64_t *dst, uint32_t count, int sh
     if (e != hipSuccess) return e;
     e = scan_exclusive_u32(hist, offs, hist_n, scan_scratch, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_radix_scatter<Src>, dim3(tiles), dim3(kSortThreads), 0, s, in, dst,
-                       count, shift, nbits, offs, tiles, status);
+    hipLaunchKernelGGL((k_radix_scatter<Src, Dst>), dim3(tiles), dim3(kSortThreads), 0, s, in,
+                       dst, count, shift, nbits, offs, tiles, status);
     return hipGetLastError();
 }
 
@@ -562,7 +575,8 @@ hipError_t sort_u64(uint64_t *keys, uint64_t *tmp, uint32_t count, int lo_bit, i
         return hipSuccess;
     }
     for (int shift = lo_bit; shift < hi_bit; shift += 8) {
-        hipError_t e = radix_pass(Keys64{src}, dst, count, shift, hi_bit, scratch, status, s);
+        hipError_t e =
+            radix_pass(Keys64{src}, Out64{dst}, count, shift, hi_bit, scratch, status, s);
         if (e != hipSuccess) return e;
         uint64_t *x = src;
         src = dst;
@@ -572,20 +586,27 @@ hipError_t sort_u64(uint64_t *keys, uint64_t *tmp, uint32_t count, int lo_bit, i
     return hipSuccess;
 }
 
-hipError_t sort_hi32_u64(const uint32_t *hi, uint64_t *out, uint64_t *tmp, uint32_t count,
-                         int hi_bits, void *scratch, int32_t *status, hipStream_t s,
-                         uint64_t **result, bool onesweep) {
-    *result = out;
+hipError_t sort_lists(const uint32_t *cid, uint32_t count, int bits, uint64_t *a, uint64_t *b,
+                      uint32_t *cbeg, void *scratch, int32_t *status, hipStream_t s,
+                      uint32_t **list, bool onesweep) {
+    *list = (uint32_t *)a;
     if (count == 0) return hipSuccess;
-    if (count == 1 || hi_bits <= 0) {  // no pass to form the keys: one pass on no bits
-        hipError_t e = radix_pass(KeysHiIndex{hi}, out, count, 32, 32, scratch, status, s);
-        return e;
-    }
-    const int hi_bit = 32 + hi_bits;
-    const int first = hi_bits < 8 ? hi_bit : 40;
-    hipError_t e = radix_pass(KeysHiIndex{hi}, out, count, 32, hi_bit, scratch, status, s);
+    const int hi_bit = 32 + (bits > 0 ? bits : 0);
+    const int passes = bits > 0 ? (bits + 7) / 8 : 1;
+    if (passes == 1)  // one pass from the ids to the split output
+        return radix_pass(KeysHiIndex{cid}, OutListBeg{*list, cbeg}, count, 32, hi_bit, scratch,
+                          status, s);
+    hipError_t e = radix_pass(KeysHiIndex{cid}, Out64{a}, count, 32, hi_bit, scratch, status, s);
     if (e != hipSuccess) return e;
-    return sort_u64(out, tmp, count, first, hi_bit, scratch, status, s, result, onesweep);
+    const int last = 32 + 8 * (passes - 1);  // the last pass's digit
+    uint64_t *mid = a;
+    if (passes > 2) {
+        e = sort_u64(a, b, count, 40, last, scratch, status, s, &mid, onesweep);
+        if (e != hipSuccess) return e;
+    }
+    *list = (uint32_t *)(mid == a ? b : a);  // the buffer the last pass does not read
+    return radix_pass(Keys64{mid}, OutListBeg{*list, cbeg}, count, last, hi_bit, scratch, status,
+                      s);
 }
 
 }  // namespace tc
