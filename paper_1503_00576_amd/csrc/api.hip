@@ -27,7 +27,9 @@ __global__ void k_orient_cells(const int2 *, uint64_t, uint32_t, const uint32_t 
                                uint64_t *, const int32_t *);
 __global__ void k_both_check(const uint32_t *, uint32_t, int32_t *);
 __global__ void k_csr(const uint64_t *, uint32_t, uint32_t, int, uint32_t, uint32_t *,
-                      uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t *, int32_t *);
+                      uint32_t *, uint32_t *, uint32_t *, uint32_t *, int32_t *);
+__global__ void k_row_bounds(const uint32_t *, uint32_t, uint32_t, uint32_t *, uint32_t *,
+                             uint32_t *, const int32_t *);
 __global__ void k_row_sort(uint32_t *, const uint32_t *, const uint32_t *, uint32_t, uint32_t,
                            uint32_t, uint32_t *, uint32_t *, uint32_t *, int32_t *);
 __global__ void k_row_sort_long(uint32_t *, const uint32_t *, const uint32_t *,
@@ -362,6 +364,7 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
     void *sort_scr = at<void>(ws, L.sort_scratch);
     uint32_t *row_ptr = at<uint32_t>(ws, L.row_ptr);
     uint32_t *col = at<uint32_t>(ws, L.col);
+    uint32_t *src = at<uint32_t>(ws, L.src);
     const int2 *edges = (const int2 *)d_edges;
     const bool both = flags & TC_EDGES_BOTH;
 
@@ -420,9 +423,10 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
             hipLaunchKernelGGL(k_both_check, dim3(1), dim3(64), 0, s, ctl + kCtlBoth, mf, status);
             TC_LAUNCH_CHECK();
         }
-        // by source only when the rows can be sorted in place afterwards (k_row_sort)
-        TC_HIP(sort_u64(ka, kb, mf, row_sort ? b : 0, 2 * b, sort_scr, status, s, &sorted,
-                        onesweep));
+        if (row_sort)  // by source only, unzipped by the last pass (rows sorted by k_row_sort)
+            TC_HIP(sort_unzip(ka, kb, mf, b, 2 * b, b, col, src, sort_scr, status, s, onesweep));
+        else
+            TC_HIP(sort_u64(ka, kb, mf, 0, 2 * b, sort_scr, status, s, &sorted, onesweep));
     }
     if (mf == 0) {
         TC_HIP(fill_u32(row_ptr, 0u, n1, s));
@@ -433,13 +437,16 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
     uint32_t *rowlen = at<uint32_t>(ws, L.rowlen);
     TC_HIP(fill_u32(rs, 0u, n1, s));
     TC_HIP(fill_u32(re, 0u, n1, s));
-    uint32_t *src = at<uint32_t>(ws, L.src);
     uint32_t *hrow = at<uint32_t>(ws, L.hrow);
     TC_HIP(fill_u32(hrow, ~0u, n, s));
     uint32_t *rchunk = at<uint32_t>(ws, L.rchunk);
-    hipLaunchKernelGGL(k_csr, dim3(grid_for(mf, 256 * 4)), dim3(256), 0, s, sorted, mf, n, b,
-                       L.hbase, col, src, rs, re, hrow, row_sort ? rchunk : nullptr,
-                       status);  // 4 keys per thread (prep.hip, kCsrKeys)
+    // 4 entries per thread (prep.hip, kCsrKeys)
+    if (row_sort)
+        hipLaunchKernelGGL(k_row_bounds, dim3(grid_for(mf, 256 * 4)), dim3(256), 0, s, src, mf,
+                           n, rs, re, rchunk, status);
+    else
+        hipLaunchKernelGGL(k_csr, dim3(grid_for(mf, 256 * 4)), dim3(256), 0, s, sorted, mf, n,
+                           b, L.hbase, col, src, rs, re, hrow, status);
     TC_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_rowlen, dim3(grid_for(n1, 256)), dim3(256), 0, s, rs, re, n, rowlen);
     TC_LAUNCH_CHECK();

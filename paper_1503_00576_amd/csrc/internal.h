@@ -107,6 +107,11 @@ size_t sort_scratch_bytes(uint64_t count);
 hipError_t sort_u64(uint64_t *keys, uint64_t *tmp, uint32_t count, int lo_bit, int hi_bit,
                     void *scratch, int32_t *status, hipStream_t s, uint64_t **result,
                     bool onesweep = false);
+// keys sorted (stably) on bits lo_bit .. hi_bit and written unzipped: col[i] = low b bits,
+// src[i] = the bits above (keys and tmp are clobbered); same scratch as sort_u64
+hipError_t sort_unzip(uint64_t *keys, uint64_t *tmp, uint32_t count, int lo_bit, int hi_bit,
+                      int b, uint32_t *col, uint32_t *src, void *scratch, int32_t *status,
+                      hipStream_t s, bool onesweep = false);
 // The in-edge lists: the keys (cid[i] << 32) | i sorted (stably) on their bits 32 .. 32 +
 // bits, written split: *list (list ids, in a or b, whichever the last pass does not read)
 // and cbeg (position + 1).  The first pass reads the 32-bit ids, the middle ones ping-pong

@@ -348,15 +348,12 @@ constexpr uint32_t kRowChunk = 4096;  // CSR positions per workgroup of k_row_so
 // Unzip the sorted keys into the neighbour array (Section 3.2, step 7) and mark where every
 // non-empty row starts and ends; row lengths and their prefix sum give the node array.
 // hrow[u] receives the position of the first entry >= hbase of row u (left untouched, all
-// ones from the caller's fill, when the row has none).  With keys sorted by their source only
-// (rchunk non-null) the rows are not yet ordered: the duplicate check and hrow are left to
-// k_row_sort, and rchunk[c] receives the first row starting at or after position
-// c * kRowChunk (the chunks of k_row_sort).
+// ones from the caller's fill, when the row has none).  (Keys sorted by (source, target): the
+// path of graphs too large for the row sort, or with it switched off.)
 __global__ void k_csr(const uint64_t *__restrict__ keys, uint32_t mf, uint32_t n, int b,
                       uint32_t hbase, uint32_t *__restrict__ col, uint32_t *__restrict__ src,
                       uint32_t *__restrict__ rs, uint32_t *__restrict__ re,
-                      uint32_t *__restrict__ hrow, uint32_t *__restrict__ rchunk,
-                      int32_t *__restrict__ status) {
+                      uint32_t *__restrict__ hrow, int32_t *__restrict__ status) {
     if (*status) return;
     // kCsrKeys keys a block apart per thread, all loaded before any is used
     const uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x * kCsrKeys + threadIdx.x;
@@ -379,14 +376,39 @@ __global__ void k_csr(const uint64_t *__restrict__ keys, uint32_t mf, uint32_t n
         if (s >= n) continue;  // only for invalid input, reported elsewhere
         const bool row_start = i == 0 || (uint32_t)(kp[t] >> b) != s;
         if (row_start) rs[s] = (uint32_t)i;
-        if (rchunk) {
-            if ((i & (kRowChunk - 1)) == 0) rchunk[i / kRowChunk] = row_start ? s : s + 1;
-        } else {
-            if (c >= hbase && (row_start || (uint32_t)(kp[t] & ((1ull << b) - 1)) < hbase))
-                hrow[s] = (uint32_t)i;
-            if (i > 0 && kp[t] == k[t]) set_status(status, TC_E_DUP_EDGE);
-        }
+        if (c >= hbase && (row_start || (uint32_t)(kp[t] & ((1ull << b) - 1)) < hbase))
+            hrow[s] = (uint32_t)i;
+        if (i > 0 && kp[t] == k[t]) set_status(status, TC_E_DUP_EDGE);
         if (i == mf - 1 || (uint32_t)(kn[t] >> b) != s) re[s] = (uint32_t)(i + 1);
+    }
+}
+
+// With the keys sorted by source only and unzipped by the sort's last pass (col, src): where
+// every non-empty row starts and ends, and rchunk[c] = the first row starting at or after
+// position c * kRowChunk (the chunks of k_row_sort, which sorts the rows, checks them for
+// duplicates and records hrow).
+__global__ void k_row_bounds(const uint32_t *__restrict__ src, uint32_t mf, uint32_t n,
+                             uint32_t *__restrict__ rs, uint32_t *__restrict__ re,
+                             uint32_t *__restrict__ rchunk, const int32_t *__restrict__ status) {
+    if (*status) return;
+    const uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x * kCsrKeys + threadIdx.x;
+    uint32_t x[kCsrKeys], xp[kCsrKeys], xn[kCsrKeys];
+#pragma unroll
+    for (uint32_t t = 0; t < kCsrKeys; ++t) {
+        const uint64_t i = i0 + (uint64_t)t * blockDim.x;
+        x[t] = i < mf ? src[i] : 0u;
+        xp[t] = (i < mf && i > 0) ? src[i - 1] : ~0u;
+        xn[t] = i + 1 < mf ? src[i + 1] : ~0u;
+    }
+#pragma unroll
+    for (uint32_t t = 0; t < kCsrKeys; ++t) {
+        const uint64_t i = i0 + (uint64_t)t * blockDim.x;
+        const uint32_t s = x[t];
+        if (i >= mf || s >= n) continue;  // (s >= n only for invalid input, reported elsewhere)
+        const bool row_start = i == 0 || xp[t] != s;
+        if (row_start) rs[s] = (uint32_t)i;
+        if ((i & (kRowChunk - 1)) == 0) rchunk[i / kRowChunk] = row_start ? s : s + 1;
+        if (i == mf - 1 || xn[t] != s) re[s] = (uint32_t)(i + 1);
     }
 }
 

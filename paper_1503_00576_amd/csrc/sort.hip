@@ -175,6 +175,16 @@ struct Out64 {
     uint64_t *p;
     __device__ __forceinline__ void operator()(uint64_t pos, uint64_t key) const { p[pos] = key; }
 };
+// ... or unzipped, for the last pass of the edge sort: target (low b bits) and source.
+struct OutColSrc {
+    uint32_t *col, *src;
+    uint64_t tmask;
+    int b;
+    __device__ __forceinline__ void operator()(uint64_t pos, uint64_t key) const {
+        col[pos] = (uint32_t)(key & tmask);
+        src[pos] = (uint32_t)(key >> b);
+    }
+};
 struct OutListBeg {
     uint32_t *list, *beg;
     __device__ __forceinline__ void operator()(uint64_t pos, uint64_t key) const {
@@ -584,6 +594,19 @@ hipError_t sort_u64(uint64_t *keys, uint64_t *tmp, uint32_t count, int lo_bit, i
     }
     *result = src;
     return hipSuccess;
+}
+
+hipError_t sort_unzip(uint64_t *keys, uint64_t *tmp, uint32_t count, int lo_bit, int hi_bit,
+                      int b, uint32_t *col, uint32_t *src, void *scratch, int32_t *status,
+                      hipStream_t s, bool onesweep) {
+    if (count == 0) return hipSuccess;
+    const int passes = hi_bit > lo_bit ? (hi_bit - lo_bit + 7) / 8 : 1;
+    const int last = hi_bit > lo_bit ? lo_bit + 8 * (passes - 1) : hi_bit;
+    uint64_t *mid = keys;
+    hipError_t e = sort_u64(keys, tmp, count, lo_bit, last, scratch, status, s, &mid, onesweep);
+    if (e != hipSuccess) return e;
+    return radix_pass(Keys64{mid}, OutColSrc{col, src, (1ull << b) - 1, b}, count, last, hi_bit,
+                      scratch, status, s);
 }
 
 hipError_t sort_lists(const uint32_t *cid, uint32_t count, int bits, uint64_t *a, uint64_t *b,
