@@ -13,10 +13,12 @@ namespace tc {
 // kernels of prep.hip
 __global__ void k_part_hist(const int2 *, uint64_t, uint32_t, uint32_t, int, int, uint32_t *,
                             uint32_t, int32_t *);
+template <class P>
 __global__ void k_part_scatter(const int2 *, uint64_t, uint32_t, uint32_t, int, int,
-                               const uint32_t *, const uint32_t *, uint32_t, uint32_t *, int2 *);
-__global__ void k_part_count(const uint32_t *, const uint32_t *, uint32_t, int, uint32_t,
-                             uint32_t, uint32_t *, const int32_t *);
+                               const uint32_t *, const uint32_t *, uint32_t, P *, int2 *);
+template <class P>
+__global__ void k_part_count(const P *, const uint32_t *, uint32_t, int, uint32_t, uint32_t,
+                             uint32_t *, const int32_t *);
 __global__ void k_degree_atomic(const int2 *, uint64_t, uint32_t, uint32_t, uint32_t *,
                                 int32_t *);
 __global__ void k_vkeys(const uint32_t *, uint32_t, int, uint64_t *);
@@ -380,20 +382,33 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
         const uint32_t tiles = L.part_tiles;
         const uint64_t hp = (L.cell_shift >= 0 ? 512ull : 256ull) * tiles;
         uint32_t *ph = at<uint32_t>(ws, L.part_hist), *po = at<uint32_t>(ws, L.part_offs);
-        uint32_t *parts = (uint32_t *)kb;  // 4-byte endpoints fit the 8-byte key buffer
+        // the endpoints' offsets inside their buckets, 2 bytes each when a bucket holds at most
+        // 2^16 ids, else 4 (either fits the 8-byte key buffer)
+        const bool narrow = L.part_shift <= 16;
         TC_HIP(fill_u32(ph + hp, 0u, 1, s));
         hipLaunchKernelGGL(k_part_hist, dim3(tiles), dim3(256), 0, s, edges, (uint64_t)m, n,
                            (uint32_t)both, L.part_shift, L.cell_shift, ph, tiles, status);
         TC_LAUNCH_CHECK();
         TC_HIP(scan_exclusive_u32(ph, po, hp + 1, at<uint32_t>(ws, L.part_scan), s));
-        hipLaunchKernelGGL(k_part_scatter, dim3(tiles), dim3(256), 0, s, edges, (uint64_t)m, n,
-                           (uint32_t)both, L.part_shift, L.cell_shift, ph, po, tiles, parts,
-                           cells);
+        if (narrow)
+            hipLaunchKernelGGL((k_part_scatter<uint16_t>), dim3(tiles), dim3(256), 0, s, edges,
+                               (uint64_t)m, n, (uint32_t)both, L.part_shift, L.cell_shift, ph,
+                               po, tiles, (uint16_t *)kb, cells);
+        else
+            hipLaunchKernelGGL((k_part_scatter<uint32_t>), dim3(tiles), dim3(256), 0, s, edges,
+                               (uint64_t)m, n, (uint32_t)both, L.part_shift, L.cell_shift, ph,
+                               po, tiles, (uint32_t *)kb, cells);
         TC_LAUNCH_CHECK();
         const uint32_t buckets = 1u << (L.id_bits - L.part_shift);
         const uint32_t slices = buckets >= 512 ? 1u : 512u / buckets;
-        hipLaunchKernelGGL(k_part_count, dim3(buckets * slices), dim3(1024), 0, s, parts, po,
-                           tiles, L.part_shift, n, slices, deg, status);
+        if (narrow)
+            hipLaunchKernelGGL((k_part_count<uint16_t>), dim3(buckets * slices), dim3(1024), 0, s,
+                               (const uint16_t *)kb, po, tiles, L.part_shift, n, slices, deg,
+                               status);
+        else
+            hipLaunchKernelGGL((k_part_count<uint32_t>), dim3(buckets * slices), dim3(1024), 0, s,
+                               (const uint32_t *)kb, po, tiles, L.part_shift, n, slices, deg,
+                               status);
         TC_LAUNCH_CHECK();
     } else if (m > 0) {
         hipLaunchKernelGGL(k_degree_atomic, dim3(grid_for(m, 256, 8192)), dim3(256), 0, s, edges,

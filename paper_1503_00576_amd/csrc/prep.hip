@@ -85,13 +85,15 @@ __global__ __launch_bounds__(kPartThreads) void k_part_hist(
     if (cs >= 0) hist[(uint64_t)(256 + t) * tiles + tile] = hc[t];
 }
 
-// Endpoints of one tile placed bucket by bucket in LDS, then written as contiguous runs; with
+// Endpoints of one tile placed bucket by bucket in LDS, then written as contiguous runs of
+// their offsets inside the bucket (type P: 16 bits when a bucket holds at most 2^16 ids); with
 // cs >= 0 the tile's edges then go through the same LDS buffer to their cells' runs (any
 // order inside a run).
+template <class P>
 __global__ __launch_bounds__(kPartThreads) void k_part_scatter(
     const int2 *__restrict__ edges, uint64_t m, uint32_t n, uint32_t both, int sh, int cs,
     const uint32_t *__restrict__ hist, const uint32_t *__restrict__ offs, uint32_t tiles,
-    uint32_t *__restrict__ parts, int2 *__restrict__ cells) {
+    P *__restrict__ parts, int2 *__restrict__ cells) {
     __shared__ __align__(16) uint32_t s_stage[2 * kPartTile];  // endpoints, then edges (int2)
     __shared__ uint32_t s_fill[256], s_glob[256], s_wsum[kPartThreads / kWave];
     const uint32_t t = threadIdx.x, w = t / kWave;
@@ -122,9 +124,10 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scatter(
     }
     __syncthreads();
     const uint32_t total = s_fill[255];  // end of the last bucket = endpoints in this tile
+    const uint32_t omask = (uint32_t)((1ull << sh) - 1);
     for (uint32_t j = t; j < total; j += kPartThreads) {
         const uint32_t x = s_stage[j];
-        parts[s_glob[x >> sh] + j] = x;
+        parts[s_glob[x >> sh] + j] = (P)(x & omask);
     }
     if (cs < 0) return;
     // cells: the same placement with the cell digits (entries 256.. of the tables; their
@@ -155,9 +158,11 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scatter(
     }
 }
 
-// Workgroup (bucket, slice): counts its slice of the bucket's endpoints in LDS, window by
-// window of kPartWindow ids, and adds the counts to deg (zeroed beforehand).
-__global__ __launch_bounds__(1024) void k_part_count(const uint32_t *__restrict__ parts,
+// Workgroup (bucket, slice): counts its slice of the bucket's endpoints (offsets inside the
+// bucket) in LDS, window by window of kPartWindow ids, and adds the counts to deg (zeroed
+// beforehand).
+template <class P>
+__global__ __launch_bounds__(1024) void k_part_count(const P *__restrict__ parts,
                                                      const uint32_t *__restrict__ offs,
                                                      uint32_t tiles, int sh, uint32_t n,
                                                      uint32_t slices,
@@ -178,17 +183,19 @@ __global__ __launch_bounds__(1024) void k_part_count(const uint32_t *__restrict_
         const uint32_t wn = (uint32_t)((ids - w0) < kPartWindow ? (ids - w0) : kPartWindow);
         for (uint32_t i = t; i < wn; i += blockDim.x) cntr[i] = 0;
         __syncthreads();
-        const uint32_t lo = (uint32_t)(id0 + w0);
-        // the slice's 16-byte aligned body as uint4 loads, kPartLoads of them in flight per
-        // thread before their LDS increments; the unaligned ends one endpoint per thread
-        const uint32_t q0 = (s0 + 3u) >> 2, q1 = s1 >> 2;  // body: endpoints [4 q0, 4 q1)
-        const uint32_t e0 = q0 < q1 ? 4u * q0 : s1, e1 = q0 < q1 ? 4u * q1 : s1;
+        const uint32_t lo = (uint32_t)w0;  // window start, as an offset inside the bucket
+        // the slice's 16-byte aligned body as uint4 loads (kPer endpoints each), kPartLoads of
+        // them in flight per thread before their LDS increments; the unaligned ends one
+        // endpoint per thread
+        constexpr uint32_t kPer = 16 / sizeof(P);
+        const uint32_t q0 = (s0 + kPer - 1) / kPer, q1 = s1 / kPer;  // body: [kPer q0, kPer q1)
+        const uint32_t e0 = q0 < q1 ? kPer * q0 : s1, e1 = q0 < q1 ? kPer * q1 : s1;
         if (t < e0 - s0) {
-            const uint32_t x = parts[s0 + t] - lo;
+            const uint32_t x = (uint32_t)parts[s0 + t] - lo;
             if (x < wn) atomicAdd(&cntr[x], 1u);
         }
         if (t < s1 - e1) {
-            const uint32_t x = parts[e1 + t] - lo;
+            const uint32_t x = (uint32_t)parts[e1 + t] - lo;
             if (x < wn) atomicAdd(&cntr[x], 1u);
         }
         const uint4 *__restrict__ parts4 = reinterpret_cast<const uint4 *>(parts);
@@ -198,26 +205,44 @@ __global__ __launch_bounds__(1024) void k_part_count(const uint32_t *__restrict_
 #pragma unroll
             for (uint32_t k = 0; k < kPartLoads; ++k) {
                 const uint32_t j = j0 + k * blockDim.x;
-                x[k] = j < q1 ? parts4[j] : make_uint4(~0u, ~0u, ~0u, ~0u);
+                x[k] = j < q1 ? parts4[j] : make_uint4(0u, 0u, 0u, 0u);
             }
 #pragma unroll
             for (uint32_t k = 0; k < kPartLoads; ++k) {
-                const uint32_t a = x[k].x - lo, b = x[k].y - lo, c = x[k].z - lo,
-                               d = x[k].w - lo;
-                if (a < wn) atomicAdd(&cntr[a], 1u);
-                if (b < wn) atomicAdd(&cntr[b], 1u);
-                if (c < wn) atomicAdd(&cntr[c], 1u);
-                if (d < wn) atomicAdd(&cntr[d], 1u);
+                if (j0 + k * blockDim.x >= q1) continue;
+                const uint32_t wd[4] = {x[k].x, x[k].y, x[k].z, x[k].w};
+#pragma unroll
+                for (uint32_t q = 0; q < 4; ++q) {
+                    if (sizeof(P) == 2) {  // two offsets per word
+                        const uint32_t a = (wd[q] & 0xFFFFu) - lo, b = (wd[q] >> 16) - lo;
+                        if (a < wn) atomicAdd(&cntr[a], 1u);
+                        if (b < wn) atomicAdd(&cntr[b], 1u);
+                    } else {
+                        const uint32_t a = wd[q] - lo;
+                        if (a < wn) atomicAdd(&cntr[a], 1u);
+                    }
+                }
             }
         }
         __syncthreads();
         for (uint32_t i = t; i < wn; i += blockDim.x) {
             const uint32_t c = cntr[i];
-            if (c) atomicAdd(&deg[lo + i], c);
+            if (c) atomicAdd(&deg[id0 + lo + i], c);
         }
         __syncthreads();
     }
 }
+
+template __global__ void k_part_scatter<uint16_t>(const int2 *, uint64_t, uint32_t, uint32_t, int,
+                                                  int, const uint32_t *, const uint32_t *,
+                                                  uint32_t, uint16_t *, int2 *);
+template __global__ void k_part_scatter<uint32_t>(const int2 *, uint64_t, uint32_t, uint32_t, int,
+                                                  int, const uint32_t *, const uint32_t *,
+                                                  uint32_t, uint32_t *, int2 *);
+template __global__ void k_part_count<uint16_t>(const uint16_t *, const uint32_t *, uint32_t, int,
+                                                uint32_t, uint32_t, uint32_t *, const int32_t *);
+template __global__ void k_part_count<uint32_t>(const uint32_t *, const uint32_t *, uint32_t, int,
+                                                uint32_t, uint32_t, uint32_t *, const int32_t *);
 
 // Fallback for inputs whose endpoint count does not fit the partition's 32-bit offsets, or
 // whose buckets would need too many LDS windows: one atomic increment per endpoint.

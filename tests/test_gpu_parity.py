@@ -142,6 +142,27 @@ def test_row_blocks_forced(blocks):
         check_vs_oracle(e.cpu().numpy(), n, options=opt, prepared_pv=True)
 
 
+@pytest.mark.parametrize("n", [(1 << 24) - 3, (1 << 25) + 7])
+def test_degree_partition_wide_ids(n):
+    """The degree partition on id ranges whose 256 buckets hold 2^16 ids (endpoints kept as
+    2-byte offsets, two LDS windows per bucket) and 2^17 ids (4-byte offsets, four windows):
+    degrees and counts against the oracle on a sparse graph spread over the whole id range
+    with a dense cluster at its top (its ids fall in the last, ragged bucket)."""
+    rng = np.random.default_rng(n % 1000)
+    a = rng.integers(0, n, 300_000)
+    b = rng.integers(0, n, 300_000)
+    top = n - 1 - np.arange(60)
+    ci, cj = np.triu_indices(60, 1)
+    e = np.concatenate([np.stack([a, b], 1), np.stack([top[ci], top[cj]], 1)])
+    e = e[e[:, 0] != e[:, 1]]
+    key = np.minimum(e[:, 0], e[:, 1]) * n + np.maximum(e[:, 0], e[:, 1])
+    _, first = np.unique(key, return_index=True)
+    e = np.ascontiguousarray(e[np.sort(first)].astype(np.int32))
+    out = api.preprocess(torch.as_tensor(e, device=DEV), n)
+    assert np.array_equal(out["deg"].cpu().numpy().astype(np.int64), oracle.degrees(e, n))
+    assert check_vs_oracle(e, n) >= math.comb(60, 3)
+
+
 @pytest.mark.parametrize("both", [False, True])
 def test_degree_atomic_path(both):
     """Degrees by one atomic per endpoint and orientation in input order (the path of graphs
