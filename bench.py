@@ -169,8 +169,8 @@ def cpu_baseline(dev):
             "seconds": g["oracle_seconds"], "edges": g["m"],
             "intersections_per_s": g["m"] / g["oracle_seconds"],
             "note": "the stored oracle run of the full R-MAT scale 23 graph (total and "
-                    "per-vertex counts), one core of the container that wrote the goldens "
-                    "(tests/golden/make_golden.py --c3), not of the GPU box's host"}
+                    "per-vertex counts), one core of the machine that wrote the goldens "
+                    "(tests/golden/make_golden.py --c3), not of this host"}
     return out
 
 
