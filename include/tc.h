@@ -107,8 +107,9 @@ const char *tc_strerror(int status);
  *                     graphs beyond the partition's limits, 2^27 vertices or 2^32 endpoints,
  *                     take anyway).
  *   sort_onesweep     0 (default): every radix pass is a histogram pass, a scan and a scatter;
- *                     1: sorts of at least 2^20 keys use single-sweep passes (decoupled
- *                     look-back).
+ *                     1: the sort of the oriented edges, when it has at least 2^20 keys,
+ *                     uses single-sweep passes (decoupled look-back), except for the last
+ *                     pass of the source-only sort, which unzips the keys.
  *   high_ranks        the node array's entries among the top high_ranks ranks are also kept
  *                     as 16-bit offsets, and total counts stream them at two bytes instead of
  *                     four (on R-MAT graphs nearly all streamed entries are such ranks); the

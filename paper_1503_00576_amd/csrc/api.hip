@@ -45,8 +45,8 @@ __global__ void k_csc_keys(const uint32_t *, const uint32_t *, const uint32_t *,
                            const uint32_t *, const uint32_t *, uint32_t, const uint64_t *,
                            uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t,
                            uint32_t *, uint4 *, uint16_t *, const int32_t *);
-__global__ void k_csc_final(const uint32_t *, uint32_t, uint64_t, uint32_t *, uint32_t *,
-                            const int32_t *);
+__global__ void k_csc_final(const uint32_t *, uint32_t, const uint32_t *, uint64_t, uint32_t *,
+                            uint32_t *, const int32_t *);
 __global__ void k_items(const uint32_t *, const uint32_t *, const uint32_t *, uint32_t, uint32_t,
                         uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t *,
                         uint32_t *,
@@ -100,7 +100,7 @@ struct Layout {
 // two item queues, the fingerprint of the prepared layout, status of the current count
 enum {
     kCtlStatus = 0, kCtlBoth = 1, kCtlQueueA = 2, kCtlQueueB = 3, kCtlFinger = 4, kCtlRun = 5,
-    kCtlQueueC = 6, kCtlLongRows = 7, kCtlWords = 64
+    kCtlQueueC = 6, kCtlLongRows = 7, kCtlKept = 8, kCtlWords = 64
 };
 // start of a preprocessing: clear the control words and record the layout's fingerprint
 __global__ void k_ctl_init(uint32_t *__restrict__ ctl, uint32_t finger) {
@@ -525,14 +525,16 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
                        src, row_ptr, hrow, hstart, L.hbase, pr, mf, n, L.nblk, L.p0,
                        count_panel(), L.h0, cid, eu, hcol, status);
     TC_LAUNCH_CHECK();
-    // sorted into (list id, cbeg) pairs: the list ids land in ck or ck2 (as 32-bit words)
+    // sorted into (list id, cbeg) pairs: the list ids land in ck or ck2 (as 32-bit words);
+    // the in-edges of no list are dropped by the first pass (ctl[kCtlKept] of them remain)
     uint32_t *clist = nullptr;
-    TC_HIP(sort_lists(cid, mf, id_bits_for64(l1), ck, ck2, at<uint32_t>(ws, L.cbeg), sort_scr,
-                      status, s, &clist, onesweep));
+    TC_HIP(sort_lists(cid, (uint32_t)L.lists, mf, id_bits_for64(l1), ck, ck2,
+                      at<uint32_t>(ws, L.cbeg), ctl + kCtlKept, sort_scr, status, s, &clist));
     TC_HIP(fill_u32(lrs, 0u, l1, s));
     TC_HIP(fill_u32(lre, 0u, l1, s));
     hipLaunchKernelGGL(k_csc_final, dim3(grid_for(mf, 256 * 4)), dim3(256), 0, s, clist, mf,
-                       L.lists, lrs, lre, status);  // 4 ids per thread (prep.hip, kCscFinalKeys)
+                       ctl + kCtlKept, L.lists, lrs, lre,
+                       status);  // 4 ids per thread (prep.hip, kCscFinalKeys)
     TC_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_rowlen, dim3(grid_for(l1, 256)), dim3(256), 0, s, lrs, lre,
                        (uint32_t)L.lists, cnt);

@@ -112,13 +112,14 @@ hipError_t sort_u64(uint64_t *keys, uint64_t *tmp, uint32_t count, int lo_bit, i
 hipError_t sort_unzip(uint64_t *keys, uint64_t *tmp, uint32_t count, int lo_bit, int hi_bit,
                       int b, uint32_t *col, uint32_t *src, void *scratch, int32_t *status,
                       hipStream_t s, bool onesweep = false);
-// The in-edge lists: the keys (cid[i] << 32) | i sorted (stably) on their bits 32 .. 32 +
-// bits, written split: *list (list ids, in a or b, whichever the last pass does not read)
-// and cbeg (position + 1).  The first pass reads the 32-bit ids, the middle ones ping-pong
-// between a and b (cid may alias b, not a); same scratch as sort_u64.
-hipError_t sort_lists(const uint32_t *cid, uint32_t count, int bits, uint64_t *a, uint64_t *b,
-                      uint32_t *cbeg, void *scratch, int32_t *status, hipStream_t s,
-                      uint32_t **list, bool onesweep = false);
+// The in-edge lists: the keys (cid[i] << 32) | i with cid[i] != drop sorted (stably) on their
+// bits 32 .. 32 + bits, written split: *list (list ids, in a or b, whichever the last pass
+// does not read) and cbeg (position + 1), *kept of them (a device word).  The first pass
+// reads the 32-bit ids and drops the others, the middle ones ping-pong between a and b on the
+// kept keys (cid may alias b, not a); two-kernel passes; same scratch as sort_u64.
+hipError_t sort_lists(const uint32_t *cid, uint32_t drop, uint32_t count, int bits,
+                      uint64_t *a, uint64_t *b, uint32_t *cbeg, uint32_t *kept, void *scratch,
+                      int32_t *status, hipStream_t s, uint32_t **list);
 
 hipError_t fill_u32(uint32_t *p, uint32_t value, uint64_t count, hipStream_t s);
 

@@ -861,15 +861,17 @@ __global__ void k_csc_keys(const uint32_t *__restrict__ col, const uint32_t *__r
 }
 
 // The lists themselves: list c occupies sorted positions [rs[c], re[c]) (useful in-edges
-// only; rs and re zeroed beforehand), found from the sorted list ids; entry j names its
-// in-edge by cbeg[j] = e + 1, the start of the suffix (written by the sort's last pass); the
-// counting kernels read the in-edge's record (k_csc_keys) from there.  kCscFinalKeys ids a
-// block apart per thread, all loaded before any is used.
+// only, *kept of them; rs and re zeroed beforehand), found from the sorted list ids; entry j
+// names its in-edge by cbeg[j] = e + 1, the start of the suffix (written by the sort's last
+// pass); the counting kernels read the in-edge's record (k_csc_keys) from there.
+// kCscFinalKeys ids a block apart per thread, all loaded before any is used.
 constexpr uint32_t kCscFinalKeys = 4;
-__global__ void k_csc_final(const uint32_t *__restrict__ list, uint32_t mf, uint64_t lists,
+__global__ void k_csc_final(const uint32_t *__restrict__ list, uint32_t mf,
+                            const uint32_t *__restrict__ kept, uint64_t lists,
                             uint32_t *__restrict__ rs, uint32_t *__restrict__ re,
                             const int32_t *__restrict__ status) {
     if (*status) return;
+    mf = min(mf, *kept);
     const uint64_t j0 = (uint64_t)blockIdx.x * blockDim.x * kCscFinalKeys + threadIdx.x;
     uint32_t k[kCscFinalKeys], kp[kCscFinalKeys], kn[kCscFinalKeys];
 #pragma unroll

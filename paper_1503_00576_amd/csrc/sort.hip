@@ -158,14 +158,21 @@ __device__ __forceinline__ uint64_t tile_key_index(uint64_t base, uint32_t w, in
 // Where a pass reads its keys: 64-bit keys, or (for the first pass of a sort of keys
 // (value << 32) | position) 32-bit values whose key is formed with the value's own index, so
 // that the producer writes and the first pass reads 4 bytes per key instead of 8.
+// keep(key): whether the pass takes the key (the others are dropped, and the output holds
+// only the kept keys, in order).
 struct Keys64 {
     const uint64_t *p;
     __device__ __forceinline__ uint64_t operator()(uint64_t i) const { return p[i]; }
+    __device__ __forceinline__ bool keep(uint64_t) const { return true; }
 };
-struct KeysHiIndex {
+struct KeysHiIndex {  // drops the keys whose value is `drop`
     const uint32_t *p;
+    uint32_t drop;
     __device__ __forceinline__ uint64_t operator()(uint64_t i) const {
         return ((uint64_t)p[i] << 32) | (uint32_t)i;
+    }
+    __device__ __forceinline__ bool keep(uint64_t key) const {
+        return (uint32_t)(key >> 32) != drop;
     }
 };
 
@@ -193,28 +200,34 @@ struct OutListBeg {
     }
 };
 
-// Loads the calling wave's 16 rows of the tile (all loads in flight before any use);
+// Loads the calling wave's 16 rows of the tile (all loads in flight before any use) and
+// returns the lane's mask of rows whose key takes part (below count, and kept);
 // kFull: the whole tile lies below count.
 template <bool kFull, class Src>
-__device__ __forceinline__ void load_tile_keys(const Src in, uint32_t count, uint64_t base,
-                                               uint32_t w, uint64_t (&keys)[kSortItems]) {
+__device__ __forceinline__ uint32_t load_tile_keys(const Src in, uint32_t count, uint64_t base,
+                                                   uint32_t w, uint64_t (&keys)[kSortItems]) {
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         const uint64_t idx = tile_key_index(base, w, r);
         keys[r] = (kFull || idx < count) ? in(idx) : 0ull;
     }
+    uint32_t vmask = 0;
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const uint64_t idx = tile_key_index(base, w, r);
+        if ((kFull || idx < count) && in.keep(keys[r])) vmask |= 1u << r;
+    }
+    return vmask;
 }
 
 // Per-wave digit counts of the wave's rows into cnt[256] (the wave's own row of counters,
 // zero on entry), and each key's rank among the wave's earlier keys of the same digit.
-template <bool kFull>
-__device__ __forceinline__ void wave_rank_rows(const uint64_t (&keys)[kSortItems], uint32_t count,
-                                               uint64_t base, uint32_t w, int shift,
-                                               uint32_t mask, uint32_t *cnt,
+__device__ __forceinline__ void wave_rank_rows(const uint64_t (&keys)[kSortItems], uint32_t vmask,
+                                               int shift, uint32_t mask, uint32_t *cnt,
                                                uint32_t (&ranks)[kSortItems]) {
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
-        const bool valid = kFull || tile_key_index(base, w, r) < count;
+        const bool valid = (vmask >> r) & 1u;
         const uint32_t d = (uint32_t)(keys[r] >> shift) & mask;
         const uint64_t peers = match_digit(d, valid);
         const uint32_t below = lanes_below(peers);
@@ -233,6 +246,7 @@ struct SortTileLds {
     uint32_t glob[256];              // global start minus local start of each digit
     uint32_t dsum[4];                // per-wave sums of the digit scan (digits by 4 waves)
     uint32_t gsum[4];                // the same for the global digit counts (single sweep)
+    uint32_t total;                  // keys of the tile that take part
 };
 
 // Block part of the placement (all threads, after the waves' counts are in wcnt): turns wcnt
@@ -256,36 +270,34 @@ __device__ __forceinline__ uint32_t tile_digit_offsets(SortTileLds &L) {
         uint32_t before = 0;
         for (uint32_t k = 0; k < t / kWave; ++k) before += L.dsum[k];
         L.loc[t] = before + incl - c;
+        if (t == 255) L.total = before + incl;
     }
     return c;
 }
 
 // Places the wave's keys in L.stage (after tile_digit_offsets and a barrier).
-template <bool kFull>
 __device__ __forceinline__ void stage_keys(SortTileLds &L, const uint64_t (&keys)[kSortItems],
-                                           const uint32_t (&ranks)[kSortItems], uint32_t count,
-                                           uint64_t base, uint32_t w, int shift, uint32_t mask) {
+                                           const uint32_t (&ranks)[kSortItems], uint32_t vmask,
+                                           uint32_t w, int shift, uint32_t mask) {
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
-        if (kFull || tile_key_index(base, w, r) < count) {
+        if ((vmask >> r) & 1u) {
             const uint32_t d = (uint32_t)(keys[r] >> shift) & mask;
             L.stage[L.loc[d] + L.wcnt[w][d] + ranks[r]] = keys[r];
         }
     }
 }
 
-// Writes the staged tile: consecutive threads write consecutive positions of one digit's run
-// (L.glob[d] + j is the output position of staged key j of digit d).
-template <bool kFull, class Dst>
+// Writes the staged tile (L.total keys): consecutive threads write consecutive positions of
+// one digit's run (L.glob[d] + j is the output position of staged key j of digit d).
+template <class Dst>
 __device__ __forceinline__ void write_staged(const SortTileLds &L, const Dst out, uint32_t count,
-                                             uint64_t base, int shift, uint32_t mask,
-                                             int32_t *status) {
-    const uint64_t rest = count - base;
-    const uint32_t ntile = kFull ? (uint32_t)kSortTile : (uint32_t)rest;
+                                             int shift, uint32_t mask, int32_t *status) {
+    const uint32_t ntile = L.total;
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
         const uint32_t j = (uint32_t)i * kSortThreads + threadIdx.x;
-        if (kFull || j < ntile) {
+        if (j < ntile) {
             const uint64_t key = L.stage[j];
             const uint32_t d = (uint32_t)(key >> shift) & mask;
             const uint32_t pos = L.glob[d] + j;
@@ -308,7 +320,7 @@ __device__ __forceinline__ void hist_tile(const Src in, uint32_t count, int shif
     const uint32_t t = threadIdx.x, w = t / kWave;
     const uint64_t base = (uint64_t)tile * kSortTile;
     uint64_t keys[kSortItems];
-    load_tile_keys<kFull>(in, count, base, w, keys);
+    const uint32_t vmask = load_tile_keys<kFull>(in, count, base, w, keys);
     for (uint32_t k = lane_id(); k < 256; k += kWave) h[w][k] = 0;
     wave_lds_sync();
     // counts only (no ranks): the keys of a row that share the first lane's digit are added
@@ -317,7 +329,7 @@ __device__ __forceinline__ void hist_tile(const Src in, uint32_t count, int shif
     // serialise many atomics on one counter)
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
-        const bool valid = kFull || tile_key_index(base, w, r) < count;
+        const bool valid = (vmask >> r) & 1u;
         const uint32_t d = (uint32_t)(keys[r] >> shift) & mask;
         const uint32_t d0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)d);
         const uint64_t same = __ballot(valid && d == d0);
@@ -333,13 +345,17 @@ __device__ __forceinline__ void hist_tile(const Src in, uint32_t count, int shif
     }
 }
 
+// dcount (nullable): the number of keys, read from the device (a bound set by an earlier pass
+// that dropped keys; count is then the capacity the grid was sized for)
 template <class Src>
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const Src in, uint32_t count,
+                                                             const uint32_t *__restrict__ dcount,
                                                              int shift, uint32_t nbits,
                                                              uint32_t *__restrict__ hist,
                                                              uint32_t tiles,
                                                              const int32_t *__restrict__ status) {
     if (status && *status) return;
+    if (dcount) count = min(count, *dcount);
     __shared__ uint32_t h[kSortWaves][256];
     const uint32_t tile = xcd_tile(blockIdx.x, tiles);
     const uint32_t mask = (1u << nbits) - 1u;
@@ -360,27 +376,29 @@ __device__ __forceinline__ void scatter_tile(const Src in, const Dst out, uint32
     const uint32_t t = threadIdx.x, w = t / kWave;
     const uint64_t base = (uint64_t)tile * kSortTile;
     uint64_t keys[kSortItems];
-    load_tile_keys<kFull>(in, count, base, w, keys);
+    const uint32_t vmask = load_tile_keys<kFull>(in, count, base, w, keys);
     for (uint32_t k = lane_id(); k < 256; k += kWave) L.wcnt[w][k] = 0;
     wave_lds_sync();
     uint32_t ranks[kSortItems];
-    wave_rank_rows<kFull>(keys, count, base, w, shift, mask, L.wcnt[w], ranks);
+    wave_rank_rows(keys, vmask, shift, mask, L.wcnt[w], ranks);
     tile_digit_offsets(L);
     if (t < 256) L.glob[t] = offs[(uint64_t)t * tiles + tile] - L.loc[t];
     __syncthreads();
-    stage_keys<kFull>(L, keys, ranks, count, base, w, shift, mask);
+    stage_keys(L, keys, ranks, vmask, w, shift, mask);
     __syncthreads();
-    write_staged<kFull>(L, out, count, base, shift, mask, nullptr);
+    write_staged(L, out, count, shift, mask, nullptr);
 }
 
 template <class Src, class Dst>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
-    const Src in, const Dst out, uint32_t count, int shift,
+    const Src in, const Dst out, uint32_t count, const uint32_t *__restrict__ dcount, int shift,
     uint32_t nbits, const uint32_t *__restrict__ offs, uint32_t tiles,
     const int32_t *__restrict__ status) {
     if (status && *status) return;
+    if (dcount) count = min(count, *dcount);
     __shared__ SortTileLds L;
     const uint32_t tile = xcd_tile(blockIdx.x, tiles);
+    if ((uint64_t)tile * kSortTile >= count) return;  // past the keys (a device count)
     const uint32_t mask = (1u << nbits) - 1u;
     if ((uint64_t)(tile + 1) * kSortTile <= count)
         scatter_tile<true>(in, out, count, shift, mask, offs, tiles, tile, L);
@@ -432,11 +450,11 @@ __device__ __forceinline__ void onesweep_tile(const uint64_t *__restrict__ in,
     const uint32_t t = threadIdx.x, w = t / kWave;
     const uint64_t base = (uint64_t)tile * kSortTile;
     uint64_t keys[kSortItems];
-    load_tile_keys<kFull>(Keys64{in}, count, base, w, keys);
+    const uint32_t vmask = load_tile_keys<kFull>(Keys64{in}, count, base, w, keys);
     for (uint32_t k = lane_id(); k < 256; k += kWave) L.wcnt[w][k] = 0;
     wave_lds_sync();
     uint32_t ranks[kSortItems];
-    wave_rank_rows<kFull>(keys, count, base, w, shift, mask, L.wcnt[w], ranks);
+    wave_rank_rows(keys, vmask, shift, mask, L.wcnt[w], ranks);
     const uint32_t c = tile_digit_offsets(L);
     if (t < 256)
         __hip_atomic_store(&flags[(uint64_t)tile * 256 + t], (tile == 0 ? kLbIncl : kLbAgg) | c,
@@ -446,7 +464,7 @@ __device__ __forceinline__ void onesweep_tile(const uint64_t *__restrict__ in,
     const uint32_t gincl = wave_incl_scan(gc);
     if (t < 256 && lane_id() == kWave - 1) L.gsum[w] = gincl;
     __syncthreads();
-    stage_keys<kFull>(L, keys, ranks, count, base, w, shift, mask);
+    stage_keys(L, keys, ranks, vmask, w, shift, mask);
     if (t < 256) {
         uint32_t gbefore = 0;
         for (uint32_t k = 0; k < w; ++k) gbefore += L.gsum[k];
@@ -494,7 +512,7 @@ __device__ __forceinline__ void onesweep_tile(const uint64_t *__restrict__ in,
         L.glob[t] = gstart + excl - L.loc[t];
     }
     __syncthreads();
-    write_staged<kFull>(L, Out64{out}, count, base, shift, mask, status);
+    write_staged(L, Out64{out}, count, shift, mask, status);
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_radix_onesweep(
@@ -527,11 +545,19 @@ size_t sort_scratch_bytes(uint64_t count) {
     return 2 * align_up(hist * 4, 256) + align_up(scan_scratch_words(hist) * 4, 256);
 }
 
+// the number of keys a pass wrote: the end of the last digit run of the last tile
+__global__ void k_sort_total(const uint32_t *__restrict__ hist, const uint32_t *__restrict__ offs,
+                             uint64_t last, uint32_t *__restrict__ total) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *total = offs[last] + hist[last];
+}
+
 // One stable two-kernel pass on the digit at `shift` (at most 8 bits, below hi_bit) from the
-// keys `in` yields to dst.
+// keys `in` yields to dst.  dcount (nullable): the number of keys on the device (count: the
+// capacity); total (nullable): receives the number of keys written (the kept ones).
 template <class Src, class Dst>
 static hipError_t radix_pass(const Src in, const Dst dst, uint32_t count, int shift, int hi_bit,
-                             void *scratch, int32_t *status, hipStream_t s) {
+                             void *scratch, int32_t *status, hipStream_t s,
+                             const uint32_t *dcount = nullptr, uint32_t *total = nullptr) {
     const uint32_t tiles = ceil_div(count, kSortTile);
     const uint64_t hist_n = 256ull * tiles;
     uint32_t *hist = (uint32_t *)scratch;
@@ -539,13 +565,17 @@ static hipError_t radix_pass(const Src in, const Dst dst, uint32_t count, int sh
     uint32_t *scan_scratch = (uint32_t *)((char *)scratch + 2 * align_up(hist_n * 4, 256));
     const uint32_t nbits = (uint32_t)((hi_bit - shift) < 8 ? (hi_bit - shift) : 8);
     hipLaunchKernelGGL(k_radix_hist<Src>, dim3(tiles), dim3(kSortThreads), 0, s, in, count,
-                       shift, nbits, hist, tiles, status);
+                       dcount, shift, nbits, hist, tiles, status);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = scan_exclusive_u32(hist, offs, hist_n, scan_scratch, s);
     if (e != hipSuccess) return e;
+    if (total) {
+        hipLaunchKernelGGL(k_sort_total, dim3(1), dim3(64), 0, s, hist, offs, hist_n - 1, total);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     hipLaunchKernelGGL((k_radix_scatter<Src, Dst>), dim3(tiles), dim3(kSortThreads), 0, s, in,
-                       dst, count, shift, nbits, offs, tiles, status);
+                       dst, count, dcount, shift, nbits, offs, tiles, status);
     return hipGetLastError();
 }
 
@@ -609,27 +639,32 @@ hipError_t sort_unzip(uint64_t *keys, uint64_t *tmp, uint32_t count, int lo_bit,
                       scratch, status, s);
 }
 
-hipError_t sort_lists(const uint32_t *cid, uint32_t count, int bits, uint64_t *a, uint64_t *b,
-                      uint32_t *cbeg, void *scratch, int32_t *status, hipStream_t s,
-                      uint32_t **list, bool onesweep) {
+hipError_t sort_lists(const uint32_t *cid, uint32_t drop, uint32_t count, int bits,
+                      uint64_t *a, uint64_t *b, uint32_t *cbeg, uint32_t *kept, void *scratch,
+                      int32_t *status, hipStream_t s, uint32_t **list) {
     *list = (uint32_t *)a;
-    if (count == 0) return hipSuccess;
+    if (count == 0) return fill_u32(kept, 0u, 1, s);
     const int hi_bit = 32 + (bits > 0 ? bits : 0);
     const int passes = bits > 0 ? (bits + 7) / 8 : 1;
+    const KeysHiIndex first{cid, drop};
     if (passes == 1)  // one pass from the ids to the split output
-        return radix_pass(KeysHiIndex{cid}, OutListBeg{*list, cbeg}, count, 32, hi_bit, scratch,
-                          status, s);
-    hipError_t e = radix_pass(KeysHiIndex{cid}, Out64{a}, count, 32, hi_bit, scratch, status, s);
+        return radix_pass(first, OutListBeg{*list, cbeg}, count, 32, hi_bit, scratch, status, s,
+                          nullptr, kept);
+    hipError_t e =
+        radix_pass(first, Out64{a}, count, 32, hi_bit, scratch, status, s, nullptr, kept);
     if (e != hipSuccess) return e;
-    const int last = 32 + 8 * (passes - 1);  // the last pass's digit
-    uint64_t *mid = a;
-    if (passes > 2) {
-        e = sort_u64(a, b, count, 40, last, scratch, status, s, &mid, onesweep);
+    uint64_t *src = a, *dst = b;
+    for (int p = 1; p < passes - 1; ++p) {  // the middle passes, on the kept keys
+        e = radix_pass(Keys64{src}, Out64{dst}, count, 32 + 8 * p, hi_bit, scratch, status, s,
+                       kept);
         if (e != hipSuccess) return e;
+        uint64_t *x = src;
+        src = dst;
+        dst = x;
     }
-    *list = (uint32_t *)(mid == a ? b : a);  // the buffer the last pass does not read
-    return radix_pass(Keys64{mid}, OutListBeg{*list, cbeg}, count, last, hi_bit, scratch, status,
-                      s);
+    *list = (uint32_t *)dst;  // the buffer the last pass does not read
+    return radix_pass(Keys64{src}, OutListBeg{*list, cbeg}, count, 32 + 8 * (passes - 1), hi_bit,
+                      scratch, status, s, kept);
 }
 
 }  // namespace tc

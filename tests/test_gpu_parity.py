@@ -210,10 +210,12 @@ def test_wide_panels_per_vertex():
                     prepared_pv=True)
 
 
-def test_single_sweep_sort():
-    """The single-sweep radix variant (look-back instead of a histogram pass) in the edge and
-    in-edge sorts of graphs above its 2^20-key threshold, with ragged last tiles."""
-    opt = {"sort_onesweep": 1}
+@pytest.mark.parametrize("row_sort", [1, 0])
+def test_single_sweep_sort(row_sort):
+    """The single-sweep radix variant (look-back instead of a histogram pass) in the sort of
+    the oriented edges (by source, its passes before the unzipping one; by (source, target),
+    all six) of graphs above its 2^20-key threshold, with ragged last tiles."""
+    opt = {"sort_onesweep": 1, "row_sort": row_sort}
     for e, n in [synth.rmat_graph(17, 16, seed=21), synth.rmat_graph(18, 6, seed=22)]:
         assert e.shape[0] >= (1 << 20) and e.shape[0] % 4096
         check_vs_oracle(e.numpy(), n, options=opt)
