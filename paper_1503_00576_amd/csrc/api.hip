@@ -22,7 +22,6 @@ __global__ void k_part_count(const P *, const uint32_t *, uint32_t, int, uint32_
 __global__ void k_degree_atomic(const int2 *, uint64_t, uint32_t, uint32_t, uint32_t *,
                                 int32_t *);
 __global__ void k_vkeys(const uint32_t *, uint32_t, int, uint64_t *);
-__global__ void k_rank(const uint64_t *, uint32_t, int, uint32_t *, uint32_t *);
 __global__ void k_orient(const int2 *, uint64_t, uint32_t, const uint32_t *, int, uint64_t *,
                          uint32_t *, const int32_t *);
 __global__ void k_orient_cells(const int2 *, uint64_t, uint32_t, const uint32_t *, int,
@@ -419,10 +418,8 @@ static int run_preprocess(const int32_t *d_edges, uint32_t flags, void *ws, cons
     if (n > 0) {
         hipLaunchKernelGGL(k_vkeys, dim3(grid_for(n, 256)), dim3(256), 0, s, deg, n, b, ka);
         TC_LAUNCH_CHECK();
-        uint64_t *vs = nullptr;
-        TC_HIP(sort_u64(ka, kb, n, b, 2 * b, sort_scr, nullptr, s, &vs));
-        hipLaunchKernelGGL(k_rank, dim3(grid_for(n, 256)), dim3(256), 0, s, vs, n, b, perm, rank);
-        TC_LAUNCH_CHECK();
+        // the last pass writes perm and rank
+        TC_HIP(sort_ranks(ka, kb, n, b, 2 * b, b, perm, rank, sort_scr, nullptr, s));
     }
     uint64_t *sorted = ka;
     if (m > 0) {

@@ -112,6 +112,11 @@ hipError_t sort_u64(uint64_t *keys, uint64_t *tmp, uint32_t count, int lo_bit, i
 hipError_t sort_unzip(uint64_t *keys, uint64_t *tmp, uint32_t count, int lo_bit, int hi_bit,
                       int b, uint32_t *col, uint32_t *src, void *scratch, int32_t *status,
                       hipStream_t s, bool onesweep = false);
+// the vertex order: keys (degree << b) | id sorted (stably) on bits lo_bit .. hi_bit, the last
+// pass writing perm[r] = id of position r and rank[id] = r (keys and tmp are clobbered)
+hipError_t sort_ranks(uint64_t *keys, uint64_t *tmp, uint32_t count, int lo_bit, int hi_bit,
+                      int b, uint32_t *perm, uint32_t *rank, void *scratch, int32_t *status,
+                      hipStream_t s);
 // The in-edge lists: the keys (cid[i] << 32) | i with cid[i] != drop sorted (stably) on their
 // bits 32 .. 32 + bits, written split: *list (list ids, in a or b, whichever the last pass
 // does not read) and cbeg (position + 1), *kept of them (a device word).  The first pass

@@ -5,12 +5,15 @@
 //                the edges in cells of id ranges for k_orient_cells
 //   k_vkeys      packs (degree, id) so that a stable sort yields the total order of Section 2.2
 //                (degree first, ties by id); the position of a vertex in that order is its rank
-//   k_rank       perm[r] = vertex of rank r, rank[v] = r
+//                (the sort's last pass writes perm[r] = vertex of rank r, rank[v] = r)
 //   k_orient*    every edge becomes a packed key (rank s << b) | rank t with s < t, i.e. the
 //                edge kept only in its forward direction (Section 3.2, steps 5-6); in the
 //                paper's two-direction format backward entries are dropped
-//   k_csr        the unzipped neighbour array (step 7), row boundaries for the node array
-//                (steps 4/8: row_ptr[x] = first key whose source is >= x), duplicate check
+//   k_row_*      with the keys sorted by source only (the sort's last pass unzips them into
+//                the neighbour and source arrays, step 7): row boundaries for the node array
+//                (steps 4/8: row_ptr[x] = first key whose source is >= x), every row sorted
+//                in place with the duplicate check
+//   k_csr        the same from keys sorted by (source, target): unzip, boundaries, duplicates
 //   k_csc_*      for every vertex v the list of in-edges u -> v with a non-empty suffix of
 //                N+(u) after v (the elements that can close a triangle through v), stored
 //                as a [begin, end) range;
@@ -273,15 +276,6 @@ __global__ void k_vkeys(const uint32_t *__restrict__ deg, uint32_t n, int b,
     uint64_t d = deg[x];
     if (d > lim) d = lim;  // only possible for invalid input, which is reported elsewhere
     vkeys[x] = (d << b) | x;
-}
-
-__global__ void k_rank(const uint64_t *__restrict__ sorted, uint32_t n, int b,
-                       uint32_t *__restrict__ perm, uint32_t *__restrict__ rank) {
-    uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    uint32_t x = (uint32_t)(sorted[r] & ((1ull << b) - 1));
-    perm[r] = x;
-    rank[x] = r;
 }
 
 __global__ void k_orient(const int2 *__restrict__ edges, uint64_t m, uint32_t both,

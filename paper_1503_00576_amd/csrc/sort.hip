@@ -192,6 +192,17 @@ struct OutColSrc {
         src[pos] = (uint32_t)(key >> b);
     }
 };
+// ... or, for the last pass of the vertex order: perm[r] = the vertex (low b bits) of the key
+// at position r, rank[vertex] = r.
+struct OutPermRank {
+    uint32_t *perm, *rank;
+    uint64_t mask;
+    __device__ __forceinline__ void operator()(uint64_t pos, uint64_t key) const {
+        const uint32_t x = (uint32_t)(key & mask);
+        perm[pos] = x;
+        rank[x] = (uint32_t)pos;
+    }
+};
 struct OutListBeg {
     uint32_t *list, *beg;
     __device__ __forceinline__ void operator()(uint64_t pos, uint64_t key) const {
@@ -636,6 +647,19 @@ hipError_t sort_unzip(uint64_t *keys, uint64_t *tmp, uint32_t count, int lo_bit,
     hipError_t e = sort_u64(keys, tmp, count, lo_bit, last, scratch, status, s, &mid, onesweep);
     if (e != hipSuccess) return e;
     return radix_pass(Keys64{mid}, OutColSrc{col, src, (1ull << b) - 1, b}, count, last, hi_bit,
+                      scratch, status, s);
+}
+
+hipError_t sort_ranks(uint64_t *keys, uint64_t *tmp, uint32_t count, int lo_bit, int hi_bit,
+                      int b, uint32_t *perm, uint32_t *rank, void *scratch, int32_t *status,
+                      hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    const int passes = hi_bit > lo_bit ? (hi_bit - lo_bit + 7) / 8 : 1;
+    const int last = hi_bit > lo_bit ? lo_bit + 8 * (passes - 1) : hi_bit;
+    uint64_t *mid = keys;
+    hipError_t e = sort_u64(keys, tmp, count, lo_bit, last, scratch, status, s, &mid);
+    if (e != hipSuccess) return e;
+    return radix_pass(Keys64{mid}, OutPermRank{perm, rank, (1ull << b) - 1}, count, last, hi_bit,
                       scratch, status, s);
 }
 
