@@ -160,9 +160,11 @@ __device__ __forceinline__ uint64_t tile_key_index(uint64_t base, uint32_t w, in
 // that the producer writes and the first pass reads 4 bytes per key instead of 8.
 // keep(key): whether the pass takes the key (the others are dropped, and the output holds
 // only the kept keys, in order).
-struct Keys64 {
+struct Keys64 {  // (read once per pass, with a non-temporal hint: no reuse within a pass)
     const uint64_t *p;
-    __device__ __forceinline__ uint64_t operator()(uint64_t i) const { return p[i]; }
+    __device__ __forceinline__ uint64_t operator()(uint64_t i) const {
+        return __builtin_nontemporal_load(p + i);
+    }
     __device__ __forceinline__ bool keep(uint64_t) const { return true; }
 };
 struct KeysHiIndex {  // drops the keys whose value is `drop`
