@@ -40,6 +40,12 @@ constexpr uint32_t kPartTile = kPartThreads * kPartEdges;    // 4096 edges per t
 constexpr uint32_t kPartWindow = 32768;                      // LDS counters per workgroup
 constexpr uint32_t kPartLoads = 4;                           // 16-byte loads in flight per thread
 
+// an edge of the input stream, read once per pass: non-temporal hint
+__device__ __forceinline__ int2 load_edge_nt(const int2 *edges, uint64_t i) {
+    const uint64_t w = __builtin_nontemporal_load(reinterpret_cast<const uint64_t *>(edges) + i);
+    return make_int2((int)(uint32_t)w, (int)(uint32_t)(w >> 32));
+}
+
 __device__ __forceinline__ bool endpoint_ok(int2 e, uint32_t n) {
     return (uint32_t)e.x < n && (uint32_t)e.y < n && e.x != e.y;
 }
@@ -67,7 +73,7 @@ __global__ __launch_bounds__(kPartThreads) void k_part_hist(
 #pragma unroll
     for (int r = 0; r < kPartEdges; ++r) {
         uint64_t i = base + (uint64_t)r * kPartThreads + t;
-        ed[r] = i < m ? edges[i] : make_int2(-1, -1);
+        ed[r] = i < m ? load_edge_nt(edges, i) : make_int2(-1, -1);
     }
 #pragma unroll
     for (int r = 0; r < kPartEdges; ++r) {
@@ -116,7 +122,7 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scatter(
 #pragma unroll
     for (int r = 0; r < kPartEdges; ++r) {
         uint64_t i = base + (uint64_t)r * kPartThreads + t;
-        ed[r] = i < m ? edges[i] : make_int2(-1, -1);
+        ed[r] = i < m ? load_edge_nt(edges, i) : make_int2(-1, -1);
     }
 #pragma unroll
     for (int r = 0; r < kPartEdges; ++r) {
@@ -415,7 +421,7 @@ __global__ void k_row_bounds(const uint32_t *__restrict__ src, uint32_t mf, uint
 #pragma unroll
     for (uint32_t t = 0; t < kCsrKeys; ++t) {
         const uint64_t i = i0 + (uint64_t)t * blockDim.x;
-        x[t] = i < mf ? src[i] : 0u;
+        x[t] = i < mf ? __builtin_nontemporal_load(src + i) : 0u;
         xp[t] = (i < mf && i > 0) ? src[i - 1] : ~0u;
         xn[t] = i + 1 < mf ? src[i + 1] : ~0u;
     }
@@ -871,7 +877,7 @@ __global__ void k_csc_final(const uint32_t *__restrict__ list, uint32_t mf,
 #pragma unroll
     for (uint32_t t = 0; t < kCscFinalKeys; ++t) {
         const uint64_t j = j0 + (uint64_t)t * blockDim.x;
-        k[t] = j < mf ? list[j] : ~0u;
+        k[t] = j < mf ? __builtin_nontemporal_load(list + j) : ~0u;
         kp[t] = (j < mf && j > 0) ? list[j - 1] : ~0u;
         kn[t] = j + 1 < mf ? list[j + 1] : ~0u;
     }

@@ -171,7 +171,7 @@ struct KeysHiIndex {  // drops the keys whose value is `drop`
     const uint32_t *p;
     uint32_t drop;
     __device__ __forceinline__ uint64_t operator()(uint64_t i) const {
-        return ((uint64_t)p[i] << 32) | (uint32_t)i;
+        return ((uint64_t)__builtin_nontemporal_load(p + i) << 32) | (uint32_t)i;
     }
     __device__ __forceinline__ bool keep(uint64_t key) const {
         return (uint32_t)(key >> 32) != drop;
