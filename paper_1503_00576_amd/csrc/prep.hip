@@ -40,6 +40,17 @@ constexpr uint32_t kPartTile = kPartThreads * kPartEdges;    // 4096 edges per t
 constexpr uint32_t kPartWindow = 32768;                      // LDS counters per workgroup
 constexpr uint32_t kPartLoads = 4;                           // 16-byte loads in flight per thread
 
+// 16-byte loads and stores with a non-temporal hint (streams touched once)
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 load_nt_u4(const uint4 *p) {
+    const u32x4_t v = __builtin_nontemporal_load(reinterpret_cast<const u32x4_t *>(p));
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void store_nt_u4(uint4 *p, uint4 x) {
+    const u32x4_t v = {x.x, x.y, x.z, x.w};
+    __builtin_nontemporal_store(v, reinterpret_cast<u32x4_t *>(p));
+}
+
 // an edge of the input stream, read once per pass: non-temporal hint
 __device__ __forceinline__ int2 load_edge_nt(const int2 *edges, uint64_t i) {
     const uint64_t w = __builtin_nontemporal_load(reinterpret_cast<const uint64_t *>(edges) + i);
@@ -214,7 +225,7 @@ __global__ __launch_bounds__(1024) void k_part_count(const P *__restrict__ parts
 #pragma unroll
             for (uint32_t k = 0; k < kPartLoads; ++k) {
                 const uint32_t j = j0 + k * blockDim.x;
-                x[k] = j < q1 ? parts4[j] : make_uint4(0u, 0u, 0u, 0u);
+                x[k] = j < q1 ? load_nt_u4(parts4 + j) : make_uint4(0u, 0u, 0u, 0u);
             }
 #pragma unroll
             for (uint32_t k = 0; k < kPartLoads; ++k) {
@@ -789,7 +800,7 @@ __global__ void k_csc_keys(const uint32_t *__restrict__ col, const uint32_t *__r
     for (uint32_t k = 0; k < kCscEdges; ++k) {
         const uint64_t e = e0 + (uint64_t)k * blockDim.x;
         const bool in = e < mf;
-        u[k] = in ? src[e] : 0u;
+        u[k] = in ? __builtin_nontemporal_load(src + e) : 0u;
         v[k] = in ? col[e] : 0u;
         prv[k] = (in && e > 0) ? col[e - 1] : 0u;
         nxt[k] = (in && e + 1 < mf) ? col[e + 1] : 0u;
@@ -856,7 +867,7 @@ __global__ void k_csc_keys(const uint32_t *__restrict__ col, const uint32_t *__r
             }
         }
         ckey[e] = (uint32_t)c;  // list ids are below 2^32 (the host bounds the row blocks)
-        eu[e] = make_uint4(end_u, mask, hpos, u[k]);
+        store_nt_u4(eu + e, make_uint4(end_u, mask, hpos, u[k]));
     }
 }
 
